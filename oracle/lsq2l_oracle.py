@@ -1,0 +1,452 @@
+"""Plain FP64 CPU oracle of the two-level Schwarz preconditioned normal equations.
+
+TEST INFRASTRUCTURE.  This module exists to check the GPU library; only the
+tests, the smoke entry point and the CPU-baseline leg of the benchmark may
+import it.  It shares no code with the library (no kernels, headers, helpers
+or constants); both are fed by the seeded generators in ``workloads``.
+
+What it computes (Al Daas, Jolivet, Scott, "A robust algebraic domain
+decomposition preconditioner for sparse normal equations"):
+
+* ``index_sets``        -- Section 3, eq. (reorderedA) and Algorithm 1:
+                           Xi_i, Omega_Gamma_i, Omega_i = [Omega_Ii, Omega_Gamma_i];
+* ``partition_of_unity``-- Section 3, the 0/1 matrices D_i of the worked
+                           example and Section 3.3.1;
+* ``local_matrices``    -- C_ii = A(:,Omega_i)^T A(:,Omega_i) (Section 3.1) and
+                           the local SPSD splitting
+                           Ct_ii = A(Xi_i,Omega_i)^T A(Xi_i,Omega_i) (eq. spsd_normal_eq);
+* ``coarse_vectors``    -- Lemma 2.4 / eq. (gevp) with its 0 and infinity
+                           conventions (Section 3.3.2): Z_i = L_i^perp (+)
+                           span{v : lambda > 1/tau}, returned as the interior
+                           part X_i of D_i Z_i;
+* ``Oracle.setup``      -- Algorithm 1 steps in order: index sets, D_i, R_i,
+                           Cholesky of C_ii, Z_i, R_0^T = [R_1^T D_1 Z_1, ...],
+                           Cholesky of C_00 = (A R_0^T)^T (A R_0^T);
+* ``Oracle.apply``      -- M_additive = R_0^T C_00^{-1} R_0 + sum_i R_i^T C_ii^{-1} R_i
+                           (eq. two_level_schwarz), or the one-level M_ASM
+                           (eq. one_level_schwarz);
+* ``pcg``               -- preconditioned conjugate gradients on C x = A^T b
+                           (eq. normal), x_0 = 0, C applied as A^T (A p);
+* ``Oracle.backward``   -- adjoint of x = C^{-1} A^T b: lambda = C^{-1} g,
+                           dL/db = A lambda, dL/dA_ij = r_i lambda_j - (A lambda)_i x_j
+                           on the stored pattern (differentiation of eq. normal);
+* pin helpers           -- multiplicity m_j and k_m (Lemma 3.1), greedy colouring
+                           k_c (Lemma 2.2), the bound of Theorem 2.6, and three
+                           independent routes to the selection count (Schur
+                           pencil, principal angles, inertia).
+
+Readings of points the paper leaves open (all listed in the design notes):
+nonzero means structurally stored; overlap is one layer; the eigenproblem is
+solved exactly (no shift s) and selection is strict lambda > 1/tau; the
+numerical rank of Ct_ii is decided after a symmetric diagonal scaling to unit
+diagonal (a congruence that commutes with D_i and leaves the eigenvalues of
+eq. gevp unchanged) with relative tolerance n_i * eps, a kernel direction is
+infinite (in L^perp) when its interior part exceeds 1e-8, and the number of
+coarse vectors p_i is the rank of D_i Z_i; no cap on the number
+of eigenpairs unless ``nev_max`` is given; PCG stops on the recurrence
+residual ||r_k|| <= tol ||A^T b|| and then checks the true residual,
+restarting from it at most three times.
+
+Parity status: every function here is pinned by a CPU test against values
+the paper prints, closed forms, library routines or the paper's lemmas;
+iteration counts have no published counterpart (parity unpinned against the
+paper, the tables' data files are absent).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+EPS = np.finfo(np.float64).eps
+
+__all__ = [
+    "Subdomain", "index_sets", "partition_of_unity", "restriction",
+    "local_matrices", "coarse_vectors", "selection_count_schur",
+    "selection_count_angles", "selection_count_inertia", "multiplicity",
+    "greedy_colouring", "theorem26_bound", "Oracle", "pcg", "csr_matrix",
+    "dense_preconditioner", "spmv", "spmv_t",
+]
+
+
+def csr_matrix(m, n, indptr, indices, data) -> sp.csr_matrix:
+    return sp.csr_matrix((np.asarray(data, dtype=np.float64),
+                          np.asarray(indices), np.asarray(indptr)), shape=(m, n))
+
+
+def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
+    """y = A x, y_i = sum_k A_ik x_k (library sparse product)."""
+    return A @ x
+
+
+def spmv_t(A: sp.csr_matrix, y: np.ndarray) -> np.ndarray:
+    """x = A^T y (library sparse product on the transpose)."""
+    return A.T @ y
+
+
+# ---------------------------------------------------------------------------
+# Section 3: index sets, restriction, partition of unity
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Subdomain:
+    I: np.ndarray    # Omega_Ii, sorted column indices (0-based)
+    Xi: np.ndarray   # Xi_i, sorted row indices of the nonzero rows of A(:, Omega_Ii)
+    G: np.ndarray    # Omega_Gamma_i, sorted
+
+    @property
+    def Omega(self) -> np.ndarray:
+        return np.concatenate([self.I, self.G])
+
+    @property
+    def nI(self) -> int:
+        return int(self.I.size)
+
+    @property
+    def nG(self) -> int:
+        return int(self.G.size)
+
+    @property
+    def ni(self) -> int:
+        return self.nI + self.nG
+
+
+def index_sets(A: sp.csr_matrix, part: np.ndarray, nparts: int) -> list[Subdomain]:
+    """Section 3 (eq. reorderedA), Algorithm 1 (FindNonzeroRows, FindNonzeroColumns).
+
+    Xi_i     = rows of A with a stored entry in some column of Omega_Ii;
+    Gamma_i  = columns with a stored entry in some row of Xi_i, minus Omega_Ii;
+    Omega_i  = [Omega_Ii, Omega_Gamma_i], each part in ascending order.
+    """
+    A = sp.csr_matrix(A)
+    Acsc = A.tocsc()
+    out = []
+    for i in range(nparts):
+        I = np.flatnonzero(np.asarray(part) == i).astype(np.int64)
+        Xi = np.unique(Acsc[:, I].indices).astype(np.int64)
+        cols = np.unique(A[Xi, :].indices).astype(np.int64)
+        G = np.setdiff1d(cols, I, assume_unique=True)
+        out.append(Subdomain(I, Xi, G))
+    return out
+
+
+def partition_of_unity(s: Subdomain) -> np.ndarray:
+    """Diagonal of D_i: one on the n_Ii interior entries, zero on Gamma (Section 3,
+    worked example; Section 3.3.1)."""
+    return np.concatenate([np.ones(s.nI), np.zeros(s.nG)])
+
+
+def restriction(s: Subdomain, n: int) -> sp.csr_matrix:
+    """R_i = I_n(Omega_i, :) (Section 2)."""
+    Om = s.Omega
+    return sp.csr_matrix((np.ones(Om.size), (np.arange(Om.size), Om)), shape=(Om.size, n))
+
+
+def local_matrices(A: sp.csr_matrix, s: Subdomain) -> tuple[np.ndarray, np.ndarray]:
+    """C_ii = A(:,Omega_i)^T A(:,Omega_i) (Section 3.1) and
+    Ct_ii = A(Xi_i,Omega_i)^T A(Xi_i,Omega_i) (eq. spsd_normal_eq), both dense."""
+    A = sp.csr_matrix(A)
+    Ac = A[:, s.Omega]
+    Cii = (Ac.T @ Ac).toarray()
+    At = A[s.Xi, :][:, s.Omega]
+    Ctii = (At.T @ At).toarray()
+    return Cii, Ctii
+
+
+# ---------------------------------------------------------------------------
+# Lemma 2.4: local filtering eigenproblem and the coarse vectors
+# ---------------------------------------------------------------------------
+
+def coarse_vectors(Cii: np.ndarray, Ctii: np.ndarray, nI: int, tau: float,
+                   nev_max: int = 0) -> dict:
+    """Z_i of Lemma 2.4 with the conventions of eq. (gevp), restricted by D_i.
+
+    The pencil D_i C_ii D_i v = lambda Ct_ii v is solved on range(Ct_ii);
+    Ct_ii's kernel is split into L_i = ker(D C D) cap ker(Ct) (lambda = 0) and
+    its complement L_i^perp inside ker(Ct) (lambda = infinity).  Selected:
+    L_i^perp and every finite lambda > 1/tau.  Returns the interior block X_i
+    of D_i Z_i, orthonormalised in the C_I = C_ii(I,I) inner product, plus the
+    finite eigenvalues and counts.
+    """
+    ni = Cii.shape[0]
+    d = np.concatenate([np.ones(nI), np.zeros(ni - nI)])
+    DCD = d[:, None] * Cii * d[None, :]
+    # symmetric diagonal scaling S Ct S, S = diag(Ct)^(-1/2); D S = S D.
+    sc = 1.0 / np.sqrt(np.diag(Ctii))
+    Ct_s = sc[:, None] * Ctii * sc[None, :]
+    DCD_s = sc[:, None] * DCD * sc[None, :]
+    lam_t, Q = sla.eigh(Ct_s)
+    tol = ni * EPS * max(float(lam_t.max()), 0.0)
+    in_range = lam_t > tol
+    Qr, Qk = Q[:, in_range], Q[:, ~in_range]
+    # finite eigenvalues: restrict to range(Ct) (the projection P_0 of Lemma 2.4)
+    Wr = Qr / np.sqrt(lam_t[in_range])[None, :]
+    H = Wr.T @ DCD_s @ Wr
+    H = 0.5 * (H + H.T)
+    lam, Y = sla.eigh(H)
+    fin_vecs = Wr @ Y
+    # infinite eigenvalues: L^perp in ker(Ct), L = {v in ker(Ct): D v = 0}
+    if Qk.shape[1] > 0:
+        # the kernel basis is orthonormal; a direction belongs to L^perp when
+        # its interior part is not zero, decided at 1e-8 (the computed kernel
+        # basis carries eps / gap noise in the interior rows of L)
+        KI = Qk[:nI, :]
+        _, sv, Vt = np.linalg.svd(KI, full_matrices=False)
+        rk = int((sv > 1e-8).sum())
+        inf_vecs = Qk @ Vt[:rk].T
+    else:
+        rk = 0
+        inf_vecs = np.zeros((ni, 0))
+    order_fin = np.argsort(-lam, kind="stable")          # largest lambda first
+    sel_fin = [k for k in order_fin if lam[k] > 1.0 / tau]
+    Z = np.concatenate([inf_vecs, fin_vecs[:, sel_fin]], axis=1)
+    if nev_max and Z.shape[1] > nev_max:
+        Z = Z[:, :nev_max]
+    Z = sc[:, None] * Z                                  # undo the scaling: v = S w
+    # The coarse space takes D_i Z_i (the columns R_i^T D_i Z_i of R_0^T).  A
+    # vector of L^perp and a finite eigenvector of the range-restricted pencil
+    # can share their D-part, so p_i is the rank of D_i Z_i: an orthonormal
+    # basis of its span in the C_I inner product is kept.
+    X = Z[:nI, :]                                        # D_i Z_i restricted to Omega_Ii
+    p = 0
+    if X.shape[1] > 0:
+        CI = Cii[:nI, :nI]
+        Gm = X.T @ CI @ X
+        Gm = 0.5 * (Gm + Gm.T)
+        w, U = sla.eigh(Gm)
+        keep = w > ni * EPS * max(float(w.max()), 0.0)
+        X = X @ (U[:, keep] / np.sqrt(w[keep])[None, :])
+        p = int(keep.sum())
+    return {"X": X, "Z": Z, "p": p, "lam": lam, "n_inf": rk, "n_fin": len(sel_fin),
+            "rank_ct": int(in_range.sum())}
+
+
+def selection_count_schur(Cii, Ctii, nI, tau) -> tuple[int, np.ndarray]:
+    """Route (i): S x = mu C_I x with S = C_I - C_IG Ct_GG^+ C_GI; count mu < tau.
+
+    Eliminating the Gamma block from eq. (gevp) gives C_I x = lambda S x, so
+    lambda = 1/mu and lambda > 1/tau is mu < tau.
+    """
+    CI = Cii[:nI, :nI]
+    CIG = Ctii[:nI, nI:]
+    CtGG = Ctii[nI:, nI:]
+    if CtGG.shape[0]:
+        S = CI - CIG @ sla.pinvh(CtGG) @ CIG.T
+    else:
+        S = CI.copy()
+    mu = sla.eigh(0.5 * (S + S.T), CI, eigvals_only=True)
+    return int((mu < tau).sum()), mu
+
+
+def selection_count_angles(A: sp.csr_matrix, s: Subdomain, tau) -> tuple[int, np.ndarray]:
+    """Route (iii): principal angles theta between range(A(Xi,Omega_I)) and
+    range(A(Xi,Omega_Gamma)) (library routine); mu = sin^2 theta < tau."""
+    A = sp.csr_matrix(A)
+    AI = A[s.Xi, :][:, s.I].toarray()
+    AG = A[s.Xi, :][:, s.G].toarray()
+    if AG.shape[1] == 0:
+        return 0, np.zeros(0)
+    th = sla.subspace_angles(AI, AG)
+    mu = np.sin(th) ** 2
+    return int((mu < tau).sum()), mu
+
+
+def selection_count_inertia(Cii, Ctii, nI, tau) -> int:
+    """Route (iv): number of negative eigenvalues of Ct_ii - tau D C_ii D
+    (with a tolerance n_i eps ||.||), i.e. directions where lambda > 1/tau."""
+    ni = Cii.shape[0]
+    d = np.concatenate([np.ones(nI), np.zeros(ni - nI)])
+    Mx = Ctii - tau * (d[:, None] * Cii * d[None, :])
+    ev = sla.eigvalsh(Mx)
+    return int((ev < -ni * EPS * np.abs(ev).max()).sum())
+
+
+# ---------------------------------------------------------------------------
+# constants of the condition-number bound
+# ---------------------------------------------------------------------------
+
+def multiplicity(A: sp.csr_matrix, sets: list[Subdomain]) -> tuple[np.ndarray, int]:
+    """m_j = #{i : j in Xi_i} and k_m = max_j m_j (Lemma 3.1)."""
+    mj = np.zeros(A.shape[0], dtype=np.int64)
+    for s in sets:
+        mj[s.Xi] += 1
+    return mj, int(mj.max(initial=0))
+
+
+def greedy_colouring(A: sp.csr_matrix, sets: list[Subdomain]) -> tuple[np.ndarray, int]:
+    """Colours of subdomains such that two subdomains with a stored coupling
+    C(Omega_i, Omega_j) != 0 get different colours (Lemma 2.2); greedy in
+    index order, so k_c is an upper bound on the minimum."""
+    A = sp.csr_matrix(A)
+    C = (A.T @ A).tocsr()
+    C.data[:] = 1.0
+    N = len(sets)
+    member = sp.csr_matrix((np.ones(sum(s.ni for s in sets)),
+                            (np.concatenate([np.full(s.ni, i) for i, s in enumerate(sets)]),
+                             np.concatenate([s.Omega for s in sets]))),
+                           shape=(N, A.shape[1]))
+    adj = (member @ C @ member.T).tocsr()
+    colour = -np.ones(N, dtype=np.int64)
+    for i in range(N):
+        nb = adj.indices[adj.indptr[i]:adj.indptr[i + 1]]
+        used = set(int(colour[j]) for j in nb if j != i and colour[j] >= 0)
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return colour, int(colour.max(initial=-1) + 1)
+
+
+def theorem26_bound(kc: int, km: int, tau: float) -> float:
+    """kappa(M_additive C) <= (k_c + 1)(2 + (2 k_c + 1) k_m / tau) (Theorem 2.6)."""
+    return (kc + 1) * (2.0 + (2 * kc + 1) * km / tau)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 and the preconditioned solve
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Oracle:
+    A: sp.csr_matrix
+    part: np.ndarray
+    nparts: int
+    tau: float
+    variant: str = "additive"          # or "one_level"
+    nev_max: int = 0
+    sets: list = field(default_factory=list)
+    chol: list = field(default_factory=list)
+    X: list = field(default_factory=list)
+    p: np.ndarray = None
+    R0T: sp.csr_matrix = None
+    E: np.ndarray = None
+    cholE: tuple = None
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def n0(self) -> int:
+        return int(self.p.sum()) if self.p is not None else 0
+
+    def setup(self, subdomains=None) -> "Oracle":
+        """Algorithm 1.  ``subdomains`` restricts the per-subdomain work to a
+        list of indices (used to time a bounded sample; the result is then not
+        a usable preconditioner)."""
+        A = self.A = sp.csr_matrix(self.A)
+        self.sets = index_sets(A, self.part, self.nparts)
+        todo = range(self.nparts) if subdomains is None else subdomains
+        self.chol = [None] * self.nparts
+        self.X = [np.zeros((s.nI, 0)) for s in self.sets]
+        self.info = [None] * self.nparts
+        for i in todo:
+            s = self.sets[i]
+            Cii, Ctii = local_matrices(A, s)
+            self.chol[i] = sla.cho_factor(Cii, lower=True)
+            if self.variant == "additive":
+                res = coarse_vectors(Cii, Ctii, s.nI, self.tau, self.nev_max)
+                self.X[i] = res["X"]
+                self.info[i] = res
+        self.p = np.array([x.shape[1] for x in self.X], dtype=np.int64)
+        if subdomains is not None:
+            return self
+        n0 = self.n0
+        if n0 > 0:
+            rows, cols, vals = [], [], []
+            off = 0
+            for s, X in zip(self.sets, self.X):
+                pi = X.shape[1]
+                if pi == 0:
+                    continue
+                rr, cc = np.meshgrid(s.I, np.arange(pi) + off, indexing="ij")
+                rows.append(rr.ravel()); cols.append(cc.ravel()); vals.append(X.ravel())
+                off += pi
+            self.R0T = sp.csr_matrix((np.concatenate(vals),
+                                      (np.concatenate(rows), np.concatenate(cols))),
+                                     shape=(self.n, n0))
+            W = (A @ self.R0T).toarray()
+            self.E = W.T @ W
+            self.cholE = sla.cho_factor(self.E, lower=True)
+        return self
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """z = M r with M = sum_i R_i^T C_ii^{-1} R_i (+ R_0^T C_00^{-1} R_0)."""
+        z = np.zeros(self.n)
+        for s, F in zip(self.sets, self.chol):
+            Om = s.Omega
+            z[Om] += sla.cho_solve(F, r[Om])
+        if self.cholE is not None:
+            z += self.R0T @ sla.cho_solve(self.cholE, self.R0T.T @ r)
+        return z
+
+    def solve(self, b: np.ndarray, tol: float = 1e-8, maxit: int = 10000,
+              flexible: bool = False) -> dict:
+        return pcg(self.A, self.A.T @ b, self.apply, tol, maxit, flexible)
+
+    def backward(self, b: np.ndarray, x: np.ndarray, g: np.ndarray,
+                 tol: float = 1e-12, maxit: int = 10000) -> dict:
+        """lambda = C^{-1} g; dL/db = A lambda; dL/dvals = r_i lambda_j - (A lambda)_i x_j."""
+        A = self.A
+        sol = pcg(A, g, self.apply, tol, maxit)
+        lam = sol["x"]
+        Alam = A @ lam
+        r = b - A @ x
+        rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+        dvals = r[rows] * lam[A.indices] - Alam[rows] * x[A.indices]
+        return {"dLdb": Alam, "dLdvals": dvals, "lam": lam, "its": sol["its"]}
+
+
+def pcg(A: sp.csr_matrix, rhs: np.ndarray, M, tol: float, maxit: int,
+        flexible: bool = False) -> dict:
+    """Preconditioned CG on C x = rhs, C = A^T A applied as A^T (A p), x_0 = 0.
+
+    Stops when ||r_k|| <= tol ||rhs|| on the recurrence residual, then forms
+    the true residual rhs - C x; if that misses tol the iteration restarts from
+    it (at most three restarts).  ``flexible`` uses
+    beta = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k).
+    """
+    n = A.shape[1]
+    x = np.zeros(n)
+    nrm0 = float(np.linalg.norm(rhs))
+    hist = []
+    if nrm0 == 0.0:
+        return {"x": x, "its": 0, "relres": 0.0, "hist": hist, "restarts": 0}
+    r = rhs.copy()
+    its = 0
+    restarts = 0
+    while True:
+        z = M(r)
+        rz = float(r @ z)
+        p = z.copy()
+        while its < maxit:
+            q = A.T @ (A @ p)
+            pq = float(p @ q)
+            alpha = rz / pq
+            x = x + alpha * p
+            r_old = r
+            r = r - alpha * q
+            its += 1
+            rel = float(np.linalg.norm(r)) / nrm0
+            hist.append(rel)
+            if rel <= tol:
+                break
+            z_new = M(r)
+            rz_new = float(r @ z_new)
+            beta = (float(z_new @ (r - r_old)) if flexible else rz_new) / rz
+            rz = rz_new
+            p = z_new + beta * p
+        true_r = rhs - A.T @ (A @ x)
+        relt = float(np.linalg.norm(true_r)) / nrm0
+        if relt <= tol or restarts == 3 or its >= maxit:
+            return {"x": x, "its": its, "relres": relt, "hist": hist, "restarts": restarts}
+        r = true_r
+        restarts += 1
+
+
+def dense_preconditioner(orc: Oracle) -> np.ndarray:
+    """The matrix M of ``orc.apply`` (small problems only)."""
+    n = orc.n
+    return np.column_stack([orc.apply(e) for e in np.eye(n)])
