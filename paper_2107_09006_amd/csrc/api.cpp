@@ -1,0 +1,685 @@
+// C ABI of the lsq2l library: setup (Algorithm 1), the preconditioned CG
+// solve on the normal equations (eq. normal), the adjoint solve, and the
+// accessors used for validation.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace lsq2l {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+int32_t roundup32(int64_t x) { return (int32_t)((x + TS - 1) / TS * TS); }
+
+int pick_group(double avg) {
+  int g = 1;
+  while (g < 64 && g < avg) g *= 2;
+  return g;
+}
+
+}  // namespace
+}  // namespace lsq2l
+
+using namespace lsq2l;
+
+struct lsq2l_ctx {
+  hipStream_t st = nullptr;
+  lsq2l_options opt{};
+  double tau = 0.0;
+  int S = 1;
+  int nsub = 0;
+  std::vector<SegDesc> segs_h;
+  std::vector<int64_t> seg_row_h, seg_col_h;
+  int64_t* d_seg_row = nullptr;
+  int64_t* d_seg_col = nullptr;
+  DevMatrix M;
+  DevPlan P;
+  DevCoarse Cc;
+  HostPlan H;
+  CoarsePlan CP;
+  bool coarse = false;
+  int64_t n0tot = 0;        // padded coarse size over all instances
+  int64_t n0 = 0;           // true coarse size
+  int64_t etiles = 0;
+  double *fac = nullptr, *dinv = nullptr, *scale = nullptr, *ctg = nullptr;
+  float *fac32 = nullptr, *dinv32 = nullptr;
+  double *X = nullptr, *W = nullptr, *efac = nullptr, *edinv = nullptr, *einv = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr, *rold = nullptr;
+  double *tm = nullptr, *tm2 = nullptr, *loc = nullptr, *cvec = nullptr, *dvec = nullptr;
+  double *partial = nullptr, *partial2 = nullptr, *xwork = nullptr;
+  double *bsave = nullptr, *xsave = nullptr;
+  bool have_solution = false;
+  Scalars sc{};
+  int32_t* status = nullptr;
+  int32_t* h_done = nullptr;      // pinned
+  double* h_rn2 = nullptr;        // pinned
+  double* h_r0n2 = nullptr;       // pinned
+  std::vector<int32_t> p_h;
+  lsq2l_setup_info info{};
+  std::vector<void*> dev_allocs;
+  std::vector<void*> host_allocs;
+
+  template <typename T>
+  lsq2l_status dalloc(T** ptr, int64_t count) {
+    *ptr = nullptr;
+    if (count <= 0) return LSQ2L_OK;
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+      set_error("device allocation of " + std::to_string((size_t)count * sizeof(T)) +
+                " bytes failed: " + hipGetErrorString(e));
+      return LSQ2L_ENOMEM;
+    }
+    dev_allocs.push_back(v);
+    *ptr = (T*)v;
+    return LSQ2L_OK;
+  }
+  template <typename T>
+  lsq2l_status halloc(T** ptr, int64_t count) {
+    void* v = nullptr;
+    hipError_t e = hipHostMalloc(&v, (size_t)std::max<int64_t>(count, 1) * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) { set_error("pinned host allocation failed"); return LSQ2L_ENOMEM; }
+    host_allocs.push_back(v);
+    *ptr = (T*)v;
+    return LSQ2L_OK;
+  }
+  template <typename T>
+  lsq2l_status upload(T** dst, const std::vector<T>& src) {
+    lsq2l_status s = dalloc(dst, (int64_t)src.size());
+    if (s != LSQ2L_OK) return s;
+    if (!src.empty()) LSQ2L_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return LSQ2L_OK;
+  }
+  ~lsq2l_ctx() {
+    if (st) (void)hipStreamSynchronize(st);
+    else (void)hipDeviceSynchronize();
+    for (void* v : dev_allocs) (void)hipFree(v);
+    for (void* v : host_allocs) (void)hipHostFree(v);
+  }
+};
+
+#define TRY(expr)                             \
+  do {                                        \
+    lsq2l_status _s = (expr);                 \
+    if (_s != LSQ2L_OK) return _s;            \
+  } while (0)
+
+namespace {
+
+lsq2l_status validate_csr(int32_t m, int32_t n, const std::vector<int32_t>& rp,
+                          const std::vector<int32_t>& ci) {
+  if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
+  for (int32_t r = 0; r < m; ++r) {
+    if (rp[r + 1] < rp[r]) { set_error("rowptr is not monotone at row " + std::to_string(r)); return LSQ2L_EINVAL; }
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] >= n) { set_error("column index out of range in row " + std::to_string(r)); return LSQ2L_EINVAL; }
+      if (e > rp[r] && ci[e] <= ci[e - 1]) { set_error("columns not strictly increasing in row " + std::to_string(r)); return LSQ2L_EINVAL; }
+    }
+  }
+  return LSQ2L_OK;
+}
+
+// z = M r: local solves (eq. one_level_schwarz) plus the coarse correction
+// R_0^T E^{-1} R_0 r (eq. two_level_schwarz).
+void apply_M(lsq2l_ctx* c, const double* r, double* z) {
+  const hipStream_t st = c->st;
+  launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
+  if (c->opt.precision == LSQ2L_MIXED)
+    launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
+  else
+    launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
+  if (c->coarse) {
+    launch_coarse_restrict(st, c->nsub, c->P, c->X, r, c->cvec);
+    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+  }
+  launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
+}
+
+void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
+  launch_spmv(c->st, c->M.m, c->M.rowptr, c->M.colind, c->M.vals, x, y, c->M.spmv_group);
+}
+void spmv_AT(lsq2l_ctx* c, const double* y, double* x) {
+  launch_spmv(c->st, c->M.n, c->M.trowptr, c->M.trow, c->M.tvals, y, x, c->M.spmvt_group);
+}
+
+lsq2l_status read_flags(lsq2l_ctx* c) {
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_done, c->sc.done, sizeof(int32_t) * c->S, hipMemcpyDeviceToHost, c->st));
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_rn2, c->sc.rn2, sizeof(double) * c->S, hipMemcpyDeviceToHost, c->st));
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_r0n2, c->sc.r0n2, sizeof(double) * c->S, hipMemcpyDeviceToHost, c->st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  return LSQ2L_OK;
+}
+
+// PCG on C x = rhs (x_0 = 0), C = A^T A applied as A^T (A p).  x is written.
+lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, double* relres_true,
+                 double* relres_rec) {
+  const hipStream_t st = c->st;
+  const int S = c->S;
+  const int64_t n = c->M.n;
+  const double tol2 = c->opt.tol * c->opt.tol;
+  const int flexible = c->opt.flexible;
+  launch_fill(st, n, 0.0, x);
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->r, c->rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
+  launch_scalar(st, OP_R0, S, c->partial, nullptr, c->sc, tol2, flexible);
+  int its = 0, restarts = 0;
+  bool breakdown = false;
+  while (true) {
+    apply_M(c, c->r, c->z);
+    launch_dot(st, S, c->d_seg_col, c->r, c->z, c->partial);
+    launch_scalar(st, OP_RHO_INIT, S, c->partial, nullptr, c->sc, tol2, flexible);
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->p, c->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    TRY(read_flags(c));
+    bool all_done = true;
+    for (int s = 0; s < S; ++s) all_done &= (c->h_done[s] != 0);
+    while (!all_done && its < c->opt.max_it) {
+      spmv_A(c, c->p, c->tm);
+      spmv_AT(c, c->tm, c->q);
+      launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
+      launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
+      if (flexible) LSQ2L_HIP_TRY(hipMemcpyAsync(c->rold, c->r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_axpy_xr(st, n, S, c->d_seg_col, c->sc.alpha, c->p, c->q, x, c->r);
+      launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
+      launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+      ++its;
+      if (its % std::max(1, c->opt.check_every) == 0 || its >= c->opt.max_it) {
+        TRY(read_flags(c));
+        all_done = true;
+        for (int s = 0; s < S; ++s) {
+          all_done &= (c->h_done[s] != 0);
+          breakdown |= (c->h_done[s] == 2);
+        }
+        if (all_done) break;
+      }
+      apply_M(c, c->r, c->z);
+      launch_dot(st, S, c->d_seg_col, c->r, c->z, c->partial);
+      if (flexible) launch_dot(st, S, c->d_seg_col, c->rold, c->z, c->partial2);
+      launch_scalar(st, OP_BETA, S, c->partial, flexible ? c->partial2 : nullptr, c->sc, tol2, flexible);
+      launch_xpby(st, n, S, c->d_seg_col, c->sc.beta, c->z, c->p);
+    }
+    // true residual rhs - A^T A x
+    spmv_A(c, x, c->tm);
+    spmv_AT(c, c->tm, c->q);
+    launch_sub(st, n, c->rhs, c->q, c->q);
+    launch_dot(st, S, c->d_seg_col, c->q, c->q, c->partial);
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_done, c->sc.done, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    std::vector<double> part((size_t)S * RED_BLOCKS);
+    LSQ2L_HIP_TRY(hipMemcpyAsync(part.data(), c->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_rn2, c->sc.rn2, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_r0n2, c->sc.r0n2, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    bool all_ok = true;
+    for (int s = 0; s < S; ++s) {
+      double t = 0.0;
+      for (int b = 0; b < RED_BLOCKS; ++b) t += part[(size_t)s * RED_BLOCKS + b];
+      const double r0 = c->h_r0n2[s];
+      relres_true[s] = r0 > 0 ? std::sqrt(t / r0) : 0.0;
+      relres_rec[s] = r0 > 0 ? std::sqrt(c->h_rn2[s] / r0) : 0.0;
+      if (c->h_done[s] == 2) breakdown = true;
+      if (!(relres_true[s] <= c->opt.tol)) all_ok = false;
+    }
+    if (all_ok || breakdown || restarts == 3 || its >= c->opt.max_it) break;
+    // restart from the true residual; converged instances re-check immediately
+    ++restarts;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->r, c->q, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
+    LSQ2L_HIP_TRY(hipMemsetAsync(c->sc.done, 0, sizeof(int32_t) * S, st));
+    launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+  }
+  *its_out = its;
+  *restarts_out = restarts;
+  if (breakdown) { set_error("PCG breakdown (non-positive curvature or non-finite value)"); return LSQ2L_PCG_BREAKDOWN; }
+  for (int s = 0; s < S; ++s)
+    if (!(relres_true[s] <= c->opt.tol)) {
+      set_error("PCG did not reach the tolerance within max_it iterations");
+      return LSQ2L_NOT_CONVERGED;
+    }
+  return LSQ2L_OK;
+}
+
+// Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
+lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                        const std::vector<int32_t>& part, int32_t nparts,
+                        const std::vector<int32_t>& seg_of_part) {
+  const hipStream_t st = c->st;
+  const int32_t m = c->M.m, n = c->M.n;
+  const int64_t nnz = c->M.nnz;
+  auto t_all = clk::now();
+  auto t0 = clk::now();
+  // --- transpose and index sets
+  std::vector<int32_t> trp, tcol, tperm;
+  plan_transpose(m, n, rp.data(), ci.data(), trp, tcol, tperm);
+  TRY(c->upload(&c->M.trowptr, trp));
+  TRY(c->upload(&c->M.trow, tcol));
+  TRY(c->upload(&c->M.tperm, tperm));
+  TRY(c->dalloc(&c->M.tvals, nnz));
+  launch_gather_values(st, nnz, c->M.tperm, c->M.vals, c->M.tvals);
+  c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
+  c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
+  std::string err;
+  if (!plan_build(m, n, rp.data(), ci.data(), trp, tcol, part.data(), nparts, seg_of_part, c->H, err)) {
+    set_error(err);
+    return LSQ2L_EINVAL;
+  }
+  HostPlan& H = c->H;
+  c->nsub = nparts;
+  TRY(c->upload(&c->P.subs, H.subs));
+  TRY(c->upload(&c->P.omega, H.omega));
+  TRY(c->upload(&c->P.xi, H.xi));
+  TRY(c->upload(&c->P.part, part));
+  TRY(c->upload(&c->P.locown, H.locown));
+  TRY(c->upload(&c->P.tileF, H.tileF));
+  TRY(c->upload(&c->P.tileOff, H.tileOff));
+  TRY(c->upload(&c->P.own_ptr, H.own_ptr));
+  TRY(c->upload(&c->P.own_pos, H.own_pos));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  c->info.t_plan_ms = ms_since(t0);
+  // --- local matrices
+  t0 = clk::now();
+  TRY(c->dalloc(&c->fac, H.total_fac));
+  TRY(c->dalloc(&c->dinv, H.total_dinv));
+  TRY(c->dalloc(&c->scale, H.total_loc));
+  TRY(c->dalloc(&c->ctg, H.total_g));
+  TRY(c->dalloc(&c->status, 8));
+  LSQ2L_HIP_TRY(hipMemsetAsync(c->status, 0, 8 * sizeof(int32_t), st));
+  LSQ2L_HIP_TRY(hipMemsetAsync(c->fac, 0, H.total_fac * sizeof(double), st));
+  if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(c->ctg, 0, H.total_g * sizeof(double), st));
+  launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg);
+  launch_equilibrate(st, nparts, c->P, c->fac, c->ctg, c->scale);
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  c->info.t_assemble_ms = ms_since(t0);
+  // --- batched local Cholesky
+  t0 = clk::now();
+  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status);
+  int32_t hstat[8];
+  LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  c->info.t_factor_ms = ms_since(t0);
+  if (hstat[0] != 0) {
+    set_error("local Cholesky breakdown in subdomain " + std::to_string(hstat[0] - 1));
+    return LSQ2L_CHOL_BREAKDOWN;
+  }
+  // --- coarse space
+  c->p_h.assign(nparts, 0);
+  c->coarse = false;
+  c->n0 = 0;
+  c->n0tot = 0;
+  t0 = clk::now();
+  if (c->opt.variant == LSQ2L_ADDITIVE) {
+    double *Tg = nullptr, *work = nullptr, *sig = nullptr;
+    int32_t* pc = nullptr;
+    TRY(c->dalloc(&Tg, H.total_g));
+    TRY(c->dalloc(&work, 4 * H.total_g));
+    TRY(c->dalloc(&sig, H.total_loc));
+    TRY(c->dalloc(&pc, nparts + 1));
+    if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(work, 0, 4 * H.total_g * sizeof(double), st));
+    LSQ2L_HIP_TRY(hipMemsetAsync(pc, 0, (nparts + 1) * sizeof(int32_t), st));
+    launch_gamma_T(st, nparts, c->P, c->fac, Tg);
+    launch_reduced_eig(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig);
+    std::vector<int32_t> ph(nparts + 1);
+    LSQ2L_HIP_TRY(hipMemcpyAsync(ph.data(), pc, (nparts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    if (ph[nparts] != 0) {
+      set_error(ph[nparts] == 2 ? "interface larger than the eigensolver limit (1024)"
+                                : "QL iteration did not converge in the coarse eigensolver");
+      return LSQ2L_EINVAL;
+    }
+    CoarsePlan& CP = c->CP;
+    plan_coarse(H, c->S, m, ph, CP);
+    c->segs_h = CP.segs;
+    for (int i = 0; i < nparts; ++i) c->p_h[i] = ph[i];
+    c->n0 = CP.n0;
+    c->n0tot = CP.n0tot;
+    c->etiles = CP.etiles;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->P.subs, H.subs.data(), H.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice, st));
+    TRY(c->upload(&c->Cc.segs, c->segs_h));
+    if (c->n0 > 0) {
+      c->coarse = true;
+      TRY(c->dalloc(&c->X, CP.xtot));
+      TRY(c->dalloc(&c->W, CP.wtot));
+      launch_coarse_X(st, nparts, c->P, c->fac, c->dinv, c->scale, work, sig, c->X);
+      launch_coarse_W(st, nparts, c->P, c->M, c->X, c->W);
+      LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+      c->info.t_eigen_ms = ms_since(t0);
+      t0 = clk::now();
+      TRY(c->upload(&c->Cc.pairs, CP.pairs));
+      TRY(c->upload(&c->Cc.pair_rows, CP.pair_rows));
+      TRY(c->upload(&c->Cc.eF, CP.eF));
+      TRY(c->upload(&c->Cc.eOff, CP.eOff));
+      TRY(c->upload(&c->Cc.e_seg_of_tile, CP.seg_of_tile));
+      int64_t* d_pad = nullptr;
+      TRY(c->upload(&d_pad, CP.pad_idx));
+      TRY(c->dalloc(&c->efac, CP.efac_tiles * TT));
+      TRY(c->dalloc(&c->edinv, c->etiles * TT));
+      LSQ2L_HIP_TRY(hipMemsetAsync(c->efac, 0, CP.efac_tiles * TT * sizeof(double), st));
+      launch_set_values(st, (int64_t)CP.pad_idx.size(), d_pad, 1.0, c->efac);
+      launch_coarse_E(st, (int)CP.pairs.size(), c->P, c->Cc, c->W, c->efac);
+      // right-looking Cholesky of E, one tile column per step
+      int32_t* d_erows = nullptr;
+      TRY(c->upload(&d_erows, CP.erows));
+      for (int64_t J = 0; J < c->etiles; ++J) {
+        const int nr = (int)(CP.eptr[J + 1] - CP.eptr[J]);
+        launch_echol_diag(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac, c->edinv, c->status + 1);
+        launch_echol_update(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac);
+      }
+      TRY(c->dalloc(&c->einv, CP.einv_tot));
+      launch_einv(st, (int)c->etiles, c->Cc, c->efac, c->edinv, c->einv);
+      TRY(c->dalloc(&c->cvec, c->n0tot));
+      TRY(c->dalloc(&c->dvec, c->n0tot));
+      LSQ2L_HIP_TRY(hipMemsetAsync(c->cvec, 0, c->n0tot * sizeof(double), st));
+      LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+      LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+      if (hstat[1] != 0) {
+        set_error("coarse Cholesky breakdown at tile " + std::to_string(hstat[1] - 1));
+        return LSQ2L_CHOL_BREAKDOWN;
+      }
+      c->info.t_coarse_ms = ms_since(t0);
+    } else {
+      LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+      c->info.t_eigen_ms = ms_since(t0);
+    }
+  }
+  // --- mixed precision copy of the local factors
+  if (c->opt.precision == LSQ2L_MIXED) {
+    TRY(c->dalloc(&c->fac32, H.total_fac));
+    TRY(c->dalloc(&c->dinv32, H.total_dinv));
+    launch_to_float(st, H.total_fac, c->fac, c->fac32);
+    launch_to_float(st, H.total_dinv, c->dinv, c->dinv32);
+  }
+  // --- solve workspace
+  TRY(c->dalloc(&c->r, n));
+  TRY(c->dalloc(&c->z, n));
+  TRY(c->dalloc(&c->p, n));
+  TRY(c->dalloc(&c->q, n));
+  TRY(c->dalloc(&c->rhs, n));
+  TRY(c->dalloc(&c->rold, n));
+  TRY(c->dalloc(&c->xwork, n));
+  TRY(c->dalloc(&c->xsave, n));
+  TRY(c->dalloc(&c->tm, m));
+  TRY(c->dalloc(&c->tm2, m));
+  TRY(c->dalloc(&c->bsave, m));
+  TRY(c->dalloc(&c->loc, H.total_loc));
+  TRY(c->dalloc(&c->partial, (int64_t)c->S * RED_BLOCKS));
+  TRY(c->dalloc(&c->partial2, (int64_t)c->S * RED_BLOCKS));
+  double* scal = nullptr;
+  TRY(c->dalloc(&scal, 6 * (int64_t)c->S));
+  c->sc.rho = scal; c->sc.alpha = scal + c->S; c->sc.beta = scal + 2 * c->S;
+  c->sc.rn2 = scal + 3 * c->S; c->sc.r0n2 = scal + 4 * c->S; c->sc.pq = scal + 5 * c->S;
+  TRY(c->dalloc(&c->sc.done, c->S));
+  TRY(c->halloc(&c->h_done, c->S));
+  TRY(c->halloc(&c->h_rn2, c->S));
+  TRY(c->halloc(&c->h_r0n2, c->S));
+  TRY(c->upload(&c->d_seg_col, c->seg_col_h));
+  TRY(c->upload(&c->d_seg_row, c->seg_row_h));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  // --- info
+  lsq2l_setup_info& inf = c->info;
+  inf.m = m; inf.n = n; inf.nnz = nnz; inf.nparts = nparts; inf.ninstances = c->S;
+  inf.n0 = c->n0;
+  inf.max_ni = 0; inf.max_p = 0;
+  int64_t dense = 0;
+  for (const SubDesc& d : H.subs) {
+    inf.max_ni = std::max(inf.max_ni, d.nI + d.nG);
+    inf.max_p = std::max(inf.max_p, d.p);
+    dense += (int64_t)(d.nI + d.nG) * (d.nI + d.nG + 1) / 2 * (int64_t)sizeof(double);
+  }
+  inf.factor_tiles = H.total_fac / TT;
+  inf.factor_bytes = H.total_fac * (c->opt.precision == LSQ2L_MIXED ? sizeof(float) : sizeof(double));
+  inf.factor_dense_bytes = dense;
+  inf.t_total_ms = ms_since(t_all);
+  return LSQ2L_OK;
+}
+
+lsq2l_status check_common(double tau, const lsq2l_options* opt) {
+  if (!(tau > 0.0 && tau <= 1.0)) { set_error("tau must lie in (0, 1]"); return LSQ2L_EINVAL; }
+  if (opt) {
+    if (!(opt->tol > 0.0)) { set_error("tol must be positive"); return LSQ2L_EINVAL; }
+    if (opt->max_it < 1) { set_error("max_it must be >= 1"); return LSQ2L_EINVAL; }
+    if (opt->precision != LSQ2L_FP64 && opt->precision != LSQ2L_MIXED) { set_error("bad precision"); return LSQ2L_EINVAL; }
+    if (opt->variant != LSQ2L_ADDITIVE && opt->variant != LSQ2L_ONE_LEVEL) { set_error("bad variant"); return LSQ2L_EINVAL; }
+    if (opt->nev_max < 0) { set_error("nev_max must be >= 0"); return LSQ2L_EINVAL; }
+  }
+  return LSQ2L_OK;
+}
+
+lsq2l_status solve_impl(lsq2l_ctx* c, double* x, lsq2l_solve_info* info) {
+  auto t0 = clk::now();
+  std::vector<double> rt(c->S), rr(c->S);
+  int its = 0, restarts = 0;
+  lsq2l_status s = pcg(c, x, &its, &restarts, rt.data(), rr.data());
+  const double ms = ms_since(t0);
+  if (info)
+    for (int k = 0; k < c->S; ++k) {
+      info[k].iterations = its;
+      info[k].restarts = restarts;
+      info[k].relres = rt[k];
+      info[k].relres_rec = rr[k];
+      info[k].solve_ms = ms;
+    }
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lsq2l_default_options(lsq2l_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->tol = 1e-8;
+  opt->max_it = 10000;
+  opt->precision = LSQ2L_FP64;
+  opt->flexible = 0;
+  opt->variant = LSQ2L_ADDITIVE;
+  opt->nev_max = 0;
+  opt->check_every = 1;
+}
+
+const char* lsq2l_last_error(void) { return g_err.c_str(); }
+
+lsq2l_status lsq2l_setup(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
+                         const int32_t* colind, const double* vals, const int32_t* part,
+                         int32_t nparts, int32_t overlap, double tau, const lsq2l_options* opt,
+                         void* hip_stream, lsq2l_handle* out) {
+  g_err.clear();
+  if (!out) { set_error("out is NULL"); return LSQ2L_EINVAL; }
+  *out = nullptr;
+  if (m < 1 || n < 1 || m < n) { set_error("need m >= n >= 1"); return LSQ2L_EINVAL; }
+  if (nnz < 0 || !rowptr || (nnz > 0 && (!colind || !vals)) || !part) { set_error("bad CSR pointers"); return LSQ2L_EINVAL; }
+  if (nparts < 1 || nparts > n) { set_error("nparts must lie in [1, n]"); return LSQ2L_EINVAL; }
+  if (overlap != 1) { set_error("only overlap = 1 (one layer, Section 3) is supported"); return LSQ2L_EINVAL; }
+  TRY(check_common(tau, opt));
+  for (int32_t j = 0; j < n; ++j)
+    if (part[j] < 0 || part[j] >= nparts) { set_error("part[" + std::to_string(j) + "] out of range"); return LSQ2L_EINVAL; }
+  lsq2l_ctx* c = new lsq2l_ctx();
+  c->st = (hipStream_t)hip_stream;
+  lsq2l_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  c->tau = tau;
+  c->S = 1;
+  c->M.m = m; c->M.n = n; c->M.nnz = nnz;
+  c->seg_row_h = {0, m};
+  c->seg_col_h = {0, n};
+  auto fail = [&](lsq2l_status s) { delete c; return s; };
+  std::vector<int32_t> rp(m + 1), ci(nnz), pt(part, part + n);
+  lsq2l_status s;
+  if ((s = c->dalloc(&c->M.rowptr, m + 1)) != LSQ2L_OK) return fail(s);
+  if ((s = c->dalloc(&c->M.colind, nnz)) != LSQ2L_OK) return fail(s);
+  if ((s = c->dalloc(&c->M.vals, nnz)) != LSQ2L_OK) return fail(s);
+  hipError_t e = hipMemcpyAsync(rp.data(), rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(ci.data(), colind, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
+  if (rp[m] != nnz) { set_error("rowptr[m] != nnz"); return fail(LSQ2L_EINVAL); }
+  if ((s = validate_csr(m, n, rp, ci)) != LSQ2L_OK) return fail(s);
+  e = hipMemcpyAsync(c->M.rowptr, rp.data(), (m + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.colind, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
+  if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
+  std::vector<int32_t> seg_of_part(nparts, 0);
+  s = setup_core(c, rp, ci, pt, nparts, seg_of_part);
+  if (s != LSQ2L_OK) return fail(s);
+  *out = c;
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_setup_batched(int32_t count, const lsq2l_problem* probs, double tau,
+                                 const lsq2l_options* opt, void* hip_stream, lsq2l_handle* out) {
+  g_err.clear();
+  if (!out || !probs || count < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
+  *out = nullptr;
+  TRY(check_common(tau, opt));
+  int64_t M = 0, N = 0, NNZ = 0, NP = 0;
+  for (int k = 0; k < count; ++k) {
+    const lsq2l_problem& pr = probs[k];
+    if (pr.m < 1 || pr.n < 1 || pr.m < pr.n || pr.nnz < 0 || pr.nparts < 1 || pr.nparts > pr.n ||
+        !pr.rowptr || !pr.part || (pr.nnz > 0 && (!pr.colind || !pr.vals))) {
+      set_error("bad problem " + std::to_string(k));
+      return LSQ2L_EINVAL;
+    }
+    M += pr.m; N += pr.n; NNZ += pr.nnz; NP += pr.nparts;
+  }
+  if (M >= INT32_MAX || NNZ >= INT32_MAX) { set_error("batch too large for int32 indices"); return LSQ2L_EINVAL; }
+  lsq2l_ctx* c = new lsq2l_ctx();
+  c->st = (hipStream_t)hip_stream;
+  lsq2l_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  c->tau = tau;
+  c->S = count;
+  c->M.m = (int32_t)M; c->M.n = (int32_t)N; c->M.nnz = NNZ;
+  auto fail = [&](lsq2l_status s) { delete c; return s; };
+  std::vector<int32_t> rp(M + 1, 0), ci(NNZ), pt(N), seg_of_part(NP);
+  c->seg_row_h.assign(count + 1, 0);
+  c->seg_col_h.assign(count + 1, 0);
+  lsq2l_status s;
+  if ((s = c->dalloc(&c->M.rowptr, M + 1)) != LSQ2L_OK) return fail(s);
+  if ((s = c->dalloc(&c->M.colind, NNZ)) != LSQ2L_OK) return fail(s);
+  if ((s = c->dalloc(&c->M.vals, NNZ)) != LSQ2L_OK) return fail(s);
+  int64_t r0 = 0, c0 = 0, e0 = 0, p0 = 0;
+  for (int k = 0; k < count; ++k) {
+    const lsq2l_problem& pr = probs[k];
+    std::vector<int32_t> lrp(pr.m + 1), lci(pr.nnz);
+    hipError_t e = hipMemcpyAsync(lrp.data(), pr.rowptr, (pr.m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && pr.nnz) e = hipMemcpyAsync(lci.data(), pr.colind, pr.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && pr.nnz) e = hipMemcpyAsync(c->M.vals + e0, pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) { set_error(std::string("reading problem: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
+    if (lrp[pr.m] != pr.nnz) { set_error("rowptr[m] != nnz in problem " + std::to_string(k)); return fail(LSQ2L_EINVAL); }
+    if ((s = validate_csr(pr.m, pr.n, lrp, lci)) != LSQ2L_OK) return fail(s);
+    for (int32_t rr = 0; rr < pr.m; ++rr) rp[r0 + rr + 1] = (int32_t)(e0 + lrp[rr + 1]);
+    for (int32_t q = 0; q < pr.nnz; ++q) ci[e0 + q] = (int32_t)(c0 + lci[q]);
+    for (int32_t j = 0; j < pr.n; ++j) {
+      if (pr.part[j] < 0 || pr.part[j] >= pr.nparts) { set_error("part out of range in problem " + std::to_string(k)); return fail(LSQ2L_EINVAL); }
+      pt[c0 + j] = (int32_t)(p0 + pr.part[j]);
+    }
+    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0 + q] = k;
+    r0 += pr.m; c0 += pr.n; e0 += pr.nnz; p0 += pr.nparts;
+    c->seg_row_h[k + 1] = r0;
+    c->seg_col_h[k + 1] = c0;
+  }
+  hipError_t e = hipMemcpyAsync(c->M.rowptr, rp.data(), (M + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess && NNZ) e = hipMemcpyAsync(c->M.colind, ci.data(), NNZ * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
+  if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
+  s = setup_core(c, rp, ci, pt, (int32_t)NP, seg_of_part);
+  if (s != LSQ2L_OK) return fail(s);
+  *out = c;
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_solve(lsq2l_handle c, const double* b, double* x, lsq2l_solve_info* info) {
+  g_err.clear();
+  if (!c || !b || !x) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->bsave, b, c->M.m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  spmv_AT(c, b, c->rhs);
+  lsq2l_status s = solve_impl(c, x, info);
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->xsave, x, c->M.n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  c->have_solution = (s == LSQ2L_OK || s == LSQ2L_NOT_CONVERGED);
+  return s;
+}
+
+lsq2l_status lsq2l_backward(lsq2l_handle c, const double* g, double* dLdb, double* dLdvals,
+                            lsq2l_solve_info* info) {
+  g_err.clear();
+  if (!c || !g) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  if (!c->have_solution) { set_error("backward needs a previous solve"); return LSQ2L_EINVAL; }
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->rhs, g, c->M.n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  lsq2l_status s = solve_impl(c, c->xwork, info);       // lambda = C^{-1} g
+  if (s != LSQ2L_OK && s != LSQ2L_NOT_CONVERGED) return s;
+  spmv_A(c, c->xwork, c->tm);                            // A lambda
+  if (dLdb) LSQ2L_HIP_TRY(hipMemcpyAsync(dLdb, c->tm, c->M.m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  if (dLdvals) {
+    spmv_A(c, c->xsave, c->tm2);                         // r = b - A x
+    launch_sub(c->st, c->M.m, c->bsave, c->tm2, c->tm2);
+    launch_grad_vals(c->st, c->M.m, c->M.rowptr, c->M.colind, c->tm2, c->xwork, c->tm, c->xsave, dLdvals);
+  }
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  return s;
+}
+
+lsq2l_status lsq2l_spmv(lsq2l_handle c, int32_t trans, const double* x, double* y) {
+  g_err.clear();
+  if (!c || !x || !y) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  if (trans) spmv_AT(c, x, y); else spmv_A(c, x, y);
+  LSQ2L_HIP_TRY(hipGetLastError());
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_apply_preconditioner(lsq2l_handle c, const double* r, double* z) {
+  g_err.clear();
+  if (!c || !r || !z) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  apply_M(c, r, z);
+  LSQ2L_HIP_TRY(hipGetLastError());
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_get_info(lsq2l_handle c, lsq2l_setup_info* out) {
+  if (!c || !out) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  *out = c->info;
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_get_subdomain(lsq2l_handle c, int32_t i, int32_t* sizes, int32_t* interior,
+                                 int32_t* xi, int32_t* gamma) {
+  if (!c) { set_error("NULL handle"); return LSQ2L_EINVAL; }
+  if (i < 0 || i >= c->nsub) { set_error("subdomain index out of range"); return LSQ2L_EINVAL; }
+  const SubDesc& d = c->H.subs[i];
+  if (sizes) { sizes[0] = d.nI; sizes[1] = d.nXi; sizes[2] = d.nG; sizes[3] = d.p; }
+  if (interior) std::memcpy(interior, &c->H.omega[d.omega_off], sizeof(int32_t) * d.nI);
+  if (gamma) std::memcpy(gamma, &c->H.omega[d.omega_off + d.nI], sizeof(int32_t) * d.nG);
+  if (xi) std::memcpy(xi, &c->H.xi[d.xi_off], sizeof(int32_t) * d.nXi);
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_get_coarse_basis(lsq2l_handle c, int32_t i, double* X) {
+  if (!c || !X) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  if (i < 0 || i >= c->nsub) { set_error("subdomain index out of range"); return LSQ2L_EINVAL; }
+  const SubDesc& d = c->H.subs[i];
+  if (d.p == 0) return LSQ2L_OK;
+  std::vector<double> tmp((size_t)d.nIp * d.p);
+  LSQ2L_HIP_TRY(hipMemcpyAsync(tmp.data(), c->X + d.x_off, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  for (int k = 0; k < d.p; ++k)
+    std::memcpy(X + (size_t)k * d.nI, tmp.data() + (size_t)k * d.nIp, sizeof(double) * d.nI);
+  return LSQ2L_OK;
+}
+
+void lsq2l_destroy(lsq2l_handle c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Internal declarations of the lsq2l library (HIP, gfx950).
+//
+// Data layout in HBM (all per handle):
+//   * A in CSR (int32 row pointers and columns, double values) and its
+//     transpose in CSR with the permutation into A's value array;
+//   * per subdomain i a local, zero-padded index space of size np_i:
+//       [0, nI)           interior columns Omega_Ii (ascending)
+//       [nI, nIp)         padding (identity rows), nIp = roundup(nI, 32)
+//       [nIp, nIp + nG)   interface columns Omega_Gamma_i (ascending)
+//       [nIp + nG, np)    padding, np = nIp + roundup(nG, 32)
+//   * local factors in a tile-envelope layout: the lower triangle is cut in
+//     32 x 32 tiles; tile row I keeps the tiles J = F(I) .. I contiguously
+//     (column-major inside a tile), where F(I) is the first tile column any
+//     row of the tile couples to.  Cholesky creates no fill outside the row
+//     envelope, so the factor overwrites the matrix in place;
+//   * the inverse of every diagonal factor tile (used by the blocked
+//     triangular solves);
+//   * coarse basis X_i (nIp x p_i, column-major), W_i = A(Xi_i, Omega_Ii) X_i,
+//     the coarse matrix E in the same tile-envelope layout, and dense
+//     per-instance inverses of E.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/lsq2l.h"
+
+namespace lsq2l {
+
+constexpr int TS = 32;        // tile edge
+constexpr int TT = TS * TS;   // elements per tile
+constexpr int LDT = TS + 1;   // padded leading dimension of tiles staged in LDS
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+struct SubDesc {
+  int32_t nI, nG, nIp, np;    // interior, interface, padded interior, padded total
+  int32_t ntiles, ntI;        // tiles per side, interior tiles (nIp / 32)
+  int32_t nXi, p;             // |Xi_i| and number of coarse vectors
+  int32_t seg, nGp;           // instance index, padded interface size
+  int64_t omega_off;          // int32 offset: Omega_i (nI interior then nG interface)
+  int64_t xi_off;             // int32 offset: Xi_i
+  int64_t loc_off;            // double offset: local vectors (np entries)
+  int64_t tile_base;          // offset into tile envelope tables (ntiles entries)
+  int64_t fac_off;            // element offset of the first factor tile
+  int64_t dinv_off;           // element offset of the diagonal inverse tiles
+  int64_t g_off;              // element offset of interface work matrices (nGp * nGp)
+  int64_t x_off;              // element offset of X_i (nIp * p)
+  int64_t c_off;              // first coarse index of this subdomain (within its instance)
+  int64_t cg_off;             // first coarse index in the global coarse numbering
+  int64_t w_off;              // element offset of W_i (nXi * p)
+};
+
+// Pair of subdomains that share rows of A (for the blocks of E).
+struct PairDesc {
+  int32_t i, j;               // i <= j
+  int32_t nrows;              // shared rows
+  int32_t pad;
+  int64_t rows_off;           // offset into pair row lists (pos in Xi_i, pos in Xi_j)
+};
+
+struct SegDesc {              // one least-squares instance of a batch
+  int64_t row0, m, col0, n;
+  int64_t n0, c0;             // coarse size and first global coarse index
+  int64_t einv_off;           // element offset of the dense inverse of E (n0 x n0)
+  int64_t etile0, etiles;     // first tile row of E and number of tile rows
+};
+
+// -------------------------------------------------------------------------
+// tile addressing
+// -------------------------------------------------------------------------
+__host__ __device__ inline int64_t tile_pos(const int32_t* F, const int64_t* off, int I, int J) {
+  return off[I] + (J - F[I]);
+}
+
+// -------------------------------------------------------------------------
+// MFMA helpers: one wave computes a 32 x 32 tile as 2 x 2 blocks of 16 x 16.
+// Operand lane maps (gfx950 v_mfma_*_16x16x4): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  The accumulator maps are given by acc_row/acc_col.
+// -------------------------------------------------------------------------
+template <typename T> struct Mfma;
+
+template <> struct Mfma<double> {
+  typedef double4_t acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // element v of lane l holds D[acc_row(l, v)][acc_col(l, v)]; the f64 form
+  // interleaves rows (measured on gfx950), the f32 form keeps them in blocks of 4
+  __device__ static inline int acc_row(int l, int v) { return l / 16 + 4 * v; }
+  __device__ static inline int acc_col(int l, int v) { return l % 16; }
+};
+
+template <> struct Mfma<float> {
+  typedef float4_t acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int acc_row(int l, int v) { return 4 * (l / 16) + v; }
+  __device__ static inline int acc_col(int l, int v) { return l % 16; }
+};
+
+// acc[bi * 2 + bj] covers rows 16 bi .. 16 bi + 15, columns 16 bj .. 16 bj + 15.
+template <typename T>
+__device__ inline void tile_acc_load(typename Mfma<T>::acc_t acc[4], const T* C, int ldc, int lane) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = 16 * bi + Mfma<T>::acc_row(lane, v), c = 16 * bj + Mfma<T>::acc_col(lane, v);
+        acc[bi * 2 + bj][v] = C[(int64_t)c * ldc + r];
+      }
+}
+
+template <typename T>
+__device__ inline void tile_acc_store(const typename Mfma<T>::acc_t acc[4], T* C, int ldc, int lane) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = 16 * bi + Mfma<T>::acc_row(lane, v), c = 16 * bj + Mfma<T>::acc_col(lane, v);
+        C[(int64_t)c * ldc + r] = acc[bi * 2 + bj][v];
+      }
+}
+
+template <typename T>
+__device__ inline void tile_acc_zero(typename Mfma<T>::acc_t acc[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = Mfma<T>::zero();
+}
+
+// acc += sign * A * B^T with A, B 32 x 32 column-major (leading dims lda, ldb).
+template <typename T, bool NEG>
+__device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, int lda,
+                                   const T* B, int ldb, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll 2
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = A[(int64_t)(kk + lk) * lda + li];
+    T a1 = A[(int64_t)(kk + lk) * lda + 16 + li];
+    T b0 = B[(int64_t)(kk + lk) * ldb + li];
+    T b1 = B[(int64_t)(kk + lk) * ldb + 16 + li];
+    if (NEG) { a0 = -a0; a1 = -a1; }
+    acc[0] = Mfma<T>::mma(a0, b0, acc[0]);
+    acc[1] = Mfma<T>::mma(a0, b1, acc[1]);
+    acc[2] = Mfma<T>::mma(a1, b0, acc[2]);
+    acc[3] = Mfma<T>::mma(a1, b1, acc[3]);
+  }
+}
+
+// -------------------------------------------------------------------------
+// Cholesky and inverse of one 32 x 32 diagonal tile staged in LDS
+// (column-major, leading dimension LDT).  All threads of the block call it.
+// W: the tile (lower part read; destroyed), L: the factor, Inv: L^{-1}.
+// Returns false (in every thread) if a pivot is not positive and finite; the
+// pivot is then replaced by 1 so that the caller can continue and report.
+// -------------------------------------------------------------------------
+template <typename T>
+__device__ inline bool tile_potrf_inv_lds(T* W, T* L, T* Inv, int tid, int nthr) {
+  bool ok = true;
+  for (int k = 0; k < TS; ++k) {
+    __syncthreads();
+    T d = W[k * LDT + k];
+    if (!(d > T(0)) || !(d < T(INFINITY))) { ok = false; d = T(1); }
+    T sd = sqrt(d);
+    T inv_sd = T(1) / sd;
+    // column k of the factor
+    for (int i = k + tid; i < TS; i += nthr) L[k * LDT + i] = (i == k) ? sd : W[k * LDT + i] * inv_sd;
+    for (int i = tid; i < k; i += nthr) L[k * LDT + i] = T(0);
+    // trailing update, reading the unscaled column k
+    T invd = T(1) / d;
+    const int rem = TS - 1 - k;
+    for (int e = tid; e < rem * rem; e += nthr) {
+      int i = k + 1 + e % rem, j = k + 1 + e / rem;
+      if (j <= i) W[j * LDT + i] -= W[k * LDT + i] * W[k * LDT + j] * invd;
+    }
+  }
+  __syncthreads();
+  // inverse of the lower-triangular factor, one column per thread
+  for (int j = tid; j < TS; j += nthr) {
+    for (int i = 0; i < j; ++i) Inv[j * LDT + i] = T(0);
+    Inv[j * LDT + j] = T(1) / L[j * LDT + j];
+    for (int i = j + 1; i < TS; ++i) {
+      T s = T(0);
+      for (int k = j; k < i; ++k) s += L[k * LDT + i] * Inv[j * LDT + k];
+      Inv[j * LDT + i] = -s / L[i * LDT + i];
+    }
+  }
+  __syncthreads();
+  return ok;
+}
+
+// -------------------------------------------------------------------------
+// host-side helpers shared by the translation units
+// -------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define LSQ2L_HIP_TRY(expr)                                                              \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) {                                                              \
+      ::lsq2l::set_error(std::string("HIP error ") + hipGetErrorString(_e) + " at " +   \
+                         __FILE__ + ":" + std::to_string(__LINE__) + " in " #expr);      \
+      return LSQ2L_EHIP;                                                                 \
+    }                                                                                    \
+  } while (0)
+
+}  // namespace lsq2l

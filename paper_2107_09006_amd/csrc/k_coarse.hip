@@ -1,0 +1,715 @@
+// Coarse space and coarse solve (Lemma 2.4, eq. gevp, Algorithm 1).
+//
+// Selection.  With the 0/1 partition of unity D_i of Section 3.3.1 and the
+// splitting of eq. (spsd_normal_eq), a vector v = (x, y) of eq. (gevp),
+// D C D v = lambda Ct v, has lambda = 0 when x = 0; for x != 0 the interface
+// part can be eliminated, which leaves the interior pencil
+//     S x = mu C_I x,  S = C_I - Ct_IG Ct_GG^+ Ct_GI,  mu = 1 / lambda,
+// so lambda > 1/tau is mu < tau.  Its nonzero spectrum is that of the small
+// interface pencil (size n_Gamma instead of n_I)
+//     T y = sigma^2 Ct_GG y  on range(Ct_GG),  T = Ct_GI C_I^{-1} Ct_IG,
+// with sigma^2 = 1 - mu, and the interior vectors are x = C_I^{-1} Ct_IG y.
+// Because Ct_IG = C_IG, L_GI^T = L_I^{-1} C_IG in the Cholesky factor of
+// C_ii, so T = L_GI L_GI^T comes straight from the local factor.
+// Selected: sigma^2 > 1 - tau.  X_i = L_I^{-T} L_GI^T Y diag(1/sigma) is
+// C_I-orthonormal (X^T C_I X = diag(sigma)^-1 Y^T T Y diag(sigma)^-1 = I).
+//
+// Coarse operator.  W = A R_0^T has block i = A(Xi_i, Omega_Ii) X_i; the
+// Galerkin matrix E = W^T W (Algorithm 1, C_00 = (A R_0^T)^T (A R_0^T)) has a
+// block for every pair of subdomains that share rows.  E is factored in the
+// same tile-envelope layout as the local matrices and its dense inverse is
+// formed for the per-iteration coarse solve.
+#include "kernels.hpp"
+
+namespace lsq2l {
+
+// ---------------------------------------------------------------------------
+// tile helpers for multi-right-hand-side products (one 16 x 16 quadrant per wave)
+// ---------------------------------------------------------------------------
+// acc += op(A) * B for the quadrant (bi, bj); op(A) = A or A^T; A, B are
+// 32 x 32 column-major with leading dimensions lda, ldb.
+template <bool TA>
+__device__ inline void quad_mma(double4_t& acc, const double* A, int lda, const double* B, int ldb,
+                                int bi, int bj, int lane, bool neg) {
+  const int li = lane % 16, lk = lane / 16;
+  for (int kk = 0; kk < TS; kk += 4) {
+    const int k = kk + lk;
+    double a = TA ? A[(int64_t)(16 * bi + li) * lda + k] : A[(int64_t)k * lda + 16 * bi + li];
+    double b = B[(int64_t)(16 * bj + li) * ldb + k];
+    if (neg) a = -a;
+    acc = Mfma<double>::mma(a, b, acc);
+  }
+}
+
+__device__ inline void quad_load(double4_t& acc, const double* C, int ldc, int bi, int bj, int lane) {
+  for (int v = 0; v < 4; ++v)
+    acc[v] = C[(int64_t)(16 * bj + Mfma<double>::acc_col(lane, v)) * ldc + 16 * bi +
+               Mfma<double>::acc_row(lane, v)];
+}
+
+__device__ inline void quad_store(const double4_t& acc, double* C, int ldc, int bi, int bj, int lane) {
+  for (int v = 0; v < 4; ++v)
+    C[(int64_t)(16 * bj + Mfma<double>::acc_col(lane, v)) * ldc + 16 * bi +
+      Mfma<double>::acc_row(lane, v)] = acc[v];
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x, n = blockDim.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = n / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// T = L_GI L_GI^T (interface x interface, full symmetric, ld nGp)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gamma_T(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+          const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
+          double* __restrict__ Tg) {
+  const SubDesc d = subs[blockIdx.x];
+  if (d.nG == 0) return;
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  double* T = Tg + d.g_off;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  const int ng = d.ntiles - d.ntI;
+  int item = 0;
+  for (int a = 0; a < ng; ++a)
+    for (int b = 0; b <= a; ++b, ++item) {
+      if (item % nwaves != wave) continue;
+      const int Ia = d.ntI + a, Ib = d.ntI + b;
+      double4_t acc[4];
+      tile_acc_zero<double>(acc);
+      const int K0 = max(F[Ia], F[Ib]);
+      for (int K = K0; K < d.ntI; ++K)
+        tile_mma_nt<double, false>(acc, A + tile_pos(F, off, Ia, K) * TT, TS,
+                                   A + tile_pos(F, off, Ib, K) * TT, TS, lane);
+      tile_acc_store<double>(acc, T + (int64_t)(b * TS) * d.nGp + a * TS, d.nGp, lane);
+      if (a != b) {
+        // transpose block
+        for (int q = 0; q < 4; ++q)
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * (q / 2) + Mfma<double>::acc_row(lane, v);
+            const int c = 16 * (q % 2) + Mfma<double>::acc_col(lane, v);
+            T[(int64_t)(a * TS + r) * d.nGp + b * TS + c] = acc[q][v];
+          }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver for one n x n matrix per workgroup (n <= nGp):
+// Householder tridiagonalization, explicit orthogonal factor, then the
+// implicit QL iteration with Wilkinson shifts accumulating the rotations.
+// A (column-major, ld) is destroyed; Q receives the eigenvectors, ev the
+// eigenvalues (unsorted).  Scratch in LDS: v, w (n each), rotations (2n).
+// ---------------------------------------------------------------------------
+struct EigLds {
+  double* v; double* w; double* cs; double* sn; double* d; double* e; double* red;
+};
+
+__device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* fail) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  double* d = L.d;
+  double* e = L.e;
+  // -- tridiagonalization A = Q T Q^T (lower), reflectors kept in A
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;                    // length of x = A[k+1:n, k]
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += nthr) { double t = A[(int64_t)k * ld + k + 1 + i]; part += t * t; }
+    const double xnorm2 = block_sum(part, L.red);
+    const double alpha = A[(int64_t)k * ld + k + 1];
+    double tau = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      const double sc = 1.0 / (alpha - beta);
+      for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : A[(int64_t)k * ld + k + 1 + i] * sc;
+    } else {
+      for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) { e[k] = beta; d[k] = A[(int64_t)k * ld + k]; L.cs[k] = tau; }
+    for (int i = 1 + tid; i < m; i += nthr) A[(int64_t)k * ld + k + 1 + i] = L.v[i];
+    if (tau != 0.0) {
+      // w = tau * A22 v
+      for (int i = tid; i < m; i += nthr) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += A[(int64_t)(k + 1 + j) * ld + k + 1 + i] * L.v[j];
+        L.w[i] = tau * s;
+      }
+      __syncthreads();
+      double pp = 0.0;
+      for (int i = tid; i < m; i += nthr) pp += L.w[i] * L.v[i];
+      const double wv = block_sum(pp, L.red);
+      const double a2 = -0.5 * tau * wv;
+      for (int i = tid; i < m; i += nthr) L.w[i] += a2 * L.v[i];
+      __syncthreads();
+      for (int64_t q = tid; q < (int64_t)m * m; q += nthr) {
+        const int i = (int)(q % m), j = (int)(q / m);
+        A[(int64_t)(k + 1 + j) * ld + k + 1 + i] -= L.v[i] * L.w[j] + L.w[i] * L.v[j];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) { e[n - 2] = A[(int64_t)(n - 2) * ld + n - 1]; d[n - 2] = A[(int64_t)(n - 2) * ld + n - 2]; }
+    d[n - 1] = A[(int64_t)(n - 1) * ld + n - 1];
+    e[n - 1] = 0.0;
+  }
+  __syncthreads();
+  // -- explicit Q = H_0 H_1 ... H_{n-3}
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int i = (int)(q % n), j = (int)(q / n);
+    Q[(int64_t)j * ld + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
+  for (int k = n - 3; k >= 0; --k) {
+    const double tau = L.cs[k];
+    if (tau == 0.0) continue;
+    const int m = n - k - 1;
+    for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : A[(int64_t)k * ld + k + 1 + i];
+    __syncthreads();
+    // u_j = v^T Q[k+1:, j], one wave per column
+    for (int j = wave; j < m; j += nwaves) {
+      double s = 0.0;
+      for (int i = lane; i < m; i += 64) s += L.v[i] * Q[(int64_t)(k + 1 + j) * ld + k + 1 + i];
+      for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
+      if (lane == 0) L.w[j] = s;
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)m * m; q += nthr) {
+      const int i = (int)(q % m), j = (int)(q / m);
+      Q[(int64_t)(k + 1 + j) * ld + k + 1 + i] -= tau * L.v[i] * L.w[j];
+    }
+    __syncthreads();
+  }
+  // -- implicit QL on (d, e) with the rotations applied to the rows of Q.
+  // An off-diagonal is negligible below eps * ||T|| (absolute accuracy is all
+  // the selection needs; a relative test stalls on clusters at rounding level).
+  __shared__ int s_m, s_nrot;
+  __shared__ double s_anorm;
+  if (tid == 0) {
+    double an = 0.0;
+    for (int i = 0; i < n; ++i)
+      an = fmax(an, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+    s_anorm = an;
+  }
+  __syncthreads();
+  const double small = 2.220446049250313e-16 * s_anorm;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    while (true) {
+      if (tid == 0) {
+        int m = l;
+        for (; m < n - 1; ++m)
+          if (fabs(e[m]) <= small) break;   // negligible coupling
+        s_m = m;
+        s_nrot = 0;
+        if (m != l) {
+          if (iter >= 60) { atomicExch(fail, 1); }
+          double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+          double r = hypot(g, 1.0);
+          g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+          double s = 1.0, c = 1.0, p = 0.0;
+          int i = m - 1;
+          bool early = false;
+          for (; i >= l; --i) {
+            const double f = s * e[i], b = c * e[i];
+            r = hypot(f, g);
+            e[i + 1] = r;
+            if (r == 0.0) { d[i + 1] -= p; e[m] = 0.0; early = true; break; }
+            s = f / r; c = g / r;
+            g = d[i + 1] - p;
+            r = (d[i] - g) * s + 2.0 * c * b;
+            p = s * r;
+            d[i + 1] = g + p;
+            g = c * r - b;
+            L.cs[s_nrot] = c; L.sn[s_nrot] = s; s_nrot++;
+          }
+          if (!early) { d[l] -= p; e[l] = g; e[m] = 0.0; }
+        }
+      }
+      __syncthreads();
+      const int m = s_m, nrot = s_nrot;
+      if (m == l) break;
+      // rotation t acts on columns (i, i+1), i = m - 1 - t
+      for (int row = tid; row < n; row += nthr) {
+        for (int t = 0; t < nrot; ++t) {
+          const int i = m - 1 - t;
+          const double c = L.cs[t], s = L.sn[t];
+          double* qi = Q + (int64_t)i * ld + row;
+          double* qi1 = Q + (int64_t)(i + 1) * ld + row;
+          const double f = *qi1;
+          *qi1 = s * (*qi) + c * f;
+          *qi = c * (*qi) - s * f;
+        }
+      }
+      __syncthreads();
+      if (++iter > 60) break;
+    }
+  }
+  __syncthreads();
+}
+
+// Reduced interface pencil per subdomain; work holds 4 matrices of nGp x nGp:
+//   M0: Ct (equilibrated), then Y (selected, nG x p)
+//   M1: eigenvectors of the scaled Ct, then K's eigenvectors
+//   M2: W = D2 V_r Lambda_r^{-1/2}
+//   M3: T W, then K = W^T T W
+constexpr int EIG_MAXN = 1024;
+
+__global__ void __launch_bounds__(256)
+k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
+              const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
+              int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail) {
+  __shared__ double sv[EIG_MAXN], sw[EIG_MAXN], scs[EIG_MAXN], ssn[EIG_MAXN], sd[EIG_MAXN],
+      se[EIG_MAXN], sred[256];
+  __shared__ int32_t sel[EIG_MAXN];
+  __shared__ int s_r, s_p;
+  const int i = blockIdx.x;
+  const SubDesc d = subs[i];
+  const int n = d.nG, ld = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
+  if (n == 0 || n > EIG_MAXN) {
+    if (tid == 0) { p_out[i] = 0; if (n > EIG_MAXN) atomicExch(fail, 2); }
+    return;
+  }
+  const int64_t mm = (int64_t)ld * ld;
+  double* M0 = work + 4 * d.g_off;
+  double* M1 = M0 + mm;
+  double* M2 = M1 + mm;
+  double* M3 = M2 + mm;
+  const double* Ct = ctg + d.g_off;
+  const double* T = Tg + d.g_off;
+  EigLds L{sv, sw, scs, ssn, sd, se, sred};
+  // D2 = diag(Ct)^{-1/2}; M0 = D2 Ct D2 (full symmetric from the lower triangle)
+  for (int a = tid; a < n; a += nthr) sw[a] = 1.0 / sqrt(Ct[(int64_t)a * ld + a]);
+  __syncthreads();
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
+    const int r = (int)(q % n), c = (int)(q / n);
+    const double v = (r >= c) ? Ct[(int64_t)c * ld + r] : Ct[(int64_t)r * ld + c];
+    M0[(int64_t)c * ld + r] = v * sw[r] * sw[c];
+  }
+  __syncthreads();
+  for (int a = tid; a < n; a += nthr) M3[a] = sw[a];   // keep D2 in M3's first column
+  __syncthreads();
+  wg_syev(M0, M1, n, ld, L, fail);
+  // rank of Ct: eigenvalues above n * eps * max
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < n; ++k) mx = fmax(mx, sd[k]);
+    const double tol = n * 2.220446049250313e-16 * mx;
+    int r = 0;
+    for (int k = 0; k < n; ++k) if (sd[k] > tol) sel[r++] = k;
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  // M2 = D2 V_r Lambda_r^{-1/2}
+  for (int64_t q = tid; q < (int64_t)n * r; q += nthr) {
+    const int a = (int)(q % n), c = (int)(q / n);
+    const int k = sel[c];
+    M2[(int64_t)c * ld + a] = M3[a] * M1[(int64_t)k * ld + a] / sqrt(sd[k]);
+  }
+  __syncthreads();
+  // M3 = T M2 (n x r)
+  for (int64_t q = tid; q < (int64_t)n * r; q += nthr) {
+    const int a = (int)(q % n), c = (int)(q / n);
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += T[(int64_t)b * ld + a] * M2[(int64_t)c * ld + b];
+    M3[(int64_t)c * ld + a] = s;
+  }
+  __syncthreads();
+  // M0 = K = M2^T M3 (r x r), symmetrised
+  for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {
+    const int a = (int)(q % r), c = (int)(q / r);
+    if (a < c) continue;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < n; ++b) {
+      s1 += M2[(int64_t)a * ld + b] * M3[(int64_t)c * ld + b];
+      s2 += M2[(int64_t)c * ld + b] * M3[(int64_t)a * ld + b];
+    }
+    const double v = 0.5 * (s1 + s2);
+    M0[(int64_t)c * ld + a] = v;
+    M0[(int64_t)a * ld + c] = v;
+  }
+  __syncthreads();
+  if (r > 0) wg_syev(M0, M1, r, ld, L, fail);
+  // select sigma^2 > 1 - tau, largest first (ties: lower index first)
+  if (tid == 0) {
+    int p = 0;
+    for (int k = 0; k < r; ++k)
+      if (sd[k] > 1.0 - tau) sel[p++] = k;
+    for (int a = 1; a < p; ++a) {        // insertion sort, descending value
+      const int key = sel[a];
+      int b = a - 1;
+      while (b >= 0 && (sd[sel[b]] < sd[key] || (sd[sel[b]] == sd[key] && sel[b] > key))) {
+        sel[b + 1] = sel[b];
+        --b;
+      }
+      sel[b + 1] = key;
+    }
+    if (nev_max > 0 && p > nev_max) p = nev_max;
+    s_p = p;
+    p_out[i] = p;
+  }
+  __syncthreads();
+  const int p = s_p;
+  // Y = M2 U_sel into M0 (n x p, padding rows zero); sigma into sig_out
+  for (int64_t q = tid; q < (int64_t)ld * p; q += nthr) {
+    const int a = (int)(q % ld), c = (int)(q / ld);
+    double s = 0.0;
+    if (a < n) {
+      const int k = sel[c];
+      for (int b = 0; b < r; ++b) s += M2[(int64_t)b * ld + a] * M1[(int64_t)k * ld + b];
+    }
+    M0[(int64_t)c * ld + a] = s;
+  }
+  for (int c = tid; c < p; c += nthr) sig_out[d.loc_off + c] = sqrt(sd[sel[c]]);
+}
+
+// X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
+__global__ void __launch_bounds__(256)
+k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+           const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
+           const double* __restrict__ dinv, const double* __restrict__ scale,
+           const double* __restrict__ work, const double* __restrict__ sig, double* __restrict__ X) {
+  const SubDesc d = subs[blockIdx.x];
+  if (d.p == 0) return;
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  const double* Di = dinv + d.dinv_off;
+  const double* Y = work + 4 * d.g_off;     // nGp x p, ld nGp
+  double* H = X + d.x_off;                 // nIp x p, ld nIp
+  const int p = d.p, ldh = d.nIp, ldy = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
+  // H_J = sum over interface tile rows I with F(I) <= J of L(I,J)^T Y_I
+  for (int J = 0; J < d.ntI; ++J) {
+    for (int q = tid; q < TS * p; q += nthr) {
+      const int c = q % TS, k = q / TS;
+      double s = 0.0;
+      for (int I = max(d.ntI, 0); I < d.ntiles; ++I) {
+        if (F[I] > J) continue;
+        const double* t = A + tile_pos(F, off, I, J) * TT;
+        const double* y = Y + (int64_t)k * ldy + (I - d.ntI) * TS;
+        for (int rr = 0; rr < TS; ++rr) s += t[c * TS + rr] * y[rr];
+      }
+      H[(int64_t)k * ldh + J * TS + c] = s;
+    }
+  }
+  __syncthreads();
+  // backward substitution with L_I^T (interior tiles only)
+  __shared__ double xs[TS * 64];
+  for (int I = d.ntI - 1; I >= 0; --I) {
+    const double* inv = Di + (int64_t)I * TT;
+    for (int k0 = 0; k0 < p; k0 += 64) {
+      const int kb = min(64, p - k0);
+      for (int q = tid; q < TS * kb; q += nthr) {
+        const int rr = q % TS, k = k0 + q / TS;
+        double s = 0.0;
+        for (int c = 0; c < TS; ++c) s += inv[rr * TS + c] * H[(int64_t)k * ldh + I * TS + c];
+        xs[q] = s;
+      }
+      __syncthreads();
+      for (int q = tid; q < TS * kb; q += nthr) {
+        const int rr = q % TS, k = k0 + q / TS;
+        H[(int64_t)k * ldh + I * TS + rr] = xs[q];
+      }
+      __syncthreads();
+      for (int K = F[I]; K < I; ++K) {
+        const double* t = A + tile_pos(F, off, I, K) * TT;
+        for (int q = tid; q < TS * kb; q += nthr) {
+          const int c = q % TS, k = k0 + q / TS;
+          double s = 0.0;
+          for (int rr = 0; rr < TS; ++rr) s += t[c * TS + rr] * xs[(q / TS) * TS + rr];
+          H[(int64_t)k * ldh + K * TS + c] -= s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // scale rows by S_I and columns by 1/sigma; zero the padding rows
+  const double* s_loc = scale + d.loc_off;
+  for (int64_t q = tid; q < (int64_t)ldh * p; q += nthr) {
+    const int a = (int)(q % ldh), k = (int)(q / ldh);
+    H[q] = (a < d.nI) ? H[q] * s_loc[a] / sig[d.loc_off + k] : 0.0;
+  }
+}
+
+// W_i = A(Xi_i, Omega_Ii) X_i  (nXi x p, column-major)
+__global__ void __launch_bounds__(256)
+k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
+           const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
+           const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+           const double* __restrict__ vals, const double* __restrict__ X, double* __restrict__ W) {
+  const int i = blockIdx.x;
+  const SubDesc d = subs[i];
+  if (d.p == 0) return;
+  const int32_t* rows = xi + d.xi_off;
+  const double* Xi = X + d.x_off;
+  double* Wi = W + d.w_off;
+  for (int64_t q = threadIdx.x; q < (int64_t)d.nXi * d.p; q += blockDim.x) {
+    const int rho = (int)(q % d.nXi), k = (int)(q / d.nXi);
+    const int r = rows[rho];
+    double s = 0.0;
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      const int c = colind[e];
+      if (part[c] == i) s += vals[e] * Xi[(int64_t)k * d.nIp + locown[c]];
+    }
+    Wi[q] = s;
+  }
+}
+
+// Blocks of E = W^T W for every pair (i <= j) sharing rows; lower part only,
+// in the tile-envelope layout of E (global coarse numbering).
+__global__ void __launch_bounds__(256)
+k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
+           const int32_t* __restrict__ pair_rows, const int32_t* __restrict__ eF,
+           const int64_t* __restrict__ eOff, const double* __restrict__ W,
+           double* __restrict__ efac) {
+  const PairDesc pr = pairs[blockIdx.x];
+  const SubDesc di = subs[pr.i], dj = subs[pr.j];
+  const double* Wi = W + di.w_off;
+  const double* Wj = W + dj.w_off;
+  const int32_t* rl = pair_rows + 2 * pr.rows_off;
+  for (int64_t q = threadIdx.x; q < (int64_t)di.p * dj.p; q += blockDim.x) {
+    const int k = (int)(q % di.p), l = (int)(q / di.p);
+    const int64_t row = dj.cg_off + l, col = di.cg_off + k;
+    if (pr.i == pr.j && row < col) continue;
+    double s = 0.0;
+    if (pr.i == pr.j) {
+      for (int rho = 0; rho < di.nXi; ++rho)
+        s += Wi[(int64_t)k * di.nXi + rho] * Wj[(int64_t)l * dj.nXi + rho];
+    } else {
+      for (int t = 0; t < pr.nrows; ++t)
+        s += Wi[(int64_t)k * di.nXi + rl[2 * t]] * Wj[(int64_t)l * dj.nXi + rl[2 * t + 1]];
+    }
+    const int I = (int)(row / TS), J = (int)(col / TS);
+    efac[tile_pos(eF, eOff, I, J) * TT + (col % TS) * TS + (row % TS)] = s;
+  }
+}
+
+// One step J of the right-looking tile Cholesky of E: diagonal tile and panel
+// (one workgroup), then the trailing update (one wave per pair of rows).
+__global__ void __launch_bounds__(256)
+k_echol_diag(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
+             const int32_t* __restrict__ rows, int nr, double* __restrict__ efac,
+             double* __restrict__ edinv, int32_t* __restrict__ status) {
+  __shared__ double sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
+  double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
+  for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
+  const bool ok = tile_potrf_inv_lds<double>(sW, sL, sInv, tid, nthr);
+  for (int e = tid; e < TT; e += nthr) {
+    Ajj[e] = sL[(e / TS) * LDT + e % TS];
+    edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
+  }
+  if (!ok && tid == 0) atomicCAS(status, 0, J + 1);
+  for (int a = wave; a < nr; a += nwaves) {
+    double* Aij = efac + tile_pos(eF, eOff, rows[a], J) * TT;
+    double4_t acc[4];
+    tile_acc_zero<double>(acc);
+    tile_mma_nt<double, false>(acc, Aij, TS, sInv, LDT, lane);
+    tile_acc_store<double>(acc, Aij, TS, lane);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_echol_update(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
+               const int32_t* __restrict__ rows, int nr, double* __restrict__ efac) {
+  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) / 64, lane = threadIdx.x % 64;
+  const int64_t npairs = (int64_t)nr * (nr + 1) / 2;
+  if (gw >= npairs) return;
+  // pair index -> (a, b), a >= b
+  int a = (int)((sqrt(8.0 * gw + 1.0) - 1.0) / 2.0);
+  while ((int64_t)a * (a + 1) / 2 > gw) --a;
+  while ((int64_t)(a + 1) * (a + 2) / 2 <= gw) ++a;
+  const int b = (int)(gw - (int64_t)a * (a + 1) / 2);
+  const int Ia = rows[a], Ib = rows[b];
+  double* Cab = efac + tile_pos(eF, eOff, Ia, Ib) * TT;
+  double4_t acc[4];
+  tile_acc_load<double>(acc, Cab, TS, lane);
+  tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, Ia, J) * TT, TS,
+                            efac + tile_pos(eF, eOff, Ib, J) * TT, TS, lane);
+  tile_acc_store<double>(acc, Cab, TS, lane);
+}
+
+// Dense inverse of E per instance: column block c (32 columns) solves
+// L L^T X = I(:, c) by tile forward and backward substitution, 4 waves each
+// owning one 16 x 16 quadrant of the 32 x 32 right-hand-side tile.
+__global__ void __launch_bounds__(256)
+k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
+       const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
+       const double* __restrict__ efac, const double* __restrict__ edinv, double* __restrict__ einv) {
+  __shared__ double sY[TS * LDT];
+  const int cglob = blockIdx.x;
+  const SegDesc sg = segs[seg_of_tile[cglob]];
+  const int t0 = (int)sg.etile0, nt = (int)sg.etiles;
+  const int c = cglob - t0;                   // local tile column
+  const int ld = nt * TS;
+  double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;   // ld x 32, column-major
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int bi = wave / 2, bj = wave % 2;
+  // zero the column block
+  for (int64_t q = threadIdx.x; q < (int64_t)ld * TS; q += blockDim.x) Xc[q] = 0.0;
+  __syncthreads();
+  // forward: Y_I = Inv(I,I) (delta_{I c} I - sum_K L(I,K) Y_K), I >= c
+  for (int I = c; I < nt; ++I) {
+    const int Ig = t0 + I;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    if (I == c) {
+      for (int v = 0; v < 4; ++v)
+        acc[v] = (16 * bi + Mfma<double>::acc_row(lane, v) == 16 * bj + Mfma<double>::acc_col(lane, v)) ? 1.0 : 0.0;
+    }
+    for (int K = max(eF[Ig] - t0, c); K < I; ++K)
+      quad_mma<false>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld, bi, bj,
+                      lane, true);
+    quad_store(acc, sY, LDT, bi, bj, lane);
+    __syncthreads();
+    double4_t y = {0.0, 0.0, 0.0, 0.0};
+    quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+    quad_store(y, Xc + I * TS, ld, bi, bj, lane);
+    __syncthreads();
+  }
+  // backward: X_I = Inv(I,I)^T Y_I; Y_K -= L(I,K)^T X_I for K in [F(I), I)
+  for (int I = nt - 1; I >= 0; --I) {
+    const int Ig = t0 + I;
+    for (int e = threadIdx.x; e < TT; e += blockDim.x)
+      sY[(e / TS) * LDT + e % TS] = Xc[(int64_t)(e / TS) * ld + I * TS + e % TS];
+    __syncthreads();
+    double4_t x = {0.0, 0.0, 0.0, 0.0};
+    quad_mma<true>(x, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+    quad_store(x, Xc + I * TS, ld, bi, bj, lane);
+    __syncthreads();
+    for (int K = eF[Ig] - t0; K < I; ++K) {
+      double4_t acc;
+      quad_load(acc, Xc + K * TS, ld, bi, bj, lane);
+      quad_mma<true>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + I * TS, ld, bi, bj,
+                     lane, true);
+      quad_store(acc, Xc + K * TS, ld, bi, bj, lane);
+    }
+    __syncthreads();
+  }
+}
+
+// c_i = X_i^T r(Omega_Ii), one wave per coarse vector
+__global__ void __launch_bounds__(256)
+k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
+                  const double* __restrict__ X, const double* __restrict__ r,
+                  double* __restrict__ cvec) {
+  const SubDesc d = subs[blockIdx.x];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  const int32_t* om = omega + d.omega_off;
+  for (int k = wave; k < d.p; k += nwaves) {
+    const double* xk = X + d.x_off + (int64_t)k * d.nIp;
+    double s = 0.0;
+    for (int a = lane; a < d.nI; a += 64) s += xk[a] * r[om[a]];
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
+    if (lane == 0) cvec[d.cg_off + k] = s;
+  }
+}
+
+// d = E^{-1} c per instance, one wave per row of the dense inverse
+__global__ void __launch_bounds__(256)
+k_einv_gemv(int64_t n0tot, int S, const SegDesc* __restrict__ segs, const double* __restrict__ einv,
+            const double* __restrict__ cvec, double* __restrict__ dvec) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= n0tot) return;
+  int s = 0;
+  while (s + 1 < S && segs[s + 1].c0 <= row) ++s;
+  const SegDesc sg = segs[s];
+  const int64_t ld = sg.etiles * TS;
+  const int64_t lr = row - sg.c0;
+  const double* col = einv + sg.einv_off + lr * ld;   // symmetric: row = column
+  const double* cv = cvec + sg.c0;
+  double acc = 0.0;
+  for (int64_t j = lane; j < ld; j += 64) acc += col[j] * cv[j];
+  for (int w = 32; w > 0; w >>= 1) acc += __shfl_down(acc, w, 64);
+  if (lane == 0) dvec[row] = acc;
+}
+
+__global__ void k_set_values(int64_t n, const int64_t* __restrict__ idx, double v,
+                             double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[idx[k]] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, double* out) {
+  if (n == 0) return;
+  k_set_values<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, idx, v, out);
+}
+
+void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg) {
+  k_gamma_T<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, Tg);
+}
+
+void launch_reduced_eig(hipStream_t st, int nsub, const DevPlan& P, const double* ctg,
+                        const double* Tg, double* work, double tau, int nev_max, int32_t* p_out,
+                        double* sig_out) {
+  k_reduced_eig<<<nsub, 256, 0, st>>>(P.subs, ctg, Tg, work, tau, nev_max, p_out, sig_out,
+                                      p_out + nsub);
+}
+
+void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                     const double* dinv, const double* scale, const double* work,
+                     const double* sig, double* X) {
+  k_coarse_X<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, scale, work, sig, X);
+}
+
+void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
+                     const double* X, double* W) {
+  k_coarse_W<<<nsub, 256, 0, st>>>(P.subs, P.xi, P.part, P.locown, M.rowptr, M.colind, M.vals, X,
+                                   W);
+}
+
+void launch_coarse_E(hipStream_t st, int npairs, const DevPlan& P, const DevCoarse& Cc,
+                     const double* W, double* efac) {
+  if (npairs == 0) return;
+  k_coarse_E<<<npairs, 256, 0, st>>>(P.subs, Cc.pairs, Cc.pair_rows, Cc.eF, Cc.eOff, W, efac);
+}
+
+void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                       double* efac, double* edinv, int32_t* status) {
+  k_echol_diag<<<1, 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
+}
+
+void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                         double* efac) {
+  const int64_t npairs = (int64_t)nr * (nr + 1) / 2;
+  if (npairs == 0) return;
+  k_echol_update<<<(unsigned)((npairs + 3) / 4), 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac);
+}
+
+void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
+                 const double* edinv, double* einv) {
+  if (ntiles_total == 0) return;
+  k_einv<<<ntiles_total, 256, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, efac, edinv,
+                                       einv);
+}
+
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,
+                            const double* r, double* c) {
+  k_coarse_restrict<<<nsub, 256, 0, st>>>(P.subs, P.omega, X, r, c);
+}
+
+void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,
+                      const double* c, double* d) {
+  if (n0 == 0) return;
+  k_einv_gemv<<<(unsigned)((n0 * 64 + 255) / 256), 256, 0, st>>>(n0, S, Cc.segs, einv, c, d);
+}
+
+}  // namespace lsq2l

@@ -1,0 +1,374 @@
+// Subdomain kernels: local matrices, batched Cholesky, local solves.
+//
+//   C_ii  = A(:,Omega_i)^T A(:,Omega_i)            (Section 3.1)
+//   Ct_GG = A(Xi_i,Omega_Gamma_i)^T A(Xi_i,Omega_Gamma_i)
+//           (the only block in which the local SPSD splitting of
+//            eq. spsd_normal_eq differs from C_ii: rows outside Xi_i have no
+//            entry in Omega_Ii, so Ct_II = C_II and Ct_IG = C_IG)
+//   C_ii  = L_i L_i^T                              (Algorithm 1, local Cholesky)
+//   z_i   = C_ii^{-1} r_i                          (eq. one_level_schwarz)
+//
+// One workgroup owns one subdomain; subdomains of uneven size share a launch.
+#include "kernels.hpp"
+
+namespace lsq2l {
+
+__global__ void k_gather_values(int64_t nnz, const int32_t* __restrict__ perm,
+                                const double* __restrict__ src, double* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) dst[k] = src[perm[k]];
+}
+
+// Local position of global column c in subdomain i (or -1): interior columns
+// are found through the owner table, interface columns by binary search in
+// the sorted Omega_Gamma_i.
+__device__ inline int local_pos(int i, int c, const int32_t* __restrict__ part,
+                                const int32_t* __restrict__ locown, const int32_t* __restrict__ G,
+                                int nG, int nIp) {
+  if (part[c] == i) return locown[c];
+  int lo = 0, hi = nG;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (G[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return (lo < nG && G[lo] == c) ? nIp + lo : -1;
+}
+
+// Lower triangle of C_ii (tile-envelope layout) and of Ct_GG (dense, ld nGp).
+// Thread per local column: every write of a thread lands in its own column,
+// so the accumulation order is fixed and no atomics are needed.
+__global__ void __launch_bounds__(256)
+k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
+           const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
+           const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+           const double* __restrict__ vals, const int32_t* __restrict__ trowptr,
+           const int32_t* __restrict__ trow, const double* __restrict__ tvals,
+           const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
+           double* __restrict__ fac, double* __restrict__ ctg) {
+  const int i = blockIdx.x;
+  const SubDesc d = subs[i];
+  const int32_t* om = omega + d.omega_off;
+  const int32_t* G = om + d.nI;
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  double* A = fac + d.fac_off;
+  double* Ct = ctg + d.g_off;
+  for (int a = threadIdx.x; a < d.nI + d.nG; a += blockDim.x) {
+    const int j = om[a];
+    const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
+    const int ta = posa / TS, ra = posa % TS;
+    for (int k = trowptr[j]; k < trowptr[j + 1]; ++k) {
+      const int r = trow[k];
+      const double va = tvals[k];
+      const int e0 = rowptr[r], e1 = rowptr[r + 1];
+      bool inxi = false;
+      for (int e = e0; e < e1; ++e) inxi |= (part[colind[e]] == i);
+      for (int e = e0; e < e1; ++e) {
+        const int posc = local_pos(i, colind[e], part, locown, G, d.nG, d.nIp);
+        if (posc < posa) continue;
+        const double v = vals[e] * va;
+        const int tc = posc / TS;
+        A[tile_pos(F, off, tc, ta) * TT + ra * TS + (posc % TS)] += v;
+        if (inxi && a >= d.nI) Ct[(int64_t)(posa - d.nIp) * d.nGp + (posc - d.nIp)] += v;
+      }
+    }
+  }
+}
+
+// Symmetric diagonal equilibration S C S, S = diag(C)^{-1/2} (an exact
+// congruence: C^{-1} = S (S C S)^{-1} S), applied to C_ii and to Ct_GG; the
+// padding rows become identity rows.  scale[pos] = S_pos (0 on padding).
+__global__ void __launch_bounds__(256)
+k_equilibrate(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+              const int64_t* __restrict__ tileOff, double* __restrict__ fac,
+              double* __restrict__ ctg, double* __restrict__ scale) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  double* A = fac + d.fac_off;
+  double* s = scale + d.loc_off;
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    const bool real = pos < d.nI || (pos >= d.nIp && pos < d.nIp + d.nG);
+    double* diag = A + tile_pos(F, off, pos / TS, pos / TS) * TT + (pos % TS) * TS + pos % TS;
+    if (real) {
+      s[pos] = 1.0 / sqrt(*diag);   // diagonal > 0: every column of Omega_i has a stored entry
+    } else {
+      s[pos] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < d.ntiles; ++t) {
+    const int nt = t - F[t] + 1;
+    for (int64_t e = threadIdx.x; e < (int64_t)nt * TT; e += blockDim.x) {
+      const int J = F[t] + (int)(e / TT);
+      const int rc = (int)(e % TT);
+      const int r = t * TS + rc % TS, c = J * TS + rc / TS;
+      double* ptr = A + (off[t] + (J - F[t])) * TT + rc;
+      const double sr = s[r], sc = s[c];
+      if (r == c && sr == 0.0) *ptr = 1.0;
+      else *ptr *= sr * sc;
+    }
+  }
+  double* Ct = ctg + d.g_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)d.nGp * d.nGp; e += blockDim.x) {
+    const int r = (int)(e % d.nGp), c = (int)(e / d.nGp);
+    Ct[e] *= s[d.nIp + r] * s[d.nIp + c];   // zero on padding
+  }
+}
+
+// Rows I > J of the tile envelope whose envelope reaches column J, in
+// ascending order (ballot compaction by wave 0).  Returns the count.
+__device__ inline int envelope_rows(const int32_t* F, int J, int ntiles, int32_t* list, int cap,
+                                    int* s_count) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int cnt = 0;
+    for (int base = J + 1; base < ntiles; base += 64) {
+      const int I = base + lane;
+      const bool fl = I < ntiles && F[I] <= J;
+      const unsigned long long mask = __ballot(fl);
+      const int before = __popcll(mask & ((1ull << lane) - 1ull));
+      if (fl && cnt + before < cap) list[cnt + before] = I;
+      cnt += __popcll(mask);
+    }
+    if (lane == 0) *s_count = cnt;
+  }
+  __syncthreads();
+  return *s_count;
+}
+
+constexpr int ROWCAP = 2048;
+
+// Right-looking tile Cholesky of one envelope matrix per workgroup:
+// for each tile column J: factor and invert the diagonal tile in LDS,
+// L(I,J) = A(I,J) L(J,J)^{-T} for the envelope rows, then
+// A(I,K) -= L(I,J) L(K,J)^T for every pair of envelope rows (MFMA).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+             const int64_t* __restrict__ tileOff, T* __restrict__ fac, T* __restrict__ dinv,
+             int32_t* __restrict__ status) {
+  __shared__ T sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
+  __shared__ int32_t rows[ROWCAP];
+  __shared__ int s_count;
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  T* A = fac + d.fac_off;
+  T* Di = dinv + d.dinv_off;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
+  bool failed = false;
+  for (int J = 0; J < d.ntiles; ++J) {
+    T* Ajj = A + tile_pos(F, off, J, J) * TT;
+    for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
+    const bool ok = tile_potrf_inv_lds<T>(sW, sL, sInv, tid, nthr);
+    if (!ok) failed = true;
+    for (int e = tid; e < TT; e += nthr) {
+      Ajj[e] = sL[(e / TS) * LDT + e % TS];
+      Di[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
+    }
+    const int nr = envelope_rows(F, J, d.ntiles, rows, ROWCAP, &s_count);
+    if (nr > ROWCAP) { failed = true; break; }
+    // panel
+    for (int a = wave; a < nr; a += nwaves) {
+      T* Aij = A + tile_pos(F, off, rows[a], J) * TT;
+      typename Mfma<T>::acc_t acc[4];
+      tile_acc_zero<T>(acc);
+      tile_mma_nt<T, false>(acc, Aij, TS, sInv, LDT, lane);
+      tile_acc_store<T>(acc, Aij, TS, lane);
+    }
+    __syncthreads();
+    // trailing update over pairs (a >= b) of envelope rows
+    int item = 0;
+    for (int a = 0; a < nr; ++a)
+      for (int b = 0; b <= a; ++b, ++item) {
+        if (item % nwaves != wave) continue;
+        const int Ia = rows[a], Ib = rows[b];
+        const T* La = A + tile_pos(F, off, Ia, J) * TT;
+        const T* Lb = A + tile_pos(F, off, Ib, J) * TT;
+        T* Cab = A + tile_pos(F, off, Ia, Ib) * TT;
+        typename Mfma<T>::acc_t acc[4];
+        tile_acc_load<T>(acc, Cab, TS, lane);
+        tile_mma_nt<T, true>(acc, La, TS, Lb, TS, lane);
+        tile_acc_store<T>(acc, Cab, TS, lane);
+      }
+    __syncthreads();
+  }
+  if (failed && tid == 0) atomicCAS(status, 0, blockIdx.x + 1);
+}
+
+template __global__ void k_chol_local<double>(const SubDesc*, const int32_t*, const int64_t*,
+                                              double*, double*, int32_t*);
+template __global__ void k_chol_local<float>(const SubDesc*, const int32_t*, const int64_t*,
+                                             float*, float*, int32_t*);
+
+__global__ void k_to_float(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = (float)src[k];
+}
+
+// loc_i = S_i R_i r (padding zero)
+__global__ void __launch_bounds__(256)
+k_gather_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
+               const double* __restrict__ scale, const double* __restrict__ r,
+               double* __restrict__ loc) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* om = omega + d.omega_off;
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    double v = 0.0;
+    if (pos < d.nI) v = r[om[pos]];
+    else if (pos >= d.nIp && pos < d.nIp + d.nG) v = r[om[d.nI + pos - d.nIp]];
+    loc[d.loc_off + pos] = scale[d.loc_off + pos] * v;
+  }
+}
+
+// In-place solve L L^T y = loc_i with the tile-envelope factor and the
+// inverted diagonal tiles; forward substitution by tile rows (row access),
+// backward substitution right-looking (y_K -= L(I,K)^T x_I).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+              const int64_t* __restrict__ tileOff, const T* __restrict__ fac,
+              const T* __restrict__ dinv, double* __restrict__ loc) {
+  __shared__ double part[8][TS];
+  __shared__ double sv[TS];
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const T* A = fac + d.fac_off;
+  const T* Di = dinv + d.dinv_off;
+  double* y = loc + d.loc_off;
+  const int tid = threadIdx.x;
+  const int r = tid % TS, g = tid / TS, ng = blockDim.x / TS;
+  for (int I = 0; I < d.ntiles; ++I) {
+    double acc = 0.0;
+    for (int K = F[I] + g; K < I; K += ng) {
+      const T* t = A + (off[I] + (K - F[I])) * TT;
+      const double* yk = y + K * TS;
+#pragma unroll 8
+      for (int c = 0; c < TS; ++c) acc += (double)t[c * TS + r] * yk[c];
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < TS) {
+      double s = y[I * TS + tid];
+      for (int q = 0; q < ng; ++q) s -= part[q][tid];
+      sv[tid] = s;
+    }
+    __syncthreads();
+    if (tid < TS) {
+      const T* inv = Di + (int64_t)I * TT;
+      double s = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < TS; ++c) s += (double)inv[c * TS + tid] * sv[c];
+      y[I * TS + tid] = s;
+    }
+    __syncthreads();
+  }
+  for (int I = d.ntiles - 1; I >= 0; --I) {
+    if (tid < TS) {
+      const T* inv = Di + (int64_t)I * TT;
+      double s = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < TS; ++c) s += (double)inv[tid * TS + c] * y[I * TS + c];
+      sv[tid] = s;
+    }
+    __syncthreads();
+    if (tid < TS) y[I * TS + tid] = sv[tid];
+    for (int K = F[I] + g; K < I; K += ng) {
+      const T* t = A + (off[I] + (K - F[I])) * TT;
+      double s = 0.0;
+#pragma unroll 8
+      for (int rr = 0; rr < TS; ++rr) s += (double)t[r * TS + rr] * sv[rr];
+      y[K * TS + r] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+template __global__ void k_local_solve<double>(const SubDesc*, const int32_t*, const int64_t*,
+                                               const double*, const double*, double*);
+template __global__ void k_local_solve<float>(const SubDesc*, const int32_t*, const int64_t*,
+                                              const float*, const float*, double*);
+
+// z_j = sum over the subdomains holding column j of S_pos loc_pos (fixed
+// order), plus the coarse prolongation X_i d_i on the interior of its owner.
+__global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
+                                const int32_t* __restrict__ own_pos, const double* __restrict__ scale,
+                                const double* __restrict__ loc, const int32_t* __restrict__ part,
+                                const int32_t* __restrict__ locown, const SubDesc* __restrict__ subs,
+                                const double* __restrict__ X, const double* __restrict__ dcoarse,
+                                double* __restrict__ z) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int q = own_ptr[j]; q < own_ptr[j + 1]; ++q) {
+    const int pos = own_pos[q];
+    s += scale[pos] * loc[pos];
+  }
+  if (dcoarse != nullptr) {
+    const SubDesc d = subs[part[j]];
+    const int a = locown[j];
+    const double* xr = X + d.x_off + a;
+    const double* dc = dcoarse + d.cg_off;
+    double c = 0.0;
+    for (int k = 0; k < d.p; ++k) c += xr[(int64_t)k * d.nIp] * dc[k];
+    s += c;
+  }
+  z[j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, const double* src,
+                          double* dst) {
+  if (nnz == 0) return;
+  k_gather_values<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, perm, src, dst);
+}
+
+void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
+                     double* ctg) {
+  k_assemble<<<nsub, 256, 0, st>>>(P.subs, P.omega, P.part, P.locown, M.rowptr, M.colind, M.vals,
+                                   M.trowptr, M.trow, M.tvals, P.tileF, P.tileOff, fac, ctg);
+}
+
+void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
+                        double* scale) {
+  k_equilibrate<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, ctg, scale);
+}
+
+void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
+                       int32_t* status) {
+  k_chol_local<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, status);
+}
+
+void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst) {
+  if (n == 0) return;
+  k_to_float<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, src, dst);
+}
+
+void launch_gather_local(hipStream_t st, int nsub, const DevPlan& P, const double* scale,
+                         const double* r, double* loc) {
+  k_gather_local<<<nsub, 256, 0, st>>>(P.subs, P.omega, scale, r, loc);
+}
+
+void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                        const double* dinv, double* loc) {
+  k_local_solve<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
+}
+
+void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
+                            const float* dinv, double* loc) {
+  k_local_solve<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
+}
+
+void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
+                          const double* loc, const double* X, const double* dcoarse, double* z) {
+  if (n == 0) return;
+  k_scatter_local<<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc, P.part,
+                                                   P.locown, P.subs, X, dcoarse, z);
+}
+
+}  // namespace lsq2l

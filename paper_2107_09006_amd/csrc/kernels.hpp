@@ -1,0 +1,111 @@
+// Device-side data of a handle and the host launchers of every kernel.
+#pragma once
+
+#include "internal.hpp"
+
+namespace lsq2l {
+
+struct DevMatrix {            // A and its transpose (device copies owned by the handle)
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  int32_t* rowptr = nullptr;  // m + 1
+  int32_t* colind = nullptr;  // nnz
+  double* vals = nullptr;     // nnz
+  int32_t* trowptr = nullptr; // n + 1
+  int32_t* trow = nullptr;    // nnz
+  double* tvals = nullptr;    // nnz
+  int32_t* tperm = nullptr;   // nnz: A^T entry k is vals[tperm[k]]
+  int spmv_group = 1;         // lanes per row for A x
+  int spmvt_group = 1;        // lanes per row for A^T y
+};
+
+struct DevPlan {              // subdomain layout (device copies of HostPlan)
+  SubDesc* subs = nullptr;
+  int32_t* omega = nullptr;
+  int32_t* xi = nullptr;
+  int32_t* part = nullptr;
+  int32_t* locown = nullptr;
+  int32_t* tileF = nullptr;
+  int64_t* tileOff = nullptr;
+  int32_t* own_ptr = nullptr;
+  int32_t* own_pos = nullptr;
+};
+
+struct DevCoarse {            // coarse space and coarse operator
+  PairDesc* pairs = nullptr;
+  int32_t* pair_rows = nullptr;   // (pos in Xi_i, pos in Xi_j) per shared row
+  SegDesc* segs = nullptr;
+  int32_t* eF = nullptr;          // envelope of E (tile rows, global coarse numbering)
+  int64_t* eOff = nullptr;
+  int32_t* e_seg_of_tile = nullptr;
+};
+
+// --- sparse kernels -------------------------------------------------------
+void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
+                 const double* vals, const double* x, double* y, int group);
+void launch_grad_vals(hipStream_t st, int32_t m, const int32_t* rowptr, const int32_t* colind,
+                      const double* r, const double* lam, const double* Alam, const double* x,
+                      double* out);
+
+// --- vector / reduction kernels --------------------------------------------
+constexpr int RED_BLOCKS = 256;   // partial sums per segment
+void launch_dot(hipStream_t st, int S, const int64_t* seg_ptr, const double* a, const double* b,
+                double* partial);
+enum ScalarOp { OP_R0 = 0, OP_RHO_INIT = 1, OP_ALPHA = 2, OP_RNORM = 3, OP_BETA = 4 };
+struct Scalars {
+  double *rho, *alpha, *beta, *rn2, *r0n2, *pq;
+  int32_t* done;      // 0 active, 1 converged, 2 breakdown
+};
+void launch_scalar(hipStream_t st, int op, int S, const double* partial, const double* partial2,
+                   Scalars sc, double tol2, int flexible);
+void launch_axpy_xr(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const double* alpha,
+                    const double* p, const double* q, double* x, double* r);
+void launch_xpby(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const double* beta,
+                 const double* z, double* p);
+void launch_sub(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
+void launch_fill(hipStream_t st, int64_t n, double v, double* out);
+
+// --- subdomain kernels -------------------------------------------------------
+void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, const double* src,
+                          double* dst);
+void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
+                     double* ctg);
+void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
+                        double* scale);
+void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
+                       int32_t* status);
+void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst);
+void launch_gather_local(hipStream_t st, int nsub, const DevPlan& P, const double* scale,
+                         const double* r, double* loc);
+void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                        const double* dinv, double* loc);
+void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
+                            const float* dinv, double* loc);
+void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
+                          const double* loc, const double* X, const double* dcoarse, double* z);
+
+// --- coarse space ------------------------------------------------------------
+void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
+void launch_reduced_eig(hipStream_t st, int nsub, const DevPlan& P, const double* ctg,
+                        const double* Tg, double* work, double tau, int nev_max, int32_t* p_out,
+                        double* sig_out);
+void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                     const double* dinv, const double* scale, const double* work,
+                     const double* sig, double* X);
+void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
+                     const double* X, double* W);
+void launch_coarse_E(hipStream_t st, int npairs, const DevPlan& P, const DevCoarse& Cc,
+                     const double* W, double* efac);
+void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                       double* efac, double* edinv, int32_t* status);
+void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                         double* efac);
+void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
+                 const double* edinv, double* einv);
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,
+                            const double* r, double* c);
+void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, double* out);
+void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,
+                      const double* c, double* d);
+
+}  // namespace lsq2l

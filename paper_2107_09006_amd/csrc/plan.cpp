@@ -1,0 +1,346 @@
+// Host-side setup planner: index sets of Section 3 (Algorithm 1, lines
+// FindNonzeroRows / FindNonzeroColumns), the padded local index spaces, the
+// tile envelopes of the local matrices, and the inverse overlap map used by
+// the deterministic sum over overlapping subdomains.
+//
+// Everything here is integer work on the sparsity pattern; the floating-point
+// work of the setup runs on the device.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+
+namespace lsq2l {
+
+static inline int32_t roundup32(int32_t x) { return (x + TS - 1) / TS * TS; }
+
+bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                    std::vector<int32_t>& trowptr, std::vector<int32_t>& tcol,
+                    std::vector<int32_t>& tperm) {
+  const int64_t nnz = rowptr[m];
+  trowptr.assign((size_t)n + 1, 0);
+  tcol.resize((size_t)nnz);
+  tperm.resize((size_t)nnz);
+  for (int64_t e = 0; e < nnz; ++e) trowptr[colind[e] + 1]++;
+  for (int32_t j = 0; j < n; ++j) trowptr[j + 1] += trowptr[j];
+  std::vector<int32_t> fill(trowptr.begin(), trowptr.end() - 1);
+  for (int32_t r = 0; r < m; ++r)
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      int32_t c = colind[e];
+      int32_t k = fill[c]++;
+      tcol[k] = r;      // rows ascend inside each column (stable)
+      tperm[k] = e;     // value of A^T entry k is vals[e]
+    }
+  return true;
+}
+
+namespace {
+
+struct Scratch {
+  std::vector<int32_t> rowmark, colmark, gpos;
+  explicit Scratch(int32_t m, int32_t n) : rowmark(m, -1), colmark(n, -1), gpos(n, -1) {}
+};
+
+struct LocalOut {
+  std::vector<int32_t> xi, gamma, F;
+};
+
+void plan_one(int32_t i, int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+              const int32_t* trowptr, const int32_t* tcol, const int32_t* part,
+              const int32_t* locown, const int32_t* I, int32_t nI, Scratch& s, LocalOut& out) {
+  (void)m; (void)n;
+  // Xi_i: rows with a stored entry in a column of Omega_Ii
+  out.xi.clear();
+  for (int32_t a = 0; a < nI; ++a) {
+    int32_t c = I[a];
+    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
+      int32_t r = tcol[k];
+      if (s.rowmark[r] != i) { s.rowmark[r] = i; out.xi.push_back(r); }
+    }
+  }
+  std::sort(out.xi.begin(), out.xi.end());
+  // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii
+  out.gamma.clear();
+  for (int32_t r : out.xi)
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      int32_t c = colind[e];
+      if (part[c] != i && s.colmark[c] != i) { s.colmark[c] = i; out.gamma.push_back(c); }
+    }
+  std::sort(out.gamma.begin(), out.gamma.end());
+  const int32_t nG = (int32_t)out.gamma.size();
+  const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
+  for (int32_t g = 0; g < nG; ++g) s.gpos[out.gamma[g]] = nIp + g;
+  // row envelope of C_ii: f(a) = smallest local position coupled to a
+  std::vector<int32_t> f(np);
+  for (int32_t a = 0; a < np; ++a) f[a] = a;
+  auto scan = [&](int32_t a, int32_t c) {
+    int32_t best = f[a];
+    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
+      int32_t r = tcol[k];
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t cc = colind[e];
+        int32_t pos = (part[cc] == i) ? locown[cc] : (s.colmark[cc] == i ? s.gpos[cc] : -1);
+        if (pos >= 0 && pos < best) best = pos;
+      }
+    }
+    f[a] = best;
+  };
+  for (int32_t a = 0; a < nI; ++a) scan(a, I[a]);
+  for (int32_t g = 0; g < nG; ++g) scan(nIp + g, out.gamma[g]);
+  const int32_t nt = np / TS;
+  out.F.assign(nt, 0);
+  for (int32_t t = 0; t < nt; ++t) {
+    int32_t mn = t * TS;
+    for (int32_t a = t * TS; a < (t + 1) * TS; ++a) mn = std::min(mn, f[a]);
+    out.F[t] = mn / TS;
+  }
+}
+
+}  // namespace
+
+bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                const std::vector<int32_t>& trowptr, const std::vector<int32_t>& tcol,
+                const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
+                HostPlan& P, std::string& err) {
+  P.nparts = nparts;
+  // columns of each part, ascending, and each column's position in its part
+  std::vector<int64_t> pptr((size_t)nparts + 1, 0);
+  for (int32_t j = 0; j < n; ++j) pptr[part[j] + 1]++;
+  for (int32_t i = 0; i < nparts; ++i) {
+    if (pptr[i + 1] == 0) { err = "part " + std::to_string(i) + " is empty"; return false; }
+    pptr[i + 1] += pptr[i];
+  }
+  std::vector<int32_t> pcols((size_t)n);
+  P.locown.assign((size_t)n, 0);
+  {
+    std::vector<int64_t> fill(pptr.begin(), pptr.end() - 1);
+    for (int32_t j = 0; j < n; ++j) {
+      int64_t k = fill[part[j]]++;
+      pcols[k] = j;
+      P.locown[j] = (int32_t)(k - pptr[part[j]]);
+    }
+  }
+  // per-subdomain work in parallel
+  std::vector<LocalOut> outs((size_t)nparts);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nth = std::min<unsigned>(nth, (unsigned)nparts);
+  {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t)
+      pool.emplace_back([&, t]() {
+        Scratch s(m, n);
+        for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
+          plan_one(i, m, n, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
+                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), s, outs[i]);
+      });
+    for (auto& th : pool) th.join();
+  }
+  // offsets
+  P.subs.assign((size_t)nparts, SubDesc{});
+  int64_t omega_off = 0, xi_off = 0, loc_off = 0, tile_base = 0, fac_tiles = 0, g_off = 0;
+  for (int32_t i = 0; i < nparts; ++i) {
+    SubDesc& d = P.subs[i];
+    d.nI = (int32_t)(pptr[i + 1] - pptr[i]);
+    d.nG = (int32_t)outs[i].gamma.size();
+    d.nIp = roundup32(d.nI);
+    d.nGp = roundup32(d.nG);
+    d.np = d.nIp + d.nGp;
+    d.ntiles = d.np / TS;
+    d.ntI = d.nIp / TS;
+    d.nXi = (int32_t)outs[i].xi.size();
+    d.p = 0;
+    d.seg = seg_of_part[i];
+    d.omega_off = omega_off; omega_off += d.nI + d.nG;
+    d.xi_off = xi_off; xi_off += d.nXi;
+    d.loc_off = loc_off; loc_off += d.np;
+    d.tile_base = tile_base; tile_base += d.ntiles;
+    d.fac_off = fac_tiles * TT;
+    int64_t stored = 0;
+    for (int32_t t = 0; t < d.ntiles; ++t) stored += t - outs[i].F[t] + 1;
+    fac_tiles += stored;
+    d.dinv_off = 0;  // assigned below (separate array)
+    d.g_off = g_off; g_off += (int64_t)d.nGp * d.nGp;
+  }
+  if (loc_off >= (int64_t)1 << 31) { err = "local index space exceeds 2^31"; return false; }
+  P.total_loc = loc_off;
+  P.total_tiles = tile_base;
+  P.total_fac = fac_tiles * TT;
+  P.total_g = g_off;
+  P.omega.resize((size_t)omega_off);
+  P.xi.resize((size_t)xi_off);
+  P.tileF.resize((size_t)tile_base);
+  P.tileOff.resize((size_t)tile_base);
+  int64_t dinv = 0;
+  for (int32_t i = 0; i < nparts; ++i) {
+    SubDesc& d = P.subs[i];
+    std::memcpy(&P.omega[d.omega_off], pcols.data() + pptr[i], sizeof(int32_t) * d.nI);
+    std::memcpy(&P.omega[d.omega_off + d.nI], outs[i].gamma.data(), sizeof(int32_t) * d.nG);
+    std::memcpy(&P.xi[d.xi_off], outs[i].xi.data(), sizeof(int32_t) * d.nXi);
+    int64_t off = 0;   // relative to the subdomain's first tile (fac_off / TT)
+    for (int32_t t = 0; t < d.ntiles; ++t) {
+      P.tileF[d.tile_base + t] = outs[i].F[t];
+      P.tileOff[d.tile_base + t] = off;
+      off += t - outs[i].F[t] + 1;
+    }
+    d.dinv_off = dinv; dinv += (int64_t)d.ntiles * TT;
+  }
+  P.total_dinv = dinv;
+  // inverse overlap map: for every column, the local positions holding it,
+  // in increasing subdomain order (deterministic summation order)
+  P.own_ptr.assign((size_t)n + 1, 0);
+  for (int32_t i = 0; i < nparts; ++i) {
+    const SubDesc& d = P.subs[i];
+    for (int32_t a = 0; a < d.nI + d.nG; ++a) P.own_ptr[P.omega[d.omega_off + a] + 1]++;
+  }
+  for (int32_t j = 0; j < n; ++j) P.own_ptr[j + 1] += P.own_ptr[j];
+  P.own_pos.resize((size_t)P.own_ptr[n]);
+  {
+    std::vector<int32_t> fill(P.own_ptr.begin(), P.own_ptr.end() - 1);
+    for (int32_t i = 0; i < nparts; ++i) {
+      const SubDesc& d = P.subs[i];
+      for (int32_t a = 0; a < d.nI; ++a)
+        P.own_pos[fill[P.omega[d.omega_off + a]]++] = (int32_t)(d.loc_off + a);
+      for (int32_t g = 0; g < d.nG; ++g)
+        P.own_pos[fill[P.omega[d.omega_off + d.nI + g]]++] = (int32_t)(d.loc_off + d.nIp + g);
+    }
+  }
+  // for each row, the subdomains whose Xi contains it (with the position)
+  P.rsub_ptr.assign((size_t)m + 1, 0);
+  for (int32_t i = 0; i < nparts; ++i) {
+    const SubDesc& d = P.subs[i];
+    for (int32_t k = 0; k < d.nXi; ++k) P.rsub_ptr[P.xi[d.xi_off + k] + 1]++;
+  }
+  for (int32_t r = 0; r < m; ++r) P.rsub_ptr[r + 1] += P.rsub_ptr[r];
+  P.rsub.resize((size_t)P.rsub_ptr[m]);
+  P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
+  {
+    std::vector<int64_t> fill(P.rsub_ptr.begin(), P.rsub_ptr.end() - 1);
+    for (int32_t i = 0; i < nparts; ++i) {
+      const SubDesc& d = P.subs[i];
+      for (int32_t k = 0; k < d.nXi; ++k) {
+        int64_t q = fill[P.xi[d.xi_off + k]]++;
+        P.rsub[q] = i;
+        P.rsub_pos[q] = k;
+      }
+    }
+  }
+  return true;
+}
+
+void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& ph, CoarsePlan& C) {
+  const int nparts = H.nparts;
+  C.segs.assign(S, SegDesc{});
+  for (int i = 0; i < nparts; ++i) C.segs[H.subs[i].seg].n0 += ph[i];
+  int64_t cglob = 0;
+  for (int s = 0; s < S; ++s) {
+    SegDesc& sg = C.segs[s];
+    sg.c0 = cglob;
+    const int64_t n0p = (sg.n0 + TS - 1) / TS * TS;
+    sg.etile0 = cglob / TS;
+    sg.etiles = n0p / TS;
+    cglob += n0p;
+  }
+  std::vector<int64_t> seg_fill(S, 0);
+  int64_t xoff = 0, woff = 0;
+  for (int i = 0; i < nparts; ++i) {
+    SubDesc& d = H.subs[i];
+    d.p = ph[i];
+    d.x_off = xoff; xoff += (int64_t)d.nIp * d.p;
+    d.w_off = woff; woff += (int64_t)d.nXi * d.p;
+    d.c_off = seg_fill[d.seg];
+    d.cg_off = C.segs[d.seg].c0 + d.c_off;
+    seg_fill[d.seg] += d.p;
+  }
+  int64_t einv_off = 0;
+  C.n0 = 0;
+  for (int s = 0; s < S; ++s) {
+    C.segs[s].einv_off = einv_off;
+    einv_off += C.segs[s].etiles * TS * C.segs[s].etiles * TS;
+    C.n0 += C.segs[s].n0;
+  }
+  C.n0tot = cglob;
+  C.etiles = cglob / TS;
+  C.xtot = xoff;
+  C.wtot = woff;
+  C.einv_tot = einv_off;
+  // pairs of subdomains with p > 0 that share rows; diagonal pairs use all of Xi_i
+  std::unordered_map<int64_t, int> pid;
+  std::vector<std::vector<int32_t>> prow;
+  C.pairs.clear();
+  for (int i = 0; i < nparts; ++i)
+    if (ph[i] > 0) {
+      pid[(int64_t)i * nparts + i] = (int)C.pairs.size();
+      C.pairs.push_back(PairDesc{i, i, H.subs[i].nXi, 0, 0});
+      prow.emplace_back();
+    }
+  for (int32_t r = 0; r < m; ++r) {
+    const int64_t a0 = H.rsub_ptr[r], a1 = H.rsub_ptr[r + 1];
+    for (int64_t a = a0; a < a1; ++a)
+      for (int64_t b = a + 1; b < a1; ++b) {
+        const int i = H.rsub[a], j = H.rsub[b];   // i < j: lists follow subdomain order
+        if (ph[i] == 0 || ph[j] == 0) continue;
+        const int64_t key = (int64_t)i * nparts + j;
+        auto it = pid.find(key);
+        int id;
+        if (it == pid.end()) {
+          id = (int)C.pairs.size();
+          pid[key] = id;
+          C.pairs.push_back(PairDesc{i, j, 0, 0, 0});
+          prow.emplace_back();
+        } else {
+          id = it->second;
+        }
+        prow[id].push_back(H.rsub_pos[a]);
+        prow[id].push_back(H.rsub_pos[b]);
+      }
+  }
+  C.pair_rows.clear();
+  for (size_t k = 0; k < C.pairs.size(); ++k) {
+    if (C.pairs[k].i != C.pairs[k].j) C.pairs[k].nrows = (int32_t)(prow[k].size() / 2);
+    C.pairs[k].rows_off = (int64_t)C.pair_rows.size() / 2;
+    C.pair_rows.insert(C.pair_rows.end(), prow[k].begin(), prow[k].end());
+  }
+  // envelope of E: the coarse rows of subdomain j couple to the columns of
+  // every subdomain i <= j it pairs with
+  std::vector<int64_t> fmin(nparts, INT64_MAX);
+  for (const PairDesc& pr : C.pairs) fmin[pr.j] = std::min<int64_t>(fmin[pr.j], H.subs[pr.i].cg_off);
+  std::vector<int64_t> frow(C.n0tot);
+  for (int64_t q = 0; q < C.n0tot; ++q) frow[q] = q;
+  for (int i = 0; i < nparts; ++i)
+    for (int k = 0; k < ph[i]; ++k) frow[H.subs[i].cg_off + k] = fmin[i];
+  C.eF.assign(C.etiles, 0);
+  C.eOff.assign(C.etiles, 0);
+  C.seg_of_tile.assign(C.etiles, 0);
+  for (int s = 0; s < S; ++s)
+    for (int64_t t = C.segs[s].etile0; t < C.segs[s].etile0 + C.segs[s].etiles; ++t) C.seg_of_tile[t] = s;
+  int64_t tiles = 0;
+  for (int64_t t = 0; t < C.etiles; ++t) {
+    int64_t mn = t * TS;
+    for (int64_t q = t * TS; q < (t + 1) * TS; ++q) mn = std::min(mn, frow[q]);
+    C.eF[t] = (int32_t)(mn / TS);
+    C.eOff[t] = tiles;
+    tiles += t - C.eF[t] + 1;
+  }
+  C.efac_tiles = tiles;
+  C.pad_idx.clear();
+  for (int s = 0; s < S; ++s) {
+    const SegDesc& sg = C.segs[s];
+    for (int64_t q = sg.c0 + sg.n0; q < sg.c0 + sg.etiles * TS; ++q) {
+      const int64_t t = q / TS;
+      C.pad_idx.push_back((C.eOff[t] + (t - C.eF[t])) * TT + (q % TS) * TS + q % TS);
+    }
+  }
+  C.erows.clear();
+  C.eptr.assign(C.etiles + 1, 0);
+  for (int64_t J = 0; J < C.etiles; ++J) {
+    const int s = C.seg_of_tile[J];
+    const int64_t tend = C.segs[s].etile0 + C.segs[s].etiles;
+    for (int64_t I = J + 1; I < tend; ++I)
+      if (C.eF[I] <= J) C.erows.push_back((int32_t)I);
+    C.eptr[J + 1] = (int64_t)C.erows.size();
+  }
+}
+
+}  // namespace lsq2l

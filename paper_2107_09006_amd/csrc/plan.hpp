@@ -1,0 +1,57 @@
+// Host setup planner (integer work on the sparsity pattern).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lsq2l {
+
+struct HostPlan {
+  int32_t nparts = 0;
+  std::vector<SubDesc> subs;
+  std::vector<int32_t> omega;    // per subdomain: Omega_Ii then Omega_Gamma_i
+  std::vector<int32_t> xi;       // per subdomain: Xi_i
+  std::vector<int32_t> tileF;    // first stored tile of each tile row
+  std::vector<int64_t> tileOff;  // tile index of (I, F(I)) relative to fac_off / TT
+  std::vector<int32_t> locown;   // position of each column inside its own interior
+  std::vector<int32_t> own_ptr;  // inverse overlap map (n + 1)
+  std::vector<int32_t> own_pos;  // local-buffer positions holding each column
+  std::vector<int64_t> rsub_ptr; // for each row: subdomains whose Xi holds it
+  std::vector<int32_t> rsub, rsub_pos;
+  int64_t total_loc = 0, total_tiles = 0, total_fac = 0, total_dinv = 0, total_g = 0;
+};
+
+// CSR pattern transpose (counting sort, rows ascending inside each column);
+// tperm[k] is the index in A of the k-th entry of A^T.
+bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                    std::vector<int32_t>& trowptr, std::vector<int32_t>& tcol,
+                    std::vector<int32_t>& tperm);
+
+// Index sets, local layouts, envelopes and overlap maps of every subdomain.
+bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                const std::vector<int32_t>& trowptr, const std::vector<int32_t>& tcol,
+                const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
+                HostPlan& P, std::string& err);
+
+// Coarse numbering (per instance, subdomains in order, padded to 32), the
+// pairs of subdomains whose rows overlap (blocks of E), the tile envelope of
+// E and the row lists of its right-looking Cholesky.
+struct CoarsePlan {
+  std::vector<SegDesc> segs;
+  int64_t n0 = 0, n0tot = 0, etiles = 0, efac_tiles = 0;
+  int64_t xtot = 0, wtot = 0, einv_tot = 0;
+  std::vector<PairDesc> pairs;
+  std::vector<int32_t> pair_rows;     // (pos in Xi_i, pos in Xi_j) per shared row
+  std::vector<int32_t> eF, seg_of_tile;
+  std::vector<int64_t> eOff;
+  std::vector<int64_t> pad_idx;       // efac offsets of the diagonal of padding rows
+  std::vector<int32_t> erows;         // envelope rows of every tile column
+  std::vector<int64_t> eptr;
+};
+
+// Fills p, x_off, w_off, c_off, cg_off of every subdomain of H and the plan of E.
+void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& p, CoarsePlan& C);
+
+}  // namespace lsq2l
