@@ -1,0 +1,204 @@
+"""Benchmark: time-to-solve of two-level Schwarz PCG on the grid-gradient workload.
+
+One step = the whole hot path on one batch of synthetic input: setup
+(index sets, local matrices, batched Cholesky, coarse eigenproblems, coarse
+operator) plus the PCG solve to a 1e-8 relative normal-equation residual.
+Inputs (CSR of A, b) are resident in HBM before the timed region starts.
+
+Workload: forward-difference operator of a 1000 x 1000 grid (m = 2,998,000,
+n = 1,000,000, nnz = 4,996,000) split into 16 x 16 square-patch subdomains,
+overlap 1, tau = 0.1, seeded synthetic data.
+
+Prints ONE JSON line.  ``value`` is the time-to-solve (ms) of the mixed
+precision path; the FP64 path, its ratio, SpMV bandwidth and the roofline of
+the dominant per-iteration kernel are reported beside it, with the CPU
+oracle (a bounded sample, extrapolated) as the reported CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_step(L, dev, prob, precision):
+    """setup + solve + destroy; returns (ms, solve info, setup info)."""
+    import torch
+    t0 = time.perf_counter()
+    s = L.Solver(dev["rowptr"], dev["colind"], dev["vals"], prob.part, prob.nparts, prob.m,
+                 prob.n, prob.tau, device="cuda:0", precision=precision, tol=prob.tol)
+    x, info, _ = s.solve(dev["b"], x=dev["x"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    sinfo = s.info()
+    s.close()
+    return ms, info[0], sinfo
+
+
+def cpu_baseline(prob, iterations, budget_s=20.0):
+    """Time the oracle on a bounded sample of the same workload and
+    extrapolate: setup on k subdomains (scaled by N / k), plus ``iterations``
+    PCG iterations whose cost is the two SpMVs plus k local solves (scaled)."""
+    import oracle as O
+    import scipy.linalg as sla
+    A = prob.scipy()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    sets = O.index_sets(A, prob.part, prob.nparts)
+    t_index = time.perf_counter() - t0
+    k = 0
+    t_sub = 0.0
+    t_apply = 0.0
+    r = np.random.default_rng(0).standard_normal(prob.n)
+    while k < prob.nparts and t_sub < budget_s:
+        s = sets[k]
+        t1 = time.perf_counter()
+        Cii, Ctii = O.local_matrices(A, s)
+        F = sla.cho_factor(Cii, lower=True)
+        O.coarse_vectors(Cii, Ctii, s.nI, prob.tau)
+        t_sub += time.perf_counter() - t1
+        t2 = time.perf_counter()
+        sla.cho_solve(F, r[s.Omega])
+        t_apply += time.perf_counter() - t2
+        k += 1
+    t3 = time.perf_counter()
+    A.T @ (A @ r)
+    t_spmv = time.perf_counter() - t3
+    scale = prob.nparts / k
+    setup = t_index + t_sub * scale
+    per_it = t_spmv + t_apply * scale
+    total_ms = (setup + iterations * per_it) * 1e3
+    return {"value": round(total_ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": (f"oracle setup (local matrices, Cholesky, Lemma 2.4 eigenproblems) on "
+                       f"{k} of {prob.nparts} subdomains and {k} local solves, scaled by "
+                       f"{scale:.1f}; index sets and one A^T A p in full; {iterations} "
+                       f"iterations (the GPU count); extrapolated")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=1000)
+    ap.add_argument("--patches", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2107_09006_amd as L
+    from workloads import generators as W
+
+    log(f"[bench] generating grid {args.grid} x {args.grid}, {args.patches}^2 patches")
+    prob = W.strip_rng(W.grid_gradient(args.grid, args.patches, seed=1, tau=0.1, tol=1e-8,
+                                       name="grid_gradient"))
+    dev = {
+        "rowptr": torch.as_tensor(prob.indptr).cuda(),
+        "colind": torch.as_tensor(prob.indices).cuda(),
+        "vals": torch.as_tensor(prob.data).cuda(),
+        "b": torch.as_tensor(prob.b).cuda(),
+        "x": torch.empty(prob.n, dtype=torch.float64, device="cuda"),
+    }
+    torch.cuda.synchronize()
+    results = {}
+    for prec, name in [(L.FP64, "fp64"), (L.MIXED, "mixed")]:
+        for w in range(args.warmup):
+            ms, info, sinfo = run_step(L, dev, prob, prec)
+            log(f"[bench] warmup {name} {w}: {ms:.1f} ms, its {info['iterations']}, relres {info['relres']:.2e}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = []
+        for k in range(args.steps):
+            steps.append(run_step(L, dev, prob, prec))
+            log(f"[bench] step {name} {k}: {steps[-1][0]:.1f} ms, its {steps[-1][1]['iterations']}, "
+                f"relres {steps[-1][1]['relres']:.2e}")
+        torch.cuda.synchronize()
+        total = (time.perf_counter() - t0) * 1e3
+        results[name] = {"ms_per_step": total / args.steps, "info": steps[-1][1], "setup": steps[-1][2],
+                         "solve_ms": float(np.mean([s[1]["solve_ms"] for s in steps])),
+                         "setup_ms": float(np.mean([s[2]["t_total_ms"] for s in steps]))}
+
+    # kernel timings on a live handle of each precision
+    kern = {}
+    for prec, name in [(L.FP64, "fp64"), (L.MIXED, "mixed")]:
+        s = L.Solver(dev["rowptr"], dev["colind"], dev["vals"], prob.part, prob.nparts, prob.m,
+                     prob.n, prob.tau, precision=prec, tol=prob.tol)
+        for kid, kname in [(0, "spmv_A"), (1, "spmv_AT"), (2, "local_solve"), (3, "coarse_solve")]:
+            try:
+                ms, by = s.time_kernel(kid, reps=20)
+            except Exception as e:  # no coarse space
+                log(f"[bench] {kname}: {e}")
+                continue
+            kern[f"{kname}_{name}"] = {"ms": ms, "bytes": by, "GBs": by / ms / 1e6}
+            log(f"[bench] kernel {kname} ({name}): {ms * 1e3:.1f} us, {by / 1e6:.1f} MB, {by / ms / 1e6:.0f} GB/s")
+        s.close()
+
+    mixed, fp64 = results["mixed"], results["fp64"]
+    its = mixed["info"]["iterations"]
+    # dominant per-iteration kernel: the batched local triangular solves
+    dom = kern.get("local_solve_mixed")
+    roofline = None
+    if dom:
+        roofline = {"kernel": "k_local_solve<float>", "bound": "hbm",
+                    "achieved": round(dom["GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dom["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": dom["bytes"], "launch_ms": dom["ms"]}
+    spmv = kern.get("spmv_A_fp64")
+    spmvt = kern.get("spmv_AT_fp64")
+    out = {
+        "metric": "time-to-solve @1e-8 rel normal-eq residual; SpMV GB/s; mixed vs FP64 speedup",
+        "value": round(mixed["ms_per_step"], 2),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"grid_gradient {args.grid}x{args.grid}, {args.patches}x{args.patches} patches",
+                   "m": prob.m, "n": prob.n, "nnz": prob.nnz, "nparts": prob.nparts,
+                   "tau": prob.tau, "tol": prob.tol, "overlap": 1},
+        "iterations": its,
+        "relres": mixed["info"]["relres"],
+        "setup_ms": round(mixed["setup_ms"], 2),
+        "solve_ms": round(mixed["solve_ms"], 2),
+        "fp64_ms_per_step": round(fp64["ms_per_step"], 2),
+        "fp64_iterations": fp64["info"]["iterations"],
+        "fp64_relres": fp64["info"]["relres"],
+        "mixed_vs_fp64_speedup": round(fp64["ms_per_step"] / mixed["ms_per_step"], 3),
+        "n0": mixed["setup"]["n0"],
+        "setup_phases_ms": {k: round(mixed["setup"][k], 2) for k in
+                            ["t_plan_ms", "t_assemble_ms", "t_factor_ms", "t_eigen_ms", "t_coarse_ms"]},
+        "spmv_GBs": {"A": round(spmv["GBs"], 1) if spmv else None,
+                     "AT": round(spmvt["GBs"], 1) if spmvt else None},
+        "kernels": {k: {"us": round(v["ms"] * 1e3, 2), "MB": round(v["bytes"] / 1e6, 2),
+                        "GBs": round(v["GBs"], 1)} for k, v in kern.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(prob, its)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,19 @@ lsq2l_status lsq2l_get_subdomain(lsq2l_handle h, int32_t i, int32_t* sizes,
  */
 lsq2l_status lsq2l_get_coarse_basis(lsq2l_handle h, int32_t i, double* X);
 
+/*
+ * Profiling hook: launch one hot-path kernel `reps` times on the handle's
+ * stream between two HIP events and report the mean duration per launch
+ * (*avg_ms) and the algorithmic HBM bytes one launch must move (*bytes).
+ * kernel: 0 = y = A x, 1 = x = A^T y (CSR SpMV), 2 = batched local
+ * triangular solves of the preconditioner (precision of the handle),
+ * 3 = dense coarse solve E^{-1} c.  Buffers are the handle's own work
+ * vectors; results are discarded.  EINVAL for an unknown kernel or a kernel
+ * the handle does not use (3 without a coarse space).
+ */
+lsq2l_status lsq2l_time_kernel(lsq2l_handle h, int32_t kernel, int32_t reps, double* avg_ms,
+                               double* bytes);
+
 /* Release every resource of the handle (NULL is ignored). */
 void lsq2l_destroy(lsq2l_handle h);
 

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EH
 # every function the header declares
 EXPORTS = ["lsq2l_default_options", "lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve",
            "lsq2l_backward", "lsq2l_spmv", "lsq2l_apply_preconditioner", "lsq2l_get_info",
-           "lsq2l_get_subdomain", "lsq2l_get_coarse_basis", "lsq2l_destroy", "lsq2l_last_error"]
+           "lsq2l_get_subdomain", "lsq2l_get_coarse_basis", "lsq2l_time_kernel",
+           "lsq2l_destroy", "lsq2l_last_error"]
 
 
 class Options(C.Structure):
@@ -87,12 +88,13 @@ def load_library(path: str = LIB_PATH):
     lib.lsq2l_get_info.argtypes = [vp, C.POINTER(SetupInfo)]
     lib.lsq2l_get_subdomain.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.lsq2l_get_coarse_basis.argtypes = [vp, i32, vp]
+    lib.lsq2l_time_kernel.argtypes = [vp, i32, i32, C.POINTER(dbl), C.POINTER(dbl)]
     lib.lsq2l_destroy.argtypes = [vp]
     lib.lsq2l_destroy.restype = None
     lib.lsq2l_last_error.restype = C.c_char_p
     for name in ["lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve", "lsq2l_backward",
                  "lsq2l_spmv", "lsq2l_apply_preconditioner", "lsq2l_get_info",
-                 "lsq2l_get_subdomain", "lsq2l_get_coarse_basis"]:
+                 "lsq2l_get_subdomain", "lsq2l_get_coarse_basis", "lsq2l_time_kernel"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -131,6 +133,15 @@ def _dev(t, dtype):
     return C.c_void_p(t.data_ptr())
 
 
+def _to_device(a, dtype, device):
+    """A contiguous device tensor of the given dtype (no copy if it already is one)."""
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    npdt = {torch.int32: np.int32, torch.float64: np.float64}[dtype]
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=npdt))).to(device)
+
+
 def _stream(device):
     import torch
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
@@ -145,9 +156,9 @@ class Solver:
         lib = load_library()
         self.device = torch.device(device)
         self.m, self.n = int(m), int(n)
-        self.rowptr = torch.as_tensor(np.asarray(rowptr, dtype=np.int32)).to(self.device)
-        self.colind = torch.as_tensor(np.asarray(colind, dtype=np.int32)).to(self.device)
-        self.vals = torch.as_tensor(vals, dtype=torch.float64).to(self.device).contiguous()
+        self.rowptr = _to_device(rowptr, torch.int32, self.device)
+        self.colind = _to_device(colind, torch.int32, self.device)
+        self.vals = _to_device(vals, torch.float64, self.device)
         self.nnz = int(self.colind.numel())
         part_np = np.ascontiguousarray(np.asarray(part, dtype=np.int32))
         self.opts = default_options(**options)
@@ -173,9 +184,9 @@ class Solver:
         arr = (Problem * len(problems))()
         M = N = NNZ = 0
         for k, (rp, ci, va, pt, npart, m, n) in enumerate(problems):
-            rp_t = torch.as_tensor(np.asarray(rp, dtype=np.int32)).to(self.device)
-            ci_t = torch.as_tensor(np.asarray(ci, dtype=np.int32)).to(self.device)
-            va_t = torch.as_tensor(va, dtype=torch.float64).to(self.device).contiguous()
+            rp_t = _to_device(rp, torch.int32, self.device)
+            ci_t = _to_device(ci, torch.int32, self.device)
+            va_t = _to_device(va, torch.float64, self.device)
             pt_np = np.ascontiguousarray(np.asarray(pt, dtype=np.int32))
             self._keep += [rp_t, ci_t, va_t, pt_np]
             arr[k] = Problem(int(m), int(n), int(ci_t.numel()), rp_t.data_ptr(), ci_t.data_ptr(),
@@ -206,7 +217,10 @@ class Solver:
         return x, [i.asdict() for i in infos], st
 
     def backward(self, g, want_b=True, want_vals=True):
+        """dL/db and dL/dvals for g = dL/dx.  An adjoint solve that stops at its
+        attainable accuracy (NOT_CONVERGED) warns instead of raising."""
         import torch
+        import warnings
         lib = load_library()
         dLdb = torch.empty(self.m, dtype=torch.float64, device=self.device) if want_b else None
         dLdv = torch.empty(self.nnz, dtype=torch.float64, device=self.device) if want_vals else None
@@ -215,7 +229,9 @@ class Solver:
             st = lib.lsq2l_backward(self.handle, _dev(g, torch.float64),
                                     _dev(dLdb, torch.float64) if want_b else None,
                                     _dev(dLdv, torch.float64) if want_vals else None, infos)
-        _check(st)
+        _check(st, (OK, NOT_CONVERGED))
+        if st == NOT_CONVERGED:
+            warnings.warn(f"adjoint PCG stopped at relative residual {infos[0].relres:.2e}")
         return dLdb, dLdv, [i.asdict() for i in infos]
 
     def spmv(self, x, trans=False):
@@ -257,6 +273,15 @@ class Solver:
         X = np.zeros((max(1, d["p"]), max(1, d["I"].size)), dtype=np.float64)
         _check(load_library().lsq2l_get_coarse_basis(self.handle, int(i), X.ctypes.data))
         return X[:d["p"], :d["I"].size].T.copy()
+
+    def time_kernel(self, kernel: int, reps: int = 20):
+        """(mean ms per launch, algorithmic bytes per launch) of a hot-path kernel."""
+        import torch
+        ms, by = C.c_double(), C.c_double()
+        with torch.cuda.device(self.device):
+            _check(load_library().lsq2l_time_kernel(self.handle, int(kernel), int(reps),
+                                                    C.byref(ms), C.byref(by)))
+        return ms.value, by.value
 
     def close(self):
         if getattr(self, "handle", None):

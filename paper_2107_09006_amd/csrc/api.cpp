@@ -680,6 +680,54 @@ lsq2l_status lsq2l_get_coarse_basis(lsq2l_handle c, int32_t i, double* X) {
   return LSQ2L_OK;
 }
 
+lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, double* avg_ms,
+                               double* bytes) {
+  g_err.clear();
+  if (!c || !avg_ms || !bytes || reps < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
+  if (kernel < 0 || kernel > 3 || (kernel == 3 && !c->coarse)) { set_error("unknown or unused kernel"); return LSQ2L_EINVAL; }
+  const double m = c->M.m, n = c->M.n, nnz = (double)c->M.nnz;
+  const double eb = (c->opt.precision == LSQ2L_MIXED) ? 4.0 : 8.0;
+  switch (kernel) {
+    case 0: *bytes = 12.0 * nnz + 4.0 * (m + 1) + 8.0 * n + 8.0 * m; break;
+    case 1: *bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * m + 8.0 * n; break;
+    case 2: *bytes = 2.0 * eb * (double)(c->H.total_fac + c->H.total_dinv) + 16.0 * (double)c->H.total_loc; break;
+    default: {
+      double e = 0;
+      for (const SegDesc& sg : c->segs_h) e += (double)(sg.etiles * TS) * (double)(sg.etiles * TS);
+      *bytes = 8.0 * e + 16.0 * (double)c->n0tot;
+    }
+  }
+  launch_fill(c->st, c->M.n, 1.0, c->p);
+  launch_fill(c->st, c->M.m, 1.0, c->tm);
+  launch_fill(c->st, c->H.total_loc, 1.0, c->loc);
+  if (c->coarse) launch_fill(c->st, c->n0tot, 1.0, c->cvec);
+  hipEvent_t e0, e1;
+  LSQ2L_HIP_TRY(hipEventCreate(&e0));
+  LSQ2L_HIP_TRY(hipEventCreate(&e1));
+  auto once = [&]() {
+    switch (kernel) {
+      case 0: spmv_A(c, c->p, c->tm); break;
+      case 1: spmv_AT(c, c->tm, c->q); break;
+      case 2:
+        if (c->opt.precision == LSQ2L_MIXED) launch_local_solve_f32(c->st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
+        else launch_local_solve(c->st, c->nsub, c->P, c->fac, c->dinv, c->loc);
+        break;
+      default: launch_einv_gemv(c->st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+    }
+  };
+  once();
+  LSQ2L_HIP_TRY(hipEventRecord(e0, c->st));
+  for (int k = 0; k < reps; ++k) once();
+  LSQ2L_HIP_TRY(hipEventRecord(e1, c->st));
+  LSQ2L_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  LSQ2L_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return LSQ2L_OK;
+}
+
 void lsq2l_destroy(lsq2l_handle c) { delete c; }
 
 }  // extern "C"

@@ -1,0 +1,160 @@
+// Host-logic check of the lsq2l planner: builds the real host plan (index
+// sets, tile envelopes, overlap maps, coarse numbering and the envelope of E)
+// for a problem read from a file, then replays the address arithmetic of
+// every device kernel on the CPU and fails on the first access outside its
+// buffer or outside a tile envelope.  No GPU is used.
+// Input file: int32 header {m, n, nnz, nparts, ninstances}, then rowptr,
+// colind, part (concatenated instances) and the instance of every part.
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+#include "../../paper_2107_09006_amd/csrc/plan.hpp"
+using namespace lsq2l;
+#define CHECK(c, ...) do { if (!(c)) { fprintf(stderr, "FAIL %s:%d: ", __FILE__, __LINE__); fprintf(stderr, __VA_ARGS__); fprintf(stderr, "\n"); exit(1); } } while (0)
+
+int main(int argc, char** argv) {
+  FILE* f = fopen(argv[1], "rb");
+  int32_t hdr[5];
+  fread(hdr, 4, 5, f);
+  int32_t m = hdr[0], n = hdr[1], nnz = hdr[2], nparts = hdr[3], S = hdr[4];
+  std::vector<int32_t> rp(m + 1), ci(nnz), part(n), sop(nparts);
+  fread(rp.data(), 4, m + 1, f); fread(ci.data(), 4, nnz, f); fread(part.data(), 4, n, f); fread(sop.data(), 4, nparts, f);
+  fclose(f);
+  std::vector<int32_t> trp, tcol, tperm;
+  plan_transpose(m, n, rp.data(), ci.data(), trp, tcol, tperm);
+  for (int k = 0; k < nnz; ++k) CHECK(tperm[k] >= 0 && tperm[k] < nnz, "tperm");
+  HostPlan H; std::string err;
+  CHECK(plan_build(m, n, rp.data(), ci.data(), trp, tcol, part.data(), nparts, sop, H, err), "%s", err.c_str());
+  int64_t maxrows = 0;
+  for (int i = 0; i < nparts; ++i) {
+    const SubDesc& d = H.subs[i];
+    const int64_t fac_end = (i + 1 < nparts) ? H.subs[i + 1].fac_off : H.total_fac;
+    const int64_t stored = (fac_end - d.fac_off) / TT;
+    const int32_t* F = &H.tileF[d.tile_base];
+    const int64_t* off = &H.tileOff[d.tile_base];
+    auto tp = [&](int I, int J) -> int64_t {
+      CHECK(I >= 0 && I < d.ntiles && J <= I && J >= F[I], "tile (%d,%d) outside envelope of sub %d (F=%d)", I, J, i, I < d.ntiles ? F[I] : -1);
+      int64_t t = off[I] + (J - F[I]);
+      CHECK(t >= 0 && t < stored, "tile index %lld out of %lld", (long long)t, (long long)stored);
+      return t;
+    };
+    CHECK(off[0] == 0, "first tile offset");
+    CHECK(off[d.ntiles - 1] + (d.ntiles - 1 - F[d.ntiles - 1]) + 1 == stored, "stored count");
+    const int32_t* om = &H.omega[d.omega_off];
+    const int32_t* G = om + d.nI;
+    auto local_pos = [&](int c) -> int {
+      if (part[c] == i) return H.locown[c];
+      int lo = 0, hi = d.nG;
+      while (lo < hi) { int mid = (lo + hi) / 2; if (G[mid] < c) lo = mid + 1; else hi = mid; }
+      return (lo < d.nG && G[lo] == c) ? d.nIp + lo : -1;
+    };
+    for (int a = 0; a < d.nI; ++a) CHECK(part[om[a]] == i && H.locown[om[a]] == a, "interior order");
+    // k_assemble
+    for (int a = 0; a < d.nI + d.nG; ++a) {
+      const int j = om[a];
+      const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
+      for (int k = trp[j]; k < trp[j + 1]; ++k) {
+        const int r = tcol[k];
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+          const int posc = local_pos(ci[e]);
+          if (posc < posa) continue;
+          CHECK(posc < d.np, "posc");
+          tp(posc / TS, posa / TS);
+          if (a >= d.nI) CHECK((int64_t)(posa - d.nIp) * d.nGp + (posc - d.nIp) < (int64_t)d.nGp * d.nGp, "ct");
+        }
+      }
+    }
+    // k_chol_local / k_local_solve
+    for (int J = 0; J < d.ntiles; ++J) {
+      tp(J, J);
+      std::vector<int> rows;
+      for (int I = J + 1; I < d.ntiles; ++I) if (F[I] <= J) rows.push_back(I);
+      CHECK(rows.size() <= 2048, "ROWCAP");
+      maxrows = std::max<int64_t>(maxrows, rows.size());
+      for (size_t x = 0; x < rows.size(); ++x) {
+        tp(rows[x], J);
+        for (size_t y = 0; y <= x; ++y) tp(rows[x], rows[y]);
+      }
+      for (int K = F[J]; K < J; ++K) tp(J, K);
+    }
+    // k_gamma_T
+    for (int a = 0; a < d.ntiles - d.ntI; ++a)
+      for (int b = 0; b <= a; ++b) {
+        const int Ia = d.ntI + a, Ib = d.ntI + b;
+        for (int K = std::max(F[Ia], F[Ib]); K < d.ntI; ++K) { tp(Ia, K); tp(Ib, K); }
+      }
+    // k_coarse_X (interior backward solve)
+    for (int J = 0; J < d.ntI; ++J)
+      for (int I = d.ntI; I < d.ntiles; ++I) if (F[I] <= J) tp(I, J);
+    for (int I = 0; I < d.ntI; ++I) for (int K = F[I]; K < I; ++K) tp(I, K);
+    CHECK(d.loc_off + d.np <= H.total_loc, "loc");
+    CHECK(d.g_off + (int64_t)d.nGp * d.nGp <= H.total_g, "g");
+    CHECK(d.dinv_off + (int64_t)d.ntiles * TT <= H.total_dinv, "dinv");
+    CHECK(d.nG <= 1024, "eig limit");
+  }
+  for (size_t q = 0; q < H.own_pos.size(); ++q) CHECK(H.own_pos[q] >= 0 && H.own_pos[q] < H.total_loc, "own_pos");
+  CHECK(H.own_ptr[n] == (int32_t)H.own_pos.size(), "own_ptr");
+  // coarse plan with random p
+  std::mt19937 rng(7);
+  for (int trial = 0; trial < 3; ++trial) {
+    std::vector<int32_t> ph(nparts);
+    for (int i = 0; i < nparts; ++i) {
+      int nG = H.subs[i].nG;
+      ph[i] = (trial == 2) ? 0 : (nG ? (int)(rng() % (nG + 1)) : 0);
+      if (trial == 1 && i % 3 == 0) ph[i] = 0;
+    }
+    HostPlan H2 = H;
+    CoarsePlan C;
+    plan_coarse(H2, S, m, ph, C);
+    int64_t xt = 0, wt = 0;
+    for (int i = 0; i < nparts; ++i) {
+      const SubDesc& d = H2.subs[i];
+      CHECK(d.x_off + (int64_t)d.nIp * d.p <= C.xtot, "x");
+      CHECK(d.w_off + (int64_t)d.nXi * d.p <= C.wtot, "w");
+      CHECK(d.p == 0 || d.cg_off + d.p <= C.segs[d.seg].c0 + C.segs[d.seg].n0, "cg");
+      xt += (int64_t)d.nIp * d.p; wt += (int64_t)d.nXi * d.p;
+    }
+    CHECK(xt == C.xtot && wt == C.wtot, "totals");
+    auto etp = [&](int64_t I, int64_t J) -> int64_t {
+      CHECK(I >= 0 && I < C.etiles && J <= I && J >= C.eF[I], "E tile (%lld,%lld) outside envelope", (long long)I, (long long)J);
+      int64_t t = C.eOff[I] + (J - C.eF[I]);
+      CHECK(t >= 0 && t < C.efac_tiles, "E tile index");
+      return t;
+    };
+    for (const PairDesc& pr : C.pairs) {
+      const SubDesc &di = H2.subs[pr.i], &dj = H2.subs[pr.j];
+      CHECK(pr.i <= pr.j && di.seg == dj.seg, "pair order/segment");
+      if (pr.i != pr.j)
+        for (int t = 0; t < pr.nrows; ++t) {
+          CHECK(C.pair_rows[2 * (pr.rows_off + t)] < di.nXi && C.pair_rows[2 * (pr.rows_off + t) + 1] < dj.nXi, "pair rows");
+          CHECK(H2.xi[di.xi_off + C.pair_rows[2 * (pr.rows_off + t)]] == H2.xi[dj.xi_off + C.pair_rows[2 * (pr.rows_off + t) + 1]], "shared row");
+        }
+      for (int k = 0; k < di.p; ++k)
+        for (int l = 0; l < dj.p; ++l) {
+          int64_t row = dj.cg_off + l, col = di.cg_off + k;
+          if (pr.i == pr.j && row < col) continue;
+          etp(row / TS, col / TS);
+        }
+    }
+    for (int64_t q : C.pad_idx) CHECK(q >= 0 && q < C.efac_tiles * TT, "pad");
+    for (int64_t J = 0; J < C.etiles; ++J) {
+      etp(J, J);
+      for (int64_t a = C.eptr[J]; a < C.eptr[J + 1]; ++a) {
+        etp(C.erows[a], J);
+        for (int64_t b = C.eptr[J]; b <= a; ++b) etp(C.erows[a], C.erows[b]);
+      }
+    }
+    for (int s = 0; s < S; ++s) {
+      const SegDesc& sg = C.segs[s];
+      const int64_t t0 = sg.etile0, nt = sg.etiles;
+      for (int64_t c = 0; c < nt; ++c) {
+        for (int64_t I = c; I < nt; ++I) for (int64_t K = std::max<int64_t>(C.eF[t0 + I] - t0, c); K < I; ++K) etp(t0 + I, t0 + K);
+        for (int64_t I = nt - 1; I >= 0; --I) { CHECK(C.eF[t0 + I] - t0 >= 0, "eF segment"); for (int64_t K = C.eF[t0 + I] - t0; K < I; ++K) etp(t0 + I, t0 + K); }
+      }
+      CHECK(sg.einv_off + nt * TS * nt * TS <= C.einv_tot, "einv");
+    }
+  }
+  printf("OK subdomains=%d total_fac=%lld maxrows=%lld total_loc=%lld\n", nparts, (long long)H.total_fac, (long long)maxrows, (long long)H.total_loc);
+  return 0;
+}
