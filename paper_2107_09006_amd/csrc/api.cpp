@@ -367,7 +367,12 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       TRY(c->dalloc(&c->edinv, c->etiles * TT));
       LSQ2L_HIP_TRY(hipMemsetAsync(c->efac, 0, CP.efac_tiles * TT * sizeof(double), st));
       launch_set_values(st, (int64_t)CP.pad_idx.size(), d_pad, 1.0, c->efac);
-      launch_coarse_E(st, (int)CP.pairs.size(), c->P, c->Cc, c->W, c->efac);
+      {
+        int32_t* d_items = nullptr;
+        TRY(c->upload(&d_items, CP.items));
+        c->Cc.e_items = (int4*)d_items;
+      }
+      launch_coarse_E(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->W, c->efac);
       // right-looking Cholesky of E, one tile column per step
       int32_t* d_erows = nullptr;
       TRY(c->upload(&d_erows, CP.erows));
@@ -377,6 +382,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
         launch_echol_update(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac);
       }
       TRY(c->dalloc(&c->einv, CP.einv_tot));
+      TRY(c->dalloc(&c->Cc.e_part, CP.einv_tot / TS));
+      TRY(c->dalloc(&c->Cc.e_u, c->n0tot));
       launch_einv(st, (int)c->etiles, c->Cc, c->efac, c->edinv, c->einv);
       TRY(c->dalloc(&c->cvec, c->n0tot));
       TRY(c->dalloc(&c->dvec, c->n0tot));

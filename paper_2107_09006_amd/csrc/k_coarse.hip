@@ -268,12 +268,12 @@ __device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* 
 //   M3: T W, then K = W^T T W
 constexpr int EIG_MAXN = 1024;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
               const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
               int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail) {
   __shared__ double sv[EIG_MAXN], sw[EIG_MAXN], scs[EIG_MAXN], ssn[EIG_MAXN], sd[EIG_MAXN],
-      se[EIG_MAXN], sred[256];
+      se[EIG_MAXN], sred[1024];
   __shared__ int32_t sel[EIG_MAXN];
   __shared__ int s_r, s_p;
   const int i = blockIdx.x;
@@ -302,7 +302,20 @@ k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __syncthreads();
   for (int a = tid; a < n; a += nthr) M3[a] = sw[a];   // keep D2 in M3's first column
   __syncthreads();
-  wg_syev(M0, M1, n, ld, L, fail);
+  // a diagonal Ct_GG (every interface column met by its own rows of Xi) needs
+  // no eigensolver: eigenvalues = diagonal, eigenvectors = identity
+  double off = 0.0;
+  for (int64_t q = tid; q < (int64_t)n * n; q += nthr)
+    if (q % n != q / n) off += fabs(M0[(q / n) * ld + q % n]);
+  off = block_sum(off, sred);
+  if (off == 0.0) {
+    for (int a = tid; a < n; a += nthr) sd[a] = M0[(int64_t)a * ld + a];
+    for (int64_t q = tid; q < (int64_t)n * n; q += nthr)
+      M1[(q / n) * ld + q % n] = (q % n == q / n) ? 1.0 : 0.0;
+    __syncthreads();
+  } else {
+    wg_syev(M0, M1, n, ld, L, fail);
+  }
   // rank of Ct: eigenvalues above n * eps * max
   if (tid == 0) {
     double mx = 0.0;
@@ -470,37 +483,53 @@ k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
 }
 
 // Blocks of E = W^T W for every pair (i <= j) sharing rows; lower part only,
-// in the tile-envelope layout of E (global coarse numbering).
+// in the tile-envelope layout of E (global coarse numbering).  One work item
+// = (pair, 32 x 32 output block); each wave forms one 16 x 16 quadrant with
+// MFMA over the shared rows.
 __global__ void __launch_bounds__(256)
 k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
-           const int32_t* __restrict__ pair_rows, const int32_t* __restrict__ eF,
-           const int64_t* __restrict__ eOff, const double* __restrict__ W,
-           double* __restrict__ efac) {
-  const PairDesc pr = pairs[blockIdx.x];
+           const int32_t* __restrict__ pair_rows, const int4* __restrict__ items,
+           const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
+           const double* __restrict__ W, double* __restrict__ efac) {
+  const int4 it = items[blockIdx.x];
+  const PairDesc pr = pairs[it.x];
   const SubDesc di = subs[pr.i], dj = subs[pr.j];
+  const bool diag = pr.i == pr.j;
   const double* Wi = W + di.w_off;
   const double* Wj = W + dj.w_off;
   const int32_t* rl = pair_rows + 2 * pr.rows_off;
-  for (int64_t q = threadIdx.x; q < (int64_t)di.p * dj.p; q += blockDim.x) {
-    const int k = (int)(q % di.p), l = (int)(q / di.p);
-    const int64_t row = dj.cg_off + l, col = di.cg_off + k;
-    if (pr.i == pr.j && row < col) continue;
-    double s = 0.0;
-    if (pr.i == pr.j) {
-      for (int rho = 0; rho < di.nXi; ++rho)
-        s += Wi[(int64_t)k * di.nXi + rho] * Wj[(int64_t)l * dj.nXi + rho];
-    } else {
-      for (int t = 0; t < pr.nrows; ++t)
-        s += Wi[(int64_t)k * di.nXi + rl[2 * t]] * Wj[(int64_t)l * dj.nXi + rl[2 * t + 1]];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int bi = wave / 2, bj = wave % 2, li = lane % 16, lk = lane / 16;
+  const int l = it.y * TS + 16 * bi + li;     // row of E inside subdomain j's block
+  const int k = it.z * TS + 16 * bj + li;     // column of E inside subdomain i's block
+  const bool lv = l < dj.p, kv = k < di.p;
+  const int nrows = diag ? di.nXi : pr.nrows;
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int t0 = 0; t0 < nrows; t0 += 4) {
+    const int t = t0 + lk;
+    double a = 0.0, b = 0.0;
+    if (t < nrows) {
+      const int rj = diag ? t : rl[2 * t + 1];
+      const int ri = diag ? t : rl[2 * t];
+      if (lv) a = Wj[(int64_t)l * dj.nXi + rj];
+      if (kv) b = Wi[(int64_t)k * di.nXi + ri];
     }
+    acc = Mfma<double>::mma(a, b, acc);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int lr = it.y * TS + 16 * bi + Mfma<double>::acc_row(lane, v);
+    const int kc = it.z * TS + 16 * bj + Mfma<double>::acc_col(lane, v);
+    if (lr >= dj.p || kc >= di.p) continue;
+    const int64_t row = dj.cg_off + lr, col = di.cg_off + kc;
+    if (diag && row < col) continue;
     const int I = (int)(row / TS), J = (int)(col / TS);
-    efac[tile_pos(eF, eOff, I, J) * TT + (col % TS) * TS + (row % TS)] = s;
+    efac[tile_pos(eF, eOff, I, J) * TT + (col % TS) * TS + (row % TS)] = acc[v];
   }
 }
 
 // One step J of the right-looking tile Cholesky of E: diagonal tile and panel
 // (one workgroup), then the trailing update (one wave per pair of rows).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_echol_diag(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
              const int32_t* __restrict__ rows, int nr, double* __restrict__ efac,
              double* __restrict__ edinv, int32_t* __restrict__ status) {
@@ -544,54 +573,70 @@ k_echol_update(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
   tile_acc_store<double>(acc, Cab, TS, lane);
 }
 
-// Dense inverse of E per instance: column block c (32 columns) solves
-// L L^T X = I(:, c) by tile forward and backward substitution, 4 waves each
-// owning one 16 x 16 quadrant of the 32 x 32 right-hand-side tile.
-__global__ void __launch_bounds__(256)
+// Dense inverse of E per instance, lower block triangle: column block c (32
+// columns) solves L L^T X = I(:, c) by tile forward substitution (rows >= c)
+// and backward substitution stopped at row block c (rows of X below the
+// diagonal block only need rows >= c of the forward result).  16 waves: the
+// 4 quadrants of the 32 x 32 right-hand side times 4 groups that split the
+// tile sum; the group partials are added in a fixed order.
+__global__ void __launch_bounds__(1024)
 k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
        const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
        const double* __restrict__ efac, const double* __restrict__ edinv, double* __restrict__ einv) {
   __shared__ double sY[TS * LDT];
+  __shared__ double spart[4][4][256];
   const int cglob = blockIdx.x;
   const SegDesc sg = segs[seg_of_tile[cglob]];
   const int t0 = (int)sg.etile0, nt = (int)sg.etiles;
-  const int c = cglob - t0;                   // local tile column
+  const int c = cglob - t0;
   const int ld = nt * TS;
-  double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;   // ld x 32, column-major
+  double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int bi = wave / 2, bj = wave % 2;
-  // zero the column block
-  for (int64_t q = threadIdx.x; q < (int64_t)ld * TS; q += blockDim.x) Xc[q] = 0.0;
+  const int q = wave % 4, g = wave / 4;
+  const int bi = q / 2, bj = q % 2;
+  for (int64_t e = threadIdx.x; e < (int64_t)(ld - c * TS) * TS; e += blockDim.x) {
+    const int col = (int)(e / (ld - c * TS)), row = c * TS + (int)(e % (ld - c * TS));
+    Xc[(int64_t)col * ld + row] = 0.0;
+  }
   __syncthreads();
-  // forward: Y_I = Inv(I,I) (delta_{I c} I - sum_K L(I,K) Y_K), I >= c
   for (int I = c; I < nt; ++I) {
     const int Ig = t0 + I;
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    if (I == c) {
-      for (int v = 0; v < 4; ++v)
-        acc[v] = (16 * bi + Mfma<double>::acc_row(lane, v) == 16 * bj + Mfma<double>::acc_col(lane, v)) ? 1.0 : 0.0;
-    }
-    for (int K = max(eF[Ig] - t0, c); K < I; ++K)
+    for (int K = max(eF[Ig] - t0, c) + g; K < I; K += 4)
       quad_mma<false>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld, bi, bj,
                       lane, true);
-    quad_store(acc, sY, LDT, bi, bj, lane);
+    for (int v = 0; v < 4; ++v) spart[g][q][lane * 4 + v] = acc[v];
     __syncthreads();
-    double4_t y = {0.0, 0.0, 0.0, 0.0};
-    quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
-    quad_store(y, Xc + I * TS, ld, bi, bj, lane);
+    if (g == 0) {
+      double4_t s4;
+      for (int v = 0; v < 4; ++v) {
+        double sum = (I == c && 16 * bi + Mfma<double>::acc_row(lane, v) ==
+                                   16 * bj + Mfma<double>::acc_col(lane, v)) ? 1.0 : 0.0;
+        for (int gg = 0; gg < 4; ++gg) sum += spart[gg][q][lane * 4 + v];
+        s4[v] = sum;
+      }
+      quad_store(s4, sY, LDT, bi, bj, lane);
+    }
+    __syncthreads();
+    if (g == 0) {
+      double4_t y = {0.0, 0.0, 0.0, 0.0};
+      quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+      quad_store(y, Xc + I * TS, ld, bi, bj, lane);
+    }
     __syncthreads();
   }
-  // backward: X_I = Inv(I,I)^T Y_I; Y_K -= L(I,K)^T X_I for K in [F(I), I)
-  for (int I = nt - 1; I >= 0; --I) {
+  for (int I = nt - 1; I >= c; --I) {
     const int Ig = t0 + I;
     for (int e = threadIdx.x; e < TT; e += blockDim.x)
       sY[(e / TS) * LDT + e % TS] = Xc[(int64_t)(e / TS) * ld + I * TS + e % TS];
     __syncthreads();
-    double4_t x = {0.0, 0.0, 0.0, 0.0};
-    quad_mma<true>(x, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
-    quad_store(x, Xc + I * TS, ld, bi, bj, lane);
+    if (g == 0) {
+      double4_t x = {0.0, 0.0, 0.0, 0.0};
+      quad_mma<true>(x, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+      quad_store(x, Xc + I * TS, ld, bi, bj, lane);
+    }
     __syncthreads();
-    for (int K = eF[Ig] - t0; K < I; ++K) {
+    for (int K = max(eF[Ig] - t0, c) + g; K < I; K += 4) {
       double4_t acc;
       quad_load(acc, Xc + K * TS, ld, bi, bj, lane);
       quad_mma<true>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + I * TS, ld, bi, bj,
@@ -602,41 +647,108 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
   }
 }
 
-// c_i = X_i^T r(Omega_Ii), one wave per coarse vector
-__global__ void __launch_bounds__(256)
+// c_i = X_i^T r(Omega_Ii): r gathered once into LDS (in chunks), one wave per
+// coarse vector.
+constexpr int RCHUNK = 8192;
+__global__ void __launch_bounds__(1024)
 k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
                   const double* __restrict__ X, const double* __restrict__ r,
                   double* __restrict__ cvec) {
+  __shared__ double sr[RCHUNK];
+  __shared__ double sacc[128];
   const SubDesc d = subs[blockIdx.x];
+  if (d.p == 0) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
   const int32_t* om = omega + d.omega_off;
-  for (int k = wave; k < d.p; k += nwaves) {
-    const double* xk = X + d.x_off + (int64_t)k * d.nIp;
-    double s = 0.0;
-    for (int a = lane; a < d.nI; a += 64) s += xk[a] * r[om[a]];
-    for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
-    if (lane == 0) cvec[d.cg_off + k] = s;
+  double acc[8];
+  for (int kb = 0; kb < d.p; kb += 8 * nwaves) {
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int a0 = 0; a0 < d.nI; a0 += RCHUNK) {
+      const int len = min(RCHUNK, d.nI - a0);
+      __syncthreads();
+      for (int a = threadIdx.x; a < len; a += blockDim.x) sr[a] = r[om[a0 + a]];
+      __syncthreads();
+      for (int u = 0; u < 8; ++u) {
+        const int k = kb + u * nwaves + wave;
+        if (k >= d.p) break;
+        const double* xk = X + d.x_off + (int64_t)k * d.nIp + a0;
+        double s = 0.0;
+        for (int a = lane; a < len; a += 64) s += xk[a] * sr[a];
+        acc[u] += s;
+      }
+    }
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + u * nwaves + wave;
+      if (k >= d.p) break;
+      double s = acc[u];
+      for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
+      if (lane == 0) cvec[d.cg_off + k] = s;
+    }
+  }
+  (void)sacc;
+}
+
+// d = E^{-1} c with the lower block triangle of the symmetric inverse, read
+// once.  Pass 1 (one workgroup per tile column J of an instance): the column
+// part u_J = sum_{I > J} T_IJ^T c_I plus the diagonal tile's product, and the
+// row parts P_J(I) = T_IJ c_J for every row block I > J.  Pass 2: d_I = u_I +
+// sum_{J < I} P_J(I), the partials added in increasing J.
+__global__ void __launch_bounds__(256)
+k_esym_pass1(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
+             const double* __restrict__ einv, const double* __restrict__ cvec,
+             double* __restrict__ part, double* __restrict__ uvec) {
+  __shared__ double scol[256][TS + 1];
+  __shared__ double cJ[TS], dsum[TS];
+  const int cglob = blockIdx.x;
+  const SegDesc sg = segs[seg_of_tile[cglob]];
+  const int J = cglob - (int)sg.etile0;
+  const int ld = (int)sg.etiles * TS;
+  const double* Xc = einv + sg.einv_off + (int64_t)J * TS * ld;
+  const double* cv = cvec + sg.c0;
+  double* P = part + sg.einv_off / TS + (int64_t)J * ld;
+  const int tid = threadIdx.x;
+  if (tid < TS) cJ[tid] = cv[J * TS + tid];
+  __syncthreads();
+  double colacc[TS];
+  for (int k = 0; k < TS; ++k) colacc[k] = 0.0;
+  for (int r = J * TS + tid; r < ld; r += blockDim.x) {
+    double rowsum = 0.0;
+    const double cr = cv[r];
+    const double cb = (r >= (J + 1) * TS) ? cr : 0.0;   // the diagonal tile adds by rows only
+#pragma unroll
+    for (int k = 0; k < TS; ++k) {
+      const double e = Xc[(int64_t)k * ld + r];
+      rowsum += e * cJ[k];
+      colacc[k] += e * cb;
+    }
+    if (r >= (J + 1) * TS) P[r] = rowsum;
+    else dsum[r - J * TS] = rowsum;      // diagonal tile: its row sums belong to d_J
+  }
+#pragma unroll
+  for (int k = 0; k < TS; ++k) scol[tid][k] = colacc[k];
+  __syncthreads();
+  if (tid < TS) {
+    double s = dsum[tid];
+    for (int t = 0; t < (int)blockDim.x; ++t) s += scol[t][tid];
+    uvec[sg.c0 + J * TS + tid] = s;
   }
 }
 
-// d = E^{-1} c per instance, one wave per row of the dense inverse
-__global__ void __launch_bounds__(256)
-k_einv_gemv(int64_t n0tot, int S, const SegDesc* __restrict__ segs, const double* __restrict__ einv,
-            const double* __restrict__ cvec, double* __restrict__ dvec) {
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  const int lane = threadIdx.x % 64;
+__global__ void k_esym_pass2(int64_t n0tot, int S, const SegDesc* __restrict__ segs,
+                             const double* __restrict__ part, const double* __restrict__ uvec,
+                             double* __restrict__ dvec) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n0tot) return;
   int s = 0;
   while (s + 1 < S && segs[s + 1].c0 <= row) ++s;
   const SegDesc sg = segs[s];
   const int64_t ld = sg.etiles * TS;
   const int64_t lr = row - sg.c0;
-  const double* col = einv + sg.einv_off + lr * ld;   // symmetric: row = column
-  const double* cv = cvec + sg.c0;
-  double acc = 0.0;
-  for (int64_t j = lane; j < ld; j += 64) acc += col[j] * cv[j];
-  for (int w = 32; w > 0; w >>= 1) acc += __shfl_down(acc, w, 64);
-  if (lane == 0) dvec[row] = acc;
+  const int I = (int)(lr / TS);
+  const double* P = part + sg.einv_off / TS;
+  double acc = uvec[row];
+  for (int J = 0; J < I; ++J) acc += P[(int64_t)J * ld + lr];
+  dvec[row] = acc;
 }
 
 __global__ void k_set_values(int64_t n, const int64_t* __restrict__ idx, double v,
@@ -660,7 +772,7 @@ void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fa
 void launch_reduced_eig(hipStream_t st, int nsub, const DevPlan& P, const double* ctg,
                         const double* Tg, double* work, double tau, int nev_max, int32_t* p_out,
                         double* sig_out) {
-  k_reduced_eig<<<nsub, 256, 0, st>>>(P.subs, ctg, Tg, work, tau, nev_max, p_out, sig_out,
+  k_reduced_eig<<<nsub, 1024, 0, st>>>(P.subs, ctg, Tg, work, tau, nev_max, p_out, sig_out,
                                       p_out + nsub);
 }
 
@@ -676,15 +788,16 @@ void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix
                                    W);
 }
 
-void launch_coarse_E(hipStream_t st, int npairs, const DevPlan& P, const DevCoarse& Cc,
+void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
                      const double* W, double* efac) {
-  if (npairs == 0) return;
-  k_coarse_E<<<npairs, 256, 0, st>>>(P.subs, Cc.pairs, Cc.pair_rows, Cc.eF, Cc.eOff, W, efac);
+  if (nitems == 0) return;
+  k_coarse_E<<<nitems, 256, 0, st>>>(P.subs, Cc.pairs, Cc.pair_rows, Cc.e_items, Cc.eF, Cc.eOff, W,
+                                     efac);
 }
 
 void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                        double* efac, double* edinv, int32_t* status) {
-  k_echol_diag<<<1, 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
+  k_echol_diag<<<1, 1024, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
 }
 
 void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
@@ -697,19 +810,21 @@ void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32
 void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
                  const double* edinv, double* einv) {
   if (ntiles_total == 0) return;
-  k_einv<<<ntiles_total, 256, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, efac, edinv,
+  k_einv<<<ntiles_total, 1024, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, efac, edinv,
                                        einv);
 }
 
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,
                             const double* r, double* c) {
-  k_coarse_restrict<<<nsub, 256, 0, st>>>(P.subs, P.omega, X, r, c);
+  k_coarse_restrict<<<nsub, 1024, 0, st>>>(P.subs, P.omega, X, r, c);
 }
 
 void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,
                       const double* c, double* d) {
   if (n0 == 0) return;
-  k_einv_gemv<<<(unsigned)((n0 * 64 + 255) / 256), 256, 0, st>>>(n0, S, Cc.segs, einv, c, d);
+  const int ntiles = (int)(n0 / TS);
+  k_esym_pass1<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, einv, c, Cc.e_part, Cc.e_u);
+  k_esym_pass2<<<(unsigned)((n0 + 255) / 256), 256, 0, st>>>(n0, S, Cc.segs, Cc.e_part, Cc.e_u, d);
 }
 
 }  // namespace lsq2l

@@ -38,6 +38,9 @@ struct DevCoarse {            // coarse space and coarse operator
   int32_t* eF = nullptr;          // envelope of E (tile rows, global coarse numbering)
   int64_t* eOff = nullptr;
   int32_t* e_seg_of_tile = nullptr;
+  int4* e_items = nullptr;        // (pair, row block, column block) work items of E
+  double* e_part = nullptr;       // row partials of the symmetric coarse solve
+  double* e_u = nullptr;          // column parts of the symmetric coarse solve
 };
 
 // --- sparse kernels -------------------------------------------------------
@@ -94,7 +97,7 @@ void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* f
                      const double* sig, double* X);
 void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
                      const double* X, double* W);
-void launch_coarse_E(hipStream_t st, int npairs, const DevPlan& P, const DevCoarse& Cc,
+void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
                      const double* W, double* efac);
 void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                        double* efac, double* edinv, int32_t* status);

@@ -302,6 +302,17 @@ void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& ph, 
     C.pairs[k].rows_off = (int64_t)C.pair_rows.size() / 2;
     C.pair_rows.insert(C.pair_rows.end(), prow[k].begin(), prow[k].end());
   }
+  // E assembly work items: 32 x 32 output blocks of every pair (lower blocks
+  // only for diagonal pairs)
+  C.items.clear();
+  for (size_t q = 0; q < C.pairs.size(); ++q) {
+    const int pi = H.subs[C.pairs[q].i].p, pj = H.subs[C.pairs[q].j].p;
+    for (int tr = 0; tr < (pj + TS - 1) / TS; ++tr)
+      for (int tc = 0; tc < (pi + TS - 1) / TS; ++tc) {
+        if (C.pairs[q].i == C.pairs[q].j && tc > tr) continue;
+        C.items.insert(C.items.end(), {(int32_t)q, tr, tc, 0});
+      }
+  }
   // envelope of E: the coarse rows of subdomain j couple to the columns of
   // every subdomain i <= j it pairs with
   std::vector<int64_t> fmin(nparts, INT64_MAX);

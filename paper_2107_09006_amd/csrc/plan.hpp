@@ -49,6 +49,7 @@ struct CoarsePlan {
   std::vector<int64_t> pad_idx;       // efac offsets of the diagonal of padding rows
   std::vector<int32_t> erows;         // envelope rows of every tile column
   std::vector<int64_t> eptr;
+  std::vector<int32_t> items;         // E assembly work items: (pair, row block, column block, 0)
 };
 
 // Fills p, x_off, w_off, c_off, cg_off of every subdomain of H and the plan of E.

@@ -138,6 +138,14 @@ int main(int argc, char** argv) {
         }
     }
     for (int64_t q : C.pad_idx) CHECK(q >= 0 && q < C.efac_tiles * TT, "pad");
+    CHECK(C.items.size() % 4 == 0, "items");
+    for (size_t a = 0; a < C.items.size(); a += 4) {
+      const int q = C.items[a], tr = C.items[a + 1], tc = C.items[a + 2];
+      CHECK(q >= 0 && q < (int)C.pairs.size(), "item pair");
+      const SubDesc &di = H2.subs[C.pairs[q].i], &dj = H2.subs[C.pairs[q].j];
+      CHECK(tr * TS < dj.p && tc * TS < di.p, "item block");
+      if (C.pairs[q].i == C.pairs[q].j) CHECK(tc <= tr, "item lower");
+    }
     for (int64_t J = 0; J < C.etiles; ++J) {
       etp(J, J);
       for (int64_t a = C.eptr[J]; a < C.eptr[J + 1]; ++a) {
@@ -153,6 +161,7 @@ int main(int argc, char** argv) {
         for (int64_t I = nt - 1; I >= 0; --I) { CHECK(C.eF[t0 + I] - t0 >= 0, "eF segment"); for (int64_t K = C.eF[t0 + I] - t0; K < I; ++K) etp(t0 + I, t0 + K); }
       }
       CHECK(sg.einv_off + nt * TS * nt * TS <= C.einv_tot, "einv");
+      CHECK(sg.einv_off % TS == 0 && sg.einv_off / TS + nt * (nt * TS) <= C.einv_tot / TS, "esym partials");
     }
   }
   printf("OK subdomains=%d total_fac=%lld maxrows=%lld total_loc=%lld\n", nparts, (long long)H.total_fac, (long long)maxrows, (long long)H.total_loc);
