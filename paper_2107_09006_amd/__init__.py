@@ -9,3 +9,4 @@ from .binding import (  # noqa: F401
     OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN,
     FP64, MIXED, ADDITIVE, ONE_LEVEL, EXPORTS,
 )
+from .autograd import LeastSquaresSolve, lstsq  # noqa: F401,E402

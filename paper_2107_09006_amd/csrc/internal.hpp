@@ -161,39 +161,59 @@ __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, i
 // Cholesky and inverse of one 32 x 32 diagonal tile staged in LDS
 // (column-major, leading dimension LDT).  All threads of the block call it.
 // W: the tile (lower part read; destroyed), L: the factor, Inv: L^{-1}.
+// Step k eliminates column k and applies the same elementary inverse to the
+// running inverse Z (rows i > k: Z(i, :) -= W(i,k) / d_k * Z(k, :)); the
+// scaling of row k by 1 / sqrt(d_k) is done one step later, when no thread
+// reads row k any more.  One barrier per step.
 // Returns false (in every thread) if a pivot is not positive and finite; the
 // pivot is then replaced by 1 so that the caller can continue and report.
 // -------------------------------------------------------------------------
 template <typename T>
+__device__ inline T pivot_of(const T* W, int k, bool* ok) {
+  T d = W[k * LDT + k];
+  if (!(d > T(0)) || !(d < T(INFINITY))) { *ok = false; d = T(1); }
+  return d;
+}
+
+template <typename T>
 __device__ inline bool tile_potrf_inv_lds(T* W, T* L, T* Inv, int tid, int nthr) {
   bool ok = true;
+  for (int e = tid; e < TS * TS; e += nthr) {
+    const int i = e % TS, j = e / TS;
+    Inv[j * LDT + i] = (i == j) ? T(1) : T(0);
+  }
   for (int k = 0; k < TS; ++k) {
     __syncthreads();
-    T d = W[k * LDT + k];
-    if (!(d > T(0)) || !(d < T(INFINITY))) { ok = false; d = T(1); }
-    T sd = sqrt(d);
-    T inv_sd = T(1) / sd;
+    const T d = pivot_of(W, k, &ok);
+    const T sd = sqrt(d);
+    const T inv_sd = T(1) / sd;
+    const T invd = T(1) / d;
     // column k of the factor
     for (int i = k + tid; i < TS; i += nthr) L[k * LDT + i] = (i == k) ? sd : W[k * LDT + i] * inv_sd;
     for (int i = tid; i < k; i += nthr) L[k * LDT + i] = T(0);
-    // trailing update, reading the unscaled column k
-    T invd = T(1) / d;
+    // trailing update of W (reads the unscaled column k)
     const int rem = TS - 1 - k;
     for (int e = tid; e < rem * rem; e += nthr) {
-      int i = k + 1 + e % rem, j = k + 1 + e / rem;
+      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
       if (j <= i) W[j * LDT + i] -= W[k * LDT + i] * W[k * LDT + j] * invd;
+    }
+    // running inverse: rows i > k, columns j <= k
+    for (int e = tid; e < rem * (k + 1); e += nthr) {
+      const int i = k + 1 + e % rem, j = e / rem;
+      Inv[j * LDT + i] -= W[k * LDT + i] * invd * Inv[j * LDT + k];
+    }
+    // deferred scaling of row k - 1
+    if (k > 0) {
+      bool okp = true;
+      const T sp = T(1) / sqrt(pivot_of(W, k - 1, &okp));
+      for (int j = tid; j < k; j += nthr) Inv[j * LDT + (k - 1)] *= sp;
     }
   }
   __syncthreads();
-  // inverse of the lower-triangular factor, one column per thread
-  for (int j = tid; j < TS; j += nthr) {
-    for (int i = 0; i < j; ++i) Inv[j * LDT + i] = T(0);
-    Inv[j * LDT + j] = T(1) / L[j * LDT + j];
-    for (int i = j + 1; i < TS; ++i) {
-      T s = T(0);
-      for (int k = j; k < i; ++k) s += L[k * LDT + i] * Inv[j * LDT + k];
-      Inv[j * LDT + i] = -s / L[i * LDT + i];
-    }
+  {
+    bool okp = true;
+    const T sp = T(1) / sqrt(pivot_of(W, TS - 1, &okp));
+    for (int j = tid; j < TS; j += nthr) Inv[j * LDT + (TS - 1)] *= sp;
   }
   __syncthreads();
   return ok;

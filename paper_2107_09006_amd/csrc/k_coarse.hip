@@ -21,24 +21,61 @@
 // formed for the per-iteration coarse solve.
 #include "kernels.hpp"
 
+#ifdef LSQ2L_PHASE_TIMING
+__device__ unsigned long long g_phase[256];
+__device__ int g_phase_n;
+#define PHASE(tag)                                                                         \
+  do {                                                                                     \
+    __syncthreads();                                                                       \
+    if (blockIdx.x == 0 && threadIdx.x == 0 && g_phase_n < 256)                            \
+      g_phase[g_phase_n++] = wall_clock64();                                               \
+  } while (0)
+#define PHASE_INIT PHASE("init")
+extern "C" void lsq2l_dbg_phases(unsigned long long* out, int* n) {
+  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 256);
+  (void)hipMemcpyFromSymbol(n, HIP_SYMBOL(g_phase_n), sizeof(int));
+  int zero = 0;
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(g_phase_n), &zero, sizeof(int));
+}
+#else
+#define PHASE(tag) do {} while (0)
+#define PHASE_INIT do {} while (0)
+#endif
+
 namespace lsq2l {
 
 // ---------------------------------------------------------------------------
 // tile helpers for multi-right-hand-side products (one 16 x 16 quadrant per wave)
 // ---------------------------------------------------------------------------
 // acc += op(A) * B for the quadrant (bi, bj); op(A) = A or A^T; A, B are
-// 32 x 32 column-major with leading dimensions lda, ldb.
+// 32 x 32 column-major with leading dimensions lda, ldb.  The operand
+// fragments of a whole 32-deep product are loaded first (16 independent
+// loads), then the 8 MFMAs run.
+struct QuadFrag { double a[8], b[8]; };
+
+template <bool TA>
+__device__ inline void quad_frag_load(QuadFrag& f, const double* A, int lda, const double* B, int ldb,
+                                      int bi, int bj, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k = 4 * q + lk;
+    f.a[q] = TA ? A[(int64_t)(16 * bi + li) * lda + k] : A[(int64_t)k * lda + 16 * bi + li];
+    f.b[q] = B[(int64_t)(16 * bj + li) * ldb + k];
+  }
+}
+
+__device__ inline void quad_frag_mma(double4_t& acc, const QuadFrag& f, bool neg) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc = Mfma<double>::mma(neg ? -f.a[q] : f.a[q], f.b[q], acc);
+}
+
 template <bool TA>
 __device__ inline void quad_mma(double4_t& acc, const double* A, int lda, const double* B, int ldb,
                                 int bi, int bj, int lane, bool neg) {
-  const int li = lane % 16, lk = lane / 16;
-  for (int kk = 0; kk < TS; kk += 4) {
-    const int k = kk + lk;
-    double a = TA ? A[(int64_t)(16 * bi + li) * lda + k] : A[(int64_t)k * lda + 16 * bi + li];
-    double b = B[(int64_t)(16 * bj + li) * ldb + k];
-    if (neg) a = -a;
-    acc = Mfma<double>::mma(a, b, acc);
-  }
+  QuadFrag f;
+  quad_frag_load<TA>(f, A, lda, B, ldb, bi, bj, lane);
+  quad_frag_mma(acc, f, neg);
 }
 
 __device__ inline void quad_load(double4_t& acc, const double* C, int ldc, int bi, int bj, int lane) {
@@ -118,6 +155,7 @@ struct EigLds {
 
 __device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* fail) {
   const int tid = threadIdx.x, nthr = blockDim.x;
+  PHASE_INIT;
   double* d = L.d;
   double* e = L.e;
   // -- tridiagonalization A = Q T Q^T (lower), reflectors kept in A
@@ -166,6 +204,7 @@ __device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* 
     e[n - 1] = 0.0;
   }
   __syncthreads();
+  PHASE("tridiag");
   // -- explicit Q = H_0 H_1 ... H_{n-3}
   for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
     const int i = (int)(q % n), j = (int)(q / n);
@@ -193,6 +232,7 @@ __device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* 
     }
     __syncthreads();
   }
+  PHASE("formQ");
   // -- implicit QL on (d, e) with the rotations applied to the rows of Q.
   // An off-diagonal is negligible below eps * ||T|| (absolute accuracy is all
   // the selection needs; a relative test stalls on clusters at rounding level).
@@ -242,23 +282,27 @@ __device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* 
       __syncthreads();
       const int m = s_m, nrot = s_nrot;
       if (m == l) break;
-      // rotation t acts on columns (i, i+1), i = m - 1 - t
+      // rotation t acts on columns (i, i+1), i = m - 1 - t.  Column i + 1 is
+      // final after rotation t, column i is carried to the next rotation in a
+      // register, so the loads never wait on this thread's own stores.
       for (int row = tid; row < n; row += nthr) {
+        if (nrot == 0) break;
+        double carry = Q[(int64_t)m * ld + row];
         for (int t = 0; t < nrot; ++t) {
           const int i = m - 1 - t;
           const double c = L.cs[t], s = L.sn[t];
-          double* qi = Q + (int64_t)i * ld + row;
-          double* qi1 = Q + (int64_t)(i + 1) * ld + row;
-          const double f = *qi1;
-          *qi1 = s * (*qi) + c * f;
-          *qi = c * (*qi) - s * f;
+          const double qi = Q[(int64_t)i * ld + row];
+          Q[(int64_t)(i + 1) * ld + row] = s * qi + c * carry;
+          carry = c * qi - s * carry;
         }
+        Q[(int64_t)(m - nrot) * ld + row] = carry;
       }
       __syncthreads();
       if (++iter > 60) break;
     }
   }
   __syncthreads();
+  PHASE("QL");
 }
 
 // Reduced interface pencil per subdomain; work holds 4 matrices of nGp x nGp:
@@ -291,6 +335,7 @@ k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   const double* Ct = ctg + d.g_off;
   const double* T = Tg + d.g_off;
   EigLds L{sv, sw, scs, ssn, sd, se, sred};
+  PHASE_INIT;
   // D2 = diag(Ct)^{-1/2}; M0 = D2 Ct D2 (full symmetric from the lower triangle)
   for (int a = tid; a < n; a += nthr) sw[a] = 1.0 / sqrt(Ct[(int64_t)a * ld + a]);
   __syncthreads();
@@ -316,6 +361,7 @@ k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   } else {
     wg_syev(M0, M1, n, ld, L, fail);
   }
+  PHASE("eig1");
   // rank of Ct: eigenvalues above n * eps * max
   if (tid == 0) {
     double mx = 0.0;
@@ -342,6 +388,7 @@ k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     M3[(int64_t)c * ld + a] = s;
   }
   __syncthreads();
+  PHASE("TW");
   // M0 = K = M2^T M3 (r x r), symmetrised
   for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {
     const int a = (int)(q % r), c = (int)(q / r);
@@ -356,7 +403,9 @@ k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     M0[(int64_t)a * ld + c] = v;
   }
   __syncthreads();
+  PHASE("K");
   if (r > 0) wg_syev(M0, M1, r, ld, L, fail);
+  PHASE("eig2");
   // select sigma^2 > 1 - tau, largest first (ties: lower index first)
   if (tid == 0) {
     int p = 0;
@@ -602,9 +651,22 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
   for (int I = c; I < nt; ++I) {
     const int Ig = t0 + I;
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int K = max(eF[Ig] - t0, c) + g; K < I; K += 4)
-      quad_mma<false>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld, bi, bj,
-                      lane, true);
+    {
+      // software pipeline: fragments of the next tile load during this one's MFMAs
+      int K = max(eF[Ig] - t0, c) + g;
+      QuadFrag cur, nxt;
+      if (K < I)
+        quad_frag_load<false>(cur, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld,
+                              bi, bj, lane);
+      for (; K < I; K += 4) {
+        const int Kn = K + 4;
+        if (Kn < I)
+          quad_frag_load<false>(nxt, efac + tile_pos(eF, eOff, Ig, t0 + Kn) * TT, TS, Xc + Kn * TS,
+                                ld, bi, bj, lane);
+        quad_frag_mma(acc, cur, true);
+        cur = nxt;
+      }
+    }
     for (int v = 0; v < 4; ++v) spart[g][q][lane * 4 + v] = acc[v];
     __syncthreads();
     if (g == 0) {

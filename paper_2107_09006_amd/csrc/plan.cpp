@@ -8,6 +8,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <thread>
 #include <unordered_map>
@@ -19,28 +20,64 @@ static inline int32_t roundup32(int32_t x) { return (x + TS - 1) / TS * TS; }
 bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
                     std::vector<int32_t>& trowptr, std::vector<int32_t>& tcol,
                     std::vector<int32_t>& tperm) {
+  // Stable counting sort by column, parallel over row blocks: thread t counts
+  // its rows per column, the per-(column, thread) offsets keep row blocks in
+  // order, so rows ascend inside each column exactly as in a serial pass.
   const int64_t nnz = rowptr[m];
   trowptr.assign((size_t)n + 1, 0);
   tcol.resize((size_t)nnz);
   tperm.resize((size_t)nnz);
-  for (int64_t e = 0; e < nnz; ++e) trowptr[colind[e] + 1]++;
+  unsigned nth = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  if (nnz < (1 << 20)) nth = 1;
+  std::vector<int32_t> r0(nth + 1);
+  for (unsigned t = 0; t <= nth; ++t) {
+    // split rows so that every thread gets about nnz / nth entries
+    const int64_t target = nnz * (int64_t)t / nth;
+    r0[t] = (int32_t)(std::lower_bound(rowptr, rowptr + m + 1, target) - rowptr);
+  }
+  r0[nth] = m;
+  std::vector<std::vector<int32_t>> cnt(nth);
+  auto par = [&](auto&& fn) {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
+    for (auto& th : pool) th.join();
+  };
+  par([&](unsigned t) {
+    cnt[t].assign((size_t)n, 0);
+    for (int32_t e = rowptr[r0[t]]; e < rowptr[r0[t + 1]]; ++e) cnt[t][colind[e]]++;
+  });
+  // column totals, then each thread's first slot in every column
+  for (int32_t j = 0; j < n; ++j) {
+    int32_t tot = 0;
+    for (unsigned t = 0; t < nth; ++t) tot += cnt[t][j];
+    trowptr[j + 1] = tot;
+  }
   for (int32_t j = 0; j < n; ++j) trowptr[j + 1] += trowptr[j];
-  std::vector<int32_t> fill(trowptr.begin(), trowptr.end() - 1);
-  for (int32_t r = 0; r < m; ++r)
-    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      int32_t c = colind[e];
-      int32_t k = fill[c]++;
-      tcol[k] = r;      // rows ascend inside each column (stable)
-      tperm[k] = e;     // value of A^T entry k is vals[e]
+  par([&](unsigned t) {
+    const int32_t j0 = (int32_t)((int64_t)n * t / nth), j1 = (int32_t)((int64_t)n * (t + 1) / nth);
+    for (int32_t j = j0; j < j1; ++j) {
+      int32_t run = trowptr[j];
+      for (unsigned u = 0; u < nth; ++u) { const int32_t c = cnt[u][j]; cnt[u][j] = run; run += c; }
     }
+  });
+  par([&](unsigned t) {
+    std::vector<int32_t>& pos = cnt[t];
+    for (int32_t r = r0[t]; r < r0[t + 1]; ++r)
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const int32_t k = pos[colind[e]]++;
+        tcol[k] = r;      // rows ascend inside each column (stable)
+        tperm[k] = e;     // value of A^T entry k is vals[e]
+      }
+  });
   return true;
 }
 
 namespace {
 
 struct Scratch {
-  std::vector<int32_t> rowmark, colmark, gpos;
-  explicit Scratch(int32_t m, int32_t n) : rowmark(m, -1), colmark(n, -1), gpos(n, -1) {}
+  std::vector<int32_t> rowmark, colmark, gpos, rowmin;
+  explicit Scratch(int32_t m, int32_t n)
+      : rowmark(m, -1), colmark(n, -1), gpos(n, -1), rowmin(m, 0) {}
 };
 
 struct LocalOut {
@@ -49,7 +86,8 @@ struct LocalOut {
 
 void plan_one(int32_t i, int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
               const int32_t* trowptr, const int32_t* tcol, const int32_t* part,
-              const int32_t* locown, const int32_t* I, int32_t nI, Scratch& s, LocalOut& out) {
+              const int32_t* locown, const int32_t* I, int32_t nI, int32_t nparts_tag, Scratch& s,
+              LocalOut& out) {
   (void)m; (void)n;
   // Xi_i: rows with a stored entry in a column of Omega_Ii
   out.xi.clear();
@@ -72,19 +110,26 @@ void plan_one(int32_t i, int32_t m, int32_t n, const int32_t* rowptr, const int3
   const int32_t nG = (int32_t)out.gamma.size();
   const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
   for (int32_t g = 0; g < nG; ++g) s.gpos[out.gamma[g]] = nIp + g;
-  // row envelope of C_ii: f(a) = smallest local position coupled to a
+  // row envelope of C_ii: f(a) = smallest local position coupled to a, i.e.
+  // the minimum over the rows r holding column a of the smallest local
+  // position among r's columns (computed once per row, then per column)
   std::vector<int32_t> f(np);
   for (int32_t a = 0; a < np; ++a) f[a] = a;
+  auto row_min = [&](int32_t r) -> int32_t {
+    if (s.rowmark[r] == i + nparts_tag) return s.rowmin[r];
+    int32_t best = INT32_MAX;
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      const int32_t cc = colind[e];
+      const int32_t pos = (part[cc] == i) ? locown[cc] : (s.colmark[cc] == i ? s.gpos[cc] : -1);
+      if (pos >= 0 && pos < best) best = pos;
+    }
+    s.rowmark[r] = i + nparts_tag;
+    s.rowmin[r] = best;
+    return best;
+  };
   auto scan = [&](int32_t a, int32_t c) {
     int32_t best = f[a];
-    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
-      int32_t r = tcol[k];
-      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t cc = colind[e];
-        int32_t pos = (part[cc] == i) ? locown[cc] : (s.colmark[cc] == i ? s.gpos[cc] : -1);
-        if (pos >= 0 && pos < best) best = pos;
-      }
-    }
+    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) best = std::min(best, row_min(tcol[k]));
     f[a] = best;
   };
   for (int32_t a = 0; a < nI; ++a) scan(a, I[a]);
@@ -133,7 +178,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
         Scratch s(m, n);
         for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
           plan_one(i, m, n, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
-                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), s, outs[i]);
+                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), nparts, s, outs[i]);
       });
     for (auto& th : pool) th.join();
   }
@@ -206,25 +251,43 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
         P.own_pos[fill[P.omega[d.omega_off + d.nI + g]]++] = (int32_t)(d.loc_off + d.nIp + g);
     }
   }
-  // for each row, the subdomains whose Xi contains it (with the position)
+  // for each row, the subdomains whose Xi contains it (with the position):
+  // row r is in Xi_i exactly when one of its columns lies in part i, so the
+  // list is the sorted set of distinct parts of the row; the position comes
+  // from a binary search in the sorted Xi_i.  Rows are independent.
   P.rsub_ptr.assign((size_t)m + 1, 0);
-  for (int32_t i = 0; i < nparts; ++i) {
-    const SubDesc& d = P.subs[i];
-    for (int32_t k = 0; k < d.nXi; ++k) P.rsub_ptr[P.xi[d.xi_off + k] + 1]++;
-  }
-  for (int32_t r = 0; r < m; ++r) P.rsub_ptr[r + 1] += P.rsub_ptr[r];
-  P.rsub.resize((size_t)P.rsub_ptr[m]);
-  P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
   {
-    std::vector<int64_t> fill(P.rsub_ptr.begin(), P.rsub_ptr.end() - 1);
-    for (int32_t i = 0; i < nparts; ++i) {
-      const SubDesc& d = P.subs[i];
-      for (int32_t k = 0; k < d.nXi; ++k) {
-        int64_t q = fill[P.xi[d.xi_off + k]]++;
+    unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto par_rows = [&](auto&& fn) {
+      std::vector<std::thread> pool;
+      for (unsigned t = 0; t < nthr; ++t)
+        pool.emplace_back([&, t]() {
+          const int32_t a = (int32_t)((int64_t)m * t / nthr), b = (int32_t)((int64_t)m * (t + 1) / nthr);
+          std::vector<int32_t> buf;
+          for (int32_t r = a; r < b; ++r) {
+            buf.clear();
+            for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) buf.push_back(part[colind[e]]);
+            std::sort(buf.begin(), buf.end());
+            buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+            fn(r, buf);
+          }
+        });
+      for (auto& th : pool) th.join();
+    };
+    par_rows([&](int32_t r, const std::vector<int32_t>& parts) { P.rsub_ptr[r + 1] = (int64_t)parts.size(); });
+    for (int32_t r = 0; r < m; ++r) P.rsub_ptr[r + 1] += P.rsub_ptr[r];
+    P.rsub.resize((size_t)P.rsub_ptr[m]);
+    P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
+    par_rows([&](int32_t r, const std::vector<int32_t>& parts) {
+      int64_t q = P.rsub_ptr[r];
+      for (int32_t i : parts) {
+        const SubDesc& d = P.subs[i];
+        const int32_t* xb = P.xi.data() + d.xi_off;
         P.rsub[q] = i;
-        P.rsub_pos[q] = k;
+        P.rsub_pos[q] = (int32_t)(std::lower_bound(xb, xb + d.nXi, r) - xb);
+        ++q;
       }
-    }
+    });
   }
   return true;
 }

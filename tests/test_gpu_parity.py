@@ -319,6 +319,25 @@ def test_backward_central_differences(L):
     s.close()
 
 
+def test_autograd_function(L):
+    """torch.autograd through lstsq gives the library's adjoint gradients."""
+    import torch
+    p = problem("config0")
+    s = solver(L, p, tol=1e-12)
+    vals = s.vals.clone().requires_grad_(True)
+    b = _t(p.b).requires_grad_(True)
+    xstar = _t(np.random.default_rng(2).standard_normal(p.n))
+    x = L.lstsq(vals, b, s)
+    loss = 0.5 * torch.sum((x - xstar) ** 2)
+    loss.backward()
+    orc = oracle("config0")
+    xo = orc.solve(p.b, tol=1e-12)["x"]
+    go = orc.backward(p.b, xo, xo - _np(xstar), tol=1e-12)
+    assert np.linalg.norm(_np(b.grad) - go["dLdb"]) <= 1e-6 * np.linalg.norm(go["dLdb"])
+    assert np.linalg.norm(_np(vals.grad) - go["dLdvals"]) <= 1e-6 * np.linalg.norm(go["dLdvals"])
+    s.close()
+
+
 def test_batched_instances(L):
     probs = [W.random_banded(300 + 70 * k, 600 + 140 * k, 3 + k, seed=40 + k, name=f"b{k}")
              for k in range(5)]
