@@ -329,13 +329,13 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
     if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(work, 0, 4 * H.total_g * sizeof(double), st));
     LSQ2L_HIP_TRY(hipMemsetAsync(pc, 0, (nparts + 1) * sizeof(int32_t), st));
     launch_gamma_T(st, nparts, c->P, c->fac, Tg);
-    launch_reduced_eig(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig);
+    launch_select(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig);
     std::vector<int32_t> ph(nparts + 1);
     LSQ2L_HIP_TRY(hipMemcpyAsync(ph.data(), pc, (nparts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ2L_HIP_TRY(hipStreamSynchronize(st));
     if (ph[nparts] != 0) {
       set_error(ph[nparts] == 2 ? "interface larger than the eigensolver limit (1024)"
-                                : "QL iteration did not converge in the coarse eigensolver");
+                                : "non-finite entries in a coarse eigenproblem");
       return LSQ2L_EINVAL;
     }
     CoarsePlan& CP = c->CP;

@@ -21,27 +21,6 @@
 // formed for the per-iteration coarse solve.
 #include "kernels.hpp"
 
-#ifdef LSQ2L_PHASE_TIMING
-__device__ unsigned long long g_phase[256];
-__device__ int g_phase_n;
-#define PHASE(tag)                                                                         \
-  do {                                                                                     \
-    __syncthreads();                                                                       \
-    if (blockIdx.x == 0 && threadIdx.x == 0 && g_phase_n < 256)                            \
-      g_phase[g_phase_n++] = wall_clock64();                                               \
-  } while (0)
-#define PHASE_INIT PHASE("init")
-extern "C" void lsq2l_dbg_phases(unsigned long long* out, int* n) {
-  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 256);
-  (void)hipMemcpyFromSymbol(n, HIP_SYMBOL(g_phase_n), sizeof(int));
-  int zero = 0;
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(g_phase_n), &zero, sizeof(int));
-}
-#else
-#define PHASE(tag) do {} while (0)
-#define PHASE_INIT do {} while (0)
-#endif
-
 namespace lsq2l {
 
 // ---------------------------------------------------------------------------
@@ -90,19 +69,6 @@ __device__ inline void quad_store(const double4_t& acc, double* C, int ldc, int 
       Mfma<double>::acc_row(lane, v)] = acc[v];
 }
 
-__device__ inline double block_sum(double v, double* sh) {
-  const int tid = threadIdx.x, n = blockDim.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int w = n / 2; w > 0; w >>= 1) {
-    if (tid < w) sh[tid] += sh[tid + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // T = L_GI L_GI^T (interface x interface, full symmetric, ld nGp)
 // ---------------------------------------------------------------------------
@@ -140,303 +106,6 @@ k_gamma_T(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
           }
       }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric eigensolver for one n x n matrix per workgroup (n <= nGp):
-// Householder tridiagonalization, explicit orthogonal factor, then the
-// implicit QL iteration with Wilkinson shifts accumulating the rotations.
-// A (column-major, ld) is destroyed; Q receives the eigenvectors, ev the
-// eigenvalues (unsorted).  Scratch in LDS: v, w (n each), rotations (2n).
-// ---------------------------------------------------------------------------
-struct EigLds {
-  double* v; double* w; double* cs; double* sn; double* d; double* e; double* red;
-};
-
-__device__ void wg_syev(double* A, double* Q, int n, int ld, EigLds L, int32_t* fail) {
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  PHASE_INIT;
-  double* d = L.d;
-  double* e = L.e;
-  // -- tridiagonalization A = Q T Q^T (lower), reflectors kept in A
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;                    // length of x = A[k+1:n, k]
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += nthr) { double t = A[(int64_t)k * ld + k + 1 + i]; part += t * t; }
-    const double xnorm2 = block_sum(part, L.red);
-    const double alpha = A[(int64_t)k * ld + k + 1];
-    double tau = 0.0, beta = alpha;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      const double sc = 1.0 / (alpha - beta);
-      for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : A[(int64_t)k * ld + k + 1 + i] * sc;
-    } else {
-      for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) { e[k] = beta; d[k] = A[(int64_t)k * ld + k]; L.cs[k] = tau; }
-    for (int i = 1 + tid; i < m; i += nthr) A[(int64_t)k * ld + k + 1 + i] = L.v[i];
-    if (tau != 0.0) {
-      // w = tau * A22 v
-      for (int i = tid; i < m; i += nthr) {
-        double s = 0.0;
-        for (int j = 0; j < m; ++j) s += A[(int64_t)(k + 1 + j) * ld + k + 1 + i] * L.v[j];
-        L.w[i] = tau * s;
-      }
-      __syncthreads();
-      double pp = 0.0;
-      for (int i = tid; i < m; i += nthr) pp += L.w[i] * L.v[i];
-      const double wv = block_sum(pp, L.red);
-      const double a2 = -0.5 * tau * wv;
-      for (int i = tid; i < m; i += nthr) L.w[i] += a2 * L.v[i];
-      __syncthreads();
-      for (int64_t q = tid; q < (int64_t)m * m; q += nthr) {
-        const int i = (int)(q % m), j = (int)(q / m);
-        A[(int64_t)(k + 1 + j) * ld + k + 1 + i] -= L.v[i] * L.w[j] + L.w[i] * L.v[j];
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 2) { e[n - 2] = A[(int64_t)(n - 2) * ld + n - 1]; d[n - 2] = A[(int64_t)(n - 2) * ld + n - 2]; }
-    d[n - 1] = A[(int64_t)(n - 1) * ld + n - 1];
-    e[n - 1] = 0.0;
-  }
-  __syncthreads();
-  PHASE("tridiag");
-  // -- explicit Q = H_0 H_1 ... H_{n-3}
-  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
-    const int i = (int)(q % n), j = (int)(q / n);
-    Q[(int64_t)j * ld + i] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
-  for (int k = n - 3; k >= 0; --k) {
-    const double tau = L.cs[k];
-    if (tau == 0.0) continue;
-    const int m = n - k - 1;
-    for (int i = tid; i < m; i += nthr) L.v[i] = (i == 0) ? 1.0 : A[(int64_t)k * ld + k + 1 + i];
-    __syncthreads();
-    // u_j = v^T Q[k+1:, j], one wave per column
-    for (int j = wave; j < m; j += nwaves) {
-      double s = 0.0;
-      for (int i = lane; i < m; i += 64) s += L.v[i] * Q[(int64_t)(k + 1 + j) * ld + k + 1 + i];
-      for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
-      if (lane == 0) L.w[j] = s;
-    }
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * m; q += nthr) {
-      const int i = (int)(q % m), j = (int)(q / m);
-      Q[(int64_t)(k + 1 + j) * ld + k + 1 + i] -= tau * L.v[i] * L.w[j];
-    }
-    __syncthreads();
-  }
-  PHASE("formQ");
-  // -- implicit QL on (d, e) with the rotations applied to the rows of Q.
-  // An off-diagonal is negligible below eps * ||T|| (absolute accuracy is all
-  // the selection needs; a relative test stalls on clusters at rounding level).
-  __shared__ int s_m, s_nrot;
-  __shared__ double s_anorm;
-  if (tid == 0) {
-    double an = 0.0;
-    for (int i = 0; i < n; ++i)
-      an = fmax(an, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
-    s_anorm = an;
-  }
-  __syncthreads();
-  const double small = 2.220446049250313e-16 * s_anorm;
-  for (int l = 0; l < n; ++l) {
-    int iter = 0;
-    while (true) {
-      if (tid == 0) {
-        int m = l;
-        for (; m < n - 1; ++m)
-          if (fabs(e[m]) <= small) break;   // negligible coupling
-        s_m = m;
-        s_nrot = 0;
-        if (m != l) {
-          if (iter >= 60) { atomicExch(fail, 1); }
-          double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-          double r = hypot(g, 1.0);
-          g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-          double s = 1.0, c = 1.0, p = 0.0;
-          int i = m - 1;
-          bool early = false;
-          for (; i >= l; --i) {
-            const double f = s * e[i], b = c * e[i];
-            r = hypot(f, g);
-            e[i + 1] = r;
-            if (r == 0.0) { d[i + 1] -= p; e[m] = 0.0; early = true; break; }
-            s = f / r; c = g / r;
-            g = d[i + 1] - p;
-            r = (d[i] - g) * s + 2.0 * c * b;
-            p = s * r;
-            d[i + 1] = g + p;
-            g = c * r - b;
-            L.cs[s_nrot] = c; L.sn[s_nrot] = s; s_nrot++;
-          }
-          if (!early) { d[l] -= p; e[l] = g; e[m] = 0.0; }
-        }
-      }
-      __syncthreads();
-      const int m = s_m, nrot = s_nrot;
-      if (m == l) break;
-      // rotation t acts on columns (i, i+1), i = m - 1 - t.  Column i + 1 is
-      // final after rotation t, column i is carried to the next rotation in a
-      // register, so the loads never wait on this thread's own stores.
-      for (int row = tid; row < n; row += nthr) {
-        if (nrot == 0) break;
-        double carry = Q[(int64_t)m * ld + row];
-        for (int t = 0; t < nrot; ++t) {
-          const int i = m - 1 - t;
-          const double c = L.cs[t], s = L.sn[t];
-          const double qi = Q[(int64_t)i * ld + row];
-          Q[(int64_t)(i + 1) * ld + row] = s * qi + c * carry;
-          carry = c * qi - s * carry;
-        }
-        Q[(int64_t)(m - nrot) * ld + row] = carry;
-      }
-      __syncthreads();
-      if (++iter > 60) break;
-    }
-  }
-  __syncthreads();
-  PHASE("QL");
-}
-
-// Reduced interface pencil per subdomain; work holds 4 matrices of nGp x nGp:
-//   M0: Ct (equilibrated), then Y (selected, nG x p)
-//   M1: eigenvectors of the scaled Ct, then K's eigenvectors
-//   M2: W = D2 V_r Lambda_r^{-1/2}
-//   M3: T W, then K = W^T T W
-constexpr int EIG_MAXN = 1024;
-
-__global__ void __launch_bounds__(1024)
-k_reduced_eig(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
-              const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
-              int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail) {
-  __shared__ double sv[EIG_MAXN], sw[EIG_MAXN], scs[EIG_MAXN], ssn[EIG_MAXN], sd[EIG_MAXN],
-      se[EIG_MAXN], sred[1024];
-  __shared__ int32_t sel[EIG_MAXN];
-  __shared__ int s_r, s_p;
-  const int i = blockIdx.x;
-  const SubDesc d = subs[i];
-  const int n = d.nG, ld = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
-  if (n == 0 || n > EIG_MAXN) {
-    if (tid == 0) { p_out[i] = 0; if (n > EIG_MAXN) atomicExch(fail, 2); }
-    return;
-  }
-  const int64_t mm = (int64_t)ld * ld;
-  double* M0 = work + 4 * d.g_off;
-  double* M1 = M0 + mm;
-  double* M2 = M1 + mm;
-  double* M3 = M2 + mm;
-  const double* Ct = ctg + d.g_off;
-  const double* T = Tg + d.g_off;
-  EigLds L{sv, sw, scs, ssn, sd, se, sred};
-  PHASE_INIT;
-  // D2 = diag(Ct)^{-1/2}; M0 = D2 Ct D2 (full symmetric from the lower triangle)
-  for (int a = tid; a < n; a += nthr) sw[a] = 1.0 / sqrt(Ct[(int64_t)a * ld + a]);
-  __syncthreads();
-  for (int64_t q = tid; q < (int64_t)n * n; q += nthr) {
-    const int r = (int)(q % n), c = (int)(q / n);
-    const double v = (r >= c) ? Ct[(int64_t)c * ld + r] : Ct[(int64_t)r * ld + c];
-    M0[(int64_t)c * ld + r] = v * sw[r] * sw[c];
-  }
-  __syncthreads();
-  for (int a = tid; a < n; a += nthr) M3[a] = sw[a];   // keep D2 in M3's first column
-  __syncthreads();
-  // a diagonal Ct_GG (every interface column met by its own rows of Xi) needs
-  // no eigensolver: eigenvalues = diagonal, eigenvectors = identity
-  double off = 0.0;
-  for (int64_t q = tid; q < (int64_t)n * n; q += nthr)
-    if (q % n != q / n) off += fabs(M0[(q / n) * ld + q % n]);
-  off = block_sum(off, sred);
-  if (off == 0.0) {
-    for (int a = tid; a < n; a += nthr) sd[a] = M0[(int64_t)a * ld + a];
-    for (int64_t q = tid; q < (int64_t)n * n; q += nthr)
-      M1[(q / n) * ld + q % n] = (q % n == q / n) ? 1.0 : 0.0;
-    __syncthreads();
-  } else {
-    wg_syev(M0, M1, n, ld, L, fail);
-  }
-  PHASE("eig1");
-  // rank of Ct: eigenvalues above n * eps * max
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int k = 0; k < n; ++k) mx = fmax(mx, sd[k]);
-    const double tol = n * 2.220446049250313e-16 * mx;
-    int r = 0;
-    for (int k = 0; k < n; ++k) if (sd[k] > tol) sel[r++] = k;
-    s_r = r;
-  }
-  __syncthreads();
-  const int r = s_r;
-  // M2 = D2 V_r Lambda_r^{-1/2}
-  for (int64_t q = tid; q < (int64_t)n * r; q += nthr) {
-    const int a = (int)(q % n), c = (int)(q / n);
-    const int k = sel[c];
-    M2[(int64_t)c * ld + a] = M3[a] * M1[(int64_t)k * ld + a] / sqrt(sd[k]);
-  }
-  __syncthreads();
-  // M3 = T M2 (n x r)
-  for (int64_t q = tid; q < (int64_t)n * r; q += nthr) {
-    const int a = (int)(q % n), c = (int)(q / n);
-    double s = 0.0;
-    for (int b = 0; b < n; ++b) s += T[(int64_t)b * ld + a] * M2[(int64_t)c * ld + b];
-    M3[(int64_t)c * ld + a] = s;
-  }
-  __syncthreads();
-  PHASE("TW");
-  // M0 = K = M2^T M3 (r x r), symmetrised
-  for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {
-    const int a = (int)(q % r), c = (int)(q / r);
-    if (a < c) continue;
-    double s1 = 0.0, s2 = 0.0;
-    for (int b = 0; b < n; ++b) {
-      s1 += M2[(int64_t)a * ld + b] * M3[(int64_t)c * ld + b];
-      s2 += M2[(int64_t)c * ld + b] * M3[(int64_t)a * ld + b];
-    }
-    const double v = 0.5 * (s1 + s2);
-    M0[(int64_t)c * ld + a] = v;
-    M0[(int64_t)a * ld + c] = v;
-  }
-  __syncthreads();
-  PHASE("K");
-  if (r > 0) wg_syev(M0, M1, r, ld, L, fail);
-  PHASE("eig2");
-  // select sigma^2 > 1 - tau, largest first (ties: lower index first)
-  if (tid == 0) {
-    int p = 0;
-    for (int k = 0; k < r; ++k)
-      if (sd[k] > 1.0 - tau) sel[p++] = k;
-    for (int a = 1; a < p; ++a) {        // insertion sort, descending value
-      const int key = sel[a];
-      int b = a - 1;
-      while (b >= 0 && (sd[sel[b]] < sd[key] || (sd[sel[b]] == sd[key] && sel[b] > key))) {
-        sel[b + 1] = sel[b];
-        --b;
-      }
-      sel[b + 1] = key;
-    }
-    if (nev_max > 0 && p > nev_max) p = nev_max;
-    s_p = p;
-    p_out[i] = p;
-  }
-  __syncthreads();
-  const int p = s_p;
-  // Y = M2 U_sel into M0 (n x p, padding rows zero); sigma into sig_out
-  for (int64_t q = tid; q < (int64_t)ld * p; q += nthr) {
-    const int a = (int)(q % ld), c = (int)(q / ld);
-    double s = 0.0;
-    if (a < n) {
-      const int k = sel[c];
-      for (int b = 0; b < r; ++b) s += M2[(int64_t)b * ld + a] * M1[(int64_t)k * ld + b];
-    }
-    M0[(int64_t)c * ld + a] = s;
-  }
-  for (int c = tid; c < p; c += nthr) sig_out[d.loc_off + c] = sqrt(sd[sel[c]]);
 }
 
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
@@ -831,12 +500,6 @@ void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fa
   k_gamma_T<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, Tg);
 }
 
-void launch_reduced_eig(hipStream_t st, int nsub, const DevPlan& P, const double* ctg,
-                        const double* Tg, double* work, double tau, int nev_max, int32_t* p_out,
-                        double* sig_out) {
-  k_reduced_eig<<<nsub, 1024, 0, st>>>(P.subs, ctg, Tg, work, tau, nev_max, p_out, sig_out,
-                                      p_out + nsub);
-}
 
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                      const double* dinv, const double* scale, const double* work,

@@ -89,9 +89,8 @@ void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const dou
 
 // --- coarse space ------------------------------------------------------------
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
-void launch_reduced_eig(hipStream_t st, int nsub, const DevPlan& P, const double* ctg,
-                        const double* Tg, double* work, double tau, int nev_max, int32_t* p_out,
-                        double* sig_out);
+void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
+                   double* work, double tau, int nev_max, int32_t* p_out, double* sig_out);
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                      const double* dinv, const double* scale, const double* work,
                      const double* sig, double* X);
