@@ -5,22 +5,25 @@
 // equilibration of C_ii), the selected directions are the eigenvectors of
 //     K = W^T T W,   W^T Ct W = I,  range(W) = range(Ct),
 // with eigenvalue sigma^2 > 1 - tau.  One workgroup per subdomain:
-//   1. W: if Ct is diagonal, W = diag(Ct)^{-1/2}; otherwise a pivoted
-//      Cholesky Ct = R^T R (rank r: stop when the largest remaining diagonal
-//      of the unit-diagonal scaled matrix falls below n eps) and
-//      W = R^T (R R^T)^{-1};
-//   2. K = W^T (T W) with MFMA tile products;
+//   1. W: if Ct is diagonal, W = diag(Ct)^{-1/2}.  Otherwise a pivoted
+//      Cholesky P^T Ct P = R^T R of the unit-diagonal scaled Ct, stopped when
+//      the largest remaining diagonal falls below n eps (rank r), and
+//      W = P [R11^{-1}; 0].  R W = I gives W^T Ct W = I; range(W) differs from
+//      range(Ct) by null(Ct) only, which T annihilates (T <= Ct_GG because the
+//      splitting matrix Ct_ii is positive semidefinite with C_I as its
+//      interior block), so K is the same as on range(Ct);
+//   2. K = W^T T W with MFMA tile products;
 //   3. Householder tridiagonalization of K;
 //   4. p = number of eigenvalues above 1 - tau (one Sturm count), then the
 //      p largest eigenvalues by bisection (one thread each);
-//   5. eigenvectors of the tridiagonal matrix by inverse iteration (one thread
-//      per cluster of close eigenvalues, re-orthogonalised inside the cluster)
+//   5. eigenvectors of the tridiagonal matrix by inverse iteration (one
+//      thread per vector), clusters of close eigenvalues re-orthonormalised,
 //      and back-transformation through the Householder reflectors;
 //   6. Y = W U (interface coefficients of the selected vectors), sigma.
-// Work matrices (ld = nGp, four per subdomain at 4 g_off): M0 scaled Ct, then
-// K and the Householder vectors, then Y; M1 R^T, then U; M2 the Cholesky
-// factor of R R^T, then W; M3 scratch, T W, then scratch of the inverse
-// iteration (3 r doubles per cluster).
+// Work matrices (ld = nGp, four per subdomain at 4 g_off): M0 scaled Ct and
+// the pivoted factor, then K and the Householder vectors, then Y; M1 the
+// permuted T, then U; M2 R11^{-T}; M3 products, then scratch of the inverse
+// iteration (3 r doubles per vector).
 #include "kernels.hpp"
 
 namespace lsq2l {
@@ -62,11 +65,11 @@ __device__ inline void wg_argmax(double v, int idx, double* redv, int* redi, dou
   *outi = bi;
 }
 
-// C (M x N) = op(A) B with M, N, Kd multiples of 16 (zero padded operands),
+// C (M x N) = op(A) op(B) with M, N, Kd multiples of 16 (zero padded operands),
 // all column-major with leading dimension ld; one 16 x 16 quadrant of the
 // output per wave at a time.
 // Only the first Kv entries of the contraction are read (the rest count as 0).
-template <bool TA>
+template <bool TA, bool TB>
 __device__ void wg_gemm(double* C, const double* A, const double* B, int M, int N, int Kd, int Kv,
                         int ld) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
@@ -80,7 +83,7 @@ __device__ void wg_gemm(double* C, const double* A, const double* B, int M, int 
       double a = 0.0, b = 0.0;
       if (k < Kv) {
         a = TA ? A[(int64_t)(16 * qi + li) * ld + k] : A[(int64_t)k * ld + 16 * qi + li];
-        b = B[(int64_t)(16 * qj + li) * ld + k];
+        b = TB ? B[(int64_t)k * ld + 16 * qj + li] : B[(int64_t)(16 * qj + li) * ld + k];
       }
       acc = Mfma<double>::mma(a, b, acc);
     }
@@ -198,9 +201,9 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     }
     __syncthreads();
   } else {
-    // pivoted Cholesky of M0 (in place, original indexing); R^T kept in M1
+    // pivoted Cholesky of M0 with symmetric row/column interchanges; row k of
+    // the upper triangle receives row k of R, sperm the pivot order
     for (int a = tid; a < n; a += nthr) sperm[a] = a;
-    for (int64_t q = tid; q < mm; q += nthr) M1[q] = 0.0;
     __syncthreads();
     const double tol = n * SEL_EPS;     // the scaled matrix has unit diagonal
     int k = 0;
@@ -208,28 +211,40 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       double bv = -1.0;
       int bi = n;
       for (int j = k + tid; j < n; j += nthr) {
-        const int pj = sperm[j];
-        const double v = M0[(int64_t)pj * ld + pj];
-        if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+        const double v = M0[(int64_t)j * ld + j];
+        if (v > bv) { bv = v; bi = j; }
       }
       double mv;
       int mj;
       wg_argmax(bv, bi, sred, sredi, &mv, &mj);
       if (!(mv > tol)) break;
-      __syncthreads();
-      if (tid == 0) { const int t = sperm[k]; sperm[k] = sperm[mj]; sperm[mj] = t; }
-      __syncthreads();
-      const int pk = sperm[k];
-      const double s = sqrt(M0[(int64_t)pk * ld + pk]);
-      for (int j = k + tid; j < n; j += nthr) {
-        const int pj = sperm[j];
-        M1[(int64_t)k * ld + pj] = (j == k) ? s : M0[(int64_t)pj * ld + pk] / s;
+      if (mj != k) {
+        for (int q = tid; q < n; q += nthr) {
+          const double t = M0[(int64_t)k * ld + q];
+          M0[(int64_t)k * ld + q] = M0[(int64_t)mj * ld + q];
+          M0[(int64_t)mj * ld + q] = t;
+        }
+        __syncthreads();
+        for (int q = tid; q < n; q += nthr) {
+          const double t = M0[(int64_t)q * ld + k];
+          M0[(int64_t)q * ld + k] = M0[(int64_t)q * ld + mj];
+          M0[(int64_t)q * ld + mj] = t;
+        }
+        if (tid == 0) { const int t = sperm[k]; sperm[k] = sperm[mj]; sperm[mj] = t; }
+        __syncthreads();
+      }
+      const double sk = sqrt(M0[(int64_t)k * ld + k]);
+      for (int b = k + 1 + tid; b < n; b += nthr) {
+        const double v = M0[(int64_t)b * ld + k] / sk;
+        sv[b] = v;
+        M0[(int64_t)b * ld + k] = v;
       }
       __syncthreads();
+      if (tid == 0) M0[(int64_t)k * ld + k] = sk;
       const int rem = n - k - 1;
       for (int64_t q = tid; q < (int64_t)rem * rem; q += nthr) {
-        const int pa = sperm[k + 1 + (int)(q % rem)], pb = sperm[k + 1 + (int)(q / rem)];
-        M0[(int64_t)pb * ld + pa] -= M1[(int64_t)k * ld + pa] * M1[(int64_t)k * ld + pb];
+        const int a = k + 1 + (int)(q % rem), b = k + 1 + (int)(q / rem);
+        M0[(int64_t)b * ld + a] -= sv[a] * sv[b];
       }
       __syncthreads();
     }
@@ -238,50 +253,34 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       if (tid == 0) p_out[i] = 0;
       return;
     }
-    const int rp = (r + 15) / 16 * 16, np16 = (n + 15) / 16 * 16;
-    // G = R R^T (r x r) in M2, its Cholesky in place
-    wg_gemm<true>(M2, M1, M1, rp, rp, np16, n, ld);
+    const int rp = (r + 15) / 16 * 16;
+    // M2 = Q = R11^{-T}: thread c forms column c of R11^{-1} by back
+    // substitution and stores it as row c of Q (coalesced over c)
+    for (int64_t q = tid; q < mm; q += nthr) M2[q] = 0.0;
     __syncthreads();
-    for (int kk = 0; kk < r; ++kk) {
-      const double dk = M2[(int64_t)kk * ld + kk];
-      const double sk = sqrt(dk);
-      __syncthreads();
-      for (int a = kk + 1 + tid; a < r; a += nthr) M2[(int64_t)kk * ld + a] /= sk;
-      if (tid == 0) M2[(int64_t)kk * ld + kk] = sk;
-      __syncthreads();
-      const int rem = r - kk - 1;
-      for (int64_t q = tid; q < (int64_t)rem * rem; q += nthr) {
-        const int a = kk + 1 + (int)(q % rem), b = kk + 1 + (int)(q / rem);
-        if (b <= a) M2[(int64_t)b * ld + a] -= M2[(int64_t)kk * ld + a] * M2[(int64_t)kk * ld + b];
-      }
-      __syncthreads();
-    }
-    // W rows: w G = (R^T row) -> forward with Lg then backward with Lg^T;
-    // W stored in M3 (n x r) temporarily, then D2-scaled into M2's place below
-    for (int a = tid; a < n; a += nthr) {
-      double* w = M3 + a;                       // row a of W, stride ld
-      for (int c = 0; c < r; ++c) {             // forward: Lg y = rt
-        double s = M1[(int64_t)c * ld + a];
-        for (int b = 0; b < c; ++b) s -= M2[(int64_t)b * ld + c] * w[(int64_t)b * ld];
-        w[(int64_t)c * ld] = s / M2[(int64_t)c * ld + c];
-      }
-      for (int c = r - 1; c >= 0; --c) {        // backward: Lg^T w = y
-        double s = w[(int64_t)c * ld];
-        for (int b = c + 1; b < r; ++b) s -= M2[(int64_t)c * ld + b] * w[(int64_t)b * ld];
-        w[(int64_t)c * ld] = s / M2[(int64_t)c * ld + c];
+    for (int c = tid; c < r; c += nthr) {
+      M2[(int64_t)c * ld + c] = 1.0 / M0[(int64_t)c * ld + c];
+      for (int a = c - 1; a >= 0; --a) {
+        double t = 0.0;
+        for (int b = a + 1; b <= c; ++b) t += M0[(int64_t)b * ld + a] * M2[(int64_t)b * ld + c];
+        M2[(int64_t)a * ld + c] = -t / M0[(int64_t)a * ld + a];
       }
     }
-    __syncthreads();
-    // M2 = D2 W (n x r, zero padded)
+    // M1 = T11 = D2 T D2 in pivot order (r x r, zero padded)
     for (int64_t q = tid; q < mm; q += nthr) {
       const int a = (int)(q % ld), c = (int)(q / ld);
-      M2[q] = (a < n && c < r) ? sD2[a] * M3[q] : 0.0;
+      double v = 0.0;
+      if (a < r && c < r) {
+        const int pa = sperm[a], pc = sperm[c];
+        v = sD2[pa] * T[(int64_t)pc * ld + pa] * sD2[pc];
+      }
+      M1[q] = v;
     }
     __syncthreads();
-    // K = W^T (T W): M3 = T M2, M0 = M2^T M3
-    wg_gemm<false>(M3, T, M2, np16, rp, np16, n, ld);
+    // K = Q T11 Q^T: M3 = Q T11, M0 = M3 Q^T
+    wg_gemm<false, false>(M3, M2, M1, rp, rp, rp, r, ld);
     __syncthreads();
-    wg_gemm<true>(M0, M2, M3, rp, rp, np16, n, ld);
+    wg_gemm<false, true>(M0, M3, M2, rp, rp, rp, r, ld);
     __syncthreads();
     for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {     // symmetrise
       const int a = (int)(q % r), c = (int)(q / r);
@@ -388,10 +387,12 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   }
   __syncthreads();
 
-  // ---- 5. shifted block inverse iteration: every sweep solves all p systems
-  // in parallel (one thread per vector, scratch of 3 r doubles in M3, free
-  // now), then one wave per cluster re-orthonormalises that cluster
-  // (Gram-Schmidt, two passes).  Vectors in M1 (r x p).
+  // ---- 5. inverse iteration, one thread per vector (scratch of 3 r doubles
+  // in M3, free now).  Shifts are accurate to rounding, so after a few sweeps
+  // every vector lies in the invariant subspace of its cluster; only clusters
+  // of (numerically) multiple eigenvalues need orthonormalising, which is done
+  // after the independent sweeps and again after one cleaning sweep.
+  // Vectors in M1 (r x p).
   const double tiny = SEL_EPS * anorm;
   const int slots = (int)min<int64_t>(mm / (3 * r), nthr);
   const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
@@ -400,7 +401,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     M1[q] = row < r ? sin((row + 1.0) * (j + 1.0)) : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 5; ++sweep) {
+  for (int sweep = 0; sweep < 6; ++sweep) {
     for (int j0 = 0; j0 < p; j0 += slots) {
       const int j = j0 + tid;
       if (tid >= slots || j >= p) continue;
@@ -413,26 +414,51 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       tri_solve(sd, se, r, slam[j], tiny, x, scr, scr + r, scr + 2 * r);
     }
     __syncthreads();
-    for (int c = wave; c < s_nclus; c += nw) {
-      for (int j = scl[c]; j < scl[c + 1]; ++j) {
+    if (sweep < 4) continue;
+    // normalise every vector (one wave per vector)
+    for (int j = wave; j < p; j += nw) {
+      double* x = M1 + (int64_t)j * ld;
+      double nr = 0.0;
+      for (int q = lane; q < r; q += 64) nr += x[q] * x[q];
+      for (int w = 32; w > 0; w >>= 1) nr += __shfl_xor(nr, w, 64);
+      nr = 1.0 / sqrt(nr);
+      for (int q = lane; q < r; q += 64) x[q] *= nr;
+    }
+    __syncthreads();
+    // classical Gram-Schmidt, twice, inside every cluster of two or more
+    for (int c = 0; c < s_nclus; ++c) {
+      const int j0 = scl[c], j1 = scl[c + 1];
+      for (int j = j0 + 1; j < j1; ++j) {
         double* x = M1 + (int64_t)j * ld;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int jj = scl[c]; jj < j; ++jj) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int jj = j0 + wave; jj < j; jj += nw) {
             const double* y = M1 + (int64_t)jj * ld;
             double dp = 0.0;
             for (int q = lane; q < r; q += 64) dp += y[q] * x[q];
             for (int w = 32; w > 0; w >>= 1) dp += __shfl_xor(dp, w, 64);
-            for (int q = lane; q < r; q += 64) x[q] -= dp * y[q];
+            if (lane == 0) sw[jj - j0] = dp;
           }
+          __syncthreads();
+          for (int q = tid; q < r; q += nthr) {
+            double v = x[q];
+            for (int jj = j0; jj < j; ++jj) v -= sw[jj - j0] * M1[(int64_t)jj * ld + q];
+            x[q] = v;
+          }
+          __syncthreads();
+        }
         double nr = 0.0;
-        for (int q = lane; q < r; q += 64) nr += x[q] * x[q];
-        for (int w = 32; w > 0; w >>= 1) nr += __shfl_xor(nr, w, 64);
-        nr = 1.0 / sqrt(nr);
-        for (int q = lane; q < r; q += 64) x[q] *= nr;
+        for (int q = tid; q < r; q += nthr) nr += x[q] * x[q];
+        nr = 1.0 / sqrt(wg_sum(nr, sred));
+        for (int q = tid; q < r; q += nthr) x[q] *= nr;
+        __syncthreads();
       }
     }
-    __syncthreads();
   }
+  for (int64_t q = tid; q < (int64_t)(ld - r) * p; q += nthr) {
+    const int row = r + (int)(q % (ld - r)), j = (int)(q / (ld - r));
+    M1[(int64_t)j * ld + row] = 0.0;
+  }
+  __syncthreads();
   // back-transformation U = H_0 ... H_{r-3} Z
   for (int k = r - 3; k >= 0; --k) {
     const double tk = stau[k];
@@ -451,14 +477,21 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   }
 
   // ---- 6. Y = W U into M0 (n x p, padding rows zero), sigma
+  // (general case: row sperm[a] of Y is D2 (R11^{-1} U)(a, :) for a < r, else 0)
   for (int64_t q = tid; q < (int64_t)ld * p; q += nthr) {
     const int a = (int)(q % ld), c = (int)(q / ld);
     double s = 0.0;
-    if (a < n) {
-      if (s_diag) s = sD2[a] * M1[(int64_t)c * ld + a];
-      else for (int b = 0; b < r; ++b) s += M2[(int64_t)b * ld + a] * M1[(int64_t)c * ld + b];
+    int row = a;
+    if (s_diag) {
+      if (a < n) s = sD2[a] * M1[(int64_t)c * ld + a];
+    } else if (a < n) {
+      row = sperm[a];
+      if (a < r) {
+        for (int b = a; b < r; ++b) s += M2[(int64_t)a * ld + b] * M1[(int64_t)c * ld + b];
+        s *= sD2[row];
+      }
     }
-    M0[(int64_t)c * ld + a] = s;
+    M0[(int64_t)c * ld + row] = s;
   }
   for (int c = tid; c < p; c += nthr) sig_out[dsc.loc_off + c] = sqrt(slam[c]);
   if (tid == 0) p_out[i] = p;
