@@ -374,8 +374,9 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       }
       launch_coarse_E(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->W, c->efac);
       // right-looking Cholesky of E, one tile column per step
-      int32_t* d_erows = nullptr;
-      TRY(c->upload(&d_erows, CP.erows));
+      TRY(c->upload(&c->Cc.erows, CP.erows));
+      TRY(c->upload(&c->Cc.eptr, CP.eptr));
+      int32_t* d_erows = c->Cc.erows;
       for (int64_t J = 0; J < c->etiles; ++J) {
         const int nr = (int)(CP.eptr[J + 1] - CP.eptr[J]);
         launch_echol_diag(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac, c->edinv, c->status + 1);

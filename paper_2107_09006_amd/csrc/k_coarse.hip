@@ -291,88 +291,124 @@ k_echol_update(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
   tile_acc_store<double>(acc, Cab, TS, lane);
 }
 
-// Dense inverse of E per instance, lower block triangle: column block c (32
-// columns) solves L L^T X = I(:, c) by tile forward substitution (rows >= c)
-// and backward substitution stopped at row block c (rows of X below the
-// diagonal block only need rows >= c of the forward result).  16 waves: the
-// 4 quadrants of the 32 x 32 right-hand side times 4 groups that split the
-// tile sum; the group partials are added in a fixed order.
-__global__ void __launch_bounds__(1024)
+// Full 32 x 32 product fragments for one wave (K = 32): op(A) rows in two
+// halves, B columns in two halves; acc[bi * 2 + bj] as in tile_acc_load.
+struct TileFrag { double a[2][8], b[2][8]; };
+
+template <bool TA>
+__device__ inline void tile_frag_load(TileFrag& f, const double* A, int lda, const double* B, int ldb,
+                                      int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 4 * q + lk;
+      f.a[h][q] = TA ? A[(int64_t)(16 * h + li) * lda + k] : A[(int64_t)k * lda + 16 * h + li];
+      f.b[h][q] = B[(int64_t)(16 * h + li) * ldb + k];
+    }
+}
+
+__device__ inline void tile_frag_mma(double4_t acc[4], const TileFrag& f) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi * 2 + bj] = Mfma<double>::mma(f.a[bi][q], f.b[bj][q], acc[bi * 2 + bj]);
+}
+
+// Dense inverse of E per instance, lower block triangle.  Workgroup c solves
+// L L^T X = I(:, c) for the 32 columns of tile column c, rows >= c only:
+// forward substitution Y(I) = L_II^{-1} (delta_Ic I - sum_K L(I,K) Y(K)) for
+// I >= c, then backward substitution X(K) = L_KK^{-T} (Y(K) - sum_I L(I,K)^T
+// X(I)) for K from the last tile down to c.  Both sweeps are left-looking, so
+// every output tile is written once; the tile sum of a step is split over the
+// waves, whose partials are added in a fixed order.
+constexpr int EINV_WAVES = 8;
+
+__global__ void __launch_bounds__(EINV_WAVES * 64)
 k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
        const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
+       const int32_t* __restrict__ erows, const int64_t* __restrict__ eptr,
        const double* __restrict__ efac, const double* __restrict__ edinv, double* __restrict__ einv) {
   __shared__ double sY[TS * LDT];
-  __shared__ double spart[4][4][256];
+  __shared__ double spart[EINV_WAVES][TT];
   const int cglob = blockIdx.x;
   const SegDesc sg = segs[seg_of_tile[cglob]];
   const int t0 = (int)sg.etile0, nt = (int)sg.etiles;
   const int c = cglob - t0;
   const int ld = nt * TS;
   double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int q = wave % 4, g = wave / 4;
-  const int bi = q / 2, bj = q % 2;
-  for (int64_t e = threadIdx.x; e < (int64_t)(ld - c * TS) * TS; e += blockDim.x) {
-    const int col = (int)(e / (ld - c * TS)), row = c * TS + (int)(e % (ld - c * TS));
-    Xc[(int64_t)col * ld + row] = 0.0;
-  }
-  __syncthreads();
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int q4 = wave % 4, bi = q4 / 2, bj = q4 % 2;
+
+  // partial sums of this wave -> spart[wave] (accumulator layout)
+  auto put_partial = [&](const double4_t acc[4]) {
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) spart[wave][(qd * 4 + v) * 64 + lane] = acc[qd][v];
+  };
+  // element e of the accumulator layout -> (row, col) of the tile
+  auto elem_rc = [](int e, int& row, int& col) {
+    const int l = e % 64, v = (e / 64) % 4, qd = e / 256;
+    row = 16 * (qd / 2) + Mfma<double>::acc_row(l, v);
+    col = 16 * (qd % 2) + Mfma<double>::acc_col(l, v);
+  };
+
   for (int I = c; I < nt; ++I) {
     const int Ig = t0 + I;
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    {
-      // software pipeline: fragments of the next tile load during this one's MFMAs
-      int K = max(eF[Ig] - t0, c) + g;
-      QuadFrag cur, nxt;
-      if (K < I)
-        quad_frag_load<false>(cur, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld,
-                              bi, bj, lane);
-      for (; K < I; K += 4) {
-        const int Kn = K + 4;
-        if (Kn < I)
-          quad_frag_load<false>(nxt, efac + tile_pos(eF, eOff, Ig, t0 + Kn) * TT, TS, Xc + Kn * TS,
-                                ld, bi, bj, lane);
-        quad_frag_mma(acc, cur, true);
-        cur = nxt;
-      }
+    double4_t acc[4];
+    tile_acc_zero<double>(acc);
+    for (int K = max(eF[Ig] - t0, c) + wave; K < I; K += EINV_WAVES) {
+      TileFrag f;
+      tile_frag_load<false>(f, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld, lane);
+      tile_frag_mma(acc, f);
     }
-    for (int v = 0; v < 4; ++v) spart[g][q][lane * 4 + v] = acc[v];
+    put_partial(acc);
     __syncthreads();
-    if (g == 0) {
-      double4_t s4;
-      for (int v = 0; v < 4; ++v) {
-        double sum = (I == c && 16 * bi + Mfma<double>::acc_row(lane, v) ==
-                                   16 * bj + Mfma<double>::acc_col(lane, v)) ? 1.0 : 0.0;
-        for (int gg = 0; gg < 4; ++gg) sum += spart[gg][q][lane * 4 + v];
-        s4[v] = sum;
-      }
-      quad_store(s4, sY, LDT, bi, bj, lane);
+    for (int e = tid; e < TT; e += nthr) {
+      int row, col;
+      elem_rc(e, row, col);
+      double s = (I == c && row == col) ? 1.0 : 0.0;
+      for (int w = 0; w < EINV_WAVES; ++w) s -= spart[w][e];
+      sY[col * LDT + row] = s;
     }
     __syncthreads();
-    if (g == 0) {
+    if (wave < 4) {
       double4_t y = {0.0, 0.0, 0.0, 0.0};
       quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
       quad_store(y, Xc + I * TS, ld, bi, bj, lane);
     }
     __syncthreads();
   }
-  for (int I = nt - 1; I >= c; --I) {
-    const int Ig = t0 + I;
-    for (int e = threadIdx.x; e < TT; e += blockDim.x)
-      sY[(e / TS) * LDT + e % TS] = Xc[(int64_t)(e / TS) * ld + I * TS + e % TS];
+  for (int K = nt - 1; K >= c; --K) {
+    const int Kg = t0 + K;
+    double4_t acc[4];
+    tile_acc_zero<double>(acc);
+    for (int64_t u = eptr[Kg] + wave; u < eptr[Kg + 1]; u += EINV_WAVES) {
+      const int Ig = erows[u];
+      TileFrag f;
+      tile_frag_load<true>(f, efac + tile_pos(eF, eOff, Ig, Kg) * TT, TS, Xc + (Ig - t0) * TS, ld, lane);
+      tile_frag_mma(acc, f);
+    }
+    put_partial(acc);
     __syncthreads();
-    if (g == 0) {
-      double4_t x = {0.0, 0.0, 0.0, 0.0};
-      quad_mma<true>(x, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
-      quad_store(x, Xc + I * TS, ld, bi, bj, lane);
+    for (int e = tid; e < TT; e += nthr) {
+      int row, col;
+      elem_rc(e, row, col);
+      double s = Xc[(int64_t)col * ld + K * TS + row];
+      for (int w = 0; w < EINV_WAVES; ++w) s -= spart[w][e];
+      sY[col * LDT + row] = s;
     }
     __syncthreads();
-    for (int K = max(eF[Ig] - t0, c) + g; K < I; K += 4) {
-      double4_t acc;
-      quad_load(acc, Xc + K * TS, ld, bi, bj, lane);
-      quad_mma<true>(acc, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + I * TS, ld, bi, bj,
-                     lane, true);
-      quad_store(acc, Xc + K * TS, ld, bi, bj, lane);
+    if (wave < 4) {
+      double4_t x = {0.0, 0.0, 0.0, 0.0};
+      quad_mma<true>(x, edinv + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
+      quad_store(x, Xc + K * TS, ld, bi, bj, lane);
     }
     __syncthreads();
   }
@@ -535,8 +571,8 @@ void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32
 void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
                  const double* edinv, double* einv) {
   if (ntiles_total == 0) return;
-  k_einv<<<ntiles_total, 1024, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, efac, edinv,
-                                       einv);
+  k_einv<<<ntiles_total, EINV_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, Cc.erows,
+                                                   Cc.eptr, efac, edinv, einv);
 }
 
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,

@@ -38,6 +38,8 @@ struct DevCoarse {            // coarse space and coarse operator
   int32_t* eF = nullptr;          // envelope of E (tile rows, global coarse numbering)
   int64_t* eOff = nullptr;
   int32_t* e_seg_of_tile = nullptr;
+  int32_t* erows = nullptr;       // per tile column K: tile rows I > K with F(I) <= K
+  int64_t* eptr = nullptr;
   int4* e_items = nullptr;        // (pair, row block, column block) work items of E
   double* e_part = nullptr;       // row partials of the symmetric coarse solve
   double* e_u = nullptr;          // column parts of the symmetric coarse solve

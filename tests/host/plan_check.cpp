@@ -158,7 +158,14 @@ int main(int argc, char** argv) {
       const int64_t t0 = sg.etile0, nt = sg.etiles;
       for (int64_t c = 0; c < nt; ++c) {
         for (int64_t I = c; I < nt; ++I) for (int64_t K = std::max<int64_t>(C.eF[t0 + I] - t0, c); K < I; ++K) etp(t0 + I, t0 + K);
-        for (int64_t I = nt - 1; I >= 0; --I) { CHECK(C.eF[t0 + I] - t0 >= 0, "eF segment"); for (int64_t K = C.eF[t0 + I] - t0; K < I; ++K) etp(t0 + I, t0 + K); }
+        for (int64_t K = nt - 1; K >= c; --K) {
+          CHECK(C.eF[t0 + K] - t0 >= 0, "eF segment");
+          for (int64_t u = C.eptr[t0 + K]; u < C.eptr[t0 + K + 1]; ++u) {
+            const int64_t Ig = C.erows[u];
+            CHECK(Ig > t0 + K && Ig < t0 + nt, "backward row outside segment");
+            etp(Ig, t0 + K);
+          }
+        }
       }
       CHECK(sg.einv_off + nt * TS * nt * TS <= C.einv_tot, "einv");
       CHECK(sg.einv_off % TS == 0 && sg.einv_off / TS + nt * (nt * TS) <= C.einv_tot / TS, "esym partials");
