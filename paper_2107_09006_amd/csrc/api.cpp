@@ -698,11 +698,19 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
   switch (kernel) {
     case 0: *bytes = 12.0 * nnz + 4.0 * (m + 1) + 8.0 * n + 8.0 * m; break;
     case 1: *bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * m + 8.0 * n; break;
-    case 2: *bytes = 2.0 * eb * (double)(c->H.total_fac + c->H.total_dinv) + 16.0 * (double)c->H.total_loc; break;
+    // each sweep reads every stored off-diagonal tile and every diagonal
+    // inverse once (as many elements as the stored factor), plus y in and out
+    case 2: *bytes = 2.0 * eb * (double)c->H.total_fac + 16.0 * (double)c->H.total_loc; break;
     default: {
-      double e = 0;
-      for (const SegDesc& sg : c->segs_h) e += (double)(sg.etiles * TS) * (double)(sg.etiles * TS);
-      *bytes = 8.0 * e + 16.0 * (double)c->n0tot;
+      // lower block triangle of E^{-1} once, tile-row partials written and
+      // read back, c in and d out
+      double tri = 0, parts = 0;
+      for (const SegDesc& sg : c->segs_h) {
+        const double nt = (double)sg.etiles;
+        tri += (double)TT * nt * (nt + 1) / 2;
+        parts += (double)TS * nt * (nt - 1) / 2;
+      }
+      *bytes = 8.0 * tri + 16.0 * parts + 16.0 * (double)c->n0tot;
     }
   }
   launch_fill(c->st, c->M.n, 1.0, c->p);

