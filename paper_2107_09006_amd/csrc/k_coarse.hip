@@ -108,7 +108,44 @@ k_gamma_T(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
     }
 }
 
+// acc (32 x 32, acc[bi * 2 + bj] as in tile_acc_load) += op(A) B with K = 32;
+// op(A) = A or A^T of a 32 x 32 column-major tile, B column-major (ldb) with
+// its columns >= nb read as zero.
+template <bool TA>
+__device__ inline void tile_mma_cols(double4_t acc[4], const double* A, int lda, const double* B,
+                                     int ldb, int nb, int lane, bool neg) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll 2
+  for (int q = 0; q < 8; ++q) {
+    const int k = 4 * q + lk;
+    double a0 = TA ? A[(int64_t)li * lda + k] : A[(int64_t)k * lda + li];
+    double a1 = TA ? A[(int64_t)(16 + li) * lda + k] : A[(int64_t)k * lda + 16 + li];
+    const double b0 = li < nb ? B[(int64_t)li * ldb + k] : 0.0;
+    const double b1 = 16 + li < nb ? B[(int64_t)(16 + li) * ldb + k] : 0.0;
+    if (neg) { a0 = -a0; a1 = -a1; }
+    acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
+    acc[1] = Mfma<double>::mma(a0, b1, acc[1]);
+    acc[2] = Mfma<double>::mma(a1, b0, acc[2]);
+    acc[3] = Mfma<double>::mma(a1, b1, acc[3]);
+  }
+}
+
+__device__ inline void tile_io_cols(double4_t acc[4], double* C, int ldc, int nb, int lane, bool store) {
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * (qd / 2) + Mfma<double>::acc_row(lane, v);
+      const int c = 16 * (qd % 2) + Mfma<double>::acc_col(lane, v);
+      if (c >= nb) { if (!store) acc[qd][v] = 0.0; continue; }
+      if (store) C[(int64_t)c * ldc + r] = acc[qd][v];
+      else acc[qd][v] = C[(int64_t)c * ldc + r];
+    }
+}
+
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
+// H = L_GI^T Y by 32 x 32 output blocks (one per wave task), then the
+// backward substitution with L_I^T by tile rows (right-looking), all on MFMA.
 __global__ void __launch_bounds__(256)
 k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
            const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
@@ -123,50 +160,42 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
   const double* Y = work + 4 * d.g_off;     // nGp x p, ld nGp
   double* H = X + d.x_off;                 // nIp x p, ld nIp
   const int p = d.p, ldh = d.nIp, ldy = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
+  const int npb = (p + TS - 1) / TS;
   // H_J = sum over interface tile rows I with F(I) <= J of L(I,J)^T Y_I
-  for (int J = 0; J < d.ntI; ++J) {
-    for (int q = tid; q < TS * p; q += nthr) {
-      const int c = q % TS, k = q / TS;
-      double s = 0.0;
-      for (int I = max(d.ntI, 0); I < d.ntiles; ++I) {
-        if (F[I] > J) continue;
-        const double* t = A + tile_pos(F, off, I, J) * TT;
-        const double* y = Y + (int64_t)k * ldy + (I - d.ntI) * TS;
-        for (int rr = 0; rr < TS; ++rr) s += t[c * TS + rr] * y[rr];
-      }
-      H[(int64_t)k * ldh + J * TS + c] = s;
-    }
+  for (int t = wave; t < d.ntI * npb; t += nw) {
+    const int J = t % d.ntI, pb = t / d.ntI, nb = min(TS, p - TS * pb);
+    double4_t acc[4];
+    tile_acc_zero<double>(acc);
+    for (int I = d.ntI; I < d.ntiles; ++I)
+      if (F[I] <= J)
+        tile_mma_cols<true>(acc, A + tile_pos(F, off, I, J) * TT, TS,
+                            Y + (int64_t)(TS * pb) * ldy + (I - d.ntI) * TS, ldy, nb, lane, false);
+    tile_io_cols(acc, H + (int64_t)(TS * pb) * ldh + J * TS, ldh, nb, lane, true);
   }
   __syncthreads();
-  // backward substitution with L_I^T (interior tiles only)
-  __shared__ double xs[TS * 64];
+  // backward substitution with L_I^T: X_I = Dinv_I^T H_I, H_K -= L(I,K)^T X_I
   for (int I = d.ntI - 1; I >= 0; --I) {
-    const double* inv = Di + (int64_t)I * TT;
-    for (int k0 = 0; k0 < p; k0 += 64) {
-      const int kb = min(64, p - k0);
-      for (int q = tid; q < TS * kb; q += nthr) {
-        const int rr = q % TS, k = k0 + q / TS;
-        double s = 0.0;
-        for (int c = 0; c < TS; ++c) s += inv[rr * TS + c] * H[(int64_t)k * ldh + I * TS + c];
-        xs[q] = s;
-      }
-      __syncthreads();
-      for (int q = tid; q < TS * kb; q += nthr) {
-        const int rr = q % TS, k = k0 + q / TS;
-        H[(int64_t)k * ldh + I * TS + rr] = xs[q];
-      }
-      __syncthreads();
-      for (int K = F[I]; K < I; ++K) {
-        const double* t = A + tile_pos(F, off, I, K) * TT;
-        for (int q = tid; q < TS * kb; q += nthr) {
-          const int c = q % TS, k = k0 + q / TS;
-          double s = 0.0;
-          for (int rr = 0; rr < TS; ++rr) s += t[c * TS + rr] * xs[(q / TS) * TS + rr];
-          H[(int64_t)k * ldh + K * TS + c] -= s;
-        }
-      }
-      __syncthreads();
+    for (int pb = wave; pb < npb; pb += nw) {
+      const int nb = min(TS, p - TS * pb);
+      double* HI = H + (int64_t)(TS * pb) * ldh + I * TS;
+      double4_t acc[4];
+      tile_acc_zero<double>(acc);
+      tile_mma_cols<true>(acc, Di + (int64_t)I * TT, TS, HI, ldh, nb, lane, false);
+      tile_io_cols(acc, HI, ldh, nb, lane, true);
     }
+    __syncthreads();
+    const int nK = I - F[I];
+    for (int t = wave; t < nK * npb; t += nw) {
+      const int K = F[I] + t % nK, pb = t / nK, nb = min(TS, p - TS * pb);
+      double* HK = H + (int64_t)(TS * pb) * ldh + K * TS;
+      double4_t acc[4];
+      tile_io_cols(acc, HK, ldh, nb, lane, false);
+      tile_mma_cols<true>(acc, A + tile_pos(F, off, I, K) * TT, TS,
+                          H + (int64_t)(TS * pb) * ldh + I * TS, ldh, nb, lane, true);
+      tile_io_cols(acc, HK, ldh, nb, lane, true);
+    }
+    __syncthreads();
   }
   // scale rows by S_I and columns by 1/sigma; zero the padding rows
   const double* s_loc = scale + d.loc_off;
@@ -182,21 +211,42 @@ k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
            const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
            const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
            const double* __restrict__ vals, const double* __restrict__ X, double* __restrict__ W) {
+  constexpr int ECAP = 8;
   const int i = blockIdx.x;
   const SubDesc d = subs[i];
   if (d.p == 0) return;
   const int32_t* rows = xi + d.xi_off;
   const double* Xi = X + d.x_off;
   double* Wi = W + d.w_off;
-  for (int64_t q = threadIdx.x; q < (int64_t)d.nXi * d.p; q += blockDim.x) {
-    const int rho = (int)(q % d.nXi), k = (int)(q / d.nXi);
+  // one thread per row of Xi_i: its entries in Omega_Ii are read once and
+  // kept in registers for all p columns (rows with more than ECAP such
+  // entries read them again per column)
+  for (int rho = threadIdx.x; rho < d.nXi; rho += blockDim.x) {
     const int r = rows[rho];
-    double s = 0.0;
+    double ev[ECAP];
+    int ep[ECAP];
+    int ne = 0;
     for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
       const int c = colind[e];
-      if (part[c] == i) s += vals[e] * Xi[(int64_t)k * d.nIp + locown[c]];
+      if (part[c] != i) continue;
+      if (ne < ECAP) { ev[ne] = vals[e]; ep[ne] = locown[c]; }
+      ++ne;
     }
-    Wi[q] = s;
+    for (int k = 0; k < d.p; ++k) {
+      const double* xk = Xi + (int64_t)k * d.nIp;
+      double s = 0.0;
+      if (ne <= ECAP) {
+#pragma unroll
+        for (int q = 0; q < ECAP; ++q)
+          if (q < ne) s += ev[q] * xk[ep[q]];
+      } else {
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int c = colind[e];
+          if (part[c] == i) s += vals[e] * xk[locown[c]];
+        }
+      }
+      Wi[(int64_t)k * d.nXi + rho] = s;
+    }
   }
 }
 
