@@ -157,17 +157,6 @@ __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, i
   }
 }
 
-// -------------------------------------------------------------------------
-// Cholesky and inverse of one 32 x 32 diagonal tile staged in LDS
-// (column-major, leading dimension LDT).  All threads of the block call it.
-// W: the tile (lower part read; destroyed), L: the factor, Inv: L^{-1}.
-// Step k eliminates column k and applies the same elementary inverse to the
-// running inverse Z (rows i > k: Z(i, :) -= W(i,k) / d_k * Z(k, :)); the
-// scaling of row k by 1 / sqrt(d_k) is done one step later, when no thread
-// reads row k any more.  One barrier per step.
-// Returns false (in every thread) if a pivot is not positive and finite; the
-// pivot is then replaced by 1 so that the caller can continue and report.
-// -------------------------------------------------------------------------
 // Orders the LDS accesses of the lanes of one wave: a wave's LDS operations
 // complete in issue order, so wavefront-scope fences around a code-motion
 // barrier suffice.
@@ -177,54 +166,57 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
-__device__ inline T pivot_of(const T* W, int k, bool* ok) {
-  T d = W[k * LDT + k];
-  if (!(d > T(0)) || !(d < T(INFINITY))) { *ok = false; d = T(1); }
-  return d;
+// -------------------------------------------------------------------------
+// Cholesky factor and inverse of one 32 x 32 diagonal tile
+// -------------------------------------------------------------------------
+// Broadcast of lane l's value (l wave-uniform) through a scalar register.
+__device__ inline double lane_bcast(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
-template <typename T>
-__device__ inline bool tile_potrf_inv_lds(T* W, T* L, T* Inv, int tid, int nthr) {
+// L L^T = W and Inv = L^{-1} for one SPD tile W (column-major in LDS, leading
+// dimension LDT, lower part read), by the 64 lanes of one wave with the tile in
+// registers: lane j < 32 holds column j of the symmetric tile, lane 32 + j
+// column j of the running inverse Z.  Step k eliminates column k (trailing
+// update of columns j > k) and applies the same elementary operation to Z
+// (rows i > k: Z(i, :) -= W(i, k) / d_k Z(k, :), then row k scaled by
+// 1 / sqrt(d_k)).  Column k is broadcast by lane reads, so the 32 steps need no
+// LDS traffic and no barrier.  L and Inv are written to LDS (L may be null).
+// Returns false if a pivot is not positive and finite (it is then replaced by
+// 1, so the caller can continue and report).
+__device__ inline bool tile_potrf_inv_reg(const double* W, double* L, double* Inv, int lane) {
+  const int j = lane % TS;
+  const bool fac = lane < TS;
+  double v[TS];
+#pragma unroll
+  for (int i = 0; i < TS; ++i)
+    v[i] = fac ? ((i >= j) ? W[j * LDT + i] : W[i * LDT + j]) : ((i == j) ? 1.0 : 0.0);
   bool ok = true;
-  for (int e = tid; e < TS * TS; e += nthr) {
-    const int i = e % TS, j = e / TS;
-    Inv[j * LDT + i] = (i == j) ? T(1) : T(0);
-  }
+  double colscale = 1.0;
+  // Every lane runs the same instructions: the lane reads happen in uniform
+  // control flow and the per-lane roles are selects, never branches (a lane
+  // read inside a divergent branch may see another version of the value).
+#pragma unroll
   for (int k = 0; k < TS; ++k) {
-    __syncthreads();
-    const T d = pivot_of(W, k, &ok);
-    const T sd = sqrt(d);
-    const T inv_sd = T(1) / sd;
-    const T invd = T(1) / d;
-    // column k of the factor
-    for (int i = k + tid; i < TS; i += nthr) L[k * LDT + i] = (i == k) ? sd : W[k * LDT + i] * inv_sd;
-    for (int i = tid; i < k; i += nthr) L[k * LDT + i] = T(0);
-    // trailing update of W (reads the unscaled column k)
-    const int rem = TS - 1 - k;
-    for (int e = tid; e < rem * rem; e += nthr) {
-      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (j <= i) W[j * LDT + i] -= W[k * LDT + i] * W[k * LDT + j] * invd;
-    }
-    // running inverse: rows i > k, columns j <= k
-    for (int e = tid; e < rem * (k + 1); e += nthr) {
-      const int i = k + 1 + e % rem, j = e / rem;
-      Inv[j * LDT + i] -= W[k * LDT + i] * invd * Inv[j * LDT + k];
-    }
-    // deferred scaling of row k - 1
-    if (k > 0) {
-      bool okp = true;
-      const T sp = T(1) / sqrt(pivot_of(W, k - 1, &okp));
-      for (int j = tid; j < k; j += nthr) Inv[j * LDT + (k - 1)] *= sp;
-    }
+    double d = lane_bcast(v[k], k);
+    if (!(d > 0.0) || !(d < INFINITY)) { ok = false; d = 1.0; }
+    const double invd = 1.0 / d, inv_sd = 1.0 / sqrt(d);
+    // factor lanes j > k: W(i, j) -= W(i, k) W(k, j) / d; inverse lanes j <= k:
+    // Z(i, j) -= W(i, k) Z(k, j) / d; other lanes unchanged
+    const bool upd = fac ? (j > k) : (j <= k);
+    const double coef = upd ? v[k] * invd : 0.0;
+#pragma unroll
+    for (int i = k + 1; i < TS; ++i) v[i] -= lane_bcast(v[i], k) * coef;
+    if (!fac && j <= k) v[k] *= inv_sd;
+    if (fac && j == k) colscale = inv_sd;
   }
-  __syncthreads();
-  {
-    bool okp = true;
-    const T sp = T(1) / sqrt(pivot_of(W, TS - 1, &okp));
-    for (int j = tid; j < TS; j += nthr) Inv[j * LDT + (TS - 1)] *= sp;
+#pragma unroll
+  for (int i = 0; i < TS; ++i) {
+    if (fac) { if (L) L[j * LDT + i] = (i >= j) ? v[i] * colscale : 0.0; }
+    else Inv[j * LDT + i] = v[i];
   }
-  __syncthreads();
   return ok;
 }
 

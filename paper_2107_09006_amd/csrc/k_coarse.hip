@@ -295,24 +295,33 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
   }
 }
 
-// One step J of the right-looking tile Cholesky of E: diagonal tile and panel
-// (one workgroup), then the trailing update (one wave per pair of rows).
-__global__ void __launch_bounds__(1024)
+// One step J of the right-looking tile Cholesky of E.  k_echol_diag: every
+// workgroup factors and inverts the diagonal tile (J, J) in registers and
+// forms EDIAG_ROWS panel tiles L(I, J) = A(I, J) L_JJ^{-T} (one per wave);
+// workgroup 0 keeps L_JJ^{-1}, the only form of the diagonal tile the solves
+// read, so (J, J) itself is left unchanged.  k_echol_update: the trailing
+// update, one wave per pair of panel rows.
+constexpr int EDIAG_ROWS = 8;
+
+__global__ void __launch_bounds__(EDIAG_ROWS * 64)
 k_echol_diag(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
              const int32_t* __restrict__ rows, int nr, double* __restrict__ efac,
              double* __restrict__ edinv, int32_t* __restrict__ status) {
-  __shared__ double sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
+  __shared__ double sW[TS * LDT], sInv[TS * LDT];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
-  double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
+  const int wave = tid / 64, lane = tid % 64;
+  const double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
   for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
-  const bool ok = tile_potrf_inv_lds<double>(sW, sL, sInv, tid, nthr);
-  for (int e = tid; e < TT; e += nthr) {
-    Ajj[e] = sL[(e / TS) * LDT + e % TS];
-    edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
+  __syncthreads();
+  if (wave == 0) {
+    const bool ok = tile_potrf_inv_reg(sW, nullptr, sInv, lane);
+    if (!ok && lane == 0 && blockIdx.x == 0) atomicCAS(status, 0, J + 1);
   }
-  if (!ok && tid == 0) atomicCAS(status, 0, J + 1);
-  for (int a = wave; a < nr; a += nwaves) {
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int e = tid; e < TT; e += nthr) edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
+  const int a = blockIdx.x * EDIAG_ROWS + wave;
+  if (a < nr) {
     double* Aij = efac + tile_pos(eF, eOff, rows[a], J) * TT;
     double4_t acc[4];
     tile_acc_zero<double>(acc);
@@ -608,7 +617,8 @@ void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoar
 
 void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                        double* efac, double* edinv, int32_t* status) {
-  k_echol_diag<<<1, 1024, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
+  const int nblk = max(1, (nr + EDIAG_ROWS - 1) / EDIAG_ROWS);
+  k_echol_diag<<<nblk, EDIAG_ROWS * 64, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
 }
 
 void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,

@@ -148,9 +148,10 @@ __global__ void __launch_bounds__(256)
 k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
              const int64_t* __restrict__ tileOff, T* __restrict__ fac, T* __restrict__ dinv,
              int32_t* __restrict__ status) {
+  static_assert(sizeof(T) == sizeof(double), "the local factors are computed in double");
   __shared__ T sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
   __shared__ int32_t rows[ROWCAP];
-  __shared__ int s_count;
+  __shared__ int s_count, s_ok;
   const SubDesc d = subs[blockIdx.x];
   const int32_t* F = tileF + d.tile_base;
   const int64_t* off = tileOff + d.tile_base;
@@ -162,7 +163,13 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
   for (int J = 0; J < d.ntiles; ++J) {
     T* Ajj = A + tile_pos(F, off, J, J) * TT;
     for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
-    const bool ok = tile_potrf_inv_lds<T>(sW, sL, sInv, tid, nthr);
+    __syncthreads();
+    if (wave == 0) {
+      const bool okw = tile_potrf_inv_reg(sW, sL, sInv, lane);
+      if (lane == 0) s_ok = okw;
+    }
+    __syncthreads();
+    const bool ok = s_ok;
     if (!ok) failed = true;
     for (int e = tid; e < TT; e += nthr) {
       Ajj[e] = sL[(e / TS) * LDT + e % TS];
@@ -200,8 +207,6 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
 
 template __global__ void k_chol_local<double>(const SubDesc*, const int32_t*, const int64_t*,
                                               double*, double*, int32_t*);
-template __global__ void k_chol_local<float>(const SubDesc*, const int32_t*, const int64_t*,
-                                             float*, float*, int32_t*);
 
 __global__ void k_to_float(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
