@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -251,6 +252,23 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
   return LSQ2L_OK;
 }
 
+// The overlap maps of the plan, built on a host thread while the device
+// assembles, factors and selects; joined before their first use.
+struct MapsJob {
+  std::thread th;
+  bool ok = true;
+  std::string err;
+  void start(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* part,
+             HostPlan* H) {
+    th = std::thread([this, m, n, rp, ci, part, H]() { ok = plan_maps(m, n, rp, ci, part, *H, err); });
+  }
+  bool join() {
+    if (th.joinable()) th.join();
+    return ok;
+  }
+  ~MapsJob() { if (th.joinable()) th.join(); }
+};
+
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
                         const std::vector<int32_t>& part, int32_t nparts,
@@ -277,6 +295,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   }
   HostPlan& H = c->H;
   c->nsub = nparts;
+  MapsJob maps;
+  maps.start(m, n, rp.data(), ci.data(), part.data(), &H);
   TRY(c->upload(&c->P.subs, H.subs));
   TRY(c->upload(&c->P.omega, H.omega));
   TRY(c->upload(&c->P.xi, H.xi));
@@ -284,8 +304,6 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   TRY(c->upload(&c->P.locown, H.locown));
   TRY(c->upload(&c->P.tileF, H.tileF));
   TRY(c->upload(&c->P.tileOff, H.tileOff));
-  TRY(c->upload(&c->P.own_ptr, H.own_ptr));
-  TRY(c->upload(&c->P.own_pos, H.own_pos));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_plan_ms = ms_since(t0);
   // --- local matrices
@@ -339,6 +357,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       return LSQ2L_EINVAL;
     }
     CoarsePlan& CP = c->CP;
+    if (!maps.join()) { set_error(maps.err); return LSQ2L_EINVAL; }
     plan_coarse(H, c->S, m, ph, CP);
     c->segs_h = CP.segs;
     for (int i = 0; i < nparts; ++i) c->p_h[i] = ph[i];
@@ -401,6 +420,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       c->info.t_eigen_ms = ms_since(t0);
     }
   }
+  // --- overlap maps (owners of every column, for the scatter)
+  if (!maps.join()) { set_error(maps.err); return LSQ2L_EINVAL; }
+  TRY(c->upload(&c->P.own_ptr, H.own_ptr));
+  TRY(c->upload(&c->P.own_pos, H.own_pos));
   // --- mixed precision copy of the local factors
   if (c->opt.precision == LSQ2L_MIXED) {
     TRY(c->dalloc(&c->fac32, H.total_fac));

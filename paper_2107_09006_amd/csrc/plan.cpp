@@ -74,66 +74,64 @@ bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* 
 
 namespace {
 
-struct Scratch {
-  std::vector<int32_t> rowmark, colmark, gpos, rowmin;
-  explicit Scratch(int32_t m, int32_t n)
-      : rowmark(m, -1), colmark(n, -1), gpos(n, -1), rowmin(m, 0) {}
-};
-
 struct LocalOut {
   std::vector<int32_t> xi, gamma, F;
 };
 
-void plan_one(int32_t i, int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
-              const int32_t* trowptr, const int32_t* tcol, const int32_t* part,
-              const int32_t* locown, const int32_t* I, int32_t nI, int32_t nparts_tag, Scratch& s,
-              LocalOut& out) {
-  (void)m; (void)n;
+// Index sets and tile envelope of subdomain i.  Only lists of the size of the
+// subdomain's columns and rows are built (sorted and deduplicated), so the
+// work is proportional to the entries of A it touches.
+void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* trowptr,
+              const int32_t* tcol, const int32_t* part, const int32_t* locown, const int32_t* I,
+              int32_t nI, LocalOut& out) {
   // Xi_i: rows with a stored entry in a column of Omega_Ii
   out.xi.clear();
-  for (int32_t a = 0; a < nI; ++a) {
-    int32_t c = I[a];
-    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
-      int32_t r = tcol[k];
-      if (s.rowmark[r] != i) { s.rowmark[r] = i; out.xi.push_back(r); }
-    }
-  }
+  for (int32_t a = 0; a < nI; ++a)
+    for (int32_t k = trowptr[I[a]]; k < trowptr[I[a] + 1]; ++k) out.xi.push_back(tcol[k]);
   std::sort(out.xi.begin(), out.xi.end());
+  out.xi.erase(std::unique(out.xi.begin(), out.xi.end()), out.xi.end());
   // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii
   out.gamma.clear();
   for (int32_t r : out.xi)
-    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      int32_t c = colind[e];
-      if (part[c] != i && s.colmark[c] != i) { s.colmark[c] = i; out.gamma.push_back(c); }
-    }
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+      if (part[colind[e]] != i) out.gamma.push_back(colind[e]);
   std::sort(out.gamma.begin(), out.gamma.end());
+  out.gamma.erase(std::unique(out.gamma.begin(), out.gamma.end()), out.gamma.end());
   const int32_t nG = (int32_t)out.gamma.size();
   const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
-  for (int32_t g = 0; g < nG; ++g) s.gpos[out.gamma[g]] = nIp + g;
+  // local position of a column of Omega_i (-1 outside)
+  auto pos_of = [&](int32_t c) -> int32_t {
+    if (part[c] == i) return locown[c];
+    auto it = std::lower_bound(out.gamma.begin(), out.gamma.end(), c);
+    return (it != out.gamma.end() && *it == c) ? nIp + (int32_t)(it - out.gamma.begin()) : -1;
+  };
+
   // row envelope of C_ii: f(a) = smallest local position coupled to a, i.e.
-  // the minimum over the rows r holding column a of the smallest local
-  // position among r's columns (computed once per row, then per column)
+  // the minimum, over the rows holding column a, of the row's smallest local
+  // position.  Every row of Xi_i is visited once; rows outside Xi_i that hold
+  // an interface column are visited from that column.
   std::vector<int32_t> f(np);
   for (int32_t a = 0; a < np; ++a) f[a] = a;
-  auto row_min = [&](int32_t r) -> int32_t {
-    if (s.rowmark[r] == i + nparts_tag) return s.rowmin[r];
+  std::vector<int32_t> rpos;
+  auto visit = [&](int32_t r) {
+    rpos.clear();
     int32_t best = INT32_MAX;
     for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      const int32_t cc = colind[e];
-      const int32_t pos = (part[cc] == i) ? locown[cc] : (s.colmark[cc] == i ? s.gpos[cc] : -1);
-      if (pos >= 0 && pos < best) best = pos;
+      const int32_t q = pos_of(colind[e]);
+      if (q >= 0) { rpos.push_back(q); best = std::min(best, q); }
     }
-    s.rowmark[r] = i + nparts_tag;
-    s.rowmin[r] = best;
-    return best;
+    for (int32_t q : rpos) f[q] = std::min(f[q], best);
   };
-  auto scan = [&](int32_t a, int32_t c) {
-    int32_t best = f[a];
-    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) best = std::min(best, row_min(tcol[k]));
-    f[a] = best;
-  };
-  for (int32_t a = 0; a < nI; ++a) scan(a, I[a]);
-  for (int32_t g = 0; g < nG; ++g) scan(nIp + g, out.gamma[g]);
+  for (int32_t r : out.xi) visit(r);
+  for (int32_t g = 0; g < nG; ++g) {
+    const int32_t c = out.gamma[g];
+    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
+      const int32_t r = tcol[k];
+      bool in_xi = false;
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1] && !in_xi; ++e) in_xi = part[colind[e]] == i;
+      if (!in_xi) visit(r);
+    }
+  }
   const int32_t nt = np / TS;
   out.F.assign(nt, 0);
   for (int32_t t = 0; t < nt; ++t) {
@@ -175,10 +173,9 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nth; ++t)
       pool.emplace_back([&, t]() {
-        Scratch s(m, n);
         for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
-          plan_one(i, m, n, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
-                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), nparts, s, outs[i]);
+          plan_one(i, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
+                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), outs[i]);
       });
     for (auto& th : pool) th.join();
   }
@@ -232,6 +229,12 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     d.dinv_off = dinv; dinv += (int64_t)d.ntiles * TT;
   }
   P.total_dinv = dinv;
+  return true;
+}
+
+bool plan_maps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+               const int32_t* part, HostPlan& P, std::string& err) {
+  const int32_t nparts = P.nparts;
   // inverse overlap map: for every column, the local positions holding it,
   // in increasing subdomain order (deterministic summation order)
   P.own_ptr.assign((size_t)n + 1, 0);
@@ -251,41 +254,68 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
         P.own_pos[fill[P.omega[d.omega_off + d.nI + g]]++] = (int32_t)(d.loc_off + d.nIp + g);
     }
   }
-  // for each row, the subdomains whose Xi contains it (with the position):
-  // row r is in Xi_i exactly when one of its columns lies in part i, so the
-  // list is the sorted set of distinct parts of the row; the position comes
-  // from a binary search in the sorted Xi_i.  Rows are independent.
-  P.rsub_ptr.assign((size_t)m + 1, 0);
+  // for each row, the subdomains whose Xi contains it, with the row's rank in
+  // Xi_i: row r is in Xi_i exactly when one of its columns lies in part i, so
+  // the list is the sorted set of distinct parts of the row.  Two passes over
+  // row ranges: count rows per (thread, part), then fill, the rank coming
+  // from a running counter offset by the counts of the earlier ranges.
   {
-    unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    auto par_rows = [&](auto&& fn) {
+    const unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto row_parts = [&](int32_t r, int32_t* buf) -> int {
+      int k = 0;
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const int32_t v = part[colind[e]];
+        int q = k;
+        while (q > 0 && buf[q - 1] > v) --q;
+        if (q > 0 && buf[q - 1] == v) continue;
+        for (int u = k; u > q; --u) buf[u] = buf[u - 1];
+        buf[q] = v;
+        ++k;
+      }
+      return k;
+    };
+    int32_t maxrow = 0;
+    for (int32_t r = 0; r < m; ++r) maxrow = std::max(maxrow, rowptr[r + 1] - rowptr[r]);
+    std::vector<std::vector<int64_t>> cnt(nthr, std::vector<int64_t>((size_t)nparts, 0));
+    P.rsub_ptr.assign((size_t)m + 1, 0);
+    auto par = [&](auto&& fn) {
       std::vector<std::thread> pool;
-      for (unsigned t = 0; t < nthr; ++t)
-        pool.emplace_back([&, t]() {
-          const int32_t a = (int32_t)((int64_t)m * t / nthr), b = (int32_t)((int64_t)m * (t + 1) / nthr);
-          std::vector<int32_t> buf;
-          for (int32_t r = a; r < b; ++r) {
-            buf.clear();
-            for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) buf.push_back(part[colind[e]]);
-            std::sort(buf.begin(), buf.end());
-            buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-            fn(r, buf);
-          }
-        });
+      for (unsigned t = 0; t < nthr; ++t) pool.emplace_back([&, t]() { fn(t); });
       for (auto& th : pool) th.join();
     };
-    par_rows([&](int32_t r, const std::vector<int32_t>& parts) { P.rsub_ptr[r + 1] = (int64_t)parts.size(); });
+    auto range = [&](unsigned t, int32_t& a, int32_t& b) {
+      a = (int32_t)((int64_t)m * t / nthr);
+      b = (int32_t)((int64_t)m * (t + 1) / nthr);
+    };
+    par([&](unsigned t) {
+      std::vector<int32_t> buf((size_t)maxrow + 1);
+      int32_t a, b;
+      range(t, a, b);
+      for (int32_t r = a; r < b; ++r) {
+        const int k = row_parts(r, buf.data());
+        P.rsub_ptr[r + 1] = k;
+        for (int q = 0; q < k; ++q) cnt[t][buf[q]]++;
+      }
+    });
     for (int32_t r = 0; r < m; ++r) P.rsub_ptr[r + 1] += P.rsub_ptr[r];
+    for (int32_t i = 0; i < nparts; ++i) {
+      int64_t run = 0;
+      for (unsigned t = 0; t < nthr; ++t) { const int64_t c = cnt[t][i]; cnt[t][i] = run; run += c; }
+      if (run != P.subs[i].nXi) { err = "inconsistent row sets"; return false; }
+    }
     P.rsub.resize((size_t)P.rsub_ptr[m]);
     P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
-    par_rows([&](int32_t r, const std::vector<int32_t>& parts) {
-      int64_t q = P.rsub_ptr[r];
-      for (int32_t i : parts) {
-        const SubDesc& d = P.subs[i];
-        const int32_t* xb = P.xi.data() + d.xi_off;
-        P.rsub[q] = i;
-        P.rsub_pos[q] = (int32_t)(std::lower_bound(xb, xb + d.nXi, r) - xb);
-        ++q;
+    par([&](unsigned t) {
+      std::vector<int32_t> buf((size_t)maxrow + 1);
+      int32_t a, b;
+      range(t, a, b);
+      for (int32_t r = a; r < b; ++r) {
+        const int k = row_parts(r, buf.data());
+        int64_t q = P.rsub_ptr[r];
+        for (int u = 0; u < k; ++u, ++q) {
+          P.rsub[q] = buf[u];
+          P.rsub_pos[q] = (int32_t)cnt[t][buf[u]]++;
+        }
       }
     });
   }

@@ -29,11 +29,18 @@ bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* 
                     std::vector<int32_t>& trowptr, std::vector<int32_t>& tcol,
                     std::vector<int32_t>& tperm);
 
-// Index sets, local layouts, envelopes and overlap maps of every subdomain.
+// Index sets, local layouts and envelopes of every subdomain.
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
                 const std::vector<int32_t>& trowptr, const std::vector<int32_t>& tcol,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
                 HostPlan& P, std::string& err);
+
+// Overlap maps of a built plan: for every column the local positions holding
+// it (own_ptr / own_pos), for every row the subdomains whose Xi holds it and
+// its rank there (rsub_*).  Reads the rest of P only, so it may run while the
+// device works on the built part.
+bool plan_maps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
+               const int32_t* part, HostPlan& P, std::string& err);
 
 // Coarse numbering (per instance, subdomains in order, padded to 32), the
 // pairs of subdomains whose rows overlap (blocks of E), the tile envelope of
