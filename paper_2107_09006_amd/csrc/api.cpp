@@ -74,18 +74,40 @@ struct lsq2l_ctx {
   std::vector<void*> dev_allocs;
   std::vector<void*> host_allocs;
 
+  // Device memory of the handle: requests up to ARENA_SMALL bytes are carved
+  // (256-byte aligned) from ARENA_CHUNK-sized allocations, larger ones get
+  // their own; everything is released when the handle is destroyed.
+  static constexpr size_t ARENA_CHUNK = (size_t)256 << 20, ARENA_SMALL = (size_t)64 << 20;
+  char* arena_cur = nullptr;
+  size_t arena_used = 0;
+  lsq2l_status raw_alloc(void** v, size_t bytes) {
+    hipError_t e = hipMalloc(v, bytes);
+    if (e != hipSuccess) {
+      set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+      return LSQ2L_ENOMEM;
+    }
+    dev_allocs.push_back(*v);
+    return LSQ2L_OK;
+  }
   template <typename T>
   lsq2l_status dalloc(T** ptr, int64_t count) {
     *ptr = nullptr;
     if (count <= 0) return LSQ2L_OK;
+    const size_t bytes = ((size_t)count * sizeof(T) + 255) / 256 * 256;
     void* v = nullptr;
-    hipError_t e = hipMalloc(&v, (size_t)count * sizeof(T));
-    if (e != hipSuccess) {
-      set_error("device allocation of " + std::to_string((size_t)count * sizeof(T)) +
-                " bytes failed: " + hipGetErrorString(e));
-      return LSQ2L_ENOMEM;
+    if (bytes > ARENA_SMALL) {
+      lsq2l_status s = raw_alloc(&v, bytes);
+      if (s != LSQ2L_OK) return s;
+    } else {
+      if (!arena_cur || arena_used + bytes > ARENA_CHUNK) {
+        lsq2l_status s = raw_alloc(&v, ARENA_CHUNK);
+        if (s != LSQ2L_OK) return s;
+        arena_cur = (char*)v;
+        arena_used = 0;
+      }
+      v = arena_cur + arena_used;
+      arena_used += bytes;
     }
-    dev_allocs.push_back(v);
     *ptr = (T*)v;
     return LSQ2L_OK;
   }
@@ -557,8 +579,8 @@ lsq2l_status lsq2l_setup(int32_t m, int32_t n, int32_t nnz, const int32_t* rowpt
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
   if (rp[m] != nnz) { set_error("rowptr[m] != nnz"); return fail(LSQ2L_EINVAL); }
   if ((s = validate_csr(m, n, rp, ci)) != LSQ2L_OK) return fail(s);
-  e = hipMemcpyAsync(c->M.rowptr, rp.data(), (m + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
-  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.colind, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
+  e = hipMemcpyAsync(c->M.rowptr, rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.colind, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
   if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
   if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
   std::vector<int32_t> seg_of_part(nparts, 0);
