@@ -70,6 +70,7 @@ struct lsq2l_ctx {
   double* h_rn2 = nullptr;        // pinned
   double* h_r0n2 = nullptr;       // pinned
   std::vector<int32_t> p_h;
+  int max_p = 0;
   lsq2l_setup_info info{};
   std::vector<void*> dev_allocs;
   std::vector<void*> host_allocs;
@@ -166,7 +167,7 @@ void apply_M(lsq2l_ctx* c, const double* r, double* z) {
   else
     launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
   if (c->coarse) {
-    launch_coarse_restrict(st, c->nsub, c->P, c->X, r, c->cvec);
+    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
     launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
   }
   launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
@@ -383,6 +384,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
     plan_coarse(H, c->S, m, ph, CP);
     c->segs_h = CP.segs;
     for (int i = 0; i < nparts; ++i) c->p_h[i] = ph[i];
+    c->max_p = *std::max_element(ph.begin(), ph.begin() + nparts);
     c->n0 = CP.n0;
     c->n0tot = CP.n0tot;
     c->etiles = CP.etiles;

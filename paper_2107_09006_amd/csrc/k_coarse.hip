@@ -560,21 +560,28 @@ k_esym_pass1(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict_
   }
 }
 
-__global__ void k_esym_pass2(int64_t n0tot, int S, const SegDesc* __restrict__ segs,
-                             const double* __restrict__ part, const double* __restrict__ uvec,
-                             double* __restrict__ dvec) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n0tot) return;
-  int s = 0;
-  while (s + 1 < S && segs[s + 1].c0 <= row) ++s;
-  const SegDesc sg = segs[s];
+__global__ void __launch_bounds__(256)
+k_esym_pass2(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
+             const double* __restrict__ part, const double* __restrict__ uvec,
+             double* __restrict__ dvec) {
+  // one workgroup per tile row I: d_I = u_I + sum over J < I of the partial
+  // of tile column J at rows I (8 groups of 32 threads split J; fixed order)
+  __shared__ double sp[8][TS];
+  const int cglob = blockIdx.x;
+  const SegDesc sg = segs[seg_of_tile[cglob]];
+  const int I = cglob - (int)sg.etile0;
   const int64_t ld = sg.etiles * TS;
-  const int64_t lr = row - sg.c0;
-  const int I = (int)(lr / TS);
   const double* P = part + sg.einv_off / TS;
-  double acc = uvec[row];
-  for (int J = 0; J < I; ++J) acc += P[(int64_t)J * ld + lr];
-  dvec[row] = acc;
+  const int r = threadIdx.x % TS, g = threadIdx.x / TS;
+  double s = 0.0;
+  for (int J = g; J < I; J += 8) s += P[(int64_t)J * ld + I * TS + r];
+  sp[g][r] = s;
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    double acc = uvec[sg.c0 + I * TS + r];
+    for (int q = 0; q < 8; ++q) acc += sp[q][r];
+    dvec[sg.c0 + I * TS + r] = acc;
+  }
 }
 
 __global__ void k_set_values(int64_t n, const int64_t* __restrict__ idx, double v,
@@ -635,8 +642,9 @@ void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const do
                                                    Cc.eptr, efac, edinv, einv);
 }
 
-void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
                             const double* r, double* c) {
+  if (max_p <= 0) return;
   k_coarse_restrict<<<nsub, 1024, 0, st>>>(P.subs, P.omega, X, r, c);
 }
 
@@ -645,7 +653,7 @@ void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, co
   if (n0 == 0) return;
   const int ntiles = (int)(n0 / TS);
   k_esym_pass1<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, einv, c, Cc.e_part, Cc.e_u);
-  k_esym_pass2<<<(unsigned)((n0 + 255) / 256), 256, 0, st>>>(n0, S, Cc.segs, Cc.e_part, Cc.e_u, d);
+  k_esym_pass2<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, Cc.e_part, Cc.e_u, d);
 }
 
 }  // namespace lsq2l

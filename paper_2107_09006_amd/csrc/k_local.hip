@@ -78,39 +78,48 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
 // Symmetric diagonal equilibration S C S, S = diag(C)^{-1/2} (an exact
 // congruence: C^{-1} = S (S C S)^{-1} S), applied to C_ii and to Ct_GG; the
 // padding rows become identity rows.  scale[pos] = S_pos (0 on padding).
+// k_equil_scale forms S per subdomain; k_equil_apply scales the stored tiles
+// and Ct_GG, workgroup (i, y) taking tile rows y, y + gridDim.y, ...
 __global__ void __launch_bounds__(256)
-k_equilibrate(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+k_equil_scale(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+              const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
+              double* __restrict__ scale) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  double* s = scale + d.loc_off;
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    const bool real = pos < d.nI || (pos >= d.nIp && pos < d.nIp + d.nG);
+    const double* diag = A + tile_pos(F, off, pos / TS, pos / TS) * TT + (pos % TS) * TS + pos % TS;
+    s[pos] = real ? 1.0 / sqrt(*diag) : 0.0;   // diagonal > 0: every column of Omega_i has a stored entry
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_equil_apply(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
               const int64_t* __restrict__ tileOff, double* __restrict__ fac,
-              double* __restrict__ ctg, double* __restrict__ scale) {
+              double* __restrict__ ctg, const double* __restrict__ scale) {
   const SubDesc d = subs[blockIdx.x];
   const int32_t* F = tileF + d.tile_base;
   const int64_t* off = tileOff + d.tile_base;
   double* A = fac + d.fac_off;
-  double* s = scale + d.loc_off;
-  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
-    const bool real = pos < d.nI || (pos >= d.nIp && pos < d.nIp + d.nG);
-    double* diag = A + tile_pos(F, off, pos / TS, pos / TS) * TT + (pos % TS) * TS + pos % TS;
-    if (real) {
-      s[pos] = 1.0 / sqrt(*diag);   // diagonal > 0: every column of Omega_i has a stored entry
-    } else {
-      s[pos] = 0.0;
-    }
-  }
-  __syncthreads();
-  for (int t = 0; t < d.ntiles; ++t) {
+  const double* s = scale + d.loc_off;
+  for (int t = blockIdx.y; t < d.ntiles; t += gridDim.y) {
     const int nt = t - F[t] + 1;
+    double* row = A + off[t] * TT;
     for (int64_t e = threadIdx.x; e < (int64_t)nt * TT; e += blockDim.x) {
       const int J = F[t] + (int)(e / TT);
       const int rc = (int)(e % TT);
       const int r = t * TS + rc % TS, c = J * TS + rc / TS;
-      double* ptr = A + (off[t] + (J - F[t])) * TT + rc;
       const double sr = s[r], sc = s[c];
-      if (r == c && sr == 0.0) *ptr = 1.0;
-      else *ptr *= sr * sc;
+      if (r == c && sr == 0.0) row[e] = 1.0;
+      else row[e] *= sr * sc;
     }
   }
   double* Ct = ctg + d.g_off;
-  for (int64_t e = threadIdx.x; e < (int64_t)d.nGp * d.nGp; e += blockDim.x) {
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < (int64_t)d.nGp * d.nGp;
+       e += (int64_t)gridDim.y * blockDim.x) {
     const int r = (int)(e % d.nGp), c = (int)(e / d.nGp);
     Ct[e] *= s[d.nIp + r] * s[d.nIp + c];   // zero on padding
   }
@@ -513,7 +522,8 @@ void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix
 
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
                         double* scale) {
-  k_equilibrate<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, ctg, scale);
+  k_equil_scale<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, scale);
+  k_equil_apply<<<dim3(nsub, 32), 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, ctg, scale);
 }
 
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,

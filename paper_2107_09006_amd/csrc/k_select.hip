@@ -149,6 +149,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __shared__ double sd[SEL_MAXN], se[SEL_MAXN], stau[SEL_MAXN], sv[SEL_MAXN], sw[SEL_MAXN],
       sD2[SEL_MAXN], slam[SEL_MAXN];
   __shared__ int sperm[SEL_MAXN], scl[SEL_MAXN + 1];
+  __shared__ double spart[4][SEL_MAXN];
   __shared__ double sred[16];
   __shared__ int sredi[16];
   __shared__ int s_r, s_p, s_nclus, s_diag;
@@ -313,11 +314,22 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     if (tid == 0) { se[k] = beta; sd[k] = M0[(int64_t)k * ld + k]; stau[k] = tk; }
     for (int a = 1 + tid; a < m; a += nthr) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
     if (tk != 0.0) {
+      // w = tk A22 v: four thread groups split the columns of A22, their
+      // partial sums are added in a fixed order
+      {
+        const int g = tid / 256, t256 = tid % 256;
+        for (int a0 = 0; a0 < m; a0 += 256) {
+          const int a = a0 + t256;
+          double s = 0.0;
+          if (a < m)
+            for (int b = g; b < m; b += 4) s += M0[(int64_t)(k + 1 + b) * ld + k + 1 + a] * sv[b];
+          if (a < m) spart[g][a] = s;
+        }
+      }
+      __syncthreads();
       double pp = 0.0;
       for (int a = tid; a < m; a += nthr) {
-        double s = 0.0;
-        for (int b = 0; b < m; ++b) s += M0[(int64_t)(k + 1 + b) * ld + k + 1 + a] * sv[b];
-        sw[a] = tk * s;
+        sw[a] = tk * (((spart[0][a] + spart[1][a]) + spart[2][a]) + spart[3][a]);
         pp += sw[a] * sv[a];
       }
       const double wv = wg_sum(pp, sred);
@@ -401,7 +413,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     M1[q] = row < r ? sin((row + 1.0) * (j + 1.0)) : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 6; ++sweep) {
+  for (int sweep = 0; sweep < 4; ++sweep) {
     for (int j0 = 0; j0 < p; j0 += slots) {
       const int j = j0 + tid;
       if (tid >= slots || j >= p) continue;
@@ -414,7 +426,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       tri_solve(sd, se, r, slam[j], tiny, x, scr, scr + r, scr + 2 * r);
     }
     __syncthreads();
-    if (sweep < 4) continue;
+    if (sweep < 2) continue;
     // normalise every vector (one wave per vector)
     for (int j = wave; j < p; j += nw) {
       double* x = M1 + (int64_t)j * ld;

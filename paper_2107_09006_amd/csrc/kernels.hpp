@@ -106,7 +106,7 @@ void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32
                          double* efac);
 void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
                  const double* edinv, double* einv);
-void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, const double* X,
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
                             const double* r, double* c);
 void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, double* out);
 void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,
