@@ -302,11 +302,25 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   auto t_all = clk::now();
   auto t0 = clk::now();
   // --- transpose and index sets
-  std::vector<int32_t> trp, tcol, tperm;
-  plan_transpose(m, n, rp.data(), ci.data(), trp, tcol, tperm);
-  TRY(c->upload(&c->M.trowptr, trp));
-  TRY(c->upload(&c->M.trow, tcol));
-  TRY(c->upload(&c->M.tperm, tperm));
+  // A^T on the device; the planner reads its pattern back
+  std::vector<int32_t> trp((size_t)n + 1), tcol((size_t)nnz);
+  {
+    int32_t *keys = nullptr, *vals = nullptr, *rows = nullptr;
+    char* temp = nullptr;
+    const size_t tb = transpose_temp_bytes(nnz, n);
+    TRY(c->dalloc(&c->M.trowptr, (int64_t)n + 1));
+    TRY(c->dalloc(&c->M.trow, nnz));
+    TRY(c->dalloc(&c->M.tperm, nnz));
+    TRY(c->dalloc(&keys, nnz));
+    TRY(c->dalloc(&vals, nnz));
+    TRY(c->dalloc(&rows, nnz));
+    TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
+    LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.trowptr, c->M.trow,
+                                   c->M.tperm, keys, vals, rows, temp, tb));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(trp.data(), c->M.trowptr, trp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.data(), c->M.trow, tcol.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  }
   TRY(c->dalloc(&c->M.tvals, nnz));
   launch_gather_values(st, nnz, c->M.tperm, c->M.vals, c->M.tvals);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
@@ -428,7 +442,39 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       TRY(c->dalloc(&c->einv, CP.einv_tot));
       TRY(c->dalloc(&c->Cc.e_part, CP.einv_tot / TS));
       TRY(c->dalloc(&c->Cc.e_u, c->n0tot));
-      launch_einv(st, (int)c->etiles, c->Cc, c->efac, c->edinv, c->einv);
+      {
+        // column blocks of E^{-1} onto one workgroup per compute unit, longest
+        // first to the least loaded (block c of an instance with nt tile rows
+        // costs 2 (nt - c) + 1 tile-row steps)
+        int ncu = 0;
+        LSQ2L_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0));
+        const int nbins = (int)std::min<int64_t>(std::max(1, ncu), c->etiles);
+        std::vector<std::pair<int64_t, int32_t>> items;
+        for (const SegDesc& sg : CP.segs)
+          for (int64_t cc = 0; cc < sg.etiles; ++cc)
+            items.push_back({2 * (sg.etiles - cc) + 1, (int32_t)(sg.etile0 + cc)});
+        std::stable_sort(items.begin(), items.end(),
+                         [](const auto& x, const auto& y) { return x.first > y.first; });
+        std::vector<std::vector<int32_t>> bins(nbins);
+        std::vector<std::pair<int64_t, int>> load;   // min-heap of (load, bin)
+        for (int bb = 0; bb < nbins; ++bb) load.push_back({0, bb});
+        auto cmp = [](const auto& x, const auto& y) { return x > y; };
+        for (const auto& it : items) {
+          std::pop_heap(load.begin(), load.end(), cmp);
+          auto& top = load.back();
+          bins[top.second].push_back(it.second);
+          top.first += it.first;
+          std::push_heap(load.begin(), load.end(), cmp);
+        }
+        std::vector<int32_t> bptr(1, 0), bcols;
+        for (const auto& bl : bins) {
+          bcols.insert(bcols.end(), bl.begin(), bl.end());
+          bptr.push_back((int32_t)bcols.size());
+        }
+        TRY(c->upload(&c->Cc.einv_bin_ptr, bptr));
+        TRY(c->upload(&c->Cc.einv_bin_cols, bcols));
+        launch_einv(st, nbins, c->Cc, c->efac, c->edinv, c->einv);
+      }
       TRY(c->dalloc(&c->cvec, c->n0tot));
       TRY(c->dalloc(&c->dvec, c->n0tot));
       LSQ2L_HIP_TRY(hipMemsetAsync(c->cvec, 0, c->n0tot * sizeof(double), st));

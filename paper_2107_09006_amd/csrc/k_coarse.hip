@@ -378,96 +378,209 @@ __device__ inline void tile_frag_mma(double4_t acc[4], const TileFrag& f) {
         acc[bi * 2 + bj] = Mfma<double>::mma(f.a[bi][q], f.b[bj][q], acc[bi * 2 + bj]);
 }
 
-// Dense inverse of E per instance, lower block triangle.  Workgroup c solves
-// L L^T X = I(:, c) for the 32 columns of tile column c, rows >= c only:
-// forward substitution Y(I) = L_II^{-1} (delta_Ic I - sum_K L(I,K) Y(K)) for
-// I >= c, then backward substitution X(K) = L_KK^{-T} (Y(K) - sum_I L(I,K)^T
-// X(I)) for K from the last tile down to c.  Both sweeps are left-looking, so
-// every output tile is written once; the tile sum of a step is split over the
-// waves, whose partials are added in a fixed order.
-constexpr int EINV_WAVES = 8;
+// Dense inverse of E per instance, lower block triangle.  Column block c
+// (32 columns) solves L L^T X = I(:, c), rows >= c only: forward substitution
+// Y(I) = L_II^{-1} (delta_Ic I - sum_K L(I,K) Y(K)) for I >= c, then backward
+// substitution X(K) = L_KK^{-T} (Y(K) - sum_I L(I,K)^T X(I)) for K from the
+// last tile down to c.  Both sweeps are left-looking, so every output tile is
+// written once.
+//
+// The band of already computed tiles that a step needs stays in registers:
+// wave w keeps the EWIN_SLOTS most recent tiles with index = w (mod 4) as MFMA
+// B fragments, so a step reads only the tiles of L (shared by all column
+// blocks).  Tiles further back than the window are read from memory.  The
+// wave partials of a step are added in a fixed order.  Each workgroup works
+// through a list of column blocks chosen so that the lists have equal work
+// (the work of block c is proportional to the number of tile rows below c).
+constexpr int EINV_WAVES = 4;
+constexpr int EWIN_SLOTS = 6;
+
+struct AFrag { double a[2][8]; };
+
+template <bool TA>
+__device__ inline void afrag_load(AFrag& f, const double* A, int lda, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 4 * q + lk;
+      f.a[h][q] = TA ? A[(int64_t)(16 * h + li) * lda + k] : A[(int64_t)k * lda + 16 * h + li];
+    }
+}
+
+__device__ inline void frag_mma(double4_t acc[4], const AFrag& f, const double (&b)[2][8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi * 2 + bj] = Mfma<double>::mma(f.a[bi][q], b[bj][q], acc[bi * 2 + bj]);
+}
+
+// B fragments of a 32 x 32 column-major tile (leading dimension ld)
+__device__ inline void bfrag_load(double (&b)[2][8], const double* B, int ld, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) b[h][q] = B[(int64_t)(16 * h + li) * ld + 4 * q + lk];
+}
 
 __global__ void __launch_bounds__(EINV_WAVES * 64)
 k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
        const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
        const int32_t* __restrict__ erows, const int64_t* __restrict__ eptr,
+       const int32_t* __restrict__ bin_ptr, const int32_t* __restrict__ bin_cols,
        const double* __restrict__ efac, const double* __restrict__ edinv, double* __restrict__ einv) {
-  __shared__ double sY[TS * LDT];
+  __shared__ double sY[TS * LDT], sN[TS * LDT];
   __shared__ double spart[EINV_WAVES][TT];
-  const int cglob = blockIdx.x;
-  const SegDesc sg = segs[seg_of_tile[cglob]];
-  const int t0 = (int)sg.etile0, nt = (int)sg.etiles;
-  const int c = cglob - t0;
-  const int ld = nt * TS;
-  double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int wave = tid / 64, lane = tid % 64;
-  const int q4 = wave % 4, bi = q4 / 2, bj = q4 % 2;
+  const int w = tid / 64, lane = tid % 64;
+  const int bi = w / 2, bj = w % 2;          // quadrant of the diagonal products
 
-  // partial sums of this wave -> spart[wave] (accumulator layout)
   auto put_partial = [&](const double4_t acc[4]) {
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) spart[wave][(qd * 4 + v) * 64 + lane] = acc[qd][v];
+      for (int v = 0; v < 4; ++v) spart[w][(qd * 4 + v) * 64 + lane] = acc[qd][v];
   };
-  // element e of the accumulator layout -> (row, col) of the tile
   auto elem_rc = [](int e, int& row, int& col) {
     const int l = e % 64, v = (e / 64) % 4, qd = e / 256;
     row = 16 * (qd / 2) + Mfma<double>::acc_row(l, v);
     col = 16 * (qd % 2) + Mfma<double>::acc_col(l, v);
   };
 
-  for (int I = c; I < nt; ++I) {
-    const int Ig = t0 + I;
-    double4_t acc[4];
-    tile_acc_zero<double>(acc);
-    for (int K = max(eF[Ig] - t0, c) + wave; K < I; K += EINV_WAVES) {
-      TileFrag f;
-      tile_frag_load<false>(f, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, Xc + K * TS, ld, lane);
-      tile_frag_mma(acc, f);
+  for (int item = bin_ptr[blockIdx.x]; item < bin_ptr[blockIdx.x + 1]; ++item) {
+    const int cglob = bin_cols[item];
+    const SegDesc sg = segs[seg_of_tile[cglob]];
+    const int t0 = (int)sg.etile0, nt = (int)sg.etiles;
+    const int c = cglob - t0;
+    const int ld = nt * TS;
+    double* Xc = einv + sg.einv_off + (int64_t)c * TS * ld;
+    double win[EWIN_SLOTS][2][8];
+    int wk[EWIN_SLOTS];                     // tile index held by each slot (-1: empty)
+
+    // ---- forward
+#pragma unroll
+    for (int sl = 0; sl < EWIN_SLOTS; ++sl) wk[sl] = -1;
+    for (int I = c; I < nt; ++I) {
+      const int Ig = t0 + I;
+      const int K0 = max(eF[Ig] - t0, c);
+      double4_t acc[4];
+      tile_acc_zero<double>(acc);
+      // tiles of this wave evicted from its window (the window holds every
+      // later tile of the wave, so an empty window means there is none)
+      int kold = K0;
+#pragma unroll
+      for (int sl = EWIN_SLOTS - 1; sl >= 0; --sl)
+        if (wk[sl] >= 0) kold = wk[sl];
+      for (int K = K0 + ((w - K0 % EINV_WAVES) + EINV_WAVES) % EINV_WAVES; K < kold; K += EINV_WAVES) {
+        AFrag f;
+        double b[2][8];
+        afrag_load<false>(f, efac + tile_pos(eF, eOff, Ig, t0 + K) * TT, TS, lane);
+        bfrag_load(b, Xc + K * TS, ld, lane);
+        frag_mma(acc, f, b);
+      }
+#pragma unroll
+      for (int sl = 0; sl < EWIN_SLOTS; ++sl)
+        if (wk[sl] >= K0) {
+          AFrag f;
+          afrag_load<false>(f, efac + tile_pos(eF, eOff, Ig, t0 + wk[sl]) * TT, TS, lane);
+          frag_mma(acc, f, win[sl]);
+        }
+      put_partial(acc);
+      __syncthreads();
+      for (int e = tid; e < TT; e += nthr) {
+        int row, col;
+        elem_rc(e, row, col);
+        double v = (I == c && row == col) ? 1.0 : 0.0;
+        for (int q = 0; q < EINV_WAVES; ++q) v -= spart[q][e];
+        sY[col * LDT + row] = v;
+      }
+      __syncthreads();
+      {
+        double4_t y = {0.0, 0.0, 0.0, 0.0};
+        quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+        quad_store(y, Xc + I * TS, ld, bi, bj, lane);
+        quad_store(y, sN, LDT, bi, bj, lane);
+      }
+      __syncthreads();
+      if (I % EINV_WAVES == w) {            // the new tile enters this wave's window
+#pragma unroll
+        for (int sl = 0; sl + 1 < EWIN_SLOTS; ++sl) {
+          wk[sl] = wk[sl + 1];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) win[sl][h][q] = win[sl + 1][h][q];
+        }
+        wk[EWIN_SLOTS - 1] = I;
+        bfrag_load(win[EWIN_SLOTS - 1], sN, LDT, lane);
+      }
     }
-    put_partial(acc);
-    __syncthreads();
-    for (int e = tid; e < TT; e += nthr) {
-      int row, col;
-      elem_rc(e, row, col);
-      double s = (I == c && row == col) ? 1.0 : 0.0;
-      for (int w = 0; w < EINV_WAVES; ++w) s -= spart[w][e];
-      sY[col * LDT + row] = s;
-    }
-    __syncthreads();
-    if (wave < 4) {
-      double4_t y = {0.0, 0.0, 0.0, 0.0};
-      quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
-      quad_store(y, Xc + I * TS, ld, bi, bj, lane);
-    }
-    __syncthreads();
-  }
-  for (int K = nt - 1; K >= c; --K) {
-    const int Kg = t0 + K;
-    double4_t acc[4];
-    tile_acc_zero<double>(acc);
-    for (int64_t u = eptr[Kg] + wave; u < eptr[Kg + 1]; u += EINV_WAVES) {
-      const int Ig = erows[u];
-      TileFrag f;
-      tile_frag_load<true>(f, efac + tile_pos(eF, eOff, Ig, Kg) * TT, TS, Xc + (Ig - t0) * TS, ld, lane);
-      tile_frag_mma(acc, f);
-    }
-    put_partial(acc);
-    __syncthreads();
-    for (int e = tid; e < TT; e += nthr) {
-      int row, col;
-      elem_rc(e, row, col);
-      double s = Xc[(int64_t)col * ld + K * TS + row];
-      for (int w = 0; w < EINV_WAVES; ++w) s -= spart[w][e];
-      sY[col * LDT + row] = s;
-    }
-    __syncthreads();
-    if (wave < 4) {
-      double4_t x = {0.0, 0.0, 0.0, 0.0};
-      quad_mma<true>(x, edinv + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
-      quad_store(x, Xc + K * TS, ld, bi, bj, lane);
+
+    // ---- backward
+#pragma unroll
+    for (int sl = 0; sl < EWIN_SLOTS; ++sl) wk[sl] = -1;
+    for (int K = nt - 1; K >= c; --K) {
+      const int Kg = t0 + K;
+      double4_t acc[4];
+      tile_acc_zero<double>(acc);
+      // rows of this wave evicted from its window (rows above its oldest
+      // slot; an empty window means the wave has no computed row yet)
+      int ifar = nt;
+#pragma unroll
+      for (int sl = EWIN_SLOTS - 1; sl >= 0; --sl)
+        if (wk[sl] >= 0) ifar = wk[sl];
+      for (int64_t u = eptr[Kg]; u < eptr[Kg + 1]; ++u) {
+        const int I = erows[u] - t0;
+        if (I % EINV_WAVES != w || I <= ifar) continue;
+        AFrag f;
+        double b[2][8];
+        afrag_load<true>(f, efac + tile_pos(eF, eOff, t0 + I, Kg) * TT, TS, lane);
+        bfrag_load(b, Xc + I * TS, ld, lane);
+        frag_mma(acc, f, b);
+      }
+#pragma unroll
+      for (int sl = 0; sl < EWIN_SLOTS; ++sl) {
+        const int I = wk[sl];
+        if (I >= 0 && eF[t0 + I] <= Kg) {
+          AFrag f;
+          afrag_load<true>(f, efac + tile_pos(eF, eOff, t0 + I, Kg) * TT, TS, lane);
+          frag_mma(acc, f, win[sl]);
+        }
+      }
+      put_partial(acc);
+      __syncthreads();
+      for (int e = tid; e < TT; e += nthr) {
+        int row, col;
+        elem_rc(e, row, col);
+        double v = Xc[(int64_t)col * ld + K * TS + row];
+        for (int q = 0; q < EINV_WAVES; ++q) v -= spart[q][e];
+        sY[col * LDT + row] = v;
+      }
+      __syncthreads();
+      {
+        double4_t x = {0.0, 0.0, 0.0, 0.0};
+        quad_mma<true>(x, edinv + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
+        quad_store(x, Xc + K * TS, ld, bi, bj, lane);
+        quad_store(x, sN, LDT, bi, bj, lane);
+      }
+      __syncthreads();
+      if (K % EINV_WAVES == w) {
+#pragma unroll
+        for (int sl = 0; sl + 1 < EWIN_SLOTS; ++sl) {
+          wk[sl] = wk[sl + 1];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) win[sl][h][q] = win[sl + 1][h][q];
+        }
+        wk[EWIN_SLOTS - 1] = K;
+        bfrag_load(win[EWIN_SLOTS - 1], sN, LDT, lane);
+      }
     }
     __syncthreads();
   }
@@ -635,11 +748,12 @@ void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32
   k_echol_update<<<(unsigned)((npairs + 3) / 4), 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac);
 }
 
-void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
+void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
                  const double* edinv, double* einv) {
-  if (ntiles_total == 0) return;
-  k_einv<<<ntiles_total, EINV_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, Cc.erows,
-                                                   Cc.eptr, efac, edinv, einv);
+  if (nbins == 0) return;
+  k_einv<<<nbins, EINV_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, Cc.erows,
+                                            Cc.eptr, Cc.einv_bin_ptr, Cc.einv_bin_cols, efac, edinv,
+                                            einv);
 }
 
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,

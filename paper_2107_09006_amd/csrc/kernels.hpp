@@ -40,10 +40,19 @@ struct DevCoarse {            // coarse space and coarse operator
   int32_t* e_seg_of_tile = nullptr;
   int32_t* erows = nullptr;       // per tile column K: tile rows I > K with F(I) <= K
   int64_t* eptr = nullptr;
+  int32_t* einv_bin_ptr = nullptr;   // per workgroup of the inverse: its column blocks
+  int32_t* einv_bin_cols = nullptr;
   int4* e_items = nullptr;        // (pair, row block, column block) work items of E
   double* e_part = nullptr;       // row partials of the symmetric coarse solve
   double* e_u = nullptr;          // column parts of the symmetric coarse solve
 };
+
+// --- device transpose of A's pattern ---------------------------------------
+size_t transpose_temp_bytes(int64_t nnz, int32_t n);
+hipError_t launch_transpose(hipStream_t st, int32_t m, int32_t n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* colind, int32_t* trowptr, int32_t* trow, int32_t* tperm,
+                            int32_t* work_keys, int32_t* work_vals, int32_t* work_rows, void* temp,
+                            size_t temp_bytes);
 
 // --- sparse kernels -------------------------------------------------------
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
@@ -104,7 +113,7 @@ void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t
                        double* efac, double* edinv, int32_t* status);
 void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                          double* efac);
-void launch_einv(hipStream_t st, int ntiles_total, const DevCoarse& Cc, const double* efac,
+void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
                  const double* edinv, double* einv);
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
                             const double* r, double* c);
