@@ -36,9 +36,9 @@ CALIB_BYTES = 1 << 30          # plain device copy used to calibrate HBM counter
 # script, each scaled by the same counter's reading for the calibration copy
 # (profiles/local_solve_grid1000.md).  It describes the kernel source whose
 # SHA-256 is given; for any other source the figure is reported as null.
-TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_local.hip",
-           "sha256": "64a4f51b0b2d46e2a4eabb1699d94c298f010e402c29438fb8e842fa2bd77c7c",
-           "bytes": 1930689223}
+TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip",
+           "sha256": "e59fd33e85146c45c5723e14fda306d5d49992c7bba69529d8745aea3b9f2077",
+           "bytes": 1930644586}
 
 
 def log(*a):
