@@ -341,6 +341,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   TRY(c->upload(&c->P.locown, H.locown));
   TRY(c->upload(&c->P.tileF, H.tileF));
   TRY(c->upload(&c->P.tileOff, H.tileOff));
+  for (const SubDesc& d : H.subs) c->P.max_np = std::max(c->P.max_np, (int)d.np);
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_plan_ms = ms_since(t0);
   // --- local matrices

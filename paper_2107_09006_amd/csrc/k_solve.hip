@@ -1,6 +1,8 @@
 // Per-iteration local solves of the preconditioner: L L^T y = loc_i for every
 // subdomain with its tile-envelope factor (Algorithm 1, the local terms of
 // eq. (two_level_schwarz)), in FP64 or with the FP32 copy of the factor.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace lsq2l {
@@ -173,6 +175,306 @@ __device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_
   for (int q = tid; q < d.np; q += blockDim.x) yg[q] = ys[q];
 }
 
+// ---------------------------------------------------------------------------
+// Streaming variant for subdomains with np <= PCAP.  The tiles a sweep reads
+// form one stream: forward, row by row, the off-diagonal tiles (I, F(I)) ..
+// (I, I - 1) followed by the diagonal inverse of row I; the backward sweep
+// reads the same stream in reverse.  Since tile rows are stored one after
+// the other (F(I) .. I each), stream position t is factor tile t of the
+// subdomain, except that the last position of each row, where the diagonal
+// block sits, is served from the inverse.
+//
+// Waves 1..3 (producers) copy the stream in blocks of PB tiles into a
+// two-block LDS ring, with PD more blocks in flight in their registers.
+// Their global loads are fully coalesced (each instruction reads 1 KiB of
+// one tile).  Wave 0 (consumer) does all the arithmetic: it owns every row,
+// so no partial sums cross waves.  The LDS copy of a tile is row-major in
+// the forward sweep and column-major in the backward sweep, so that in both
+// lane (a, h) = (l % 32, l / 32) reads 16 consecutive entries with vector
+// loads: forward L(a, 16 h .. 16 h + 15) for row a of L y, backward
+// L(16 h .. 16 h + 15, a) for column a of L^T x.  One shuffle joins the
+// halves h = 0, 1.  Producer and consumer loops execute the same number of
+// block barriers.
+// ---------------------------------------------------------------------------
+constexpr int PCAP = 4608;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct PipeCfg;
+template <> struct PipeCfg<float> {
+  static constexpr int PB = 12, PD = 2;
+  using V = f32x4;
+};
+template <> struct PipeCfg<double> {
+  static constexpr int PB = 7, PD = 2;
+  using V = f64x2;
+};
+template <int V> using IC = std::integral_constant<int, V>;
+template <int B, int E, typename Fn>
+__device__ inline void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(IC<B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
+// 16 consecutive LDS entries of a tile, as doubles
+template <typename T>
+__device__ inline void lds_row16(double (&x)[16], const T* p) {
+  using V = typename PipeCfg<T>::V;
+  constexpr int NV = 16 * sizeof(T) / sizeof(V);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const V v = reinterpret_cast<const V*>(p)[c];
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int i = 0; i < 16 / NV; ++i) x[c * (16 / NV) + i] = (double)e[i];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+                   const T* __restrict__ fac, const T* __restrict__ dinv,
+                   double* __restrict__ loc) {
+  using V = typename PipeCfg<T>::V;
+  using GV = __attribute__((address_space(1))) V;   // global memory: loads count against vmcnt only
+  constexpr int PB = PipeCfg<T>::PB;
+  constexpr int PD = PipeCfg<T>::PD;
+  constexpr int EV = sizeof(V) / sizeof(T);          // entries per vector
+  constexpr int NC = TT / EV / 64;                   // vectors per lane and tile
+  constexpr int PLD = TS + EV;                       // LDS leading dimension of a tile
+  constexpr int TL = TS * PLD;
+  constexpr int PW = (PB + 2) / 3;                   // tiles per producer wave and block
+  __shared__ double ys[PCAP];
+  __shared__ __align__(16) T ring[2][PB][TL];
+  __shared__ int32_t sF[PCAP / TS], sS[PCAP / TS + 1];
+  __shared__ double sv[TS];
+  const SubDesc d = subs[blockIdx.x];
+  if (d.np > PCAP) return;
+  const int32_t* F = tileF + d.tile_base;
+  const T* A = fac + d.fac_off;
+  const T* Di = dinv + d.dinv_off;
+  double* yg = loc + d.loc_off;
+  const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int a = lane % 32, h = lane / 32;
+  const int nt = d.ntiles;
+  for (int q = tid; q < d.np; q += blockDim.x) ys[q] = yg[q];
+  for (int q = tid; q < nt; q += blockDim.x) sF[q] = F[q];
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int I = 0; I < nt; ++I) { sS[I] = acc; acc += I - sF[I] + 1; }
+    sS[nt] = acc;
+  }
+  __syncthreads();
+  const int N = sS[nt];                              // stream length
+  const int nblk = (N + PB - 1) / PB;
+
+  // ---- producers.  The walk over the stream keeps the row (wI) and its
+  // first and one-past-last positions, reading sS once per row.
+  int wI = 0, wlo = 0, whi = 0;
+  V vals[PD][PW][NC];
+  bool have[PD][PW];
+  // fetch<r>(b): block b into register slot r
+  auto fetch = [&](int b, bool rev, auto slot) {
+    constexpr int r = decltype(slot)::value;
+    const int pw = w - 1;
+    const T* src[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      src[q] = A;
+      have[r][q] = false;
+    }
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+      const int pos = b * PB + j;
+      if (pos < N) {
+        const int t = rev ? N - 1 - pos : pos;
+        if (rev) {
+          while (t < wlo) { --wI; whi = wlo; wlo = sS[wI]; }
+        } else {
+          while (t >= whi) { ++wI; wlo = whi; whi = sS[wI + 1]; }
+        }
+        if (j % 3 == pw) {
+          src[j / 3] = t == whi - 1 ? Di + (int64_t)wI * TT : A + (int64_t)t * TT;
+          have[r][j / 3] = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      if (have[r][q]) {
+        const GV* v = (const GV*)src[q] + lane;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vals[r][q][c] = v[64 * c];
+      }
+    }
+  };
+  // commit<r>(buf): register slot r into ring[buf]; vector c of lane l holds
+  // the EV entries from flat (column-major) index EV (l + 64 c)
+  auto commit = [&](int buf, bool rev, auto slot) {
+    constexpr int r = decltype(slot)::value;
+    const int pw = w - 1;
+#pragma unroll
+    for (int q = 0; q < PW; ++q)
+      if (have[r][q]) {
+        T* tile = ring[buf][pw + 3 * q];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int f0 = EV * (lane + 64 * c), col = f0 / TS, row = f0 % TS;
+          if (rev) {
+            *reinterpret_cast<V*>(tile + col * PLD + row) = vals[r][q][c];
+          } else {
+            const T* e = reinterpret_cast<const T*>(&vals[r][q][c]);
+#pragma unroll
+            for (int i = 0; i < EV; ++i) tile[(row + i) * PLD + col] = e[i];
+          }
+        }
+      }
+  };
+  // one sweep of the producers: block 0 to the ring, blocks 1 .. PD in
+  // flight; during block b, block b + 1 goes to the ring and block
+  // b + 1 + PD is fetched into the register slot it freed
+  auto producer_sweep = [&](bool rev) {
+    wI = rev ? nt - 1 : 0;
+    wlo = nt > 0 ? sS[wI] : 0;
+    whi = nt > 0 ? sS[wI + 1] : 0;
+    fetch(0, rev, IC<0>{});
+    commit(0, rev, IC<0>{});
+    static_for<1, PD + 1>([&](auto i) {
+      if (decltype(i)::value < nblk) fetch(decltype(i)::value, rev, IC<decltype(i)::value % PD>{});
+    });
+    __syncthreads();
+    for (int b0 = 0; b0 < nblk; b0 += PD) {
+      static_for<0, PD>([&](auto i) {
+        constexpr int r = (decltype(i)::value + 1) % PD;
+        const int b = b0 + decltype(i)::value;
+        if (b < nblk) {
+          if (b + 1 < nblk) {
+            commit((b + 1) & 1, rev, IC<r>{});
+            if (b + 1 + PD < nblk) fetch(b + 1 + PD, rev, IC<r>{});
+          }
+          __syncthreads();
+        }
+      });
+    }
+  };
+
+  // ---- forward sweep: y_I = Dinv_I (y_I - sum_K L(I,K) y_K).  Wave 0 keeps
+  // the row (I, F(I), its number nk of off-diagonal tiles) and the next tile
+  // index k in registers and takes the off-diagonal tiles of a block as one
+  // run, with four independent partial sums per lane.
+  if (w > 0) {
+    producer_sweep(false);
+  } else {
+    __syncthreads();
+    int I = 0, k = 0, fI = nt > 0 ? sF[0] : 0, nk = 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < nblk; ++b) {
+      const T (*rb)[TL] = ring[b & 1];
+      const int send = min(N - b * PB, PB);
+      int s = 0;
+      while (s < send && I < nt) {
+        const int run = min(nk - k, send - s);
+        const double* yk = ys + (fI + k) * TS + 16 * h;
+#pragma unroll 2
+        for (int u = 0; u < run; ++u) {
+          double l[16];
+          lds_row16(l, rb[s + u] + a * PLD + 16 * h);
+          const double* y = yk + u * TS;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[j & 3] += l[j] * y[j];
+        }
+        s += run;
+        k += run;
+        if (s < send) {                              // the diagonal inverse of row I
+          double l[16];
+          lds_row16(l, rb[s] + a * PLD + 16 * h);
+          double r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+          r += __shfl_xor(r, 32, 64);
+          if (lane < TS) sv[lane] = ys[I * TS + lane] - r;
+          wave_sync();
+          double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * sv[16 * h + j];
+          double x = (v[0] + v[1]) + (v[2] + v[3]);
+          x += __shfl_xor(x, 32, 64);
+          wave_sync();
+          if (lane < TS) ys[I * TS + lane] = x;
+          wave_sync();
+          ++s;
+          ++I;
+          k = 0;
+          if (I < nt) { fI = sF[I]; nk = I - fI; }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- backward sweep, the stream in reverse: x_I = Dinv_I^T y_I, then
+  // y_K -= L(I,K)^T x_I over the off-diagonal tiles of row I, K = F(I) + k
+  // for k = nk - 1 .. 0 (k = nk stands for the diagonal inverse).
+  if (w > 0) {
+    producer_sweep(true);
+  } else {
+    __syncthreads();
+    int I = nt - 1, fI = nt > 0 ? sF[nt - 1] : 0;
+    int nk = nt > 0 ? I - fI : 0, k = nk;
+    double xr[16];
+    for (int b = 0; b < nblk; ++b) {
+      const T (*rb)[TL] = ring[b & 1];
+      const int send = min(N - b * PB, PB);
+      int s = 0;
+      while (s < send) {
+        if (k == nk) {
+          double l[16];
+          lds_row16(l, rb[s] + a * PLD + 16 * h);
+          double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * ys[I * TS + 16 * h + j];
+          double x = (v[0] + v[1]) + (v[2] + v[3]);
+          x += __shfl_xor(x, 32, 64);
+          wave_sync();
+          if (lane < TS) ys[I * TS + lane] = x;
+          wave_sync();
+#pragma unroll
+          for (int j = 0; j < 16; ++j) xr[j] = ys[I * TS + 16 * h + j];
+          ++s;
+          --k;
+        } else {
+          const int run = min(k + 1, send - s);
+#pragma unroll 2
+          for (int u = 0; u < run; ++u) {
+            double l[16];
+            lds_row16(l, rb[s + u] + a * PLD + 16 * h);
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * xr[j];
+            double x = (v[0] + v[1]) + (v[2] + v[3]);
+            x += __shfl_xor(x, 32, 64);
+            if (lane < TS) ys[(fI + k - u) * TS + lane] -= x;
+          }
+          s += run;
+          k -= run;
+        }
+        if (k < 0) {                                 // row I done: move to row I - 1
+          if (I == 0) break;
+          wave_sync();
+          --I;
+          fI = sF[I];
+          nk = I - fI;
+          k = nk;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < d.np; q += blockDim.x) yg[q] = ys[q];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
@@ -189,6 +491,7 @@ k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tile
   const T* A = fac + d.fac_off;
   const T* Di = dinv + d.dinv_off;
   double* y = loc + d.loc_off;
+  if (d.np <= PCAP) return;                 // done by k_local_solve_pipe
   if (d.np <= YCAP) {
     local_solve_lds<T>(d, F, off, A, Di, y, ys, sF, sOff, part, sv);
     return;
@@ -248,12 +551,16 @@ template __global__ void k_local_solve<float>(const SubDesc*, const int32_t*, co
 
 void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                         const double* dinv, double* loc) {
-  k_local_solve<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
+  k_local_solve_pipe<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, fac, dinv, loc);
+  if (P.max_np > PCAP)
+    k_local_solve<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
 }
 
 void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
                             const float* dinv, double* loc) {
-  k_local_solve<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
+  k_local_solve_pipe<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, fac, dinv, loc);
+  if (P.max_np > PCAP)
+    k_local_solve<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
 }
 
 }  // namespace lsq2l

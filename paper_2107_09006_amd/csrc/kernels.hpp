@@ -29,6 +29,7 @@ struct DevPlan {              // subdomain layout (device copies of HostPlan)
   int64_t* tileOff = nullptr;
   int32_t* own_ptr = nullptr;
   int32_t* own_pos = nullptr;
+  int max_np = 0;             // largest padded local size
 };
 
 struct DevCoarse {            // coarse space and coarse operator
