@@ -220,7 +220,7 @@ __device__ inline void static_for(Fn&& fn) {
 // 16 consecutive LDS entries of a tile, as doubles
 template <typename T>
 __device__ inline void lds_row16(double (&x)[16], const T* p) {
-  using V = typename PipeCfg<T>::V;
+  using V = typename PipeCfg<T>::V;                  // 16-byte vector of T
   constexpr int NV = 16 * sizeof(T) / sizeof(V);
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
@@ -245,6 +245,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
   constexpr int PLD = TS + EV;                       // LDS leading dimension of a tile
   constexpr int TL = TS * PLD;
   constexpr int PW = (PB + 2) / 3;                   // tiles per producer wave and block
+  constexpr int CB = 4;                              // consumer batch of off-diagonal tiles
   __shared__ double ys[PCAP];
   __shared__ __align__(16) T ring[2][PB][TL];
   __shared__ int32_t sF[PCAP / TS], sS[PCAP / TS + 1];
@@ -377,14 +378,23 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
       while (s < send && I < nt) {
         const int run = min(nk - k, send - s);
         const double* yk = ys + (fI + k) * TS + 16 * h;
-#pragma unroll 2
-        for (int u = 0; u < run; ++u) {
-          double l[16];
-          lds_row16(l, rb[s + u] + a * PLD + 16 * h);
-          const double* y = yk + u * TS;
+        // batches of CB tiles: all LDS reads of a batch issue before its FMAs
+        auto fwd_batch = [&](int u0, auto nbc) {
+          constexpr int nb = decltype(nbc)::value;
+          double l[nb][16], y[nb][16];
 #pragma unroll
-          for (int j = 0; j < 16; ++j) acc[j & 3] += l[j] * y[j];
-        }
+          for (int i = 0; i < nb; ++i) {
+            lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
+            lds_row16(y[i], yk + (u0 + i) * TS);
+          }
+#pragma unroll
+          for (int i = 0; i < nb; ++i)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j & 3] += l[i][j] * y[i][j];
+        };
+        int u = 0;
+        for (; u + CB <= run; u += CB) fwd_batch(u, IC<CB>{});
+        for (; u < run; ++u) fwd_batch(u, IC<1>{});
         s += run;
         k += run;
         if (s < send) {                              // the diagonal inverse of row I
@@ -446,17 +456,27 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
           --k;
         } else {
           const int run = min(k + 1, send - s);
-#pragma unroll 2
-          for (int u = 0; u < run; ++u) {
-            double l[16];
-            lds_row16(l, rb[s + u] + a * PLD + 16 * h);
-            double v[4] = {0.0, 0.0, 0.0, 0.0};
+          auto bwd_batch = [&](int u0, auto nbc) {
+            constexpr int nb = decltype(nbc)::value;
+            double l[nb][16], x[nb];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * xr[j];
-            double x = (v[0] + v[1]) + (v[2] + v[3]);
-            x += __shfl_xor(x, 32, 64);
-            if (lane < TS) ys[(fI + k - u) * TS + lane] -= x;
-          }
+            for (int i = 0; i < nb; ++i) lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
+#pragma unroll
+            for (int i = 0; i < nb; ++i) {
+              double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int j = 0; j < 16; ++j) v[j & 3] += l[i][j] * xr[j];
+              x[i] = (v[0] + v[1]) + (v[2] + v[3]);
+            }
+#pragma unroll
+            for (int i = 0; i < nb; ++i) x[i] += __shfl_xor(x[i], 32, 64);
+#pragma unroll
+            for (int i = 0; i < nb; ++i)
+              if (lane < TS) ys[(fI + k - u0 - i) * TS + lane] -= x[i];
+          };
+          int u = 0;
+          for (; u + CB <= run; u += CB) bwd_batch(u, IC<CB>{});
+          for (; u < run; ++u) bwd_batch(u, IC<1>{});
           s += run;
           k -= run;
         }
