@@ -442,7 +442,27 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
       }
       TRY(c->dalloc(&c->einv, CP.einv_tot));
       TRY(c->dalloc(&c->Cc.e_part, CP.einv_tot / TS));
-      TRY(c->dalloc(&c->Cc.e_u, c->n0tot));
+      {
+        // chunks of the lower block triangle of E^{-1} for the coarse solve:
+        // up to ESYM_ROWTILES row tiles of one tile column each
+        std::vector<int32_t> ch, cptr(1, 0);
+        for (const SegDesc& sg : CP.segs)
+          for (int64_t cc = 0; cc < sg.etiles; ++cc) {
+            for (int64_t i0 = cc; i0 < sg.etiles; i0 += ESYM_ROWTILES) {
+              ch.push_back((int32_t)(sg.etile0 + cc));
+              ch.push_back((int32_t)i0);
+              ch.push_back((int32_t)std::min<int64_t>(ESYM_ROWTILES, sg.etiles - i0));
+              ch.push_back(0);
+            }
+            cptr.push_back((int32_t)(ch.size() / 4));
+          }
+        c->Cc.e_nchunks = (int)(ch.size() / 4);
+        int32_t* d_ch = nullptr;
+        TRY(c->upload(&d_ch, ch));
+        c->Cc.e_chunks = (int4*)d_ch;
+        TRY(c->upload(&c->Cc.e_chunk_ptr, cptr));
+        TRY(c->dalloc(&c->Cc.e_u, (int64_t)c->Cc.e_nchunks * TS));
+      }
       {
         // column blocks of E^{-1} onto one workgroup per compute unit, longest
         // first to the least loaded (block c of an instance with nt tile rows
@@ -796,15 +816,15 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
     // inverse once (as many elements as the stored factor), plus y in and out
     case 2: *bytes = 2.0 * eb * (double)c->H.total_fac + 16.0 * (double)c->H.total_loc; break;
     default: {
-      // lower block triangle of E^{-1} once, tile-row partials written and
-      // read back, c in and d out
       double tri = 0, parts = 0;
       for (const SegDesc& sg : c->segs_h) {
         const double nt = (double)sg.etiles;
         tri += (double)TT * nt * (nt + 1) / 2;
-        parts += (double)TS * nt * (nt - 1) / 2;
+        parts += (double)TS * nt * (nt + 1) / 2;
       }
-      *bytes = 8.0 * tri + 16.0 * parts + 16.0 * (double)c->n0tot;
+      // the triangle once; row and chunk column partials written and read
+      // back; c in and d out
+      *bytes = 8.0 * tri + 16.0 * parts + 16.0 * TS * (double)c->Cc.e_nchunks + 16.0 * (double)c->n0tot;
     }
   }
   launch_fill(c->st, c->M.n, 1.0, c->p);

@@ -628,57 +628,83 @@ k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ 
 }
 
 // d = E^{-1} c with the lower block triangle of the symmetric inverse, read
-// once.  Pass 1 (one workgroup per tile column J of an instance): the column
-// part u_J = sum_{I > J} T_IJ^T c_I plus the diagonal tile's product, and the
-// row parts P_J(I) = T_IJ c_J for every row block I > J.  Pass 2: d_I = u_I +
-// sum_{J < I} P_J(I), the partials added in increasing J.
+// once.  The triangle is cut into chunks of up to ESYM_ROWTILES row tiles of
+// one tile column J (equal work per workgroup).  Pass 1, one workgroup per
+// chunk, one row r per thread: the row part P_J(r) = sum_k T(r, k) c_J(k)
+// (the diagonal tile's full row sums included) and the chunk's column
+// partial sum_r T(r, k) c(r) over its rows below the diagonal tile.  Pass 2:
+// d_I = sum_{J <= I} P_J(I) + the column partials of the chunks of column I,
+// each sum in a fixed order.
 __global__ void __launch_bounds__(256)
-k_esym_pass1(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
-             const double* __restrict__ einv, const double* __restrict__ cvec,
-             double* __restrict__ part, double* __restrict__ uvec) {
-  __shared__ double scol[256][TS + 1];
-  __shared__ double cJ[TS], dsum[TS];
-  const int cglob = blockIdx.x;
-  const SegDesc sg = segs[seg_of_tile[cglob]];
-  const int J = cglob - (int)sg.etile0;
-  const int ld = (int)sg.etiles * TS;
+k_esym_pass1(const int4* __restrict__ chunks, const int32_t* __restrict__ seg_of_tile,
+             const SegDesc* __restrict__ segs, const double* __restrict__ einv,
+             const double* __restrict__ cvec, double* __restrict__ part,
+             double* __restrict__ ucol) {
+  __shared__ double cJ[TS];
+  __shared__ double wsum[4][TS];
+  const int4 ch = chunks[blockIdx.x];
+  const SegDesc sg = segs[seg_of_tile[ch.x]];
+  const int J = ch.x - (int)sg.etile0;
+  const int64_t ld = sg.etiles * TS;
   const double* Xc = einv + sg.einv_off + (int64_t)J * TS * ld;
   const double* cv = cvec + sg.c0;
   double* P = part + sg.einv_off / TS + (int64_t)J * ld;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   if (tid < TS) cJ[tid] = cv[J * TS + tid];
   __syncthreads();
-  double colacc[TS];
-  for (int k = 0; k < TS; ++k) colacc[k] = 0.0;
-  for (int r = J * TS + tid; r < ld; r += blockDim.x) {
-    double rowsum = 0.0;
-    const double cr = cv[r];
-    const double cb = (r >= (J + 1) * TS) ? cr : 0.0;   // the diagonal tile adds by rows only
+  const int64_t r = (int64_t)ch.y * TS + tid;
+  double col[TS];
+  if (tid < ch.z * TS) {
+    const double cr = r >= (J + 1) * TS ? cv[r] : 0.0;   // the diagonal tile adds by rows only
+    double e[TS];
+#pragma unroll
+    for (int k = 0; k < TS; ++k) e[k] = Xc[(int64_t)k * ld + r];
+    double rs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < TS; ++k) {
-      const double e = Xc[(int64_t)k * ld + r];
-      rowsum += e * cJ[k];
-      colacc[k] += e * cb;
+      rs[k & 3] += e[k] * cJ[k];
+      col[k] = e[k] * cr;
     }
-    if (r >= (J + 1) * TS) P[r] = rowsum;
-    else dsum[r - J * TS] = rowsum;      // diagonal tile: its row sums belong to d_J
-  }
+    P[r] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+  } else {
 #pragma unroll
-  for (int k = 0; k < TS; ++k) scol[tid][k] = colacc[k];
-  __syncthreads();
-  if (tid < TS) {
-    double s = dsum[tid];
-    for (int t = 0; t < (int)blockDim.x; ++t) s += scol[t][tid];
-    uvec[sg.c0 + J * TS + tid] = s;
+    for (int k = 0; k < TS; ++k) col[k] = 0.0;
   }
+  // column sums over the wave by recursive halving: after the step with
+  // offset o (32, 16, .., 2) a lane keeps the half of its entries selected
+  // by bit o of its lane id; a last exchange with offset 1 completes lane l's
+  // sum for column (l >> 1) with bit reversal of the kept halves.
+  int n = TS;
+#pragma unroll
+  for (int o = 32; o >= 2; o >>= 1) {
+    n >>= 1;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < TS / 2; ++i) {
+      if (i < n) {
+        const double send = up ? col[i] : col[i + n];
+        const double keep = up ? col[i + n] : col[i];
+        col[i] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+  }
+  double v = col[0] + __shfl_xor(col[0], 1, 64);
+  // lane l now holds column k(l): bits 5..1 of l, most significant first,
+  // give the halves kept at offsets 32 .. 2
+  const int k = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+                ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  if ((lane & 1) == 0) wsum[wave][k] = v;
+  __syncthreads();
+  if (tid < TS)
+    ucol[(int64_t)blockIdx.x * TS + tid] = (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
 }
 
 __global__ void __launch_bounds__(256)
 k_esym_pass2(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
-             const double* __restrict__ part, const double* __restrict__ uvec,
-             double* __restrict__ dvec) {
-  // one workgroup per tile row I: d_I = u_I + sum over J < I of the partial
-  // of tile column J at rows I (8 groups of 32 threads split J; fixed order)
+             const int32_t* __restrict__ chunk_ptr, const double* __restrict__ part,
+             const double* __restrict__ ucol, double* __restrict__ dvec) {
+  // one workgroup per tile row I: 8 groups of 32 threads split the row
+  // partials P_J(I), J <= I, and the column partials of the chunks of column I
   __shared__ double sp[8][TS];
   const int cglob = blockIdx.x;
   const SegDesc sg = segs[seg_of_tile[cglob]];
@@ -687,11 +713,12 @@ k_esym_pass2(const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict_
   const double* P = part + sg.einv_off / TS;
   const int r = threadIdx.x % TS, g = threadIdx.x / TS;
   double s = 0.0;
-  for (int J = g; J < I; J += 8) s += P[(int64_t)J * ld + I * TS + r];
+  for (int J = g; J <= I; J += 8) s += P[(int64_t)J * ld + I * TS + r];
+  for (int q = chunk_ptr[cglob] + g; q < chunk_ptr[cglob + 1]; q += 8) s += ucol[(int64_t)q * TS + r];
   sp[g][r] = s;
   __syncthreads();
   if (threadIdx.x < TS) {
-    double acc = uvec[sg.c0 + I * TS + r];
+    double acc = 0.0;
     for (int q = 0; q < 8; ++q) acc += sp[q][r];
     dvec[sg.c0 + I * TS + r] = acc;
   }
@@ -766,8 +793,9 @@ void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, co
                       const double* c, double* d) {
   if (n0 == 0) return;
   const int ntiles = (int)(n0 / TS);
-  k_esym_pass1<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, einv, c, Cc.e_part, Cc.e_u);
-  k_esym_pass2<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, Cc.e_part, Cc.e_u, d);
+  k_esym_pass1<<<Cc.e_nchunks, 256, 0, st>>>(Cc.e_chunks, Cc.e_seg_of_tile, Cc.segs, einv, c,
+                                             Cc.e_part, Cc.e_u);
+  k_esym_pass2<<<ntiles, 256, 0, st>>>(Cc.e_seg_of_tile, Cc.segs, Cc.e_chunk_ptr, Cc.e_part, Cc.e_u, d);
 }
 
 }  // namespace lsq2l

@@ -45,8 +45,15 @@ struct DevCoarse {            // coarse space and coarse operator
   int32_t* einv_bin_cols = nullptr;
   int4* e_items = nullptr;        // (pair, row block, column block) work items of E
   double* e_part = nullptr;       // row partials of the symmetric coarse solve
-  double* e_u = nullptr;          // column parts of the symmetric coarse solve
+  double* e_u = nullptr;          // column partials of the symmetric coarse solve, per chunk
+  int4* e_chunks = nullptr;       // (tile column, first row tile, row tiles) per chunk
+  int32_t* e_chunk_ptr = nullptr; // chunks of each tile column
+  int e_nchunks = 0;
 };
+
+// row tiles per chunk of the symmetric coarse solve (one row per thread of
+// a 256-thread workgroup)
+constexpr int ESYM_ROWTILES = 8;
 
 // --- device transpose of A's pattern ---------------------------------------
 size_t transpose_temp_bytes(int64_t nnz, int32_t n);
