@@ -494,7 +494,12 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
         }
         TRY(c->upload(&c->Cc.einv_bin_ptr, bptr));
         TRY(c->upload(&c->Cc.einv_bin_cols, bcols));
-        launch_einv(st, nbins, c->Cc, c->efac, c->edinv, c->einv);
+        double *efacT = nullptr, *edinvT = nullptr;
+        TRY(c->dalloc(&efacT, CP.efac_tiles * TT));
+        TRY(c->dalloc(&edinvT, c->etiles * TT));
+        launch_tile_transpose(st, CP.efac_tiles, c->efac, efacT);
+        launch_tile_transpose(st, c->etiles, c->edinv, edinvT);
+        launch_einv(st, nbins, c->Cc, c->efac, c->edinv, efacT, edinvT, c->einv);
       }
       TRY(c->dalloc(&c->cvec, c->n0tot));
       TRY(c->dalloc(&c->dvec, c->n0tot));

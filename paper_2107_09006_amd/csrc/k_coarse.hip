@@ -392,8 +392,12 @@ __device__ inline void tile_frag_mma(double4_t acc[4], const TileFrag& f) {
 // wave partials of a step are added in a fixed order.  Each workgroup works
 // through a list of column blocks chosen so that the lists have equal work
 // (the work of block c is proportional to the number of tile rows below c).
+// The backward sweep multiplies by transposed tiles of L; it reads them from
+// a tile-by-tile transposed copy (efacT, edinvT), so that every operand
+// fragment load is a column read.
 constexpr int EINV_WAVES = 4;
 constexpr int EWIN_SLOTS = 6;
+constexpr int ELIST = 256;                  // backward list entries staged in LDS
 
 struct AFrag { double a[2][8]; };
 
@@ -433,9 +437,13 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
        const int32_t* __restrict__ seg_of_tile, const SegDesc* __restrict__ segs,
        const int32_t* __restrict__ erows, const int64_t* __restrict__ eptr,
        const int32_t* __restrict__ bin_ptr, const int32_t* __restrict__ bin_cols,
-       const double* __restrict__ efac, const double* __restrict__ edinv, double* __restrict__ einv) {
+       const double* __restrict__ efac, const double* __restrict__ edinv,
+       const double* __restrict__ efacT, const double* __restrict__ edinvT,
+       double* __restrict__ einv) {
   __shared__ double sY[TS * LDT], sN[TS * LDT];
   __shared__ double spart[EINV_WAVES][TT];
+  __shared__ int32_t sEI[ELIST];            // backward step: rows I of the list (local index)
+  __shared__ int64_t sEO[ELIST];            // and the tile index of L(I, K)
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid / 64, lane = tid % 64;
   const int bi = w / 2, bj = w % 2;          // quadrant of the diagonal products
@@ -521,9 +529,28 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
       }
     }
 
-    // ---- backward
+    // ---- backward.  The list of rows I > K with F(I) <= K and the tile
+    // index of L(I, K) for each is staged in LDS by the whole workgroup one
+    // step ahead; a window slot keeps F and the tile offset of its row.
+    auto fill_list = [&](int Kg) {
+      const int64_t u0 = eptr[Kg];
+      const int n = (int)min<int64_t>(eptr[Kg + 1] - u0, ELIST);
+      for (int j = tid; j < n; j += nthr) {
+        const int Ig = erows[u0 + j];
+        sEI[j] = Ig - t0;
+        sEO[j] = tile_pos(eF, eOff, Ig, Kg);
+      }
+    };
+    int wF[EWIN_SLOTS];
+    int64_t wO[EWIN_SLOTS];
 #pragma unroll
-    for (int sl = 0; sl < EWIN_SLOTS; ++sl) wk[sl] = -1;
+    for (int sl = 0; sl < EWIN_SLOTS; ++sl) {
+      wk[sl] = -1;
+      wF[sl] = 0;
+      wO[sl] = 0;
+    }
+    fill_list(t0 + nt - 1);
+    __syncthreads();
     for (int K = nt - 1; K >= c; --K) {
       const int Kg = t0 + K;
       double4_t acc[4];
@@ -534,21 +561,30 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
 #pragma unroll
       for (int sl = EWIN_SLOTS - 1; sl >= 0; --sl)
         if (wk[sl] >= 0) ifar = wk[sl];
-      for (int64_t u = eptr[Kg]; u < eptr[Kg + 1]; ++u) {
-        const int I = erows[u] - t0;
+      const int64_t u0 = eptr[Kg];
+      const int nlist = (int)(eptr[Kg + 1] - u0);
+      for (int j = 0; j < nlist; ++j) {
+        int I;
+        int64_t off;
+        if (j < ELIST) {
+          I = sEI[j];
+          off = sEO[j];
+        } else {
+          I = erows[u0 + j] - t0;
+          off = tile_pos(eF, eOff, t0 + I, Kg);
+        }
         if (I % EINV_WAVES != w || I <= ifar) continue;
         AFrag f;
         double b[2][8];
-        afrag_load<true>(f, efac + tile_pos(eF, eOff, t0 + I, Kg) * TT, TS, lane);
+        afrag_load<false>(f, efacT + off * TT, TS, lane);
         bfrag_load(b, Xc + I * TS, ld, lane);
         frag_mma(acc, f, b);
       }
 #pragma unroll
       for (int sl = 0; sl < EWIN_SLOTS; ++sl) {
-        const int I = wk[sl];
-        if (I >= 0 && eF[t0 + I] <= Kg) {
+        if (wk[sl] >= 0 && wF[sl] <= Kg) {
           AFrag f;
-          afrag_load<true>(f, efac + tile_pos(eF, eOff, t0 + I, Kg) * TT, TS, lane);
+          afrag_load<false>(f, efacT + (wO[sl] + (Kg - wF[sl])) * TT, TS, lane);
           frag_mma(acc, f, win[sl]);
         }
       }
@@ -564,24 +600,43 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
       __syncthreads();
       {
         double4_t x = {0.0, 0.0, 0.0, 0.0};
-        quad_mma<true>(x, edinv + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
+        quad_mma<false>(x, edinvT + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
         quad_store(x, Xc + K * TS, ld, bi, bj, lane);
         quad_store(x, sN, LDT, bi, bj, lane);
       }
+      if (K > c) fill_list(Kg - 1);         // this step's list is no longer read
       __syncthreads();
       if (K % EINV_WAVES == w) {
 #pragma unroll
         for (int sl = 0; sl + 1 < EWIN_SLOTS; ++sl) {
           wk[sl] = wk[sl + 1];
+          wF[sl] = wF[sl + 1];
+          wO[sl] = wO[sl + 1];
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int q = 0; q < 8; ++q) win[sl][h][q] = win[sl + 1][h][q];
         }
         wk[EWIN_SLOTS - 1] = K;
+        wF[EWIN_SLOTS - 1] = eF[Kg];
+        wO[EWIN_SLOTS - 1] = eOff[Kg];
         bfrag_load(win[EWIN_SLOTS - 1], sN, LDT, lane);
       }
     }
+    __syncthreads();
+  }
+}
+
+// out = in with every 32 x 32 tile transposed
+__global__ void __launch_bounds__(256)
+k_tile_transpose(int64_t ntiles, const double* __restrict__ in, double* __restrict__ out) {
+  __shared__ double sT[TS * LDT];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const double* a = in + t * TT;
+    double* b = out + t * TT;
+    for (int e = threadIdx.x; e < TT; e += blockDim.x) sT[(e / TS) * LDT + e % TS] = a[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TT; e += blockDim.x) b[e] = sT[(e % TS) * LDT + e / TS];
     __syncthreads();
   }
 }
@@ -775,12 +830,17 @@ void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32
   k_echol_update<<<(unsigned)((npairs + 3) / 4), 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac);
 }
 
+void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out) {
+  if (ntiles <= 0) return;
+  k_tile_transpose<<<(unsigned)std::min<int64_t>(ntiles, 8192), 256, 0, st>>>(ntiles, in, out);
+}
+
 void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
-                 const double* edinv, double* einv) {
+                 const double* edinv, const double* efacT, const double* edinvT, double* einv) {
   if (nbins == 0) return;
   k_einv<<<nbins, EINV_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, Cc.e_seg_of_tile, Cc.segs, Cc.erows,
                                             Cc.eptr, Cc.einv_bin_ptr, Cc.einv_bin_cols, efac, edinv,
-                                            einv);
+                                            efacT, edinvT, einv);
 }
 
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,

@@ -121,8 +121,9 @@ void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t
                        double* efac, double* edinv, int32_t* status);
 void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                          double* efac);
+void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out);
 void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
-                 const double* edinv, double* einv);
+                 const double* edinv, const double* efacT, const double* edinvT, double* einv);
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
                             const double* r, double* c);
 void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, double* out);
