@@ -81,22 +81,47 @@ struct LocalOut {
 // Index sets and tile envelope of subdomain i.  Only lists of the size of the
 // subdomain's columns and rows are built (sorted and deduplicated), so the
 // work is proportional to the entries of A it touches.
+// A set of indices as a bitmap: mark() records an index and the range seen,
+// drain() appends the marked indices in ascending order and clears them, so
+// the bitmap is all zero between uses.
+struct BitSet {
+  std::vector<uint64_t> w;
+  int64_t lo = INT64_MAX, hi = -1;
+  explicit BitSet(int64_t n) : w((size_t)(n / 64 + 1), 0) {}
+  void mark(int32_t x) {
+    w[(size_t)x >> 6] |= 1ull << (x & 63);
+    lo = std::min<int64_t>(lo, x);
+    hi = std::max<int64_t>(hi, x);
+  }
+  void drain(std::vector<int32_t>& out) {
+    for (int64_t k = lo >> 6; hi >= 0 && k <= (hi >> 6); ++k) {
+      uint64_t x = w[(size_t)k];
+      if (!x) continue;
+      w[(size_t)k] = 0;
+      while (x) {
+        out.push_back((int32_t)(k * 64 + __builtin_ctzll(x)));
+        x &= x - 1;
+      }
+    }
+    lo = INT64_MAX;
+    hi = -1;
+  }
+};
+
 void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* trowptr,
               const int32_t* tcol, const int32_t* part, const int32_t* locown, const int32_t* I,
-              int32_t nI, LocalOut& out) {
-  // Xi_i: rows with a stored entry in a column of Omega_Ii
+              int32_t nI, BitSet& rowset, BitSet& colset, LocalOut& out) {
+  // Xi_i: rows with a stored entry in a column of Omega_Ii, ascending
   out.xi.clear();
   for (int32_t a = 0; a < nI; ++a)
-    for (int32_t k = trowptr[I[a]]; k < trowptr[I[a] + 1]; ++k) out.xi.push_back(tcol[k]);
-  std::sort(out.xi.begin(), out.xi.end());
-  out.xi.erase(std::unique(out.xi.begin(), out.xi.end()), out.xi.end());
-  // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii
+    for (int32_t k = trowptr[I[a]]; k < trowptr[I[a] + 1]; ++k) rowset.mark(tcol[k]);
+  rowset.drain(out.xi);
+  // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii, ascending
   out.gamma.clear();
   for (int32_t r : out.xi)
     for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
-      if (part[colind[e]] != i) out.gamma.push_back(colind[e]);
-  std::sort(out.gamma.begin(), out.gamma.end());
-  out.gamma.erase(std::unique(out.gamma.begin(), out.gamma.end()), out.gamma.end());
+      if (part[colind[e]] != i) colset.mark(colind[e]);
+  colset.drain(out.gamma);
   const int32_t nG = (int32_t)out.gamma.size();
   const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
   // local position of a column of Omega_i (-1 outside)
@@ -173,15 +198,18 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nth; ++t)
       pool.emplace_back([&, t]() {
+        BitSet rowset(m), colset(n);
         for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
           plan_one(i, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
-                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), outs[i]);
+                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), rowset, colset,
+                   outs[i]);
       });
     for (auto& th : pool) th.join();
   }
   // offsets
   P.subs.assign((size_t)nparts, SubDesc{});
   int64_t omega_off = 0, xi_off = 0, loc_off = 0, tile_base = 0, fac_tiles = 0, g_off = 0;
+  int64_t dinv_tiles = 0;
   for (int32_t i = 0; i < nparts; ++i) {
     SubDesc& d = P.subs[i];
     d.nI = (int32_t)(pptr[i + 1] - pptr[i]);
@@ -202,7 +230,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     int64_t stored = 0;
     for (int32_t t = 0; t < d.ntiles; ++t) stored += t - outs[i].F[t] + 1;
     fac_tiles += stored;
-    d.dinv_off = 0;  // assigned below (separate array)
+    d.dinv_off = dinv_tiles * TT; dinv_tiles += d.ntiles;   // separate array
     d.g_off = g_off; g_off += (int64_t)d.nGp * d.nGp;
   }
   if (loc_off >= (int64_t)1 << 31) { err = "local index space exceeds 2^31"; return false; }
@@ -214,21 +242,27 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
   P.xi.resize((size_t)xi_off);
   P.tileF.resize((size_t)tile_base);
   P.tileOff.resize((size_t)tile_base);
-  int64_t dinv = 0;
-  for (int32_t i = 0; i < nparts; ++i) {
-    SubDesc& d = P.subs[i];
-    std::memcpy(&P.omega[d.omega_off], pcols.data() + pptr[i], sizeof(int32_t) * d.nI);
-    std::memcpy(&P.omega[d.omega_off + d.nI], outs[i].gamma.data(), sizeof(int32_t) * d.nG);
-    std::memcpy(&P.xi[d.xi_off], outs[i].xi.data(), sizeof(int32_t) * d.nXi);
-    int64_t off = 0;   // relative to the subdomain's first tile (fac_off / TT)
-    for (int32_t t = 0; t < d.ntiles; ++t) {
-      P.tileF[d.tile_base + t] = outs[i].F[t];
-      P.tileOff[d.tile_base + t] = off;
-      off += t - outs[i].F[t] + 1;
-    }
-    d.dinv_off = dinv; dinv += (int64_t)d.ntiles * TT;
+  // per-subdomain copies into the flat arrays (disjoint ranges), in parallel
+  {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t)
+      pool.emplace_back([&, t]() {
+        for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth) {
+          const SubDesc& d = P.subs[i];
+          std::memcpy(&P.omega[d.omega_off], pcols.data() + pptr[i], sizeof(int32_t) * d.nI);
+          std::memcpy(&P.omega[d.omega_off + d.nI], outs[i].gamma.data(), sizeof(int32_t) * d.nG);
+          std::memcpy(&P.xi[d.xi_off], outs[i].xi.data(), sizeof(int32_t) * d.nXi);
+          int64_t off = 0;   // relative to the subdomain's first tile (fac_off / TT)
+          for (int32_t q = 0; q < d.ntiles; ++q) {
+            P.tileF[d.tile_base + q] = outs[i].F[q];
+            P.tileOff[d.tile_base + q] = off;
+            off += q - outs[i].F[q] + 1;
+          }
+        }
+      });
+    for (auto& th : pool) th.join();
   }
-  P.total_dinv = dinv;
+  P.total_dinv = dinv_tiles * TT;
   return true;
 }
 
