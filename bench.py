@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 1 << 30          # plain device copy used to calibrate HBM counters
 
-# HBM traffic of one launch of the dominant kernel (k_local_solve<float>) on
+# HBM traffic of one launch of the dominant kernel (k_local_solve_pipe<float>) on
 # this workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this
 # script, each scaled by the same counter's reading for the calibration copy
 # (profiles/local_solve_grid1000.md).  It describes the kernel source whose
@@ -187,7 +187,7 @@ def main():
     dom = kern.get("local_solve_mixed")
     roofline = None
     if dom:
-        roofline = {"kernel": "k_local_solve<float>", "bound": "hbm",
+        roofline = {"kernel": "k_local_solve_pipe<float>", "bound": "hbm",
                     "achieved": round(dom["GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(dom["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "bytes_per_launch": dom["bytes"], "launch_ms": dom["ms"]}

@@ -184,8 +184,14 @@ lsq2l_status lsq2l_get_coarse_basis(lsq2l_handle h, int32_t i, double* X);
 lsq2l_status lsq2l_time_kernel(lsq2l_handle h, int32_t kernel, int32_t reps, double* avg_ms,
                                double* bytes);
 
-/* Release every resource of the handle (NULL is ignored). */
+/* Release every resource of the handle (NULL is ignored).  Its device
+ * memory goes to a process-wide cache (at most 32 GiB) that later handles on
+ * the same device draw from. */
 void lsq2l_destroy(lsq2l_handle h);
+
+/* Free the device memory held in that cache.  Handles that are still alive
+ * keep theirs.  Call it with no setup running in another thread. */
+void lsq2l_release_cache(void);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* lsq2l_last_error(void);

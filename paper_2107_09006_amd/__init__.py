@@ -5,7 +5,7 @@ The compute path is the HIP library ``liblsq2l.so`` (C ABI in
 ``autograd`` wraps solve/backward as a ``torch.autograd.Function``.
 """
 from .binding import (  # noqa: F401
-    Solver, solver_from_problem, load_library, default_options, Lsq2lError,
+    Solver, solver_from_problem, load_library, default_options, release_cache, Lsq2lError,
     OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN,
     FP64, MIXED, ADDITIVE, ONE_LEVEL, EXPORTS,
 )

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EH
 EXPORTS = ["lsq2l_default_options", "lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve",
            "lsq2l_backward", "lsq2l_spmv", "lsq2l_apply_preconditioner", "lsq2l_get_info",
            "lsq2l_get_subdomain", "lsq2l_get_coarse_basis", "lsq2l_time_kernel",
-           "lsq2l_destroy", "lsq2l_last_error"]
+           "lsq2l_destroy", "lsq2l_release_cache", "lsq2l_last_error"]
 
 
 class Options(C.Structure):
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     lib.lsq2l_time_kernel.argtypes = [vp, i32, i32, C.POINTER(dbl), C.POINTER(dbl)]
     lib.lsq2l_destroy.argtypes = [vp]
     lib.lsq2l_destroy.restype = None
+    lib.lsq2l_release_cache.argtypes = []
+    lib.lsq2l_release_cache.restype = None
     lib.lsq2l_last_error.restype = C.c_char_p
     for name in ["lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve", "lsq2l_backward",
                  "lsq2l_spmv", "lsq2l_apply_preconditioner", "lsq2l_get_info",
@@ -293,6 +295,12 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def release_cache() -> None:
+    """Free the device memory that destroyed handles left in the library's
+    process-wide cache (handles still alive keep theirs)."""
+    load_library().lsq2l_release_cache()
 
 
 def solver_from_problem(prob, device="cuda:0", **options) -> Solver:

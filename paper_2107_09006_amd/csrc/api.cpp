@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -30,6 +31,68 @@ int pick_group(double avg) {
   int g = 1;
   while (g < 64 && g < avg) g *= 2;
   return g;
+}
+
+// Device blocks of destroyed handles, kept for later handles on the same
+// device: a setup allocates gigabytes in blocks of hundreds of megabytes,
+// and allocating or releasing a block of that size costs a sizeable fraction
+// of a millisecond.  A request takes the smallest cached block of its device
+// that is at least as large and at most a quarter larger.  At most
+// CACHE_LIMIT bytes stay cached; lsq2l_release_cache() frees them all, and an
+// allocation that fails frees them and tries once more.
+struct BlockCache {
+  struct Block { void* p; size_t bytes; int dev; };
+  static constexpr size_t CACHE_LIMIT = (size_t)32 << 30;
+  std::mutex mu;
+  std::vector<Block> blocks;
+  size_t held = 0;
+  void* take(size_t bytes, int dev, size_t* got) {
+    std::lock_guard<std::mutex> g(mu);
+    int best = -1;
+    for (int i = 0; i < (int)blocks.size(); ++i) {
+      const Block& b = blocks[i];
+      if (b.dev != dev || b.bytes < bytes || b.bytes > bytes + bytes / 4) continue;
+      if (best < 0 || b.bytes < blocks[best].bytes) best = i;
+    }
+    if (best < 0) return nullptr;
+    void* p = blocks[best].p;
+    *got = blocks[best].bytes;
+    held -= *got;
+    blocks.erase(blocks.begin() + best);
+    return p;
+  }
+  // the caller has synchronized the work that used the block
+  void give(void* p, size_t bytes, int dev) {
+    std::lock_guard<std::mutex> g(mu);
+    if (held + bytes > CACHE_LIMIT) {
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(dev);
+      (void)hipFree(p);
+      (void)hipSetDevice(cur);
+      return;
+    }
+    blocks.push_back({p, bytes, dev});
+    held += bytes;
+  }
+  void release() {
+    std::lock_guard<std::mutex> g(mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (const Block& b : blocks) {
+      (void)hipSetDevice(b.dev);
+      (void)hipFree(b.p);
+    }
+    (void)hipSetDevice(cur);
+    blocks.clear();
+    held = 0;
+  }
+};
+
+// never destroyed: device memory goes back with the process
+BlockCache& block_cache() {
+  static BlockCache* bc = new BlockCache();
+  return *bc;
 }
 
 }  // namespace
@@ -72,7 +135,8 @@ struct lsq2l_ctx {
   std::vector<int32_t> p_h;
   int max_p = 0;
   lsq2l_setup_info info{};
-  std::vector<void*> dev_allocs;
+  struct DevBlock { void* p; size_t bytes; int dev; };
+  std::vector<DevBlock> dev_allocs;
   std::vector<void*> host_allocs;
 
   // Device memory of the handle: requests up to ARENA_SMALL bytes are carved
@@ -82,12 +146,23 @@ struct lsq2l_ctx {
   char* arena_cur = nullptr;
   size_t arena_used = 0;
   lsq2l_status raw_alloc(void** v, size_t bytes) {
+    int dev = 0;
+    LSQ2L_HIP_TRY(hipGetDevice(&dev));
+    size_t got = 0;
+    if ((*v = block_cache().take(bytes, dev, &got)) != nullptr) {
+      dev_allocs.push_back({*v, got, dev});
+      return LSQ2L_OK;
+    }
     hipError_t e = hipMalloc(v, bytes);
+    if (e != hipSuccess) {
+      block_cache().release();
+      e = hipMalloc(v, bytes);
+    }
     if (e != hipSuccess) {
       set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
       return LSQ2L_ENOMEM;
     }
-    dev_allocs.push_back(*v);
+    dev_allocs.push_back({*v, bytes, dev});
     return LSQ2L_OK;
   }
   template <typename T>
@@ -131,7 +206,7 @@ struct lsq2l_ctx {
   ~lsq2l_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    for (void* v : dev_allocs) (void)hipFree(v);
+    for (const DevBlock& b : dev_allocs) block_cache().give(b.p, b.bytes, b.dev);
     for (void* v : host_allocs) (void)hipHostFree(v);
   }
 };
@@ -147,12 +222,53 @@ namespace {
 lsq2l_status validate_csr(int32_t m, int32_t n, const std::vector<int32_t>& rp,
                           const std::vector<int32_t>& ci) {
   if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
-  for (int32_t r = 0; r < m; ++r) {
-    if (rp[r + 1] < rp[r]) { set_error("rowptr is not monotone at row " + std::to_string(r)); return LSQ2L_EINVAL; }
-    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
-      if (ci[e] < 0 || ci[e] >= n) { set_error("column index out of range in row " + std::to_string(r)); return LSQ2L_EINVAL; }
-      if (e > rp[r] && ci[e] <= ci[e - 1]) { set_error("columns not strictly increasing in row " + std::to_string(r)); return LSQ2L_EINVAL; }
+  // rows checked in parallel blocks, first every row's extent (so that the
+  // column pass reads inside ci), then the columns; the first failing row of
+  // the first failing pass is reported
+  const unsigned nth = m < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nnz = (int64_t)ci.size();
+  std::vector<int32_t> bad_row(nth, INT32_MAX);
+  std::vector<int> bad_kind(nth, 0);
+  auto run = [&](auto&& fn) {
+    if (nth == 1) {
+      fn(0u);
+    } else {
+      std::vector<std::thread> pool;
+      for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
+      for (auto& th : pool) th.join();
     }
+  };
+  auto rows_of = [&](unsigned t, int32_t& r0, int32_t& r1) {
+    r0 = (int32_t)((int64_t)m * t / nth);
+    r1 = (int32_t)((int64_t)m * (t + 1) / nth);
+  };
+  run([&](unsigned t) {
+    int32_t r0, r1;
+    rows_of(t, r0, r1);
+    for (int32_t r = r0; r < r1; ++r)
+      if (rp[r + 1] < rp[r] || rp[r + 1] > nnz) { bad_row[t] = r; bad_kind[t] = 1; return; }
+  });
+  bool extents_ok = true;
+  for (unsigned t = 0; t < nth; ++t) extents_ok = extents_ok && !bad_kind[t];
+  if (extents_ok)
+    run([&](unsigned t) {
+      int32_t r0, r1;
+      rows_of(t, r0, r1);
+      for (int32_t r = r0; r < r1; ++r)
+        for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+          int kind = 0;
+          if (ci[e] < 0 || ci[e] >= n) kind = 2;
+          else if (e > rp[r] && ci[e] <= ci[e - 1]) kind = 3;
+          if (kind) { bad_row[t] = r; bad_kind[t] = kind; return; }
+        }
+    });
+  for (unsigned t = 0; t < nth; ++t) {
+    if (!bad_kind[t]) continue;
+    const std::string r = std::to_string(bad_row[t]);
+    if (bad_kind[t] == 1) set_error("rowptr is not monotone (or exceeds nnz) at row " + r);
+    else if (bad_kind[t] == 2) set_error("column index out of range in row " + r);
+    else set_error("columns not strictly increasing in row " + r);
+    return LSQ2L_EINVAL;
   }
   return LSQ2L_OK;
 }
@@ -864,5 +980,7 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
 }
 
 void lsq2l_destroy(lsq2l_handle c) { delete c; }
+
+void lsq2l_release_cache(void) { block_cache().release(); }
 
 }  // extern "C"

@@ -431,6 +431,45 @@ def test_not_converged_returns_last_iterate(L):
     s.close()
 
 
+def test_csr_validation_rejects_corrupt_input(L):
+    """Bad CSR input ends in EINVAL with the failing row named, for a small
+    matrix (serial check) and one with more than 65536 rows (parallel
+    check).  The first case has a row start beyond nnz in the middle of
+    rowptr, which must not be followed into colind."""
+    big = W.grid_gradient(200, 4, seed=3, tau=0.1, tol=1e-8, name="g200")
+    assert big.m > 65536
+    for p in (problem("config0"), big):
+        rp = p.indptr.copy()
+        rp[len(rp) // 2] = p.indices.size + 100
+        ci_range = p.indices.copy()
+        ci_range[-1] = p.n
+        ci_order = p.indices.copy()
+        r = int(np.flatnonzero(np.diff(p.indptr) >= 2)[-1])
+        a = int(p.indptr[r])
+        ci_order[a], ci_order[a + 1] = ci_order[a + 1], ci_order[a]
+        for rr, cc, msg in [(rp, p.indices, "monotone"), (p.indptr, ci_range, "out of range"),
+                            (p.indptr, ci_order, "increasing")]:
+            with pytest.raises(L.Lsq2lError) as e:
+                L.Solver(rr, cc, p.data, p.part, p.nparts, p.m, p.n, 0.1)
+            assert e.value.status == L.EINVAL and msg in str(e.value)
+
+
+def test_device_memory_cache_reuse_is_bitwise_neutral(L):
+    """Handles built on device memory taken from the cache left by destroyed
+    handles give the same bits as handles on fresh allocations."""
+    p = problem("grid")
+    L.release_cache()
+    xs = []
+    for k in range(3):
+        s = solver(L, p)
+        x, info, _ = s.solve(_t(p.b))
+        xs.append(_np(x).copy())
+        s.close()
+        if k == 1:
+            L.release_cache()
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+
+
 def test_error_paths(L):
     p = problem("config0")
     bad = p.part.copy(); bad[0] = p.nparts
