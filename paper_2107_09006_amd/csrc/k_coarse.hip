@@ -666,9 +666,14 @@ k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ 
         const int k = kb + u * nwaves + wave;
         if (k >= d.p) break;
         const double* xk = X + d.x_off + (int64_t)k * d.nIp + a0;
-        double s = 0.0;
-        for (int a = lane; a < len; a += 64) s += xk[a] * sr[a];
-        acc[u] += s;
+        // eight independent loads in flight per lane
+        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int a = lane;
+        for (; a + 7 * 64 < len; a += 8 * 64)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) s8[i] += xk[a + 64 * i] * sr[a + 64 * i];
+        for (int i = 0; a < len; a += 64, ++i) s8[i] += xk[a] * sr[a];
+        acc[u] += ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
       }
     }
     for (int u = 0; u < 8; ++u) {

@@ -258,9 +258,14 @@ __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
     const int a = locown[j];
     const double* xr = X + d.x_off + a;
     const double* dc = dcoarse + d.cg_off;
-    double c = 0.0;
-    for (int k = 0; k < d.p; ++k) c += xr[(int64_t)k * d.nIp] * dc[k];
-    s += c;
+    // eight independent loads in flight per thread
+    double c8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 8 <= d.p; k += 8)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c8[i] += xr[(int64_t)(k + i) * d.nIp] * dc[k + i];
+    for (int i = 0; k < d.p; ++k, ++i) c8[i] += xr[(int64_t)k * d.nIp] * dc[k];
+    s += ((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]));
   }
   z[j] = s;
 }
