@@ -189,8 +189,10 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle h, int32_t kernel, int32_t reps, dou
  * the same device draw from. */
 void lsq2l_destroy(lsq2l_handle h);
 
-/* Free the device memory held in that cache.  Handles that are still alive
- * keep theirs.  Call it with no setup running in another thread. */
+/* Free the device memory held in that cache, and the pinned host buffers
+ * (at most 4 GiB) that setups keep for reading A's pattern back.  Handles
+ * that are still alive keep theirs.  Call it with no setup running in
+ * another thread. */
 void lsq2l_release_cache(void);
 
 /* Message of the last error on the calling thread ("" if none). */

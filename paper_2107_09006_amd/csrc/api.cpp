@@ -95,6 +95,79 @@ BlockCache& block_cache() {
   return *bc;
 }
 
+// Pinned host buffers for the copies setup reads back from the device (A's
+// pattern, A^T's pattern), kept for later setups: a pageable copy runs at a
+// sixth of the pinned rate, and pinning fresh memory costs more than the
+// copy.  At most PINNED_LIMIT bytes stay cached.
+struct PinnedPool {
+  struct Buf { void* p; size_t bytes; };
+  static constexpr size_t PINNED_LIMIT = (size_t)4 << 30;
+  std::mutex mu;
+  std::vector<Buf> bufs;
+  size_t held = 0;
+  void* take(size_t bytes, size_t* got) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      int best = -1;
+      for (int i = 0; i < (int)bufs.size(); ++i)
+        if (bufs[i].bytes >= bytes && bufs[i].bytes <= 2 * bytes &&
+            (best < 0 || bufs[i].bytes < bufs[best].bytes))
+          best = i;
+      if (best >= 0) {
+        void* p = bufs[best].p;
+        *got = bufs[best].bytes;
+        held -= *got;
+        bufs.erase(bufs.begin() + best);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    *got = bytes;
+    return p;
+  }
+  void give(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    if (held + bytes > PINNED_LIMIT) {
+      (void)hipHostFree(p);
+      return;
+    }
+    bufs.push_back({p, bytes});
+    held += bytes;
+  }
+  void release() {
+    std::lock_guard<std::mutex> g(mu);
+    for (const Buf& b : bufs) (void)hipHostFree(b.p);
+    bufs.clear();
+    held = 0;
+  }
+};
+
+PinnedPool& pinned_pool() {
+  static PinnedPool* pp = new PinnedPool();
+  return *pp;
+}
+
+// A pinned host array of count elements from the pool, returned to it when
+// the owner goes out of scope (the work that used it has been synchronized).
+template <typename T>
+struct PinnedArray {
+  T* p = nullptr;
+  size_t bytes = 0;
+  lsq2l_status alloc(int64_t count) {
+    const size_t want = (((size_t)std::max<int64_t>(count, 1) * sizeof(T)) + ((1 << 20) - 1)) >> 20 << 20;
+    p = (T*)pinned_pool().take(want, &bytes);
+    if (!p) {
+      set_error("pinned host allocation of " + std::to_string(want) + " bytes failed");
+      return LSQ2L_ENOMEM;
+    }
+    return LSQ2L_OK;
+  }
+  ~PinnedArray() {
+    if (p) pinned_pool().give(p, bytes);
+  }
+};
+
 }  // namespace
 }  // namespace lsq2l
 
@@ -219,14 +292,12 @@ struct lsq2l_ctx {
 
 namespace {
 
-lsq2l_status validate_csr(int32_t m, int32_t n, const std::vector<int32_t>& rp,
-                          const std::vector<int32_t>& ci) {
+lsq2l_status validate_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, int64_t nnz) {
   if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
   // rows checked in parallel blocks, first every row's extent (so that the
   // column pass reads inside ci), then the columns; the first failing row of
   // the first failing pass is reported
   const unsigned nth = m < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const int64_t nnz = (int64_t)ci.size();
   std::vector<int32_t> bad_row(nth, INT32_MAX);
   std::vector<int> bad_kind(nth, 0);
   auto run = [&](auto&& fn) {
@@ -409,7 +480,7 @@ struct MapsJob {
 };
 
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
-lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const std::vector<int32_t>& part, int32_t nparts,
                         const std::vector<int32_t>& seg_of_part) {
   const hipStream_t st = c->st;
@@ -419,7 +490,9 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   auto t0 = clk::now();
   // --- transpose and index sets
   // A^T on the device; the planner reads its pattern back
-  std::vector<int32_t> trp((size_t)n + 1), tcol((size_t)nnz);
+  PinnedArray<int32_t> trp, tcol;
+  TRY(trp.alloc((int64_t)n + 1));
+  TRY(tcol.alloc(nnz));
   {
     int32_t *keys = nullptr, *vals = nullptr, *rows = nullptr;
     char* temp = nullptr;
@@ -433,8 +506,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
     TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
     LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.trowptr, c->M.trow,
                                    c->M.tperm, keys, vals, rows, temp, tb));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(trp.data(), c->M.trowptr, trp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.data(), c->M.trow, tcol.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(trp.p, c->M.trowptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.p, c->M.trow, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   }
   TRY(c->dalloc(&c->M.tvals, nnz));
@@ -442,14 +515,14 @@ lsq2l_status setup_core(lsq2l_ctx* c, const std::vector<int32_t>& rp, const std:
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
   std::string err;
-  if (!plan_build(m, n, rp.data(), ci.data(), trp, tcol, part.data(), nparts, seg_of_part, c->H, err)) {
+  if (!plan_build(m, n, rp, ci, trp.p, tcol.p, part.data(), nparts, seg_of_part, c->H, err)) {
     set_error(err);
     return LSQ2L_EINVAL;
   }
   HostPlan& H = c->H;
   c->nsub = nparts;
   MapsJob maps;
-  maps.start(m, n, rp.data(), ci.data(), part.data(), &H);
+  maps.start(m, n, rp, ci, part.data(), &H);
   TRY(c->upload(&c->P.subs, H.subs));
   TRY(c->upload(&c->P.omega, H.omega));
   TRY(c->upload(&c->P.xi, H.xi));
@@ -758,23 +831,26 @@ lsq2l_status lsq2l_setup(int32_t m, int32_t n, int32_t nnz, const int32_t* rowpt
   c->seg_row_h = {0, m};
   c->seg_col_h = {0, n};
   auto fail = [&](lsq2l_status s) { delete c; return s; };
-  std::vector<int32_t> rp(m + 1), ci(nnz), pt(part, part + n);
+  std::vector<int32_t> pt(part, part + n);
+  PinnedArray<int32_t> rp, ci;
   lsq2l_status s;
+  if ((s = rp.alloc((int64_t)m + 1)) != LSQ2L_OK) return fail(s);
+  if ((s = ci.alloc(nnz)) != LSQ2L_OK) return fail(s);
   if ((s = c->dalloc(&c->M.rowptr, m + 1)) != LSQ2L_OK) return fail(s);
   if ((s = c->dalloc(&c->M.colind, nnz)) != LSQ2L_OK) return fail(s);
   if ((s = c->dalloc(&c->M.vals, nnz)) != LSQ2L_OK) return fail(s);
-  hipError_t e = hipMemcpyAsync(rp.data(), rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
-  if (e == hipSuccess && nnz) e = hipMemcpyAsync(ci.data(), colind, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+  hipError_t e = hipMemcpyAsync(rp.p, rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(ci.p, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-  if (rp[m] != nnz) { set_error("rowptr[m] != nnz"); return fail(LSQ2L_EINVAL); }
-  if ((s = validate_csr(m, n, rp, ci)) != LSQ2L_OK) return fail(s);
+  if (rp.p[m] != nnz) { set_error("rowptr[m] != nnz"); return fail(LSQ2L_EINVAL); }
+  if ((s = validate_csr(m, n, rp.p, ci.p, nnz)) != LSQ2L_OK) return fail(s);
   e = hipMemcpyAsync(c->M.rowptr, rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
   if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.colind, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
   if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
   if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
   std::vector<int32_t> seg_of_part(nparts, 0);
-  s = setup_core(c, rp, ci, pt, nparts, seg_of_part);
+  s = setup_core(c, rp.p, ci.p, pt, nparts, seg_of_part);
   if (s != LSQ2L_OK) return fail(s);
   *out = c;
   return LSQ2L_OK;
@@ -822,7 +898,7 @@ lsq2l_status lsq2l_setup_batched(int32_t count, const lsq2l_problem* probs, doub
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) { set_error(std::string("reading problem: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
     if (lrp[pr.m] != pr.nnz) { set_error("rowptr[m] != nnz in problem " + std::to_string(k)); return fail(LSQ2L_EINVAL); }
-    if ((s = validate_csr(pr.m, pr.n, lrp, lci)) != LSQ2L_OK) return fail(s);
+    if ((s = validate_csr(pr.m, pr.n, lrp.data(), lci.data(), pr.nnz)) != LSQ2L_OK) return fail(s);
     for (int32_t rr = 0; rr < pr.m; ++rr) rp[r0 + rr + 1] = (int32_t)(e0 + lrp[rr + 1]);
     for (int32_t q = 0; q < pr.nnz; ++q) ci[e0 + q] = (int32_t)(c0 + lci[q]);
     for (int32_t j = 0; j < pr.n; ++j) {
@@ -837,7 +913,7 @@ lsq2l_status lsq2l_setup_batched(int32_t count, const lsq2l_problem* probs, doub
   hipError_t e = hipMemcpyAsync(c->M.rowptr, rp.data(), (M + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
   if (e == hipSuccess && NNZ) e = hipMemcpyAsync(c->M.colind, ci.data(), NNZ * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
   if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-  s = setup_core(c, rp, ci, pt, (int32_t)NP, seg_of_part);
+  s = setup_core(c, rp.data(), ci.data(), pt, (int32_t)NP, seg_of_part);
   if (s != LSQ2L_OK) return fail(s);
   *out = c;
   return LSQ2L_OK;
@@ -981,6 +1057,9 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
 
 void lsq2l_destroy(lsq2l_handle c) { delete c; }
 
-void lsq2l_release_cache(void) { block_cache().release(); }
+void lsq2l_release_cache(void) {
+  block_cache().release();
+  pinned_pool().release();
+}
 
 }  // extern "C"

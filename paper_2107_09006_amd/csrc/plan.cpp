@@ -169,7 +169,7 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
 }  // namespace
 
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
-                const std::vector<int32_t>& trowptr, const std::vector<int32_t>& tcol,
+                const int32_t* trowptr, const int32_t* tcol,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
                 HostPlan& P, std::string& err) {
   P.nparts = nparts;
@@ -200,7 +200,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       pool.emplace_back([&, t]() {
         BitSet rowset(m), colset(n);
         for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
-          plan_one(i, rowptr, colind, trowptr.data(), tcol.data(), part, P.locown.data(),
+          plan_one(i, rowptr, colind, trowptr, tcol, part, P.locown.data(),
                    pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), rowset, colset,
                    outs[i]);
       });

@@ -31,7 +31,7 @@ bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* 
 
 // Index sets, local layouts and envelopes of every subdomain.
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
-                const std::vector<int32_t>& trowptr, const std::vector<int32_t>& tcol,
+                const int32_t* trowptr, const int32_t* tcol,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
                 HostPlan& P, std::string& err);
 

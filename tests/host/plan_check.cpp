@@ -25,7 +25,7 @@ int main(int argc, char** argv) {
   plan_transpose(m, n, rp.data(), ci.data(), trp, tcol, tperm);
   for (int k = 0; k < nnz; ++k) CHECK(tperm[k] >= 0 && tperm[k] < nnz, "tperm");
   HostPlan H; std::string err;
-  CHECK(plan_build(m, n, rp.data(), ci.data(), trp, tcol, part.data(), nparts, sop, H, err), "%s", err.c_str());
+  CHECK(plan_build(m, n, rp.data(), ci.data(), trp.data(), tcol.data(), part.data(), nparts, sop, H, err), "%s", err.c_str());
   CHECK(plan_maps(m, n, rp.data(), ci.data(), part.data(), H, err), "%s", err.c_str());
   int64_t maxrows = 0;
   for (int i = 0; i < nparts; ++i) {
