@@ -55,8 +55,10 @@ typedef struct {
   double  tol;        /* stop when ||A^T(b - A x)||_2 <= tol ||A^T b||_2 (default 1e-8)          */
   int32_t max_it;     /* PCG iteration limit (default 10000)                                      */
   int32_t precision;  /* LSQ2L_FP64: everything in double.  LSQ2L_MIXED: the local triangular
-                         solves read a float copy of the (double) local factors; recurrences,
-                         dot products, residuals, coarse space and coarse solve stay double     */
+                         solves read a float copy of the (double) local factors, and the coarse
+                         restriction and prolongation a float copy of the (double) coarse basis
+                         (E is built from the double basis); all accumulation, recurrences, dot
+                         products, residuals and the coarse solve stay double                   */
   int32_t flexible;   /* 1: flexible PCG, beta = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k)          */
   int32_t variant;    /* LSQ2L_ADDITIVE (two-level, default) or LSQ2L_ONE_LEVEL (M_ASM)           */
   int32_t nev_max;    /* keep at most this many coarse vectors per subdomain (0 = no cap)         */

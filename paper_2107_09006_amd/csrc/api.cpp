@@ -194,6 +194,7 @@ struct lsq2l_ctx {
   int64_t etiles = 0;
   double *fac = nullptr, *dinv = nullptr, *scale = nullptr, *ctg = nullptr;
   float *fac32 = nullptr, *dinv32 = nullptr;
+  float* X32 = nullptr;      // MIXED: FP32 copy of X for the restriction and prolongation
   double *X = nullptr, *W = nullptr, *efac = nullptr, *edinv = nullptr, *einv = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr, *rold = nullptr;
   double *tm = nullptr, *tm2 = nullptr, *loc = nullptr, *cvec = nullptr, *dvec = nullptr;
@@ -353,11 +354,14 @@ void apply_M(lsq2l_ctx* c, const double* r, double* z) {
     launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
   else
     launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
+  const bool x32 = c->X32 != nullptr;
   if (c->coarse) {
-    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
+    if (x32) launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
+    else launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
     launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
   }
-  launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
+  if (x32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, c->coarse ? c->dvec : nullptr, z);
+  else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
 }
 
 void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
@@ -600,6 +604,13 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
       TRY(c->dalloc(&c->W, CP.wtot));
       launch_coarse_X(st, nparts, c->P, c->fac, c->dinv, c->scale, work, sig, c->X);
       launch_coarse_W(st, nparts, c->P, c->M, c->X, c->W);
+      if (c->opt.precision == LSQ2L_MIXED) {
+        // E below is built from the FP64 X; the per-iteration restriction
+        // and prolongation both read the same rounded copy, so the coarse
+        // term R_0^T E^{-1} R_0 stays symmetric positive semidefinite
+        TRY(c->dalloc(&c->X32, CP.xtot));
+        launch_to_float(st, CP.xtot, c->X, c->X32);
+      }
       LSQ2L_HIP_TRY(hipStreamSynchronize(st));
       c->info.t_eigen_ms = ms_since(t0);
       t0 = clk::now();

@@ -644,9 +644,10 @@ k_tile_transpose(int64_t ntiles, const double* __restrict__ in, double* __restri
 // c_i = X_i^T r(Omega_Ii): r gathered once into LDS (in chunks), one wave per
 // coarse vector.
 constexpr int RCHUNK = 8192;
+template <typename TX>
 __global__ void __launch_bounds__(1024)
 k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
-                  const double* __restrict__ X, const double* __restrict__ r,
+                  const TX* __restrict__ X, const double* __restrict__ r,
                   double* __restrict__ cvec) {
   __shared__ double sr[RCHUNK];
   __shared__ double sacc[128];
@@ -665,14 +666,14 @@ k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ 
       for (int u = 0; u < 8; ++u) {
         const int k = kb + u * nwaves + wave;
         if (k >= d.p) break;
-        const double* xk = X + d.x_off + (int64_t)k * d.nIp + a0;
+        const TX* xk = X + d.x_off + (int64_t)k * d.nIp + a0;
         // eight independent loads in flight per lane
         double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int a = lane;
         for (; a + 7 * 64 < len; a += 8 * 64)
 #pragma unroll
-          for (int i = 0; i < 8; ++i) s8[i] += xk[a + 64 * i] * sr[a + 64 * i];
-        for (int i = 0; a < len; a += 64, ++i) s8[i] += xk[a] * sr[a];
+          for (int i = 0; i < 8; ++i) s8[i] += (double)xk[a + 64 * i] * sr[a + 64 * i];
+        for (int i = 0; a < len; a += 64, ++i) s8[i] += (double)xk[a] * sr[a];
         acc[u] += ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
       }
     }
@@ -851,7 +852,13 @@ void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* e
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
                             const double* r, double* c) {
   if (max_p <= 0) return;
-  k_coarse_restrict<<<nsub, 1024, 0, st>>>(P.subs, P.omega, X, r, c);
+  k_coarse_restrict<double><<<nsub, 1024, 0, st>>>(P.subs, P.omega, X, r, c);
+}
+
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const float* X,
+                            const double* r, double* c) {
+  if (max_p <= 0) return;
+  k_coarse_restrict<float><<<nsub, 1024, 0, st>>>(P.subs, P.omega, X, r, c);
 }
 
 void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,

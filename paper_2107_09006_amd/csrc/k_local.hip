@@ -240,11 +240,12 @@ k_gather_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ ome
 
 // z_j = sum over the subdomains holding column j of S_pos loc_pos (fixed
 // order), plus the coarse prolongation X_i d_i on the interior of its owner.
+template <typename TX>
 __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
                                 const int32_t* __restrict__ own_pos, const double* __restrict__ scale,
                                 const double* __restrict__ loc, const int32_t* __restrict__ part,
                                 const int32_t* __restrict__ locown, const SubDesc* __restrict__ subs,
-                                const double* __restrict__ X, const double* __restrict__ dcoarse,
+                                const TX* __restrict__ X, const double* __restrict__ dcoarse,
                                 double* __restrict__ z) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -256,15 +257,15 @@ __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
   if (dcoarse != nullptr) {
     const SubDesc d = subs[part[j]];
     const int a = locown[j];
-    const double* xr = X + d.x_off + a;
+    const TX* xr = X + d.x_off + a;
     const double* dc = dcoarse + d.cg_off;
     // eight independent loads in flight per thread
     double c8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int k = 0;
     for (; k + 8 <= d.p; k += 8)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) c8[i] += xr[(int64_t)(k + i) * d.nIp] * dc[k + i];
-    for (int i = 0; k < d.p; ++k, ++i) c8[i] += xr[(int64_t)k * d.nIp] * dc[k];
+      for (int i = 0; i < 8; ++i) c8[i] += (double)xr[(int64_t)(k + i) * d.nIp] * dc[k + i];
+    for (int i = 0; k < d.p; ++k, ++i) c8[i] += (double)xr[(int64_t)k * d.nIp] * dc[k];
     s += ((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]));
   }
   z[j] = s;
@@ -311,8 +312,15 @@ void launch_gather_local(hipStream_t st, int nsub, const DevPlan& P, const doubl
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
                           const double* loc, const double* X, const double* dcoarse, double* z) {
   if (n == 0) return;
-  k_scatter_local<<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc, P.part,
-                                                   P.locown, P.subs, X, dcoarse, z);
+  k_scatter_local<double><<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc,
+                                                           P.part, P.locown, P.subs, X, dcoarse, z);
+}
+
+void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
+                          const double* loc, const float* X, const double* dcoarse, double* z) {
+  if (n == 0) return;
+  k_scatter_local<float><<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc,
+                                                          P.part, P.locown, P.subs, X, dcoarse, z);
 }
 
 }  // namespace lsq2l

@@ -105,6 +105,8 @@ void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const fl
                             const float* dinv, double* loc);
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
                           const double* loc, const double* X, const double* dcoarse, double* z);
+void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
+                          const double* loc, const float* X, const double* dcoarse, double* z);
 
 // --- coarse space ------------------------------------------------------------
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
@@ -125,6 +127,8 @@ void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, dou
 void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
                  const double* edinv, const double* efacT, const double* edinvT, double* einv);
 void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const double* X,
+                            const double* r, double* c);
+void launch_coarse_restrict(hipStream_t st, int nsub, const DevPlan& P, int max_p, const float* X,
                             const double* r, double* c);
 void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, double* out);
 void launch_einv_gemv(hipStream_t st, int64_t n0, int S, const DevCoarse& Cc, const double* einv,
