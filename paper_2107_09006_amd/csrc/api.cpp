@@ -631,14 +631,22 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
         c->Cc.e_items = (int4*)d_items;
       }
       launch_coarse_E(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->W, c->efac);
-      // right-looking Cholesky of E, one tile column per step
+      // right-looking Cholesky of E, one tile column per launch, each launch
+      // also applying the previous column to the tiles right of the current
+      // one (rows of column J - 1 below J: its list without row J)
       TRY(c->upload(&c->Cc.erows, CP.erows));
       TRY(c->upload(&c->Cc.eptr, CP.eptr));
       int32_t* d_erows = c->Cc.erows;
       for (int64_t J = 0; J < c->etiles; ++J) {
         const int nr = (int)(CP.eptr[J + 1] - CP.eptr[J]);
-        launch_echol_diag(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac, c->edinv, c->status + 1);
-        launch_echol_update(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, c->efac);
+        int64_t p0 = 0, p1 = 0;
+        if (J > 0) {
+          p0 = CP.eptr[J - 1];
+          p1 = CP.eptr[J];
+          if (p0 < p1 && CP.erows[p0] == J) ++p0;
+        }
+        launch_echol_step(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, d_erows + p0, (int)(p1 - p0),
+                          c->efac, c->edinv, c->status + 1);
       }
       TRY(c->dalloc(&c->einv, CP.einv_tot));
       TRY(c->dalloc(&c->Cc.e_part, CP.einv_tot / TS));

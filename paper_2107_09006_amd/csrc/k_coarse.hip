@@ -295,59 +295,81 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
   }
 }
 
-// One step J of the right-looking tile Cholesky of E.  k_echol_diag: every
-// workgroup factors and inverts the diagonal tile (J, J) in registers and
-// forms EDIAG_ROWS panel tiles L(I, J) = A(I, J) L_JJ^{-T} (one per wave);
-// workgroup 0 keeps L_JJ^{-1}, the only form of the diagonal tile the solves
-// read, so (J, J) itself is left unchanged.  k_echol_update: the trailing
-// update, one wave per pair of panel rows.
-constexpr int EDIAG_ROWS = 8;
+// One step J of the right-looking tile Cholesky of E, fused with the
+// trailing update of the previous column, in one launch.
+// - Workgroups below ndiag (panel role) apply column J - 1 to the tiles of
+//   column J themselves: A(J, J) -= L(J, J-1) L(J, J-1)^T, and for their
+//   panel rows A(I, J) -= L(I, J-1) L(J, J-1)^T.  Every such workgroup then
+//   factors and inverts the diagonal tile in registers, and forms ESTEP_WAVES
+//   panel tiles L(I, J) = A(I, J) L_JJ^{-T}, one per wave.  Workgroup 0 keeps
+//   L_JJ^{-1}, the only form of the diagonal tile the solves read, so (J, J)
+//   itself is left unchanged.
+// - The other workgroups apply the rest of column J - 1's update, one wave
+//   per pair of its rows below J: A(Ia, Ib) -= L(Ia, J-1) L(Ib, J-1)^T.
+// The two roles touch disjoint tiles (column J against columns > J), and
+// every update of column J by columns before J - 1 ran in an earlier launch.
+constexpr int ESTEP_WAVES = 8;
 
-__global__ void __launch_bounds__(EDIAG_ROWS * 64)
-k_echol_diag(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
-             const int32_t* __restrict__ rows, int nr, double* __restrict__ efac,
-             double* __restrict__ edinv, int32_t* __restrict__ status) {
+__global__ void __launch_bounds__(ESTEP_WAVES * 64)
+k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
+             const int32_t* __restrict__ rows, int nr, const int32_t* __restrict__ prows, int npr,
+             int ndiag, double* __restrict__ efac, double* __restrict__ edinv,
+             int32_t* __restrict__ status) {
   __shared__ double sW[TS * LDT], sInv[TS * LDT];
+  __shared__ double sS[ESTEP_WAVES][TS * LDT];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid / 64, lane = tid % 64;
+  double4_t acc[4];
+  if ((int)blockIdx.x >= ndiag) {
+    const int64_t gw = (int64_t)(blockIdx.x - ndiag) * ESTEP_WAVES + wave;
+    const int64_t npairs = (int64_t)npr * (npr + 1) / 2;
+    if (gw >= npairs) return;
+    // pair index -> (a, b), a >= b
+    int a = (int)((sqrt(8.0 * gw + 1.0) - 1.0) / 2.0);
+    while ((int64_t)a * (a + 1) / 2 > gw) --a;
+    while ((int64_t)(a + 1) * (a + 2) / 2 <= gw) ++a;
+    const int b = (int)(gw - (int64_t)a * (a + 1) / 2);
+    const int Ia = prows[a], Ib = prows[b];
+    double* Cab = efac + tile_pos(eF, eOff, Ia, Ib) * TT;
+    tile_acc_load<double>(acc, Cab, TS, lane);
+    tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, Ia, J - 1) * TT, TS,
+                              efac + tile_pos(eF, eOff, Ib, J - 1) * TT, TS, lane);
+    tile_acc_store<double>(acc, Cab, TS, lane);
+    return;
+  }
+  const bool prevJ = J > 0 && eF[J] <= J - 1;         // L(J, J-1) is stored
+  const double* Ljp = prevJ ? efac + tile_pos(eF, eOff, J, J - 1) * TT : nullptr;
   const double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
   for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
   __syncthreads();
   if (wave == 0) {
+    if (prevJ) {
+      tile_acc_load<double>(acc, sW, LDT, lane);
+      tile_mma_nt<double, true>(acc, Ljp, TS, Ljp, TS, lane);
+      wave_sync();
+      tile_acc_store<double>(acc, sW, LDT, lane);
+      wave_sync();
+    }
     const bool ok = tile_potrf_inv_reg(sW, nullptr, sInv, lane);
     if (!ok && lane == 0 && blockIdx.x == 0) atomicCAS(status, 0, J + 1);
   }
   __syncthreads();
   if (blockIdx.x == 0)
     for (int e = tid; e < TT; e += nthr) edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
-  const int a = blockIdx.x * EDIAG_ROWS + wave;
+  const int a = blockIdx.x * ESTEP_WAVES + wave;
   if (a < nr) {
-    double* Aij = efac + tile_pos(eF, eOff, rows[a], J) * TT;
-    double4_t acc[4];
+    const int I = rows[a];
+    double* Aij = efac + tile_pos(eF, eOff, I, J) * TT;
+    double* S = sS[wave];
+    tile_acc_load<double>(acc, Aij, TS, lane);
+    if (prevJ && eF[I] <= J - 1)
+      tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, I, J - 1) * TT, TS, Ljp, TS, lane);
+    tile_acc_store<double>(acc, S, LDT, lane);
+    wave_sync();
     tile_acc_zero<double>(acc);
-    tile_mma_nt<double, false>(acc, Aij, TS, sInv, LDT, lane);
+    tile_mma_nt<double, false>(acc, S, LDT, sInv, LDT, lane);
     tile_acc_store<double>(acc, Aij, TS, lane);
   }
-}
-
-__global__ void __launch_bounds__(256)
-k_echol_update(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
-               const int32_t* __restrict__ rows, int nr, double* __restrict__ efac) {
-  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) / 64, lane = threadIdx.x % 64;
-  const int64_t npairs = (int64_t)nr * (nr + 1) / 2;
-  if (gw >= npairs) return;
-  // pair index -> (a, b), a >= b
-  int a = (int)((sqrt(8.0 * gw + 1.0) - 1.0) / 2.0);
-  while ((int64_t)a * (a + 1) / 2 > gw) --a;
-  while ((int64_t)(a + 1) * (a + 2) / 2 <= gw) ++a;
-  const int b = (int)(gw - (int64_t)a * (a + 1) / 2);
-  const int Ia = rows[a], Ib = rows[b];
-  double* Cab = efac + tile_pos(eF, eOff, Ia, Ib) * TT;
-  double4_t acc[4];
-  tile_acc_load<double>(acc, Cab, TS, lane);
-  tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, Ia, J) * TT, TS,
-                            efac + tile_pos(eF, eOff, Ib, J) * TT, TS, lane);
-  tile_acc_store<double>(acc, Cab, TS, lane);
 }
 
 // Full 32 x 32 product fragments for one wave (K = 32): op(A) rows in two
@@ -823,17 +845,14 @@ void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoar
                                      efac);
 }
 
-void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                       double* efac, double* edinv, int32_t* status) {
-  const int nblk = max(1, (nr + EDIAG_ROWS - 1) / EDIAG_ROWS);
-  k_echol_diag<<<nblk, EDIAG_ROWS * 64, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac, edinv, status);
-}
-
-void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                         double* efac) {
-  const int64_t npairs = (int64_t)nr * (nr + 1) / 2;
-  if (npairs == 0) return;
-  k_echol_update<<<(unsigned)((npairs + 3) / 4), 256, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, efac);
+void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                       const int32_t* prows, int npr, double* efac, double* edinv,
+                       int32_t* status) {
+  const int ndiag = max(1, (nr + ESTEP_WAVES - 1) / ESTEP_WAVES);
+  const int64_t npairs = (int64_t)npr * (npr + 1) / 2;
+  const int nupd = (int)((npairs + ESTEP_WAVES - 1) / ESTEP_WAVES);
+  k_echol_step<<<ndiag + nupd, ESTEP_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, prows, npr,
+                                                         ndiag, efac, edinv, status);
 }
 
 void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out) {

@@ -119,10 +119,8 @@ void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix
                      const double* X, double* W);
 void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
                      const double* W, double* efac);
-void launch_echol_diag(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                       double* efac, double* edinv, int32_t* status);
-void launch_echol_update(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                         double* efac);
+void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
+                       const int32_t* prows, int npr, double* efac, double* edinv, int32_t* status);
 void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out);
 void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
                  const double* edinv, const double* efacT, const double* edinvT, double* einv);

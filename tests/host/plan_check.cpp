@@ -154,6 +154,25 @@ int main(int argc, char** argv) {
         for (int64_t b = C.eptr[J]; b <= a; ++b) etp(C.erows[a], C.erows[b]);
       }
     }
+    // k_echol_step: step J reads column J - 1 for the tiles of column J and
+    // updates the pairs of column J - 1's rows below J
+    for (int64_t J = 0; J < C.etiles; ++J) {
+      const bool prevJ = J > 0 && C.eF[J] <= J - 1;
+      if (prevJ) etp(J, J - 1);
+      for (int64_t a = C.eptr[J]; a < C.eptr[J + 1]; ++a) {
+        const int64_t I = C.erows[a];
+        CHECK(I > J, "row list of column %lld", (long long)J);
+        if (prevJ && C.eF[I] <= J - 1) etp(I, J - 1);
+      }
+      if (J == 0) continue;
+      int64_t p0 = C.eptr[J - 1], p1 = C.eptr[J];
+      if (p0 < p1 && C.erows[p0] == J) ++p0;
+      for (int64_t a = p0; a < p1; ++a) {
+        CHECK(C.erows[a] > J, "trailing rows of column %lld", (long long)(J - 1));
+        etp(C.erows[a], J - 1);
+        for (int64_t b = p0; b <= a; ++b) etp(C.erows[a], C.erows[b]);
+      }
+    }
     for (int s = 0; s < S; ++s) {
       const SegDesc& sg = C.segs[s];
       const int64_t t0 = sg.etile0, nt = sg.etiles;
