@@ -142,6 +142,51 @@ __device__ void tri_solve(const double* d, const double* e, int n, double lam, d
 // ----------------------------------------------------------------------------
 // the selection kernel
 // ----------------------------------------------------------------------------
+// Orders this wave's global stores before its later loads by other lanes
+// (workgroup-scope release and acquire).
+__device__ inline void wg_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// acc += sign * A * B with A, B 32 x 32 column-major (leading dims lda, ldb).
+template <bool NEG>
+__device__ inline void tile_mma_nn(double4_t acc[4], const double* A, int lda, const double* B,
+                                   int ldb, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll 2
+  for (int kk = 0; kk < TS; kk += 4) {
+    double a0 = A[(int64_t)(kk + lk) * lda + li];
+    double a1 = A[(int64_t)(kk + lk) * lda + 16 + li];
+    const double b0 = B[(int64_t)li * ldb + kk + lk];
+    const double b1 = B[(int64_t)(16 + li) * ldb + kk + lk];
+    if (NEG) { a0 = -a0; a1 = -a1; }
+    acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
+    acc[1] = Mfma<double>::mma(a0, b1, acc[1]);
+    acc[2] = Mfma<double>::mma(a1, b0, acc[2]);
+    acc[3] = Mfma<double>::mma(a1, b1, acc[3]);
+  }
+}
+
+// X = R^{-1} for the upper triangle R of a 32 x 32 tile (column-major, ld):
+// lane c < 32 forms column c by back substitution, X(a, c) = -(sum_{b =
+// a+1..c} R(a, b) X(b, c)) / R(a, a) from X(c, c) = 1 / R(c, c), the lower
+// part set to zero.  Each lane reads only what it wrote itself.
+__device__ inline void tri_inv_upper_tile(const double* R, int ld, double* X, int lane) {
+  if (lane < TS) {
+    const int c = lane;
+    double* xc = X + (int64_t)c * ld;
+    for (int a = c + 1; a < TS; ++a) xc[a] = 0.0;
+    xc[c] = 1.0 / R[(int64_t)c * ld + c];
+    for (int a = c - 1; a >= 0; --a) {
+      double t = 0.0;
+      for (int b = a + 1; b <= c; ++b) t += R[(int64_t)b * ld + a] * xc[b];
+      xc[a] = -t / R[(int64_t)a * ld + a];
+    }
+  }
+  wg_fence();
+}
+
 __global__ void __launch_bounds__(SEL_THREADS)
 k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
          const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
@@ -255,17 +300,46 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       return;
     }
     const int rp = (r + 15) / 16 * 16;
-    // M2 = Q = R11^{-T}: thread c forms column c of R11^{-1} by back
-    // substitution and stores it as row c of Q (coalesced over c)
-    for (int64_t q = tid; q < mm; q += nthr) M2[q] = 0.0;
-    __syncthreads();
-    for (int c = tid; c < r; c += nthr) {
-      M2[(int64_t)c * ld + c] = 1.0 / M0[(int64_t)c * ld + c];
-      for (int a = c - 1; a >= 0; --a) {
-        double t = 0.0;
-        for (int b = a + 1; b <= c; ++b) t += M0[(int64_t)b * ld + a] * M2[(int64_t)b * ld + c];
-        M2[(int64_t)a * ld + c] = -t / M0[(int64_t)a * ld + a];
+    // M2 = Q = R11^{-T} from X = R11^{-1}, formed in M3 by 32 x 32 tiles.
+    // The factor is padded to nb tiles with an identity block, so X is too.
+    // Phase 1: each diagonal tile's inverse D_I (one wave per tile); phase
+    // 2: column block J, from I = J - 1 up to 0,
+    //   X_IJ = -D_I (sum_{K = I+1..J} R_IK X_KJ),
+    // one wave per column block, on MFMA; phase 3: Q = X^T.
+    {
+      const int nb = (r + TS - 1) / TS, np = nb * TS;
+      const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
+      for (int64_t q = tid; q < (int64_t)np * np; q += nthr) {
+        const int a = (int)(q % np), c = (int)(q / np);
+        if (a <= c && c >= r) M0[(int64_t)c * ld + a] = (a == c) ? 1.0 : 0.0;
       }
+      __syncthreads();
+      for (int I = wv; I < nb; I += nwv)
+        tri_inv_upper_tile(M0 + (int64_t)(I * TS) * ld + I * TS, ld,
+                           M3 + (int64_t)(I * TS) * ld + I * TS, ln);
+      __syncthreads();
+      for (int J = wv; J < nb; J += nwv)
+        for (int I = J - 1; I >= 0; --I) {
+          double4_t acc[4];
+          tile_acc_zero<double>(acc);
+          for (int K = I + 1; K <= J; ++K)
+            tile_mma_nn<false>(acc, M0 + (int64_t)(K * TS) * ld + I * TS, ld,
+                               M3 + (int64_t)(J * TS) * ld + K * TS, ld, ln);
+          double* Xij = M3 + (int64_t)(J * TS) * ld + I * TS;   // the sum, then X_IJ
+          tile_acc_store<double>(acc, Xij, ld, ln);
+          wg_fence();
+          tile_acc_zero<double>(acc);
+          tile_mma_nn<true>(acc, M3 + (int64_t)(I * TS) * ld + I * TS, ld, Xij, ld, ln);
+          wg_fence();
+          tile_acc_store<double>(acc, Xij, ld, ln);
+          wg_fence();
+        }
+      __syncthreads();
+      for (int64_t q = tid; q < mm; q += nthr) {
+        const int a = (int)(q % ld), c = (int)(q / ld);
+        M2[q] = (a < r && c <= a) ? M3[(int64_t)a * ld + c] : 0.0;
+      }
+      __syncthreads();
     }
     // M1 = T11 = D2 T D2 in pivot order (r x r, zero padded)
     for (int64_t q = tid; q < mm; q += nthr) {
