@@ -160,6 +160,13 @@ __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, i
 // Orders the LDS accesses of the lanes of one wave: a wave's LDS operations
 // complete in issue order, so wavefront-scope fences around a code-motion
 // barrier suffice.
+// Orders this wave's global stores before its later loads by other lanes
+// (workgroup-scope release and acquire).
+__device__ inline void wg_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

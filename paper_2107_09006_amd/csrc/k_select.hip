@@ -142,13 +142,6 @@ __device__ void tri_solve(const double* d, const double* e, int n, double lam, d
 // ----------------------------------------------------------------------------
 // the selection kernel
 // ----------------------------------------------------------------------------
-// Orders this wave's global stores before its later loads by other lanes
-// (workgroup-scope release and acquire).
-__device__ inline void wg_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // acc += sign * A * B with A, B 32 x 32 column-major (leading dims lda, ldb).
 template <bool NEG>
 __device__ inline void tile_mma_nn(double4_t acc[4], const double* A, int lda, const double* B,
