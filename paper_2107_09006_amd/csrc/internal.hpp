@@ -143,17 +143,24 @@ template <typename T, bool NEG>
 __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, int lda,
                                    const T* B, int ldb, int lane) {
   const int li = lane % 16, lk = lane / 16;
-#pragma unroll 2
-  for (int kk = 0; kk < TS; kk += 4) {
-    T a0 = A[(int64_t)(kk + lk) * lda + li];
-    T a1 = A[(int64_t)(kk + lk) * lda + 16 + li];
-    T b0 = B[(int64_t)(kk + lk) * ldb + li];
-    T b1 = B[(int64_t)(kk + lk) * ldb + 16 + li];
-    if (NEG) { a0 = -a0; a1 = -a1; }
-    acc[0] = Mfma<T>::mma(a0, b0, acc[0]);
-    acc[1] = Mfma<T>::mma(a0, b1, acc[1]);
-    acc[2] = Mfma<T>::mma(a1, b0, acc[2]);
-    acc[3] = Mfma<T>::mma(a1, b1, acc[3]);
+  // all operand fragments load first (32 independent loads per lane), then
+  // the MFMAs run
+  T a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kk = 4 * q;
+    a0[q] = A[(int64_t)(kk + lk) * lda + li];
+    a1[q] = A[(int64_t)(kk + lk) * lda + 16 + li];
+    b0[q] = B[(int64_t)(kk + lk) * ldb + li];
+    b1[q] = B[(int64_t)(kk + lk) * ldb + 16 + li];
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const T x0 = NEG ? -a0[q] : a0[q], x1 = NEG ? -a1[q] : a1[q];
+    acc[0] = Mfma<T>::mma(x0, b0[q], acc[0]);
+    acc[1] = Mfma<T>::mma(x0, b1[q], acc[1]);
+    acc[2] = Mfma<T>::mma(x1, b0[q], acc[2]);
+    acc[3] = Mfma<T>::mma(x1, b1[q], acc[3]);
   }
 }
 

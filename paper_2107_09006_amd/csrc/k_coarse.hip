@@ -115,18 +115,24 @@ template <bool TA>
 __device__ inline void tile_mma_cols(double4_t acc[4], const double* A, int lda, const double* B,
                                      int ldb, int nb, int lane, bool neg) {
   const int li = lane % 16, lk = lane / 16;
-#pragma unroll 2
+  // all operand fragments of the 32-deep product load first (32 independent
+  // loads per lane), then the 32 MFMAs run
+  double a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int k = 4 * q + lk;
-    double a0 = TA ? A[(int64_t)li * lda + k] : A[(int64_t)k * lda + li];
-    double a1 = TA ? A[(int64_t)(16 + li) * lda + k] : A[(int64_t)k * lda + 16 + li];
-    const double b0 = li < nb ? B[(int64_t)li * ldb + k] : 0.0;
-    const double b1 = 16 + li < nb ? B[(int64_t)(16 + li) * ldb + k] : 0.0;
-    if (neg) { a0 = -a0; a1 = -a1; }
-    acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
-    acc[1] = Mfma<double>::mma(a0, b1, acc[1]);
-    acc[2] = Mfma<double>::mma(a1, b0, acc[2]);
-    acc[3] = Mfma<double>::mma(a1, b1, acc[3]);
+    a0[q] = TA ? A[(int64_t)li * lda + k] : A[(int64_t)k * lda + li];
+    a1[q] = TA ? A[(int64_t)(16 + li) * lda + k] : A[(int64_t)k * lda + 16 + li];
+    b0[q] = li < nb ? B[(int64_t)li * ldb + k] : 0.0;
+    b1[q] = 16 + li < nb ? B[(int64_t)(16 + li) * ldb + k] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double x0 = neg ? -a0[q] : a0[q], x1 = neg ? -a1[q] : a1[q];
+    acc[0] = Mfma<double>::mma(x0, b0[q], acc[0]);
+    acc[1] = Mfma<double>::mma(x0, b1[q], acc[1]);
+    acc[2] = Mfma<double>::mma(x1, b0[q], acc[2]);
+    acc[3] = Mfma<double>::mma(x1, b1[q], acc[3]);
   }
 }
 
@@ -146,7 +152,7 @@ __device__ inline void tile_io_cols(double4_t acc[4], double* C, int ldc, int nb
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
 // H = L_GI^T Y by 32 x 32 output blocks (one per wave task), then the
 // backward substitution with L_I^T by tile rows (right-looking), all on MFMA.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
            const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
            const double* __restrict__ dinv, const double* __restrict__ scale,
@@ -829,7 +835,7 @@ void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fa
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                      const double* dinv, const double* scale, const double* work,
                      const double* sig, double* X) {
-  k_coarse_X<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, scale, work, sig, X);
+  k_coarse_X<<<nsub, 512, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, scale, work, sig, X);
 }
 
 void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
