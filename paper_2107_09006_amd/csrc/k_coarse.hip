@@ -425,7 +425,7 @@ __device__ inline void tile_frag_mma(double4_t acc[4], const TileFrag& f) {
 // fragment load is a column read.
 constexpr int EINV_WAVES = 4;
 constexpr int EWIN_SLOTS = 6;
-constexpr int ELIST = 256;                  // backward list entries staged in LDS
+constexpr int ELIST = EINV_WAVES * 64;      // backward list entries staged in LDS (one per thread)
 
 struct AFrag { double a[2][8]; };
 
@@ -581,6 +581,21 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
     __syncthreads();
     for (int K = nt - 1; K >= c; --K) {
       const int Kg = t0 + K;
+      // loads whose latency the products hide: this step's tile of Y for the
+      // reduction below, and the next step's list (one entry per thread)
+      double ypre[TT / (EINV_WAVES * 64)];
+#pragma unroll
+      for (int i = 0; i < TT / (EINV_WAVES * 64); ++i) {
+        int row, col;
+        elem_rc(tid + i * EINV_WAVES * 64, row, col);
+        ypre[i] = Xc[(int64_t)col * ld + K * TS + row];
+      }
+      int nxt_n = 0, nxt_I = 0;
+      if (K > c) {
+        const int64_t un = eptr[Kg - 1];
+        nxt_n = (int)min<int64_t>(eptr[Kg] - un, ELIST);
+        if (tid < nxt_n) nxt_I = erows[un + tid];
+      }
       double4_t acc[4];
       tile_acc_zero<double>(acc);
       // rows of this wave evicted from its window (rows above its oldest
@@ -616,12 +631,15 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
           frag_mma(acc, f, win[sl]);
         }
       }
+      const int64_t nxt_O = tid < nxt_n ? tile_pos(eF, eOff, nxt_I, Kg - 1) : 0;
       put_partial(acc);
       __syncthreads();
-      for (int e = tid; e < TT; e += nthr) {
+#pragma unroll
+      for (int i = 0; i < TT / (EINV_WAVES * 64); ++i) {
+        const int e = tid + i * EINV_WAVES * 64;
         int row, col;
         elem_rc(e, row, col);
-        double v = Xc[(int64_t)col * ld + K * TS + row];
+        double v = ypre[i];
         for (int q = 0; q < EINV_WAVES; ++q) v -= spart[q][e];
         sY[col * LDT + row] = v;
       }
@@ -632,7 +650,10 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
         quad_store(x, Xc + K * TS, ld, bi, bj, lane);
         quad_store(x, sN, LDT, bi, bj, lane);
       }
-      if (K > c) fill_list(Kg - 1);         // this step's list is no longer read
+      if (tid < nxt_n) {                    // this step's list is no longer read
+        sEI[tid] = nxt_I - t0;
+        sEO[tid] = nxt_O;
+      }
       __syncthreads();
       if (K % EINV_WAVES == w) {
 #pragma unroll
