@@ -57,6 +57,24 @@ __device__ inline void quad_mma(double4_t& acc, const double* A, int lda, const 
   quad_frag_mma(acc, f, neg);
 }
 
+// the A fragments of quad_mma<false> (rows 16 bi .. 16 bi + 15 of A), for a
+// product issued later with quad_mma_pre
+__device__ inline void quad_afrag(double (&a)[8], const double* A, int lda, int bi, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = A[(int64_t)(4 * q + lk) * lda + 16 * bi + li];
+}
+
+__device__ inline void quad_mma_pre(double4_t& acc, const double (&a)[8], const double* B, int ldb,
+                                    int bj, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+  double b[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b[q] = B[(int64_t)(16 * bj + li) * ldb + 4 * q + lk];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc = Mfma<double>::mma(a[q], b[q], acc);
+}
+
 __device__ inline void quad_load(double4_t& acc, const double* C, int ldc, int bi, int bj, int lane) {
   for (int v = 0; v < 4; ++v)
     acc[v] = C[(int64_t)(16 * bj + Mfma<double>::acc_col(lane, v)) * ldc + 16 * bi +
@@ -504,6 +522,8 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
     for (int I = c; I < nt; ++I) {
       const int Ig = t0 + I;
       const int K0 = max(eF[Ig] - t0, c);
+      double dfr[8];                         // this step's diagonal inverse, loaded under the products
+      quad_afrag(dfr, edinv + (int64_t)Ig * TT, TS, bi, lane);
       double4_t acc[4];
       tile_acc_zero<double>(acc);
       // tiles of this wave evicted from its window (the window holds every
@@ -538,7 +558,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
       __syncthreads();
       {
         double4_t y = {0.0, 0.0, 0.0, 0.0};
-        quad_mma<false>(y, edinv + (int64_t)Ig * TT, TS, sY, LDT, bi, bj, lane, false);
+        quad_mma_pre(y, dfr, sY, LDT, bj, lane);
         quad_store(y, Xc + I * TS, ld, bi, bj, lane);
         quad_store(y, sN, LDT, bi, bj, lane);
       }
@@ -581,6 +601,8 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
     __syncthreads();
     for (int K = nt - 1; K >= c; --K) {
       const int Kg = t0 + K;
+      double dfr[8];                         // this step's diagonal inverse, loaded under the products
+      quad_afrag(dfr, edinvT + (int64_t)Kg * TT, TS, bi, lane);
       // loads whose latency the products hide: this step's tile of Y for the
       // reduction below, and the next step's list (one entry per thread)
       double ypre[TT / (EINV_WAVES * 64)];
@@ -646,7 +668,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
       __syncthreads();
       {
         double4_t x = {0.0, 0.0, 0.0, 0.0};
-        quad_mma<false>(x, edinvT + (int64_t)Kg * TT, TS, sY, LDT, bi, bj, lane, false);
+        quad_mma_pre(x, dfr, sY, LDT, bj, lane);
         quad_store(x, Xc + K * TS, ld, bi, bj, lane);
         quad_store(x, sN, LDT, bi, bj, lane);
       }
