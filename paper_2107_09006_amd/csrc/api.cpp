@@ -175,10 +175,6 @@ using namespace lsq2l;
 
 struct lsq2l_ctx {
   hipStream_t st = nullptr;
-  // second stream (default priority) for the coarse path of M r, which runs
-  // beside the local solves; fork and join events
-  hipStream_t st2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   lsq2l_options opt{};
   double tau = 0.0;
   int S = 1;
@@ -282,12 +278,8 @@ struct lsq2l_ctx {
     return LSQ2L_OK;
   }
   ~lsq2l_ctx() {
-    if (st2) (void)hipStreamSynchronize(st2);
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (st2) (void)hipStreamDestroy(st2);
     for (const DevBlock& b : dev_allocs) block_cache().give(b.p, b.bytes, b.dev);
     for (void* v : host_allocs) (void)hipHostFree(v);
   }
@@ -357,26 +349,17 @@ lsq2l_status validate_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t
 // R_0^T E^{-1} R_0 r (eq. two_level_schwarz).
 void apply_M(lsq2l_ctx* c, const double* r, double* z) {
   const hipStream_t st = c->st;
-  const bool x32 = c->X32 != nullptr;
-  // the coarse path reads r only: restriction and E^{-1} run on the second
-  // stream while the local solves run on the handle's stream
-  const hipStream_t sc = c->st2 ? c->st2 : st;
-  if (c->coarse) {
-    if (c->st2) {
-      (void)hipEventRecord(c->ev_fork, st);
-      (void)hipStreamWaitEvent(sc, c->ev_fork, 0);
-    }
-    if (x32) launch_coarse_restrict(sc, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
-    else launch_coarse_restrict(sc, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
-    launch_einv_gemv(sc, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
-    if (c->st2) (void)hipEventRecord(c->ev_join, sc);
-  }
   launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
   if (c->opt.precision == LSQ2L_MIXED)
     launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
   else
     launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
-  if (c->coarse && c->st2) (void)hipStreamWaitEvent(st, c->ev_join, 0);
+  const bool x32 = c->X32 != nullptr;
+  if (c->coarse) {
+    if (x32) launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
+    else launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
+    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+  }
   if (x32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, c->coarse ? c->dvec : nullptr, z);
   else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
 }
@@ -617,9 +600,6 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     TRY(c->upload(&c->Cc.segs, c->segs_h));
     if (c->n0 > 0) {
       c->coarse = true;
-      LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
-      LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-      LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
       TRY(c->dalloc(&c->X, CP.xtot));
       TRY(c->dalloc(&c->W, CP.wtot));
       launch_coarse_X(st, nparts, c->P, c->fac, c->dinv, c->scale, work, sig, c->X);

@@ -714,7 +714,7 @@ k_tile_transpose(int64_t ntiles, const double* __restrict__ in, double* __restri
 
 // c_i = X_i^T r(Omega_Ii): r gathered once into LDS (in chunks), one wave per
 // coarse vector.
-constexpr int RCHUNK = 2048;
+constexpr int RCHUNK = 8192;
 template <typename TX>
 __global__ void __launch_bounds__(1024)
 k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
