@@ -167,6 +167,17 @@ __device__ inline void tile_mma_nt(typename Mfma<T>::acc_t acc[4], const T* A, i
 // Orders the LDS accesses of the lanes of one wave: a wave's LDS operations
 // complete in issue order, so wavefront-scope fences around a code-motion
 // barrier suffice.
+// x + x of lane (l xor 32), the same value in both halves of the wave, by
+// two v_permlane32_swap (gfx950): with both operands x, the first result of
+// every lane is x of lane l % 32 and the second x of lane l % 32 + 32.  All
+// lanes of the wave must be active.
+__device__ inline double half_pair_sum(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const auto rlo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rhi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(rhi[0], rlo[0]) + __hiloint2double(rhi[1], rlo[1]);
+}
+
 // Orders this wave's global stores before its later loads by other lanes
 // (workgroup-scope release and acquire).
 __device__ inline void wg_fence() {

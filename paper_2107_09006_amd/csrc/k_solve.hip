@@ -192,9 +192,9 @@ __device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_
 // the forward sweep and column-major in the backward sweep, so that in both
 // lane (a, h) = (l % 32, l / 32) reads 16 consecutive entries with vector
 // loads: forward L(a, 16 h .. 16 h + 15) for row a of L y, backward
-// L(16 h .. 16 h + 15, a) for column a of L^T x.  One shuffle joins the
-// halves h = 0, 1.  Producer and consumer loops execute the same number of
-// block barriers.
+// L(16 h .. 16 h + 15, a) for column a of L^T x.  A swap of the wave's
+// halves joins h = 0, 1.  Producer and consumer loops execute the same
+// number of block barriers.
 // ---------------------------------------------------------------------------
 constexpr int PCAP = 4608;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -401,14 +401,14 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
           double l[16];
           lds_row16(l, rb[s] + a * PLD + 16 * h);
           double r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-          r += __shfl_xor(r, 32, 64);
+          r = half_pair_sum(r);
           if (lane < TS) sv[lane] = ys[I * TS + lane] - r;
           wave_sync();
           double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * sv[16 * h + j];
           double x = (v[0] + v[1]) + (v[2] + v[3]);
-          x += __shfl_xor(x, 32, 64);
+          x = half_pair_sum(x);
           wave_sync();
           if (lane < TS) ys[I * TS + lane] = x;
           wave_sync();
@@ -446,7 +446,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
 #pragma unroll
           for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * ys[I * TS + 16 * h + j];
           double x = (v[0] + v[1]) + (v[2] + v[3]);
-          x += __shfl_xor(x, 32, 64);
+          x = half_pair_sum(x);
           wave_sync();
           if (lane < TS) ys[I * TS + lane] = x;
           wave_sync();
@@ -469,7 +469,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
               x[i] = (v[0] + v[1]) + (v[2] + v[3]);
             }
 #pragma unroll
-            for (int i = 0; i < nb; ++i) x[i] += __shfl_xor(x[i], 32, 64);
+            for (int i = 0; i < nb; ++i) x[i] = half_pair_sum(x[i]);
 #pragma unroll
             for (int i = 0; i < nb; ++i)
               if (lane < TS) ys[(fI + k - u0 - i) * TS + lane] -= x[i];
