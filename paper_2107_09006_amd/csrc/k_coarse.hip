@@ -242,10 +242,12 @@ k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
   const int32_t* rows = xi + d.xi_off;
   const double* Xi = X + d.x_off;
   double* Wi = W + d.w_off;
-  // one thread per row of Xi_i: its entries in Omega_Ii are read once and
-  // kept in registers for all p columns (rows with more than ECAP such
+  // one thread per row of Xi_i (a subdomain's rows spread over gridDim.y
+  // workgroups): its entries in Omega_Ii are read once and kept in registers
+  // for all p columns, four columns at a time (rows with more than ECAP such
   // entries read them again per column)
-  for (int rho = threadIdx.x; rho < d.nXi; rho += blockDim.x) {
+  const int step = gridDim.y * blockDim.x;
+  for (int rho = blockIdx.y * blockDim.x + threadIdx.x; rho < d.nXi; rho += step) {
     const int r = rows[rho];
     double ev[ECAP];
     int ep[ECAP];
@@ -256,14 +258,31 @@ k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
       if (ne < ECAP) { ev[ne] = vals[e]; ep[ne] = locown[c]; }
       ++ne;
     }
+    if (ne <= ECAP) {
+      int k = 0;
+      for (; k + 4 <= d.p; k += 4) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < ECAP; ++q)
+          if (q < ne)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] += ev[q] * Xi[(int64_t)(k + u) * d.nIp + ep[q]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Wi[(int64_t)(k + u) * d.nXi + rho] = s4[u];
+      }
+      for (; k < d.p; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < ECAP; ++q)
+          if (q < ne) s += ev[q] * Xi[(int64_t)k * d.nIp + ep[q]];
+        Wi[(int64_t)k * d.nXi + rho] = s;
+      }
+      continue;
+    }
     for (int k = 0; k < d.p; ++k) {
       const double* xk = Xi + (int64_t)k * d.nIp;
       double s = 0.0;
-      if (ne <= ECAP) {
-#pragma unroll
-        for (int q = 0; q < ECAP; ++q)
-          if (q < ne) s += ev[q] * xk[ep[q]];
-      } else {
+      {
         for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
           const int c = colind[e];
           if (part[c] == i) s += vals[e] * xk[locown[c]];
@@ -883,7 +902,7 @@ void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* f
 
 void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
                      const double* X, double* W) {
-  k_coarse_W<<<nsub, 256, 0, st>>>(P.subs, P.xi, P.part, P.locown, M.rowptr, M.colind, M.vals, X,
+  k_coarse_W<<<dim3(nsub, 16), 256, 0, st>>>(P.subs, P.xi, P.part, P.locown, M.rowptr, M.colind, M.vals, X,
                                    W);
 }
 
