@@ -63,6 +63,9 @@ typedef struct {
   int32_t variant;    /* LSQ2L_ADDITIVE (two-level, default) or LSQ2L_ONE_LEVEL (M_ASM)           */
   int32_t nev_max;    /* keep at most this many coarse vectors per subdomain (0 = no cap)         */
   int32_t check_every;/* read the residual norm back every this many iterations (default 1)       */
+  int32_t use_graph;  /* 1: capture one PCG iteration (SpMVs, dot products, scalar updates, M r)
+                         into a HIP graph per solve call and replay it; results are the same as
+                         without (default 0)                                                    */
 } lsq2l_options;
 
 typedef struct {

@@ -33,7 +33,7 @@ EXPORTS = ["lsq2l_default_options", "lsq2l_setup", "lsq2l_setup_batched", "lsq2l
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_it", C.c_int32), ("precision", C.c_int32),
                 ("flexible", C.c_int32), ("variant", C.c_int32), ("nev_max", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

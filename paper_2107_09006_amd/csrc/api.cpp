@@ -175,6 +175,7 @@ using namespace lsq2l;
 
 struct lsq2l_ctx {
   hipStream_t st = nullptr;
+  hipStream_t gst = nullptr;   // stream the PCG iteration graph is captured on
   lsq2l_options opt{};
   double tau = 0.0;
   int S = 1;
@@ -280,6 +281,7 @@ struct lsq2l_ctx {
   ~lsq2l_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
+    if (gst) (void)hipStreamDestroy(gst);
     for (const DevBlock& b : dev_allocs) block_cache().give(b.p, b.bytes, b.dev);
     for (void* v : host_allocs) (void)hipHostFree(v);
   }
@@ -380,6 +382,48 @@ lsq2l_status read_flags(lsq2l_ctx* c) {
 }
 
 // PCG on C x = rhs (x_0 = 0), C = A^T A applied as A^T (A p).  x is written.
+// One PCG iteration as a HIP graph: both SpMVs, alpha, the x and r update,
+// the residual norm (which sets the per-instance done flags), M r, beta and
+// the direction update, in the order of the loop in pcg().  The graph is
+// captured on an internal stream (the handle's stream may be the null
+// stream) and launched on the handle's stream.  It holds kernel nodes only.
+lsq2l_status capture_iteration(lsq2l_ctx* c, double* x, double tol2, hipGraphExec_t* out) {
+  *out = nullptr;
+  if (!c->gst) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
+  const hipStream_t saved = c->st;
+  const int S = c->S;
+  const int64_t n = c->M.n;
+  const int flexible = c->opt.flexible;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    c->st = c->gst;
+    const hipStream_t st = c->st;
+    spmv_A(c, c->p, c->tm);
+    spmv_AT(c, c->tm, c->q);
+    launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
+    launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
+    if (flexible) launch_copy(st, n, c->r, c->rold);
+    launch_axpy_xr(st, n, S, c->d_seg_col, c->sc.alpha, c->p, c->q, x, c->r);
+    launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
+    launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+    apply_M(c, c->r, c->z);
+    launch_dot(st, S, c->d_seg_col, c->r, c->z, c->partial);
+    if (flexible) launch_dot(st, S, c->d_seg_col, c->rold, c->z, c->partial2);
+    launch_scalar(st, OP_BETA, S, c->partial, flexible ? c->partial2 : nullptr, c->sc, tol2, flexible);
+    launch_xpby(st, n, S, c->d_seg_col, c->sc.beta, c->z, c->p);
+    c->st = saved;
+    e = hipStreamEndCapture(c->gst, &g);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    set_error(std::string("capturing the PCG iteration: ") + hipGetErrorString(e));
+    return LSQ2L_EHIP;
+  }
+  return LSQ2L_OK;
+}
+
 lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, double* relres_true,
                  double* relres_rec) {
   const hipStream_t st = c->st;
@@ -401,6 +445,29 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
     TRY(read_flags(c));
     bool all_done = true;
     for (int s = 0; s < S; ++s) all_done &= (c->h_done[s] != 0);
+    // graph replay: the iteration runs whole (M r and the direction update
+    // after a converged residual norm change neither x nor r)
+    hipGraphExec_t gexec = nullptr;
+    if (c->opt.use_graph && !all_done) TRY(capture_iteration(c, x, tol2, &gexec));
+    while (gexec && !all_done && its < c->opt.max_it) {
+      const hipError_t ge = hipGraphLaunch(gexec, st);
+      if (ge != hipSuccess) {
+        (void)hipGraphExecDestroy(gexec);
+        set_error(std::string("launching the PCG iteration graph: ") + hipGetErrorString(ge));
+        return LSQ2L_EHIP;
+      }
+      ++its;
+      if (its % std::max(1, c->opt.check_every) == 0 || its >= c->opt.max_it) {
+        const lsq2l_status fs = read_flags(c);
+        if (fs != LSQ2L_OK) { (void)hipGraphExecDestroy(gexec); return fs; }
+        all_done = true;
+        for (int s = 0; s < S; ++s) {
+          all_done &= (c->h_done[s] != 0);
+          breakdown |= (c->h_done[s] == 2);
+        }
+      }
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     while (!all_done && its < c->opt.max_it) {
       spmv_A(c, c->p, c->tm);
       spmv_AT(c, c->tm, c->q);
@@ -822,6 +889,7 @@ void lsq2l_default_options(lsq2l_options* opt) {
   opt->variant = LSQ2L_ADDITIVE;
   opt->nev_max = 0;
   opt->check_every = 1;
+  opt->use_graph = 0;
 }
 
 const char* lsq2l_last_error(void) { return g_err.c_str(); }

@@ -208,6 +208,16 @@ __global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
   if (k < n) out[k] = v;
 }
 
+__global__ void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i];
+}
+
+void launch_copy(hipStream_t st, int64_t n, const double* a, double* out) {
+  if (n == 0) return;
+  k_copy<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, out);
+}
+
 void launch_fill(hipStream_t st, int64_t n, double v, double* out) {
   if (n == 0) return;
   k_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, v, out);

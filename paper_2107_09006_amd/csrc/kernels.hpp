@@ -86,6 +86,7 @@ void launch_xpby(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const
                  const double* z, double* p);
 void launch_sub(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_fill(hipStream_t st, int64_t n, double v, double* out);
+void launch_copy(hipStream_t st, int64_t n, const double* a, double* out);
 
 // --- subdomain kernels -------------------------------------------------------
 void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, const double* src,

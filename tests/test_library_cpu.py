@@ -37,7 +37,7 @@ def test_default_options():
     L, lib = _lib()
     o = L.default_options()
     assert o.tol == 1e-8 and o.max_it == 10000 and o.precision == L.FP64
-    assert o.variant == L.ADDITIVE and o.nev_max == 0 and o.check_every == 1
+    assert o.variant == L.ADDITIVE and o.nev_max == 0 and o.check_every == 1 and o.use_graph == 0
 
 
 @pytest.fixture(scope="module")
