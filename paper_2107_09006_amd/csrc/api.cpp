@@ -762,8 +762,24 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
           top.first += it.first;
           std::push_heap(load.begin(), load.end(), cmp);
         }
+        // workgroup w runs on XCD w % 8: lists ordered by their first column
+        // block go to the XCDs in runs, so that blocks close in the triangle
+        // (which read the same factor rows at about the same time) share an
+        // L2
+        std::vector<int> order(nbins);
+        for (int b = 0; b < nbins; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+          const int32_t fx = bins[x].empty() ? INT32_MAX : bins[x][0];
+          const int32_t fy = bins[y].empty() ? INT32_MAX : bins[y][0];
+          return fx < fy;
+        });
+        std::vector<int> slot(nbins);
+        const int G = nbins / 8;
+        for (int k = 0; k < nbins; ++k) slot[k] = (nbins % 8 == 0) ? (k % G) * 8 + k / G : k;
+        std::vector<std::vector<int32_t>> placed(nbins);
+        for (int k = 0; k < nbins; ++k) placed[slot[k]] = bins[order[k]];
         std::vector<int32_t> bptr(1, 0), bcols;
-        for (const auto& bl : bins) {
+        for (const auto& bl : placed) {
           bcols.insert(bcols.end(), bl.begin(), bl.end());
           bptr.push_back((int32_t)bcols.size());
         }
