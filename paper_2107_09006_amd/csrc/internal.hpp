@@ -227,7 +227,12 @@ __device__ inline bool tile_potrf_inv_reg(const double* W, double* L, double* In
   for (int k = 0; k < TS; ++k) {
     double d = lane_bcast(v[k], k);
     if (!(d > 0.0) || !(d < INFINITY)) { ok = false; d = 1.0; }
-    const double invd = 1.0 / d, inv_sd = 1.0 / sqrt(d);
+    // 1 / sqrt(d): hardware estimate refined by two Newton-Raphson steps
+    // r <- r + r (1 - d r^2) / 2 (the error roughly squares each step)
+    double rs = __builtin_amdgcn_rsq(d);
+    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+    const double invd = rs * rs, inv_sd = rs;
     // factor lanes j > k: W(i, j) -= W(i, k) W(k, j) / d; inverse lanes j <= k:
     // Z(i, j) -= W(i, k) Z(k, j) / d; other lanes unchanged
     const bool upd = fac ? (j > k) : (j <= k);

@@ -342,9 +342,10 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
 // trailing update of the previous column, in one launch.
 // - Workgroups below ndiag (panel role) apply column J - 1 to the tiles of
 //   column J themselves: A(J, J) -= L(J, J-1) L(J, J-1)^T, and for their
-//   panel rows A(I, J) -= L(I, J-1) L(J, J-1)^T.  Every such workgroup then
-//   factors and inverts the diagonal tile in registers, and forms ESTEP_WAVES
-//   panel tiles L(I, J) = A(I, J) L_JJ^{-T}, one per wave.  Workgroup 0 keeps
+//   panel rows A(I, J) -= L(I, J-1) L(J, J-1)^T.  In every such workgroup
+//   wave 0 factors and inverts the diagonal tile in registers while the other
+//   waves update their panel tiles, one each; these then form
+//   L(I, J) = A(I, J) L_JJ^{-T}.  Workgroup 0 keeps
 //   L_JJ^{-1}, the only form of the diagonal tile the solves read, so (J, J)
 //   itself is left unchanged.
 // - The other workgroups apply the rest of column J - 1's update, one wave
@@ -352,6 +353,7 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
 // The two roles touch disjoint tiles (column J against columns > J), and
 // every update of column J by columns before J - 1 ran in an earlier launch.
 constexpr int ESTEP_WAVES = 8;
+constexpr int EPANEL = ESTEP_WAVES - 1;    // panel tiles per workgroup (waves 1..)
 
 __global__ void __launch_bounds__(ESTEP_WAVES * 64)
 k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
@@ -382,10 +384,15 @@ k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, i
   }
   const bool prevJ = J > 0 && eF[J] <= J - 1;         // L(J, J-1) is stored
   const double* Ljp = prevJ ? efac + tile_pos(eF, eOff, J, J - 1) * TT : nullptr;
-  const double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
-  for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
-  __syncthreads();
+  // wave 0 factors and inverts the diagonal tile; meanwhile waves 1.. hold
+  // their panel tiles' A(I, J) - L(I, J-1) L(J, J-1)^T in registers
+  const int a = blockIdx.x * EPANEL + wave - 1;
+  const bool mine = wave > 0 && a < nr;
+  const int I = mine ? rows[a] : 0;
   if (wave == 0) {
+    const double* Ajj = efac + tile_pos(eF, eOff, J, J) * TT;
+    for (int e = lane; e < TT; e += 64) sW[(e / TS) * LDT + e % TS] = Ajj[e];
+    wave_sync();
     if (prevJ) {
       tile_acc_load<double>(acc, sW, LDT, lane);
       tile_mma_nt<double, true>(acc, Ljp, TS, Ljp, TS, lane);
@@ -395,23 +402,21 @@ k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, i
     }
     const bool ok = tile_potrf_inv_reg(sW, nullptr, sInv, lane);
     if (!ok && lane == 0 && blockIdx.x == 0) atomicCAS(status, 0, J + 1);
+  } else if (mine) {
+    tile_acc_load<double>(acc, efac + tile_pos(eF, eOff, I, J) * TT, TS, lane);
+    if (prevJ && eF[I] <= J - 1)
+      tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, I, J - 1) * TT, TS, Ljp, TS, lane);
   }
   __syncthreads();
   if (blockIdx.x == 0)
     for (int e = tid; e < TT; e += nthr) edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
-  const int a = blockIdx.x * ESTEP_WAVES + wave;
-  if (a < nr) {
-    const int I = rows[a];
-    double* Aij = efac + tile_pos(eF, eOff, I, J) * TT;
+  if (mine) {
     double* S = sS[wave];
-    tile_acc_load<double>(acc, Aij, TS, lane);
-    if (prevJ && eF[I] <= J - 1)
-      tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, I, J - 1) * TT, TS, Ljp, TS, lane);
     tile_acc_store<double>(acc, S, LDT, lane);
     wave_sync();
     tile_acc_zero<double>(acc);
     tile_mma_nt<double, false>(acc, S, LDT, sInv, LDT, lane);
-    tile_acc_store<double>(acc, Aij, TS, lane);
+    tile_acc_store<double>(acc, efac + tile_pos(eF, eOff, I, J) * TT, TS, lane);
   }
 }
 
@@ -451,17 +456,20 @@ __device__ inline void tile_frag_mma(double4_t acc[4], const TileFrag& f) {
 // written once.
 //
 // The band of already computed tiles that a step needs stays in registers:
-// wave w keeps the EWIN_SLOTS most recent tiles with index = w (mod 4) as MFMA
+// wave w keeps the EWIN_SLOTS most recent tiles with index = w (mod 8) as MFMA
 // B fragments, so a step reads only the tiles of L (shared by all column
-// blocks).  Tiles further back than the window are read from memory.  The
-// wave partials of a step are added in a fixed order.  Each workgroup works
+// blocks).  Tiles further back than the window are read from memory.  Eight
+// waves of at most 256 registers each run two to a SIMD, so one wave's
+// products overlap the other's loads; the first four also form the diagonal
+// products, one 16 x 16 quadrant each.  The wave partials of a step are added
+// in a fixed order.  Each workgroup works
 // through a list of column blocks chosen so that the lists have equal work
 // (the work of block c is proportional to the number of tile rows below c).
 // The backward sweep multiplies by transposed tiles of L; it reads them from
 // a tile-by-tile transposed copy (efacT, edinvT), so that every operand
 // fragment load is a column read.
-constexpr int EINV_WAVES = 4;
-constexpr int EWIN_SLOTS = 6;
+constexpr int EINV_WAVES = 8;
+constexpr int EWIN_SLOTS = 2;
 constexpr int ELIST = EINV_WAVES * 64;      // backward list entries staged in LDS (one per thread)
 
 struct AFrag { double a[2][8]; };
@@ -511,7 +519,8 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
   __shared__ int64_t sEO[ELIST];            // and the tile index of L(I, K)
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid / 64, lane = tid % 64;
-  const int bi = w / 2, bj = w % 2;          // quadrant of the diagonal products
+  const int bi = (w / 2) % 2, bj = w % 2;    // quadrant of the diagonal products
+  const bool dq = w < 4;                     // waves that form the diagonal products
 
   auto put_partial = [&](const double4_t acc[4]) {
 #pragma unroll
@@ -542,7 +551,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
       const int Ig = t0 + I;
       const int K0 = max(eF[Ig] - t0, c);
       double dfr[8];                         // this step's diagonal inverse, loaded under the products
-      quad_afrag(dfr, edinv + (int64_t)Ig * TT, TS, bi, lane);
+      if (dq) quad_afrag(dfr, edinv + (int64_t)Ig * TT, TS, bi, lane);
       double4_t acc[4];
       tile_acc_zero<double>(acc);
       // tiles of this wave evicted from its window (the window holds every
@@ -575,7 +584,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
         sY[col * LDT + row] = v;
       }
       __syncthreads();
-      {
+      if (dq) {
         double4_t y = {0.0, 0.0, 0.0, 0.0};
         quad_mma_pre(y, dfr, sY, LDT, bj, lane);
         quad_store(y, Xc + I * TS, ld, bi, bj, lane);
@@ -621,7 +630,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
     for (int K = nt - 1; K >= c; --K) {
       const int Kg = t0 + K;
       double dfr[8];                         // this step's diagonal inverse, loaded under the products
-      quad_afrag(dfr, edinvT + (int64_t)Kg * TT, TS, bi, lane);
+      if (dq) quad_afrag(dfr, edinvT + (int64_t)Kg * TT, TS, bi, lane);
       // loads whose latency the products hide: this step's tile of Y for the
       // reduction below, and the next step's list (one entry per thread)
       double ypre[TT / (EINV_WAVES * 64)];
@@ -685,7 +694,7 @@ k_einv(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
         sY[col * LDT + row] = v;
       }
       __syncthreads();
-      {
+      if (dq) {
         double4_t x = {0.0, 0.0, 0.0, 0.0};
         quad_mma_pre(x, dfr, sY, LDT, bj, lane);
         quad_store(x, Xc + K * TS, ld, bi, bj, lane);
@@ -916,7 +925,7 @@ void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoar
 void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                        const int32_t* prows, int npr, double* efac, double* edinv,
                        int32_t* status) {
-  const int ndiag = max(1, (nr + ESTEP_WAVES - 1) / ESTEP_WAVES);
+  const int ndiag = max(1, (nr + EPANEL - 1) / EPANEL);
   const int64_t npairs = (int64_t)npr * (npr + 1) / 2;
   const int nupd = (int)((npairs + ESTEP_WAVES - 1) / ESTEP_WAVES);
   k_echol_step<<<ndiag + nupd, ESTEP_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, prows, npr,
