@@ -178,6 +178,13 @@ __device__ inline double half_pair_sum(double x) {
   return __hiloint2double(rhi[0], rlo[0]) + __hiloint2double(rhi[1], rlo[1]);
 }
 
+// The same for a float (one swap).
+__device__ inline float half_pair_sum(float x) {
+  const int v = __float_as_int(x);
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
 // Orders this wave's global stores before its later loads by other lanes
 // (workgroup-scope release and acquire).
 __device__ inline void wg_fence() {

@@ -194,7 +194,9 @@ __device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_
 // loads: forward L(a, 16 h .. 16 h + 15) for row a of L y, backward
 // L(16 h .. 16 h + 15, a) for column a of L^T x.  A swap of the wave's
 // halves joins h = 0, 1.  Producer and consumer loops execute the same
-// number of block barriers.
+// number of block barriers.  The consumer computes in the factor's own type:
+// with the FP32 factor, the sweeps, their partial sums and the local vector
+// held in LDS are FP32 (the result is widened to FP64 on the way out).
 // ---------------------------------------------------------------------------
 constexpr int PCAP = 4608;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -217,9 +219,9 @@ __device__ inline void static_for(Fn&& fn) {
   }
 }
 
-// 16 consecutive LDS entries of a tile, as doubles
-template <typename T>
-__device__ inline void lds_row16(double (&x)[16], const T* p) {
+// 16 consecutive LDS entries of a tile, converted to R
+template <typename T, typename R>
+__device__ inline void lds_row16(R (&x)[16], const T* p) {
   using V = typename PipeCfg<T>::V;                  // 16-byte vector of T
   constexpr int NV = 16 * sizeof(T) / sizeof(V);
 #pragma unroll
@@ -227,7 +229,7 @@ __device__ inline void lds_row16(double (&x)[16], const T* p) {
     const V v = reinterpret_cast<const V*>(p)[c];
     const T* e = reinterpret_cast<const T*>(&v);
 #pragma unroll
-    for (int i = 0; i < 16 / NV; ++i) x[c * (16 / NV) + i] = (double)e[i];
+    for (int i = 0; i < 16 / NV; ++i) x[c * (16 / NV) + i] = (R)e[i];
   }
 }
 
@@ -246,10 +248,10 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
   constexpr int TL = TS * PLD;
   constexpr int PW = (PB + 2) / 3;                   // tiles per producer wave and block
   constexpr int CB = 4;                              // consumer batch of off-diagonal tiles
-  __shared__ double ys[PCAP];
+  __shared__ __align__(16) T ys[PCAP];
   __shared__ __align__(16) T ring[2][PB][TL];
   __shared__ int32_t sF[PCAP / TS], sS[PCAP / TS + 1];
-  __shared__ double sv[TS];
+  __shared__ T sv[TS];
   const SubDesc d = subs[blockIdx.x];
   if (d.np > PCAP) return;
   const int32_t* F = tileF + d.tile_base;
@@ -370,18 +372,18 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
   } else {
     __syncthreads();
     int I = 0, k = 0, fI = nt > 0 ? sF[0] : 0, nk = 0;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    T acc[4] = {0, 0, 0, 0};
     for (int b = 0; b < nblk; ++b) {
       const T (*rb)[TL] = ring[b & 1];
       const int send = min(N - b * PB, PB);
       int s = 0;
       while (s < send && I < nt) {
         const int run = min(nk - k, send - s);
-        const double* yk = ys + (fI + k) * TS + 16 * h;
+        const T* yk = ys + (fI + k) * TS + 16 * h;
         // batches of CB tiles: all LDS reads of a batch issue before its FMAs
         auto fwd_batch = [&](int u0, auto nbc) {
           constexpr int nb = decltype(nbc)::value;
-          double l[nb][16], y[nb][16];
+          T l[nb][16], y[nb][16];
 #pragma unroll
           for (int i = 0; i < nb; ++i) {
             lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
@@ -398,16 +400,16 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
         s += run;
         k += run;
         if (s < send) {                              // the diagonal inverse of row I
-          double l[16];
+          T l[16];
           lds_row16(l, rb[s] + a * PLD + 16 * h);
-          double r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+          T r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
           r = half_pair_sum(r);
           if (lane < TS) sv[lane] = ys[I * TS + lane] - r;
           wave_sync();
-          double v[4] = {0.0, 0.0, 0.0, 0.0};
+          T v[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * sv[16 * h + j];
-          double x = (v[0] + v[1]) + (v[2] + v[3]);
+          T x = (v[0] + v[1]) + (v[2] + v[3]);
           x = half_pair_sum(x);
           wave_sync();
           if (lane < TS) ys[I * TS + lane] = x;
@@ -433,19 +435,19 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
     __syncthreads();
     int I = nt - 1, fI = nt > 0 ? sF[nt - 1] : 0;
     int nk = nt > 0 ? I - fI : 0, k = nk;
-    double xr[16];
+    T xr[16];
     for (int b = 0; b < nblk; ++b) {
       const T (*rb)[TL] = ring[b & 1];
       const int send = min(N - b * PB, PB);
       int s = 0;
       while (s < send) {
         if (k == nk) {
-          double l[16];
+          T l[16];
           lds_row16(l, rb[s] + a * PLD + 16 * h);
-          double v[4] = {0.0, 0.0, 0.0, 0.0};
+          T v[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * ys[I * TS + 16 * h + j];
-          double x = (v[0] + v[1]) + (v[2] + v[3]);
+          T x = (v[0] + v[1]) + (v[2] + v[3]);
           x = half_pair_sum(x);
           wave_sync();
           if (lane < TS) ys[I * TS + lane] = x;
@@ -458,12 +460,12 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
           const int run = min(k + 1, send - s);
           auto bwd_batch = [&](int u0, auto nbc) {
             constexpr int nb = decltype(nbc)::value;
-            double l[nb][16], x[nb];
+            T l[nb][16], x[nb];
 #pragma unroll
             for (int i = 0; i < nb; ++i) lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
 #pragma unroll
             for (int i = 0; i < nb; ++i) {
-              double v[4] = {0.0, 0.0, 0.0, 0.0};
+              T v[4] = {0, 0, 0, 0};
 #pragma unroll
               for (int j = 0; j < 16; ++j) v[j & 3] += l[i][j] * xr[j];
               x[i] = (v[0] + v[1]) + (v[2] + v[3]);
