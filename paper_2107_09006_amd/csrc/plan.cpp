@@ -11,7 +11,6 @@
 #include <climits>
 #include <cstring>
 #include <thread>
-#include <unordered_map>
 
 namespace lsq2l {
 
@@ -339,19 +338,60 @@ bool plan_maps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colin
     }
     P.rsub.resize((size_t)P.rsub_ptr[m]);
     P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
+    // the fill pass also records, per row range, every pair u < v of the
+    // row's list as (i, j, pos in Xi_i, pos in Xi_j), in row order
+    std::vector<std::vector<int32_t>> rec(nthr);
     par([&](unsigned t) {
       std::vector<int32_t> buf((size_t)maxrow + 1);
       int32_t a, b;
       range(t, a, b);
       for (int32_t r = a; r < b; ++r) {
         const int k = row_parts(r, buf.data());
-        int64_t q = P.rsub_ptr[r];
+        const int64_t q0 = P.rsub_ptr[r];
+        int64_t q = q0;
         for (int u = 0; u < k; ++u, ++q) {
           P.rsub[q] = buf[u];
           P.rsub_pos[q] = (int32_t)cnt[t][buf[u]]++;
         }
+        for (int u = 0; u < k; ++u)
+          for (int v = u + 1; v < k; ++v)
+            rec[t].insert(rec[t].end(), {P.rsub[q0 + u], P.rsub[q0 + v], P.rsub_pos[q0 + u],
+                                         P.rsub_pos[q0 + v]});
       }
     });
+    // pair ids in order of first occurrence (ranges in row order), then the
+    // rows of every pair grouped by id
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> adj((size_t)nparts);   // (j, id)
+    std::vector<int32_t> rid;
+    std::vector<int64_t> pcnt;
+    P.cpair_ij.clear();
+    for (unsigned t = 0; t < nthr; ++t)
+      for (size_t e = 0; e < rec[t].size(); e += 4) {
+        const int32_t i = rec[t][e], j = rec[t][e + 1];
+        int32_t id = -1;
+        for (const auto& pr : adj[i])
+          if (pr.first == j) { id = pr.second; break; }
+        if (id < 0) {
+          id = (int32_t)pcnt.size();
+          adj[i].push_back({j, id});
+          P.cpair_ij.push_back(i);
+          P.cpair_ij.push_back(j);
+          pcnt.push_back(0);
+        }
+        ++pcnt[id];
+        rid.push_back(id);
+      }
+    P.cpair_ptr.assign(pcnt.size() + 1, 0);
+    for (size_t k = 0; k < pcnt.size(); ++k) P.cpair_ptr[k + 1] = P.cpair_ptr[k] + pcnt[k];
+    P.cpair_rows.resize((size_t)(2 * P.cpair_ptr.back()));
+    std::vector<int64_t> cur(P.cpair_ptr.begin(), P.cpair_ptr.end() - 1);
+    size_t x = 0;
+    for (unsigned t = 0; t < nthr; ++t)
+      for (size_t e = 0; e < rec[t].size(); e += 4, ++x) {
+        const int64_t at = cur[rid[x]]++;
+        P.cpair_rows[2 * at] = rec[t][e + 2];
+        P.cpair_rows[2 * at + 1] = rec[t][e + 3];
+      }
   }
   return true;
 }
@@ -392,42 +432,18 @@ void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& ph, 
   C.xtot = xoff;
   C.wtot = woff;
   C.einv_tot = einv_off;
-  // pairs of subdomains with p > 0 that share rows; diagonal pairs use all of Xi_i
-  std::unordered_map<int64_t, int> pid;
-  std::vector<std::vector<int32_t>> prow;
+  // pairs of subdomains with p > 0 that share rows (diagonal pairs first,
+  // using all of Xi_i; then the sharing pairs in order of first occurrence)
   C.pairs.clear();
-  for (int i = 0; i < nparts; ++i)
-    if (ph[i] > 0) {
-      pid[(int64_t)i * nparts + i] = (int)C.pairs.size();
-      C.pairs.push_back(PairDesc{i, i, H.subs[i].nXi, 0, 0});
-      prow.emplace_back();
-    }
-  for (int32_t r = 0; r < m; ++r) {
-    const int64_t a0 = H.rsub_ptr[r], a1 = H.rsub_ptr[r + 1];
-    for (int64_t a = a0; a < a1; ++a)
-      for (int64_t b = a + 1; b < a1; ++b) {
-        const int i = H.rsub[a], j = H.rsub[b];   // i < j: lists follow subdomain order
-        if (ph[i] == 0 || ph[j] == 0) continue;
-        const int64_t key = (int64_t)i * nparts + j;
-        auto it = pid.find(key);
-        int id;
-        if (it == pid.end()) {
-          id = (int)C.pairs.size();
-          pid[key] = id;
-          C.pairs.push_back(PairDesc{i, j, 0, 0, 0});
-          prow.emplace_back();
-        } else {
-          id = it->second;
-        }
-        prow[id].push_back(H.rsub_pos[a]);
-        prow[id].push_back(H.rsub_pos[b]);
-      }
-  }
   C.pair_rows.clear();
-  for (size_t k = 0; k < C.pairs.size(); ++k) {
-    if (C.pairs[k].i != C.pairs[k].j) C.pairs[k].nrows = (int32_t)(prow[k].size() / 2);
-    C.pairs[k].rows_off = (int64_t)C.pair_rows.size() / 2;
-    C.pair_rows.insert(C.pair_rows.end(), prow[k].begin(), prow[k].end());
+  for (int i = 0; i < nparts; ++i)
+    if (ph[i] > 0) C.pairs.push_back(PairDesc{i, i, H.subs[i].nXi, 0, 0});
+  for (size_t k = 0; k + 1 < H.cpair_ptr.size(); ++k) {
+    const int i = H.cpair_ij[2 * k], j = H.cpair_ij[2 * k + 1];
+    if (ph[i] == 0 || ph[j] == 0) continue;
+    const int64_t r0 = H.cpair_ptr[k], r1 = H.cpair_ptr[k + 1];
+    C.pairs.push_back(PairDesc{i, j, (int32_t)(r1 - r0), 0, (int64_t)C.pair_rows.size() / 2});
+    C.pair_rows.insert(C.pair_rows.end(), H.cpair_rows.begin() + 2 * r0, H.cpair_rows.begin() + 2 * r1);
   }
   // E assembly work items: 32 x 32 output blocks of every pair (lower blocks
   // only for diagonal pairs)

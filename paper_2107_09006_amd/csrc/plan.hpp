@@ -20,6 +20,11 @@ struct HostPlan {
   std::vector<int32_t> own_pos;  // local-buffer positions holding each column
   std::vector<int64_t> rsub_ptr; // for each row: subdomains whose Xi holds it
   std::vector<int32_t> rsub, rsub_pos;
+  // pairs i < j of subdomains whose Xi share rows, in order of first
+  // occurrence (by row, then by position in the row's list), with the shared
+  // rows of pair k at cpair_rows[2 cpair_ptr[k] ..] as (pos in Xi_i, pos in Xi_j)
+  std::vector<int32_t> cpair_ij, cpair_rows;
+  std::vector<int64_t> cpair_ptr;
   int64_t total_loc = 0, total_tiles = 0, total_fac = 0, total_dinv = 0, total_g = 0;
 };
 
@@ -37,7 +42,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
 
 // Overlap maps of a built plan: for every column the local positions holding
 // it (own_ptr / own_pos), for every row the subdomains whose Xi holds it and
-// its rank there (rsub_*).  Reads the rest of P only, so it may run while the
+// its rank there (rsub_*), and the pairs of subdomains sharing rows (cpair_*).  Reads the rest of P only, so it may run while the
 // device works on the built part.
 bool plan_maps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
                const int32_t* part, HostPlan& P, std::string& err);
