@@ -109,34 +109,58 @@ __device__ inline int sturm_below(const double* d, const double* e, int n, doubl
 }
 
 // Solve (T - lam I) x = b (b overwritten by x) with Gaussian elimination and
-// row interchanges; a, up, u2 are scratch of length n.
-__device__ void tri_solve(const double* d, const double* e, int n, double lam, double tiny, double* b,
-                          double* a, double* up, double* u2) {
-  for (int i = 0; i < n; ++i) { a[i] = d[i] - lam; u2[i] = 0.0; }
-  for (int i = 0; i + 1 < n; ++i) up[i] = e[i];
+// row interchanges; a, up, u2 are scratch of length n.  The elimination
+// carries the entries of rows i and i + 1 it updates in registers and only
+// stores the finished row i, so no step reads back what the previous one
+// wrote; the back substitution reads the stored rows.
+__device__ void tri_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
+                          double lam, double tiny, double* __restrict__ b, double* __restrict__ a,
+                          double* __restrict__ up, double* __restrict__ u2) {
+  // row i: diagonal ai, superdiagonal upi, right-hand side bi; row i + 1:
+  // diagonal an, superdiagonal upn, right-hand side bn
+  double ai = d[0] - lam, upi = n > 1 ? e[0] : 0.0, bi = b[0];
   for (int i = 0; i + 1 < n; ++i) {
     const double lo = e[i];
-    if (fabs(a[i]) >= fabs(lo)) {
-      if (a[i] == 0.0) a[i] = tiny;
-      const double mlt = lo / a[i];
-      a[i + 1] -= mlt * up[i];
-      b[i + 1] -= mlt * b[i];
+    double an = d[i + 1] - lam, upn = i + 2 < n ? e[i + 1] : 0.0, bn = b[i + 1];
+    double u2i = 0.0;
+    if (fabs(ai) >= fabs(lo)) {
+      if (ai == 0.0) ai = tiny;
+      const double mlt = lo / ai;
+      an -= mlt * upi;
+      bn -= mlt * bi;
     } else {
-      const double mlt = a[i] / lo;
-      a[i] = lo;
-      const double t = a[i + 1];
-      a[i + 1] = up[i] - mlt * t;
-      if (i + 2 < n) { u2[i] = up[i + 1]; up[i + 1] = -mlt * u2[i]; }
-      up[i] = t;
-      const double bi = b[i];
-      b[i] = b[i + 1];
-      b[i + 1] = bi - mlt * b[i + 1];
+      const double mlt = ai / lo;
+      ai = lo;
+      const double t = an;
+      an = upi - mlt * t;
+      if (i + 2 < n) { u2i = upn; upn = -mlt * u2i; }
+      upi = t;
+      const double bo = bi;
+      bi = bn;
+      bn = bo - mlt * bn;
     }
+    a[i] = ai;
+    up[i] = upi;
+    u2[i] = u2i;
+    b[i] = bi;
+    ai = an;
+    upi = upn;
+    bi = bn;
   }
-  if (a[n - 1] == 0.0) a[n - 1] = tiny;
-  b[n - 1] = b[n - 1] / a[n - 1];
-  if (n >= 2) b[n - 2] = (b[n - 2] - up[n - 2] * b[n - 1]) / a[n - 2];
-  for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - up[i] * b[i + 1] - u2[i] * b[i + 2]) / a[i];
+  if (ai == 0.0) ai = tiny;
+  double x1 = bi / ai, x2 = 0.0;             // x(i + 1), x(i + 2)
+  b[n - 1] = x1;
+  if (n >= 2) {
+    x2 = x1;
+    x1 = (b[n - 2] - up[n - 2] * x2) / a[n - 2];
+    b[n - 2] = x1;
+  }
+  for (int i = n - 3; i >= 0; --i) {
+    const double x = (b[i] - up[i] * x1 - u2[i] * x2) / a[i];
+    b[i] = x;
+    x2 = x1;
+    x1 = x;
+  }
 }
 
 // ----------------------------------------------------------------------------
