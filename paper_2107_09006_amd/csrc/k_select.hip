@@ -212,6 +212,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       sD2[SEL_MAXN], slam[SEL_MAXN];
   __shared__ int sperm[SEL_MAXN], scl[SEL_MAXN + 1];
   __shared__ double spart[4][SEL_MAXN];
+  __shared__ double svp[SEL_MAXN], swp[SEL_MAXN];   // the previous reflector's v and w
   __shared__ double sred[16];
   __shared__ int sredi[16];
   __shared__ int s_r, s_p, s_nclus, s_diag;
@@ -385,39 +386,64 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     __syncthreads();
   }
 
-  // ---- 3. tridiagonalization of K (r x r) in M0
+  // ---- 3. tridiagonalization of K (r x r) in M0.  Step k reflects column k
+  // (v, tk) and updates the trailing block, A22 -= v w^T + w v^T with
+  // w = tk A22 v - (tk^2 / 2) (v^T A22 v) v.  The update of step k is applied
+  // during the pass of step k + 1 that forms A22 v there, so each step reads
+  // and writes the trailing block once; column k + 1, which the next reflector
+  // needs first, takes the pending update on its own.  Every entry receives
+  // the same operations in the same order as with the update as a pass of its
+  // own.
+  bool pend = false;                      // svp, swp hold an update not yet applied
   for (int k = 0; k + 2 < r; ++k) {
     const int m = r - k - 1;
+    // column k (rows k .. r-1) with the pending update of step k - 1, whose
+    // block starts at row k (local index i - k), into sw
+    for (int a = tid; a <= m; a += nthr) {
+      double x = M0[(int64_t)k * ld + k + a];
+      if (pend) x -= svp[a] * swp[0] + swp[a] * svp[0];
+      sw[a] = x;
+    }
+    __syncthreads();
     double part = 0.0;
-    for (int a = 1 + tid; a < m; a += nthr) { const double t = M0[(int64_t)k * ld + k + 1 + a]; part += t * t; }
+    for (int a = 1 + tid; a < m; a += nthr) { const double t = sw[1 + a]; part += t * t; }
     const double xn2 = wg_sum(part, sred);
-    const double alpha = M0[(int64_t)k * ld + k + 1];
+    const double alpha = sw[1];
     double tk = 0.0, beta = alpha;
     if (xn2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
       tk = (beta - alpha) / beta;
       const double sc = 1.0 / (alpha - beta);
-      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : M0[(int64_t)k * ld + k + 1 + a] * sc;
+      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : sw[1 + a] * sc;
     } else {
       for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (tid == 0) { se[k] = beta; sd[k] = M0[(int64_t)k * ld + k]; stau[k] = tk; }
+    if (tid == 0) { se[k] = beta; sd[k] = sw[0]; stau[k] = tk; }
     for (int a = 1 + tid; a < m; a += nthr) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
-    if (tk != 0.0) {
-      // w = tk A22 v: four thread groups split the columns of A22, their
-      // partial sums are added in a fixed order
-      {
-        const int g = tid / 256, t256 = tid % 256;
-        for (int a0 = 0; a0 < m; a0 += 256) {
-          const int a = a0 + t256;
-          double s = 0.0;
-          if (a < m)
-            for (int b = g; b < m; b += 4) s += M0[(int64_t)(k + 1 + b) * ld + k + 1 + a] * sv[b];
-          if (a < m) spart[g][a] = s;
-        }
+    if (tk != 0.0 || pend) {
+      // one pass over A22 (rows and columns k + 1 ..): the pending update,
+      // then w = tk A22 v from four thread groups splitting the columns,
+      // their partial sums added in a fixed order
+      const int g = tid / 256, t256 = tid % 256;
+      for (int a0 = 0; a0 < m; a0 += 256) {
+        const int a = a0 + t256;
+        double acc = 0.0;
+        if (a < m)
+          for (int b = g; b < m; b += 4) {
+            double* e = M0 + (int64_t)(k + 1 + b) * ld + k + 1 + a;
+            double x = *e;
+            if (pend) {
+              x -= svp[a + 1] * swp[b + 1] + swp[a + 1] * svp[b + 1];
+              *e = x;
+            }
+            acc += x * sv[b];
+          }
+        if (a < m) spart[g][a] = acc;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (tk != 0.0) {
       double pp = 0.0;
       for (int a = tid; a < m; a += nthr) {
         sw[a] = tk * (((spart[0][a] + spart[1][a]) + spart[2][a]) + spart[3][a]);
@@ -425,15 +451,20 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       }
       const double wv = wg_sum(pp, sred);
       const double a2 = -0.5 * tk * wv;
-      for (int a = tid; a < m; a += nthr) sw[a] += a2 * sv[a];
-      __syncthreads();
-      for (int64_t q = tid; q < (int64_t)m * m; q += nthr) {
-        const int a = (int)(q % m), b = (int)(q / m);
-        M0[(int64_t)(k + 1 + b) * ld + k + 1 + a] -= sv[a] * sw[b] + sw[a] * sv[b];
+      for (int a = tid; a < m; a += nthr) {
+        swp[a] = sw[a] + a2 * sv[a];
+        svp[a] = sv[a];
       }
     }
+    pend = tk != 0.0;
     __syncthreads();
   }
+  if (pend && tid == 0) {                 // the last update reaches rows r-2, r-1
+    for (int b = 0; b < 2; ++b)
+      for (int a = b; a < 2; ++a)
+        M0[(int64_t)(r - 2 + b) * ld + r - 2 + a] -= svp[a] * swp[b] + swp[a] * svp[b];
+  }
+  __syncthreads();
   if (tid == 0) {
     if (r >= 2) { se[r - 2] = M0[(int64_t)(r - 2) * ld + r - 1]; sd[r - 2] = M0[(int64_t)(r - 2) * ld + r - 2]; }
     sd[r - 1] = M0[(int64_t)(r - 1) * ld + r - 1];
