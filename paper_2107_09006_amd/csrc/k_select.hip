@@ -266,7 +266,9 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     __syncthreads();
   } else {
     // pivoted Cholesky of M0 with symmetric row/column interchanges; row k of
-    // the upper triangle receives row k of R, sperm the pivot order
+    // the upper triangle receives row k of R, sperm the pivot order.  Only the
+    // upper triangle is kept up to date (the trailing block is symmetric, and
+    // R and every later read lie in the upper triangle)
     for (int a = tid; a < n; a += nthr) sperm[a] = a;
     __syncthreads();
     const double tol = n * SEL_EPS;     // the scaled matrix has unit diagonal
@@ -283,16 +285,21 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       wg_argmax(bv, bi, sred, sredi, &mv, &mj);
       if (!(mv > tol)) break;
       if (mj != k) {
+        // interchange k and mj (k < mj) in the upper triangle: columns k and
+        // mj of the rows of R above k; in the trailing block the diagonal
+        // entries, (k, q) with (q, mj) for k < q < mj, and (k, q) with
+        // (mj, q) for q > mj ((k, mj) stays).  The pairs are disjoint.
         for (int q = tid; q < n; q += nthr) {
-          const double t = M0[(int64_t)k * ld + q];
-          M0[(int64_t)k * ld + q] = M0[(int64_t)mj * ld + q];
-          M0[(int64_t)mj * ld + q] = t;
-        }
-        __syncthreads();
-        for (int q = tid; q < n; q += nthr) {
-          const double t = M0[(int64_t)q * ld + k];
-          M0[(int64_t)q * ld + k] = M0[(int64_t)q * ld + mj];
-          M0[(int64_t)q * ld + mj] = t;
+          int64_t x = -1, y = -1;
+          if (q < k) { x = (int64_t)k * ld + q; y = (int64_t)mj * ld + q; }
+          else if (q == k) { x = (int64_t)k * ld + k; y = (int64_t)mj * ld + mj; }
+          else if (q < mj) { x = (int64_t)q * ld + k; y = (int64_t)mj * ld + q; }
+          else if (q > mj) { x = (int64_t)q * ld + k; y = (int64_t)q * ld + mj; }
+          if (x >= 0) {
+            const double t = M0[x];
+            M0[x] = M0[y];
+            M0[y] = t;
+          }
         }
         if (tid == 0) { const int t = sperm[k]; sperm[k] = sperm[mj]; sperm[mj] = t; }
         __syncthreads();
@@ -308,7 +315,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       const int rem = n - k - 1;
       for (int64_t q = tid; q < (int64_t)rem * rem; q += nthr) {
         const int a = k + 1 + (int)(q % rem), b = k + 1 + (int)(q / rem);
-        M0[(int64_t)b * ld + a] -= sv[a] * sv[b];
+        if (a <= b) M0[(int64_t)b * ld + a] -= sv[a] * sv[b];
       }
       __syncthreads();
     }
