@@ -108,44 +108,55 @@ __device__ inline int sturm_below(const double* d, const double* e, int n, doubl
   return cnt;
 }
 
-// Solve (T - lam I) x = b (b overwritten by x) with Gaussian elimination and
-// row interchanges; a, up, u2 are scratch of length n.  The elimination
+// Solve (T - lam I) x = sc b (b overwritten by x) with Gaussian elimination
+// and row interchanges; a, up, u2 are scratch of length n.  The elimination
 // carries the entries of rows i and i + 1 it updates in registers and only
 // stores the finished row i, so no step reads back what the previous one
-// wrote; the back substitution reads the stored rows.
+// wrote; the back substitution reads the stored rows.  Both sweeps load
+// their operands TRI_CH rows at a time ahead of the dependent steps.
+constexpr int TRI_CH = 8;
 __device__ void tri_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
-                          double lam, double tiny, double* __restrict__ b, double* __restrict__ a,
-                          double* __restrict__ up, double* __restrict__ u2) {
+                          double lam, double tiny, double sc, double* __restrict__ b,
+                          double* __restrict__ a, double* __restrict__ up,
+                          double* __restrict__ u2) {
   // row i: diagonal ai, superdiagonal upi, right-hand side bi; row i + 1:
   // diagonal an, superdiagonal upn, right-hand side bn
-  double ai = d[0] - lam, upi = n > 1 ? e[0] : 0.0, bi = b[0];
-  for (int i = 0; i + 1 < n; ++i) {
-    const double lo = e[i];
-    double an = d[i + 1] - lam, upn = i + 2 < n ? e[i + 1] : 0.0, bn = b[i + 1];
-    double u2i = 0.0;
-    if (fabs(ai) >= fabs(lo)) {
-      if (ai == 0.0) ai = tiny;
-      const double mlt = lo / ai;
-      an -= mlt * upi;
-      bn -= mlt * bi;
-    } else {
-      const double mlt = ai / lo;
-      ai = lo;
-      const double t = an;
-      an = upi - mlt * t;
-      if (i + 2 < n) { u2i = upn; upn = -mlt * u2i; }
-      upi = t;
-      const double bo = bi;
+  double ai = d[0] - lam, upi = n > 1 ? e[0] : 0.0, bi = b[0] * sc;
+  for (int i0 = 0; i0 + 1 < n; i0 += TRI_CH) {
+    double bq[TRI_CH];
+#pragma unroll
+    for (int u = 0; u < TRI_CH; ++u) bq[u] = i0 + 1 + u < n ? b[i0 + 1 + u] * sc : 0.0;
+#pragma unroll
+    for (int u = 0; u < TRI_CH; ++u) {
+      const int i = i0 + u;
+      if (i + 1 >= n) break;
+      const double lo = e[i];
+      double an = d[i + 1] - lam, upn = i + 2 < n ? e[i + 1] : 0.0, bn = bq[u];
+      double u2i = 0.0;
+      if (fabs(ai) >= fabs(lo)) {
+        if (ai == 0.0) ai = tiny;
+        const double mlt = lo / ai;
+        an -= mlt * upi;
+        bn -= mlt * bi;
+      } else {
+        const double mlt = ai / lo;
+        ai = lo;
+        const double t = an;
+        an = upi - mlt * t;
+        if (i + 2 < n) { u2i = upn; upn = -mlt * u2i; }
+        upi = t;
+        const double bo = bi;
+        bi = bn;
+        bn = bo - mlt * bn;
+      }
+      a[i] = ai;
+      up[i] = upi;
+      u2[i] = u2i;
+      b[i] = bi;
+      ai = an;
+      upi = upn;
       bi = bn;
-      bn = bo - mlt * bn;
     }
-    a[i] = ai;
-    up[i] = upi;
-    u2[i] = u2i;
-    b[i] = bi;
-    ai = an;
-    upi = upn;
-    bi = bn;
   }
   if (ai == 0.0) ai = tiny;
   double x1 = bi / ai, x2 = 0.0;             // x(i + 1), x(i + 2)
@@ -155,11 +166,25 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
     x1 = (b[n - 2] - up[n - 2] * x2) / a[n - 2];
     b[n - 2] = x1;
   }
-  for (int i = n - 3; i >= 0; --i) {
-    const double x = (b[i] - up[i] * x1 - u2[i] * x2) / a[i];
-    b[i] = x;
-    x2 = x1;
-    x1 = x;
+  for (int i0 = n - 3; i0 >= 0; i0 -= TRI_CH) {
+    double aq[TRI_CH], uq[TRI_CH], vq[TRI_CH], bq[TRI_CH];
+#pragma unroll
+    for (int u = 0; u < TRI_CH; ++u) {
+      const int i = i0 - u;
+      aq[u] = i >= 0 ? a[i] : 1.0;
+      uq[u] = i >= 0 ? up[i] : 0.0;
+      vq[u] = i >= 0 ? u2[i] : 0.0;
+      bq[u] = i >= 0 ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < TRI_CH; ++u) {
+      const int i = i0 - u;
+      if (i < 0) break;
+      const double x = (bq[u] - uq[u] * x1 - vq[u] * x2) / aq[u];
+      b[i] = x;
+      x2 = x1;
+      x1 = x;
+    }
   }
 }
 
@@ -515,9 +540,13 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     slam[j] = 0.5 * (lo + hi);
   }
   __syncthreads();
-  // clusters of close eigenvalues (descending order); separate equal ones
+  // clusters of close eigenvalues (descending order); separate equal ones.
+  // Inverse iteration with a shift accurate to rounding leaves a vector off
+  // its eigenvector by about eps ||T|| / gap, so vectors whose eigenvalues
+  // are more than 1e-6 ||T|| apart come out orthogonal to about 1e-10
+  // without re-orthogonalisation; only closer ones form a cluster.
   if (tid == 0) {
-    const double ortol = 1e-3 * anorm, sep = 10.0 * SEL_EPS * anorm;
+    const double ortol = 1e-6 * anorm, sep = 10.0 * SEL_EPS * anorm;
     int nc = 0;
     for (int j = 0; j < p; ++j) {
       if (j > 0 && fabs(slam[j - 1] - slam[j]) < sep) slam[j] = slam[j - 1] - sep;
@@ -549,10 +578,17 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       double* x = M1 + (int64_t)j * ld;
       double* scr = M3 + (int64_t)tid * 3 * r;
       double nr = 0.0;
-      for (int q = 0; q < r; ++q) nr += x[q] * x[q];
+      for (int q0 = 0; q0 < r; q0 += TRI_CH) {
+        double xq[TRI_CH];
+#pragma unroll
+        for (int u = 0; u < TRI_CH; ++u) xq[u] = q0 + u < r ? x[q0 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TRI_CH; ++u)
+          if (q0 + u < r) nr += xq[u] * xq[u];
+      }
       nr = 1.0 / sqrt(nr);
-      for (int q = 0; q < r; ++q) x[q] *= nr;
-      tri_solve(sd, se, r, slam[j], tiny, x, scr, scr + r, scr + 2 * r);
+      // the solve scales its right-hand side by nr as it reads it
+      tri_solve(sd, se, r, slam[j], tiny, nr, x, scr, scr + r, scr + 2 * r);
     }
     __syncthreads();
     if (sweep < 2) continue;
