@@ -114,7 +114,7 @@ __device__ inline int sturm_below(const double* d, const double* e, int n, doubl
 // stores the finished row i, so no step reads back what the previous one
 // wrote; the back substitution reads the stored rows.  Both sweeps load
 // their operands TRI_CH rows at a time ahead of the dependent steps.
-constexpr int TRI_CH = 8;
+constexpr int TRI_CH = 4;
 __device__ void tri_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
                           double lam, double tiny, double sc, double* __restrict__ b,
                           double* __restrict__ a, double* __restrict__ up,
@@ -636,22 +636,46 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     M1[(int64_t)j * ld + row] = 0.0;
   }
   __syncthreads();
-  // back-transformation U = H_0 ... H_{r-3} Z
-  for (int k = r - 3; k >= 0; --k) {
-    const double tk = stau[k];
-    if (tk == 0.0) continue;
-    const int m = r - k - 1;
-    for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : M0[(int64_t)k * ld + k + 1 + a];
-    __syncthreads();
-    for (int j = wave; j < p; j += nw) {
-      double* x = M1 + (int64_t)j * ld + k + 1;
-      double s = 0.0;
-      for (int a = lane; a < m; a += 64) s += sv[a] * x[a];
-      for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
-      for (int a = lane; a < m; a += 64) x[a] -= tk * s * sv[a];
+  // back-transformation U = H_0 ... H_{r-3} Z.  The vectors are independent,
+  // so each wave takes up to BT_VEC of them (j = wave, wave + nw, ...) through
+  // all the reflectors without block barriers; a reflector (v(0) = 1, the rest
+  // stored in column k of M0) is read straight from memory.
+  {
+    constexpr int BT_VEC = 4;
+    for (int jb = wave; jb < p; jb += nw * BT_VEC) {
+      const int ng = min(BT_VEC, (p - jb + nw - 1) / nw);   // vectors jb + g nw, g < ng
+      double* x0 = M1 + (int64_t)jb * ld;
+      const int64_t js = (int64_t)nw * ld;
+      for (int k = r - 3; k >= 0; --k) {
+        const double tk = stau[k];
+        if (tk == 0.0) continue;
+        const int m = r - k - 1;
+        const double* vk = M0 + (int64_t)k * ld + k + 1;
+        double* xk = x0 + k + 1;
+        double sg[BT_VEC];
+#pragma unroll
+        for (int g = 0; g < BT_VEC; ++g) sg[g] = 0.0;
+#pragma unroll 1
+        for (int a = lane; a < m; a += 64) {
+          const double va = a == 0 ? 1.0 : vk[a];
+#pragma unroll
+          for (int g = 0; g < BT_VEC; ++g)
+            if (g < ng) sg[g] += va * xk[g * js + a];
+        }
+#pragma unroll
+        for (int g = 0; g < BT_VEC; ++g)
+          for (int w = 32; w > 0; w >>= 1) sg[g] += __shfl_xor(sg[g], w, 64);
+#pragma unroll 1
+        for (int a = lane; a < m; a += 64) {
+          const double va = a == 0 ? 1.0 : vk[a];
+#pragma unroll
+          for (int g = 0; g < BT_VEC; ++g)
+            if (g < ng) xk[g * js + a] -= tk * sg[g] * va;
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // ---- 6. Y = W U into M0 (n x p, padding rows zero), sigma
   // (general case: row sperm[a] of Y is D2 (R11^{-1} U)(a, :) for a < r, else 0)
