@@ -33,10 +33,33 @@ constexpr int SEL_MAXN = 1024;
 constexpr double SEL_EPS = 2.220446049250313e-16;
 
 // ----------------------------------------------------------------------------
-// block-wide reductions (shuffles inside a wave, one LDS round across waves)
+// block-wide reductions (a wave sum, one LDS round across waves)
 // ----------------------------------------------------------------------------
+// x + x of the lane whose index differs by the DPP pattern CTRL
+template <int CTRL>
+__device__ inline double dpp_pair_sum(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return x + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane: lane pairs within
+// quads (DPP quad permutations 1032 and 2301), the two quads of each group of
+// eight (row half mirror), the two halves of each row of 16 (row mirror),
+// rows 0, 1 and 2, 3 (one cross-lane read), then the halves of the wave.
+// Each step adds two values that the partner lane adds in the other order,
+// so every lane ends with the same bits.
+__device__ inline double wave_allsum(double x) {
+  x = dpp_pair_sum<0xB1>(x);
+  x = dpp_pair_sum<0x4E>(x);
+  x = dpp_pair_sum<0x141>(x);
+  x = dpp_pair_sum<0x140>(x);
+  x += __shfl_xor(x, 16, 64);
+  return half_pair_sum(x);
+}
+
 __device__ inline double wg_sum(double v, double* red) {
-  for (int w = 32; w > 0; w >>= 1) v += __shfl_down(v, w, 64);
+  v = wave_allsum(v);
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
   __syncthreads();
   if (lane == 0) red[wave] = v;
@@ -597,7 +620,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       double* x = M1 + (int64_t)j * ld;
       double nr = 0.0;
       for (int q = lane; q < r; q += 64) nr += x[q] * x[q];
-      for (int w = 32; w > 0; w >>= 1) nr += __shfl_xor(nr, w, 64);
+      nr = wave_allsum(nr);
       nr = 1.0 / sqrt(nr);
       for (int q = lane; q < r; q += 64) x[q] *= nr;
     }
@@ -612,7 +635,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
             const double* y = M1 + (int64_t)jj * ld;
             double dp = 0.0;
             for (int q = lane; q < r; q += 64) dp += y[q] * x[q];
-            for (int w = 32; w > 0; w >>= 1) dp += __shfl_xor(dp, w, 64);
+            dp = wave_allsum(dp);
             if (lane == 0) sw[jj - j0] = dp;
           }
           __syncthreads();
@@ -637,40 +660,102 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   }
   __syncthreads();
   // back-transformation U = H_0 ... H_{r-3} Z.  The vectors are independent,
-  // so each wave takes up to BT_VEC of them (j = wave, wave + nw, ...) through
-  // all the reflectors without block barriers; a reflector (v(0) = 1, the rest
-  // stored in column k of M0) is read straight from memory.
+  // so each wave takes its own (j = wave, wave + nw, ...) through all the
+  // reflectors without block barriers; a reflector (v(0) = 1, the rest stored
+  // in column k of M0) is read straight from memory.  With r <= 256 a wave
+  // holds BT_REG_V of its vectors in registers (lane l: rows l, l + 64, ...)
+  // for a whole sweep over the reflectors; otherwise each reflector updates
+  // them in memory, BT_VEC at a time.
   {
-    constexpr int BT_VEC = 4;
-    for (int jb = wave; jb < p; jb += nw * BT_VEC) {
-      const int ng = min(BT_VEC, (p - jb + nw - 1) / nw);   // vectors jb + g nw, g < ng
-      double* x0 = M1 + (int64_t)jb * ld;
-      const int64_t js = (int64_t)nw * ld;
-      for (int k = r - 3; k >= 0; --k) {
-        const double tk = stau[k];
-        if (tk == 0.0) continue;
-        const int m = r - k - 1;
-        const double* vk = M0 + (int64_t)k * ld + k + 1;
-        double* xk = x0 + k + 1;
-        double sg[BT_VEC];
+    constexpr int BT_REG_V = 4, BT_VEC = 4;
+    if (r <= 256) {
+      for (int jb = wave; jb < p; jb += nw * BT_REG_V) {
+        const int nv = min(BT_REG_V, (p - jb + nw - 1) / nw);   // vectors jb + g nw, g < nv
+        double z[BT_REG_V][4];
 #pragma unroll
-        for (int g = 0; g < BT_VEC; ++g) sg[g] = 0.0;
-#pragma unroll 1
-        for (int a = lane; a < m; a += 64) {
-          const double va = a == 0 ? 1.0 : vk[a];
+        for (int g = 0; g < BT_REG_V; ++g)
 #pragma unroll
-          for (int g = 0; g < BT_VEC; ++g)
-            if (g < ng) sg[g] += va * xk[g * js + a];
+          for (int i = 0; i < 4; ++i) {
+            const int q = lane + 64 * i;
+            z[g][i] = 0.0;
+            if (g < nv && q < r) z[g][i] = M1[(int64_t)(jb + g * nw) * ld + q];
+          }
+        // reflector k in v, the next one (k - 1) loading under the products
+        auto load_v = [&](int k, double (&v)[4]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int q = lane + 64 * i;
+            v[i] = q == k + 1 ? 1.0 : 0.0;
+            if (q > k + 1 && q < r) v[i] = M0[(int64_t)k * ld + q];
+          }
+        };
+        double v[4];
+        if (r >= 3) load_v(r - 3, v);
+        for (int k = r - 3; k >= 0; --k) {
+          double vn[4] = {0.0, 0.0, 0.0, 0.0};
+          if (k > 0) load_v(k - 1, vn);
+          const double tk = stau[k];
+          if (tk == 0.0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = vn[i];
+            continue;
+          }
+          double sg[BT_REG_V];
+#pragma unroll
+          for (int g = 0; g < BT_REG_V; ++g) {
+            sg[g] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sg[g] += v[i] * z[g][i];
+          }
+#pragma unroll
+          for (int g = 0; g < BT_REG_V; ++g)
+            sg[g] = wave_allsum(sg[g]);
+#pragma unroll
+          for (int g = 0; g < BT_REG_V; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[g][i] -= tk * sg[g] * v[i];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = vn[i];
         }
 #pragma unroll
-        for (int g = 0; g < BT_VEC; ++g)
-          for (int w = 32; w > 0; w >>= 1) sg[g] += __shfl_xor(sg[g], w, 64);
+        for (int g = 0; g < BT_REG_V; ++g)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int q = lane + 64 * i;
+            if (g < nv && q < r) M1[(int64_t)(jb + g * nw) * ld + q] = z[g][i];
+          }
+      }
+    } else {
+      for (int jb = wave; jb < p; jb += nw * BT_VEC) {
+        const int ng = min(BT_VEC, (p - jb + nw - 1) / nw);   // vectors jb + g nw, g < ng
+        double* x0 = M1 + (int64_t)jb * ld;
+        const int64_t js = (int64_t)nw * ld;
+        for (int k = r - 3; k >= 0; --k) {
+          const double tk = stau[k];
+          if (tk == 0.0) continue;
+          const int m = r - k - 1;
+          const double* vk = M0 + (int64_t)k * ld + k + 1;
+          double* xk = x0 + k + 1;
+          double sg[BT_VEC];
+#pragma unroll
+          for (int g = 0; g < BT_VEC; ++g) sg[g] = 0.0;
 #pragma unroll 1
-        for (int a = lane; a < m; a += 64) {
-          const double va = a == 0 ? 1.0 : vk[a];
+          for (int a = lane; a < m; a += 64) {
+            const double va = a == 0 ? 1.0 : vk[a];
+#pragma unroll
+            for (int g = 0; g < BT_VEC; ++g)
+              if (g < ng) sg[g] += va * xk[g * js + a];
+          }
 #pragma unroll
           for (int g = 0; g < BT_VEC; ++g)
-            if (g < ng) xk[g * js + a] -= tk * sg[g] * va;
+            sg[g] = wave_allsum(sg[g]);
+#pragma unroll 1
+          for (int a = lane; a < m; a += 64) {
+            const double va = a == 0 ? 1.0 : vk[a];
+#pragma unroll
+            for (int g = 0; g < BT_VEC; ++g)
+              if (g < ng) xk[g * js + a] -= tk * sg[g] * va;
+          }
         }
       }
     }
