@@ -118,6 +118,33 @@ __device__ void wg_gemm(double* C, const double* A, const double* B, int M, int 
 // ----------------------------------------------------------------------------
 // tridiagonal helpers (single thread)
 // ----------------------------------------------------------------------------
+// 1 / x for |x| in the normal range: hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r) (the error roughly squares each
+// step); a few units in the last place from the rounded quotient, in a
+// third of the dependent latency of a division
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Sturm count with the reciprocal above, for the bisection steps (the count
+// that decides how many eigenvalues are selected uses sturm_below)
+__device__ inline int sturm_below_fast(const double* d, const double* e, int n, double x,
+                                       double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] * rcp_nr(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
 __device__ inline int sturm_below(const double* d, const double* e, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
@@ -158,11 +185,11 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
       double u2i = 0.0;
       if (fabs(ai) >= fabs(lo)) {
         if (ai == 0.0) ai = tiny;
-        const double mlt = lo / ai;
+        const double mlt = lo * rcp_nr(ai);
         an -= mlt * upi;
         bn -= mlt * bi;
       } else {
-        const double mlt = ai / lo;
+        const double mlt = ai * rcp_nr(lo);
         ai = lo;
         const double t = an;
         an = upi - mlt * t;
@@ -182,11 +209,11 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
     }
   }
   if (ai == 0.0) ai = tiny;
-  double x1 = bi / ai, x2 = 0.0;             // x(i + 1), x(i + 2)
+  double x1 = bi * rcp_nr(ai), x2 = 0.0;     // x(i + 1), x(i + 2)
   b[n - 1] = x1;
   if (n >= 2) {
     x2 = x1;
-    x1 = (b[n - 2] - up[n - 2] * x2) / a[n - 2];
+    x1 = (b[n - 2] - up[n - 2] * x2) * rcp_nr(a[n - 2]);
     b[n - 2] = x1;
   }
   for (int i0 = n - 3; i0 >= 0; i0 -= TRI_CH) {
@@ -203,7 +230,7 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
     for (int u = 0; u < TRI_CH; ++u) {
       const int i = i0 - u;
       if (i < 0) break;
-      const double x = (bq[u] - uq[u] * x1 - vq[u] * x2) / aq[u];
+      const double x = (bq[u] - uq[u] * x1 - vq[u] * x2) * rcp_nr(aq[u]);
       b[i] = x;
       x2 = x1;
       x1 = x;
@@ -558,7 +585,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     for (int it = 0; it < 200; ++it) {
       const double mid = 0.5 * (lo + hi);
       if (hi - lo <= 2.0 * SEL_EPS * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-      if (sturm_below(sd, se, r, mid, pivmin) > kidx) hi = mid; else lo = mid;
+      if (sturm_below_fast(sd, se, r, mid, pivmin) > kidx) hi = mid; else lo = mid;
     }
     slam[j] = 0.5 * (lo + hi);
   }
