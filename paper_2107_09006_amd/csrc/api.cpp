@@ -643,10 +643,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     double *Tg = nullptr, *work = nullptr, *sig = nullptr;
     int32_t* pc = nullptr;
     TRY(c->dalloc(&Tg, H.total_g));
-    TRY(c->dalloc(&work, 4 * H.total_g));
+    TRY(c->dalloc(&work, SEL_WORK_MATS * H.total_g));
     TRY(c->dalloc(&sig, H.total_loc));
     TRY(c->dalloc(&pc, nparts + 1));
-    if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(work, 0, 4 * H.total_g * sizeof(double), st));
+    if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(work, 0, SEL_WORK_MATS * H.total_g * sizeof(double), st));
     LSQ2L_HIP_TRY(hipMemsetAsync(pc, 0, (nparts + 1) * sizeof(int32_t), st));
     launch_gamma_T(st, nparts, c->P, c->fac, Tg);
     launch_select(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig);

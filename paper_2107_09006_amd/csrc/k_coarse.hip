@@ -181,7 +181,7 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
   const int64_t* off = tileOff + d.tile_base;
   const double* A = fac + d.fac_off;
   const double* Di = dinv + d.dinv_off;
-  const double* Y = work + 4 * d.g_off;     // nGp x p, ld nGp
+  const double* Y = work + SEL_WORK_MATS * d.g_off;   // nGp x p, ld nGp
   double* H = X + d.x_off;                 // nIp x p, ld nIp
   const int p = d.p, ldh = d.nIp, ldy = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;

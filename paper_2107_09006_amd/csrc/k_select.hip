@@ -20,10 +20,10 @@
 //      thread per vector), clusters of close eigenvalues re-orthonormalised,
 //      and back-transformation through the Householder reflectors;
 //   6. Y = W U (interface coefficients of the selected vectors), sigma.
-// Work matrices (ld = nGp, four per subdomain at 4 g_off): M0 scaled Ct and
+// Work matrices (ld = nGp, five per subdomain at 5 g_off): M0 scaled Ct and
 // the pivoted factor, then K and the Householder vectors, then Y; M1 the
-// permuted T, then U; M2 R11^{-T}; M3 products, then scratch of the inverse
-// iteration (3 r doubles per vector).
+// permuted T, then U; M2 R11^{-T}; M3 products, then with M4 the scratch of
+// the inverse iteration (3 r doubles per vector, the vector index fastest).
 #include "kernels.hpp"
 
 namespace lsq2l {
@@ -168,7 +168,7 @@ constexpr int TRI_CH = 4;
 __device__ void tri_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
                           double lam, double tiny, double sc, double* __restrict__ b,
                           double* __restrict__ a, double* __restrict__ up,
-                          double* __restrict__ u2) {
+                          double* __restrict__ u2, int sst) {
   // row i: diagonal ai, superdiagonal upi, right-hand side bi; row i + 1:
   // diagonal an, superdiagonal upn, right-hand side bn
   double ai = d[0] - lam, upi = n > 1 ? e[0] : 0.0, bi = b[0] * sc;
@@ -199,9 +199,9 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
         bi = bn;
         bn = bo - mlt * bn;
       }
-      a[i] = ai;
-      up[i] = upi;
-      u2[i] = u2i;
+      a[i * sst] = ai;
+      up[i * sst] = upi;
+      u2[i * sst] = u2i;
       b[i] = bi;
       ai = an;
       upi = upn;
@@ -213,7 +213,7 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
   b[n - 1] = x1;
   if (n >= 2) {
     x2 = x1;
-    x1 = (b[n - 2] - up[n - 2] * x2) * rcp_nr(a[n - 2]);
+    x1 = (b[n - 2] - up[(n - 2) * sst] * x2) * rcp_nr(a[(n - 2) * sst]);
     b[n - 2] = x1;
   }
   for (int i0 = n - 3; i0 >= 0; i0 -= TRI_CH) {
@@ -221,9 +221,9 @@ __device__ void tri_solve(const double* __restrict__ d, const double* __restrict
 #pragma unroll
     for (int u = 0; u < TRI_CH; ++u) {
       const int i = i0 - u;
-      aq[u] = i >= 0 ? a[i] : 1.0;
-      uq[u] = i >= 0 ? up[i] : 0.0;
-      vq[u] = i >= 0 ? u2[i] : 0.0;
+      aq[u] = i >= 0 ? a[i * sst] : 1.0;
+      uq[u] = i >= 0 ? up[i * sst] : 0.0;
+      vq[u] = i >= 0 ? u2[i * sst] : 0.0;
       bq[u] = i >= 0 ? b[i] : 0.0;
     }
 #pragma unroll
@@ -300,7 +300,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     return;
   }
   const int64_t mm = (int64_t)ld * ld;
-  double* M0 = work + 4 * dsc.g_off;
+  double* M0 = work + SEL_WORK_MATS * dsc.g_off;
   double* M1 = M0 + mm;
   double* M2 = M1 + mm;
   double* M3 = M2 + mm;
@@ -614,7 +614,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   // after the independent sweeps and again after one cleaning sweep.
   // Vectors in M1 (r x p).
   const double tiny = SEL_EPS * anorm;
-  const int slots = (int)min<int64_t>(mm / (3 * r), nthr);
+  const int slots = (int)min<int64_t>(2 * mm / (3 * r), nthr);
   const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
   for (int64_t q = tid; q < (int64_t)ld * p; q += nthr) {
     const int row = (int)(q % ld), j = (int)(q / ld);
@@ -626,7 +626,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       const int j = j0 + tid;
       if (tid >= slots || j >= p) continue;
       double* x = M1 + (int64_t)j * ld;
-      double* scr = M3 + (int64_t)tid * 3 * r;
+      double* scr = M3 + tid;                // row q of array k at (k r + q) slots
       double nr = 0.0;
       for (int q0 = 0; q0 < r; q0 += TRI_CH) {
         double xq[TRI_CH];
@@ -638,7 +638,8 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       }
       nr = 1.0 / sqrt(nr);
       // the solve scales its right-hand side by nr as it reads it
-      tri_solve(sd, se, r, slam[j], tiny, nr, x, scr, scr + r, scr + 2 * r);
+      tri_solve(sd, se, r, slam[j], tiny, nr, x, scr, scr + (int64_t)r * slots,
+                scr + (int64_t)2 * r * slots, slots);
     }
     __syncthreads();
     if (sweep < 2) continue;

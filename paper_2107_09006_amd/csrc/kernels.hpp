@@ -111,6 +111,9 @@ void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const dou
 
 // --- coarse space ------------------------------------------------------------
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
+// ld x ld work matrices per subdomain of the selection (work holds
+// SEL_WORK_MATS * total_g doubles; Y, the selected vectors, is the first)
+constexpr int SEL_WORK_MATS = 5;
 void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
                    double* work, double tau, int nev_max, int32_t* p_out, double* sig_out);
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
