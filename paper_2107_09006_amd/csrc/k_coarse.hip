@@ -316,14 +316,33 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
   const bool lv = l < dj.p, kv = k < di.p;
   const int nrows = diag ? di.nXi : pr.nrows;
   double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int t0 = 0; t0 < nrows; t0 += 4) {
+  // the shared rows in steps of 4; EU steps load their operands before their
+  // products, so the loads of a batch overlap (same product order)
+  constexpr int EU = 8;
+  const double* wj = Wj + (int64_t)l * dj.nXi;
+  const double* wi = Wi + (int64_t)k * di.nXi;
+  int t0 = 0;
+  for (; t0 + 4 * EU <= nrows; t0 += 4 * EU) {
+    double a[EU], b[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int t = t0 + 4 * u + lk;
+      const int rj = diag ? t : rl[2 * t + 1];
+      const int ri = diag ? t : rl[2 * t];
+      a[u] = lv ? wj[rj] : 0.0;
+      b[u] = kv ? wi[ri] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) acc = Mfma<double>::mma(a[u], b[u], acc);
+  }
+  for (; t0 < nrows; t0 += 4) {
     const int t = t0 + lk;
     double a = 0.0, b = 0.0;
     if (t < nrows) {
       const int rj = diag ? t : rl[2 * t + 1];
       const int ri = diag ? t : rl[2 * t];
-      if (lv) a = Wj[(int64_t)l * dj.nXi + rj];
-      if (kv) b = Wi[(int64_t)k * di.nXi + ri];
+      if (lv) a = wj[rj];
+      if (kv) b = wi[ri];
     }
     acc = Mfma<double>::mma(a, b, acc);
   }
