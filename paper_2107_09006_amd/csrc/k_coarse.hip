@@ -169,7 +169,8 @@ __device__ inline void tile_io_cols(double4_t acc[4], double* C, int ldc, int nb
 
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
 // H = L_GI^T Y by 32 x 32 output blocks (one per wave task), then the
-// backward substitution with L_I^T by tile rows (right-looking), all on MFMA.
+// backward substitution with L_I^T by tile rows (left-looking, a wave per
+// block of columns), all on MFMA.
 __global__ void __launch_bounds__(512)
 k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
            const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
@@ -198,29 +199,28 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
     tile_io_cols(acc, H + (int64_t)(TS * pb) * ldh + J * TS, ldh, nb, lane, true);
   }
   __syncthreads();
-  // backward substitution with L_I^T: X_I = Dinv_I^T H_I, H_K -= L(I,K)^T X_I
-  for (int I = d.ntI - 1; I >= 0; --I) {
-    for (int pb = wave; pb < npb; pb += nw) {
-      const int nb = min(TS, p - TS * pb);
-      double* HI = H + (int64_t)(TS * pb) * ldh + I * TS;
+  // backward substitution with L_I^T, left-looking, one wave per block of 32
+  // columns with no block barriers: for I from the last tile row down,
+  // X_I = Dinv_I^T (H_I - sum over K > I with F(K) <= I of L(K,I)^T X_K)
+  for (int pb = wave; pb < npb; pb += nw) {
+    const int nb = min(TS, p - TS * pb);
+    double* Hp = H + (int64_t)(TS * pb) * ldh;
+    for (int I = d.ntI - 1; I >= 0; --I) {
       double4_t acc[4];
+      tile_io_cols(acc, Hp + I * TS, ldh, nb, lane, false);
+      for (int K = I + 1; K < d.ntI; ++K)
+        if (F[K] <= I)
+          tile_mma_cols<true>(acc, A + tile_pos(F, off, K, I) * TT, TS, Hp + K * TS, ldh, nb, lane, true);
+      tile_io_cols(acc, Hp + I * TS, ldh, nb, lane, true);
+      wg_fence();
       tile_acc_zero<double>(acc);
-      tile_mma_cols<true>(acc, Di + (int64_t)I * TT, TS, HI, ldh, nb, lane, false);
-      tile_io_cols(acc, HI, ldh, nb, lane, true);
+      tile_mma_cols<true>(acc, Di + (int64_t)I * TT, TS, Hp + I * TS, ldh, nb, lane, false);
+      wg_fence();
+      tile_io_cols(acc, Hp + I * TS, ldh, nb, lane, true);
+      wg_fence();
     }
-    __syncthreads();
-    const int nK = I - F[I];
-    for (int t = wave; t < nK * npb; t += nw) {
-      const int K = F[I] + t % nK, pb = t / nK, nb = min(TS, p - TS * pb);
-      double* HK = H + (int64_t)(TS * pb) * ldh + K * TS;
-      double4_t acc[4];
-      tile_io_cols(acc, HK, ldh, nb, lane, false);
-      tile_mma_cols<true>(acc, A + tile_pos(F, off, I, K) * TT, TS,
-                          H + (int64_t)(TS * pb) * ldh + I * TS, ldh, nb, lane, true);
-      tile_io_cols(acc, HK, ldh, nb, lane, true);
-    }
-    __syncthreads();
   }
+  __syncthreads();
   // scale rows by S_I and columns by 1/sigma; zero the padding rows
   const double* s_loc = scale + d.loc_off;
   for (int64_t q = tid; q < (int64_t)ldh * p; q += nthr) {
