@@ -773,26 +773,42 @@ k_coarse_restrict(const SubDesc* __restrict__ subs, const int32_t* __restrict__ 
   if (d.p == 0) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
   const int32_t* om = omega + d.omega_off;
+  constexpr int EV = 16 / sizeof(TX);
+  typedef TX V __attribute__((ext_vector_type(EV)));
   double acc[8];
   for (int kb = 0; kb < d.p; kb += 8 * nwaves) {
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
     for (int a0 = 0; a0 < d.nI; a0 += RCHUNK) {
       const int len = min(RCHUNK, d.nI - a0);
+      // the chunk in whole 16-byte vectors of X (columns are padded with
+      // zeros to a multiple of 32 rows; the copy of r is zero there too)
+      const int nvec = (len + EV - 1) / EV;
       __syncthreads();
-      for (int a = threadIdx.x; a < len; a += blockDim.x) sr[a] = r[om[a0 + a]];
+      for (int a = threadIdx.x; a < nvec * EV; a += blockDim.x) sr[a] = a < len ? r[om[a0 + a]] : 0.0;
       __syncthreads();
+#pragma unroll 1
       for (int u = 0; u < 8; ++u) {
         const int k = kb + u * nwaves + wave;
         if (k >= d.p) break;
-        const TX* xk = X + d.x_off + (int64_t)k * d.nIp + a0;
-        // eight independent loads in flight per lane
-        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int a = lane;
-        for (; a + 7 * 64 < len; a += 8 * 64)
+        const V* xk = reinterpret_cast<const V*>(X + d.x_off + (int64_t)k * d.nIp + a0);
+        // four independent 16-byte loads in flight per lane
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = lane;
+        for (; q + 3 * 64 < nvec; q += 4 * 64) {
+          V xv[4];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) s8[i] += (double)xk[a + 64 * i] * sr[a + 64 * i];
-        for (int i = 0; a < len; a += 64, ++i) s8[i] += (double)xk[a] * sr[a];
-        acc[u] += ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+          for (int i = 0; i < 4; ++i) xv[i] = xk[q + 64 * i];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < EV; ++e) s4[i] += (double)xv[i][e] * sr[(q + 64 * i) * EV + e];
+        }
+        for (int i = 0; q < nvec; q += 64, ++i) {
+          const V xv = xk[q];
+#pragma unroll
+          for (int e = 0; e < EV; ++e) s4[i] += (double)xv[e] * sr[q * EV + e];
+        }
+        acc[u] += (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
     }
     for (int u = 0; u < 8; ++u) {
