@@ -105,16 +105,21 @@ k_equil_apply(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tile
   const int64_t* off = tileOff + d.tile_base;
   double* A = fac + d.fac_off;
   const double* s = scale + d.loc_off;
+  // pairs of entries (rows r, r + 1 of one column c) as 16-byte accesses
+  typedef double d2 __attribute__((ext_vector_type(2)));
   for (int t = blockIdx.y; t < d.ntiles; t += gridDim.y) {
     const int nt = t - F[t] + 1;
-    double* row = A + off[t] * TT;
-    for (int64_t e = threadIdx.x; e < (int64_t)nt * TT; e += blockDim.x) {
+    d2* row = reinterpret_cast<d2*>(A + off[t] * TT);
+    for (int64_t e2 = threadIdx.x; e2 < (int64_t)nt * (TT / 2); e2 += blockDim.x) {
+      const int64_t e = 2 * e2;
       const int J = F[t] + (int)(e / TT);
       const int rc = (int)(e % TT);
       const int r = t * TS + rc % TS, c = J * TS + rc / TS;
-      const double sr = s[r], sc = s[c];
-      if (r == c && sr == 0.0) row[e] = 1.0;
-      else row[e] *= sr * sc;
+      const double sr0 = s[r], sr1 = s[r + 1], sc = s[c];
+      d2 v = row[e2];
+      v.x = (r == c && sr0 == 0.0) ? 1.0 : v.x * (sr0 * sc);
+      v.y = (r + 1 == c && sr1 == 0.0) ? 1.0 : v.y * (sr1 * sc);
+      row[e2] = v;
     }
   }
   double* Ct = ctg + d.g_off;
