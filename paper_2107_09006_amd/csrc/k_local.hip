@@ -154,9 +154,11 @@ __device__ inline int envelope_rows(const int32_t* F, int J, int ntiles, int32_t
 constexpr int ROWCAP = 2048;
 
 // Right-looking tile Cholesky of one envelope matrix per workgroup:
-// for each tile column J: factor and invert the diagonal tile in LDS,
-// L(I,J) = A(I,J) L(J,J)^{-T} for the envelope rows, then
-// A(I,K) -= L(I,J) L(K,J)^T for every pair of envelope rows (MFMA).
+// for each tile column J: the diagonal tile factored and inverted in
+// registers (one step ahead, see below), L(I,J) = A(I,J) L(J,J)^{-T} for the
+// envelope rows, then A(I,K) -= L(I,J) L(K,J)^T for every pair of envelope
+// rows (MFMA).  Wave 0 applies column J to tile (J+1, J+1) first and factors
+// it while the other waves work through the remaining pairs.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
@@ -174,15 +176,22 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid / 64, lane = tid % 64, nwaves = nthr / 64;
   bool failed = false;
+  __shared__ int s_next;
+  // factor and invert diagonal tile J (its updates applied) by wave 0; the
+  // tile is in sW on entry
+  auto diag_factor = [&]() {
+    const bool okw = tile_potrf_inv_reg(sW, sL, sInv, lane);
+    if (lane == 0) s_ok = okw;
+  };
+  if (wave == 0 && d.ntiles > 0) {
+    const T* A00 = A + tile_pos(F, off, 0, 0) * TT;
+    for (int e = lane; e < TT; e += 64) sW[(e / TS) * LDT + e % TS] = A00[e];
+    wave_sync();
+    diag_factor();
+  }
+  __syncthreads();
   for (int J = 0; J < d.ntiles; ++J) {
     T* Ajj = A + tile_pos(F, off, J, J) * TT;
-    for (int e = tid; e < TT; e += nthr) sW[(e / TS) * LDT + e % TS] = Ajj[e];
-    __syncthreads();
-    if (wave == 0) {
-      const bool okw = tile_potrf_inv_reg(sW, sL, sInv, lane);
-      if (lane == 0) s_ok = okw;
-    }
-    __syncthreads();
     const bool ok = s_ok;
     if (!ok) failed = true;
     for (int e = tid; e < TT; e += nthr) {
@@ -199,21 +208,47 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
       tile_mma_nt<T, false>(acc, Aij, TS, sInv, LDT, lane);
       tile_acc_store<T>(acc, Aij, TS, lane);
     }
+    // the next diagonal tile gets its update from column J (when coupled)
+    // and is factored by wave 0 while the other waves take the remaining
+    // pairs (a >= b) of envelope rows from a shared counter; wave 0 joins
+    // them when done
+    const bool next = J + 1 < d.ntiles;
+    const bool next_coupled = next && nr > 0 && rows[0] == J + 1;
+    const int npairs = nr * (nr + 1) / 2;
+    if (tid == 0) s_next = next_coupled ? 1 : 0;
     __syncthreads();
-    // trailing update over pairs (a >= b) of envelope rows
-    int item = 0;
-    for (int a = 0; a < nr; ++a)
-      for (int b = 0; b <= a; ++b, ++item) {
-        if (item % nwaves != wave) continue;
-        const int Ia = rows[a], Ib = rows[b];
-        const T* La = A + tile_pos(F, off, Ia, J) * TT;
-        const T* Lb = A + tile_pos(F, off, Ib, J) * TT;
-        T* Cab = A + tile_pos(F, off, Ia, Ib) * TT;
+    if (wave == 0 && next) {
+      const T* Ann = A + tile_pos(F, off, J + 1, J + 1) * TT;
+      if (next_coupled) {
+        const T* Ln = A + tile_pos(F, off, J + 1, J) * TT;
         typename Mfma<T>::acc_t acc[4];
-        tile_acc_load<T>(acc, Cab, TS, lane);
-        tile_mma_nt<T, true>(acc, La, TS, Lb, TS, lane);
-        tile_acc_store<T>(acc, Cab, TS, lane);
+        tile_acc_load<T>(acc, Ann, TS, lane);
+        tile_mma_nt<T, true>(acc, Ln, TS, Ln, TS, lane);
+        tile_acc_store<T>(acc, sW, LDT, lane);
+      } else {
+        for (int e = lane; e < TT; e += 64) sW[(e / TS) * LDT + e % TS] = Ann[e];
       }
+      wave_sync();
+      diag_factor();
+    }
+    while (true) {
+      int it = 0;
+      if (lane == 0) it = atomicAdd(&s_next, 1);
+      it = __shfl(it, 0, 64);
+      if (it >= npairs) break;
+      int a = (int)((sqrt(8.0 * it + 1.0) - 1.0) / 2.0);
+      while (a * (a + 1) / 2 > it) --a;
+      while ((a + 1) * (a + 2) / 2 <= it) ++a;
+      const int b = it - a * (a + 1) / 2;
+      const int Ia = rows[a], Ib = rows[b];
+      const T* La = A + tile_pos(F, off, Ia, J) * TT;
+      const T* Lb = A + tile_pos(F, off, Ib, J) * TT;
+      T* Cab = A + tile_pos(F, off, Ia, Ib) * TT;
+      typename Mfma<T>::acc_t acc[4];
+      tile_acc_load<T>(acc, Cab, TS, lane);
+      tile_mma_nt<T, true>(acc, La, TS, Lb, TS, lane);
+      tile_acc_store<T>(acc, Cab, TS, lane);
+    }
     __syncthreads();
   }
   if (failed && tid == 0) atomicCAS(status, 0, blockIdx.x + 1);
