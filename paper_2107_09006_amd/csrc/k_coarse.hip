@@ -167,6 +167,7 @@ __device__ inline void tile_io_cols(double4_t acc[4], double* C, int ldc, int nb
     }
 }
 
+constexpr int XS_MAXROWS = 8192, XS_MAXP = 1024;   // LDS copies of S_I and sigma (p <= 1024 always)
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
 // H = L_GI^T Y by 32 x 32 output blocks (one per wave task), then the
 // backward substitution with L_I^T by tile rows (left-looking, a wave per
@@ -176,6 +177,7 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
            const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
            const double* __restrict__ dinv, const double* __restrict__ scale,
            const double* __restrict__ work, const double* __restrict__ sig, double* __restrict__ X) {
+  __shared__ double sXs[XS_MAXROWS], sXg[XS_MAXP];
   const SubDesc d = subs[blockIdx.x];
   if (d.p == 0) return;
   const int32_t* F = tileF + d.tile_base;
@@ -187,16 +189,55 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
   const int p = d.p, ldh = d.nIp, ldy = d.nGp, tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
   const int npb = (p + TS - 1) / TS;
-  // H_J = sum over interface tile rows I with F(I) <= J of L(I,J)^T Y_I
-  for (int t = wave; t < d.ntI * npb; t += nw) {
-    const int J = t % d.ntI, pb = t / d.ntI, nb = min(TS, p - TS * pb);
-    double4_t acc[4];
-    tile_acc_zero<double>(acc);
-    for (int I = d.ntI; I < d.ntiles; ++I)
-      if (F[I] <= J)
-        tile_mma_cols<true>(acc, A + tile_pos(F, off, I, J) * TT, TS,
-                            Y + (int64_t)(TS * pb) * ldy + (I - d.ntI) * TS, ldy, nb, lane, false);
-    tile_io_cols(acc, H + (int64_t)(TS * pb) * ldh + J * TS, ldh, nb, lane, true);
+  // H_J = sum over interface tile rows I with F(I) <= J of L(I,J)^T Y_I: a
+  // wave task is tile row J of up to XG column blocks, so that each tile of
+  // L is loaded once for all of them
+  constexpr int XG = 4;
+  const int ngrp = (npb + XG - 1) / XG;
+  for (int t = wave; t < d.ntI * ngrp; t += nw) {
+    const int J = t % d.ntI, g0 = (t / d.ntI) * XG;
+    const int ng = min(XG, npb - g0);
+    double4_t acc[XG][4];
+#pragma unroll
+    for (int g = 0; g < XG; ++g) tile_acc_zero<double>(acc[g]);
+    const int li = lane % 16, lk = lane / 16;
+    for (int I = d.ntI; I < d.ntiles; ++I) {
+      if (F[I] > J) continue;
+      const double* At = A + tile_pos(F, off, I, J) * TT;
+      double a0[8], a1[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 4 * q + lk;
+        a0[q] = At[li * TS + k];
+        a1[q] = At[(16 + li) * TS + k];
+      }
+#pragma unroll
+      for (int g = 0; g < XG; ++g) {
+        if (g >= ng) break;
+        const int nb = min(TS, p - TS * (g0 + g));
+        const double* Bt = Y + (int64_t)(TS * (g0 + g)) * ldy + (I - d.ntI) * TS;
+        double b0[8], b1[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = 4 * q + lk;
+          b0[q] = li < nb ? Bt[(int64_t)li * ldy + k] : 0.0;
+          b1[q] = 16 + li < nb ? Bt[(int64_t)(16 + li) * ldy + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          acc[g][0] = Mfma<double>::mma(a0[q], b0[q], acc[g][0]);
+          acc[g][1] = Mfma<double>::mma(a0[q], b1[q], acc[g][1]);
+          acc[g][2] = Mfma<double>::mma(a1[q], b0[q], acc[g][2]);
+          acc[g][3] = Mfma<double>::mma(a1[q], b1[q], acc[g][3]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < XG; ++g) {
+      if (g >= ng) break;
+      const int nb = min(TS, p - TS * (g0 + g));
+      tile_io_cols(acc[g], H + (int64_t)(TS * (g0 + g)) * ldh + J * TS, ldh, nb, lane, true);
+    }
   }
   __syncthreads();
   // backward substitution with L_I^T, left-looking, one wave per block of 32
@@ -221,11 +262,38 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
     }
   }
   __syncthreads();
-  // scale rows by S_I and columns by 1/sigma; zero the padding rows
+  // scale rows by S_I and columns by 1/sigma; zero the padding rows.  S_I
+  // and sigma from LDS, pairs of entries as 16-byte accesses, eight in
+  // flight per thread
   const double* s_loc = scale + d.loc_off;
-  for (int64_t q = tid; q < (int64_t)ldh * p; q += nthr) {
-    const int a = (int)(q % ldh), k = (int)(q / ldh);
-    H[q] = (a < d.nI) ? H[q] * s_loc[a] / sig[d.loc_off + k] : 0.0;
+  if (ldh > XS_MAXROWS) {                  // larger interiors: straight from memory
+    for (int64_t q = tid; q < (int64_t)ldh * p; q += nthr) {
+      const int a = (int)(q % ldh), k = (int)(q / ldh);
+      H[q] = (a < d.nI) ? H[q] * s_loc[a] / sig[d.loc_off + k] : 0.0;
+    }
+    return;
+  }
+  for (int a = tid; a < ldh; a += nthr) sXs[a] = a < d.nI ? s_loc[a] : 0.0;
+  for (int k = tid; k < p; k += nthr) sXg[k] = sig[d.loc_off + k];
+  __syncthreads();
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2* H2 = reinterpret_cast<d2*>(H);       // ldh is even: a pair never spans two columns
+  const int64_t n2 = (int64_t)ldh * p / 2;
+  for (int64_t q0 = tid; q0 < n2; q0 += 8 * nthr) {
+    d2 h[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) h[u] = q0 + u * nthr < n2 ? H2[q0 + u * nthr] : d2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = q0 + u * nthr;
+      if (q >= n2) break;
+      const int k = (int)(2 * q / ldh), a = (int)(2 * q % ldh);
+      const double g = sXg[k];
+      d2 v;
+      v.x = (a < d.nI) ? h[u].x * sXs[a] / g : 0.0;
+      v.y = (a + 1 < d.nI) ? h[u].y * sXs[a + 1] / g : 0.0;
+      H2[q] = v;
+    }
   }
 }
 
