@@ -172,27 +172,50 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
                 HostPlan& P, std::string& err) {
   P.nparts = nparts;
-  // columns of each part, ascending, and each column's position in its part
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nth = std::min<unsigned>(nth, (unsigned)nparts);
+  // columns of each part, ascending, and each column's position in its part:
+  // a counting sort over column ranges, one per thread (each range's columns
+  // follow those of the earlier ranges inside every part)
   std::vector<int64_t> pptr((size_t)nparts + 1, 0);
-  for (int32_t j = 0; j < n; ++j) pptr[part[j] + 1]++;
-  for (int32_t i = 0; i < nparts; ++i) {
-    if (pptr[i + 1] == 0) { err = "part " + std::to_string(i) + " is empty"; return false; }
-    pptr[i + 1] += pptr[i];
-  }
   std::vector<int32_t> pcols((size_t)n);
-  P.locown.assign((size_t)n, 0);
+  P.locown.resize((size_t)n);
   {
-    std::vector<int64_t> fill(pptr.begin(), pptr.end() - 1);
-    for (int32_t j = 0; j < n; ++j) {
-      int64_t k = fill[part[j]]++;
-      pcols[k] = j;
-      P.locown[j] = (int32_t)(k - pptr[part[j]]);
+    const unsigned ct = n < (1 << 16) ? 1u : nth;
+    std::vector<std::vector<int64_t>> cnt(ct, std::vector<int64_t>((size_t)nparts, 0));
+    auto crange = [&](unsigned t, int32_t& a, int32_t& b) {
+      a = (int32_t)((int64_t)n * t / ct);
+      b = (int32_t)((int64_t)n * (t + 1) / ct);
+    };
+    auto cpar = [&](auto&& fn) {
+      std::vector<std::thread> pool;
+      for (unsigned t = 0; t < ct; ++t) pool.emplace_back([&, t]() { fn(t); });
+      for (auto& th : pool) th.join();
+    };
+    cpar([&](unsigned t) {
+      int32_t a, b;
+      crange(t, a, b);
+      for (int32_t j = a; j < b; ++j) cnt[t][part[j]]++;
+    });
+    for (int32_t i = 0; i < nparts; ++i) {
+      int64_t run = 0;
+      for (unsigned t = 0; t < ct; ++t) { const int64_t c = cnt[t][i]; cnt[t][i] = run; run += c; }
+      if (run == 0) { err = "part " + std::to_string(i) + " is empty"; return false; }
+      pptr[i + 1] = pptr[i] + run;
     }
+    cpar([&](unsigned t) {
+      int32_t a, b;
+      crange(t, a, b);
+      for (int32_t j = a; j < b; ++j) {
+        const int32_t i = part[j];
+        const int64_t r = cnt[t][i]++;          // rank of j inside part i
+        pcols[pptr[i] + r] = j;
+        P.locown[j] = (int32_t)r;
+      }
+    });
   }
   // per-subdomain work in parallel
   std::vector<LocalOut> outs((size_t)nparts);
-  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  nth = std::min<unsigned>(nth, (unsigned)nparts);
   {
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nth; ++t)
