@@ -51,6 +51,9 @@ PROBLEMS = {
     "grid": lambda: W.small_config("grid"),
     "irregular": lambda: W.small_config("irregular"),
     "parts32": lambda: W.random_banded(480, 960, 32, seed=232, name="parts32"),
+    # interfaces of 490 columns: a non-diagonal Ct_GG (pivoted range basis)
+    # and reduced problems beyond 256 (the selection's wide-interface paths)
+    "wide": lambda: W.random_banded(1600, 4800, 4, seed=77, tau=0.3, half_width=160, name="wide"),
 }
 _cache = {}
 
@@ -121,7 +124,7 @@ def _near_ties(p, tau):
 @pytest.mark.parametrize("name,tau", [("worked", 0.6), ("worked", 0.7), ("config0", 0.1),
                                       ("config0", 0.4), ("banded", 0.1), ("grid", 0.1),
                                       ("grid", 0.02), ("irregular", 0.05), ("irregular", 0.3),
-                                      ("parts32", 0.1)])
+                                      ("parts32", 0.1), ("wide", 0.3)])
 def test_selection_count_bit_exact(L, name, tau):
     p = problem(name)
     orc = oracle(name, tau)
@@ -157,7 +160,7 @@ def span_tolerance(Cii, Ctii, nI, tau):
     return max(1e-10, 10 * EPS * (kI + 1.0 / lam_r) / gap)
 
 
-@pytest.mark.parametrize("name", ["config0", "grid", "parts32"])
+@pytest.mark.parametrize("name", ["config0", "grid", "parts32", "wide"])
 def test_coarse_span_parity(L, name):
     """The GPU basis spans the same space as the oracle's (principal angles)
     and is C_I-orthonormal, within the conditioning bound of each subdomain."""
@@ -253,7 +256,7 @@ def test_solve_parity_fp64(L, name, variant):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["config0", "grid", "irregular", "parts32"])
+@pytest.mark.parametrize("name", ["config0", "grid", "irregular", "parts32", "wide"])
 def test_solve_parity_mixed(L, name):
     p = problem(name)
     ref = oracle(name).solve(p.b, tol=1e-10)

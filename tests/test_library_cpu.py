@@ -59,6 +59,7 @@ CASES = {
     "irregular_small": lambda: [W.small_config("irregular")],
     "single_part": lambda: [W.random_banded(200, 400, 1, seed=3)],
     "many_parts": lambda: [W.random_banded(480, 960, 32, seed=232)],
+    "wide_interfaces": lambda: [W.random_banded(1600, 4800, 4, seed=77, tau=0.3, half_width=160)],
     "batch": lambda: [W.random_banded(300 + 50 * k, 600 + 100 * k, 3 + k, seed=k) for k in range(4)],
     "grid_500": lambda: [W.config4()],
     "grid_1000": lambda: [W.config1()],
