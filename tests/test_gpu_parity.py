@@ -46,7 +46,7 @@ def _np(t):
 
 PROBLEMS = {
     "worked": lambda: W.worked_example(),
-    "config0": lambda: W.config0(),
+    "banded_1000": lambda: W.banded_1000(),
     "banded": lambda: W.small_config("banded"),
     "grid": lambda: W.small_config("grid"),
     "irregular": lambda: W.small_config("irregular"),
@@ -121,8 +121,8 @@ def _near_ties(p, tau):
     return out
 
 
-@pytest.mark.parametrize("name,tau", [("worked", 0.6), ("worked", 0.7), ("config0", 0.1),
-                                      ("config0", 0.4), ("banded", 0.1), ("grid", 0.1),
+@pytest.mark.parametrize("name,tau", [("worked", 0.6), ("worked", 0.7), ("banded_1000", 0.1),
+                                      ("banded_1000", 0.4), ("banded", 0.1), ("grid", 0.1),
                                       ("grid", 0.02), ("irregular", 0.05), ("irregular", 0.3),
                                       ("parts32", 0.1), ("wide", 0.3)])
 def test_selection_count_bit_exact(L, name, tau):
@@ -160,7 +160,7 @@ def span_tolerance(Cii, Ctii, nI, tau):
     return max(1e-10, 10 * EPS * (kI + 1.0 / lam_r) / gap)
 
 
-@pytest.mark.parametrize("name", ["config0", "grid", "parts32", "wide"])
+@pytest.mark.parametrize("name", ["banded_1000", "grid", "parts32", "wide"])
 def test_coarse_span_parity(L, name):
     """The GPU basis spans the same space as the oracle's (principal angles)
     and is C_I-orthonormal, within the conditioning bound of each subdomain."""
@@ -256,7 +256,7 @@ def test_solve_parity_fp64(L, name, variant):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["config0", "grid", "irregular", "parts32", "wide"])
+@pytest.mark.parametrize("name", ["banded_1000", "grid", "irregular", "parts32", "wide"])
 def test_solve_parity_mixed(L, name):
     p = problem(name)
     ref = oracle(name).solve(p.b, tol=1e-10)
@@ -269,7 +269,7 @@ def test_solve_parity_mixed(L, name):
 
 
 def test_solve_matches_dense_least_squares(L):
-    p = W.config0()
+    p = W.banded_1000()
     s = solver(L, p, tol=1e-12)
     x, info, _ = s.solve(_t(p.b))
     xs = np.linalg.lstsq(p.scipy().toarray(), p.b, rcond=None)[0]
@@ -277,7 +277,7 @@ def test_solve_matches_dense_least_squares(L):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["config0", "grid", "banded"])
+@pytest.mark.parametrize("name", ["banded_1000", "grid", "banded"])
 def test_backward_parity(L, name):
     p = problem(name)
     orc = oracle(name)
@@ -329,7 +329,7 @@ def test_backward_central_differences(L):
 def test_autograd_function(L):
     """torch.autograd through lstsq gives the library's adjoint gradients."""
     import torch
-    p = problem("config0")
+    p = problem("banded_1000")
     s = solver(L, p, tol=1e-12)
     vals = s.vals.clone().requires_grad_(True)
     b = _t(p.b).requires_grad_(True)
@@ -337,7 +337,7 @@ def test_autograd_function(L):
     x = L.lstsq(vals, b, s)
     loss = 0.5 * torch.sum((x - xstar) ** 2)
     loss.backward()
-    orc = oracle("config0")
+    orc = oracle("banded_1000")
     xo = orc.solve(p.b, tol=1e-12)["x"]
     go = orc.backward(p.b, xo, xo - _np(xstar), tol=1e-12)
     assert np.linalg.norm(_np(b.grad) - go["dLdb"]) <= 1e-6 * np.linalg.norm(go["dLdb"])
@@ -398,7 +398,7 @@ def test_single_subdomain_is_direct_solve(L):
 
 
 def test_tiny_tau_is_one_level(L):
-    p = problem("config0")
+    p = problem("banded_1000")
     s1 = solver(L, p, tau=1e-12)
     s2 = solver(L, p, variant=L.ONE_LEVEL)
     assert s1.info()["n0"] == 0
@@ -410,13 +410,13 @@ def test_tiny_tau_is_one_level(L):
 def test_tau_near_one_and_nev_cap(L):
     """tau close to 1 (tau = 1 itself sits on the multiple eigenvalue mu = 1 of
     every subdomain, a tie) and a cap on the number of vectors per subdomain."""
-    p = problem("config0")
+    p = problem("banded_1000")
     s = solver(L, p, tau=0.99)
-    orc = oracle("config0", tau=0.99)
+    orc = oracle("banded_1000", tau=0.99)
     assert [s.subdomain(i)["p"] for i in range(p.nparts)] == list(orc.p)
     s.close()
     s = solver(L, p, tau=0.4, nev_max=1)
-    orc = oracle("config0", tau=0.4, nev_max=1)
+    orc = oracle("banded_1000", tau=0.4, nev_max=1)
     assert [s.subdomain(i)["p"] for i in range(p.nparts)] == list(orc.p)
     r = np.random.default_rng(6).standard_normal(p.n)
     z = _np(s.apply_preconditioner(_t(r)))
@@ -481,7 +481,7 @@ def test_csr_validation_rejects_corrupt_input(L):
     rowptr, which must not be followed into colind."""
     big = W.grid_gradient(200, 4, seed=3, tau=0.1, tol=1e-8, name="g200")
     assert big.m > 65536
-    for p in (problem("config0"), big):
+    for p in (problem("banded_1000"), big):
         rp = p.indptr.copy()
         rp[len(rp) // 2] = p.indices.size + 100
         ci_range = p.indices.copy()
@@ -514,7 +514,7 @@ def test_device_memory_cache_reuse_is_bitwise_neutral(L):
 
 
 def test_error_paths(L):
-    p = problem("config0")
+    p = problem("banded_1000")
     bad = p.part.copy(); bad[0] = p.nparts
     with pytest.raises(L.Lsq2lError) as e:
         L.Solver(p.indptr, p.indices, p.data, bad, p.nparts, p.m, p.n, 0.1)
@@ -553,7 +553,7 @@ def test_error_paths(L):
 def test_full_size_grid(L):
     """The 1000 x 1000 grid with 256 patches, as timed by bench.py: both
     precisions reach 1e-8; sampled subdomains match the oracle exactly."""
-    p = W.config1()
+    p = W.grid_1000()
     A = p.scipy()
     dev = [_t(p.data)]
     results = {}

@@ -54,15 +54,15 @@ def plan_check(tmp_path_factory):
 
 CASES = {
     "worked": lambda: [W.worked_example()],
-    "config0": lambda: [W.config0()],
+    "banded_1000": lambda: [W.banded_1000()],
     "grid_small": lambda: [W.small_config("grid")],
     "irregular_small": lambda: [W.small_config("irregular")],
     "single_part": lambda: [W.random_banded(200, 400, 1, seed=3)],
     "many_parts": lambda: [W.random_banded(480, 960, 32, seed=232)],
     "wide_interfaces": lambda: [W.random_banded(1600, 4800, 4, seed=77, tau=0.3, half_width=160)],
     "batch": lambda: [W.random_banded(300 + 50 * k, 600 + 100 * k, 3 + k, seed=k) for k in range(4)],
-    "grid_500": lambda: [W.config4()],
-    "grid_1000": lambda: [W.config1()],
+    "grid_500": lambda: [W.grid_500()],
+    "grid_1000": lambda: [W.grid_1000()],
 }
 
 

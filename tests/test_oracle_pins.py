@@ -203,7 +203,7 @@ def test_multiplicity_one_gives_exact_splitting():
 # coarse selection: independent routes and Lemma 2.4
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prob", [W.config0(), W.small_config("grid"),
+@pytest.mark.parametrize("prob", [W.banded_1000(), W.small_config("grid"),
                                   W.small_config("banded"),
                                   W.random_banded(480, 960, 32, seed=232, name="rb32")],
                          ids=lambda p: p.name)
@@ -241,7 +241,7 @@ def _stability_ratio(Cii, Ctii, nI, Z, w):
 def test_lemma24_stable_and_minimal(tau):
     """tau u_i^T C_ii u_i <= u^T Ct_i u for every u (Lemma 2.4), and dropping any
     selected vector breaks it for some u (minimality)."""
-    prob = W.config0()
+    prob = W.banded_1000()
     A = prob.scipy()
     sets = O.index_sets(A, prob.part, prob.nparts)
     rng = np.random.default_rng(5)
@@ -346,7 +346,7 @@ def test_tiny_tau_gives_one_level_asm():
 
 @pytest.mark.parametrize("variant", ["additive", "one_level"])
 def test_pcg_matches_dense_least_squares(variant):
-    prob = W.config0()
+    prob = W.banded_1000()
     A = prob.scipy()
     orc = O.Oracle(A, prob.part, prob.nparts, prob.tau, variant=variant).setup()
     sol = orc.solve(prob.b, tol=1e-12)
@@ -356,7 +356,7 @@ def test_pcg_matches_dense_least_squares(variant):
 
 
 def test_flexible_pcg_same_solution():
-    prob = W.config0()
+    prob = W.banded_1000()
     A = prob.scipy()
     orc = O.Oracle(A, prob.part, prob.nparts, prob.tau).setup()
     a = orc.solve(prob.b, tol=1e-10)
@@ -409,8 +409,8 @@ def test_adjoint_against_central_differences():
 
 
 def test_generators_are_deterministic():
-    a = W.config0()
-    b = W.config0()
+    a = W.banded_1000()
+    b = W.banded_1000()
     for f in ["indptr", "indices", "data", "b", "part"]:
         np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
     assert a.m == 3000 and a.n == 1000 and a.nnz == 9000

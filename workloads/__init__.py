@@ -11,11 +11,11 @@ from .generators import (  # noqa: F401
     random_banded,
     grid_gradient,
     irregular_clustered,
-    config0,
-    config1,
-    config2,
-    config3,
-    config4,
+    banded_1000,
+    grid_1000,
+    irregular_1m,
+    banded_batch_64,
+    grid_500,
     small_config,
     fd_entries,
 )

@@ -306,25 +306,25 @@ def irregular_clustered(n: int, m_rows: int, nparts: int, seed: int, tau: float 
 # the named workloads
 # ---------------------------------------------------------------------------
 
-def config0() -> Problem:
+def banded_1000() -> Problem:
     """Tiny plain FP64 workload: 2000 random rows + 1000 rows 0.1 e_j, n = 1000,
     8 contiguous parts, tau = 0.1, tol 1e-8, seed 0."""
-    return random_banded(1000, 2000, 8, seed=0, tau=0.1, tol=1e-8, name="config0")
+    return random_banded(1000, 2000, 8, seed=0, tau=0.1, tol=1e-8, name="banded_1000")
 
 
-def config1(G: int = 1000, P: int = 16) -> Problem:
+def grid_1000(G: int = 1000, P: int = 16) -> Problem:
     """Grid-gradient workload: 1000 x 1000 grid (n = 1e6, m = 2,998,000),
     16 x 16 = 256 square patches, tau = 0.1, seed 1."""
-    return strip_rng(grid_gradient(G, P, seed=1, tau=0.1, tol=1e-8, name="config1"))
+    return strip_rng(grid_gradient(G, P, seed=1, tau=0.1, tol=1e-8, name="grid_1000"))
 
 
-def config2(n: int = 1_000_000, m_rows: int = 3_000_000, nparts: int = 512) -> Problem:
+def irregular_1m(n: int = 1_000_000, m_rows: int = 3_000_000, nparts: int = 512) -> Problem:
     """Ill-conditioned irregular workload: 3e6 random rows + 1e6 rows 1e-4 e_j,
     512 BFS parts, tau = 0.05, seed 2."""
-    return irregular_clustered(n, m_rows, nparts, seed=2, tau=0.05, tol=1e-8, name="config2")
+    return irregular_clustered(n, m_rows, nparts, seed=2, tau=0.05, tol=1e-8, name="irregular_1m")
 
 
-def config3(count: int = 64, n_lo: float = 5e3, n_hi: float = 2e5) -> list[Problem]:
+def banded_batch_64(count: int = 64, n_lo: float = 5e3, n_hi: float = 2e5) -> list[Problem]:
     """Batched workload: ``count`` independent random-banded instances.
 
     Instance j uses default_rng(3000 + j): n_j = round(exp U(ln n_lo, ln n_hi)),
@@ -338,14 +338,14 @@ def config3(count: int = 64, n_lo: float = 5e3, n_hi: float = 2e5) -> list[Probl
         Nj = int(round(math.exp(rng.uniform(math.log(8), math.log(128)))))
         sub_seed = int(rng.integers(0, 2**31 - 1))
         probs.append(random_banded(nj, 2 * nj, Nj, seed=sub_seed, tau=0.1, tol=1e-8,
-                                   name=f"config3[{j}]"))
+                                   name=f"banded_batch_64[{j}]"))
     return probs
 
 
-def config4(G: int = 500, P: int = 16) -> Problem:
+def grid_500(G: int = 500, P: int = 16) -> Problem:
     """Differentiable workload: the grid generator at 500 x 500, tol 1e-10,
     seed 4; ``extra['x_star']`` ~ N(0,1) is drawn after b."""
-    p = grid_gradient(G, P, seed=4, tau=0.1, tol=1e-10, name="config4")
+    p = grid_gradient(G, P, seed=4, tau=0.1, tol=1e-10, name="grid_500")
     rng = p.extra.pop("rng")
     p.extra["x_star"] = rng.standard_normal(p.n)
     return p
