@@ -27,13 +27,14 @@ double ms_since(clk::time_point t0) {
 }
 int32_t roundup32(int64_t x) { return (int32_t)((x + TS - 1) / TS * TS); }
 
-// Lanes per row of the SpMV: the largest power of two not above the mean
-// row length, so that no lane of a group idles on an average row (1.67
-// entries per row of A on the 1000 x 1000 grid: one lane; 5 per row of A^T:
-// four lanes, against 4.4 and 3.6 TB/s with two and eight)
+// Lanes per row of the SpMV: the largest power of two not above half the
+// mean row length, so that a lane takes about two entries of an average row
+// (1.67 entries per row of A on the 1000 x 1000 grid: one lane, 5.0 TB/s
+// against 4.4 with two; 5 per row of A^T: two lanes, 4.7 TB/s against 4.2,
+// 3.6 and 3.4 with four, eight and one)
 int pick_group(double avg) {
   int g = 1;
-  while (g < 64 && 2 * g <= avg) g *= 2;
+  while (g < 64 && 4 * g <= avg) g *= 2;
   return g;
 }
 
