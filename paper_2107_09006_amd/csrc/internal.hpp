@@ -185,6 +185,29 @@ __device__ inline float half_pair_sum(float x) {
   return __int_as_float(r[0]) + __int_as_float(r[1]);
 }
 
+// x + x of the lane whose index differs by the DPP pattern CTRL
+template <int CTRL>
+__device__ inline double dpp_pair_sum(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return x + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane: lane pairs within
+// quads (DPP quad permutations 1032 and 2301), the two quads of each group of
+// eight (row half mirror), the two halves of each row of 16 (row mirror),
+// rows 0, 1 and 2, 3 (one cross-lane read), then the halves of the wave.
+// Each step adds two values that the partner lane adds in the other order,
+// so every lane ends with the same bits.
+__device__ inline double wave_allsum(double x) {
+  x = dpp_pair_sum<0xB1>(x);
+  x = dpp_pair_sum<0x4E>(x);
+  x = dpp_pair_sum<0x141>(x);
+  x = dpp_pair_sum<0x140>(x);
+  x += __shfl_xor(x, 16, 64);
+  return half_pair_sum(x);
+}
+
 // Orders this wave's global stores before its later loads by other lanes
 // (workgroup-scope release and acquire).
 __device__ inline void wg_fence() {

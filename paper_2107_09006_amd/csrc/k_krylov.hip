@@ -66,15 +66,14 @@ void launch_grad_vals(hipStream_t st, int32_t m, const int32_t* rowptr, const in
   k_grad_vals<<<(m + 255) / 256, 256, 0, st>>>(m, rowptr, colind, r, lam, Alam, x, out);
 }
 
+// Sum over a block of 256 threads: a sum in every wave, then the four wave
+// sums in order (the result is returned to every thread)
 __device__ inline double block_reduce_256(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
+  v = wave_allsum(v);
+  const int wave = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) sh[wave] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) sh[tid] += sh[tid + w];
-    __syncthreads();
-  }
-  return sh[0];
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // partial[s * RED_BLOCKS + b] = sum over chunk b of segment s of a .* b

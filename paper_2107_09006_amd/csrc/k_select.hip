@@ -35,29 +35,6 @@ constexpr double SEL_EPS = 2.220446049250313e-16;
 // ----------------------------------------------------------------------------
 // block-wide reductions (a wave sum, one LDS round across waves)
 // ----------------------------------------------------------------------------
-// x + x of the lane whose index differs by the DPP pattern CTRL
-template <int CTRL>
-__device__ inline double dpp_pair_sum(double x) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
-  return x + __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes, the same value in every lane: lane pairs within
-// quads (DPP quad permutations 1032 and 2301), the two quads of each group of
-// eight (row half mirror), the two halves of each row of 16 (row mirror),
-// rows 0, 1 and 2, 3 (one cross-lane read), then the halves of the wave.
-// Each step adds two values that the partner lane adds in the other order,
-// so every lane ends with the same bits.
-__device__ inline double wave_allsum(double x) {
-  x = dpp_pair_sum<0xB1>(x);
-  x = dpp_pair_sum<0x4E>(x);
-  x = dpp_pair_sum<0x141>(x);
-  x = dpp_pair_sum<0x140>(x);
-  x += __shfl_xor(x, 16, 64);
-  return half_pair_sum(x);
-}
-
 __device__ inline double wg_sum(double v, double* red) {
   v = wave_allsum(v);
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
