@@ -314,7 +314,7 @@ class Oracle:
     part: np.ndarray
     nparts: int
     tau: float
-    variant: str = "additive"          # or "one_level"
+    variant: str = "additive"          # or "one_level", "balanced"
     nev_max: int = 0
     sets: list = field(default_factory=list)
     chol: list = field(default_factory=list)
@@ -346,7 +346,7 @@ class Oracle:
             s = self.sets[i]
             Cii, Ctii = local_matrices(A, s)
             self.chol[i] = sla.cho_factor(Cii, lower=True)
-            if self.variant == "additive":
+            if self.variant in ("additive", "balanced"):
                 res = coarse_vectors(Cii, Ctii, s.nI, self.tau, self.nev_max)
                 self.X[i] = res["X"]
                 self.info[i] = res
@@ -372,14 +372,37 @@ class Oracle:
             self.cholE = sla.cho_factor(self.E, lower=True)
         return self
 
-    def apply(self, r: np.ndarray) -> np.ndarray:
-        """z = M r with M = sum_i R_i^T C_ii^{-1} R_i (+ R_0^T C_00^{-1} R_0)."""
+    def apply_one_level(self, r: np.ndarray) -> np.ndarray:
+        """M_ASM r = sum_{i >= 1} R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz)."""
         z = np.zeros(self.n)
         for s, F in zip(self.sets, self.chol):
             Om = s.Omega
             z[Om] += sla.cho_solve(F, r[Om])
-        if self.cholE is not None:
-            z += self.R0T @ sla.cho_solve(self.cholE, self.R0T.T @ r)
+        return z
+
+    def apply_coarse(self, r: np.ndarray) -> np.ndarray:
+        """Q r with Q = R_0^T C_00^{-1} R_0 and C_00 = E = R_0 C R_0^T."""
+        if self.cholE is None:
+            return np.zeros(self.n)
+        return self.R0T @ sla.cho_solve(self.cholE, self.R0T.T @ r)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """z = M r.
+
+        additive (eq. two_level_schwarz): M = M_ASM + Q.
+        one_level: M = M_ASM.
+        balanced (eq. balanced, with M_ASM as the first level):
+        M = Q + (I - C Q)^T M_ASM (I - C Q); C and Q are symmetric, so
+        (I - C Q)^T = I - Q C.  C is applied as A^T (A .)."""
+        A = self.A
+        if self.variant == "balanced":
+            Qr = self.apply_coarse(r)
+            v = r - A.T @ (A @ Qr)                  # (I - C Q) r
+            y = self.apply_one_level(v)             # M_ASM (I - C Q) r
+            return Qr + y - self.apply_coarse(A.T @ (A @ y))
+        z = self.apply_one_level(r)
+        if self.variant == "additive":
+            z += self.apply_coarse(r)
         return z
 
     def solve(self, b: np.ndarray, tol: float = 1e-8, maxit: int = 10000,

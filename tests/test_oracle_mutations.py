@@ -117,3 +117,29 @@ def test_adjoint_with_wrong_sign_is_caught(monkeypatch):
     monkeypatch.setattr(O.Oracle, "backward", bad)
     with pytest.raises(AssertionError):
         P.test_adjoint_against_central_differences()
+
+
+def test_balanced_without_first_coarse_term_is_caught(monkeypatch):
+    """Dropped term: M r = (I - Q C) M_ASM (I - C Q) r without the leading Q r."""
+    def bad(self, r):
+        A = self.A
+        Qr = self.apply_coarse(r)
+        y = self.apply_one_level(r - A.T @ (A @ Qr))
+        return y - self.apply_coarse(A.T @ (A @ y))
+    monkeypatch.setattr(OM.Oracle, "apply", bad)
+    with pytest.raises(AssertionError):
+        P.test_balanced_coarse_space_is_unit_eigenspace()
+
+
+def test_balanced_with_untransposed_left_factor_is_caught(monkeypatch):
+    """Transposed operand: (I - C Q) on the left instead of (I - C Q)^T."""
+    def bad(self, r):
+        A = self.A
+        Qr = self.apply_coarse(r)
+        y = self.apply_one_level(r - A.T @ (A @ Qr))
+        return Qr + y - A.T @ (A @ self.apply_coarse(y))
+    monkeypatch.setattr(OM.Oracle, "apply", bad)
+    with pytest.raises(AssertionError):
+        P.test_balanced_correction_is_C_orthogonal_to_coarse_space()
+    with pytest.raises(AssertionError):
+        P.test_balanced_is_symmetric_positive_definite()

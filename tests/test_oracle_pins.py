@@ -344,7 +344,7 @@ def test_tiny_tau_gives_one_level_asm():
                                atol=1e-12 * np.abs(Masm).max())
 
 
-@pytest.mark.parametrize("variant", ["additive", "one_level"])
+@pytest.mark.parametrize("variant", ["additive", "one_level", "balanced"])
 def test_pcg_matches_dense_least_squares(variant):
     prob = W.banded_1000()
     A = prob.scipy()
@@ -353,6 +353,77 @@ def test_pcg_matches_dense_least_squares(variant):
     xs = np.linalg.lstsq(A.toarray(), prob.b, rcond=None)[0]
     assert np.linalg.norm(sol["x"] - xs) <= 1e-9 * np.linalg.norm(xs)
     assert sol["relres"] <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# balanced two-level form (eq. balanced): properties fixed by C, Q and E
+# ---------------------------------------------------------------------------
+
+def _balanced_small():
+    prob = W.random_banded(240, 480, 6, seed=5)
+    A = prob.scipy()
+    orc = O.Oracle(A, prob.part, prob.nparts, 0.3, variant="balanced").setup()
+    assert orc.n0 > 0
+    return A, orc
+
+
+def test_balanced_coarse_space_is_unit_eigenspace():
+    """M C R_0^T = R_0^T: with E = R_0 C R_0^T, (I - C Q) C R_0^T = 0 and
+    Q C R_0^T = R_0^T, so every coarse vector is an eigenvector of M C with
+    eigenvalue 1."""
+    A, orc = _balanced_small()
+    CR0T = (A.T @ (A @ orc.R0T)).toarray()
+    R0T = orc.R0T.toarray()
+    MC = np.column_stack([orc.apply(CR0T[:, k]) for k in range(orc.n0)])
+    np.testing.assert_allclose(MC, R0T, atol=1e-9 * np.abs(R0T).max())
+
+
+def test_balanced_correction_is_C_orthogonal_to_coarse_space():
+    """R_0 C (M r - Q r) = 0: the first-level part leaves the coarse space
+    C-orthogonally, since R_0 C (I - Q C) = 0."""
+    A, orc = _balanced_small()
+    rng = np.random.default_rng(1)
+    C = (A.T @ A).toarray()
+    for _ in range(3):
+        r = rng.standard_normal(orc.n)
+        d = orc.apply(r) - orc.apply_coarse(r)
+        lhs = orc.R0T.T @ (C @ d)
+        scale = np.abs(orc.R0T.T @ (C @ np.abs(d))).max()
+        assert np.abs(lhs).max() <= 1e-11 * scale
+
+
+def test_balanced_is_symmetric_positive_definite():
+    """Symmetric when M_ASM is (the paper states it), and positive definite:
+    the eigenvalues of L^T M L (C = L L^T) are those of M C, all positive,
+    with the n_0 unit ones of the coarse space among them."""
+    A, orc = _balanced_small()
+    M = O.dense_preconditioner(orc)
+    np.testing.assert_allclose(M, M.T, atol=1e-12 * np.abs(M).max())
+    Lc = np.linalg.cholesky((A.T @ A).toarray())
+    ev = sla.eigvalsh(Lc.T @ M @ Lc)
+    assert ev.min() > 0
+    assert np.sum(np.abs(ev - 1.0) < 1e-8) >= orc.n0
+
+
+def test_balanced_without_coarse_space_is_one_level():
+    """n_0 = 0 (tau tiny): Q = 0, so the balanced form is M_ASM."""
+    prob = W.random_banded(240, 480, 6, seed=5)
+    A = prob.scipy()
+    bal = O.Oracle(A, prob.part, prob.nparts, 1e-12, variant="balanced").setup()
+    one = O.Oracle(A, prob.part, prob.nparts, 1e-12, variant="one_level").setup()
+    assert bal.n0 == 0
+    r = np.random.default_rng(2).standard_normal(bal.n)
+    np.testing.assert_allclose(bal.apply(r), one.apply(r), rtol=0, atol=0)
+
+
+def test_balanced_needs_no_more_iterations_than_additive():
+    """The balanced form converges at least as fast as the additive one on the
+    banded 1000-column problem (its spectrum clusters the coarse space at 1)."""
+    prob = W.banded_1000()
+    A = prob.scipy()
+    its = {v: O.Oracle(A, prob.part, prob.nparts, prob.tau, variant=v).setup()
+           .solve(prob.b, tol=1e-8)["its"] for v in ["additive", "balanced"]}
+    assert its["balanced"] <= its["additive"]
 
 
 def test_flexible_pcg_same_solution():
