@@ -45,12 +45,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+VARIANT = 0   # preconditioner variant (0 additive, 2 balanced), from --variant
+
+
 def run_step(L, dev, prob, precision):
     """setup + solve + destroy; returns (ms, solve info, setup info)."""
     import torch
     t0 = time.perf_counter()
     s = L.Solver(dev["rowptr"], dev["colind"], dev["vals"], prob.part, prob.nparts, prob.m,
-                 prob.n, prob.tau, device="cuda:0", precision=precision, tol=prob.tol)
+                 prob.n, prob.tau, device="cuda:0", precision=precision, tol=prob.tol,
+                 variant=VARIANT, flexible=int(VARIANT == 2 and precision == 1))
     x, info, _ = s.solve(dev["b"], x=dev["x"])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
@@ -127,7 +131,11 @@ def main():
     ap.add_argument("--grid", type=int, default=1000)
     ap.add_argument("--patches", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", choices=["additive", "balanced"], default="additive",
+                    help="second-level form (eq. two_level_schwarz or eq. balanced)")
     args = ap.parse_args()
+    global VARIANT
+    VARIANT = 2 if args.variant == "balanced" else 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -208,7 +216,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"grid_gradient {args.grid}x{args.grid}, {args.patches}x{args.patches} patches",
                    "m": prob.m, "n": prob.n, "nnz": prob.nnz, "nparts": prob.nparts,
-                   "tau": prob.tau, "tol": prob.tol, "overlap": 1},
+                   "tau": prob.tau, "tol": prob.tol, "overlap": 1, "variant": args.variant},
         "iterations": its,
         "relres": mixed["info"]["relres"],
         "setup_ms": round(mixed["setup_ms"], 2),

@@ -49,7 +49,13 @@ typedef enum {
 } lsq2l_status;
 
 enum { LSQ2L_FP64 = 0, LSQ2L_MIXED = 1 };           /* lsq2l_options.precision */
-enum { LSQ2L_ADDITIVE = 0, LSQ2L_ONE_LEVEL = 1 };   /* lsq2l_options.variant   */
+/* lsq2l_options.variant.  ADDITIVE: M = M_ASM + Q (eq. two_level_schwarz).
+ * ONE_LEVEL: M = M_ASM (eq. one_level_schwarz), no coarse space is computed.
+ * BALANCED: M = Q + (I - C Q)^T M_ASM (I - C Q) (eq. balanced), the paper's
+ * choice in practice with M_ASM; same setup as ADDITIVE, and each application
+ * costs two coarse corrections and two products with C = A^T A more.
+ * Q = R_0^T E^{-1} R_0 with E = R_0 C R_0^T in all three. */
+enum { LSQ2L_ADDITIVE = 0, LSQ2L_ONE_LEVEL = 1, LSQ2L_BALANCED = 2 };
 
 typedef struct {
   double  tol;        /* stop when ||A^T(b - A x)||_2 <= tol ||A^T b||_2 (default 1e-8)          */
@@ -60,7 +66,8 @@ typedef struct {
                          (E is built from the double basis); all accumulation, recurrences, dot
                          products, residuals and the coarse solve stay double                   */
   int32_t flexible;   /* 1: flexible PCG, beta = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k)          */
-  int32_t variant;    /* LSQ2L_ADDITIVE (two-level, default) or LSQ2L_ONE_LEVEL (M_ASM)           */
+  int32_t variant;    /* LSQ2L_ADDITIVE (two-level, default), LSQ2L_ONE_LEVEL (M_ASM) or
+                         LSQ2L_BALANCED (eq. balanced); any other value returns LSQ2L_EINVAL    */
   int32_t nev_max;    /* keep at most this many coarse vectors per subdomain (0 = no cap)         */
   int32_t check_every;/* read the residual norm back every this many iterations (default 1)       */
   int32_t use_graph;  /* 1: capture one PCG iteration (SpMVs, dot products, scalar updates, M r)
@@ -155,7 +162,8 @@ lsq2l_status lsq2l_backward(lsq2l_handle h, const double* g, double* dLdb, doubl
 /* y = A x (trans = 0; x has n, y has m entries) or y = A^T x (trans = 1), device. */
 lsq2l_status lsq2l_spmv(lsq2l_handle h, int32_t trans, const double* x, double* y);
 
-/* z = M r with the preconditioner of the handle (device, n entries each). */
+/* z = M r with the preconditioner of the handle (device, n entries each).
+ * z may be r itself. */
 lsq2l_status lsq2l_apply_preconditioner(lsq2l_handle h, const double* r, double* z);
 
 /* Sizes and phase timings of the setup. */

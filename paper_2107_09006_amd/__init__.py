@@ -7,6 +7,6 @@ The compute path is the HIP library ``liblsq2l.so`` (C ABI in
 from .binding import (  # noqa: F401
     Solver, solver_from_problem, load_library, default_options, release_cache, Lsq2lError,
     OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN,
-    FP64, MIXED, ADDITIVE, ONE_LEVEL, EXPORTS,
+    FP64, MIXED, ADDITIVE, ONE_LEVEL, BALANCED, EXPORTS,
 )
 from .autograd import LeastSquaresSolve, lstsq  # noqa: F401,E402

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblsq2l.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
-ADDITIVE, ONE_LEVEL = 0, 1
+ADDITIVE, ONE_LEVEL, BALANCED = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
                 -4: "CHOL_BREAKDOWN", -5: "PCG_BREAKDOWN"}
@@ -245,10 +245,11 @@ class Solver:
                                   _dev(y, torch.float64)))
         return y
 
-    def apply_preconditioner(self, r):
+    def apply_preconditioner(self, r, out=None):
+        """z = M r; ``out`` (n doubles on the device, may be ``r``) receives z."""
         import torch
         lib = load_library()
-        z = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        z = torch.empty(self.n, dtype=torch.float64, device=self.device) if out is None else out
         with torch.cuda.device(self.device):
             _check(lib.lsq2l_apply_preconditioner(self.handle, _dev(r, torch.float64),
                                                   _dev(z, torch.float64)))

@@ -206,6 +206,7 @@ struct lsq2l_ctx {
   double *tm = nullptr, *tm2 = nullptr, *loc = nullptr, *cvec = nullptr, *dvec = nullptr;
   double *partial = nullptr, *partial2 = nullptr, *xwork = nullptr;
   double *bsave = nullptr, *xsave = nullptr;
+  double *bal_u = nullptr, *bal_w = nullptr;   // balanced form: two n-vectors
   bool have_solution = false;
   Scalars sc{};
   int32_t* status = nullptr;
@@ -352,9 +353,67 @@ lsq2l_status validate_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t
   return LSQ2L_OK;
 }
 
+void spmv_A(lsq2l_ctx* c, const double* x, double* y);
+void spmv_AT(lsq2l_ctx* c, const double* y, double* x);
+
+// z = Q r = R_0^T E^{-1} R_0 r (restriction, symmetric E^{-1} product, prolongation)
+void apply_Q(lsq2l_ctx* c, const double* r, double* z) {
+  const hipStream_t st = c->st;
+  if (c->X32) {
+    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
+    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+    launch_scatter_local(st, c->M.n, c->P, c->scale, nullptr, c->X32, c->dvec, z);
+  } else {
+    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
+    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+    launch_scatter_local(st, c->M.n, c->P, c->scale, nullptr, c->X, c->dvec, z);
+  }
+}
+
+// z = M_ASM r = sum_i R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz)
+void apply_one_level(lsq2l_ctx* c, const double* r, double* z) {
+  const hipStream_t st = c->st;
+  launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
+  if (c->opt.precision == LSQ2L_MIXED)
+    launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
+  else
+    launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
+  if (c->X32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, nullptr, z);
+  else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, nullptr, z);
+}
+
+// Balanced form (eq. balanced) with M_ASM as the first level:
+// M r = Q r + (I - Q C) M_ASM (I - C Q) r, evaluated as
+//   u = Q r;  y = M_ASM (r - C u);  z = y + Q (r - C y),
+// C applied as A^T (A .).  Two coarse corrections, four SpMVs, one set of
+// local solves per application.
+void apply_M_balanced(lsq2l_ctx* c, const double* r, double* z) {
+  const hipStream_t st = c->st;
+  const int64_t n = c->M.n;
+  if (z == r) {                 // r is read again after z is first written
+    launch_copy(st, n, r, c->rold);
+    r = c->rold;
+  }
+  apply_Q(c, r, c->bal_u);
+  spmv_A(c, c->bal_u, c->tm2);
+  spmv_AT(c, c->tm2, c->bal_w);
+  launch_sub(st, n, r, c->bal_w, c->bal_w);            // (I - C Q) r
+  apply_one_level(c, c->bal_w, z);                      // y
+  spmv_A(c, z, c->tm2);
+  spmv_AT(c, c->tm2, c->bal_w);
+  launch_sub(st, n, r, c->bal_w, c->bal_w);            // r - C y
+  apply_Q(c, c->bal_w, c->bal_u);
+  launch_add(st, n, z, c->bal_u, z);
+}
+
 // z = M r: local solves (eq. one_level_schwarz) plus the coarse correction
-// R_0^T E^{-1} R_0 r (eq. two_level_schwarz).
+// R_0^T E^{-1} R_0 r (eq. two_level_schwarz), or the balanced form.
 void apply_M(lsq2l_ctx* c, const double* r, double* z) {
+  if (c->opt.variant == LSQ2L_BALANCED) {
+    if (c->coarse) apply_M_balanced(c, r, z);
+    else apply_one_level(c, r, z);
+    return;
+  }
   const hipStream_t st = c->st;
   launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
   if (c->opt.precision == LSQ2L_MIXED)
@@ -640,7 +699,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   c->n0 = 0;
   c->n0tot = 0;
   t0 = clk::now();
-  if (c->opt.variant == LSQ2L_ADDITIVE) {
+  if (c->opt.variant != LSQ2L_ONE_LEVEL) {
     double *Tg = nullptr, *work = nullptr, *sig = nullptr;
     int32_t* pc = nullptr;
     TRY(c->dalloc(&Tg, H.total_g));
@@ -834,6 +893,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->dalloc(&c->xsave, n));
   TRY(c->dalloc(&c->tm, m));
   TRY(c->dalloc(&c->tm2, m));
+  if (c->opt.variant == LSQ2L_BALANCED) {
+    TRY(c->dalloc(&c->bal_u, n));
+    TRY(c->dalloc(&c->bal_w, n));
+  }
   TRY(c->dalloc(&c->bsave, m));
   TRY(c->dalloc(&c->loc, H.total_loc));
   TRY(c->dalloc(&c->partial, (int64_t)c->S * RED_BLOCKS));
@@ -873,7 +936,8 @@ lsq2l_status check_common(double tau, const lsq2l_options* opt) {
     if (!(opt->tol > 0.0)) { set_error("tol must be positive"); return LSQ2L_EINVAL; }
     if (opt->max_it < 1) { set_error("max_it must be >= 1"); return LSQ2L_EINVAL; }
     if (opt->precision != LSQ2L_FP64 && opt->precision != LSQ2L_MIXED) { set_error("bad precision"); return LSQ2L_EINVAL; }
-    if (opt->variant != LSQ2L_ADDITIVE && opt->variant != LSQ2L_ONE_LEVEL) { set_error("bad variant"); return LSQ2L_EINVAL; }
+    if (opt->variant != LSQ2L_ADDITIVE && opt->variant != LSQ2L_ONE_LEVEL &&
+        opt->variant != LSQ2L_BALANCED) { set_error("bad variant"); return LSQ2L_EINVAL; }
     if (opt->nev_max < 0) { set_error("nev_max must be >= 0"); return LSQ2L_EINVAL; }
   }
   return LSQ2L_OK;

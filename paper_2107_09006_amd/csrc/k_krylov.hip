@@ -202,6 +202,17 @@ void launch_sub(hipStream_t st, int64_t n, const double* a, const double* b, dou
   k_sub<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, b, out);
 }
 
+__global__ void k_add(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
+  if (n == 0) return;
+  k_add<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, b, out);
+}
+
 __global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) out[k] = v;

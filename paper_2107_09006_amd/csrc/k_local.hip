@@ -280,6 +280,7 @@ k_gather_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ ome
 
 // z_j = sum over the subdomains holding column j of S_pos loc_pos (fixed
 // order), plus the coarse prolongation X_i d_i on the interior of its owner.
+// Without loc only the prolongation is formed, without dcoarse only the sum.
 template <typename TX>
 __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
                                 const int32_t* __restrict__ own_pos, const double* __restrict__ scale,
@@ -290,10 +291,11 @@ __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double s = 0.0;
-  for (int q = own_ptr[j]; q < own_ptr[j + 1]; ++q) {
-    const int pos = own_pos[q];
-    s += scale[pos] * loc[pos];
-  }
+  if (loc != nullptr)
+    for (int q = own_ptr[j]; q < own_ptr[j + 1]; ++q) {
+      const int pos = own_pos[q];
+      s += scale[pos] * loc[pos];
+    }
   if (dcoarse != nullptr) {
     const SubDesc d = subs[part[j]];
     const int a = locown[j];

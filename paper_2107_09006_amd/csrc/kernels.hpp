@@ -85,6 +85,7 @@ void launch_axpy_xr(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, co
 void launch_xpby(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const double* beta,
                  const double* z, double* p);
 void launch_sub(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
+void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_fill(hipStream_t st, int64_t n, double v, double* out);
 void launch_copy(hipStream_t st, int64_t n, const double* a, double* out);
 
