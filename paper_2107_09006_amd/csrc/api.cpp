@@ -190,6 +190,8 @@ struct lsq2l_ctx {
   int64_t* d_seg_row = nullptr;
   int64_t* d_seg_col = nullptr;
   DevMatrix M;
+  DevMatrix Mi;             // row-permuted copy of A and its transpose for C p = A^T (A p)
+  bool row_perm = false;    // Mi is in use
   DevPlan P;
   DevCoarse Cc;
   HostPlan H;
@@ -353,8 +355,8 @@ lsq2l_status validate_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t
   return LSQ2L_OK;
 }
 
-void spmv_A(lsq2l_ctx* c, const double* x, double* y);
-void spmv_AT(lsq2l_ctx* c, const double* y, double* x);
+void spmv_it_A(lsq2l_ctx* c, const double* x, double* y);
+void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x);
 
 // z = Q r = R_0^T E^{-1} R_0 r (restriction, symmetric E^{-1} product, prolongation)
 void apply_Q(lsq2l_ctx* c, const double* r, double* z) {
@@ -395,12 +397,12 @@ void apply_M_balanced(lsq2l_ctx* c, const double* r, double* z) {
     r = c->rold;
   }
   apply_Q(c, r, c->bal_u);
-  spmv_A(c, c->bal_u, c->tm2);
-  spmv_AT(c, c->tm2, c->bal_w);
+  spmv_it_A(c, c->bal_u, c->tm2);
+  spmv_it_AT(c, c->tm2, c->bal_w);
   launch_sub(st, n, r, c->bal_w, c->bal_w);            // (I - C Q) r
   apply_one_level(c, c->bal_w, z);                      // y
-  spmv_A(c, z, c->tm2);
-  spmv_AT(c, c->tm2, c->bal_w);
+  spmv_it_A(c, z, c->tm2);
+  spmv_it_AT(c, c->tm2, c->bal_w);
   launch_sub(st, n, r, c->bal_w, c->bal_w);            // r - C y
   apply_Q(c, c->bal_w, c->bal_u);
   launch_add(st, n, z, c->bal_u, z);
@@ -428,6 +430,18 @@ void apply_M(lsq2l_ctx* c, const double* r, double* z) {
   }
   if (x32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, c->coarse ? c->dvec : nullptr, z);
   else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
+}
+
+// C p = A^T (A p) inside the iteration.  A p never leaves the library, so it
+// may be formed with a row-permuted copy of A: C = A^T A is the same for any
+// row order of A.
+void spmv_it_A(lsq2l_ctx* c, const double* x, double* y) {
+  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
+  launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, x, y, M.spmv_group);
+}
+void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x) {
+  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
+  launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, y, x, M.spmvt_group);
 }
 
 void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
@@ -463,8 +477,8 @@ lsq2l_status capture_iteration(lsq2l_ctx* c, double* x, double tol2, hipGraphExe
   if (e == hipSuccess) {
     c->st = c->gst;
     const hipStream_t st = c->st;
-    spmv_A(c, c->p, c->tm);
-    spmv_AT(c, c->tm, c->q);
+    spmv_it_A(c, c->p, c->tm);
+    spmv_it_AT(c, c->tm, c->q);
     launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
     launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
     if (flexible) launch_copy(st, n, c->r, c->rold);
@@ -533,8 +547,8 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
     }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     while (!all_done && its < c->opt.max_it) {
-      spmv_A(c, c->p, c->tm);
-      spmv_AT(c, c->tm, c->q);
+      spmv_it_A(c, c->p, c->tm);
+      spmv_it_AT(c, c->tm, c->q);
       launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
       launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
       if (flexible) LSQ2L_HIP_TRY(hipMemcpyAsync(c->rold, c->r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -558,8 +572,8 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
       launch_xpby(st, n, S, c->d_seg_col, c->sc.beta, c->z, c->p);
     }
     // true residual rhs - A^T A x
-    spmv_A(c, x, c->tm);
-    spmv_AT(c, c->tm, c->q);
+    spmv_it_A(c, x, c->tm);
+    spmv_it_AT(c, c->tm, c->q);
     launch_sub(st, n, c->rhs, c->q, c->q);
     launch_dot(st, S, c->d_seg_col, c->q, c->q, c->partial);
     LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_done, c->sc.done, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
@@ -628,10 +642,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   PinnedArray<int32_t> trp, tcol;
   TRY(trp.alloc((int64_t)n + 1));
   TRY(tcol.alloc(nnz));
+  int32_t *keys = nullptr, *vals = nullptr, *rows = nullptr;
+  char* temp = nullptr;
+  const size_t tb = transpose_temp_bytes(nnz, n);
   {
-    int32_t *keys = nullptr, *vals = nullptr, *rows = nullptr;
-    char* temp = nullptr;
-    const size_t tb = transpose_temp_bytes(nnz, n);
     TRY(c->dalloc(&c->M.trowptr, (int64_t)n + 1));
     TRY(c->dalloc(&c->M.trow, nnz));
     TRY(c->dalloc(&c->M.tperm, nnz));
@@ -649,6 +663,44 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   launch_gather_values(st, nnz, c->M.tperm, c->M.vals, c->M.tvals);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
+  // Row order of the copy used for C p = A^T (A p): when consecutive rows of
+  // A start at unrelated columns (more than one descent of the first column
+  // per 16 rows), the rows are sorted stably by their first column, so that
+  // the x gathers of A p and the (A p) gathers of A^T (A p) stay local.
+  {
+    auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
+    int64_t desc = 0;
+    for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
+    c->row_perm = m >= 65536 && desc * 16 > m;
+    if (c->row_perm) {
+      std::vector<int32_t> start((size_t)n + 2, 0), perm((size_t)m), prp((size_t)m + 1);
+      for (int32_t i = 0; i < m; ++i) ++start[(size_t)key(i) + 1];
+      for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+      for (int32_t i = 0; i < m; ++i) perm[start[key(i)]++] = i;
+      prp[0] = 0;
+      for (int32_t i = 0; i < m; ++i) prp[(size_t)i + 1] = prp[i] + (rp[perm[i] + 1] - rp[perm[i]]);
+      DevMatrix& Mi = c->Mi;
+      Mi.m = m;
+      Mi.n = n;
+      Mi.nnz = nnz;
+      Mi.spmv_group = c->M.spmv_group;
+      Mi.spmvt_group = c->M.spmvt_group;
+      int32_t* dperm = nullptr;
+      TRY(c->upload(&dperm, perm));
+      TRY(c->upload(&Mi.rowptr, prp));
+      TRY(c->dalloc(&Mi.colind, nnz));
+      TRY(c->dalloc(&Mi.vals, nnz));
+      TRY(c->dalloc(&Mi.trowptr, (int64_t)n + 1));
+      TRY(c->dalloc(&Mi.trow, nnz));
+      TRY(c->dalloc(&Mi.tperm, nnz));
+      TRY(c->dalloc(&Mi.tvals, nnz));
+      launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
+      LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.trowptr, Mi.trow, Mi.tperm,
+                                     keys, vals, rows, temp, tb));
+      launch_gather_values(st, nnz, Mi.tperm, Mi.vals, Mi.tvals);
+      LSQ2L_HIP_TRY(hipStreamSynchronize(st));   // perm and prp are host vectors of this scope
+    }
+  }
   std::string err;
   if (!plan_build(m, n, rp, ci, trp.p, tcol.p, part.data(), nparts, seg_of_part, c->H, err)) {
     set_error(err);
@@ -1205,8 +1257,8 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
   LSQ2L_HIP_TRY(hipEventCreate(&e1));
   auto once = [&]() {
     switch (kernel) {
-      case 0: spmv_A(c, c->p, c->tm); break;
-      case 1: spmv_AT(c, c->tm, c->q); break;
+      case 0: spmv_it_A(c, c->p, c->tm); break;
+      case 1: spmv_it_AT(c, c->tm, c->q); break;
       case 2:
         if (c->opt.precision == LSQ2L_MIXED) launch_local_solve_f32(c->st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
         else launch_local_solve(c->st, c->nsub, c->P, c->fac, c->dinv, c->loc);

@@ -37,6 +37,29 @@ __global__ void k_gather_i32(int64_t n, const int32_t* __restrict__ idx, const i
   if (k < n) dst[k] = src[idx[k]];
 }
 
+// Row i of the row-permuted copy is row perm[i] of A (one thread per row;
+// prowptr holds the permuted row starts).
+__global__ void k_permute_rows(int32_t m, const int32_t* __restrict__ perm,
+                               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                               const double* __restrict__ vals, const int32_t* __restrict__ prowptr,
+                               int32_t* __restrict__ pcolind, double* __restrict__ pvals) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t r = perm[i];
+  int32_t d = prowptr[i];
+  for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k, ++d) {
+    pcolind[d] = colind[k];
+    pvals[d] = vals[k];
+  }
+}
+
+void launch_permute_rows(hipStream_t st, int32_t m, const int32_t* perm, const int32_t* rowptr,
+                         const int32_t* colind, const double* vals, const int32_t* prowptr,
+                         int32_t* pcolind, double* pvals) {
+  if (m == 0) return;
+  k_permute_rows<<<(m + 255) / 256, 256, 0, st>>>(m, perm, rowptr, colind, vals, prowptr, pcolind, pvals);
+}
+
 static int key_bits(int32_t n) {
   int b = 1;
   while (b < 31 && ((int64_t)1 << b) < n) ++b;

@@ -57,6 +57,9 @@ constexpr int ESYM_ROWTILES = 8;
 
 // --- device transpose of A's pattern ---------------------------------------
 size_t transpose_temp_bytes(int64_t nnz, int32_t n);
+void launch_permute_rows(hipStream_t st, int32_t m, const int32_t* perm, const int32_t* rowptr,
+                         const int32_t* colind, const double* vals, const int32_t* prowptr,
+                         int32_t* pcolind, double* pvals);
 hipError_t launch_transpose(hipStream_t st, int32_t m, int32_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* colind, int32_t* trowptr, int32_t* trow, int32_t* tperm,
                             int32_t* work_keys, int32_t* work_vals, int32_t* work_rows, void* temp,
