@@ -629,6 +629,40 @@ struct MapsJob {
 };
 
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
+// When consecutive rows of A start at unrelated columns (more than one
+// descent of the first column per 16 rows, at least 65,536 rows), the rows
+// sorted stably by their first column (counting sort): perm[i] is the row of A
+// placed at i, prp the row starts of the permuted copy.  The x gathers of A p
+// and the (A p) gathers of A^T (A p) then stay local.
+// a thread joined on every exit from the scope that owns it
+struct JoiningThread {
+  std::thread t;
+  ~JoiningThread() {
+    if (t.joinable()) t.join();
+  }
+};
+
+struct RowOrder {
+  bool use = false;
+  std::vector<int32_t> perm, prp;
+};
+
+void row_order(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, RowOrder& ro) {
+  auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
+  int64_t desc = 0;
+  for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
+  ro.use = m >= 65536 && desc * 16 > m;
+  if (!ro.use) return;
+  std::vector<int32_t> start((size_t)n + 2, 0);
+  ro.perm.resize((size_t)m);
+  ro.prp.resize((size_t)m + 1);
+  for (int32_t i = 0; i < m; ++i) ++start[(size_t)key(i) + 1];
+  for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+  for (int32_t i = 0; i < m; ++i) ro.perm[start[key(i)]++] = i;
+  ro.prp[0] = 0;
+  for (int32_t i = 0; i < m; ++i) ro.prp[(size_t)i + 1] = ro.prp[i] + (rp[ro.perm[i] + 1] - rp[ro.perm[i]]);
+}
+
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const std::vector<int32_t>& part, int32_t nparts,
                         const std::vector<int32_t>& seg_of_part) {
@@ -663,44 +697,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   launch_gather_values(st, nnz, c->M.tperm, c->M.vals, c->M.tvals);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
-  // Row order of the copy used for C p = A^T (A p): when consecutive rows of
-  // A start at unrelated columns (more than one descent of the first column
-  // per 16 rows), the rows are sorted stably by their first column, so that
-  // the x gathers of A p and the (A p) gathers of A^T (A p) stay local.
-  {
-    auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
-    int64_t desc = 0;
-    for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
-    c->row_perm = m >= 65536 && desc * 16 > m;
-    if (c->row_perm) {
-      std::vector<int32_t> start((size_t)n + 2, 0), perm((size_t)m), prp((size_t)m + 1);
-      for (int32_t i = 0; i < m; ++i) ++start[(size_t)key(i) + 1];
-      for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
-      for (int32_t i = 0; i < m; ++i) perm[start[key(i)]++] = i;
-      prp[0] = 0;
-      for (int32_t i = 0; i < m; ++i) prp[(size_t)i + 1] = prp[i] + (rp[perm[i] + 1] - rp[perm[i]]);
-      DevMatrix& Mi = c->Mi;
-      Mi.m = m;
-      Mi.n = n;
-      Mi.nnz = nnz;
-      Mi.spmv_group = c->M.spmv_group;
-      Mi.spmvt_group = c->M.spmvt_group;
-      int32_t* dperm = nullptr;
-      TRY(c->upload(&dperm, perm));
-      TRY(c->upload(&Mi.rowptr, prp));
-      TRY(c->dalloc(&Mi.colind, nnz));
-      TRY(c->dalloc(&Mi.vals, nnz));
-      TRY(c->dalloc(&Mi.trowptr, (int64_t)n + 1));
-      TRY(c->dalloc(&Mi.trow, nnz));
-      TRY(c->dalloc(&Mi.tperm, nnz));
-      TRY(c->dalloc(&Mi.tvals, nnz));
-      launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
-      LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.trowptr, Mi.trow, Mi.tperm,
-                                     keys, vals, rows, temp, tb));
-      launch_gather_values(st, nnz, Mi.tperm, Mi.vals, Mi.tvals);
-      LSQ2L_HIP_TRY(hipStreamSynchronize(st));   // perm and prp are host vectors of this scope
-    }
-  }
+  // Row order of the copy used for C p = A^T (A p), found on a host thread
+  // while the device assembles, factors and selects (see row_order).
+  RowOrder ro;
+  JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci]() { row_order(m, n, rp, ci, ro); })};
   std::string err;
   if (!plan_build(m, n, rp, ci, trp.p, tcol.p, part.data(), nparts, seg_of_part, c->H, err)) {
     set_error(err);
@@ -933,6 +933,31 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     TRY(c->dalloc(&c->dinv32, H.total_dinv));
     launch_to_float(st, H.total_fac, c->fac, c->fac32);
     launch_to_float(st, H.total_dinv, c->dinv, c->dinv32);
+  }
+  // --- row-permuted iteration copy of A
+  ro_thread.t.join();
+  c->row_perm = ro.use;
+  if (c->row_perm) {
+    DevMatrix& Mi = c->Mi;
+    Mi.m = m;
+    Mi.n = n;
+    Mi.nnz = nnz;
+    Mi.spmv_group = c->M.spmv_group;
+    Mi.spmvt_group = c->M.spmvt_group;
+    int32_t* dperm = nullptr;
+    TRY(c->upload(&dperm, ro.perm));
+    TRY(c->upload(&Mi.rowptr, ro.prp));
+    TRY(c->dalloc(&Mi.colind, nnz));
+    TRY(c->dalloc(&Mi.vals, nnz));
+    TRY(c->dalloc(&Mi.trowptr, (int64_t)n + 1));
+    TRY(c->dalloc(&Mi.trow, nnz));
+    TRY(c->dalloc(&Mi.tperm, nnz));
+    TRY(c->dalloc(&Mi.tvals, nnz));
+    launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
+    LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.trowptr, Mi.trow, Mi.tperm,
+                                   keys, vals, rows, temp, tb));
+    launch_gather_values(st, nnz, Mi.tperm, Mi.vals, Mi.tvals);
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));   // ro's vectors are uploaded from pageable memory
   }
   // --- solve workspace
   TRY(c->dalloc(&c->r, n));
