@@ -629,11 +629,6 @@ struct MapsJob {
 };
 
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
-// When consecutive rows of A start at unrelated columns (more than one
-// descent of the first column per 16 rows, at least 65,536 rows), the rows
-// sorted stably by their first column (counting sort): perm[i] is the row of A
-// placed at i, prp the row starts of the permuted copy.  The x gathers of A p
-// and the (A p) gathers of A^T (A p) then stay local.
 // a thread joined on every exit from the scope that owns it
 struct JoiningThread {
   std::thread t;
@@ -641,27 +636,6 @@ struct JoiningThread {
     if (t.joinable()) t.join();
   }
 };
-
-struct RowOrder {
-  bool use = false;
-  std::vector<int32_t> perm, prp;
-};
-
-void row_order(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, RowOrder& ro) {
-  auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
-  int64_t desc = 0;
-  for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
-  ro.use = m >= 65536 && desc * 16 > m;
-  if (!ro.use) return;
-  std::vector<int32_t> start((size_t)n + 2, 0);
-  ro.perm.resize((size_t)m);
-  ro.prp.resize((size_t)m + 1);
-  for (int32_t i = 0; i < m; ++i) ++start[(size_t)key(i) + 1];
-  for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
-  for (int32_t i = 0; i < m; ++i) ro.perm[start[key(i)]++] = i;
-  ro.prp[0] = 0;
-  for (int32_t i = 0; i < m; ++i) ro.prp[(size_t)i + 1] = ro.prp[i] + (rp[ro.perm[i] + 1] - rp[ro.perm[i]]);
-}
 
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const std::vector<int32_t>& part, int32_t nparts,

@@ -520,4 +520,21 @@ void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& ph, 
   }
 }
 
+void row_order(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, RowOrder& ro) {
+  auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
+  int64_t desc = 0;
+  for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
+  ro.use = m >= 65536 && desc * 16 > m;
+  if (!ro.use) return;
+  std::vector<int32_t> start((size_t)n + 2, 0);
+  ro.perm.resize((size_t)m);
+  ro.prp.resize((size_t)m + 1);
+  for (int32_t i = 0; i < m; ++i) ++start[(size_t)key(i) + 1];
+  for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+  for (int32_t i = 0; i < m; ++i) ro.perm[start[key(i)]++] = i;
+  ro.prp[0] = 0;
+  for (int32_t i = 0; i < m; ++i) ro.prp[(size_t)i + 1] = ro.prp[i] + (rp[ro.perm[i] + 1] - rp[ro.perm[i]]);
+}
+
+
 }  // namespace lsq2l

@@ -24,6 +24,29 @@ int main(int argc, char** argv) {
   std::vector<int32_t> trp, tcol, tperm;
   plan_transpose(m, n, rp.data(), ci.data(), trp, tcol, tperm);
   for (int k = 0; k < nnz; ++k) CHECK(tperm[k] >= 0 && tperm[k] < nnz, "tperm");
+  // row-sorted iteration copy (row_order) and k_permute_rows: every source
+  // row read once, every destination entry inside [0, nnz) written once
+  RowOrder ro;
+  row_order(m, n, rp.data(), ci.data(), ro);
+  if (ro.use) {
+    CHECK((int64_t)ro.perm.size() == m && (int64_t)ro.prp.size() == (int64_t)m + 1, "row order sizes");
+    std::vector<char> seen(m, 0), written(nnz, 0);
+    CHECK(ro.prp[0] == 0 && ro.prp[m] == nnz, "permuted row starts");
+    for (int i = 0; i < m; ++i) {
+      const int r = ro.perm[i];
+      CHECK(r >= 0 && r < m && !seen[r], "perm entry %d", i);
+      seen[r] = 1;
+      CHECK(i == 0 || (rp[ro.perm[i - 1]] < rp[ro.perm[i - 1] + 1] ? ci[rp[ro.perm[i - 1]]] : n) <=
+                      (rp[r] < rp[r + 1] ? ci[rp[r]] : n), "rows not sorted by first column at %d", i);
+      int d = ro.prp[i];
+      for (int k = rp[r]; k < rp[r + 1]; ++k, ++d) {
+        CHECK(d >= 0 && d < nnz && !written[d], "permuted entry %d of row %d", d, i);
+        written[d] = 1;
+      }
+      CHECK(d == ro.prp[i + 1], "row %d length", i);
+    }
+    printf("row order: permuted\n");
+  }
   HostPlan H; std::string err;
   CHECK(plan_build(m, n, rp.data(), ci.data(), trp.data(), tcol.data(), part.data(), nparts, sop, H, err), "%s", err.c_str());
   CHECK(plan_maps(m, n, rp.data(), ci.data(), part.data(), H, err), "%s", err.c_str());

@@ -63,6 +63,9 @@ CASES = {
     "batch": lambda: [W.random_banded(300 + 50 * k, 600 + 100 * k, 3 + k, seed=k) for k in range(4)],
     "grid_500": lambda: [W.grid_500()],
     "grid_1000": lambda: [W.grid_1000()],
+    # rows starting at unrelated columns, 65,536 rows: the row-sorted iteration copy
+    "irregular_16k": lambda: [W.irregular_clustered(16384, 49152, 16, seed=21, tau=0.05, tol=1e-8,
+                                                    name="irregular_16k")],
 }
 
 
@@ -74,4 +77,6 @@ def test_host_plan_accesses_in_bounds(plan_check, name):
     dump_problems(CASES[name](), path)
     r = subprocess.run([exe, path], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr + r.stdout
-    assert r.stdout.startswith("OK")
+    assert r.stdout.splitlines()[-1].startswith("OK")
+    if name == "irregular_16k":
+        assert "row order: permuted" in r.stdout
