@@ -23,13 +23,29 @@ decomposition preconditioner for sparse normal equations"):
                            Cholesky of C_ii, Z_i, R_0^T = [R_1^T D_1 Z_1, ...],
                            Cholesky of C_00 = (A R_0^T)^T (A R_0^T);
 * ``Oracle.apply``      -- M_additive = R_0^T C_00^{-1} R_0 + sum_i R_i^T C_ii^{-1} R_i
-                           (eq. two_level_schwarz), or the one-level M_ASM
-                           (eq. one_level_schwarz);
+                           (eq. two_level_schwarz), the one-level M_ASM
+                           (eq. one_level_schwarz), M_RAS (eq. RAS), and the
+                           balanced and deflated second levels (eqs. balanced,
+                           deflated);
+* ``diag_shift_rel``    -- Section 4.1 "Setup phase": the preconditioner is
+                           built for C + s I, s = diag_shift_rel ||C||_F (the
+                           least-squares matrix [A; sqrt(s) I]) and applied to C;
 * ``pcg``               -- preconditioned conjugate gradients on C x = A^T b
                            (eq. normal), x_0 = 0, C applied as A^T (A p);
+* ``lsqr``              -- left-preconditioned LSQR (Section 4.1, "Solution
+                           phase"): Golub-Kahan bidiagonalization of A W^{-1}
+                           for M = W^{-1} W^{-T}, carried with products by M
+                           only; stops on LSQR's estimate of
+                           ||(A W^{-1})^T r|| / (||A W^{-1}||_F ||r||);
+* ``gmres``             -- right-preconditioned restarted GMRES on C x = A^T b
+                           (Section 4.2), stopping on the unpreconditioned
+                           residual;
 * ``Oracle.backward``   -- adjoint of x = C^{-1} A^T b: lambda = C^{-1} g,
                            dL/db = A lambda, dL/dA_ij = r_i lambda_j - (A lambda)_i x_j
                            on the stored pattern (differentiation of eq. normal);
+* ``normal_solve_direct``, ``gradients`` -- the solution of eq. (normal) by a
+                           sparse direct factorization of C, and the adjoint
+                           gradient formula, for full-size checks;
 * pin helpers           -- multiplicity m_j and k_m (Lemma 3.1), greedy colouring
                            k_c (Lemma 2.2), the bound of Theorem 2.6, and three
                            independent routes to the selection count (Schur
@@ -66,8 +82,9 @@ __all__ = [
     "Subdomain", "index_sets", "partition_of_unity", "restriction",
     "local_matrices", "coarse_vectors", "selection_count_schur",
     "selection_count_angles", "selection_count_inertia", "multiplicity",
-    "greedy_colouring", "theorem26_bound", "Oracle", "pcg", "csr_matrix",
-    "dense_preconditioner", "spmv", "spmv_t",
+    "greedy_colouring", "theorem26_bound", "Oracle", "pcg", "lsqr", "gmres", "csr_matrix",
+    "dense_preconditioner", "spmv", "spmv_t", "frobenius_normal", "gradients",
+    "normal_solve_direct",
 ]
 
 
@@ -113,17 +130,19 @@ class Subdomain:
         return self.nI + self.nG
 
 
-def index_sets(A: sp.csr_matrix, part: np.ndarray, nparts: int) -> list[Subdomain]:
+def index_sets(A: sp.csr_matrix, part: np.ndarray, nparts: int,
+               subdomains=None) -> list[Subdomain]:
     """Section 3 (eq. reorderedA), Algorithm 1 (FindNonzeroRows, FindNonzeroColumns).
 
     Xi_i     = rows of A with a stored entry in some column of Omega_Ii;
     Gamma_i  = columns with a stored entry in some row of Xi_i, minus Omega_Ii;
     Omega_i  = [Omega_Ii, Omega_Gamma_i], each part in ascending order.
+    ``subdomains`` restricts the list to those indices (in that order).
     """
     A = sp.csr_matrix(A)
     Acsc = A.tocsc()
     out = []
-    for i in range(nparts):
+    for i in (range(nparts) if subdomains is None else subdomains):
         I = np.flatnonzero(np.asarray(part) == i).astype(np.int64)
         Xi = np.unique(Acsc[:, I].indices).astype(np.int64)
         cols = np.unique(A[Xi, :].indices).astype(np.int64)
@@ -314,8 +333,10 @@ class Oracle:
     part: np.ndarray
     nparts: int
     tau: float
-    variant: str = "additive"          # or "one_level", "balanced"
+    variant: str = "additive"          # or "one_level", "balanced", "ras", "deflated"
     nev_max: int = 0
+    diag_shift_rel: float = 0.0
+    shift: float = 0.0
     sets: list = field(default_factory=list)
     chol: list = field(default_factory=list)
     X: list = field(default_factory=list)
@@ -337,16 +358,25 @@ class Oracle:
         list of indices (used to time a bounded sample; the result is then not
         a usable preconditioner)."""
         A = self.A = sp.csr_matrix(self.A)
-        self.sets = index_sets(A, self.part, self.nparts)
+        # the preconditioner is built for C + s I, i.e. for [A; sqrt(s) I]
+        # (Section 4.1, "Setup phase"); the solve still uses A
+        self.shift = self.diag_shift_rel * frobenius_normal(A) if self.diag_shift_rel > 0 else 0.0
+        if self.shift > 0:
+            n = A.shape[1]
+            Ab = sp.vstack([A, np.sqrt(self.shift) * sp.identity(n, format="csr")]).tocsr()
+        else:
+            Ab = A
+        self.Ab = Ab
+        self.sets = index_sets(Ab, self.part, self.nparts)
         todo = range(self.nparts) if subdomains is None else subdomains
         self.chol = [None] * self.nparts
         self.X = [np.zeros((s.nI, 0)) for s in self.sets]
         self.info = [None] * self.nparts
         for i in todo:
             s = self.sets[i]
-            Cii, Ctii = local_matrices(A, s)
+            Cii, Ctii = local_matrices(Ab, s)
             self.chol[i] = sla.cho_factor(Cii, lower=True)
-            if self.variant in ("additive", "balanced"):
+            if self.variant in ("additive", "balanced", "deflated"):
                 res = coarse_vectors(Cii, Ctii, s.nI, self.tau, self.nev_max)
                 self.X[i] = res["X"]
                 self.info[i] = res
@@ -367,17 +397,21 @@ class Oracle:
             self.R0T = sp.csr_matrix((np.concatenate(vals),
                                       (np.concatenate(rows), np.concatenate(cols))),
                                      shape=(self.n, n0))
-            W = (A @ self.R0T).toarray()
+            W = (Ab @ self.R0T).toarray()
             self.E = W.T @ W
             self.cholE = sla.cho_factor(self.E, lower=True)
         return self
 
-    def apply_one_level(self, r: np.ndarray) -> np.ndarray:
-        """M_ASM r = sum_{i >= 1} R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz)."""
+    def apply_one_level(self, r: np.ndarray, restricted: bool = False) -> np.ndarray:
+        """M_ASM r = sum_{i >= 1} R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz),
+        or with ``restricted`` M_RAS r = sum_i R_i^T D_i C_ii^{-1} R_i r (eq. RAS)."""
         z = np.zeros(self.n)
         for s, F in zip(self.sets, self.chol):
             Om = s.Omega
-            z[Om] += sla.cho_solve(F, r[Om])
+            zi = sla.cho_solve(F, r[Om])
+            if restricted:
+                zi = partition_of_unity(s) * zi
+            z[Om] += zi
         return z
 
     def apply_coarse(self, r: np.ndarray) -> np.ndarray:
@@ -393,8 +427,18 @@ class Oracle:
         one_level: M = M_ASM.
         balanced (eq. balanced, with M_ASM as the first level):
         M = Q + (I - C Q)^T M_ASM (I - C Q); C and Q are symmetric, so
-        (I - C Q)^T = I - Q C.  C is applied as A^T (A .)."""
+        (I - C Q)^T = I - Q C.
+        ras (eq. RAS): M = M_RAS.
+        deflated (eq. deflated, with M_RAS as the first level):
+        M = Q + M_RAS (I - C Q).
+        C is applied as A^T (A .); it is the matrix of the least-squares
+        problem (unshifted), the factors come from the shifted one."""
         A = self.A
+        if self.variant == "ras":
+            return self.apply_one_level(r, restricted=True)
+        if self.variant == "deflated":
+            Qr = self.apply_coarse(r)
+            return Qr + self.apply_one_level(r - A.T @ (A @ Qr), restricted=True)
         if self.variant == "balanced":
             Qr = self.apply_coarse(r)
             v = r - A.T @ (A @ Qr)                  # (I - C Q) r
@@ -406,7 +450,11 @@ class Oracle:
         return z
 
     def solve(self, b: np.ndarray, tol: float = 1e-8, maxit: int = 10000,
-              flexible: bool = False) -> dict:
+              flexible: bool = False, method: str = "pcg", restart: int = 100) -> dict:
+        if method == "lsqr":
+            return lsqr(self.A, b, self.apply, tol, maxit)
+        if method == "gmres":
+            return gmres(self.A, self.A.T @ b, self.apply, tol, maxit, restart)
         return pcg(self.A, self.A.T @ b, self.apply, tol, maxit, flexible)
 
     def backward(self, b: np.ndarray, x: np.ndarray, g: np.ndarray,
@@ -415,11 +463,9 @@ class Oracle:
         A = self.A
         sol = pcg(A, g, self.apply, tol, maxit)
         lam = sol["x"]
-        Alam = A @ lam
-        r = b - A @ x
-        rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
-        dvals = r[rows] * lam[A.indices] - Alam[rows] * x[A.indices]
-        return {"dLdb": Alam, "dLdvals": dvals, "lam": lam, "its": sol["its"]}
+        out = gradients(A, b, x, lam)
+        out.update({"lam": lam, "its": sol["its"]})
+        return out
 
 
 def pcg(A: sp.csr_matrix, rhs: np.ndarray, M, tol: float, maxit: int,
@@ -473,3 +519,148 @@ def dense_preconditioner(orc: Oracle) -> np.ndarray:
     """The matrix M of ``orc.apply`` (small problems only)."""
     n = orc.n
     return np.column_stack([orc.apply(e) for e in np.eye(n)])
+
+
+def frobenius_normal(A: sp.csr_matrix) -> float:
+    """||C||_F for C = A^T A (library sparse product)."""
+    C = (A.T @ A).tocsr()
+    return float(np.sqrt(np.sum(C.data ** 2)))
+
+
+def lsqr(A: sp.csr_matrix, b: np.ndarray, M, tol: float, maxit: int) -> dict:
+    """Left-preconditioned LSQR on min ||A x - b||_2 (Section 4.1).
+
+    With M = W^{-1} W^{-T} symmetric positive definite, LSQR (Paige and
+    Saunders) runs on the operator A W^{-1}; its right vectors v are kept as
+    vt = W^{-1} v and zh = W^T v, so that
+        beta u = A vt - alpha u,
+        alpha v = W^{-T} A^T u - beta v   becomes
+        q = A^T u - beta zh,  s = M q,  alpha = sqrt(q^T s),
+        zh = q / alpha,  vt = s / alpha,
+    and the iterate x = W^{-1} y is updated with wt = W^{-1} w.  Stops when
+    the estimate alpha |tau| / (anorm phibar) of
+    ||(A W^{-1})^T r|| / (||A W^{-1}||_F ||r||) is at most tol, anorm the
+    Frobenius norm of the bidiagonal matrix so far.
+    """
+    n = A.shape[1]
+    x = np.zeros(n)
+    u = b.copy()
+    beta = float(np.linalg.norm(u))
+    hist = []
+    if beta == 0.0:
+        return {"x": x, "its": 0, "test": 0.0, "hist": hist}
+    u /= beta
+    q = A.T @ u
+    s = M(q)
+    alpha = float(np.sqrt(q @ s))
+    if alpha == 0.0:
+        return {"x": x, "its": 0, "test": 0.0, "hist": hist}
+    zh = q / alpha
+    vt = s / alpha
+    wt = vt.copy()
+    rhobar, phibar = alpha, beta
+    anorm2 = 0.0
+    its = 0
+    test = 1.0
+    while its < maxit:
+        u = A @ vt - alpha * u
+        beta = float(np.linalg.norm(u))
+        anorm2 += alpha * alpha + beta * beta
+        if beta > 0:
+            u /= beta
+        q = A.T @ u - beta * zh
+        s = M(q)
+        alpha = float(np.sqrt(q @ s))
+        # plane rotation eliminating beta below the diagonal
+        rho = float(np.hypot(rhobar, beta))
+        c, sn = rhobar / rho, beta / rho
+        theta = sn * alpha
+        rhobar = -c * alpha
+        phi = c * phibar
+        phibar = sn * phibar
+        tau = sn * phi
+        x = x + (phi / rho) * wt
+        if alpha > 0:
+            zh = q / alpha
+            vt = s / alpha
+        else:
+            zh = np.zeros(n)
+            vt = np.zeros(n)
+        wt = vt - (theta / rho) * wt
+        its += 1
+        test = 0.0 if phibar == 0.0 else alpha * abs(tau) / (np.sqrt(anorm2) * phibar)
+        hist.append(test)
+        if test <= tol or alpha == 0.0:
+            break
+    return {"x": x, "its": its, "test": test, "hist": hist}
+
+
+def gmres(A: sp.csr_matrix, rhs: np.ndarray, M, tol: float, maxit: int,
+          restart: int = 100) -> dict:
+    """Right-preconditioned restarted GMRES on C x = rhs, C = A^T A (Section 4.2).
+
+    Each cycle builds an orthonormal basis V of the Krylov space of C M from
+    the true residual (Arnoldi, modified Gram-Schmidt), minimizes the residual
+    over x_0 + M V y by the Hessenberg least-squares problem (library
+    lstsq), and restarts.  Stops when ||rhs - C x|| <= tol ||rhs|| (the
+    unpreconditioned residual), checked on the Arnoldi estimate inside a cycle
+    and on the true residual between cycles.
+    """
+    n = A.shape[1]
+    x = np.zeros(n)
+    nrm0 = float(np.linalg.norm(rhs))
+    its = 0
+    cycles = 0
+    hist = []
+    while True:
+        r = rhs - A.T @ (A @ x)
+        beta = float(np.linalg.norm(r))
+        if beta <= tol * nrm0 or its >= maxit:
+            return {"x": x, "its": its, "relres": beta / nrm0 if nrm0 else 0.0,
+                    "cycles": cycles, "hist": hist}
+        V = [r / beta]
+        H = np.zeros((restart + 1, restart))
+        k = 0
+        for j in range(restart):
+            if its >= maxit:
+                break
+            w = A.T @ (A @ M(V[j]))
+            for i in range(j + 1):
+                H[i, j] = float(V[i] @ w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = float(np.linalg.norm(w))
+            its += 1
+            k = j + 1
+            e1 = np.zeros(k + 1)
+            e1[0] = beta
+            y = np.linalg.lstsq(H[:k + 1, :k], e1, rcond=None)[0]
+            est = float(np.linalg.norm(e1 - H[:k + 1, :k] @ y))
+            hist.append(est / nrm0)
+            if est <= tol * nrm0 or H[j + 1, j] == 0.0:
+                break
+            V.append(w / H[j + 1, j])
+        e1 = np.zeros(k + 1)
+        e1[0] = beta
+        y = np.linalg.lstsq(H[:k + 1, :k], e1, rcond=None)[0]
+        x = x + M(np.column_stack(V[:k]) @ y)
+        cycles += 1
+
+
+def gradients(A: sp.csr_matrix, b: np.ndarray, x: np.ndarray, lam: np.ndarray) -> dict:
+    """Implicit differentiation of x = C^{-1} A^T b for L(x) with lam = C^{-1} dL/dx:
+    dL/db = A lam and dL/dA_ij = r_i lam_j - (A lam)_i x_j, r = b - A x, on the
+    stored pattern of A (CSR order)."""
+    Alam = A @ lam
+    r = b - A @ x
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    dvals = r[rows] * lam[A.indices] - Alam[rows] * x[A.indices]
+    return {"dLdb": Alam, "dLdvals": dvals}
+
+
+def normal_solve_direct(A: sp.csr_matrix, rhs: np.ndarray) -> np.ndarray:
+    """C x = rhs, C = A^T A, by a sparse direct factorization of C (library
+    LU); used where an iterative oracle solve would take too long."""
+    import scipy.sparse.linalg as spla
+    C = (A.T @ A).tocsc()
+    return spla.spsolve(C, rhs)
+

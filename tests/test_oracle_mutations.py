@@ -143,3 +143,66 @@ def test_balanced_with_untransposed_left_factor_is_caught(monkeypatch):
         P.test_balanced_correction_is_C_orthogonal_to_coarse_space()
     with pytest.raises(AssertionError):
         P.test_balanced_is_symmetric_positive_definite()
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes in the Krylov methods, the RAS / deflated forms and the
+# shift: one edit of the oracle's source each, checked against the pins of
+# test_oracle_krylov.py
+# ---------------------------------------------------------------------------
+import inspect  # noqa: E402
+import textwrap  # noqa: E402
+
+from tests import test_oracle_krylov as PK  # noqa: E402
+
+
+def mutant(fn, old, new):
+    """The oracle function ``fn`` with one source fragment replaced."""
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert src.count(old) == 1, old
+    ns = dict(vars(OM))
+    exec(compile(src.replace(old, new), OM.__file__, "exec"), ns)
+    return ns[fn.__name__]
+
+
+def test_lsqr_rotation_sign_is_caught(monkeypatch):
+    plant(monkeypatch, "lsqr", mutant(OM.lsqr, "rhobar = -c * alpha", "rhobar = c * alpha"))
+    with pytest.raises(AssertionError):
+        PK.test_lsqr_identity_preconditioner_matches_library_lsqr(5)
+
+
+def test_lsqr_missing_preconditioner_in_alpha_is_caught(monkeypatch):
+    """alpha from ||q|| instead of sqrt(q^T M q)."""
+    plant(monkeypatch, "lsqr", mutant(OM.lsqr, "alpha = float(np.sqrt(q @ s))\n        # plane",
+                                      "alpha = float(np.linalg.norm(q))\n        # plane"))
+    with pytest.raises(AssertionError):
+        PK.test_lsqr_preconditioned_is_lsqr_on_transformed_operator(3)
+
+
+def test_gmres_update_without_preconditioner_is_caught(monkeypatch):
+    """x += V y instead of x += M V y (right preconditioning dropped)."""
+    plant(monkeypatch, "gmres", mutant(OM.gmres, "x = x + M(np.column_stack(V[:k]) @ y)",
+                                       "x = x + np.column_stack(V[:k]) @ y"))
+    with pytest.raises(AssertionError):
+        PK.test_gmres_iterate_minimizes_residual_over_krylov_space(4)
+
+
+def test_ras_without_partition_of_unity_is_caught(monkeypatch):
+    bad = mutant(OM.Oracle.apply_one_level, "zi = partition_of_unity(s) * zi", "zi = 1.0 * zi")
+    monkeypatch.setattr(OM.Oracle, "apply_one_level", bad)
+    with pytest.raises(AssertionError):
+        PK.test_ras_differs_from_asm_with_overlap()
+
+
+def test_deflated_wrong_sign_is_caught(monkeypatch):
+    bad = mutant(OM.Oracle.apply, "r - A.T @ (A @ Qr), restricted=True",
+                 "r + A.T @ (A @ Qr), restricted=True")
+    monkeypatch.setattr(OM.Oracle, "apply", bad)
+    with pytest.raises(AssertionError):
+        PK.test_deflated_coarse_space_is_unit_eigenspace()
+
+
+def test_shift_on_squared_norm_is_caught(monkeypatch):
+    plant(monkeypatch, "frobenius_normal", lambda A: float(np.sum((A.T @ A).tocsr().data ** 2)))
+    with pytest.raises(AssertionError):
+        PK.test_shift_single_subdomain_is_shifted_inverse()
