@@ -159,7 +159,7 @@ def main():
                                            name="grid_gradient"))
         workload = f"grid_gradient {args.grid}x{args.grid}, {args.patches}x{args.patches} patches"
     dev = {
-        "rowptr": torch.as_tensor(prob.indptr).cuda(),
+        "rowptr": torch.as_tensor(prob.indptr.astype(np.int64)).cuda(),
         "colind": torch.as_tensor(prob.indices).cuda(),
         "vals": torch.as_tensor(prob.data).cuda(),
         "b": torch.as_tensor(prob.b).cuda(),

@@ -1,18 +1,18 @@
-// C ABI of the lsq2l library: setup (Algorithm 1), the preconditioned CG
-// solve on the normal equations (eq. normal), the adjoint solve, and the
-// accessors used for validation.
+// C ABI of the lsq2l library: setup (Algorithm 1), the preconditioners of
+// Section 2 (eqs. one_level_schwarz, RAS, two_level_schwarz, balanced,
+// deflated), the CG solve on the normal equations (eq. normal; LSQR and
+// GMRES live in krylov.cpp), the adjoint solve, and the accessors used for
+// validation.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
-#include "kernels.hpp"
-#include "plan.hpp"
+#include "ctx.hpp"
+#include "krylov.hpp"
 
 namespace lsq2l {
 
@@ -21,17 +21,12 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 namespace {
 
-using clk = std::chrono::steady_clock;
-double ms_since(clk::time_point t0) {
-  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-}
-int32_t roundup32(int64_t x) { return (int32_t)((x + TS - 1) / TS * TS); }
-
 // Lanes per row of the SpMV: the largest power of two not above half the
 // mean row length, so that a lane takes about two entries of an average row
 // (1.67 entries per row of A on the 1000 x 1000 grid: one lane, 5.0 TB/s
 // against 4.4 with two; 5 per row of A^T: two lanes, 4.7 TB/s against 4.2,
-// 3.6 and 3.4 with four, eight and one)
+// 3.6 and 3.4 with four, eight and one).  lsq2l_autotune replaces it by a
+// measured choice.
 int pick_group(double avg) {
   int g = 1;
   while (g < 64 && 4 * g <= avg) g *= 2;
@@ -101,9 +96,10 @@ BlockCache& block_cache() {
 }
 
 // Pinned host buffers for the copies setup reads back from the device (A's
-// pattern, A^T's pattern), kept for later setups: a pageable copy runs at a
-// sixth of the pinned rate, and pinning fresh memory costs more than the
-// copy.  At most PINNED_LIMIT bytes stay cached.
+// pattern, A^T's pattern) and stages its uploads through, kept for later
+// setups: a pageable copy runs at a sixth of the pinned rate, and pinning
+// fresh memory costs more than the copy.  At most PINNED_LIMIT bytes stay
+// cached.
 struct PinnedPool {
   struct Buf { void* p; size_t bytes; };
   static constexpr size_t PINNED_LIMIT = (size_t)4 << 30;
@@ -153,235 +149,107 @@ PinnedPool& pinned_pool() {
   return *pp;
 }
 
-// A pinned host array of count elements from the pool, returned to it when
-// the owner goes out of scope (the work that used it has been synchronized).
-template <typename T>
-struct PinnedArray {
-  T* p = nullptr;
-  size_t bytes = 0;
-  lsq2l_status alloc(int64_t count) {
-    const size_t want = (((size_t)std::max<int64_t>(count, 1) * sizeof(T)) + ((1 << 20) - 1)) >> 20 << 20;
-    p = (T*)pinned_pool().take(want, &bytes);
-    if (!p) {
-      set_error("pinned host allocation of " + std::to_string(want) + " bytes failed");
-      return LSQ2L_ENOMEM;
-    }
-    return LSQ2L_OK;
-  }
-  ~PinnedArray() {
-    if (p) pinned_pool().give(p, bytes);
-  }
-};
-
 }  // namespace
+
+void* cache_take(size_t bytes, int dev, size_t* got) { return block_cache().take(bytes, dev, got); }
+void cache_give(void* p, size_t bytes, int dev) { block_cache().give(p, bytes, dev); }
+void cache_release() { block_cache().release(); }
+void* pinned_take(size_t bytes, size_t* got) { return pinned_pool().take(bytes, got); }
+void pinned_give(void* p, size_t bytes) { pinned_pool().give(p, bytes); }
+void pinned_release() { pinned_pool().release(); }
+
 }  // namespace lsq2l
 
 using namespace lsq2l;
 
-struct lsq2l_ctx {
-  hipStream_t st = nullptr;
-  hipStream_t gst = nullptr;   // stream the PCG iteration graph is captured on
-  lsq2l_options opt{};
-  double tau = 0.0;
-  int S = 1;
-  int nsub = 0;
-  std::vector<SegDesc> segs_h;
-  std::vector<int64_t> seg_row_h, seg_col_h;
-  int64_t* d_seg_row = nullptr;
-  int64_t* d_seg_col = nullptr;
-  DevMatrix M;
-  DevMatrix Mi;             // row-permuted copy of A and its transpose for C p = A^T (A p)
-  bool row_perm = false;    // Mi is in use
-  DevPlan P;
-  DevCoarse Cc;
-  HostPlan H;
-  CoarsePlan CP;
-  bool coarse = false;
-  int64_t n0tot = 0;        // padded coarse size over all instances
-  int64_t n0 = 0;           // true coarse size
-  int64_t etiles = 0;
-  double *fac = nullptr, *dinv = nullptr, *scale = nullptr, *ctg = nullptr;
-  float *fac32 = nullptr, *dinv32 = nullptr;
-  float* X32 = nullptr;      // MIXED: FP32 copy of X for the restriction and prolongation
-  double *X = nullptr, *W = nullptr, *efac = nullptr, *edinv = nullptr, *einv = nullptr;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr, *rold = nullptr;
-  double *tm = nullptr, *tm2 = nullptr, *loc = nullptr, *cvec = nullptr, *dvec = nullptr;
-  double *partial = nullptr, *partial2 = nullptr, *xwork = nullptr;
-  double *bsave = nullptr, *xsave = nullptr;
-  double *bal_u = nullptr, *bal_w = nullptr;   // balanced form: two n-vectors
-  bool have_solution = false;
-  Scalars sc{};
-  int32_t* status = nullptr;
-  int32_t* h_done = nullptr;      // pinned
-  double* h_rn2 = nullptr;        // pinned
-  double* h_r0n2 = nullptr;       // pinned
-  std::vector<int32_t> p_h;
-  int max_p = 0;
-  lsq2l_setup_info info{};
-  struct DevBlock { void* p; size_t bytes; int dev; };
-  std::vector<DevBlock> dev_allocs;
-  std::vector<void*> host_allocs;
-
-  // Device memory of the handle: requests up to ARENA_SMALL bytes are carved
-  // (256-byte aligned) from ARENA_CHUNK-sized allocations, larger ones get
-  // their own; everything is released when the handle is destroyed.
-  static constexpr size_t ARENA_CHUNK = (size_t)256 << 20, ARENA_SMALL = (size_t)64 << 20;
-  char* arena_cur = nullptr;
-  size_t arena_used = 0;
-  lsq2l_status raw_alloc(void** v, size_t bytes) {
-    int dev = 0;
-    LSQ2L_HIP_TRY(hipGetDevice(&dev));
-    size_t got = 0;
-    if ((*v = block_cache().take(bytes, dev, &got)) != nullptr) {
-      dev_allocs.push_back({*v, got, dev});
-      return LSQ2L_OK;
-    }
-    hipError_t e = hipMalloc(v, bytes);
-    if (e != hipSuccess) {
-      block_cache().release();
-      e = hipMalloc(v, bytes);
-    }
-    if (e != hipSuccess) {
-      set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-      return LSQ2L_ENOMEM;
-    }
-    dev_allocs.push_back({*v, bytes, dev});
+lsq2l_status lsq2l_ctx::raw_alloc(void** v, size_t bytes) {
+  int dev = 0;
+  LSQ2L_HIP_TRY(hipGetDevice(&dev));
+  size_t got = 0;
+  if ((*v = cache_take(bytes, dev, &got)) != nullptr) {
+    dev_allocs.push_back({*v, got, dev});
     return LSQ2L_OK;
   }
-  template <typename T>
-  lsq2l_status dalloc(T** ptr, int64_t count) {
-    *ptr = nullptr;
-    if (count <= 0) return LSQ2L_OK;
-    const size_t bytes = ((size_t)count * sizeof(T) + 255) / 256 * 256;
-    void* v = nullptr;
-    if (bytes > ARENA_SMALL) {
-      lsq2l_status s = raw_alloc(&v, bytes);
-      if (s != LSQ2L_OK) return s;
-    } else {
-      if (!arena_cur || arena_used + bytes > ARENA_CHUNK) {
-        lsq2l_status s = raw_alloc(&v, ARENA_CHUNK);
-        if (s != LSQ2L_OK) return s;
-        arena_cur = (char*)v;
-        arena_used = 0;
-      }
-      v = arena_cur + arena_used;
-      arena_used += bytes;
-    }
-    *ptr = (T*)v;
-    return LSQ2L_OK;
+  hipError_t e = hipMalloc(v, bytes);
+  if (e != hipSuccess) {
+    cache_release();
+    e = hipMalloc(v, bytes);
   }
-  template <typename T>
-  lsq2l_status halloc(T** ptr, int64_t count) {
-    void* v = nullptr;
-    hipError_t e = hipHostMalloc(&v, (size_t)std::max<int64_t>(count, 1) * sizeof(T), hipHostMallocDefault);
-    if (e != hipSuccess) { set_error("pinned host allocation failed"); return LSQ2L_ENOMEM; }
-    host_allocs.push_back(v);
-    *ptr = (T*)v;
-    return LSQ2L_OK;
+  if (e != hipSuccess) {
+    set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    return LSQ2L_ENOMEM;
   }
-  template <typename T>
-  lsq2l_status upload(T** dst, const std::vector<T>& src) {
-    lsq2l_status s = dalloc(dst, (int64_t)src.size());
-    if (s != LSQ2L_OK) return s;
-    if (!src.empty()) LSQ2L_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
-    return LSQ2L_OK;
-  }
-  ~lsq2l_ctx() {
-    if (st) (void)hipStreamSynchronize(st);
-    else (void)hipDeviceSynchronize();
-    if (gst) (void)hipStreamDestroy(gst);
-    for (const DevBlock& b : dev_allocs) block_cache().give(b.p, b.bytes, b.dev);
-    for (void* v : host_allocs) (void)hipHostFree(v);
-  }
-};
-
-#define TRY(expr)                             \
-  do {                                        \
-    lsq2l_status _s = (expr);                 \
-    if (_s != LSQ2L_OK) return _s;            \
-  } while (0)
-
-namespace {
-
-lsq2l_status validate_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, int64_t nnz) {
-  if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
-  // rows checked in parallel blocks, first every row's extent (so that the
-  // column pass reads inside ci), then the columns; the first failing row of
-  // the first failing pass is reported
-  const unsigned nth = m < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<int32_t> bad_row(nth, INT32_MAX);
-  std::vector<int> bad_kind(nth, 0);
-  auto run = [&](auto&& fn) {
-    if (nth == 1) {
-      fn(0u);
-    } else {
-      std::vector<std::thread> pool;
-      for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
-      for (auto& th : pool) th.join();
-    }
-  };
-  auto rows_of = [&](unsigned t, int32_t& r0, int32_t& r1) {
-    r0 = (int32_t)((int64_t)m * t / nth);
-    r1 = (int32_t)((int64_t)m * (t + 1) / nth);
-  };
-  run([&](unsigned t) {
-    int32_t r0, r1;
-    rows_of(t, r0, r1);
-    for (int32_t r = r0; r < r1; ++r)
-      if (rp[r + 1] < rp[r] || rp[r + 1] > nnz) { bad_row[t] = r; bad_kind[t] = 1; return; }
-  });
-  bool extents_ok = true;
-  for (unsigned t = 0; t < nth; ++t) extents_ok = extents_ok && !bad_kind[t];
-  if (extents_ok)
-    run([&](unsigned t) {
-      int32_t r0, r1;
-      rows_of(t, r0, r1);
-      for (int32_t r = r0; r < r1; ++r)
-        for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
-          int kind = 0;
-          if (ci[e] < 0 || ci[e] >= n) kind = 2;
-          else if (e > rp[r] && ci[e] <= ci[e - 1]) kind = 3;
-          if (kind) { bad_row[t] = r; bad_kind[t] = kind; return; }
-        }
-    });
-  for (unsigned t = 0; t < nth; ++t) {
-    if (!bad_kind[t]) continue;
-    const std::string r = std::to_string(bad_row[t]);
-    if (bad_kind[t] == 1) set_error("rowptr is not monotone (or exceeds nnz) at row " + r);
-    else if (bad_kind[t] == 2) set_error("column index out of range in row " + r);
-    else set_error("columns not strictly increasing in row " + r);
-    return LSQ2L_EINVAL;
-  }
+  dev_allocs.push_back({*v, bytes, dev});
   return LSQ2L_OK;
 }
 
-void spmv_it_A(lsq2l_ctx* c, const double* x, double* y);
-void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x);
+lsq2l_ctx::~lsq2l_ctx() {
+  if (st) (void)hipStreamSynchronize(st);
+  else (void)hipDeviceSynchronize();
+  release_staged();
+  if (gst) (void)hipStreamDestroy(gst);
+  for (const DevBlock& b : dev_allocs) cache_give(b.p, b.bytes, b.dev);
+  for (void* v : host_allocs) (void)hipHostFree(v);
+}
+
+namespace lsq2l {
+
+// ---------------------------------------------------------------------------
+// products with A, A^T and the preconditioners
+// ---------------------------------------------------------------------------
+
+// C p = A^T (A p) inside the iteration.  A p never leaves the library, so it
+// may be formed with a row-permuted copy of A: C = A^T A is the same for any
+// row order of A.
+void spmv_it_A(lsq2l_ctx* c, const double* x, double* y) {
+  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
+  launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, x, y, M.spmv_group);
+}
+void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x) {
+  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
+  launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, y, x, M.spmvt_group);
+}
+void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
+  launch_spmv(c->st, c->M.m, c->M.rowptr, c->M.colind, c->M.vals, x, y, c->M.spmv_group);
+}
+void spmv_AT(lsq2l_ctx* c, const double* y, double* x) {
+  launch_spmv(c->st, c->M.n, c->M.trowptr, c->M.trow, c->M.tvals, y, x, c->M.spmvt_group);
+}
+// y = C x = A^T (A x), with tmp (m doubles) for A x
+void apply_C(lsq2l_ctx* c, const double* x, double* y, double* tmp) {
+  spmv_it_A(c, x, tmp);
+  spmv_it_AT(c, tmp, y);
+}
+
+void local_solves(lsq2l_ctx* c) {
+  if (c->opt.precision == LSQ2L_MIXED)
+    launch_local_solve_f32(c->st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
+  else
+    launch_local_solve(c->st, c->nsub, c->P, c->fac, c->dinv, c->loc);
+}
+
+namespace {
+
+void scatter(lsq2l_ctx* c, const double* loc, const double* dcoarse, double* z, bool restricted) {
+  if (c->X32) launch_scatter_local(c->st, c->M.n, c->P, c->scale, loc, c->X32, dcoarse, z, restricted);
+  else launch_scatter_local(c->st, c->M.n, c->P, c->scale, loc, c->X, dcoarse, z, restricted);
+}
 
 // z = Q r = R_0^T E^{-1} R_0 r (restriction, symmetric E^{-1} product, prolongation)
 void apply_Q(lsq2l_ctx* c, const double* r, double* z) {
   const hipStream_t st = c->st;
-  if (c->X32) {
-    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
-    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
-    launch_scatter_local(st, c->M.n, c->P, c->scale, nullptr, c->X32, c->dvec, z);
-  } else {
-    launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
-    launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
-    launch_scatter_local(st, c->M.n, c->P, c->scale, nullptr, c->X, c->dvec, z);
-  }
+  if (c->X32) launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
+  else launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
+  launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
+  scatter(c, nullptr, c->dvec, z, false);
 }
 
-// z = M_ASM r = sum_i R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz)
-void apply_one_level(lsq2l_ctx* c, const double* r, double* z) {
-  const hipStream_t st = c->st;
-  launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
-  if (c->opt.precision == LSQ2L_MIXED)
-    launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
-  else
-    launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
-  if (c->X32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, nullptr, z);
-  else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, nullptr, z);
+// z = M_ASM r = sum_i R_i^T C_ii^{-1} R_i r (eq. one_level_schwarz), or with
+// `restricted` M_RAS r = sum_i R_i^T D_i C_ii^{-1} R_i r (eq. RAS)
+void apply_one_level(lsq2l_ctx* c, const double* r, double* z, bool restricted) {
+  launch_gather_local(c->st, c->nsub, c->P, c->scale, r, c->loc);
+  local_solves(c);
+  scatter(c, c->loc, nullptr, z, restricted);
 }
 
 // Balanced form (eq. balanced) with M_ASM as the first level:
@@ -397,59 +265,102 @@ void apply_M_balanced(lsq2l_ctx* c, const double* r, double* z) {
     r = c->rold;
   }
   apply_Q(c, r, c->bal_u);
-  spmv_it_A(c, c->bal_u, c->tm2);
-  spmv_it_AT(c, c->tm2, c->bal_w);
+  apply_C(c, c->bal_u, c->bal_w, c->tm2);
   launch_sub(st, n, r, c->bal_w, c->bal_w);            // (I - C Q) r
-  apply_one_level(c, c->bal_w, z);                      // y
-  spmv_it_A(c, z, c->tm2);
-  spmv_it_AT(c, c->tm2, c->bal_w);
+  apply_one_level(c, c->bal_w, z, false);              // y
+  apply_C(c, z, c->bal_w, c->tm2);
   launch_sub(st, n, r, c->bal_w, c->bal_w);            // r - C y
   apply_Q(c, c->bal_w, c->bal_u);
   launch_add(st, n, z, c->bal_u, z);
 }
 
-// z = M r: local solves (eq. one_level_schwarz) plus the coarse correction
-// R_0^T E^{-1} R_0 r (eq. two_level_schwarz), or the balanced form.
+// Deflated form (eq. deflated) with M_RAS as the first level:
+// M r = Q r + M_RAS (I - C Q) r = u + M_RAS (r - C u), u = Q r.  One coarse
+// correction, two SpMVs, one set of local solves per application.
+void apply_M_deflated(lsq2l_ctx* c, const double* r, double* z) {
+  const hipStream_t st = c->st;
+  const int64_t n = c->M.n;
+  apply_Q(c, r, c->bal_u);
+  apply_C(c, c->bal_u, c->bal_w, c->tm2);
+  launch_sub(st, n, r, c->bal_w, c->bal_w);            // (I - C Q) r
+  apply_one_level(c, c->bal_w, z, true);               // M_RAS (I - C Q) r
+  launch_add(st, n, z, c->bal_u, z);
+}
+
+}  // namespace
+
+// z = M r for the variant of the handle (z == r allowed).
 void apply_M(lsq2l_ctx* c, const double* r, double* z) {
-  if (c->opt.variant == LSQ2L_BALANCED) {
-    if (c->coarse) apply_M_balanced(c, r, z);
-    else apply_one_level(c, r, z);
+  const int v = c->opt.variant;
+  if (v == LSQ2L_ONE_LEVEL || (v == LSQ2L_BALANCED && !c->coarse)) { apply_one_level(c, r, z, false); return; }
+  if (v == LSQ2L_RAS || (v == LSQ2L_DEFLATED && !c->coarse)) { apply_one_level(c, r, z, true); return; }
+  if (v == LSQ2L_BALANCED) { apply_M_balanced(c, r, z); return; }
+  if (v == LSQ2L_DEFLATED) {
+    if (z == r) {               // r is read again after z is first written
+      launch_copy(c->st, c->M.n, r, c->rold);
+      r = c->rold;
+    }
+    apply_M_deflated(c, r, z);
     return;
   }
+  // additive: local solves plus the coarse correction R_0^T E^{-1} R_0 r
+  // (eq. two_level_schwarz), the coarse restriction and solve between the
+  // local solves and the scatter that adds both
   const hipStream_t st = c->st;
   launch_gather_local(st, c->nsub, c->P, c->scale, r, c->loc);
-  if (c->opt.precision == LSQ2L_MIXED)
-    launch_local_solve_f32(st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
-  else
-    launch_local_solve(st, c->nsub, c->P, c->fac, c->dinv, c->loc);
-  const bool x32 = c->X32 != nullptr;
+  local_solves(c);
   if (c->coarse) {
-    if (x32) launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
+    if (c->X32) launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X32, r, c->cvec);
     else launch_coarse_restrict(st, c->nsub, c->P, c->max_p, c->X, r, c->cvec);
     launch_einv_gemv(st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
   }
-  if (x32) launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X32, c->coarse ? c->dvec : nullptr, z);
-  else launch_scatter_local(st, c->M.n, c->P, c->scale, c->loc, c->X, c->coarse ? c->dvec : nullptr, z);
+  scatter(c, c->loc, c->coarse ? c->dvec : nullptr, z, false);
 }
 
-// C p = A^T (A p) inside the iteration.  A p never leaves the library, so it
-// may be formed with a row-permuted copy of A: C = A^T A is the same for any
-// row order of A.
-void spmv_it_A(lsq2l_ctx* c, const double* x, double* y) {
-  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
-  launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, x, y, M.spmv_group);
-}
-void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x) {
-  const DevMatrix& M = c->row_perm ? c->Mi : c->M;
-  launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, y, x, M.spmvt_group);
+// per-instance sums of the RED_BLOCKS partials (host, fixed order)
+lsq2l_status read_seg_sums(lsq2l_ctx* c, const double* partial, std::vector<double>& out) {
+  const int S = c->S;
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_part, partial, sizeof(double) * S * RED_BLOCKS,
+                               hipMemcpyDeviceToHost, c->st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  out.assign(S, 0.0);
+  for (int s = 0; s < S; ++s) {
+    double t = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) t += c->h_part[(size_t)s * RED_BLOCKS + b];
+    out[s] = t;
+  }
+  return LSQ2L_OK;
 }
 
-void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
-  launch_spmv(c->st, c->M.m, c->M.rowptr, c->M.colind, c->M.vals, x, y, c->M.spmv_group);
+// ||C||_2 per instance, from below, by 30 steps of the power method on C
+// (device-side normalisation, one read-back at the end).  Kept in the handle.
+lsq2l_status norm_C(lsq2l_ctx* c) {
+  if (!c->normC.empty()) return LSQ2L_OK;
+  const hipStream_t st = c->st;
+  const int S = c->S;
+  const int64_t n = c->M.n;
+  double* v = c->rold;
+  double* w = c->q;
+  double* nrm = c->sc.pq;          // S doubles, free outside the iteration
+  launch_hash_fill(st, n, v);
+  launch_dot(st, S, c->d_seg_col, v, v, c->partial);
+  launch_seg_sum(st, S, c->partial, nrm);
+  launch_normalize_seg(st, n, S, c->d_seg_col, nrm, nullptr, v, v);
+  for (int it = 0; it < 30; ++it) {
+    apply_C(c, v, w, c->tm);
+    launch_dot(st, S, c->d_seg_col, w, w, c->partial);
+    launch_seg_sum(st, S, c->partial, nrm);
+    launch_normalize_seg(st, n, S, c->d_seg_col, nrm, nullptr, w, v);
+  }
+  std::vector<double> h(S);
+  LSQ2L_HIP_TRY(hipMemcpyAsync(h.data(), nrm, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  c->normC.resize(S);
+  for (int s = 0; s < S; ++s) c->normC[s] = std::sqrt(h[s]);
+  return LSQ2L_OK;
 }
-void spmv_AT(lsq2l_ctx* c, const double* y, double* x) {
-  launch_spmv(c->st, c->M.n, c->M.trowptr, c->M.trow, c->M.tvals, y, x, c->M.spmvt_group);
-}
+
+namespace {
 
 lsq2l_status read_flags(lsq2l_ctx* c) {
   LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_done, c->sc.done, sizeof(int32_t) * c->S, hipMemcpyDeviceToHost, c->st));
@@ -459,7 +370,12 @@ lsq2l_status read_flags(lsq2l_ctx* c) {
   return LSQ2L_OK;
 }
 
-// PCG on C x = rhs (x_0 = 0), C = A^T A applied as A^T (A p).  x is written.
+// The residual-norm step of a CG iteration (sets the done flags).
+void rnorm_step(lsq2l_ctx* c, double tol2, int flexible) {
+  launch_dot(c->st, c->S, c->d_seg_col, c->r, c->r, c->partial);
+  launch_scalar(c->st, OP_RNORM, c->S, c->partial, nullptr, c->sc, tol2, flexible);
+}
+
 // One PCG iteration as a HIP graph: both SpMVs, alpha, the x and r update,
 // the residual norm (which sets the per-instance done flags), M r, beta and
 // the direction update, in the order of the loop in pcg().  The graph is
@@ -477,14 +393,12 @@ lsq2l_status capture_iteration(lsq2l_ctx* c, double* x, double tol2, hipGraphExe
   if (e == hipSuccess) {
     c->st = c->gst;
     const hipStream_t st = c->st;
-    spmv_it_A(c, c->p, c->tm);
-    spmv_it_AT(c, c->tm, c->q);
+    apply_C(c, c->p, c->q, c->tm);
     launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
     launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
     if (flexible) launch_copy(st, n, c->r, c->rold);
     launch_axpy_xr(st, n, S, c->d_seg_col, c->sc.alpha, c->p, c->q, x, c->r);
-    launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
-    launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+    rnorm_step(c, tol2, flexible);
     apply_M(c, c->r, c->z);
     launch_dot(st, S, c->d_seg_col, c->r, c->z, c->partial);
     if (flexible) launch_dot(st, S, c->d_seg_col, c->rold, c->z, c->partial2);
@@ -502,24 +416,36 @@ lsq2l_status capture_iteration(lsq2l_ctx* c, double* x, double tol2, hipGraphExe
   return LSQ2L_OK;
 }
 
-lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, double* relres_true,
-                 double* relres_rec) {
+}  // namespace
+
+// PCG on C x = rhs (x_0 = 0), C = A^T A applied as A^T (A p).  x is written.
+// It stops on the relative residual ||rhs - C x|| <= tol ||rhs||.  With
+// adjoint set, an instance whose true residual still misses that after the
+// restarts (the attainable accuracy of CG on an ill-conditioned C) is
+// accepted if its normwise backward error
+// ||rhs - C x|| / (||C||_2 ||x|| + ||rhs||) is at most tol (c->normC known).
+lsq2l_status pcg(lsq2l_ctx* c, double* x, bool adjoint, double tol, KrylovResult& res) {
   const hipStream_t st = c->st;
   const int S = c->S;
   const int64_t n = c->M.n;
-  const double tol2 = c->opt.tol * c->opt.tol;
+  const double tol2 = tol * tol;
   const int flexible = c->opt.flexible;
   launch_fill(st, n, 0.0, x);
-  LSQ2L_HIP_TRY(hipMemcpyAsync(c->r, c->rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_fill_i32(st, S, 0, c->sc.its);
+  launch_copy(st, n, c->rhs, c->r);
   launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
   launch_scalar(st, OP_R0, S, c->partial, nullptr, c->sc, tol2, flexible);
   int its = 0, restarts = 0;
   bool breakdown = false;
+  res.relres.assign(S, 0.0);
+  res.relres_rec.assign(S, 0.0);
+  res.backward_err.assign(S, 0.0);
+  res.converged.assign(S, 0);
   while (true) {
     apply_M(c, c->r, c->z);
     launch_dot(st, S, c->d_seg_col, c->r, c->z, c->partial);
     launch_scalar(st, OP_RHO_INIT, S, c->partial, nullptr, c->sc, tol2, flexible);
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->p, c->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_copy(st, n, c->z, c->p);
     TRY(read_flags(c));
     bool all_done = true;
     for (int s = 0; s < S; ++s) all_done &= (c->h_done[s] != 0);
@@ -547,14 +473,12 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
     }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     while (!all_done && its < c->opt.max_it) {
-      spmv_it_A(c, c->p, c->tm);
-      spmv_it_AT(c, c->tm, c->q);
+      apply_C(c, c->p, c->q, c->tm);
       launch_dot(st, S, c->d_seg_col, c->p, c->q, c->partial);
       launch_scalar(st, OP_ALPHA, S, c->partial, nullptr, c->sc, tol2, flexible);
-      if (flexible) LSQ2L_HIP_TRY(hipMemcpyAsync(c->rold, c->r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if (flexible) launch_copy(st, n, c->r, c->rold);
       launch_axpy_xr(st, n, S, c->d_seg_col, c->sc.alpha, c->p, c->q, x, c->r);
-      launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
-      launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+      rnorm_step(c, tol2, flexible);
       ++its;
       if (its % std::max(1, c->opt.check_every) == 0 || its >= c->opt.max_it) {
         TRY(read_flags(c));
@@ -572,44 +496,76 @@ lsq2l_status pcg(lsq2l_ctx* c, double* x, int* its_out, int* restarts_out, doubl
       launch_xpby(st, n, S, c->d_seg_col, c->sc.beta, c->z, c->p);
     }
     // true residual rhs - A^T A x
-    spmv_it_A(c, x, c->tm);
-    spmv_it_AT(c, c->tm, c->q);
+    apply_C(c, x, c->q, c->tm);
     launch_sub(st, n, c->rhs, c->q, c->q);
     launch_dot(st, S, c->d_seg_col, c->q, c->q, c->partial);
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_done, c->sc.done, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
-    std::vector<double> part((size_t)S * RED_BLOCKS);
-    LSQ2L_HIP_TRY(hipMemcpyAsync(part.data(), c->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_rn2, c->sc.rn2, sizeof(double) * S, hipMemcpyDeviceToHost, st));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_r0n2, c->sc.r0n2, sizeof(double) * S, hipMemcpyDeviceToHost, st));
-    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
-    bool all_ok = true;
-    for (int s = 0; s < S; ++s) {
-      double t = 0.0;
-      for (int b = 0; b < RED_BLOCKS; ++b) t += part[(size_t)s * RED_BLOCKS + b];
-      const double r0 = c->h_r0n2[s];
-      relres_true[s] = r0 > 0 ? std::sqrt(t / r0) : 0.0;
-      relres_rec[s] = r0 > 0 ? std::sqrt(c->h_rn2[s] / r0) : 0.0;
-      if (c->h_done[s] == 2) breakdown = true;
-      if (!(relres_true[s] <= c->opt.tol)) all_ok = false;
+    std::vector<double> t2, x2;
+    TRY(read_seg_sums(c, c->partial, t2));
+    if (adjoint) {
+      launch_dot(st, S, c->d_seg_col, x, x, c->partial2);
+      TRY(read_seg_sums(c, c->partial2, x2));
     }
-    if (all_ok || breakdown || restarts == 3 || its >= c->opt.max_it) break;
+    TRY(read_flags(c));
+    bool all_ok = true;
+    const bool last = restarts == 3 || its >= c->opt.max_it;
+    for (int s = 0; s < S; ++s) {
+      const double r0 = c->h_r0n2[s];
+      res.relres[s] = r0 > 0 ? std::sqrt(t2[s] / r0) : 0.0;
+      res.relres_rec[s] = r0 > 0 ? std::sqrt(c->h_rn2[s] / r0) : 0.0;
+      bool ok = res.relres[s] <= tol;
+      if (adjoint) {
+        const double bound = c->normC[s] * std::sqrt(x2[s]) + std::sqrt(r0);
+        res.backward_err[s] = bound > 0 ? std::sqrt(t2[s]) / bound : 0.0;
+        if (last && res.backward_err[s] <= tol) ok = true;
+      }
+      res.converged[s] = ok ? 1 : 0;
+      if (c->h_done[s] == 2) breakdown = true;
+      if (!ok) all_ok = false;
+    }
+    if (all_ok || breakdown || last) break;
     // restart from the true residual; converged instances re-check immediately
     ++restarts;
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->r, c->q, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_dot(st, S, c->d_seg_col, c->r, c->r, c->partial);
-    LSQ2L_HIP_TRY(hipMemsetAsync(c->sc.done, 0, sizeof(int32_t) * S, st));
-    launch_scalar(st, OP_RNORM, S, c->partial, nullptr, c->sc, tol2, flexible);
+    launch_copy(st, n, c->q, c->r);
+    launch_fill_i32(st, S, 0, c->sc.done);
+    rnorm_step(c, tol2, flexible);
   }
-  *its_out = its;
-  *restarts_out = restarts;
+  LSQ2L_HIP_TRY(hipMemcpyAsync(c->h_its, c->sc.its, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  res.its.assign(c->h_its, c->h_its + S);
+  res.restarts = restarts;
+  res.total_its = its;
   if (breakdown) { set_error("PCG breakdown (non-positive curvature or non-finite value)"); return LSQ2L_PCG_BREAKDOWN; }
   for (int s = 0; s < S; ++s)
-    if (!(relres_true[s] <= c->opt.tol)) {
+    if (!res.converged[s]) {
       set_error("PCG did not reach the tolerance within max_it iterations");
       return LSQ2L_NOT_CONVERGED;
     }
   return LSQ2L_OK;
 }
+
+// True relative normal-equation residual ||rhs - C x|| / ||rhs|| per
+// instance (and ||x||^2 if asked), through the work vectors q and tm.
+lsq2l_status true_residual(lsq2l_ctx* c, const double* x, std::vector<double>& rel,
+                           std::vector<double>* x2) {
+  const hipStream_t st = c->st;
+  const int S = c->S;
+  apply_C(c, x, c->q, c->tm);
+  launch_sub(st, c->M.n, c->rhs, c->q, c->q);
+  std::vector<double> t2, r2;
+  launch_dot(st, S, c->d_seg_col, c->q, c->q, c->partial);
+  TRY(read_seg_sums(c, c->partial, t2));
+  launch_dot(st, S, c->d_seg_col, c->rhs, c->rhs, c->partial);
+  TRY(read_seg_sums(c, c->partial, r2));
+  if (x2) {
+    launch_dot(st, S, c->d_seg_col, x, x, c->partial);
+    TRY(read_seg_sums(c, c->partial, *x2));
+  }
+  rel.assign(S, 0.0);
+  for (int s = 0; s < S; ++s) rel[s] = r2[s] > 0 ? std::sqrt(t2[s] / r2[s]) : 0.0;
+  return LSQ2L_OK;
+}
+
+namespace {
 
 // The overlap maps of the plan, built on a host thread while the device
 // assembles, factors and selects; joined before their first use.
@@ -628,7 +584,6 @@ struct MapsJob {
   ~MapsJob() { if (th.joinable()) th.join(); }
 };
 
-// Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 // a thread joined on every exit from the scope that owns it
 struct JoiningThread {
   std::thread t;
@@ -637,6 +592,9 @@ struct JoiningThread {
   }
 };
 
+lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps);
+
+// Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const std::vector<int32_t>& part, int32_t nparts,
                         const std::vector<int32_t>& seg_of_part) {
@@ -650,25 +608,18 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   PinnedArray<int32_t> trp, tcol;
   TRY(trp.alloc((int64_t)n + 1));
   TRY(tcol.alloc(nnz));
-  int32_t *keys = nullptr, *vals = nullptr, *rows = nullptr;
   char* temp = nullptr;
   const size_t tb = transpose_temp_bytes(nnz, n);
-  {
-    TRY(c->dalloc(&c->M.trowptr, (int64_t)n + 1));
-    TRY(c->dalloc(&c->M.trow, nnz));
-    TRY(c->dalloc(&c->M.tperm, nnz));
-    TRY(c->dalloc(&keys, nnz));
-    TRY(c->dalloc(&vals, nnz));
-    TRY(c->dalloc(&rows, nnz));
-    TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
-    LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.trowptr, c->M.trow,
-                                   c->M.tperm, keys, vals, rows, temp, tb));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(trp.p, c->M.trowptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.p, c->M.trow, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
-  }
+  TRY(c->dalloc(&c->M.trowptr, (int64_t)n + 1));
+  TRY(c->dalloc(&c->M.trow, nnz));
+  TRY(c->dalloc(&c->M.tperm, nnz));
   TRY(c->dalloc(&c->M.tvals, nnz));
-  launch_gather_values(st, nnz, c->M.tperm, c->M.vals, c->M.tvals);
+  TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
+  LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.vals, c->M.trowptr,
+                                 c->M.trow, c->M.tvals, c->M.tperm, temp, tb));
+  LSQ2L_HIP_TRY(hipMemcpyAsync(trp.p, c->M.trowptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.p, c->M.trow, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
   // Row order of the copy used for C p = A^T (A p), found on a host thread
@@ -705,6 +656,29 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   LSQ2L_HIP_TRY(hipMemsetAsync(c->fac, 0, H.total_fac * sizeof(double), st));
   if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(c->ctg, 0, H.total_g * sizeof(double), st));
   launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg);
+  // Global shift of Section 4.1 ("Setup phase"): the preconditioner is built
+  // for C + s I, s = diag_shift_rel ||C||_F, i.e. for the least-squares
+  // matrix [A; sqrt(s) I].  Its rows sqrt(s) e_j enter Xi_i for j in
+  // Omega_Ii only, so C_ii gains s I, Ct_GG is unchanged, and the diagonal
+  // blocks of E gain s X_i^T X_i.  ||C||_F^2 sums, over the subdomains, the
+  // squares of their interior rows of C.
+  c->shift = 0.0;
+  if (c->opt.diag_shift_rel > 0.0) {
+    double* fr = nullptr;
+    TRY(c->dalloc(&fr, nparts));
+    launch_frob_interior(st, nparts, c->P, c->fac, fr);
+    std::vector<double> h(nparts);
+    LSQ2L_HIP_TRY(hipMemcpyAsync(h.data(), fr, sizeof(double) * nparts, hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    // a batch uses the largest instance norm (the shift only guards
+    // definiteness of the local and coarse factorizations)
+    std::vector<double> f2(c->S, 0.0);
+    for (int i = 0; i < nparts; ++i) f2[seg_of_part[i]] += h[i];
+    double fmax = 0.0;
+    for (double v : f2) fmax = std::max(fmax, v);
+    c->shift = c->opt.diag_shift_rel * std::sqrt(fmax);
+    if (c->shift > 0.0) launch_add_diag(st, nparts, c->P, c->shift, c->fac);
+  }
   launch_equilibrate(st, nparts, c->P, c->fac, c->ctg, c->scale);
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_assemble_ms = ms_since(t0);
@@ -725,7 +699,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   c->n0 = 0;
   c->n0tot = 0;
   t0 = clk::now();
-  if (c->opt.variant != LSQ2L_ONE_LEVEL) {
+  const bool two_level = c->opt.variant != LSQ2L_ONE_LEVEL && c->opt.variant != LSQ2L_RAS;
+  if (two_level) {
     double *Tg = nullptr, *work = nullptr, *sig = nullptr;
     int32_t* pc = nullptr;
     TRY(c->dalloc(&Tg, H.total_g));
@@ -753,7 +728,11 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     c->n0 = CP.n0;
     c->n0tot = CP.n0tot;
     c->etiles = CP.etiles;
-    LSQ2L_HIP_TRY(hipMemcpyAsync(c->P.subs, H.subs.data(), H.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice, st));
+    {
+      SubDesc* d_subs = nullptr;       // the coarse offsets filled in by plan_coarse
+      TRY(c->upload(&d_subs, H.subs));
+      c->P.subs = d_subs;
+    }
     TRY(c->upload(&c->Cc.segs, c->segs_h));
     if (c->n0 > 0) {
       c->coarse = true;
@@ -788,6 +767,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
         c->Cc.e_items = (int4*)d_items;
       }
       launch_coarse_E(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->W, c->efac);
+      if (c->shift > 0.0)
+        launch_coarse_E_shift(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->X, c->shift, c->efac);
       // right-looking Cholesky of E, one tile column per launch, each launch
       // also applying the previous column to the tiles right of the current
       // one (rows of column J - 1 below J: its list without row J)
@@ -832,8 +813,9 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
         // column blocks of E^{-1} onto one workgroup per compute unit, longest
         // first to the least loaded (block c of an instance with nt tile rows
         // costs 2 (nt - c) + 1 tile-row steps)
-        int ncu = 0;
-        LSQ2L_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0));
+        int ncu = 0, dev = 0;
+        LSQ2L_HIP_TRY(hipGetDevice(&dev));
+        LSQ2L_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         const int nbins = (int)std::min<int64_t>(std::max(1, ncu), c->etiles);
         std::vector<std::pair<int64_t, int32_t>> items;
         for (const SegDesc& sg : CP.segs)
@@ -919,21 +901,20 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     Mi.spmv_group = c->M.spmv_group;
     Mi.spmvt_group = c->M.spmvt_group;
     int32_t* dperm = nullptr;
-    TRY(c->upload(&dperm, ro.perm));
-    TRY(c->upload(&Mi.rowptr, ro.prp));
     TRY(c->dalloc(&Mi.colind, nnz));
     TRY(c->dalloc(&Mi.vals, nnz));
     TRY(c->dalloc(&Mi.trowptr, (int64_t)n + 1));
     TRY(c->dalloc(&Mi.trow, nnz));
     TRY(c->dalloc(&Mi.tperm, nnz));
     TRY(c->dalloc(&Mi.tvals, nnz));
+    TRY(c->upload(&dperm, ro.perm));
+    TRY(c->upload(&Mi.rowptr, ro.prp));
     launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
-    LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.trowptr, Mi.trow, Mi.tperm,
-                                   keys, vals, rows, temp, tb));
-    launch_gather_values(st, nnz, Mi.tperm, Mi.vals, Mi.tvals);
-    LSQ2L_HIP_TRY(hipStreamSynchronize(st));   // ro's vectors are uploaded from pageable memory
+    LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.vals, Mi.trowptr, Mi.trow,
+                                   Mi.tvals, Mi.tperm, temp, tb));
   }
   // --- solve workspace
+  const int S = c->S;
   TRY(c->dalloc(&c->r, n));
   TRY(c->dalloc(&c->z, n));
   TRY(c->dalloc(&c->p, n));
@@ -944,28 +925,34 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->dalloc(&c->xsave, n));
   TRY(c->dalloc(&c->tm, m));
   TRY(c->dalloc(&c->tm2, m));
-  if (c->opt.variant == LSQ2L_BALANCED) {
+  if (c->opt.variant == LSQ2L_BALANCED || c->opt.variant == LSQ2L_DEFLATED) {
     TRY(c->dalloc(&c->bal_u, n));
     TRY(c->dalloc(&c->bal_w, n));
   }
   TRY(c->dalloc(&c->bsave, m));
   TRY(c->dalloc(&c->loc, H.total_loc));
-  TRY(c->dalloc(&c->partial, (int64_t)c->S * RED_BLOCKS));
-  TRY(c->dalloc(&c->partial2, (int64_t)c->S * RED_BLOCKS));
+  TRY(c->dalloc(&c->partial, (int64_t)S * RED_BLOCKS));
+  TRY(c->dalloc(&c->partial2, (int64_t)S * RED_BLOCKS));
   double* scal = nullptr;
-  TRY(c->dalloc(&scal, 6 * (int64_t)c->S));
-  c->sc.rho = scal; c->sc.alpha = scal + c->S; c->sc.beta = scal + 2 * c->S;
-  c->sc.rn2 = scal + 3 * c->S; c->sc.r0n2 = scal + 4 * c->S; c->sc.pq = scal + 5 * c->S;
-  TRY(c->dalloc(&c->sc.done, c->S));
-  TRY(c->halloc(&c->h_done, c->S));
-  TRY(c->halloc(&c->h_rn2, c->S));
-  TRY(c->halloc(&c->h_r0n2, c->S));
+  TRY(c->dalloc(&scal, 6 * (int64_t)S));
+  c->sc.rho = scal; c->sc.alpha = scal + S; c->sc.beta = scal + 2 * S;
+  c->sc.rn2 = scal + 3 * S; c->sc.r0n2 = scal + 4 * S; c->sc.pq = scal + 5 * S;
+  TRY(c->dalloc(&c->sc.done, S));
+  TRY(c->dalloc(&c->sc.its, S));
+  TRY(c->halloc(&c->h_done, S));
+  TRY(c->halloc(&c->h_its, S));
+  TRY(c->halloc(&c->h_rn2, S));
+  TRY(c->halloc(&c->h_r0n2, S));
+  TRY(c->halloc(&c->h_part, (int64_t)S * RED_BLOCKS));
   TRY(c->upload(&c->d_seg_col, c->seg_col_h));
   TRY(c->upload(&c->d_seg_row, c->seg_row_h));
+  TRY(krylov_alloc(c));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  c->release_staged();
+  if (c->opt.autotune) TRY(autotune_spmv(c, 10));
   // --- info
   lsq2l_setup_info& inf = c->info;
-  inf.m = m; inf.n = n; inf.nnz = nnz; inf.nparts = nparts; inf.ninstances = c->S;
+  inf.m = m; inf.n = n; inf.nnz = nnz; inf.nparts = nparts; inf.ninstances = S;
   inf.n0 = c->n0;
   inf.max_ni = 0; inf.max_p = 0;
   int64_t dense = 0;
@@ -977,6 +964,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   inf.factor_tiles = H.total_fac / TT;
   inf.factor_bytes = H.total_fac * (c->opt.precision == LSQ2L_MIXED ? sizeof(float) : sizeof(double));
   inf.factor_dense_bytes = dense;
+  inf.factor_nnz_min = -1;
+  inf.shift = c->shift;
+  inf.spmv_lanes_A = c->M.spmv_group;
+  inf.spmv_lanes_AT = c->M.spmvt_group;
   inf.t_total_ms = ms_since(t_all);
   return LSQ2L_OK;
 }
@@ -987,31 +978,240 @@ lsq2l_status check_common(double tau, const lsq2l_options* opt) {
     if (!(opt->tol > 0.0)) { set_error("tol must be positive"); return LSQ2L_EINVAL; }
     if (opt->max_it < 1) { set_error("max_it must be >= 1"); return LSQ2L_EINVAL; }
     if (opt->precision != LSQ2L_FP64 && opt->precision != LSQ2L_MIXED) { set_error("bad precision"); return LSQ2L_EINVAL; }
-    if (opt->variant != LSQ2L_ADDITIVE && opt->variant != LSQ2L_ONE_LEVEL &&
-        opt->variant != LSQ2L_BALANCED) { set_error("bad variant"); return LSQ2L_EINVAL; }
+    if (opt->variant < LSQ2L_ADDITIVE || opt->variant > LSQ2L_DEFLATED) { set_error("bad variant"); return LSQ2L_EINVAL; }
+    if (opt->krylov < LSQ2L_PCG || opt->krylov > LSQ2L_GMRES) { set_error("bad krylov method"); return LSQ2L_EINVAL; }
+    if (opt->krylov != LSQ2L_GMRES && (opt->variant == LSQ2L_RAS || opt->variant == LSQ2L_DEFLATED)) {
+      set_error("RAS and DEFLATED are nonsymmetric preconditioners: use them with GMRES");
+      return LSQ2L_EINVAL;
+    }
+    if (opt->krylov == LSQ2L_GMRES && (opt->restart < 1 || opt->restart > 1000)) {
+      set_error("restart must lie in [1, 1000]");
+      return LSQ2L_EINVAL;
+    }
     if (opt->nev_max < 0) { set_error("nev_max must be >= 0"); return LSQ2L_EINVAL; }
+    if (!(opt->diag_shift_rel >= 0.0) || !(opt->adjoint_tol >= 0.0)) {
+      set_error("diag_shift_rel and adjoint_tol must be >= 0");
+      return LSQ2L_EINVAL;
+    }
   }
   return LSQ2L_OK;
 }
 
-lsq2l_status solve_impl(lsq2l_ctx* c, double* x, lsq2l_solve_info* info) {
+// Memory allocated on a device with hipMalloc (anything else, plain or
+// pinned host memory, is read on the host).
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t at;
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+// Row extents, column ranges and column order of one instance, with int64
+// row pointers rp (m + 1) and the instance's columns ci already shifted by
+// col0 (valid range [col0, col0 + n)).  Rows are checked in parallel blocks,
+// first every row's extent (so that the column pass reads inside ci), then
+// the columns; the first failing row of the first failing pass is reported.
+lsq2l_status validate_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, int64_t nnz,
+                          int64_t col0) {
+  if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
+  if (rp[m] != nnz) { set_error("rowptr[m] != nnz"); return LSQ2L_EINVAL; }
+  const unsigned nth = m < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<int64_t> bad_row(nth, INT64_MAX);
+  std::vector<int> bad_kind(nth, 0);
+  auto run = [&](auto&& fn) {
+    if (nth == 1) {
+      fn(0u);
+    } else {
+      std::vector<std::thread> pool;
+      for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
+      for (auto& th : pool) th.join();
+    }
+  };
+  auto rows_of = [&](unsigned t, int64_t& r0, int64_t& r1) {
+    r0 = m * t / nth;
+    r1 = m * (t + 1) / nth;
+  };
+  run([&](unsigned t) {
+    int64_t r0, r1;
+    rows_of(t, r0, r1);
+    for (int64_t r = r0; r < r1; ++r)
+      if (rp[r + 1] < rp[r] || rp[r + 1] > nnz) { bad_row[t] = r; bad_kind[t] = 1; return; }
+  });
+  bool extents_ok = true;
+  for (unsigned t = 0; t < nth; ++t) extents_ok = extents_ok && !bad_kind[t];
+  if (extents_ok)
+    run([&](unsigned t) {
+      int64_t r0, r1;
+      rows_of(t, r0, r1);
+      for (int64_t r = r0; r < r1; ++r)
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+          int kind = 0;
+          if (ci[e] < col0 || ci[e] >= col0 + n) kind = 2;
+          else if (e > rp[r] && ci[e] <= ci[e - 1]) kind = 3;
+          if (kind) { bad_row[t] = r; bad_kind[t] = kind; return; }
+        }
+    });
+  for (unsigned t = 0; t < nth; ++t) {
+    if (!bad_kind[t]) continue;
+    const std::string r = std::to_string(bad_row[t]);
+    if (bad_kind[t] == 1) set_error("rowptr is not monotone (or exceeds nnz) at row " + r);
+    else if (bad_kind[t] == 2) set_error("column index out of range in row " + r);
+    else set_error("columns not strictly increasing in row " + r);
+    return LSQ2L_EINVAL;
+  }
+  return LSQ2L_OK;
+}
+
+// Setup of one or several instances: their CSR arrays are concatenated on
+// the device (row pointers narrowed to int32 and shifted, columns shifted),
+// the patterns read back once into pinned memory and validated per instance.
+lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs) {
+  const hipStream_t st = c->st;
+  int64_t M = 0, N = 0, NNZ = 0, NP = 0;
+  for (int k = 0; k < count; ++k) {
+    const lsq2l_problem& pr = probs[k];
+    if (pr.m < 1 || pr.n < 1 || pr.m < pr.n || pr.nnz < 0 || pr.nparts < 1 || pr.nparts > pr.n ||
+        !pr.rowptr || !pr.part || (pr.nnz > 0 && (!pr.colind || !pr.vals))) {
+      set_error(count == 1 ? std::string("bad sizes or pointers: need m >= n >= 1, 1 <= nparts <= n")
+                           : "bad problem " + std::to_string(k));
+      return LSQ2L_EINVAL;
+    }
+    M += pr.m; N += pr.n; NNZ += pr.nnz; NP += pr.nparts;
+  }
+  if (M >= INT32_MAX || N >= INT32_MAX || NNZ >= INT32_MAX) {
+    set_error("m, n and nnz (summed over the instances) must stay below 2^31");
+    return LSQ2L_EINVAL;
+  }
+  c->S = count;
+  c->M.m = (int32_t)M; c->M.n = (int32_t)N; c->M.nnz = NNZ;
+  c->seg_row_h.assign(count + 1, 0);
+  c->seg_col_h.assign(count + 1, 0);
+  TRY(c->dalloc(&c->M.rowptr, M + 1));
+  TRY(c->dalloc(&c->M.colind, NNZ));
+  TRY(c->dalloc(&c->M.vals, NNZ));
+  PinnedArray<int64_t> rp64;
+  PinnedArray<int32_t> ci;
+  TRY(rp64.alloc(M + count));
+  TRY(ci.alloc(NNZ));
+  int64_t r0 = 0, c0 = 0, e0 = 0;
+  for (int k = 0; k < count; ++k) {
+    const lsq2l_problem& pr = probs[k];
+    launch_narrow_i64(st, pr.m + 1, pr.rowptr, 0, (int32_t)e0, c->M.rowptr + r0);
+    launch_offset_i32(st, pr.nnz, pr.colind, (int32_t)c0, c->M.colind + e0);
+    if (pr.nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(c->M.vals + e0, pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(rp64.p + r0 + k, pr.rowptr, (pr.m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    r0 += pr.m; c0 += pr.n; e0 += pr.nnz;
+    c->seg_row_h[k + 1] = r0;
+    c->seg_col_h[k + 1] = c0;
+  }
+  if (NNZ) LSQ2L_HIP_TRY(hipMemcpyAsync(ci.p, c->M.colind, NNZ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  // partitions: host arrays are read in place, device arrays copied back
+  std::vector<int32_t> pt(N), seg_of_part(NP);
+  std::vector<std::vector<int32_t>> pdev(count);
+  for (int k = 0; k < count; ++k)
+    if (is_device_ptr(probs[k].part)) {
+      pdev[k].resize(probs[k].n);
+      LSQ2L_HIP_TRY(hipMemcpyAsync(pdev[k].data(), probs[k].part, probs[k].n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+  const hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return LSQ2L_EHIP; }
+  std::vector<int32_t> rp(M + 1);
+  r0 = 0; c0 = 0; e0 = 0;
+  int64_t p0 = 0;
+  for (int k = 0; k < count; ++k) {
+    const lsq2l_problem& pr = probs[k];
+    const int64_t* lrp = rp64.p + r0 + k;
+    const lsq2l_status s = validate_csr(pr.m, pr.n, lrp, ci.p + e0, pr.nnz, c0);
+    if (s != LSQ2L_OK) {
+      if (count > 1) set_error("problem " + std::to_string(k) + ": " + g_err);
+      return s;
+    }
+    for (int64_t r = 0; r <= pr.m; ++r) rp[r0 + r] = (int32_t)(e0 + lrp[r]);
+    const int32_t* part = pdev[k].empty() ? probs[k].part : pdev[k].data();
+    for (int64_t j = 0; j < pr.n; ++j) {
+      if (part[j] < 0 || part[j] >= pr.nparts) {
+        set_error(count == 1 ? "part[" + std::to_string(j) + "] out of range"
+                             : "part out of range in problem " + std::to_string(k));
+        return LSQ2L_EINVAL;
+      }
+      pt[c0 + j] = (int32_t)(p0 + part[j]);
+    }
+    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0 + q] = k;
+    r0 += pr.m; c0 += pr.n; e0 += pr.nnz; p0 += pr.nparts;
+  }
+  return setup_core(c, rp.data(), ci.p, pt, (int32_t)NP, seg_of_part);
+}
+
+lsq2l_ctx* new_handle(double tau, const lsq2l_options* opt, void* hip_stream) {
+  lsq2l_ctx* c = new lsq2l_ctx();
+  c->st = (hipStream_t)hip_stream;
+  lsq2l_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  c->tau = tau;
+  return c;
+}
+
+lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps) {
+  hipEvent_t e0, e1;
+  LSQ2L_HIP_TRY(hipEventCreate(&e0));
+  LSQ2L_HIP_TRY(hipEventCreate(&e1));
+  struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{e0, e1};
+  launch_fill(c->st, c->M.n, 1.0, c->p);
+  launch_fill(c->st, c->M.m, 1.0, c->tm);
+  DevMatrix& M = c->row_perm ? c->Mi : c->M;
+  for (int which = 0; which < 2; ++which) {
+    int best = 1;
+    float best_ms = 1e30f;
+    for (int g = 1; g <= 64; g *= 2) {
+      auto once = [&]() {
+        if (which == 0) launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, c->p, c->tm2, g);
+        else launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, c->tm, c->q, g);
+      };
+      once();
+      LSQ2L_HIP_TRY(hipEventRecord(e0, c->st));
+      for (int k = 0; k < reps; ++k) once();
+      LSQ2L_HIP_TRY(hipEventRecord(e1, c->st));
+      LSQ2L_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      LSQ2L_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) { best_ms = ms; best = g; }
+    }
+    if (which == 0) { c->M.spmv_group = best; c->Mi.spmv_group = best; }
+    else { c->M.spmvt_group = best; c->Mi.spmvt_group = best; }
+  }
+  c->info.spmv_lanes_A = c->M.spmv_group;
+  c->info.spmv_lanes_AT = c->M.spmvt_group;
+  return LSQ2L_OK;
+}
+
+lsq2l_status solve_dispatch(lsq2l_ctx* c, double* x, bool adjoint, lsq2l_solve_info* info) {
   auto t0 = clk::now();
-  std::vector<double> rt(c->S), rr(c->S);
-  int its = 0, restarts = 0;
-  lsq2l_status s = pcg(c, x, &its, &restarts, rt.data(), rr.data());
+  KrylovResult res;
+  lsq2l_status s;
+  const double tol = adjoint && c->opt.adjoint_tol > 0.0 ? c->opt.adjoint_tol : c->opt.tol;
+  if (adjoint) TRY(norm_C(c));
+  if (c->opt.krylov == LSQ2L_GMRES) s = gmres(c, x, adjoint, tol, res);
+  else if (c->opt.krylov == LSQ2L_LSQR && !adjoint) s = lsqr(c, c->bsave, x, tol, res);
+  else s = pcg(c, x, adjoint, tol, res);    // CG, and the adjoint of LSQR (M is symmetric)
+  if (s != LSQ2L_OK && s != LSQ2L_NOT_CONVERGED) return s;
   const double ms = ms_since(t0);
   if (info)
     for (int k = 0; k < c->S; ++k) {
-      info[k].iterations = its;
-      info[k].restarts = restarts;
-      info[k].relres = rt[k];
-      info[k].relres_rec = rr[k];
+      info[k].iterations = k < (int)res.its.size() ? res.its[k] : res.total_its;
+      info[k].restarts = res.restarts;
+      info[k].relres = k < (int)res.relres.size() ? res.relres[k] : 0.0;
+      info[k].relres_rec = k < (int)res.relres_rec.size() ? res.relres_rec[k] : 0.0;
       info[k].solve_ms = ms;
+      info[k].backward_err = adjoint && k < (int)res.backward_err.size() ? res.backward_err[k] : 0.0;
     }
   return s;
 }
 
 }  // namespace
+}  // namespace lsq2l
 
 extern "C" {
 
@@ -1026,55 +1226,30 @@ void lsq2l_default_options(lsq2l_options* opt) {
   opt->nev_max = 0;
   opt->check_every = 1;
   opt->use_graph = 0;
+  opt->krylov = LSQ2L_PCG;
+  opt->restart = 100;
+  opt->diag_shift_rel = 0.0;
+  opt->adjoint_tol = 0.0;
+  opt->autotune = 0;
 }
 
 const char* lsq2l_last_error(void) { return g_err.c_str(); }
 
-lsq2l_status lsq2l_setup(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
+lsq2l_status lsq2l_setup(int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
                          const int32_t* colind, const double* vals, const int32_t* part,
                          int32_t nparts, int32_t overlap, double tau, const lsq2l_options* opt,
                          void* hip_stream, lsq2l_handle* out) {
   g_err.clear();
   if (!out) { set_error("out is NULL"); return LSQ2L_EINVAL; }
   *out = nullptr;
-  if (m < 1 || n < 1 || m < n) { set_error("need m >= n >= 1"); return LSQ2L_EINVAL; }
-  if (nnz < 0 || !rowptr || (nnz > 0 && (!colind || !vals)) || !part) { set_error("bad CSR pointers"); return LSQ2L_EINVAL; }
-  if (nparts < 1 || nparts > n) { set_error("nparts must lie in [1, n]"); return LSQ2L_EINVAL; }
   if (overlap != 1) { set_error("only overlap = 1 (one layer, Section 3) is supported"); return LSQ2L_EINVAL; }
   TRY(check_common(tau, opt));
-  for (int32_t j = 0; j < n; ++j)
-    if (part[j] < 0 || part[j] >= nparts) { set_error("part[" + std::to_string(j) + "] out of range"); return LSQ2L_EINVAL; }
-  lsq2l_ctx* c = new lsq2l_ctx();
-  c->st = (hipStream_t)hip_stream;
-  lsq2l_default_options(&c->opt);
-  if (opt) c->opt = *opt;
-  c->tau = tau;
-  c->S = 1;
-  c->M.m = m; c->M.n = n; c->M.nnz = nnz;
-  c->seg_row_h = {0, m};
-  c->seg_col_h = {0, n};
-  auto fail = [&](lsq2l_status s) { delete c; return s; };
-  std::vector<int32_t> pt(part, part + n);
-  PinnedArray<int32_t> rp, ci;
-  lsq2l_status s;
-  if ((s = rp.alloc((int64_t)m + 1)) != LSQ2L_OK) return fail(s);
-  if ((s = ci.alloc(nnz)) != LSQ2L_OK) return fail(s);
-  if ((s = c->dalloc(&c->M.rowptr, m + 1)) != LSQ2L_OK) return fail(s);
-  if ((s = c->dalloc(&c->M.colind, nnz)) != LSQ2L_OK) return fail(s);
-  if ((s = c->dalloc(&c->M.vals, nnz)) != LSQ2L_OK) return fail(s);
-  hipError_t e = hipMemcpyAsync(rp.p, rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
-  if (e == hipSuccess && nnz) e = hipMemcpyAsync(ci.p, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-  if (rp.p[m] != nnz) { set_error("rowptr[m] != nnz"); return fail(LSQ2L_EINVAL); }
-  if ((s = validate_csr(m, n, rp.p, ci.p, nnz)) != LSQ2L_OK) return fail(s);
-  e = hipMemcpyAsync(c->M.rowptr, rowptr, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
-  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.colind, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st);
-  if (e == hipSuccess && nnz) e = hipMemcpyAsync(c->M.vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
-  if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-  std::vector<int32_t> seg_of_part(nparts, 0);
-  s = setup_core(c, rp.p, ci.p, pt, nparts, seg_of_part);
-  if (s != LSQ2L_OK) return fail(s);
+  lsq2l_problem pr{};
+  pr.m = m; pr.n = n; pr.nnz = nnz;
+  pr.rowptr = rowptr; pr.colind = colind; pr.vals = vals; pr.part = part; pr.nparts = nparts;
+  lsq2l_ctx* c = new_handle(tau, opt, hip_stream);
+  const lsq2l_status s = setup_instances(c, 1, &pr);
+  if (s != LSQ2L_OK) { delete c; return s; }
   *out = c;
   return LSQ2L_OK;
 }
@@ -1085,59 +1260,9 @@ lsq2l_status lsq2l_setup_batched(int32_t count, const lsq2l_problem* probs, doub
   if (!out || !probs || count < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
   *out = nullptr;
   TRY(check_common(tau, opt));
-  int64_t M = 0, N = 0, NNZ = 0, NP = 0;
-  for (int k = 0; k < count; ++k) {
-    const lsq2l_problem& pr = probs[k];
-    if (pr.m < 1 || pr.n < 1 || pr.m < pr.n || pr.nnz < 0 || pr.nparts < 1 || pr.nparts > pr.n ||
-        !pr.rowptr || !pr.part || (pr.nnz > 0 && (!pr.colind || !pr.vals))) {
-      set_error("bad problem " + std::to_string(k));
-      return LSQ2L_EINVAL;
-    }
-    M += pr.m; N += pr.n; NNZ += pr.nnz; NP += pr.nparts;
-  }
-  if (M >= INT32_MAX || NNZ >= INT32_MAX) { set_error("batch too large for int32 indices"); return LSQ2L_EINVAL; }
-  lsq2l_ctx* c = new lsq2l_ctx();
-  c->st = (hipStream_t)hip_stream;
-  lsq2l_default_options(&c->opt);
-  if (opt) c->opt = *opt;
-  c->tau = tau;
-  c->S = count;
-  c->M.m = (int32_t)M; c->M.n = (int32_t)N; c->M.nnz = NNZ;
-  auto fail = [&](lsq2l_status s) { delete c; return s; };
-  std::vector<int32_t> rp(M + 1, 0), ci(NNZ), pt(N), seg_of_part(NP);
-  c->seg_row_h.assign(count + 1, 0);
-  c->seg_col_h.assign(count + 1, 0);
-  lsq2l_status s;
-  if ((s = c->dalloc(&c->M.rowptr, M + 1)) != LSQ2L_OK) return fail(s);
-  if ((s = c->dalloc(&c->M.colind, NNZ)) != LSQ2L_OK) return fail(s);
-  if ((s = c->dalloc(&c->M.vals, NNZ)) != LSQ2L_OK) return fail(s);
-  int64_t r0 = 0, c0 = 0, e0 = 0, p0 = 0;
-  for (int k = 0; k < count; ++k) {
-    const lsq2l_problem& pr = probs[k];
-    std::vector<int32_t> lrp(pr.m + 1), lci(pr.nnz);
-    hipError_t e = hipMemcpyAsync(lrp.data(), pr.rowptr, (pr.m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
-    if (e == hipSuccess && pr.nnz) e = hipMemcpyAsync(lci.data(), pr.colind, pr.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
-    if (e == hipSuccess && pr.nnz) e = hipMemcpyAsync(c->M.vals + e0, pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    if (e != hipSuccess) { set_error(std::string("reading problem: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-    if (lrp[pr.m] != pr.nnz) { set_error("rowptr[m] != nnz in problem " + std::to_string(k)); return fail(LSQ2L_EINVAL); }
-    if ((s = validate_csr(pr.m, pr.n, lrp.data(), lci.data(), pr.nnz)) != LSQ2L_OK) return fail(s);
-    for (int32_t rr = 0; rr < pr.m; ++rr) rp[r0 + rr + 1] = (int32_t)(e0 + lrp[rr + 1]);
-    for (int32_t q = 0; q < pr.nnz; ++q) ci[e0 + q] = (int32_t)(c0 + lci[q]);
-    for (int32_t j = 0; j < pr.n; ++j) {
-      if (pr.part[j] < 0 || pr.part[j] >= pr.nparts) { set_error("part out of range in problem " + std::to_string(k)); return fail(LSQ2L_EINVAL); }
-      pt[c0 + j] = (int32_t)(p0 + pr.part[j]);
-    }
-    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0 + q] = k;
-    r0 += pr.m; c0 += pr.n; e0 += pr.nnz; p0 += pr.nparts;
-    c->seg_row_h[k + 1] = r0;
-    c->seg_col_h[k + 1] = c0;
-  }
-  hipError_t e = hipMemcpyAsync(c->M.rowptr, rp.data(), (M + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
-  if (e == hipSuccess && NNZ) e = hipMemcpyAsync(c->M.colind, ci.data(), NNZ * sizeof(int32_t), hipMemcpyHostToDevice, c->st);
-  if (e != hipSuccess) { set_error(std::string("copying A: ") + hipGetErrorString(e)); return fail(LSQ2L_EHIP); }
-  s = setup_core(c, rp.data(), ci.data(), pt, (int32_t)NP, seg_of_part);
-  if (s != LSQ2L_OK) return fail(s);
+  lsq2l_ctx* c = new_handle(tau, opt, hip_stream);
+  const lsq2l_status s = setup_instances(c, count, probs);
+  if (s != LSQ2L_OK) { delete c; return s; }
   *out = c;
   return LSQ2L_OK;
 }
@@ -1145,12 +1270,37 @@ lsq2l_status lsq2l_setup_batched(int32_t count, const lsq2l_problem* probs, doub
 lsq2l_status lsq2l_solve(lsq2l_handle c, const double* b, double* x, lsq2l_solve_info* info) {
   g_err.clear();
   if (!c || !b || !x) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  c->have_solution = false;
   LSQ2L_HIP_TRY(hipMemcpyAsync(c->bsave, b, c->M.m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   spmv_AT(c, b, c->rhs);
-  lsq2l_status s = solve_impl(c, x, info);
+  const lsq2l_status s = solve_dispatch(c, x, false, info);
+  if (s != LSQ2L_OK && s != LSQ2L_NOT_CONVERGED) return s;
   LSQ2L_HIP_TRY(hipMemcpyAsync(c->xsave, x, c->M.n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
-  c->have_solution = (s == LSQ2L_OK || s == LSQ2L_NOT_CONVERGED);
+  c->have_solution = true;
+  return s;
+}
+
+lsq2l_status lsq2l_solve_batched(lsq2l_handle c, const double* const* b, double* const* x,
+                                 lsq2l_solve_info* info) {
+  g_err.clear();
+  if (!c || !b || !x) { set_error("NULL argument"); return LSQ2L_EINVAL; }
+  for (int k = 0; k < c->S; ++k)
+    if (!b[k] || !x[k]) { set_error("NULL right-hand side or solution of instance " + std::to_string(k)); return LSQ2L_EINVAL; }
+  c->have_solution = false;
+  for (int k = 0; k < c->S; ++k) {
+    const int64_t r0 = c->seg_row_h[k], mk = c->seg_row_h[k + 1] - r0;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(c->bsave + r0, b[k], mk * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  }
+  spmv_AT(c, c->bsave, c->rhs);
+  const lsq2l_status s = solve_dispatch(c, c->xsave, false, info);
+  if (s != LSQ2L_OK && s != LSQ2L_NOT_CONVERGED) return s;
+  for (int k = 0; k < c->S; ++k) {
+    const int64_t c0 = c->seg_col_h[k], nk = c->seg_col_h[k + 1] - c0;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(x[k], c->xsave + c0, nk * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  }
+  LSQ2L_HIP_TRY(hipStreamSynchronize(c->st));
+  c->have_solution = true;
   return s;
 }
 
@@ -1160,7 +1310,7 @@ lsq2l_status lsq2l_backward(lsq2l_handle c, const double* g, double* dLdb, doubl
   if (!c || !g) { set_error("NULL argument"); return LSQ2L_EINVAL; }
   if (!c->have_solution) { set_error("backward needs a previous solve"); return LSQ2L_EINVAL; }
   LSQ2L_HIP_TRY(hipMemcpyAsync(c->rhs, g, c->M.n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  lsq2l_status s = solve_impl(c, c->xwork, info);       // lambda = C^{-1} g
+  const lsq2l_status s = solve_dispatch(c, c->xwork, true, info);       // lambda = C^{-1} g
   if (s != LSQ2L_OK && s != LSQ2L_NOT_CONVERGED) return s;
   spmv_A(c, c->xwork, c->tm);                            // A lambda
   if (dLdb) LSQ2L_HIP_TRY(hipMemcpyAsync(dLdb, c->tm, c->M.m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
@@ -1194,6 +1344,7 @@ lsq2l_status lsq2l_apply_preconditioner(lsq2l_handle c, const double* r, double*
 lsq2l_status lsq2l_get_info(lsq2l_handle c, lsq2l_setup_info* out) {
   if (!c || !out) { set_error("NULL argument"); return LSQ2L_EINVAL; }
   *out = c->info;
+  out->factor_nnz_min = c->fac_nnz_min;
   return LSQ2L_OK;
 }
 
@@ -1226,15 +1377,24 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
                                double* bytes) {
   g_err.clear();
   if (!c || !avg_ms || !bytes || reps < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
-  if (kernel < 0 || kernel > 3 || (kernel == 3 && !c->coarse)) { set_error("unknown or unused kernel"); return LSQ2L_EINVAL; }
+  if (kernel < 0 || kernel > 4 || (kernel == 3 && !c->coarse)) { set_error("unknown or unused kernel"); return LSQ2L_EINVAL; }
   const double m = c->M.m, n = c->M.n, nnz = (double)c->M.nnz;
   const double eb = (c->opt.precision == LSQ2L_MIXED) ? 4.0 : 8.0;
+  if (kernel == 4) TRY(factor_nnz_min(c));
   switch (kernel) {
     case 0: *bytes = 12.0 * nnz + 4.0 * (m + 1) + 8.0 * n + 8.0 * m; break;
     case 1: *bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * m + 8.0 * n; break;
     // each sweep reads every stored off-diagonal tile and every diagonal
     // inverse once (as many elements as the stored factor), plus y in and out
     case 2: *bytes = 2.0 * eb * (double)c->H.total_fac + 16.0 * (double)c->H.total_loc; break;
+    // the algorithmic minimum: each sweep reads the nnz(L_i) entries of the
+    // factors under a fill-reducing order, y in and out per local unknown
+    case 4: {
+      double nloc = 0;
+      for (const SubDesc& d : c->H.subs) nloc += d.nI + d.nG;
+      *bytes = 2.0 * eb * (double)c->fac_nnz_min + 16.0 * nloc;
+      break;
+    }
     default: {
       double tri = 0, parts = 0;
       for (const SegDesc& sg : c->segs_h) {
@@ -1259,9 +1419,7 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
       case 0: spmv_it_A(c, c->p, c->tm); break;
       case 1: spmv_it_AT(c, c->tm, c->q); break;
       case 2:
-        if (c->opt.precision == LSQ2L_MIXED) launch_local_solve_f32(c->st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
-        else launch_local_solve(c->st, c->nsub, c->P, c->fac, c->dinv, c->loc);
-        break;
+      case 4: local_solves(c); break;
       default: launch_einv_gemv(c->st, c->n0tot, c->S, c->Cc, c->einv, c->cvec, c->dvec);
     }
   };
@@ -1278,11 +1436,56 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
   return LSQ2L_OK;
 }
 
+lsq2l_status lsq2l_autotune(lsq2l_handle c, int32_t reps, int32_t* lanes) {
+  g_err.clear();
+  if (!c || reps < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
+  TRY(autotune_spmv(c, reps));
+  if (lanes) { lanes[0] = c->M.spmv_group; lanes[1] = c->M.spmvt_group; }
+  return LSQ2L_OK;
+}
+
+lsq2l_status lsq2l_transpose(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
+                             const int32_t* colind, const double* vals, int32_t* trowptr,
+                             int32_t* trow, double* tvals, int32_t* tperm, void* hip_stream) {
+  g_err.clear();
+  if (m < 0 || n < 0 || nnz < 0 || !rowptr || !trowptr || (nnz > 0 && (!colind || !trow)) ||
+      (nnz > 0 && tvals && !vals)) {
+    set_error("bad sizes or NULL required pointer");
+    return LSQ2L_EINVAL;
+  }
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const size_t tb = transpose_temp_bytes(nnz, n);
+  // the sort carries the permutation; a caller that does not want it gets
+  // a temporary one.  The last 256 bytes hold the column check flag.
+  const size_t perm_bytes = tperm ? 0 : ((size_t)nnz * sizeof(int32_t) + 255) / 256 * 256;
+  void* temp = nullptr;
+  LSQ2L_HIP_TRY(hipMalloc(&temp, tb + perm_bytes + 256));
+  int32_t* perm = tperm ? tperm : (int32_t*)((char*)temp + tb);
+  int32_t* flag = (int32_t*)((char*)temp + tb + perm_bytes);
+  int32_t hflag = 0;
+  launch_check_cols(st, nnz, colind, n, flag);
+  hipError_t e = hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && hflag == 0)
+    e = launch_transpose(st, m, n, nnz, rowptr, colind, vals, trowptr, trow, tvals, perm, temp, tb);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(temp);
+  if (e != hipSuccess) {
+    set_error(std::string("transpose: ") + hipGetErrorString(e));
+    return LSQ2L_EHIP;
+  }
+  if (hflag) {
+    set_error("transpose: a column index lies outside [0, n)");
+    return LSQ2L_EINVAL;
+  }
+  return LSQ2L_OK;
+}
+
 void lsq2l_destroy(lsq2l_handle c) { delete c; }
 
 void lsq2l_release_cache(void) {
-  block_cache().release();
-  pinned_pool().release();
+  cache_release();
+  pinned_release();
 }
 
 }  // extern "C"

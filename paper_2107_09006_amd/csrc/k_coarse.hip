@@ -425,6 +425,45 @@ k_coarse_E(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
   }
 }
 
+// Diagonal blocks of E for a shifted C: E_ii += s X_i^T X_i, the
+// contribution of the rows sqrt(s) e_j (j in Omega_Ii) that the shift adds to
+// A.  Same work items and output layout as k_coarse_E; only the items of
+// diagonal pairs act, with the interior rows of X_i as the shared rows.
+__global__ void __launch_bounds__(256)
+k_coarse_E_shift(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ pairs,
+                 const int4* __restrict__ items, const int32_t* __restrict__ eF,
+                 const int64_t* __restrict__ eOff, const double* __restrict__ X, double shift,
+                 double* __restrict__ efac) {
+  const int4 it = items[blockIdx.x];
+  const PairDesc pr = pairs[it.x];
+  if (pr.i != pr.j) return;
+  const SubDesc d = subs[pr.i];
+  const double* Xi = X + d.x_off;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int bi = wave / 2, bj = wave % 2, li = lane % 16, lk = lane / 16;
+  const int l = it.y * TS + 16 * bi + li;
+  const int k = it.z * TS + 16 * bj + li;
+  const bool lv = l < d.p, kv = k < d.p;
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const double* xl = Xi + (int64_t)l * d.nIp;
+  const double* xk = Xi + (int64_t)k * d.nIp;
+  for (int t0 = 0; t0 < d.nI; t0 += 4) {
+    const int t = t0 + lk;
+    const double a = (lv && t < d.nI) ? xl[t] : 0.0;
+    const double b = (kv && t < d.nI) ? xk[t] : 0.0;
+    acc = Mfma<double>::mma(a, b, acc);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int lr = it.y * TS + 16 * bi + Mfma<double>::acc_row(lane, v);
+    const int kc = it.z * TS + 16 * bj + Mfma<double>::acc_col(lane, v);
+    if (lr >= d.p || kc >= d.p) continue;
+    const int64_t row = d.cg_off + lr, col = d.cg_off + kc;
+    if (row < col) continue;
+    const int I = (int)(row / TS), J = (int)(col / TS);
+    efac[tile_pos(eF, eOff, I, J) * TT + (col % TS) * TS + (row % TS)] += shift * acc[v];
+  }
+}
+
 // One step J of the right-looking tile Cholesky of E, fused with the
 // trailing update of the previous column, in one launch.
 // - Workgroups below ndiag (panel role) apply column J - 1 to the tiles of
@@ -1023,6 +1062,12 @@ void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoar
   if (nitems == 0) return;
   k_coarse_E<<<nitems, 256, 0, st>>>(P.subs, Cc.pairs, Cc.pair_rows, Cc.e_items, Cc.eF, Cc.eOff, W,
                                      efac);
+}
+
+void launch_coarse_E_shift(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
+                           const double* X, double s, double* efac) {
+  if (nitems == 0) return;
+  k_coarse_E_shift<<<nitems, 256, 0, st>>>(P.subs, Cc.pairs, Cc.e_items, Cc.eF, Cc.eOff, X, s, efac);
 }
 
 void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,

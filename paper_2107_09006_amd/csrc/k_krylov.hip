@@ -125,6 +125,7 @@ __global__ void k_scalar(int op, int S, const double* __restrict__ partial,
         sc.done[s] = 2;
       } else {
         sc.alpha[s] = sc.rho[s] / v;
+        sc.its[s] += 1;
       }
       break;
     case OP_RNORM:
@@ -231,6 +232,321 @@ void launch_copy(hipStream_t st, int64_t n, const double* a, double* out) {
 void launch_fill(hipStream_t st, int64_t n, double v, double* out) {
   if (n == 0) return;
   k_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, v, out);
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = v;
+}
+
+void launch_fill_i32(hipStream_t st, int64_t n, int32_t v, int32_t* out) {
+  if (n == 0) return;
+  k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, v, out);
+}
+
+__global__ void k_hash_fill(int64_t n, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint64_t h = (uint64_t)k * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  out[k] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+void launch_hash_fill(hipStream_t st, int64_t n, double* out) {
+  if (n == 0) return;
+  k_hash_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, out);
+}
+
+__global__ void k_scale_seg(int64_t n, int S, const int64_t* __restrict__ seg_ptr,
+                            const double* __restrict__ f, const double* __restrict__ a,
+                            double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  out[k] = a[k] * f[S == 1 ? 0 : seg_of(k, S, seg_ptr)];
+}
+
+void launch_scale_seg(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const double* f,
+                      const double* a, double* out) {
+  if (n == 0) return;
+  k_scale_seg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, S, seg_ptr, f, a, out);
+}
+
+// ---------------------------------------------------------------------------
+// LSQR (Section 4.1, "Solution phase"): Golub-Kahan bidiagonalization of
+// A W^{-1}, M = W^{-1} W^{-T}, carried in x-space.  With v the unit vector of
+// the bidiagonalization, the iteration keeps vt = W^{-1} v and zh = W^T v:
+//   u <- (A vt - alpha u) / beta,
+//   q  = A^T u - beta zh,  s = M q,  alpha = sqrt(q^T s),
+//   zh <- q / alpha,  vt <- s / alpha,
+// so alpha = ||W^{-T} A^T u - beta v|| needs products with M only.  The
+// plane rotations, the step x += (phi / rho) wt, wt <- vt - (theta / rho) wt
+// and the estimates ||A W^{-1}||_F^2 = sum (alpha^2 + beta^2),
+// ||(A W^{-1})^T r|| = alpha |c phibar|-style follow Paige and Saunders.
+// done: 0 active, 1 converged, 2 breakdown, 3 converged by this step (its
+// update still applies).
+// ---------------------------------------------------------------------------
+__global__ void k_lsqr_scalar(int op, int S, const double* __restrict__ partial,
+                              double* __restrict__ scb, int32_t* __restrict__ done,
+                              int32_t* __restrict__ its, double tol) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double v = 0.0;
+  for (int b = 0; b < RED_BLOCKS; ++b) v += partial[(int64_t)s * RED_BLOCKS + b];
+  double* sc = scb + (int64_t)s * LSQR_NSC;
+  switch (op) {
+    case LSQR_INIT_BETA: {
+      const double beta = sqrt(v);
+      sc[LS_BETA] = beta;
+      sc[LS_PHIBAR] = beta;
+      sc[LS_ANORM2] = 0.0;
+      sc[LS_RNORM0] = beta;
+      sc[LS_TEST] = 1.0;
+      its[s] = 0;
+      done[s] = !isfinite(v) ? 2 : (beta == 0.0 ? 1 : 0);
+      break;
+    }
+    case LSQR_INIT_ALPHA: {
+      if (done[s] != 0) { sc[LS_ALPHA] = 0.0; break; }
+      if (!isfinite(v) || v < 0.0) { done[s] = 2; sc[LS_ALPHA] = 0.0; break; }
+      const double alpha = sqrt(v);
+      sc[LS_ALPHA] = alpha;
+      sc[LS_RHOBAR] = alpha;
+      if (alpha == 0.0) { done[s] = 1; sc[LS_TEST] = 0.0; }
+      break;
+    }
+    case LSQR_BETA: {
+      if (done[s] == 3) done[s] = 1;
+      if (done[s] != 0) break;
+      if (!isfinite(v)) { done[s] = 2; break; }
+      const double beta = sqrt(v);
+      const double a = sc[LS_ALPHA];
+      sc[LS_ANORM2] += a * a + beta * beta;
+      sc[LS_BETA] = beta;
+      break;
+    }
+    case LSQR_ALPHA: {
+      if (done[s] != 0) break;
+      if (!isfinite(v) || v < 0.0) { done[s] = 2; break; }
+      const double alpha = sqrt(v);
+      const double rhobar = sc[LS_RHOBAR], beta = sc[LS_BETA], phibar = sc[LS_PHIBAR];
+      const double rho = hypot(rhobar, beta);
+      const double c = rhobar / rho, sn = beta / rho;
+      const double theta = sn * alpha;
+      const double phi = c * phibar;
+      const double phibar_new = sn * phibar;
+      const double tau = sn * phi;
+      sc[LS_RHOBAR] = -c * alpha;
+      sc[LS_PHIBAR] = phibar_new;
+      sc[LS_T1] = phi / rho;
+      sc[LS_T2] = -theta / rho;
+      sc[LS_ALPHA] = alpha;
+      const double anorm = sqrt(sc[LS_ANORM2]);
+      const double test = (phibar_new == 0.0) ? 0.0 : alpha * fabs(tau) / (anorm * phibar_new);
+      sc[LS_TEST] = test;
+      its[s] += 1;
+      if (!isfinite(test) || !isfinite(sc[LS_T1])) done[s] = 2;
+      else if (test <= tol || alpha == 0.0) done[s] = 3;
+      break;
+    }
+  }
+}
+
+void launch_lsqr_scalar(hipStream_t st, int op, int S, const double* partial, double* sc,
+                        int32_t* done, int32_t* its, double tol) {
+  k_lsqr_scalar<<<(S + 63) / 64, 64, 0, st>>>(op, S, partial, sc, done, its, tol);
+}
+
+__global__ void k_lsqr_u(int64_t m, int S, const int64_t* __restrict__ seg_ptr,
+                         const double* __restrict__ sc, const int32_t* __restrict__ done,
+                         const double* __restrict__ a, double* __restrict__ u, int first) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  if (done[s] != 0) return;
+  u[k] = first ? a[k] : a[k] - sc[(int64_t)s * LSQR_NSC + LS_ALPHA] * u[k];
+}
+
+void launch_lsqr_u(hipStream_t st, int64_t m, int S, const int64_t* seg_row, const double* sc,
+                   const int32_t* done, const double* a, double* u, int first) {
+  if (m == 0) return;
+  k_lsqr_u<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, S, seg_row, sc, done, a, u, first);
+}
+
+__global__ void k_lsqr_unorm(int64_t m, int S, const int64_t* __restrict__ seg_ptr,
+                             const double* __restrict__ sc, const int32_t* __restrict__ done,
+                             double* __restrict__ u) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  if (done[s] != 0) return;
+  const double beta = sc[(int64_t)s * LSQR_NSC + LS_BETA];
+  u[k] = beta > 0.0 ? u[k] / beta : 0.0;
+}
+
+void launch_lsqr_unorm(hipStream_t st, int64_t m, int S, const int64_t* seg_row, const double* sc,
+                       const int32_t* done, double* u) {
+  if (m == 0) return;
+  k_lsqr_unorm<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, S, seg_row, sc, done, u);
+}
+
+__global__ void k_lsqr_q(int64_t n, int S, const int64_t* __restrict__ seg_ptr,
+                         const double* __restrict__ sc, const int32_t* __restrict__ done,
+                         const double* __restrict__ zh, double* __restrict__ q, int first) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  if (done[s] != 0) { q[k] = 0.0; return; }
+  if (!first) q[k] -= sc[(int64_t)s * LSQR_NSC + LS_BETA] * zh[k];
+}
+
+void launch_lsqr_q(hipStream_t st, int64_t n, int S, const int64_t* seg_col, const double* sc,
+                   const int32_t* done, const double* zh, double* q, int first) {
+  if (n == 0) return;
+  k_lsqr_q<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, S, seg_col, sc, done, zh, q, first);
+}
+
+__global__ void k_lsqr_update(int64_t n, int S, const int64_t* __restrict__ seg_ptr,
+                              const double* __restrict__ scb, const int32_t* __restrict__ done,
+                              const double* __restrict__ q, const double* __restrict__ sv,
+                              double* __restrict__ zh, double* __restrict__ v,
+                              double* __restrict__ w, double* __restrict__ x, int first) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  const int dn = done[s];
+  if (!(dn == 0 || dn == 3)) return;
+  const double* sc = scb + (int64_t)s * LSQR_NSC;
+  const double alpha = sc[LS_ALPHA];
+  const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  const double vn = sv[k] * ia;
+  zh[k] = q[k] * ia;
+  v[k] = vn;
+  if (first) {
+    w[k] = vn;
+  } else {
+    const double wo = w[k];
+    x[k] += sc[LS_T1] * wo;
+    w[k] = vn + sc[LS_T2] * wo;
+  }
+}
+
+void launch_lsqr_update(hipStream_t st, int64_t n, int S, const int64_t* seg_col, const double* sc,
+                        const int32_t* done, const double* q, const double* s, double* zh,
+                        double* v, double* w, double* x, int first) {
+  if (n == 0) return;
+  k_lsqr_update<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, S, seg_col, sc, done, q, s, zh, v,
+                                                             w, x, first);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES building blocks: Gram-Schmidt against the stored basis V, with
+// per-instance coefficients and fixed-order reductions
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum_256_sync(double v, double* sh) {
+  v = wave_allsum(v);
+  const int wave = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) sh[wave] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256)
+k_multidot(const int64_t* __restrict__ seg_ptr, int64_t n, int kv, const double* __restrict__ V,
+           const double* __restrict__ w, double* __restrict__ partial, int ld) {
+  __shared__ double sh[4];
+  const int s = blockIdx.y, blk = blockIdx.x;
+  const int64_t lo = seg_ptr[s], hi = seg_ptr[s + 1];
+  const int64_t chunk = (hi - lo + RED_BLOCKS - 1) / RED_BLOCKS;
+  const int64_t c0 = lo + blk * chunk, c1 = min(hi, c0 + chunk);
+  for (int i = 0; i < kv; ++i) {
+    const double* vi = V + (int64_t)i * n;
+    double acc = 0.0;
+    for (int64_t k = c0 + threadIdx.x; k < c1; k += blockDim.x) acc += vi[k] * w[k];
+    acc = block_sum_256_sync(acc, sh);
+    if (threadIdx.x == 0) partial[((int64_t)s * RED_BLOCKS + blk) * ld + i] = acc;
+  }
+}
+
+void launch_multidot(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                     const double* V, const double* w, double* partial, int ld) {
+  if (k == 0) return;
+  k_multidot<<<dim3(RED_BLOCKS, S), 256, 0, st>>>(seg_ptr, n, k, V, w, partial, ld);
+}
+
+__global__ void k_multidot_reduce(int S, int kv, const double* __restrict__ partial, int ld,
+                                  double* __restrict__ h, int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S * kv) return;
+  const int s = t / kv, i = t % kv;
+  double v = 0.0;
+  for (int b = 0; b < RED_BLOCKS; ++b) v += partial[((int64_t)s * RED_BLOCKS + b) * ld + i];
+  if (accumulate) h[(int64_t)s * ld + i] += v;
+  else h[(int64_t)s * ld + i] = v;
+}
+
+void launch_multidot_reduce(hipStream_t st, int S, int k, const double* partial, int ld,
+                            double* h, int accumulate) {
+  if (k == 0) return;
+  k_multidot_reduce<<<(S * k + 63) / 64, 64, 0, st>>>(S, k, partial, ld, h, accumulate);
+}
+
+// out_k (-)= sum_i V_i[k] c[seg(k) * ld + i]
+template <bool SUB>
+__global__ void k_multi_comb(int S, const int64_t* __restrict__ seg_ptr, int64_t n, int kv,
+                             const double* __restrict__ V, const double* __restrict__ c, int ld,
+                             double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  const double* cs = c + (int64_t)s * ld;
+  double acc = 0.0;
+  for (int i = 0; i < kv; ++i) acc += V[(int64_t)i * n + k] * cs[i];
+  out[k] = SUB ? out[k] - acc : acc;
+}
+
+void launch_multi_axpy(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                       const double* V, const double* h, int ld, double* w) {
+  if (n == 0 || k == 0) return;
+  k_multi_comb<true><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(S, seg_ptr, n, k, V, h, ld, w);
+}
+
+void launch_multi_gemv(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                       const double* V, const double* y, int ld, double* out) {
+  if (n == 0) return;
+  k_multi_comb<false><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(S, seg_ptr, n, k, V, y, ld, out);
+}
+
+__global__ void k_normalize_seg(int64_t n, int S, const int64_t* __restrict__ seg_ptr,
+                                const double* __restrict__ nrm2, const int32_t* __restrict__ done,
+                                const double* __restrict__ a, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int s = S == 1 ? 0 : seg_of(k, S, seg_ptr);
+  const double q = nrm2[s];
+  const bool ok = q > 0.0 && isfinite(q) && (done == nullptr || done[s] == 0);
+  out[k] = ok ? a[k] / sqrt(q) : 0.0;
+}
+
+void launch_normalize_seg(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr,
+                          const double* nrm2, const int32_t* done, const double* a, double* out) {
+  if (n == 0) return;
+  k_normalize_seg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, S, seg_ptr, nrm2, done, a, out);
+}
+
+__global__ void k_seg_sum(int S, const double* __restrict__ partial, double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double v = 0.0;
+  for (int b = 0; b < RED_BLOCKS; ++b) v += partial[(int64_t)s * RED_BLOCKS + b];
+  out[s] = v;
+}
+
+void launch_seg_sum(hipStream_t st, int S, const double* partial, double* out) {
+  k_seg_sum<<<(S + 63) / 64, 64, 0, st>>>(S, partial, out);
 }
 
 }  // namespace lsq2l

@@ -281,21 +281,29 @@ k_gather_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ ome
 // z_j = sum over the subdomains holding column j of S_pos loc_pos (fixed
 // order), plus the coarse prolongation X_i d_i on the interior of its owner.
 // Without loc only the prolongation is formed, without dcoarse only the sum.
+// With `restricted`, column j takes only the value of its own subdomain's
+// interior (R_i^T D_i of eq. RAS: D_i is zero on Omega_Gamma_i).
 template <typename TX>
 __global__ void k_scatter_local(int32_t n, const int32_t* __restrict__ own_ptr,
                                 const int32_t* __restrict__ own_pos, const double* __restrict__ scale,
                                 const double* __restrict__ loc, const int32_t* __restrict__ part,
                                 const int32_t* __restrict__ locown, const SubDesc* __restrict__ subs,
                                 const TX* __restrict__ X, const double* __restrict__ dcoarse,
-                                double* __restrict__ z) {
+                                double* __restrict__ z, int restricted) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double s = 0.0;
-  if (loc != nullptr)
-    for (int q = own_ptr[j]; q < own_ptr[j + 1]; ++q) {
-      const int pos = own_pos[q];
-      s += scale[pos] * loc[pos];
+  if (loc != nullptr) {
+    if (restricted) {
+      const int64_t pos = subs[part[j]].loc_off + locown[j];
+      s = scale[pos] * loc[pos];
+    } else {
+      for (int q = own_ptr[j]; q < own_ptr[j + 1]; ++q) {
+        const int pos = own_pos[q];
+        s += scale[pos] * loc[pos];
+      }
     }
+  }
   if (dcoarse != nullptr) {
     const SubDesc d = subs[part[j]];
     const int a = locown[j];
@@ -352,17 +360,80 @@ void launch_gather_local(hipStream_t st, int nsub, const DevPlan& P, const doubl
 
 
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
-                          const double* loc, const double* X, const double* dcoarse, double* z) {
+                          const double* loc, const double* X, const double* dcoarse, double* z,
+                          bool restricted) {
   if (n == 0) return;
   k_scatter_local<double><<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc,
-                                                           P.part, P.locown, P.subs, X, dcoarse, z);
+                                                           P.part, P.locown, P.subs, X, dcoarse, z,
+                                                           restricted ? 1 : 0);
 }
 
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
-                          const double* loc, const float* X, const double* dcoarse, double* z) {
+                          const double* loc, const float* X, const double* dcoarse, double* z,
+                          bool restricted) {
   if (n == 0) return;
   k_scatter_local<float><<<(n + 255) / 256, 256, 0, st>>>(n, P.own_ptr, P.own_pos, scale, loc,
-                                                          P.part, P.locown, P.subs, X, dcoarse, z);
+                                                          P.part, P.locown, P.subs, X, dcoarse, z,
+                                                          restricted ? 1 : 0);
+}
+
+// ||C(Omega_Ii, :)||_F^2 from the lower triangle of the assembled C_ii: the
+// rows of C owned by subdomain i are its interior rows, and every column
+// they couple to lies in Omega_i.  Entries (r, c), r >= c, count twice when
+// both are interior (the upper mirror), once on the diagonal and once in the
+// (Gamma, I) block; the (Gamma, Gamma) block belongs to other subdomains.
+// One workgroup per subdomain, the sum in a fixed order.
+__global__ void __launch_bounds__(256)
+k_frob_interior(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+                const int64_t* __restrict__ tileOff, const double* __restrict__ fac,
+                double* __restrict__ out) {
+  __shared__ double sh[4];
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  double acc = 0.0;
+  for (int t = 0; t < d.ntiles; ++t) {
+    const int nt = t - F[t] + 1;
+    const double* row = A + off[t] * TT;
+    for (int64_t e = threadIdx.x; e < (int64_t)nt * TT; e += blockDim.x) {
+      const int J = F[t] + (int)(e / TT);
+      const int rc = (int)(e % TT);
+      const int r = t * TS + rc % TS, c = J * TS + rc / TS;
+      if (r < c || c >= d.nI) continue;      // upper part, or a column outside the interior
+      const double v = row[e];
+      const double wgt = (r < d.nI) ? (r == c ? 1.0 : 2.0) : 1.0;
+      acc += wgt * v * v;
+    }
+  }
+  acc = wave_allsum(acc);
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// C_ii += s I on the positions of real columns (the padding keeps its zero
+// diagonal until the equilibration turns it into identity rows)
+__global__ void __launch_bounds__(256)
+k_add_diag(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
+           const int64_t* __restrict__ tileOff, double s, double* __restrict__ fac) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  double* A = fac + d.fac_off;
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    const bool real = pos < d.nI || (pos >= d.nIp && pos < d.nIp + d.nG);
+    if (real) A[tile_pos(F, off, pos / TS, pos / TS) * TT + (pos % TS) * TS + pos % TS] += s;
+  }
+}
+
+void launch_frob_interior(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                          double* out) {
+  k_frob_interior<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, out);
+}
+
+void launch_add_diag(hipStream_t st, int nsub, const DevPlan& P, double s, double* fac) {
+  k_add_diag<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, s, fac);
 }
 
 }  // namespace lsq2l

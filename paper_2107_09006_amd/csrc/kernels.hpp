@@ -55,15 +55,22 @@ struct DevCoarse {            // coarse space and coarse operator
 // a 256-thread workgroup)
 constexpr int ESYM_ROWTILES = 8;
 
-// --- device transpose of A's pattern ---------------------------------------
+// --- device transpose of A (hand-written radix sort) ------------------------
 size_t transpose_temp_bytes(int64_t nnz, int32_t n);
 void launch_permute_rows(hipStream_t st, int32_t m, const int32_t* perm, const int32_t* rowptr,
                          const int32_t* colind, const double* vals, const int32_t* prowptr,
                          int32_t* pcolind, double* pvals);
+// trowptr (n + 1), trow and tperm (nnz) written; tvals written if not null
+// (vals must then be given); temp holds transpose_temp_bytes(nnz, n) bytes
 hipError_t launch_transpose(hipStream_t st, int32_t m, int32_t n, int64_t nnz, const int32_t* rowptr,
-                            const int32_t* colind, int32_t* trowptr, int32_t* trow, int32_t* tperm,
-                            int32_t* work_keys, int32_t* work_vals, int32_t* work_rows, void* temp,
+                            const int32_t* colind, const double* vals, int32_t* trowptr,
+                            int32_t* trow, double* tvals, int32_t* tperm, void* temp,
                             size_t temp_bytes);
+void launch_narrow_i64(hipStream_t st, int64_t n, const int64_t* in, int64_t sub, int32_t add,
+                       int32_t* out);
+void launch_offset_i32(hipStream_t st, int64_t n, const int32_t* in, int32_t add, int32_t* out);
+// flag (one int32, device) = 1 if a column index lies outside [0, n)
+void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32_t n, int32_t* flag);
 
 // --- sparse kernels -------------------------------------------------------
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
@@ -80,6 +87,7 @@ enum ScalarOp { OP_R0 = 0, OP_RHO_INIT = 1, OP_ALPHA = 2, OP_RNORM = 3, OP_BETA 
 struct Scalars {
   double *rho, *alpha, *beta, *rn2, *r0n2, *pq;
   int32_t* done;      // 0 active, 1 converged, 2 breakdown
+  int32_t* its;       // iterations of each instance (x updated while active)
 };
 void launch_scalar(hipStream_t st, int op, int S, const double* partial, const double* partial2,
                    Scalars sc, double tol2, int flexible);
@@ -91,6 +99,53 @@ void launch_sub(hipStream_t st, int64_t n, const double* a, const double* b, dou
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_fill(hipStream_t st, int64_t n, double v, double* out);
 void launch_copy(hipStream_t st, int64_t n, const double* a, double* out);
+// out_k = a_k * f[segment of k] (per-instance factors on the device)
+void launch_scale_seg(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr, const double* f,
+                      const double* a, double* out);
+void launch_fill_i32(hipStream_t st, int64_t n, int32_t v, int32_t* out);
+// a fixed pseudo-random vector in [-1, 1) (start of the power method)
+void launch_hash_fill(hipStream_t st, int64_t n, double* out);
+
+// --- LSQR (left-preconditioned, M^{-1} inner product) ------------------------
+// per-instance scalars, LSQR_NSC per instance at sc + s * LSQR_NSC
+enum LsqrSc { LS_ALPHA = 0, LS_BETA, LS_RHOBAR, LS_PHIBAR, LS_ANORM2, LS_T1, LS_T2, LS_TEST,
+              LS_RNORM0, LS_NSC };
+constexpr int LSQR_NSC = LS_NSC;
+enum LsqrOp { LSQR_INIT_BETA = 0, LSQR_INIT_ALPHA = 1, LSQR_BETA = 2, LSQR_ALPHA = 3 };
+void launch_lsqr_scalar(hipStream_t st, int op, int S, const double* partial, double* sc,
+                        int32_t* done, int32_t* its, double tol);
+// u = a - alpha u (m-space, row segments; active instances only)
+void launch_lsqr_u(hipStream_t st, int64_t m, int S, const int64_t* seg_row, const double* sc,
+                   const int32_t* done, const double* a, double* u, int first);
+// u *= 1 / beta (m-space)
+void launch_lsqr_unorm(hipStream_t st, int64_t m, int S, const int64_t* seg_row, const double* sc,
+                       const int32_t* done, double* u);
+// q = q - beta zh (n-space)
+void launch_lsqr_q(hipStream_t st, int64_t n, int S, const int64_t* seg_col, const double* sc,
+                   const int32_t* done, const double* zh, double* q, int first);
+// zh = q / alpha; v = s / alpha; x += t1 w; w = v + t2 w (first: w = v, x untouched)
+void launch_lsqr_update(hipStream_t st, int64_t n, int S, const int64_t* seg_col, const double* sc,
+                        const int32_t* done, const double* q, const double* s, double* zh,
+                        double* v, double* w, double* x, int first);
+
+// --- GMRES -------------------------------------------------------------------
+// partial[(s * RED_BLOCKS + b) * ld + i] = chunk b of segment s of V_i . w, i < k
+void launch_multidot(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                     const double* V, const double* w, double* partial, int ld);
+// h[s * ld + i] (+)= sum_b partial (fixed order), i < k
+void launch_multidot_reduce(hipStream_t st, int S, int k, const double* partial, int ld,
+                            double* h, int accumulate);
+// w -= sum_{i<k} V_i h[s * ld + i]
+void launch_multi_axpy(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                       const double* V, const double* h, int ld, double* w);
+// out = sum_{i<k} V_i y[s * ld + i]
+void launch_multi_gemv(hipStream_t st, int S, const int64_t* seg_ptr, int64_t n, int k,
+                       const double* V, const double* y, int ld, double* out);
+// out_k = a_k / sqrt(nrm2[segment]) (0 where the norm is zero or the instance is done)
+void launch_normalize_seg(hipStream_t st, int64_t n, int S, const int64_t* seg_ptr,
+                          const double* nrm2, const int32_t* done, const double* a, double* out);
+// norm2[s] = sum_b partial[s * RED_BLOCKS + b]
+void launch_seg_sum(hipStream_t st, int S, const double* partial, double* out);
 
 // --- subdomain kernels -------------------------------------------------------
 void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, const double* src,
@@ -108,10 +163,18 @@ void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double
                         const double* dinv, double* loc);
 void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
                             const float* dinv, double* loc);
+// restricted: each column takes its owner's interior value only (R_i^T D_i, eq. RAS)
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
-                          const double* loc, const double* X, const double* dcoarse, double* z);
+                          const double* loc, const double* X, const double* dcoarse, double* z,
+                          bool restricted = false);
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
-                          const double* loc, const float* X, const double* dcoarse, double* z);
+                          const double* loc, const float* X, const double* dcoarse, double* z,
+                          bool restricted = false);
+// ||C(Omega_Ii, :)||_F^2 of every subdomain from the assembled (unscaled) C_ii
+void launch_frob_interior(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
+                          double* out);
+// C_ii += s I on the real (non-padding) positions
+void launch_add_diag(hipStream_t st, int nsub, const DevPlan& P, double s, double* fac);
 
 // --- coarse space ------------------------------------------------------------
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
@@ -127,6 +190,9 @@ void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix
                      const double* X, double* W);
 void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
                      const double* W, double* efac);
+// diagonal blocks of E += s X_i^T X_i (the rows sqrt(s) e_j of a shifted C)
+void launch_coarse_E_shift(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
+                           const double* X, double s, double* efac);
 void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
                        const int32_t* prows, int npr, double* efac, double* edinv, int32_t* status);
 void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out);

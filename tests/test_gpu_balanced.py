@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.test_gpu_parity import (EPS, L, _np, _t, max_local_condition,  # noqa: F401
+from tests.test_gpu_parity import (EPS, L, _np, _t, assert_close, max_local_condition,  # noqa: F401
                                    max_span_tolerance, oracle, problem, solver)
 
 pytestmark = pytest.mark.gpu
@@ -109,13 +109,13 @@ def test_balanced_solve_parity(L, name):
     s = solver(L, p, tol=1e-10, variant=L.BALANCED)
     x, info, _ = s.solve(_t(p.b))
     assert info[0]["relres"] <= 1e-10
-    assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    assert_close(_np(x), ref["x"], 1e-8)
     assert abs(info[0]["iterations"] - ref["its"]) <= max(1, math.ceil(0.03 * ref["its"]))
     s.close()
     s = solver(L, p, tol=1e-10, variant=L.BALANCED, precision=L.MIXED, flexible=1)
     x, info, _ = s.solve(_t(p.b))
     assert info[0]["relres"] <= 1e-10
-    assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+    assert_close(_np(x), ref["x"], 1e-6)
     s.close()
 
 

@@ -8,9 +8,13 @@ Bars (derived in the design notes):
     sides hold different, equally valid bases of the same coarse space, so
     the coarse solve differs at the rounding level amplified by kappa(E));
   * solution: relative error <= 1e-8 (FP64) / 1e-6 (mixed) against the oracle
-    PCG at tol 1e-10, true relative residual <= tol, iterations within 1
-    (FP64);
+    PCG at tol 1e-10, true relative residual <= tol, iterations within
+    max(1, 3%) (FP64, two-level);
   * gradients: relative error <= 1e-5.
+Every norm-wise comparison of a vector comes with a component-wise one
+(``assert_close``): each entry's error is at most 10 tol times its own
+magnitude plus the vector's root-mean-square, so that a few badly wrong
+entries cannot hide under the 2-norm.
 """
 import math
 
@@ -42,6 +46,20 @@ def _t(a):
 
 def _np(t):
     return t.detach().cpu().numpy()
+
+
+def assert_close(x, ref, tol):
+    """||x - ref|| <= tol ||ref||, and entry-wise
+    |x_i - ref_i| <= 10 tol (|ref_i| + rms(ref))."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    nrm = np.linalg.norm(ref)
+    err = np.linalg.norm(x - ref)
+    assert err <= tol * nrm, f"norm-wise relative error {err / nrm:.3e} > {tol:.1e}"
+    rms = nrm / np.sqrt(max(ref.size, 1))
+    ce = np.abs(x - ref) / (np.abs(ref) + rms)
+    k = int(np.argmax(ce))
+    assert ce[k] <= 10 * tol, f"component-wise error {ce[k]:.3e} at entry {k} > {10 * tol:.1e}"
 
 
 PROBLEMS = {
@@ -231,8 +249,7 @@ def test_preconditioner_parity(L, name, variant):
     tol = 10 * EPS * max_local_condition(name)
     if variant == "additive" and orc.E is not None:
         tol = max(tol, 1e-13 * np.linalg.cond(orc.E), max_span_tolerance(name))
-    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
-    assert err <= tol, f"relative error {err:.3e} > {tol:.3e}"
+    assert_close(z, zr, tol)
     s.close()
 
 
@@ -246,7 +263,7 @@ def test_solve_parity_fp64(L, name, variant):
     x, info, st = s.solve(_t(p.b))
     x = _np(x)
     assert info[0]["relres"] <= 1e-10
-    assert np.linalg.norm(x - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    assert_close(x, ref["x"], 1e-8)
     # Rounding differences (summation order) shift the iteration count of a
     # run once its Krylov basis has lost orthogonality: a few steps for the
     # two-level method, more for one-level runs of 100+ iterations, whose
@@ -264,7 +281,7 @@ def test_solve_parity_mixed(L, name):
         s = solver(L, p, tol=1e-10, precision=L.MIXED, flexible=flexible)
         x, info, _ = s.solve(_t(p.b))
         assert info[0]["relres"] <= 1e-10
-        assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+        assert_close(_np(x), ref["x"], 1e-6)
         s.close()
 
 
@@ -273,12 +290,14 @@ def test_solve_matches_dense_least_squares(L):
     s = solver(L, p, tol=1e-12)
     x, info, _ = s.solve(_t(p.b))
     xs = np.linalg.lstsq(p.scipy().toarray(), p.b, rcond=None)[0]
-    assert np.linalg.norm(_np(x) - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert_close(_np(x), xs, 1e-9)
     s.close()
 
 
 @pytest.mark.parametrize("name", ["banded_1000", "grid", "banded"])
 def test_backward_parity(L, name):
+    """The adjoint converges on its backward-error rule (status OK, no
+    warning) and the gradients match the oracle's within 1e-5."""
     p = problem(name)
     orc = oracle(name)
     xstar = np.random.default_rng(11).standard_normal(p.n)
@@ -286,9 +305,10 @@ def test_backward_parity(L, name):
     go = orc.backward(p.b, xo, xo - xstar, tol=1e-11)
     s = solver(L, p, tol=1e-11)
     x, _, _ = s.solve(_t(p.b))
-    dLdb, dLdv, _ = s.backward(x - _t(xstar))
-    assert np.linalg.norm(_np(dLdb) - go["dLdb"]) <= 1e-5 * np.linalg.norm(go["dLdb"])
-    assert np.linalg.norm(_np(dLdv) - go["dLdvals"]) <= 1e-5 * np.linalg.norm(go["dLdvals"])
+    dLdb, dLdv, info = s.backward(x - _t(xstar))
+    assert info[0]["relres"] <= 1e-11 or info[0]["backward_err"] <= 1e-11
+    assert_close(_np(dLdb), go["dLdb"], 1e-5)
+    assert_close(_np(dLdv), go["dLdvals"], 1e-5)
     s.close()
 
 
@@ -340,8 +360,8 @@ def test_autograd_function(L):
     orc = oracle("banded_1000")
     xo = orc.solve(p.b, tol=1e-12)["x"]
     go = orc.backward(p.b, xo, xo - _np(xstar), tol=1e-12)
-    assert np.linalg.norm(_np(b.grad) - go["dLdb"]) <= 1e-6 * np.linalg.norm(go["dLdb"])
-    assert np.linalg.norm(_np(vals.grad) - go["dLdvals"]) <= 1e-6 * np.linalg.norm(go["dLdvals"])
+    assert_close(_np(b.grad), go["dLdb"], 1e-6)
+    assert_close(_np(vals.grad), go["dLdvals"], 1e-6)
     s.close()
 
 
@@ -359,7 +379,8 @@ def test_batched_instances(L):
         orc = O.Oracle(q.scipy(), q.part, q.nparts, 0.1).setup()
         ref = orc.solve(q.b, tol=1e-10)
         assert infos[k]["relres"] <= 1e-10
-        assert np.linalg.norm(x[off:off + q.n] - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+        assert_close(x[off:off + q.n], ref["x"], 1e-8)
+        assert abs(infos[k]["iterations"] - ref["its"]) <= 1
         for i in range(q.nparts):
             d = s.subdomain(sub + i)
             np.testing.assert_array_equal(d["I"], orc.sets[i].I + off)
@@ -393,7 +414,7 @@ def test_single_subdomain_is_direct_solve(L):
     x, info, _ = s.solve(_t(p.b))
     assert info[0]["iterations"] == 1
     xs = np.linalg.lstsq(p.scipy().toarray(), p.b, rcond=None)[0]
-    assert np.linalg.norm(_np(x) - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert_close(_np(x), xs, 1e-10)
     s.close()
 
 
@@ -420,7 +441,7 @@ def test_tau_near_one_and_nev_cap(L):
     assert [s.subdomain(i)["p"] for i in range(p.nparts)] == list(orc.p)
     r = np.random.default_rng(6).standard_normal(p.n)
     z = _np(s.apply_preconditioner(_t(r)))
-    assert np.linalg.norm(z - orc.apply(r)) <= 1e-10 * np.linalg.norm(orc.apply(r))
+    assert_close(z, orc.apply(r), 1e-10)
     s.close()
 
 
@@ -571,17 +592,19 @@ def test_full_size_grid(L):
     xv = np.random.default_rng(9).standard_normal(p.n)
     ax = _np(s.spmv(_t(xv)))
     assert np.all(np.abs(ax - A @ xv) <= 8 * EPS * (abs(A) @ np.abs(xv)) + 1e-300)
-    sets = O.index_sets(A, p.part, p.nparts)
-    for i in (0, 119, 255):     # corner, interior and last patch
+    picks = (0, 119, 255)      # corner, interior (four-sided interface) and last patch
+    sets = dict(zip(picks, O.index_sets(A, p.part, p.nparts, subdomains=picks)))
+    for i in picks:
         d = s.subdomain(i)
         np.testing.assert_array_equal(d["I"], sets[i].I)
         np.testing.assert_array_equal(d["Xi"], sets[i].Xi)
         np.testing.assert_array_equal(d["G"], sets[i].G)
-    for i in (0,):              # the oracle's eigenproblem on a sampled subdomain
+    assert sets[119].nG == 252
+    for i in (0, 119):          # the oracle's eigenproblem on sampled subdomains
         d = s.subdomain(i)
         Cii, Ctii = O.local_matrices(A, sets[i])
         res = O.coarse_vectors(Cii, Ctii, sets[i].nI, p.tau)
-        assert d["p"] == res["p"]
+        assert d["p"] == res["p"], (i, d["p"], res["p"])
         ang = sla.subspace_angles(s.coarse_basis(i), res["X"])
         assert ang.max() <= span_tolerance(Cii, Ctii, sets[i].nI, p.tau)
     for prec in results:
