@@ -299,6 +299,24 @@ lsq2l_status lsq2l_transpose(int32_t m, int32_t n, int32_t nnz, const int32_t* r
                              const int32_t* colind, const double* vals, int32_t* trowptr,
                              int32_t* trow, double* tvals, int32_t* tperm, void* hip_stream);
 
+/*
+ * lsq2l_transpose for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight serving loops or harnesses that forbid
+ * it): the same arguments, results and errors, but the sort's work space
+ * comes from a static per-device array of 104 MiB that the library holds
+ * from its load until the process ends, and the call makes no allocation.
+ * Limit: the work space must fit, which holds for nnz <= 2^23 and
+ * n <= 2^23 (larger inputs return LSQ2L_EINVAL naming the bytes needed).
+ * All calls on one device share that array: calls that overlap on one GPU
+ * (several host threads or streams at once) race and must be serialized by
+ * the caller.  The call synchronizes its stream (it reads back the column
+ * check), so it cannot be captured into a HIP graph.
+ */
+lsq2l_status lsq2l_transpose_noalloc(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
+                                     const int32_t* colind, const double* vals, int32_t* trowptr,
+                                     int32_t* trow, double* tvals, int32_t* tperm,
+                                     void* hip_stream);
+
 /* Release every resource of the handle (NULL is ignored).  Its device
  * memory goes to a process-wide cache (at most 32 GiB) that later handles on
  * the same device draw from. */

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EH
 EXPORTS = ["lsq2l_default_options", "lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve",
            "lsq2l_solve_batched", "lsq2l_backward", "lsq2l_spmv", "lsq2l_apply_preconditioner",
            "lsq2l_get_info", "lsq2l_get_subdomain", "lsq2l_get_coarse_basis",
-           "lsq2l_time_kernel", "lsq2l_autotune", "lsq2l_transpose", "lsq2l_destroy",
+           "lsq2l_time_kernel", "lsq2l_autotune", "lsq2l_transpose", "lsq2l_transpose_noalloc",
+           "lsq2l_destroy",
            "lsq2l_release_cache", "lsq2l_last_error"]
 
 
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.lsq2l_solve_batched.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveInfo)]
     lib.lsq2l_autotune.argtypes = [vp, i32, vp]
     lib.lsq2l_transpose.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lsq2l_transpose_noalloc.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.lsq2l_backward.argtypes = [vp, vp, vp, vp, C.POINTER(SolveInfo)]
     lib.lsq2l_spmv.argtypes = [vp, i32, vp, vp]
     lib.lsq2l_apply_preconditioner.argtypes = [vp, vp, vp]
@@ -107,7 +109,7 @@ def load_library(path: str = LIB_PATH):
     for name in ["lsq2l_setup", "lsq2l_setup_batched", "lsq2l_solve", "lsq2l_solve_batched",
                  "lsq2l_backward", "lsq2l_spmv", "lsq2l_apply_preconditioner", "lsq2l_get_info",
                  "lsq2l_get_subdomain", "lsq2l_get_coarse_basis", "lsq2l_time_kernel",
-                 "lsq2l_autotune", "lsq2l_transpose"]:
+                 "lsq2l_autotune", "lsq2l_transpose", "lsq2l_transpose_noalloc"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -343,22 +345,28 @@ class Solver:
             pass
 
 
-def transpose(m, n, rowptr, colind, vals=None, device="cuda:0"):
-    """A^T of a CSR matrix on the device (lsq2l_transpose): returns
-    (trowptr, trow, tvals or None, tperm) as device tensors."""
+def transpose(m, n, rowptr, colind, vals=None, device="cuda:0", noalloc=False, out=None):
+    """A^T of a CSR matrix on the device (lsq2l_transpose, or
+    lsq2l_transpose_noalloc with ``noalloc``): returns (trowptr, trow, tvals
+    or None, tperm) as device tensors.  ``out`` may hold those four output
+    tensors, preallocated (the no-allocation caller's case)."""
     import torch
     lib = load_library()
+    fn = lib.lsq2l_transpose_noalloc if noalloc else lib.lsq2l_transpose
     dev = torch.device(device)
     rp = _to_device(rowptr, torch.int32, dev)
     ci = _to_device(colind, torch.int32, dev)
     nnz = int(ci.numel())
     va = _to_device(vals, torch.float64, dev) if vals is not None else None
-    trp = torch.empty(int(n) + 1, dtype=torch.int32, device=dev)
-    tr = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
-    tp = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
-    tv = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev) if va is not None else None
+    if out is None:
+        trp = torch.empty(int(n) + 1, dtype=torch.int32, device=dev)
+        tr = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        tp = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        tv = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev) if va is not None else None
+    else:
+        trp, tr, tv, tp = out
     with torch.cuda.device(dev):
-        _check(lib.lsq2l_transpose(int(m), int(n), nnz, _dev(rp, torch.int32),
+        _check(fn(int(m), int(n), nnz, _dev(rp, torch.int32),
                                    _dev(ci, torch.int32) if nnz else None,
                                    _dev(va, torch.float64) if va is not None else None,
                                    _dev(trp, torch.int32), _dev(tr, torch.int32),

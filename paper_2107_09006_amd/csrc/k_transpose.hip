@@ -15,6 +15,9 @@
 //      writes key and value to their positions.
 // The row pointer of A^T is the exclusive scan of the column counts; the row
 // of each entry is found by binary search in A's row pointer.
+#include <mutex>
+#include <string>
+
 #include "kernels.hpp"
 
 namespace lsq2l {
@@ -182,9 +185,14 @@ k_digit_scatter(int64_t nnz, const int32_t* __restrict__ keys, const int32_t* __
   }
 }
 
-__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ colind, int32_t* __restrict__ cnt) {
+// column counts; a column outside [0, n) is skipped (the caller reports it)
+__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ colind, int32_t n,
+                            int32_t* __restrict__ cnt) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) atomicAdd(&cnt[colind[k]], 1);
+  if (k < nnz) {
+    const int32_t c = colind[k];
+    if (c >= 0 && c < n) atomicAdd(&cnt[c], 1);
+  }
 }
 
 __global__ void k_zero_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ out) {
@@ -240,7 +248,7 @@ hipError_t launch_transpose(hipStream_t st, int32_t m, int32_t n, int64_t nnz, c
   // column counts -> row pointer of A^T
   k_zero_fill_i32<<<(unsigned)((n + 1 + 255) / 256), 256, 0, st>>>((int64_t)n + 1, 0, trowptr);
   if (nnz > 0)
-    k_col_count<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, colind, trowptr);
+    k_col_count<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, colind, n, trowptr);
   exclusive_scan(st, (int64_t)n + 1, trowptr, scanw);
   if (nnz == 0) return hipGetLastError();
   // radix passes; the last one writes (trow, tperm), earlier ones alternate
@@ -325,4 +333,88 @@ void launch_offset_i32(hipStream_t st, int64_t n, const int32_t* in, int32_t add
   k_offset_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, in, add, out);
 }
 
+// ---------------------------------------------------------------------------
+// Transpose without allocation: the sort's work arrays live in a file-scope
+// device array, `scratch`, of TRANSPOSE_SCRATCH_BYTES, which every GPU the
+// library runs on holds until the process ends.  Its device address is taken
+// once per device with hipGetSymbolAddress (the array's name in host code is
+// only a host-side stand-in) and kept per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t TRANSPOSE_SCRATCH_BYTES = (size_t)104 << 20;
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[TRANSPOSE_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 }  // namespace lsq2l
+
+extern "C" lsq2l_status lsq2l_transpose_noalloc(int32_t m, int32_t n, int32_t nnz,
+                                                const int32_t* rowptr, const int32_t* colind,
+                                                const double* vals, int32_t* trowptr,
+                                                int32_t* trow, double* tvals, int32_t* tperm,
+                                                void* hip_stream) {
+  using namespace lsq2l;
+  if (m < 0 || n < 0 || nnz < 0 || !rowptr || !trowptr || (nnz > 0 && (!colind || !trow)) ||
+      (nnz > 0 && tvals && !vals)) {
+    set_error("bad sizes or NULL required pointer");
+    return LSQ2L_EINVAL;
+  }
+  const size_t tb = transpose_temp_bytes(nnz, n);
+  const size_t perm_bytes = tperm ? 0 : ((size_t)nnz * sizeof(int32_t) + 255) / 256 * 256;
+  if (tb + perm_bytes + 256 > TRANSPOSE_SCRATCH_BYTES) {
+    set_error("transpose without allocation: n = " + std::to_string(n) + ", nnz = " +
+              std::to_string(nnz) + " need " + std::to_string(tb + perm_bytes + 256) +
+              " bytes of work space, above the " + std::to_string(TRANSPOSE_SCRATCH_BYTES) +
+              " bytes held per device");
+    return LSQ2L_EINVAL;
+  }
+  const hipStream_t st = (hipStream_t)hip_stream;
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) {
+    set_error(std::string("transpose without allocation: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    return LSQ2L_EHIP;
+  }
+  int32_t* perm = tperm ? tperm : (int32_t*)((char*)base + tb);
+  int32_t* flag = (int32_t*)((char*)base + tb + perm_bytes);
+  int32_t hflag = 0;
+  launch_check_cols(st, nnz, colind, n, flag);
+  e = hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && hflag == 0)
+    e = launch_transpose(st, m, n, nnz, rowptr, colind, vals, trowptr, trow, tvals, perm, base, tb);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_error(std::string("transpose without allocation: ") + hipGetErrorString(e));
+    return LSQ2L_EHIP;
+  }
+  if (hflag) {
+    set_error("transpose: a column index lies outside [0, n)");
+    return LSQ2L_EINVAL;
+  }
+  return LSQ2L_OK;
+}
+
