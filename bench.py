@@ -1,18 +1,24 @@
-"""Benchmark: time-to-solve of two-level Schwarz PCG on the grid-gradient workload.
+"""Benchmark: time-to-solve of the two-level Schwarz preconditioned normal
+equations on the batched banded workload (the largest single-GPU workload).
 
-One step = the whole hot path on one batch of synthetic input: setup
-(index sets, local matrices, batched Cholesky, coarse eigenproblems, coarse
-operator) plus the PCG solve to a 1e-8 relative normal-equation residual.
-Inputs (CSR of A, b) are resident in HBM before the timed region starts.
+One step = the whole hot path on one batch of synthetic input: setup (index
+sets, A^T, local matrices, batched Cholesky, coarse eigenproblems, coarse
+operator) plus the CG solve of every instance to a 1e-8 relative
+normal-equation residual, then destroy.  Inputs (CSR arrays of every
+instance, b) are resident in HBM before the timed region starts.
 
-Workload: forward-difference operator of a 1000 x 1000 grid (m = 2,998,000,
-n = 1,000,000, nnz = 4,996,000) split into 16 x 16 square-patch subdomains,
-overlap 1, tau = 0.1, seeded synthetic data.
+Workload (default): 64 independent least-squares instances, instance j with
+n_j = round(exp U(ln 5e3, ln 2e5)) columns, 2 n_j random rows of 4 entries
+near the diagonal plus n_j rows 0.1 e_j, N_j = round(exp U(ln 8, ln 128))
+contiguous parts, overlap 1, tau = 0.1, seeds 3000 + j; 2,990,087 columns,
+26.9M stored entries, 2,994 subdomains in total.
 
-Prints ONE JSON line.  ``value`` is the time-to-solve (ms) of the mixed
-precision path; the FP64 path, its ratio, SpMV bandwidth and the roofline of
-the dominant per-iteration kernel are reported beside it, with the CPU
-oracle (a bounded sample, extrapolated) as the reported CPU baseline.
+Prints ONE JSON line.  ``value`` is the FP64 time-to-solve (ms); the mixed
+precision path (FP32 local factors and solves), its ratio to FP64, the SpMV
+bandwidths, the roofline of the dominant per-iteration kernel (the batched
+local triangular solves) and, as context, the 1000 x 1000 grid and the
+irregular 1e6-column problem are reported beside it, with the CPU oracle (a
+bounded sample, extrapolated) as the reported CPU baseline.
 """
 from __future__ import annotations
 
@@ -31,76 +37,165 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 1 << 30          # plain device copy used to calibrate HBM counters
 
-# HBM traffic of one launch of the dominant kernel (k_local_solve_pipe<float>) on
-# this workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this
-# script, each scaled by the same counter's reading for the calibration copy
-# (profiles/local_solve_grid1000.md).  It describes the kernel source whose
-# SHA-256 is given; for any other source the figure is reported as null.
-TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip",
-           "sha256": "71a9de10107a6539ffc119224259af990ad5ad8f16865aa34aa3b5cb485036e9",
-           "bytes": 1931855776}
+# HBM traffic of one launch of the dominant kernel (the FP64 local solves,
+# k_local_solve_pipe<double>) on the default workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs of this script, each scaled by the same
+# counter's reading for the calibration copy (profiles/local_solve_banded_batch_64.md).
+# It describes the kernel source whose SHA-256 is given; for any other source
+# the figure is reported as null.
+TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip", "sha256": None, "bytes": None}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-VARIANT = 0   # preconditioner variant (0 additive, 2 balanced), from --variant
+def to_device(prob):
+    import torch
+    return {"rowptr": torch.as_tensor(prob.indptr.astype(np.int64)).cuda(),
+            "colind": torch.as_tensor(prob.indices).cuda(),
+            "vals": torch.as_tensor(prob.data).cuda(),
+            "b": torch.as_tensor(prob.b).cuda()}
 
 
-def run_step(L, dev, prob, precision):
-    """setup + solve + destroy; returns (ms, solve info, setup info)."""
+class Workload:
+    """A single problem or a batch, with its device arrays."""
+
+    def __init__(self, name, probs, describe):
+        import torch
+        self.name = name
+        self.probs = probs
+        self.describe = describe
+        self.dev = [to_device(p) for p in probs]
+        self.b = torch.cat([d["b"] for d in self.dev]) if len(probs) > 1 else self.dev[0]["b"]
+        self.n = sum(p.n for p in probs)
+        self.m = sum(p.m for p in probs)
+        self.nnz = sum(p.nnz for p in probs)
+        self.nparts = sum(p.nparts for p in probs)
+        self.x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+
+    def solver(self, L, **opts):
+        p0 = self.probs[0]
+        if len(self.probs) == 1:
+            d = self.dev[0]
+            return L.Solver(d["rowptr"], d["colind"], d["vals"], p0.part, p0.nparts, p0.m, p0.n,
+                            p0.tau, device="cuda:0", tol=p0.tol, **opts)
+        args = [(d["rowptr"], d["colind"], d["vals"], p.part, p.nparts, p.m, p.n)
+                for d, p in zip(self.dev, self.probs)]
+        return L.Solver.batched(args, p0.tau, device="cuda:0", tol=p0.tol, **opts)
+
+
+def run_step(L, wl, precision, variant):
+    """setup + solve + destroy; returns (ms, per-instance solve infos, setup info)."""
     import torch
     t0 = time.perf_counter()
-    s = L.Solver(dev["rowptr"], dev["colind"], dev["vals"], prob.part, prob.nparts, prob.m,
-                 prob.n, prob.tau, device="cuda:0", precision=precision, tol=prob.tol,
-                 variant=VARIANT, flexible=int(VARIANT == 2 and precision == 1))
-    x, info, _ = s.solve(dev["b"], x=dev["x"])
+    s = wl.solver(L, precision=precision, variant=variant,
+                  flexible=int(variant == L.BALANCED and precision == L.MIXED))
+    _, info, _ = s.solve(wl.b, x=wl.x)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     sinfo = s.info()
     s.close()
-    return ms, info[0], sinfo
+    return ms, info, sinfo
 
 
-def cpu_baseline(prob, iterations, budget_s=20.0):
-    """Time the oracle on a bounded sample of the same workload and
-    extrapolate: setup on k subdomains (scaled by N / k), plus ``iterations``
-    PCG iterations whose cost is the two SpMVs plus k local solves (scaled)."""
+def timed(L, wl, precision, variant, steps, warmup, tag):
+    import torch
+    for w in range(warmup):
+        ms, info, _ = run_step(L, wl, precision, variant)
+        log(f"[bench] {tag} warmup {w}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = []
+    for k in range(steps):
+        out.append(run_step(L, wl, precision, variant))
+        ms, info, _ = out[-1]
+        log(f"[bench] {tag} step {k}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}, "
+            f"relres {max(i['relres'] for i in info):.2e}")
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t0) * 1e3
+    ms, info, sinfo = out[-1]
+    return {"ms_per_step": total / steps,
+            "iterations_max": max(i["iterations"] for i in info),
+            "iterations_mean": float(np.mean([i["iterations"] for i in info])),
+            "relres_max": max(i["relres"] for i in info),
+            "setup_ms": float(np.mean([o[2]["t_total_ms"] for o in out])),
+            "solve_ms": float(np.mean([o[1][0]["solve_ms"] for o in out])),
+            "setup": sinfo}
+
+
+def kernel_times(L, wl, precision, reps=10):
+    s = wl.solver(L, precision=precision)
+    out = {}
+    for kid, kname in [(0, "spmv_A"), (1, "spmv_AT"), (2, "local_solve_stored"),
+                       (4, "local_solve_min"), (3, "coarse_solve")]:
+        try:
+            ms, by = s.time_kernel(kid, reps=reps)
+        except Exception as e:  # no coarse space
+            log(f"[bench] {kname}: {e}")
+            continue
+        out[kname] = {"ms": ms, "bytes": by, "GBs": by / ms / 1e6}
+        log(f"[bench] kernel {kname} ({precision}): {ms * 1e3:.1f} us, {by / 1e6:.1f} MB, "
+            f"{by / ms / 1e6:.0f} GB/s")
+    info = s.info()
+    s.close()
+    return out, info
+
+
+def cpu_baseline(wl, iterations, budget_s=20.0):
+    """The oracle on a bounded sample of the same workload, extrapolated:
+    per-subdomain setup (local matrices, Cholesky, Lemma 2.4 eigenproblem)
+    timed on seeded random subdomains with at most 3,000 local unknowns until
+    the budget is spent, fitted as c n_i^3 and summed over every subdomain;
+    index sets and one A^T A p of every instance in full; iterations x (two
+    SpMVs + the local solves, scaled the same way)."""
     import oracle as O
     import scipy.linalg as sla
-    A = prob.scipy()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    sets = O.index_sets(A, prob.part, prob.nparts)
+    sets = [O.index_sets(p.scipy(), p.part, p.nparts) for p in wl.probs]
     t_index = time.perf_counter() - t0
-    k = 0
-    t_sub = 0.0
-    t_apply = 0.0
-    r = np.random.default_rng(0).standard_normal(prob.n)
-    while k < prob.nparts and t_sub < budget_s:
-        s = sets[k]
+    allsub = [(k, i) for k, ss in enumerate(sets) for i in range(len(ss))]
+    ni = np.array([sets[k][i].ni for k, i in allsub], dtype=np.float64)
+    rng = np.random.default_rng(0)
+    cand = [j for j in rng.permutation(len(allsub)) if ni[j] <= 3000]
+    t_sub = t_app = 0.0
+    cube = square = 0.0
+    used = 0
+    for j in cand:
+        if t_sub >= budget_s:
+            break
+        k, i = allsub[j]
+        A = wl.probs[k].scipy()
+        s = sets[k][i]
+        r = rng.standard_normal(s.ni)
         t1 = time.perf_counter()
         Cii, Ctii = O.local_matrices(A, s)
         F = sla.cho_factor(Cii, lower=True)
-        O.coarse_vectors(Cii, Ctii, s.nI, prob.tau)
-        t_sub += time.perf_counter() - t1
+        O.coarse_vectors(Cii, Ctii, s.nI, wl.probs[k].tau)
         t2 = time.perf_counter()
-        sla.cho_solve(F, r[s.Omega])
-        t_apply += time.perf_counter() - t2
-        k += 1
-    t3 = time.perf_counter()
-    A.T @ (A @ r)
-    t_spmv = time.perf_counter() - t3
-    scale = prob.nparts / k
-    setup = t_index + t_sub * scale
-    per_it = t_spmv + t_apply * scale
+        sla.cho_solve(F, r)
+        t3 = time.perf_counter()
+        t_sub += t2 - t1
+        t_app += t3 - t2
+        cube += ni[j] ** 3
+        square += ni[j] ** 2
+        used += 1
+    t4 = time.perf_counter()
+    for p in wl.probs:
+        A = p.scipy()
+        A.T @ (A @ np.ones(p.n))
+    t_spmv = time.perf_counter() - t4
+    setup = t_index + t_sub / cube * float(np.sum(ni ** 3))
+    per_it = t_spmv + t_app / square * float(np.sum(ni ** 2))
     total_ms = (setup + iterations * per_it) * 1e3
     return {"value": round(total_ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle setup (local matrices, Cholesky, Lemma 2.4 eigenproblems) on "
-                       f"{k} of {prob.nparts} subdomains and {k} local solves, scaled by "
-                       f"{scale:.1f}; index sets and one A^T A p in full; {iterations} "
-                       f"iterations (the GPU count); extrapolated")}
+            "sample": (f"oracle setup (local matrices, Cholesky, Lemma 2.4 eigenproblem) and a "
+                       f"local solve timed on {used} of {len(allsub)} subdomains (seeded random, "
+                       f"n_i <= 3000), fitted as c n_i^3 (setup) and c n_i^2 (solve) and summed "
+                       f"over all subdomains; index sets and one A^T A p of every instance in "
+                       f"full; {iterations} iterations (the GPU count); extrapolated")}
 
 
 def measured_traffic():
@@ -123,132 +218,129 @@ def calibration_copy():
     del src, dst
 
 
+def make_workload(name):
+    from workloads import generators as W
+    if name == "banded_batch_64":
+        probs = W.banded_batch_64()
+        return Workload(name, probs, "banded_batch_64: 64 instances, n_j log-uniform in [5e3, 2e5], "
+                        "2 n_j rows of 4 entries near the diagonal + n_j rows 0.1 e_j, "
+                        "8-128 contiguous parts each, tau 0.1")
+    if name == "grid_1000":
+        return Workload(name, [W.grid_1000()], "grid_1000: forward differences on a 1000 x 1000 "
+                        "grid + 1e6 rows 1e-3 e_j, 16 x 16 patches, tau 0.1")
+    if name == "irregular_1m":
+        return Workload(name, [W.strip_rng(W.irregular_1m())],
+                        "irregular_1m: 3e6 clustered random rows, columns scaled 10^U(-3,3), "
+                        "+ 1e6 rows 1e-4 e_j; 512 BFS parts, tau 0.05")
+    raise ValueError(name)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=1000)
-    ap.add_argument("--patches", type=int, default=16)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["grid_gradient", "irregular_1m"], default="grid_gradient",
-                    help="grid_gradient (the default bench line) or the irregular 1e6-column problem")
+    ap.add_argument("--workload", choices=["banded_batch_64", "grid_1000", "irregular_1m"],
+                    default="banded_batch_64")
     ap.add_argument("--variant", choices=["additive", "balanced"], default="additive",
                     help="second-level form (eq. two_level_schwarz or eq. balanced)")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the other workloads reported as context")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
-    global VARIANT
-    VARIANT = 2 if args.variant == "balanced" else 0
-    # the counter-based traffic figure was taken on the default grid workload
-    default_workload = (args.workload == "grid_gradient" and args.grid == 1000 and args.patches == 16)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
     import paper_2107_09006_amd as L
-    from workloads import generators as W
 
-    if args.workload == "irregular_1m":
-        log("[bench] generating the irregular workload (3e6 + 1e6 rows, 1e6 columns, 512 BFS parts)")
-        prob = W.strip_rng(W.irregular_1m())
-        workload = ("irregular_1m: 3e6 clustered random rows, columns scaled 10^U(-3,3), "
-                    "+ 1e6 rows 1e-4 I; 512 BFS parts")
-    else:
-        log(f"[bench] generating grid {args.grid} x {args.grid}, {args.patches}^2 patches")
-        prob = W.strip_rng(W.grid_gradient(args.grid, args.patches, seed=1, tau=0.1, tol=1e-8,
-                                           name="grid_gradient"))
-        workload = f"grid_gradient {args.grid}x{args.grid}, {args.patches}x{args.patches} patches"
-    dev = {
-        "rowptr": torch.as_tensor(prob.indptr.astype(np.int64)).cuda(),
-        "colind": torch.as_tensor(prob.indices).cuda(),
-        "vals": torch.as_tensor(prob.data).cuda(),
-        "b": torch.as_tensor(prob.b).cuda(),
-        "x": torch.empty(prob.n, dtype=torch.float64, device="cuda"),
-    }
-    torch.cuda.synchronize()
+    variant = L.BALANCED if args.variant == "balanced" else L.ADDITIVE
+    log(f"[bench] generating {args.workload}")
+    wl = make_workload(args.workload)
     calibration_copy()
-    results = {}
-    for prec, name in [(L.FP64, "fp64"), (L.MIXED, "mixed")]:
-        for w in range(args.warmup):
-            ms, info, sinfo = run_step(L, dev, prob, prec)
-            log(f"[bench] warmup {name} {w}: {ms:.1f} ms, its {info['iterations']}, relres {info['relres']:.2e}")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        steps = []
-        for k in range(args.steps):
-            steps.append(run_step(L, dev, prob, prec))
-            log(f"[bench] step {name} {k}: {steps[-1][0]:.1f} ms, its {steps[-1][1]['iterations']}, "
-                f"relres {steps[-1][1]['relres']:.2e}")
-        torch.cuda.synchronize()
-        total = (time.perf_counter() - t0) * 1e3
-        results[name] = {"ms_per_step": total / args.steps, "info": steps[-1][1], "setup": steps[-1][2],
-                         "solve_ms": float(np.mean([s[1]["solve_ms"] for s in steps])),
-                         "setup_ms": float(np.mean([s[2]["t_total_ms"] for s in steps]))}
+    fp64 = timed(L, wl, L.FP64, variant, args.steps, args.warmup, "fp64")
+    mixed = timed(L, wl, L.MIXED, variant, args.steps, args.warmup, "mixed")
+    kern64, info64 = kernel_times(L, wl, L.FP64)
+    kern32, _ = kernel_times(L, wl, L.MIXED)
 
-    # kernel timings on a live handle of each precision
-    kern = {}
-    for prec, name in [(L.FP64, "fp64"), (L.MIXED, "mixed")]:
-        s = L.Solver(dev["rowptr"], dev["colind"], dev["vals"], prob.part, prob.nparts, prob.m,
-                     prob.n, prob.tau, precision=prec, tol=prob.tol)
-        for kid, kname in [(0, "spmv_A"), (1, "spmv_AT"), (2, "local_solve"), (3, "coarse_solve")]:
-            try:
-                ms, by = s.time_kernel(kid, reps=20)
-            except Exception as e:  # no coarse space
-                log(f"[bench] {kname}: {e}")
-                continue
-            kern[f"{kname}_{name}"] = {"ms": ms, "bytes": by, "GBs": by / ms / 1e6}
-            log(f"[bench] kernel {kname} ({name}): {ms * 1e3:.1f} us, {by / 1e6:.1f} MB, {by / ms / 1e6:.0f} GB/s")
-        s.close()
-
-    mixed, fp64 = results["mixed"], results["fp64"]
-    its = mixed["info"]["iterations"]
-    # dominant per-iteration kernel: the batched local triangular solves
-    dom = kern.get("local_solve_mixed")
+    # dominant per-iteration kernel of the FP64 path: the batched local
+    # triangular solves; achieved = algorithmic bytes (nnz(L_i) under a
+    # fill-reducing order, Omega_Gamma_i last, both sweeps, y in and out) per
+    # launch / the launch's duration; the fraction for the stored tile
+    # envelope is reported beside it
+    dom = kern64.get("local_solve_min")
+    stored = kern64.get("local_solve_stored")
     roofline = None
     if dom:
-        roofline = {"kernel": "k_local_solve_pipe<float>", "bound": "hbm",
+        roofline = {"kernel": "k_local_solve_pipe<double>", "bound": "hbm",
                     "achieved": round(dom["GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(dom["GBs"] / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic() if default_workload else None,
-                    "bytes_per_launch": dom["bytes"], "launch_ms": dom["ms"]}
-    spmv = kern.get("spmv_A_fp64")
-    spmvt = kern.get("spmv_AT_fp64")
+                    "traffic": measured_traffic() if args.workload == "banded_batch_64" else None,
+                    "bytes_per_launch": dom["bytes"], "launch_ms": dom["ms"],
+                    "stored_bytes_per_launch": stored["bytes"] if stored else None,
+                    "frac_stored": round(stored["GBs"] / HBM_PEAK_GBS, 4) if stored else None,
+                    "factor_nnz_min": info64["factor_nnz_min"],
+                    "factor_stored_entries": info64["factor_tiles"] * 1024}
     out = {
         "metric": "time-to-solve @1e-8 rel normal-eq residual; SpMV GB/s; mixed vs FP64 speedup",
-        "value": round(mixed["ms_per_step"], 2),
+        "value": round(fp64["ms_per_step"], 2),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(mixed["ms_per_step"], 2),
+        "ms_per_step": round(fp64["ms_per_step"], 2),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload,
-                   "m": prob.m, "n": prob.n, "nnz": prob.nnz, "nparts": prob.nparts,
-                   "tau": prob.tau, "tol": prob.tol, "overlap": 1, "variant": args.variant},
-        "iterations": its,
-        "relres": mixed["info"]["relres"],
-        "setup_ms": round(mixed["setup_ms"], 2),
-        "solve_ms": round(mixed["solve_ms"], 2),
-        "fp64_ms_per_step": round(fp64["ms_per_step"], 2),
-        "fp64_iterations": fp64["info"]["iterations"],
-        "fp64_relres": fp64["info"]["relres"],
-        "mixed_vs_fp64_speedup": round(fp64["ms_per_step"] / mixed["ms_per_step"], 3),
-        "n0": mixed["setup"]["n0"],
-        "setup_phases_ms": {k: round(mixed["setup"][k], 2) for k in
+        "config": {"workload": wl.describe, "instances": len(wl.probs), "m": wl.m, "n": wl.n,
+                   "nnz": wl.nnz, "nparts": wl.nparts, "tau": wl.probs[0].tau,
+                   "tol": wl.probs[0].tol, "overlap": 1, "variant": args.variant,
+                   "krylov": "pcg"},
+        "iterations_max": fp64["iterations_max"],
+        "iterations_mean": round(fp64["iterations_mean"], 2),
+        "relres_max": fp64["relres_max"],
+        "setup_ms": round(fp64["setup_ms"], 2),
+        "solve_ms": round(fp64["solve_ms"], 2),
+        "setup_phases_ms": {k: round(fp64["setup"][k], 2) for k in
                             ["t_plan_ms", "t_assemble_ms", "t_factor_ms", "t_eigen_ms", "t_coarse_ms"]},
-        "spmv_GBs": {"A": round(spmv["GBs"], 1) if spmv else None,
-                     "AT": round(spmvt["GBs"], 1) if spmvt else None},
-        "kernels": {k: {"us": round(v["ms"] * 1e3, 2), "MB": round(v["bytes"] / 1e6, 2),
-                        "GBs": round(v["GBs"], 1)} for k, v in kern.items()},
+        "n0": fp64["setup"]["n0"],
+        "mixed_ms_per_step": round(mixed["ms_per_step"], 2),
+        "mixed_iterations_max": mixed["iterations_max"],
+        "mixed_relres_max": mixed["relres_max"],
+        "mixed_vs_fp64_speedup": round(fp64["ms_per_step"] / mixed["ms_per_step"], 3),
+        "spmv_GBs": {"A": round(kern64["spmv_A"]["GBs"], 1), "AT": round(kern64["spmv_AT"]["GBs"], 1)},
+        "kernels": {f"{k}_{tag}": {"us": round(v["ms"] * 1e3, 2), "MB": round(v["bytes"] / 1e6, 2),
+                                   "GBs": round(v["GBs"], 1)}
+                    for tag, kd in (("fp64", kern64), ("mixed", kern32)) for k, v in kd.items()},
         "roofline": roofline,
     }
+    if not args.no_context:
+        ctx = {}
+        for name in ("grid_1000", "irregular_1m"):
+            if name == args.workload:
+                continue
+            log(f"[bench] context workload {name}")
+            w2 = make_workload(name)
+            f2 = timed(L, w2, L.FP64, variant, 1, 1, f"{name} fp64")
+            m2 = timed(L, w2, L.MIXED, variant, 1, 1, f"{name} mixed")
+            k2, _ = kernel_times(L, w2, L.FP64)
+            ctx[name] = {"fp64_ms": round(f2["ms_per_step"], 2), "mixed_ms": round(m2["ms_per_step"], 2),
+                         "mixed_vs_fp64_speedup": round(f2["ms_per_step"] / m2["ms_per_step"], 3),
+                         "iterations": f2["iterations_max"], "relres": f2["relres_max"],
+                         "setup_ms": round(f2["setup_ms"], 2), "solve_ms": round(f2["solve_ms"], 2),
+                         "spmv_GBs": {"A": round(k2["spmv_A"]["GBs"], 1),
+                                      "AT": round(k2["spmv_AT"]["GBs"], 1)},
+                         "local_solve_min_GBs": round(k2["local_solve_min"]["GBs"], 1)
+                         if "local_solve_min" in k2 else None}
+            del w2
+            torch.cuda.empty_cache()
+        out["context_workloads"] = ctx
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(prob, its)
+        out["cpu_baseline"] = cpu_baseline(wl, fp64["iterations_max"])
     print(json.dumps(out), flush=True)
 
 

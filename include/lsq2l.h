@@ -154,6 +154,8 @@ typedef struct {
   double  t_total_ms;     /* wall time of setup                                          */
   int32_t spmv_lanes_A;   /* lanes per row used by the SpMV with A (autotuned or built-in) */
   int32_t spmv_lanes_AT;  /* the same for A^T                                            */
+  double  t_prepare_ms;   /* reading, concatenating and validating the input (before
+                             t_total_ms starts)                                         */
 } lsq2l_setup_info;
 
 /* One least-squares instance for lsq2l_setup_batched. */

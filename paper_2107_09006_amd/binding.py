@@ -59,7 +59,8 @@ class SetupInfo(C.Structure):
                 ("t_plan_ms", C.c_double), ("t_assemble_ms", C.c_double),
                 ("t_factor_ms", C.c_double), ("t_eigen_ms", C.c_double),
                 ("t_coarse_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("spmv_lanes_A", C.c_int32), ("spmv_lanes_AT", C.c_int32)]
+                ("spmv_lanes_A", C.c_int32), ("spmv_lanes_AT", C.c_int32),
+                ("t_prepare_ms", C.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -643,6 +643,24 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->upload(&c->P.tileF, H.tileF));
   TRY(c->upload(&c->P.tileOff, H.tileOff));
   for (const SubDesc& d : H.subs) c->P.max_np = std::max(c->P.max_np, (int)d.np);
+  {
+    // the local solves start the subdomains with the longest tile streams
+    // first: one launch holds all of them, and the largest set its length
+    std::vector<int32_t> order(nparts);
+    std::vector<int64_t> tiles(nparts);
+    for (int i = 0; i < nparts; ++i) {
+      order[i] = i;
+      const int64_t f0 = H.subs[i].fac_off / TT;
+      const int64_t f1 = i + 1 < nparts ? H.subs[i + 1].fac_off / TT : H.total_fac / TT;
+      tiles[i] = f1 - f0;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x] > tiles[y]; });
+    TRY(c->upload(&c->P.solve_order, order));
+    static std::once_flag once;
+    static hipError_t conf = hipSuccess;
+    std::call_once(once, []() { conf = local_solve_configure(); });
+    LSQ2L_HIP_TRY(conf);
+  }
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_plan_ms = ms_since(t0);
   // --- local matrices
@@ -1009,18 +1027,26 @@ bool is_device_ptr(const void* p) {
   return at.type == hipMemoryTypeDevice;
 }
 
-// Row extents, column ranges and column order of one instance, with int64
-// row pointers rp (m + 1) and the instance's columns ci already shifted by
-// col0 (valid range [col0, col0 + n)).  Rows are checked in parallel blocks,
-// first every row's extent (so that the column pass reads inside ci), then
-// the columns; the first failing row of the first failing pass is reported.
-lsq2l_status validate_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, int64_t nnz,
-                          int64_t col0) {
-  if (rp[0] != 0) { set_error("rowptr[0] must be 0"); return LSQ2L_EINVAL; }
-  if (rp[m] != nnz) { set_error("rowptr[m] != nnz"); return LSQ2L_EINVAL; }
-  const unsigned nth = m < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+// Validation of all instances at once, on host threads over ranges of the
+// concatenated rows: row extents (int64 row pointers rp64 of instance k at
+// rp64 + r0_k + k, m_k + 1 each) first, so that the column pass reads inside
+// ci, then the columns (already shifted by the instance's first column, so
+// valid in [col0_k, col0_k + n_k)) in strictly increasing order per row.
+// The int32 row pointers of the concatenation are written on the way.  The
+// first failing row of the first failing pass is reported.
+lsq2l_status validate_all(int count, const lsq2l_problem* probs, const std::vector<int64_t>& r0,
+                          const std::vector<int64_t>& c0, const std::vector<int64_t>& e0,
+                          const int64_t* rp64, const int32_t* ci, int32_t* rp32) {
+  const int64_t M = r0[count];
+  for (int k = 0; k < count; ++k) {
+    const int64_t* lrp = rp64 + r0[k] + k;
+    const std::string who = count > 1 ? "problem " + std::to_string(k) + ": " : std::string();
+    if (lrp[0] != 0) { set_error(who + "rowptr[0] must be 0"); return LSQ2L_EINVAL; }
+    if (lrp[probs[k].m] != probs[k].nnz) { set_error(who + "rowptr[m] != nnz"); return LSQ2L_EINVAL; }
+  }
+  const unsigned nth = M < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<int64_t> bad_row(nth, INT64_MAX);
-  std::vector<int> bad_kind(nth, 0);
+  std::vector<int> bad_kind(nth, 0), bad_inst(nth, 0);
   auto run = [&](auto&& fn) {
     if (nth == 1) {
       fn(0u);
@@ -1030,36 +1056,51 @@ lsq2l_status validate_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t
       for (auto& th : pool) th.join();
     }
   };
-  auto rows_of = [&](unsigned t, int64_t& r0, int64_t& r1) {
-    r0 = m * t / nth;
-    r1 = m * (t + 1) / nth;
+  // visit(t, fn): rows [M t / nth, M (t + 1) / nth) as (instance, local row)
+  auto visit = [&](unsigned t, auto&& fn) {
+    const int64_t g0 = M * t / nth, g1 = M * (t + 1) / nth;
+    int k = (int)(std::upper_bound(r0.begin(), r0.end(), g0) - r0.begin()) - 1;
+    for (int64_t g = g0; g < g1; ++g) {
+      while (g >= r0[k + 1]) ++k;
+      if (!fn(k, g - r0[k], g)) return;
+    }
   };
   run([&](unsigned t) {
-    int64_t r0, r1;
-    rows_of(t, r0, r1);
-    for (int64_t r = r0; r < r1; ++r)
-      if (rp[r + 1] < rp[r] || rp[r + 1] > nnz) { bad_row[t] = r; bad_kind[t] = 1; return; }
+    visit(t, [&](int k, int64_t r, int64_t g) {
+      const int64_t* lrp = rp64 + r0[k] + k;
+      if (lrp[r + 1] < lrp[r] || lrp[r + 1] > probs[k].nnz) {
+        bad_row[t] = r; bad_kind[t] = 1; bad_inst[t] = k;
+        return false;
+      }
+      rp32[g + 1] = (int32_t)(e0[k] + lrp[r + 1]);
+      return true;
+    });
   });
   bool extents_ok = true;
   for (unsigned t = 0; t < nth; ++t) extents_ok = extents_ok && !bad_kind[t];
   if (extents_ok)
     run([&](unsigned t) {
-      int64_t r0, r1;
-      rows_of(t, r0, r1);
-      for (int64_t r = r0; r < r1; ++r)
-        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      visit(t, [&](int k, int64_t r, int64_t) {
+        const int64_t* lrp = rp64 + r0[k] + k;
+        const int32_t* lci = ci + e0[k];
+        const int64_t lo = c0[k], hi = c0[k] + probs[k].n;
+        for (int64_t e = lrp[r]; e < lrp[r + 1]; ++e) {
           int kind = 0;
-          if (ci[e] < col0 || ci[e] >= col0 + n) kind = 2;
-          else if (e > rp[r] && ci[e] <= ci[e - 1]) kind = 3;
-          if (kind) { bad_row[t] = r; bad_kind[t] = kind; return; }
+          if (lci[e] < lo || lci[e] >= hi) kind = 2;
+          else if (e > lrp[r] && lci[e] <= lci[e - 1]) kind = 3;
+          if (kind) { bad_row[t] = r; bad_kind[t] = kind; bad_inst[t] = k; return false; }
         }
+        return true;
+      });
     });
+  rp32[0] = 0;
   for (unsigned t = 0; t < nth; ++t) {
     if (!bad_kind[t]) continue;
+    const std::string who = count > 1 ? "problem " + std::to_string(bad_inst[t]) + ": " : std::string();
     const std::string r = std::to_string(bad_row[t]);
-    if (bad_kind[t] == 1) set_error("rowptr is not monotone (or exceeds nnz) at row " + r);
-    else if (bad_kind[t] == 2) set_error("column index out of range in row " + r);
-    else set_error("columns not strictly increasing in row " + r);
+    if (bad_kind[t] == 1) set_error(who + "rowptr is not monotone (or exceeds nnz) at row " + r);
+    else if (bad_kind[t] == 2) set_error(who + "column index out of range in row " + r);
+    else set_error(who + "columns not strictly increasing in row " + r);
     return LSQ2L_EINVAL;
   }
   return LSQ2L_OK;
@@ -1067,8 +1108,9 @@ lsq2l_status validate_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t
 
 // Setup of one or several instances: their CSR arrays are concatenated on
 // the device (row pointers narrowed to int32 and shifted, columns shifted),
-// the patterns read back once into pinned memory and validated per instance.
+// the patterns read back once into pinned memory and validated on the host.
 lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs) {
+  auto t_prep = clk::now();
   const hipStream_t st = c->st;
   int64_t M = 0, N = 0, NNZ = 0, NP = 0;
   for (int k = 0; k < count; ++k) {
@@ -1096,16 +1138,23 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   PinnedArray<int32_t> ci;
   TRY(rp64.alloc(M + count));
   TRY(ci.alloc(NNZ));
-  int64_t r0 = 0, c0 = 0, e0 = 0;
+  std::vector<int64_t> r0(count + 1, 0), c0(count + 1, 0), e0(count + 1, 0), p0(count + 1, 0);
+  for (int k = 0; k < count; ++k) {
+    r0[k + 1] = r0[k] + probs[k].m;
+    c0[k + 1] = c0[k] + probs[k].n;
+    e0[k + 1] = e0[k] + probs[k].nnz;
+    p0[k + 1] = p0[k] + probs[k].nparts;
+  }
   for (int k = 0; k < count; ++k) {
     const lsq2l_problem& pr = probs[k];
-    launch_narrow_i64(st, pr.m + 1, pr.rowptr, 0, (int32_t)e0, c->M.rowptr + r0);
-    launch_offset_i32(st, pr.nnz, pr.colind, (int32_t)c0, c->M.colind + e0);
-    if (pr.nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(c->M.vals + e0, pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(rp64.p + r0 + k, pr.rowptr, (pr.m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    r0 += pr.m; c0 += pr.n; e0 += pr.nnz;
-    c->seg_row_h[k + 1] = r0;
-    c->seg_col_h[k + 1] = c0;
+    launch_narrow_i64(st, pr.m + 1, pr.rowptr, 0, (int32_t)e0[k], c->M.rowptr + r0[k]);
+    launch_offset_i32(st, pr.nnz, pr.colind, (int32_t)c0[k], c->M.colind + e0[k]);
+    if (pr.nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(c->M.vals + e0[k], pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LSQ2L_HIP_TRY(hipMemcpyAsync(rp64.p + r0[k] + k, pr.rowptr, (pr.m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
+  for (int k = 0; k <= count; ++k) {
+    c->seg_row_h[k] = r0[k];
+    c->seg_col_h[k] = c0[k];
   }
   if (NNZ) LSQ2L_HIP_TRY(hipMemcpyAsync(ci.p, c->M.colind, NNZ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   // partitions: host arrays are read in place, device arrays copied back
@@ -1119,17 +1168,9 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   const hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return LSQ2L_EHIP; }
   std::vector<int32_t> rp(M + 1);
-  r0 = 0; c0 = 0; e0 = 0;
-  int64_t p0 = 0;
+  TRY(validate_all(count, probs, r0, c0, e0, rp64.p, ci.p, rp.data()));
   for (int k = 0; k < count; ++k) {
     const lsq2l_problem& pr = probs[k];
-    const int64_t* lrp = rp64.p + r0 + k;
-    const lsq2l_status s = validate_csr(pr.m, pr.n, lrp, ci.p + e0, pr.nnz, c0);
-    if (s != LSQ2L_OK) {
-      if (count > 1) set_error("problem " + std::to_string(k) + ": " + g_err);
-      return s;
-    }
-    for (int64_t r = 0; r <= pr.m; ++r) rp[r0 + r] = (int32_t)(e0 + lrp[r]);
     const int32_t* part = pdev[k].empty() ? probs[k].part : pdev[k].data();
     for (int64_t j = 0; j < pr.n; ++j) {
       if (part[j] < 0 || part[j] >= pr.nparts) {
@@ -1137,11 +1178,11 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
                              : "part out of range in problem " + std::to_string(k));
         return LSQ2L_EINVAL;
       }
-      pt[c0 + j] = (int32_t)(p0 + part[j]);
+      pt[c0[k] + j] = (int32_t)(p0[k] + part[j]);
     }
-    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0 + q] = k;
-    r0 += pr.m; c0 += pr.n; e0 += pr.nnz; p0 += pr.nparts;
+    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0[k] + q] = k;
   }
+  c->info.t_prepare_ms = ms_since(t_prep);
   return setup_core(c, rp.data(), ci.p, pt, (int32_t)NP, seg_of_part);
 }
 

@@ -176,8 +176,8 @@ __device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_
 }
 
 // ---------------------------------------------------------------------------
-// Streaming variant for subdomains with np <= PCAP.  The tiles a sweep reads
-// form one stream: forward, row by row, the off-diagonal tiles (I, F(I)) ..
+// Streaming variant, in two size bins.  The tiles a sweep reads form one
+// stream: forward, row by row, the off-diagonal tiles (I, F(I)) ..
 // (I, I - 1) followed by the diagonal inverse of row I; the backward sweep
 // reads the same stream in reverse.  Since tile rows are stored one after
 // the other (F(I) .. I each), stream position t is factor tile t of the
@@ -197,17 +197,23 @@ __device__ void local_solve_lds(const SubDesc& d, const int32_t* F, const int64_
 // number of block barriers.  The consumer computes in the factor's own type:
 // with the FP32 factor, the sweeps, their partial sums and the local vector
 // held in LDS are FP32 (the result is widened to FP64 on the way out).
+//
+// Both bins run in one launch, workgroups in decreasing order of stream
+// length (the largest subdomains start first).  y lives in LDS: up to
+// PCAP_S local unknowns with a ring of PB tiles per block, up to PCAP_B with
+// a ring of PB_BIG tiles, in the same dynamic LDS allocation.
 // ---------------------------------------------------------------------------
-constexpr int PCAP = 4608;
+constexpr int PCAP = 4608;            // small bin
+constexpr int PCAP_B = 12544;         // large bin
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T> struct PipeCfg;
 template <> struct PipeCfg<float> {
-  static constexpr int PB = 12, PD = 2;
+  static constexpr int PB = 12, PB_BIG = 9, PD = 2;
   using V = f32x4;
 };
 template <> struct PipeCfg<double> {
-  static constexpr int PB = 7, PD = 2;
+  static constexpr int PB = 7, PB_BIG = 3, PD = 2;
   using V = f64x2;
 };
 template <int V> using IC = std::integral_constant<int, V>;
@@ -233,27 +239,50 @@ __device__ inline void lds_row16(R (&x)[16], const T* p) {
   }
 }
 
+// LDS layout of one bin: y (YC entries), the ring (2 PB tiles of TL
+// entries), the envelope starts sF and stream offsets sS of the tile rows,
+// and a 32-entry row buffer
+template <typename T, int PB, int YC>
+struct PipeLds {
+  static constexpr int EV = sizeof(typename PipeCfg<T>::V) / sizeof(T);
+  static constexpr int TL = TS * (TS + EV);
+  static constexpr size_t ys = 0;
+  static constexpr size_t ring = ys + (size_t)YC * sizeof(T);
+  static constexpr size_t sF = ring + (size_t)2 * PB * TL * sizeof(T);
+  static constexpr size_t sS = sF + (size_t)(YC / TS) * sizeof(int32_t);
+  static constexpr size_t sv = (sS + (size_t)(YC / TS + 1) * sizeof(int32_t) + 15) / 16 * 16;
+  static constexpr size_t bytes = sv + TS * sizeof(T);
+};
+
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
-                   const T* __restrict__ fac, const T* __restrict__ dinv,
-                   double* __restrict__ loc) {
+constexpr size_t pipe_lds_bytes() {
+  constexpr size_t a = PipeLds<T, PipeCfg<T>::PB, PCAP>::bytes;
+  constexpr size_t b = PipeLds<T, PipeCfg<T>::PB_BIG, PCAP_B>::bytes;
+  return a > b ? a : b;
+}
+static_assert(pipe_lds_bytes<float>() <= 160 * 1024, "LDS of the FP32 local solve");
+static_assert(pipe_lds_bytes<double>() <= 160 * 1024, "LDS of the FP64 local solve");
+
+template <typename T, int PB, int YC>
+__device__ __forceinline__ void local_solve_pipe_body(const SubDesc& d, const int32_t* __restrict__ tileF,
+                                                      const T* __restrict__ fac,
+                                                      const T* __restrict__ dinv,
+                                                      double* __restrict__ loc, unsigned char* smem) {
   using V = typename PipeCfg<T>::V;
   using GV = __attribute__((address_space(1))) V;   // global memory: loads count against vmcnt only
-  constexpr int PB = PipeCfg<T>::PB;
+  using LY = PipeLds<T, PB, YC>;
   constexpr int PD = PipeCfg<T>::PD;
-  constexpr int EV = sizeof(V) / sizeof(T);          // entries per vector
+  constexpr int EV = LY::EV;                         // entries per vector
   constexpr int NC = TT / EV / 64;                   // vectors per lane and tile
   constexpr int PLD = TS + EV;                       // LDS leading dimension of a tile
-  constexpr int TL = TS * PLD;
+  constexpr int TL = LY::TL;
   constexpr int PW = (PB + 2) / 3;                   // tiles per producer wave and block
   constexpr int CB = 4;                              // consumer batch of off-diagonal tiles
-  __shared__ __align__(16) T ys[PCAP];
-  __shared__ __align__(16) T ring[2][PB][TL];
-  __shared__ int32_t sF[PCAP / TS], sS[PCAP / TS + 1];
-  __shared__ T sv[TS];
-  const SubDesc d = subs[blockIdx.x];
-  if (d.np > PCAP) return;
+  T* ys = reinterpret_cast<T*>(smem + LY::ys);
+  T* ring = reinterpret_cast<T*>(smem + LY::ring);
+  int32_t* sF = reinterpret_cast<int32_t*>(smem + LY::sF);
+  int32_t* sS = reinterpret_cast<int32_t*>(smem + LY::sS);
+  T* sv = reinterpret_cast<T*>(smem + LY::sv);
   const int32_t* F = tileF + d.tile_base;
   const T* A = fac + d.fac_off;
   const T* Di = dinv + d.dinv_off;
@@ -261,7 +290,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int a = lane % 32, h = lane / 32;
   const int nt = d.ntiles;
-  for (int q = tid; q < d.np; q += blockDim.x) ys[q] = yg[q];
+  for (int q = tid; q < d.np; q += blockDim.x) ys[q] = (T)yg[q];
   for (int q = tid; q < nt; q += blockDim.x) sF[q] = F[q];
   __syncthreads();
   if (tid == 0) {
@@ -313,15 +342,15 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
       }
     }
   };
-  // commit<r>(buf): register slot r into ring[buf]; vector c of lane l holds
-  // the EV entries from flat (column-major) index EV (l + 64 c)
+  // commit<r>(buf): register slot r into ring block buf; vector c of lane l
+  // holds the EV entries from flat (column-major) index EV (l + 64 c)
   auto commit = [&](int buf, bool rev, auto slot) {
     constexpr int r = decltype(slot)::value;
     const int pw = w - 1;
 #pragma unroll
     for (int q = 0; q < PW; ++q)
       if (have[r][q]) {
-        T* tile = ring[buf][pw + 3 * q];
+        T* tile = ring + (size_t)(buf * PB + pw + 3 * q) * TL;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const int f0 = EV * (lane + 64 * c), col = f0 / TS, row = f0 % TS;
@@ -374,7 +403,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
     int I = 0, k = 0, fI = nt > 0 ? sF[0] : 0, nk = 0;
     T acc[4] = {0, 0, 0, 0};
     for (int b = 0; b < nblk; ++b) {
-      const T (*rb)[TL] = ring[b & 1];
+      const T* rb = ring + (size_t)(b & 1) * PB * TL;
       const int send = min(N - b * PB, PB);
       int s = 0;
       while (s < send && I < nt) {
@@ -386,7 +415,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
           T l[nb][16], y[nb][16];
 #pragma unroll
           for (int i = 0; i < nb; ++i) {
-            lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
+            lds_row16(l[i], rb + (size_t)(s + u0 + i) * TL + a * PLD + 16 * h);
             lds_row16(y[i], yk + (u0 + i) * TS);
           }
 #pragma unroll
@@ -401,7 +430,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
         k += run;
         if (s < send) {                              // the diagonal inverse of row I
           T l[16];
-          lds_row16(l, rb[s] + a * PLD + 16 * h);
+          lds_row16(l, rb + (size_t)s * TL + a * PLD + 16 * h);
           T r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
           r = half_pair_sum(r);
           if (lane < TS) sv[lane] = ys[I * TS + lane] - r;
@@ -437,13 +466,13 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
     int nk = nt > 0 ? I - fI : 0, k = nk;
     T xr[16];
     for (int b = 0; b < nblk; ++b) {
-      const T (*rb)[TL] = ring[b & 1];
+      const T* rb = ring + (size_t)(b & 1) * PB * TL;
       const int send = min(N - b * PB, PB);
       int s = 0;
       while (s < send) {
         if (k == nk) {
           T l[16];
-          lds_row16(l, rb[s] + a * PLD + 16 * h);
+          lds_row16(l, rb + (size_t)s * TL + a * PLD + 16 * h);
           T v[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int j = 0; j < 16; ++j) v[j & 3] += l[j] * ys[I * TS + 16 * h + j];
@@ -462,7 +491,7 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
             constexpr int nb = decltype(nbc)::value;
             T l[nb][16], x[nb];
 #pragma unroll
-            for (int i = 0; i < nb; ++i) lds_row16(l[i], rb[s + u0 + i] + a * PLD + 16 * h);
+            for (int i = 0; i < nb; ++i) lds_row16(l[i], rb + (size_t)(s + u0 + i) * TL + a * PLD + 16 * h);
 #pragma unroll
             for (int i = 0; i < nb; ++i) {
               T v[4] = {0, 0, 0, 0};
@@ -497,6 +526,21 @@ k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__
   for (int q = tid; q < d.np; q += blockDim.x) yg[q] = ys[q];
 }
 
+// Workgroup b solves subdomain order[b] (decreasing stream length) in the
+// bin its size selects; subdomains above PCAP_B are left to k_local_solve.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_local_solve_pipe(const SubDesc* __restrict__ subs, const int32_t* __restrict__ order,
+                   const int32_t* __restrict__ tileF, const T* __restrict__ fac,
+                   const T* __restrict__ dinv, double* __restrict__ loc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = subs[order[blockIdx.x]];
+  if (d.np <= PCAP)
+    local_solve_pipe_body<T, PipeCfg<T>::PB, PCAP>(d, tileF, fac, dinv, loc, smem);
+  else if (d.np <= PCAP_B)
+    local_solve_pipe_body<T, PipeCfg<T>::PB_BIG, PCAP_B>(d, tileF, fac, dinv, loc, smem);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
@@ -513,7 +557,7 @@ k_local_solve(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tile
   const T* A = fac + d.fac_off;
   const T* Di = dinv + d.dinv_off;
   double* y = loc + d.loc_off;
-  if (d.np <= PCAP) return;                 // done by k_local_solve_pipe
+  if (d.np <= PCAP_B) return;               // done by k_local_solve_pipe
   if (d.np <= YCAP) {
     local_solve_lds<T>(d, F, off, A, Di, y, ys, sF, sOff, part, sv);
     return;
@@ -573,16 +617,28 @@ template __global__ void k_local_solve<float>(const SubDesc*, const int32_t*, co
 
 void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                         const double* dinv, double* loc) {
-  k_local_solve_pipe<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, fac, dinv, loc);
-  if (P.max_np > PCAP)
+  k_local_solve_pipe<double><<<nsub, 256, pipe_lds_bytes<double>(), st>>>(P.subs, P.solve_order,
+                                                                          P.tileF, fac, dinv, loc);
+  if (P.max_np > PCAP_B)
     k_local_solve<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
 }
 
 void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
                             const float* dinv, double* loc) {
-  k_local_solve_pipe<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, fac, dinv, loc);
-  if (P.max_np > PCAP)
+  k_local_solve_pipe<float><<<nsub, 256, pipe_lds_bytes<float>(), st>>>(P.subs, P.solve_order,
+                                                                        P.tileF, fac, dinv, loc);
+  if (P.max_np > PCAP_B)
     k_local_solve<float><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, loc);
+}
+
+hipError_t local_solve_configure() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_local_solve_pipe<double>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)pipe_lds_bytes<double>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_local_solve_pipe<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pipe_lds_bytes<float>());
+  return e;
 }
 
 }  // namespace lsq2l

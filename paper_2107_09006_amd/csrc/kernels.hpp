@@ -29,6 +29,7 @@ struct DevPlan {              // subdomain layout (device copies of HostPlan)
   int64_t* tileOff = nullptr;
   int32_t* own_ptr = nullptr;
   int32_t* own_pos = nullptr;
+  int32_t* solve_order = nullptr;  // subdomains by decreasing stored factor tiles
   int max_np = 0;             // largest padded local size
 };
 
@@ -163,6 +164,8 @@ void launch_local_solve(hipStream_t st, int nsub, const DevPlan& P, const double
                         const double* dinv, double* loc);
 void launch_local_solve_f32(hipStream_t st, int nsub, const DevPlan& P, const float* fac,
                             const float* dinv, double* loc);
+// allows the streaming local solve its dynamic LDS (once per process)
+hipError_t local_solve_configure();
 // restricted: each column takes its owner's interior value only (R_i^T D_i, eq. RAS)
 void launch_scatter_local(hipStream_t st, int32_t n, const DevPlan& P, const double* scale,
                           const double* loc, const double* X, const double* dcoarse, double* z,

@@ -522,8 +522,11 @@ void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& ph, 
 
 void row_order(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, RowOrder& ro) {
   auto key = [&](int32_t i) { return rp[i] < rp[i + 1] ? ci[rp[i]] : n; };
+  // far descents: the first column drops by more than ROW_ORDER_JUMP (rows
+  // that jitter around a slowly moving centre keep their x gathers local)
+  constexpr int32_t ROW_ORDER_JUMP = 256;
   int64_t desc = 0;
-  for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1);
+  for (int32_t i = 1; i < m; ++i) desc += key(i) < key(i - 1) - ROW_ORDER_JUMP;
   ro.use = m >= 65536 && desc * 16 > m;
   if (!ro.use) return;
   std::vector<int32_t> start((size_t)n + 2, 0);

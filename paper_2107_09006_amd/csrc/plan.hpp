@@ -67,10 +67,10 @@ struct CoarsePlan {
 // Fills p, x_off, w_off, c_off, cg_off of every subdomain of H and the plan of E.
 void plan_coarse(HostPlan& H, int S, int32_t m, const std::vector<int32_t>& p, CoarsePlan& C);
 
-// When consecutive rows of A start at unrelated columns (more than one
-// descent of the first column per 16 rows, at least 65,536 rows), the rows
-// sorted stably by their first column (counting sort): perm[i] is the row of A
-// placed at i, prp the row starts of the permuted copy.  The x gathers of A p
+// When consecutive rows of A start at unrelated columns (more than one drop
+// of the first column by more than 256 columns per 16 rows, at least 65,536
+// rows), the rows sorted stably by their first column (counting sort):
+// perm[i] is the row of A placed at i, prp the row starts of the permuted copy.  The x gathers of A p
 // and the (A p) gathers of A^T (A p) then stay local.
 struct RowOrder {
   bool use = false;
