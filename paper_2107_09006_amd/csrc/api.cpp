@@ -158,6 +158,21 @@ void* pinned_take(size_t bytes, size_t* got) { return pinned_pool().take(bytes, 
 void pinned_give(void* p, size_t bytes) { pinned_pool().give(p, bytes); }
 void pinned_release() { pinned_pool().release(); }
 
+// host arrays of the planner: from 1 MiB up in the pinned pool (whole MiB),
+// smaller ones from the heap
+void* host_block_take(size_t bytes, size_t* got) {
+  constexpr size_t MiB = (size_t)1 << 20;
+  if (bytes < MiB) {
+    *got = bytes;
+    return std::malloc(bytes);
+  }
+  return pinned_take((bytes + MiB - 1) / MiB * MiB, got);
+}
+void host_block_give(void* p, size_t bytes) {
+  if (bytes < ((size_t)1 << 20)) std::free(p);
+  else pinned_give(p, bytes);
+}
+
 }  // namespace lsq2l
 
 using namespace lsq2l;
@@ -573,9 +588,8 @@ struct MapsJob {
   std::thread th;
   bool ok = true;
   std::string err;
-  void start(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* part,
-             HostPlan* H) {
-    th = std::thread([this, m, n, rp, ci, part, H]() { ok = plan_maps(m, n, rp, ci, part, *H, err); });
+  void start(int32_t n, HostPlan* H) {
+    th = std::thread([this, n, H]() { ok = plan_maps(n, *H, err); });
   }
   bool join() {
     if (th.joinable()) th.join();
@@ -596,7 +610,7 @@ lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps);
 
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
-                        const std::vector<int32_t>& part, int32_t nparts,
+                        const HostVec<int32_t>& part, int32_t nparts,
                         const std::vector<int32_t>& seg_of_part) {
   const hipStream_t st = c->st;
   const int32_t m = c->M.m, n = c->M.n;
@@ -604,10 +618,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   auto t_all = clk::now();
   auto t0 = clk::now();
   // --- transpose and index sets
-  // A^T on the device; the planner reads its pattern back
-  PinnedArray<int32_t> trp, tcol;
-  TRY(trp.alloc((int64_t)n + 1));
-  TRY(tcol.alloc(nnz));
+  // A^T on the device, while the host plans from A's pattern
   char* temp = nullptr;
   const size_t tb = transpose_temp_bytes(nnz, n);
   TRY(c->dalloc(&c->M.trowptr, (int64_t)n + 1));
@@ -617,9 +628,6 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
   LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.vals, c->M.trowptr,
                                  c->M.trow, c->M.tvals, c->M.tperm, temp, tb));
-  LSQ2L_HIP_TRY(hipMemcpyAsync(trp.p, c->M.trowptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  if (nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(tcol.p, c->M.trow, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
   // Row order of the copy used for C p = A^T (A p), found on a host thread
@@ -627,14 +635,14 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   RowOrder ro;
   JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci]() { row_order(m, n, rp, ci, ro); })};
   std::string err;
-  if (!plan_build(m, n, rp, ci, trp.p, tcol.p, part.data(), nparts, seg_of_part, c->H, err)) {
+  if (!plan_build(m, n, rp, ci, part.data(), nparts, seg_of_part, c->H, err)) {
     set_error(err);
     return LSQ2L_EINVAL;
   }
   HostPlan& H = c->H;
   c->nsub = nparts;
   MapsJob maps;
-  maps.start(m, n, rp, ci, part.data(), &H);
+  maps.start(n, &H);
   TRY(c->upload(&c->P.subs, H.subs));
   TRY(c->upload(&c->P.omega, H.omega));
   TRY(c->upload(&c->P.xi, H.xi));
@@ -1158,30 +1166,49 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   }
   if (NNZ) LSQ2L_HIP_TRY(hipMemcpyAsync(ci.p, c->M.colind, NNZ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   // partitions: host arrays are read in place, device arrays copied back
-  std::vector<int32_t> pt(N), seg_of_part(NP);
-  std::vector<std::vector<int32_t>> pdev(count);
+  HostVec<int32_t> pt, rp;
+  std::vector<int32_t> seg_of_part(NP);
+  if (!pt.resize(N) || !rp.resize(M + 1)) { set_error("host allocation failed"); return LSQ2L_ENOMEM; }
+  std::vector<PinnedArray<int32_t>> pdev(count);
   for (int k = 0; k < count; ++k)
     if (is_device_ptr(probs[k].part)) {
-      pdev[k].resize(probs[k].n);
-      LSQ2L_HIP_TRY(hipMemcpyAsync(pdev[k].data(), probs[k].part, probs[k].n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      TRY(pdev[k].alloc(probs[k].n));
+      LSQ2L_HIP_TRY(hipMemcpyAsync(pdev[k].p, probs[k].part, probs[k].n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
   const hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return LSQ2L_EHIP; }
-  std::vector<int32_t> rp(M + 1);
   TRY(validate_all(count, probs, r0, c0, e0, rp64.p, ci.p, rp.data()));
-  for (int k = 0; k < count; ++k) {
-    const lsq2l_problem& pr = probs[k];
-    const int32_t* part = pdev[k].empty() ? probs[k].part : pdev[k].data();
-    for (int64_t j = 0; j < pr.n; ++j) {
-      if (part[j] < 0 || part[j] >= pr.nparts) {
-        set_error(count == 1 ? "part[" + std::to_string(j) + "] out of range"
+  // global part numbers, checked, in parallel over column ranges
+  {
+    const unsigned nth = N < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<int64_t> bad(nth, -1);
+    std::vector<std::thread> pool;
+    auto work = [&](unsigned t) {
+      const int64_t g0 = N * t / nth, g1 = N * (t + 1) / nth;
+      int k = (int)(std::upper_bound(c0.begin(), c0.end(), g0) - c0.begin()) - 1;
+      for (int64_t g = g0; g < g1; ++g) {
+        while (g >= c0[k + 1]) ++k;
+        const int32_t* part = pdev[k].p ? pdev[k].p : probs[k].part;
+        const int32_t v = part[g - c0[k]];
+        if (v < 0 || v >= probs[k].nparts) { bad[t] = g; return; }
+        pt[g] = (int32_t)(p0[k] + v);
+      }
+    };
+    if (nth == 1) work(0);
+    else {
+      for (unsigned t = 0; t < nth; ++t) pool.emplace_back(work, t);
+      for (auto& th : pool) th.join();
+    }
+    for (unsigned t = 0; t < nth; ++t)
+      if (bad[t] >= 0) {
+        const int k = (int)(std::upper_bound(c0.begin(), c0.end(), bad[t]) - c0.begin()) - 1;
+        set_error(count == 1 ? "part[" + std::to_string(bad[t]) + "] out of range"
                              : "part out of range in problem " + std::to_string(k));
         return LSQ2L_EINVAL;
       }
-      pt[c0[k] + j] = (int32_t)(p0[k] + part[j]);
-    }
-    for (int32_t q = 0; q < pr.nparts; ++q) seg_of_part[p0[k] + q] = k;
   }
+  for (int k = 0; k < count; ++k)
+    for (int32_t q = 0; q < probs[k].nparts; ++q) seg_of_part[p0[k] + q] = k;
   c->info.t_prepare_ms = ms_since(t_prep);
   return setup_core(c, rp.data(), ci.p, pt, (int32_t)NP, seg_of_part);
 }

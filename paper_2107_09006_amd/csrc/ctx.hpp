@@ -4,6 +4,8 @@
 // drivers (krylov.cpp).
 #pragma once
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <cstddef>
@@ -183,6 +185,16 @@ struct lsq2l_ctx {
     return LSQ2L_OK;
   }
   // the caller has synchronized the stream
+  // a planner array: its block is page-locked (or small), so it is copied
+  // directly; it outlives the copy (kept in the handle or synchronized)
+  template <typename T>
+  lsq2l_status upload(T** dst, const lsq2l::HostVec<T>& src) {
+    lsq2l_status s = dalloc(dst, (int64_t)src.size());
+    if (s != LSQ2L_OK) return s;
+    if (src.empty()) return LSQ2L_OK;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return LSQ2L_OK;
+  }
   void release_staged() {
     for (auto& b : staged) lsq2l::pinned_give(b.first, b.second);
     staged.clear();

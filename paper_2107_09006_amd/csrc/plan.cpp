@@ -8,6 +8,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 #include <thread>
@@ -73,13 +74,6 @@ bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* 
 
 namespace {
 
-struct LocalOut {
-  std::vector<int32_t> xi, gamma, F;
-};
-
-// Index sets and tile envelope of subdomain i.  Only lists of the size of the
-// subdomain's columns and rows are built (sorted and deduplicated), so the
-// work is proportional to the entries of A it touches.
 // A set of indices as a bitmap: mark() records an index and the range seen,
 // drain() appends the marked indices in ascending order and clears them, so
 // the bitmap is all zero between uses.
@@ -107,53 +101,97 @@ struct BitSet {
   }
 };
 
-void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* trowptr,
-              const int32_t* tcol, const int32_t* part, const int32_t* locown, const int32_t* I,
-              int32_t nI, BitSet& rowset, BitSet& colset, LocalOut& out) {
-  // Xi_i: rows with a stored entry in a column of Omega_Ii, ascending
-  out.xi.clear();
-  for (int32_t a = 0; a < nI; ++a)
-    for (int32_t k = trowptr[I[a]]; k < trowptr[I[a] + 1]; ++k) rowset.mark(tcol[k]);
-  rowset.drain(out.xi);
-  // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii, ascending
+unsigned planner_threads() {
+  return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+template <typename F>
+void run_threads(unsigned nth, F&& fn) {
+  if (nth == 1) {
+    fn(0u);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
+  for (auto& th : pool) th.join();
+}
+
+// Distinct parts of the columns of row r, ascending, into buf; returns their
+// number.  Row r belongs to Xi_i exactly for the parts i of this list.
+inline int row_parts(const int32_t* rowptr, const int32_t* colind, const int32_t* part, int32_t r,
+                     int32_t* buf) {
+  int k = 0;
+  for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int32_t v = part[colind[e]];
+    int q = k;
+    while (q > 0 && buf[q - 1] > v) --q;
+    if (q > 0 && buf[q - 1] == v) continue;
+    for (int u = k; u > q; --u) buf[u] = buf[u - 1];
+    buf[q] = v;
+    ++k;
+  }
+  return k;
+}
+
+struct LocalOut {
+  std::vector<int32_t> gamma, F;
+};
+
+// Interface set and tile envelope of subdomain i, given Xi_i (ascending) and
+// the rows that hold columns of several parts (bnd).  Work is proportional
+// to the entries of A in the rows of Xi_i.
+void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* part,
+              const int32_t* locown, const uint8_t* bnd, int32_t nI, const int32_t* xi,
+              int32_t nXi, BitSet& colset, std::vector<int32_t>& f, std::vector<int32_t>& rpos,
+              LocalOut& out) {
+  // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii, ascending; only
+  // rows with columns in several parts hold such columns
   out.gamma.clear();
-  for (int32_t r : out.xi)
+  for (int32_t a = 0; a < nXi; ++a) {
+    const int32_t r = xi[a];
+    if (!bnd[r]) continue;
     for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
       if (part[colind[e]] != i) colset.mark(colind[e]);
+  }
   colset.drain(out.gamma);
   const int32_t nG = (int32_t)out.gamma.size();
   const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
-  // local position of a column of Omega_i (-1 outside)
-  auto pos_of = [&](int32_t c) -> int32_t {
-    if (part[c] == i) return locown[c];
-    auto it = std::lower_bound(out.gamma.begin(), out.gamma.end(), c);
-    return (it != out.gamma.end() && *it == c) ? nIp + (int32_t)(it - out.gamma.begin()) : -1;
-  };
-
-  // row envelope of C_ii: f(a) = smallest local position coupled to a, i.e.
-  // the minimum, over the rows holding column a, of the row's smallest local
-  // position.  Every row of Xi_i is visited once; rows outside Xi_i that hold
-  // an interface column are visited from that column.
-  std::vector<int32_t> f(np);
+  // Row envelope of C_ii: f(a) = smallest local position coupled to a, the
+  // minimum over the rows holding column a of the row's smallest local
+  // position.  Only the rows of Xi_i are visited.  A row outside Xi_i holds
+  // interface columns only, so it couples positions >= nIp among themselves;
+  // every interface column also sits in a row of Xi_i next to an interior
+  // column, whose position (< nIp) already bounds f there.  Such rows thus
+  // never lower a tile's first column, and their entries of C_ii lie inside
+  // the envelope.
+  f.resize((size_t)np);
   for (int32_t a = 0; a < np; ++a) f[a] = a;
-  std::vector<int32_t> rpos;
-  auto visit = [&](int32_t r) {
-    rpos.clear();
-    int32_t best = INT32_MAX;
-    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      const int32_t q = pos_of(colind[e]);
-      if (q >= 0) { rpos.push_back(q); best = std::min(best, q); }
+  for (int32_t a = 0; a < nXi; ++a) {
+    const int32_t r = xi[a];
+    const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
+    if (bnd[r]) {
+      rpos.clear();
+      int32_t best = INT32_MAX;
+      for (int32_t e = e0; e < e1; ++e) {
+        const int32_t c = colind[e];
+        int32_t q;
+        if (part[c] == i) {
+          q = locown[c];
+        } else {
+          // every column of a row of Xi_i lies in Omega_i
+          q = nIp + (int32_t)(std::lower_bound(out.gamma.begin(), out.gamma.end(), c) - out.gamma.begin());
+        }
+        rpos.push_back(q);
+        best = std::min(best, q);
+      }
+      for (int32_t q : rpos) f[q] = std::min(f[q], best);
+      continue;
     }
-    for (int32_t q : rpos) f[q] = std::min(f[q], best);
-  };
-  for (int32_t r : out.xi) visit(r);
-  for (int32_t g = 0; g < nG; ++g) {
-    const int32_t c = out.gamma[g];
-    for (int32_t k = trowptr[c]; k < trowptr[c + 1]; ++k) {
-      const int32_t r = tcol[k];
-      bool in_xi = false;
-      for (int32_t e = rowptr[r]; e < rowptr[r + 1] && !in_xi; ++e) in_xi = part[colind[e]] == i;
-      if (!in_xi) visit(r);
+    // all columns in part i, ascending, and locown is increasing inside a part
+    const int32_t best = locown[colind[e0]];
+    for (int32_t e = e0; e < e1; ++e) {
+      int32_t& fq = f[locown[colind[e]]];
+      fq = std::min(fq, best);
     }
   }
   const int32_t nt = np / TS;
@@ -168,18 +206,16 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
 }  // namespace
 
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
-                const int32_t* trowptr, const int32_t* tcol,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
                 HostPlan& P, std::string& err) {
   P.nparts = nparts;
-  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  nth = std::min<unsigned>(nth, (unsigned)nparts);
+  const unsigned nth = std::min<unsigned>(planner_threads(), (unsigned)std::max(nparts, 1));
   // columns of each part, ascending, and each column's position in its part:
   // a counting sort over column ranges, one per thread (each range's columns
   // follow those of the earlier ranges inside every part)
   std::vector<int64_t> pptr((size_t)nparts + 1, 0);
-  std::vector<int32_t> pcols((size_t)n);
-  P.locown.resize((size_t)n);
+  HostVec<int32_t> pcols;
+  if (!pcols.resize((size_t)n) || !P.locown.resize((size_t)n)) { err = "host allocation failed"; return false; }
   {
     const unsigned ct = n < (1 << 16) ? 1u : nth;
     std::vector<std::vector<int64_t>> cnt(ct, std::vector<int64_t>((size_t)nparts, 0));
@@ -187,12 +223,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       a = (int32_t)((int64_t)n * t / ct);
       b = (int32_t)((int64_t)n * (t + 1) / ct);
     };
-    auto cpar = [&](auto&& fn) {
-      std::vector<std::thread> pool;
-      for (unsigned t = 0; t < ct; ++t) pool.emplace_back([&, t]() { fn(t); });
-      for (auto& th : pool) th.join();
-    };
-    cpar([&](unsigned t) {
+    run_threads(ct, [&](unsigned t) {
       int32_t a, b;
       crange(t, a, b);
       for (int32_t j = a; j < b; ++j) cnt[t][part[j]]++;
@@ -203,7 +234,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       if (run == 0) { err = "part " + std::to_string(i) + " is empty"; return false; }
       pptr[i + 1] = pptr[i] + run;
     }
-    cpar([&](unsigned t) {
+    run_threads(ct, [&](unsigned t) {
       int32_t a, b;
       crange(t, a, b);
       for (int32_t j = a; j < b; ++j) {
@@ -214,23 +245,88 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       }
     });
   }
-  // per-subdomain work in parallel
+  // Xi_i, row-major: row r belongs to Xi_i for every part i among its
+  // columns.  Two passes over row ranges (count rows per (range, part), then
+  // place them), so every Xi_i comes out ascending.  The placing pass marks
+  // the rows with columns in several parts and records, for every two parts
+  // i < j of such a row, the row's positions in Xi_i and Xi_j.
+  const unsigned rt = m < (1 << 16) ? 1u : planner_threads();
+  const int64_t nnz = rowptr[m];
+  std::vector<int32_t> rb(rt + 1, m);   // row ranges of about nnz / rt entries
+  for (unsigned t = 0; t < rt; ++t)
+    rb[t] = (int32_t)(std::lower_bound(rowptr, rowptr + m + 1, (int32_t)(nnz * (int64_t)t / rt)) - rowptr);
+  rb[rt] = m;
+  // the counting pass keeps every row's list (length, then the parts) for
+  // the placing pass
+  std::vector<std::vector<int64_t>> xcnt(rt, std::vector<int64_t>((size_t)nparts, 0));
+  std::vector<HostVec<int32_t>> lists(rt);
+  std::vector<uint8_t> ok(rt, 1);
+  run_threads(rt, [&](unsigned t) {
+    const int32_t a = rb[t], b = std::max(rb[t], rb[t + 1]);
+    if (!lists[t].resize((size_t)(b - a) + (size_t)(rowptr[b] - rowptr[a]))) { ok[t] = 0; return; }
+    int32_t* out = lists[t].data();
+    for (int32_t r = a; r < b; ++r) {
+      const int k = row_parts(rowptr, colind, part, r, out + 1);
+      *out = k;
+      for (int q = 0; q < k; ++q) xcnt[t][out[1 + q]]++;
+      out += 1 + k;
+    }
+  });
+  for (unsigned t = 0; t < rt; ++t)
+    if (!ok[t]) { err = "host allocation failed"; return false; }
+  std::vector<int64_t> xoff((size_t)nparts + 1, 0);
+  for (int32_t i = 0; i < nparts; ++i) {
+    int64_t run = 0;
+    for (unsigned t = 0; t < rt; ++t) { const int64_t c = xcnt[t][i]; xcnt[t][i] = run; run += c; }
+    xoff[i + 1] = xoff[i] + run;
+  }
+  if (!P.xi.resize((size_t)xoff[nparts])) { err = "host allocation failed"; return false; }
+  HostVec<uint8_t> bnd;
+  if (!bnd.resize((size_t)m)) { err = "host allocation failed"; return false; }
+  P.shared_rows.assign(rt, {});
+  run_threads(rt, [&](unsigned t) {
+    std::vector<int32_t> rank(64);
+    std::vector<int32_t>& rec = P.shared_rows[t];
+    const int32_t* in = lists[t].data();
+    for (int32_t r = rb[t]; r < rb[t + 1]; ++r) {
+      const int k = *in++;
+      if ((size_t)k > rank.size()) rank.resize((size_t)k);
+      for (int u = 0; u < k; ++u) {
+        const int64_t q = xcnt[t][in[u]]++;     // rank of r in Xi of that part
+        rank[u] = (int32_t)q;
+        P.xi[xoff[in[u]] + q] = r;
+      }
+      bnd[r] = k > 1;
+      for (int u = 0; u < k; ++u)
+        for (int v = u + 1; v < k; ++v) rec.insert(rec.end(), {in[u], in[v], rank[u], rank[v]});
+      in += k;
+    }
+  });
+  lists.clear();
+  // interface sets and envelopes, largest subdomains first, claimed one at
+  // a time by the threads
   std::vector<LocalOut> outs((size_t)nparts);
   {
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < nth; ++t)
-      pool.emplace_back([&, t]() {
-        BitSet rowset(m), colset(n);
-        for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth)
-          plan_one(i, rowptr, colind, trowptr, tcol, part, P.locown.data(),
-                   pcols.data() + pptr[i], (int32_t)(pptr[i + 1] - pptr[i]), rowset, colset,
-                   outs[i]);
-      });
-    for (auto& th : pool) th.join();
+    std::vector<int32_t> order((size_t)nparts);
+    for (int32_t i = 0; i < nparts; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return xoff[x + 1] - xoff[x] > xoff[y + 1] - xoff[y];
+    });
+    std::atomic<int32_t> next{0};
+    run_threads(nth, [&](unsigned) {
+      BitSet colset(n);
+      std::vector<int32_t> f, rpos;
+      for (int32_t w = next++; w < nparts; w = next++) {
+        const int32_t i = order[w];
+        plan_one(i, rowptr, colind, part, P.locown.data(), bnd.data(),
+                 (int32_t)(pptr[i + 1] - pptr[i]), P.xi.data() + xoff[i],
+                 (int32_t)(xoff[i + 1] - xoff[i]), colset, f, rpos, outs[i]);
+      }
+    });
   }
   // offsets
   P.subs.assign((size_t)nparts, SubDesc{});
-  int64_t omega_off = 0, xi_off = 0, loc_off = 0, tile_base = 0, fac_tiles = 0, g_off = 0;
+  int64_t omega_off = 0, loc_off = 0, tile_base = 0, fac_tiles = 0, g_off = 0;
   int64_t dinv_tiles = 0;
   for (int32_t i = 0; i < nparts; ++i) {
     SubDesc& d = P.subs[i];
@@ -241,11 +337,11 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     d.np = d.nIp + d.nGp;
     d.ntiles = d.np / TS;
     d.ntI = d.nIp / TS;
-    d.nXi = (int32_t)outs[i].xi.size();
+    d.nXi = (int32_t)(xoff[i + 1] - xoff[i]);
     d.p = 0;
     d.seg = seg_of_part[i];
     d.omega_off = omega_off; omega_off += d.nI + d.nG;
-    d.xi_off = xi_off; xi_off += d.nXi;
+    d.xi_off = xoff[i];
     d.loc_off = loc_off; loc_off += d.np;
     d.tile_base = tile_base; tile_base += d.ntiles;
     d.fac_off = fac_tiles * TT;
@@ -260,162 +356,103 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
   P.total_tiles = tile_base;
   P.total_fac = fac_tiles * TT;
   P.total_g = g_off;
-  P.omega.resize((size_t)omega_off);
-  P.xi.resize((size_t)xi_off);
-  P.tileF.resize((size_t)tile_base);
-  P.tileOff.resize((size_t)tile_base);
-  // per-subdomain copies into the flat arrays (disjoint ranges), in parallel
-  {
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < nth; ++t)
-      pool.emplace_back([&, t]() {
-        for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth) {
-          const SubDesc& d = P.subs[i];
-          std::memcpy(&P.omega[d.omega_off], pcols.data() + pptr[i], sizeof(int32_t) * d.nI);
-          std::memcpy(&P.omega[d.omega_off + d.nI], outs[i].gamma.data(), sizeof(int32_t) * d.nG);
-          std::memcpy(&P.xi[d.xi_off], outs[i].xi.data(), sizeof(int32_t) * d.nXi);
-          int64_t off = 0;   // relative to the subdomain's first tile (fac_off / TT)
-          for (int32_t q = 0; q < d.ntiles; ++q) {
-            P.tileF[d.tile_base + q] = outs[i].F[q];
-            P.tileOff[d.tile_base + q] = off;
-            off += q - outs[i].F[q] + 1;
-          }
-        }
-      });
-    for (auto& th : pool) th.join();
+  if (!P.omega.resize((size_t)omega_off) || !P.tileF.resize((size_t)tile_base) ||
+      !P.tileOff.resize((size_t)tile_base)) {
+    err = "host allocation failed";
+    return false;
   }
+  // per-subdomain copies into the flat arrays (disjoint ranges), in parallel
+  run_threads(nth, [&](unsigned t) {
+    for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth) {
+      const SubDesc& d = P.subs[i];
+      std::memcpy(&P.omega[d.omega_off], pcols.data() + pptr[i], sizeof(int32_t) * d.nI);
+      if (d.nG) std::memcpy(&P.omega[d.omega_off + d.nI], outs[i].gamma.data(), sizeof(int32_t) * d.nG);
+      int64_t off = 0;   // relative to the subdomain's first tile (fac_off / TT)
+      for (int32_t q = 0; q < d.ntiles; ++q) {
+        P.tileF[d.tile_base + q] = outs[i].F[q];
+        P.tileOff[d.tile_base + q] = off;
+        off += q - outs[i].F[q] + 1;
+      }
+    }
+  });
   P.total_dinv = dinv_tiles * TT;
   return true;
 }
 
-bool plan_maps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
-               const int32_t* part, HostPlan& P, std::string& err) {
+bool plan_maps(int32_t n, HostPlan& P, std::string& err) {
   const int32_t nparts = P.nparts;
+  const unsigned nth = std::min<unsigned>(planner_threads(), (unsigned)std::max(nparts, 1));
   // inverse overlap map: for every column, the local positions holding it,
-  // in increasing subdomain order (deterministic summation order)
-  P.own_ptr.assign((size_t)n + 1, 0);
-  for (int32_t i = 0; i < nparts; ++i) {
-    const SubDesc& d = P.subs[i];
-    for (int32_t a = 0; a < d.nI + d.nG; ++a) P.own_ptr[P.omega[d.omega_off + a] + 1]++;
-  }
-  for (int32_t j = 0; j < n; ++j) P.own_ptr[j + 1] += P.own_ptr[j];
-  P.own_pos.resize((size_t)P.own_ptr[n]);
-  {
-    std::vector<int32_t> fill(P.own_ptr.begin(), P.own_ptr.end() - 1);
-    for (int32_t i = 0; i < nparts; ++i) {
+  // in increasing subdomain order (deterministic summation order).  Counted
+  // and placed by subdomain in parallel, then every column's short list is
+  // sorted: local positions grow with the subdomain index.
+  if (!P.own_ptr.assign((size_t)n + 1, 0)) { err = "host allocation failed"; return false; }
+  int32_t* cnt = P.own_ptr.data() + 1;
+  run_threads(nth, [&](unsigned t) {
+    for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth) {
       const SubDesc& d = P.subs[i];
-      for (int32_t a = 0; a < d.nI; ++a)
-        P.own_pos[fill[P.omega[d.omega_off + a]]++] = (int32_t)(d.loc_off + a);
-      for (int32_t g = 0; g < d.nG; ++g)
-        P.own_pos[fill[P.omega[d.omega_off + d.nI + g]]++] = (int32_t)(d.loc_off + d.nIp + g);
+      for (int32_t a = 0; a < d.nI + d.nG; ++a)
+        __atomic_fetch_add(&cnt[P.omega[d.omega_off + a]], 1, __ATOMIC_RELAXED);
     }
-  }
-  // for each row, the subdomains whose Xi contains it, with the row's rank in
-  // Xi_i: row r is in Xi_i exactly when one of its columns lies in part i, so
-  // the list is the sorted set of distinct parts of the row.  Two passes over
-  // row ranges: count rows per (thread, part), then fill, the rank coming
-  // from a running counter offset by the counts of the earlier ranges.
+  });
+  for (int32_t j = 0; j < n; ++j) P.own_ptr[j + 1] += P.own_ptr[j];
+  if (!P.own_pos.resize((size_t)P.own_ptr[n])) { err = "host allocation failed"; return false; }
   {
-    const unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    auto row_parts = [&](int32_t r, int32_t* buf) -> int {
-      int k = 0;
-      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        const int32_t v = part[colind[e]];
-        int q = k;
-        while (q > 0 && buf[q - 1] > v) --q;
-        if (q > 0 && buf[q - 1] == v) continue;
-        for (int u = k; u > q; --u) buf[u] = buf[u - 1];
-        buf[q] = v;
-        ++k;
-      }
-      return k;
-    };
-    int32_t maxrow = 0;
-    for (int32_t r = 0; r < m; ++r) maxrow = std::max(maxrow, rowptr[r + 1] - rowptr[r]);
-    std::vector<std::vector<int64_t>> cnt(nthr, std::vector<int64_t>((size_t)nparts, 0));
-    P.rsub_ptr.assign((size_t)m + 1, 0);
-    auto par = [&](auto&& fn) {
-      std::vector<std::thread> pool;
-      for (unsigned t = 0; t < nthr; ++t) pool.emplace_back([&, t]() { fn(t); });
-      for (auto& th : pool) th.join();
-    };
-    auto range = [&](unsigned t, int32_t& a, int32_t& b) {
-      a = (int32_t)((int64_t)m * t / nthr);
-      b = (int32_t)((int64_t)m * (t + 1) / nthr);
-    };
-    par([&](unsigned t) {
-      std::vector<int32_t> buf((size_t)maxrow + 1);
-      int32_t a, b;
-      range(t, a, b);
-      for (int32_t r = a; r < b; ++r) {
-        const int k = row_parts(r, buf.data());
-        P.rsub_ptr[r + 1] = k;
-        for (int q = 0; q < k; ++q) cnt[t][buf[q]]++;
+    HostVec<int32_t> fill;
+    if (!fill.resize((size_t)n)) { err = "host allocation failed"; return false; }
+    std::memcpy(fill.data(), P.own_ptr.data(), sizeof(int32_t) * n);
+    int32_t* fp = fill.data();
+    run_threads(nth, [&](unsigned t) {
+      for (int32_t i = (int32_t)t; i < nparts; i += (int32_t)nth) {
+        const SubDesc& d = P.subs[i];
+        for (int32_t a = 0; a < d.nI + d.nG; ++a) {
+          const int32_t pos = (int32_t)(d.loc_off + (a < d.nI ? a : d.nIp + (a - d.nI)));
+          P.own_pos[__atomic_fetch_add(&fp[P.omega[d.omega_off + a]], 1, __ATOMIC_RELAXED)] = pos;
+        }
       }
     });
-    for (int32_t r = 0; r < m; ++r) P.rsub_ptr[r + 1] += P.rsub_ptr[r];
-    for (int32_t i = 0; i < nparts; ++i) {
-      int64_t run = 0;
-      for (unsigned t = 0; t < nthr; ++t) { const int64_t c = cnt[t][i]; cnt[t][i] = run; run += c; }
-      if (run != P.subs[i].nXi) { err = "inconsistent row sets"; return false; }
-    }
-    P.rsub.resize((size_t)P.rsub_ptr[m]);
-    P.rsub_pos.resize((size_t)P.rsub_ptr[m]);
-    // the fill pass also records, per row range, every pair u < v of the
-    // row's list as (i, j, pos in Xi_i, pos in Xi_j), in row order
-    std::vector<std::vector<int32_t>> rec(nthr);
-    par([&](unsigned t) {
-      std::vector<int32_t> buf((size_t)maxrow + 1);
-      int32_t a, b;
-      range(t, a, b);
-      for (int32_t r = a; r < b; ++r) {
-        const int k = row_parts(r, buf.data());
-        const int64_t q0 = P.rsub_ptr[r];
-        int64_t q = q0;
-        for (int u = 0; u < k; ++u, ++q) {
-          P.rsub[q] = buf[u];
-          P.rsub_pos[q] = (int32_t)cnt[t][buf[u]]++;
-        }
-        for (int u = 0; u < k; ++u)
-          for (int v = u + 1; v < k; ++v)
-            rec[t].insert(rec[t].end(), {P.rsub[q0 + u], P.rsub[q0 + v], P.rsub_pos[q0 + u],
-                                         P.rsub_pos[q0 + v]});
-      }
+    run_threads(nth, [&](unsigned t) {
+      const int32_t j0 = (int32_t)((int64_t)n * t / nth), j1 = (int32_t)((int64_t)n * (t + 1) / nth);
+      for (int32_t j = j0; j < j1; ++j)
+        if (P.own_ptr[j + 1] - P.own_ptr[j] > 1)
+          std::sort(P.own_pos.begin() + P.own_ptr[j], P.own_pos.begin() + P.own_ptr[j + 1]);
     });
-    // pair ids in order of first occurrence (ranges in row order), then the
-    // rows of every pair grouped by id
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> adj((size_t)nparts);   // (j, id)
-    std::vector<int32_t> rid;
-    std::vector<int64_t> pcnt;
-    P.cpair_ij.clear();
-    for (unsigned t = 0; t < nthr; ++t)
-      for (size_t e = 0; e < rec[t].size(); e += 4) {
-        const int32_t i = rec[t][e], j = rec[t][e + 1];
-        int32_t id = -1;
-        for (const auto& pr : adj[i])
-          if (pr.first == j) { id = pr.second; break; }
-        if (id < 0) {
-          id = (int32_t)pcnt.size();
-          adj[i].push_back({j, id});
-          P.cpair_ij.push_back(i);
-          P.cpair_ij.push_back(j);
-          pcnt.push_back(0);
-        }
-        ++pcnt[id];
-        rid.push_back(id);
-      }
-    P.cpair_ptr.assign(pcnt.size() + 1, 0);
-    for (size_t k = 0; k < pcnt.size(); ++k) P.cpair_ptr[k + 1] = P.cpair_ptr[k] + pcnt[k];
-    P.cpair_rows.resize((size_t)(2 * P.cpair_ptr.back()));
-    std::vector<int64_t> cur(P.cpair_ptr.begin(), P.cpair_ptr.end() - 1);
-    size_t x = 0;
-    for (unsigned t = 0; t < nthr; ++t)
-      for (size_t e = 0; e < rec[t].size(); e += 4, ++x) {
-        const int64_t at = cur[rid[x]]++;
-        P.cpair_rows[2 * at] = rec[t][e + 2];
-        P.cpair_rows[2 * at + 1] = rec[t][e + 3];
-      }
   }
+  // pairs of subdomains sharing rows: ids in order of first occurrence (row
+  // ranges in row order), then the rows of every pair grouped by id
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> adj((size_t)nparts);   // (j, id)
+  std::vector<int32_t> rid;
+  std::vector<int64_t> pcnt;
+  P.cpair_ij.clear();
+  for (const auto& rec : P.shared_rows)
+    for (size_t e = 0; e < rec.size(); e += 4) {
+      const int32_t i = rec[e], j = rec[e + 1];
+      int32_t id = -1;
+      for (const auto& pr : adj[i])
+        if (pr.first == j) { id = pr.second; break; }
+      if (id < 0) {
+        id = (int32_t)pcnt.size();
+        adj[i].push_back({j, id});
+        P.cpair_ij.push_back(i);
+        P.cpair_ij.push_back(j);
+        pcnt.push_back(0);
+      }
+      ++pcnt[id];
+      rid.push_back(id);
+    }
+  P.cpair_ptr.assign(pcnt.size() + 1, 0);
+  for (size_t k = 0; k < pcnt.size(); ++k) P.cpair_ptr[k + 1] = P.cpair_ptr[k] + pcnt[k];
+  P.cpair_rows.resize((size_t)(2 * P.cpair_ptr.back()));
+  std::vector<int64_t> cur(P.cpair_ptr.begin(), P.cpair_ptr.end() - 1);
+  size_t x = 0;
+  for (const auto& rec : P.shared_rows)
+    for (size_t e = 0; e < rec.size(); e += 4, ++x) {
+      const int64_t at = cur[rid[x]]++;
+      P.cpair_rows[2 * at] = rec[e + 2];
+      P.cpair_rows[2 * at + 1] = rec[e + 3];
+    }
+  P.shared_rows.clear();
+  P.shared_rows.shrink_to_fit();
   return true;
 }
 

@@ -7,11 +7,103 @@
 // colind, part (concatenated instances) and the instance of every part.
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <random>
+#include <set>
 #include <vector>
 #include "../../paper_2107_09006_amd/csrc/plan.hpp"
 using namespace lsq2l;
 #define CHECK(c, ...) do { if (!(c)) { fprintf(stderr, "FAIL %s:%d: ", __FILE__, __LINE__); fprintf(stderr, __VA_ARGS__); fprintf(stderr, "\n"); exit(1); } } while (0)
+
+// the planner's host arrays live on the heap here
+namespace lsq2l {
+void* host_block_take(size_t bytes, size_t* got) { *got = bytes; return std::malloc(bytes); }
+void host_block_give(void* p, size_t) { std::free(p); }
+}  // namespace lsq2l
+
+// The index sets, envelopes, overlap map and shared-row pairs straight from
+// their definitions (sets of rows and columns), compared with the plan.
+static void check_against_definitions(int m, int n, int nparts, const std::vector<int32_t>& rp,
+                                      const std::vector<int32_t>& ci, const std::vector<int32_t>& part,
+                                      const std::vector<int32_t>& trp, const std::vector<int32_t>& tcol,
+                                      const HostPlan& H) {
+  std::vector<std::vector<int32_t>> interior(nparts), xi(nparts);
+  for (int j = 0; j < n; ++j) interior[part[j]].push_back(j);
+  std::vector<std::set<int32_t>> rowparts(m);
+  for (int r = 0; r < m; ++r) {
+    for (int e = rp[r]; e < rp[r + 1]; ++e) rowparts[r].insert(part[ci[e]]);
+    for (int i : rowparts[r]) xi[i].push_back(r);
+  }
+  std::vector<std::map<int32_t, int32_t>> posmap(nparts);   // column -> local position
+  for (int i = 0; i < nparts; ++i) {
+    const SubDesc& d = H.subs[i];
+    CHECK(d.nI == (int)interior[i].size() && d.nXi == (int)xi[i].size(), "sizes of sub %d", i);
+    for (int a = 0; a < d.nXi; ++a) CHECK(H.xi[d.xi_off + a] == xi[i][a], "Xi of sub %d", i);
+    std::set<int32_t> gam;
+    for (int r : xi[i])
+      for (int e = rp[r]; e < rp[r + 1]; ++e)
+        if (part[ci[e]] != i) gam.insert(ci[e]);
+    CHECK(d.nG == (int)gam.size(), "Gamma size of sub %d", i);
+    int g = 0;
+    for (int c : gam) CHECK(H.omega[d.omega_off + d.nI + g++] == c, "Gamma of sub %d", i);
+    for (int a = 0; a < d.nI; ++a) {
+      CHECK(H.omega[d.omega_off + a] == interior[i][a], "interior of sub %d", i);
+      posmap[i][interior[i][a]] = a;
+    }
+    g = 0;
+    for (int c : gam) posmap[i][c] = d.nIp + g++;
+    // envelope: every row holding a column of Omega_i couples its columns in Omega_i
+    std::set<int32_t> rows;
+    for (const auto& kv : posmap[i])
+      for (int k = trp[kv.first]; k < trp[kv.first + 1]; ++k) rows.insert(tcol[k]);
+    std::vector<int32_t> f(d.np);
+    for (int a = 0; a < d.np; ++a) f[a] = a;
+    for (int r : rows) {
+      std::vector<int32_t> q;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        auto it = posmap[i].find(ci[e]);
+        if (it != posmap[i].end()) q.push_back(it->second);
+      }
+      const int best = *std::min_element(q.begin(), q.end());
+      for (int x : q) f[x] = std::min(f[x], best);
+    }
+    for (int t = 0; t < d.ntiles; ++t) {
+      int mn = t * TS;
+      for (int a = t * TS; a < (t + 1) * TS; ++a) mn = std::min(mn, f[a]);
+      CHECK(H.tileF[d.tile_base + t] == mn / TS, "envelope of sub %d tile %d", i, t);
+    }
+  }
+  // overlap map: positions of every column, by increasing subdomain
+  std::vector<std::vector<int32_t>> own(n);
+  for (int i = 0; i < nparts; ++i)
+    for (const auto& kv : posmap[i]) own[kv.first].push_back((int32_t)(H.subs[i].loc_off + kv.second));
+  for (int j = 0; j < n; ++j) {
+    CHECK(H.own_ptr[j + 1] - H.own_ptr[j] == (int)own[j].size(), "own count of column %d", j);
+    for (size_t q = 0; q < own[j].size(); ++q) CHECK(H.own_pos[H.own_ptr[j] + q] == own[j][q], "own of column %d", j);
+  }
+  // shared rows of every pair i < j, pairs in order of first occurrence
+  std::map<std::pair<int, int>, std::vector<int32_t>> shared;
+  std::vector<std::pair<int, int>> first;
+  std::vector<std::map<int32_t, int32_t>> rank(nparts);
+  for (int i = 0; i < nparts; ++i)
+    for (size_t a = 0; a < xi[i].size(); ++a) rank[i][xi[i][a]] = (int32_t)a;
+  for (int r = 0; r < m; ++r)
+    for (int u : rowparts[r])
+      for (int v : rowparts[r]) {
+        if (v <= u) continue;
+        auto key = std::make_pair(u, v);
+        if (!shared.count(key)) first.push_back(key);
+        shared[key].push_back(rank[u][r]);
+        shared[key].push_back(rank[v][r]);
+      }
+  CHECK(H.cpair_ij.size() == 2 * first.size(), "pair count");
+  for (size_t k = 0; k < first.size(); ++k) {
+    CHECK(H.cpair_ij[2 * k] == first[k].first && H.cpair_ij[2 * k + 1] == first[k].second, "pair %zu", k);
+    const auto& rows = shared[first[k]];
+    CHECK(2 * (H.cpair_ptr[k + 1] - H.cpair_ptr[k]) == (int64_t)rows.size(), "rows of pair %zu", k);
+    for (size_t q = 0; q < rows.size(); ++q) CHECK(H.cpair_rows[2 * H.cpair_ptr[k] + q] == rows[q], "row of pair %zu", k);
+  }
+}
 
 int main(int argc, char** argv) {
   FILE* f = fopen(argv[1], "rb");
@@ -48,8 +140,9 @@ int main(int argc, char** argv) {
     printf("row order: permuted\n");
   }
   HostPlan H; std::string err;
-  CHECK(plan_build(m, n, rp.data(), ci.data(), trp.data(), tcol.data(), part.data(), nparts, sop, H, err), "%s", err.c_str());
-  CHECK(plan_maps(m, n, rp.data(), ci.data(), part.data(), H, err), "%s", err.c_str());
+  CHECK(plan_build(m, n, rp.data(), ci.data(), part.data(), nparts, sop, H, err), "%s", err.c_str());
+  CHECK(plan_maps(n, H, err), "%s", err.c_str());
+  check_against_definitions(m, n, nparts, rp, ci, part, trp, tcol, H);
   int64_t maxrows = 0;
   for (int i = 0; i < nparts; ++i) {
     const SubDesc& d = H.subs[i];
