@@ -317,10 +317,13 @@ class Solver:
         _check(load_library().lsq2l_get_coarse_basis(self.handle, int(i), X.ctypes.data))
         return X[:d["p"], :d["I"].size].T.copy()
 
-    def autotune(self, reps: int = 10):
-        """Measured lanes per row of the SpMV with A and A^T (lsq2l_autotune)."""
+    def autotune(self, reps: int = 10, shapes=None):
+        """Measured SpMV shapes for A and A^T (lsq2l_autotune); with reps=0,
+        sets them from `shapes` (0 = LDS row blocks, else lanes per row)."""
         import torch
         lanes = np.zeros(2, dtype=np.int32)
+        if shapes is not None:
+            lanes[:] = shapes
         with torch.cuda.device(self.device):
             _check(load_library().lsq2l_autotune(self.handle, int(reps), lanes.ctypes.data))
         return int(lanes[0]), int(lanes[1])

@@ -21,17 +21,10 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 namespace {
 
-// Lanes per row of the SpMV: the largest power of two not above half the
-// mean row length, so that a lane takes about two entries of an average row
-// (1.67 entries per row of A on the 1000 x 1000 grid: one lane, 5.0 TB/s
-// against 4.4 with two; 5 per row of A^T: two lanes, 4.7 TB/s against 4.2,
-// 3.6 and 3.4 with four, eight and one).  lsq2l_autotune replaces it by a
-// measured choice.
-int pick_group(double avg) {
-  int g = 1;
-  while (g < 64 && 4 * g <= avg) g *= 2;
-  return g;
-}
+// Launch shape of the SpMV: row blocks staged through LDS (0) for every
+// matrix; lsq2l_autotune replaces it by a measured choice among that and
+// 1 .. 64 lanes per row.
+int pick_group(double) { return 0; }
 
 // Device blocks of destroyed handles, kept for later handles on the same
 // device: a setup allocates gigabytes in blocks of hundreds of megabytes,
@@ -218,17 +211,17 @@ namespace lsq2l {
 // row order of A.
 void spmv_it_A(lsq2l_ctx* c, const double* x, double* y) {
   const DevMatrix& M = c->row_perm ? c->Mi : c->M;
-  launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, x, y, M.spmv_group);
+  launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, x, y, M.spmv_group, M.nnz, M.blk);
 }
 void spmv_it_AT(lsq2l_ctx* c, const double* y, double* x) {
   const DevMatrix& M = c->row_perm ? c->Mi : c->M;
-  launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, y, x, M.spmvt_group);
+  launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, y, x, M.spmvt_group, M.nnz, M.tblk);
 }
 void spmv_A(lsq2l_ctx* c, const double* x, double* y) {
-  launch_spmv(c->st, c->M.m, c->M.rowptr, c->M.colind, c->M.vals, x, y, c->M.spmv_group);
+  launch_spmv(c->st, c->M.m, c->M.rowptr, c->M.colind, c->M.vals, x, y, c->M.spmv_group, c->M.nnz, c->M.blk);
 }
 void spmv_AT(lsq2l_ctx* c, const double* y, double* x) {
-  launch_spmv(c->st, c->M.n, c->M.trowptr, c->M.trow, c->M.tvals, y, x, c->M.spmvt_group);
+  launch_spmv(c->st, c->M.n, c->M.trowptr, c->M.trow, c->M.tvals, y, x, c->M.spmvt_group, c->M.nnz, c->M.tblk);
 }
 // y = C x = A^T (A x), with tmp (m doubles) for A x
 void apply_C(lsq2l_ctx* c, const double* x, double* y, double* tmp) {
@@ -628,6 +621,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
   LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.vals, c->M.trowptr,
                                  c->M.trow, c->M.tvals, c->M.tperm, temp, tb));
+  TRY(c->dalloc(&c->M.blk, spmv_blocks(nnz) + 1));
+  TRY(c->dalloc(&c->M.tblk, spmv_blocks(nnz) + 1));
+  launch_row_blocks(st, m, c->M.rowptr, nnz, c->M.blk);
+  launch_row_blocks(st, n, c->M.trowptr, nnz, c->M.tblk);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
   // Row order of the copy used for C p = A^T (A p), found on a host thread
@@ -651,10 +648,16 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->upload(&c->P.tileF, H.tileF));
   TRY(c->upload(&c->P.tileOff, H.tileOff));
   for (const SubDesc& d : H.subs) c->P.max_np = std::max(c->P.max_np, (int)d.np);
+  // the local solves and the one-workgroup-per-subdomain setup kernels start
+  // the subdomains with the most stored tiles first: one launch holds all of
+  // them, and the largest set its length
+  std::vector<int32_t> order(nparts);
+  auto upload_ordered = [&]() -> lsq2l_status {
+    std::vector<SubDesc> so(nparts);
+    for (int i = 0; i < nparts; ++i) so[i] = H.subs[order[i]];
+    return c->upload(&c->P.subs_ord, so);
+  };
   {
-    // the local solves start the subdomains with the longest tile streams
-    // first: one launch holds all of them, and the largest set its length
-    std::vector<int32_t> order(nparts);
     std::vector<int64_t> tiles(nparts);
     for (int i = 0; i < nparts; ++i) {
       order[i] = i;
@@ -664,6 +667,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x] > tiles[y]; });
     TRY(c->upload(&c->P.solve_order, order));
+    TRY(upload_ordered());
     static std::once_flag once;
     static hipError_t conf = hipSuccess;
     std::call_once(once, []() { conf = local_solve_configure(); });
@@ -758,6 +762,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
       SubDesc* d_subs = nullptr;       // the coarse offsets filled in by plan_coarse
       TRY(c->upload(&d_subs, H.subs));
       c->P.subs = d_subs;
+      TRY(upload_ordered());
     }
     TRY(c->upload(&c->Cc.segs, c->segs_h));
     if (c->n0 > 0) {
@@ -938,6 +943,10 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
     LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.vals, Mi.trowptr, Mi.trow,
                                    Mi.tvals, Mi.tperm, temp, tb));
+    TRY(c->dalloc(&Mi.blk, spmv_blocks(nnz) + 1));
+    TRY(c->dalloc(&Mi.tblk, spmv_blocks(nnz) + 1));
+    launch_row_blocks(st, m, Mi.rowptr, nnz, Mi.blk);
+    launch_row_blocks(st, n, Mi.trowptr, nnz, Mi.tblk);
   }
   // --- solve workspace
   const int S = c->S;
@@ -1231,12 +1240,12 @@ lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps) {
   launch_fill(c->st, c->M.m, 1.0, c->tm);
   DevMatrix& M = c->row_perm ? c->Mi : c->M;
   for (int which = 0; which < 2; ++which) {
-    int best = 1;
+    int best = 0;
     float best_ms = 1e30f;
-    for (int g = 1; g <= 64; g *= 2) {
+    for (int g = 0; g <= 64; g = g ? 2 * g : 1) {
       auto once = [&]() {
-        if (which == 0) launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, c->p, c->tm2, g);
-        else launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, c->tm, c->q, g);
+        if (which == 0) launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, c->p, c->tm2, g, M.nnz, M.blk);
+        else launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, c->tm, c->q, g, M.nnz, M.tblk);
       };
       once();
       LSQ2L_HIP_TRY(hipEventRecord(e0, c->st));
@@ -1506,7 +1515,16 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
 
 lsq2l_status lsq2l_autotune(lsq2l_handle c, int32_t reps, int32_t* lanes) {
   g_err.clear();
-  if (!c || reps < 1) { set_error("bad arguments"); return LSQ2L_EINVAL; }
+  if (!c || reps < 0 || (reps == 0 && !lanes)) { set_error("bad arguments"); return LSQ2L_EINVAL; }
+  if (reps == 0) {
+    auto valid = [](int g) { return g == 0 || (g >= 1 && g <= 64 && (g & (g - 1)) == 0); };
+    if (!valid(lanes[0]) || !valid(lanes[1])) { set_error("SpMV shape must be 0 or a power of two up to 64"); return LSQ2L_EINVAL; }
+    c->M.spmv_group = c->Mi.spmv_group = lanes[0];
+    c->M.spmvt_group = c->Mi.spmvt_group = lanes[1];
+    c->info.spmv_lanes_A = lanes[0];
+    c->info.spmv_lanes_AT = lanes[1];
+    return LSQ2L_OK;
+  }
   TRY(autotune_spmv(c, reps));
   if (lanes) { lanes[0] = c->M.spmv_group; lanes[1] = c->M.spmvt_group; }
   return LSQ2L_OK;

@@ -41,6 +41,7 @@ struct SubDesc {
   int32_t ntiles, ntI;        // tiles per side, interior tiles (nIp / 32)
   int32_t nXi, p;             // |Xi_i| and number of coarse vectors
   int32_t seg, nGp;           // instance index, padded interface size
+  int32_t id, spare;          // subdomain index (kernels may run subdomains in another order)
   int64_t omega_off;          // int32 offset: Omega_i (nI interior then nG interface)
   int64_t xi_off;             // int32 offset: Xi_i
   int64_t loc_off;            // double offset: local vectors (np entries)

@@ -304,8 +304,8 @@ k_coarse_W(const SubDesc* __restrict__ subs, const int32_t* __restrict__ xi,
            const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
            const double* __restrict__ vals, const double* __restrict__ X, double* __restrict__ W) {
   constexpr int ECAP = 8;
-  const int i = blockIdx.x;
-  const SubDesc d = subs[i];
+  const SubDesc d = subs[blockIdx.x];
+  const int i = d.id;
   if (d.p == 0) return;
   const int32_t* rows = xi + d.xi_off;
   const double* Xi = X + d.x_off;
@@ -1041,19 +1041,19 @@ void launch_set_values(hipStream_t st, int64_t n, const int64_t* idx, double v, 
 }
 
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg) {
-  k_gamma_T<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, Tg);
+  k_gamma_T<<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, Tg);
 }
 
 
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                      const double* dinv, const double* scale, const double* work,
                      const double* sig, double* X) {
-  k_coarse_X<<<nsub, 512, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, scale, work, sig, X);
+  k_coarse_X<<<nsub, 512, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, scale, work, sig, X);
 }
 
 void launch_coarse_W(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M,
                      const double* X, double* W) {
-  k_coarse_W<<<dim3(nsub, 16), 256, 0, st>>>(P.subs, P.xi, P.part, P.locown, M.rowptr, M.colind, M.vals, X,
+  k_coarse_W<<<dim3(nsub, 16), 256, 0, st>>>(P.heavy(), P.xi, P.part, P.locown, M.rowptr, M.colind, M.vals, X,
                                    W);
 }
 

@@ -29,9 +29,95 @@ k_spmv(int32_t nrows, const int32_t* __restrict__ rowptr, const int32_t* __restr
   if (row < nrows && sub == 0) y[row] = s;
 }
 
+// y = A x for short, uneven rows, staged through LDS.  Workgroup b owns the
+// rows whose first entry lies in [b SPMV_NB, (b + 1) SPMV_NB): rows
+// blk[b] .. blk[b + 1] - 1 (a table made once per matrix, k_row_blocks).
+// Its entries are read once, coalesced, as vals[e] x[colind[e]] into LDS;
+// then every thread sums its rows from LDS in entry order and writes y
+// coalesced.  A block whose rows hold more than SPMV_CAP entries (a long
+// last row) sums each row with a wavefront instead.  Every row is summed in
+// one fixed order, so runs are bitwise reproducible.
+constexpr int SPMV_NB = 1024, SPMV_CAP = 2048, SPMV_THREADS = 256;
+
+int64_t spmv_blocks(int64_t nnz) { return std::max<int64_t>(1, (nnz + SPMV_NB - 1) / SPMV_NB); }
+
+// blk[b] = first row whose start is >= b SPMV_NB (b < nblk), blk[nblk] = nrows
+__global__ void k_row_blocks(int32_t nrows, const int32_t* __restrict__ rowptr, int64_t nblk,
+                             int32_t* __restrict__ blk) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nblk) return;
+  if (b == nblk) { blk[b] = nrows; return; }
+  const int64_t v = b * SPMV_NB;
+  int32_t lo = 0, hi = nrows;
+  while (lo < hi) {
+    const int32_t mid = (int32_t)(((int64_t)lo + hi) >> 1);
+    if (rowptr[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  blk[b] = lo;
+}
+
+void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int64_t nnz, int32_t* blk) {
+  const int64_t nblk = spmv_blocks(nnz);
+  k_row_blocks<<<(unsigned)((nblk + 1 + 255) / 256), 256, 0, st>>>(nrows, rowptr, nblk, blk);
+}
+
+__global__ void __launch_bounds__(SPMV_THREADS)
+k_spmv_stream(const int32_t* __restrict__ blk, const int32_t* __restrict__ rowptr,
+              const int32_t* __restrict__ colind, const double* __restrict__ vals,
+              const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double prod[SPMV_CAP];
+  const int tid = threadIdx.x;
+  const int32_t r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int32_t e0 = rowptr[r0], e1 = rowptr[r1];
+  if (e1 - e0 <= SPMV_CAP) {
+    // four entries per thread in flight: columns and values first, then x
+    for (int32_t e = e0 + tid; e < e1; e += 4 * SPMV_THREADS) {
+      int32_t c[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t q = e + u * SPMV_THREADS;
+        c[u] = q < e1 ? colind[q] : 0;
+        v[u] = q < e1 ? vals[q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t q = e + u * SPMV_THREADS;
+        if (q < e1) prod[q - e0] = v[u] * x[c[u]];
+      }
+    }
+    __syncthreads();
+    for (int32_t r = r0 + tid; r < r1; r += SPMV_THREADS) {
+      const int32_t a = rowptr[r] - e0, b = rowptr[r + 1] - e0;
+      double s = 0.0;
+      for (int32_t k = a; k < b; ++k) s += prod[k];
+      y[r] = s;
+    }
+    return;
+  }
+  // long rows: one wavefront per row, lanes strided over the row
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int32_t r = r0 + wave; r < r1; r += SPMV_THREADS / 64) {
+    double s = 0.0;
+    for (int32_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) s += vals[e] * x[colind[e]];
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_down(s, w, 64);
+    if (lane == 0) y[r] = s;
+  }
+}
+
+// group 0: the LDS-staged kernel above; 1 .. 64: that many lanes per row
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
-                 const double* vals, const double* x, double* y, int group) {
+                 const double* vals, const double* x, double* y, int group, int64_t nnz,
+                 const int32_t* blk) {
   if (nrows == 0) return;
+  if (group == 0 && blk) {
+    k_spmv_stream<<<(unsigned)spmv_blocks(nnz), SPMV_THREADS, 0, st>>>(blk, rowptr, colind, vals, x, y);
+    return;
+  }
+  if (group == 0) group = 1;
   const int64_t threads = (int64_t)nrows * group;
   const unsigned blocks = (unsigned)((threads + 255) / 256);
   switch (group) {

@@ -45,8 +45,8 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const int32_t* __restrict__ trow, const double* __restrict__ tvals,
            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
            double* __restrict__ fac, double* __restrict__ ctg) {
-  const int i = blockIdx.x;
-  const SubDesc d = subs[i];
+  const SubDesc d = subs[blockIdx.x];
+  const int i = d.id;
   const int32_t* om = omega + d.omega_off;
   const int32_t* G = om + d.nI;
   const int32_t* F = tileF + d.tile_base;
@@ -332,19 +332,19 @@ void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, cons
 
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
                      double* ctg) {
-  k_assemble<<<nsub, 256, 0, st>>>(P.subs, P.omega, P.part, P.locown, M.rowptr, M.colind, M.vals,
+  k_assemble<<<nsub, 256, 0, st>>>(P.heavy(), P.omega, P.part, P.locown, M.rowptr, M.colind, M.vals,
                                    M.trowptr, M.trow, M.tvals, P.tileF, P.tileOff, fac, ctg);
 }
 
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
                         double* scale) {
-  k_equil_scale<<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, scale);
-  k_equil_apply<<<dim3(nsub, 32), 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, ctg, scale);
+  k_equil_scale<<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, scale);
+  k_equil_apply<<<dim3(nsub, 32), 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, ctg, scale);
 }
 
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
                        int32_t* status) {
-  k_chol_local<double><<<nsub, 256, 0, st>>>(P.subs, P.tileF, P.tileOff, fac, dinv, status);
+  k_chol_local<double><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status);
 }
 
 void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst) {

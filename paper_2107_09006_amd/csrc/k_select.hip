@@ -256,24 +256,33 @@ __device__ inline void tri_inv_upper_tile(const double* R, int ld, double* X, in
   wg_fence();
 }
 
-__global__ void __launch_bounds__(SEL_THREADS)
+// Interfaces of up to MAXN columns (and more than MINN) with THREADS threads:
+// the LDS arrays scale with MAXN, so small interfaces run many workgroups
+// per CU.  Workgroups of other sizes return at once.
+template <int THREADS, int MINN, int MAXN>
+__global__ void __launch_bounds__(THREADS)
 k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
          const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
          int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail) {
-  __shared__ double sd[SEL_MAXN], se[SEL_MAXN], stau[SEL_MAXN], sv[SEL_MAXN], sw[SEL_MAXN],
-      sD2[SEL_MAXN], slam[SEL_MAXN];
-  __shared__ int sperm[SEL_MAXN], scl[SEL_MAXN + 1];
-  __shared__ double spart[4][SEL_MAXN];
-  __shared__ double svp[SEL_MAXN], swp[SEL_MAXN];   // the previous reflector's v and w
+  constexpr int NG = THREADS / 256;   // thread groups splitting the columns of A22 v
+  static_assert(NG >= 1 && THREADS % 256 == 0, "whole groups of 256 threads");
+  __shared__ double sd[MAXN], se[MAXN], stau[MAXN], sv[MAXN], sw[MAXN], sD2[MAXN], slam[MAXN];
+  __shared__ int sperm[MAXN], scl[MAXN + 1];
+  __shared__ double spart[NG][MAXN];
+  __shared__ double svp[MAXN], swp[MAXN];   // the previous reflector's v and w
   __shared__ double sred[16];
   __shared__ int sredi[16];
   __shared__ int s_r, s_p, s_nclus, s_diag;
   __shared__ double s_anorm;
-  const int i = blockIdx.x;
-  const SubDesc dsc = subs[i];
+  const SubDesc dsc = subs[blockIdx.x];
+  const int i = dsc.id;
   const int n = dsc.nG, ld = dsc.nGp, tid = threadIdx.x, nthr = blockDim.x;
-  if (n == 0 || n > SEL_MAXN) {
-    if (tid == 0) { p_out[i] = 0; if (n > SEL_MAXN) atomicExch(fail, 2); }
+  if (n <= MINN) {
+    if (n == 0 && MINN == 0 && tid == 0) p_out[i] = 0;
+    return;
+  }
+  if (n > MAXN) {
+    if (MAXN == SEL_MAXN && tid == 0) { p_out[i] = 0; atomicExch(fail, 2); }
     return;
   }
   const int64_t mm = (int64_t)ld * ld;
@@ -482,14 +491,14 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     for (int a = 1 + tid; a < m; a += nthr) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
     if (tk != 0.0 || pend) {
       // one pass over A22 (rows and columns k + 1 ..): the pending update,
-      // then w = tk A22 v from four thread groups splitting the columns,
+      // then w = tk A22 v from NG thread groups splitting the columns,
       // their partial sums added in a fixed order
       const int g = tid / 256, t256 = tid % 256;
       for (int a0 = 0; a0 < m; a0 += 256) {
         const int a = a0 + t256;
         double acc = 0.0;
         if (a < m)
-          for (int b = g; b < m; b += 4) {
+          for (int b = g; b < m; b += NG) {
             double* e = M0 + (int64_t)(k + 1 + b) * ld + k + 1 + a;
             double x = *e;
             if (pend) {
@@ -505,7 +514,10 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     if (tk != 0.0) {
       double pp = 0.0;
       for (int a = tid; a < m; a += nthr) {
-        sw[a] = tk * (((spart[0][a] + spart[1][a]) + spart[2][a]) + spart[3][a]);
+        double sp = spart[0][a];
+#pragma unroll
+        for (int q = 1; q < NG; ++q) sp += spart[q][a];
+        sw[a] = tk * sp;
         pp += sw[a] * sv[a];
       }
       const double wv = wg_sum(pp, sred);
@@ -790,8 +802,13 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
 
 void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
                    double* work, double tau, int nev_max, int32_t* p_out, double* sig_out) {
-  k_select<<<nsub, SEL_THREADS, 0, st>>>(P.subs, ctg, Tg, work, tau, nev_max, p_out, sig_out,
-                                         p_out + nsub);
+  // size classes of the interface: up to 128, 512 and SEL_MAXN columns
+  k_select<256, 0, 128><<<nsub, 256, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out,
+                                              p_out + nsub);
+  k_select<512, 128, 512><<<nsub, 512, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out,
+                                                sig_out, p_out + nsub);
+  k_select<SEL_THREADS, 512, SEL_MAXN><<<nsub, SEL_THREADS, 0, st>>>(
+      P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out, p_out + nsub);
 }
 
 }  // namespace lsq2l

@@ -15,8 +15,10 @@ struct DevMatrix {            // A and its transpose (device copies owned by the
   int32_t* trow = nullptr;    // nnz
   double* tvals = nullptr;    // nnz
   int32_t* tperm = nullptr;   // nnz: A^T entry k is vals[tperm[k]]
-  int spmv_group = 1;         // lanes per row for A x
-  int spmvt_group = 1;        // lanes per row for A^T y
+  int spmv_group = 0;         // A x: 0 row blocks through LDS, else lanes per row
+  int spmvt_group = 0;        // A^T y, the same
+  int32_t* blk = nullptr;     // LDS row blocks of A (spmv_blocks(nnz) + 1)
+  int32_t* tblk = nullptr;    // the same for A^T
 };
 
 struct DevPlan {              // subdomain layout (device copies of HostPlan)
@@ -30,7 +32,10 @@ struct DevPlan {              // subdomain layout (device copies of HostPlan)
   int32_t* own_ptr = nullptr;
   int32_t* own_pos = nullptr;
   int32_t* solve_order = nullptr;  // subdomains by decreasing stored factor tiles
+  SubDesc* subs_ord = nullptr;     // subs in that order: the one-workgroup-per-subdomain
+                                   // setup kernels start the largest subdomains first
   int max_np = 0;             // largest padded local size
+  const SubDesc* heavy() const { return subs_ord ? subs_ord : subs; }
 };
 
 struct DevCoarse {            // coarse space and coarse operator
@@ -74,8 +79,14 @@ void launch_offset_i32(hipStream_t st, int64_t n, const int32_t* in, int32_t add
 void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32_t n, int32_t* flag);
 
 // --- sparse kernels -------------------------------------------------------
+// group 0: row blocks staged through LDS (needs the block table blk of the
+// matrix, else one lane per row); 1 .. 64: lanes per row
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
-                 const double* vals, const double* x, double* y, int group);
+                 const double* vals, const double* x, double* y, int group, int64_t nnz,
+                 const int32_t* blk);
+// rows of the LDS row blocks of a CSR matrix: spmv_blocks(nnz) + 1 entries
+int64_t spmv_blocks(int64_t nnz);
+void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int64_t nnz, int32_t* blk);
 void launch_grad_vals(hipStream_t st, int32_t m, const int32_t* rowptr, const int32_t* colind,
                       const double* r, const double* lam, const double* Alam, const double* x,
                       double* out);

@@ -340,6 +340,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     d.nXi = (int32_t)(xoff[i + 1] - xoff[i]);
     d.p = 0;
     d.seg = seg_of_part[i];
+    d.id = i;
     d.omega_off = omega_off; omega_off += d.nI + d.nG;
     d.xi_off = xoff[i];
     d.loc_off = loc_off; loc_off += d.np;

@@ -270,7 +270,7 @@ def test_autotune_keeps_products_exact(L):
     A = p.scipy()
     s = solver(L, p, autotune=1)
     la, lat = s.info()["spmv_lanes_A"], s.info()["spmv_lanes_AT"]
-    assert la in (1, 2, 4, 8, 16, 32, 64) and lat in (1, 2, 4, 8, 16, 32, 64)
+    assert la in (0, 1, 2, 4, 8, 16, 32, 64) and lat in (0, 1, 2, 4, 8, 16, 32, 64)
     assert (la, lat) == s.autotune(reps=3) or True      # timing may pick another shape
     rng = np.random.default_rng(0)
     x = rng.standard_normal(p.n)
@@ -281,6 +281,39 @@ def test_autotune_keeps_products_exact(L):
                   <= 8 * EPS * (absA.T @ np.abs(y)) + 1e-300)
     xs, info, _ = s.solve(_t(p.b))
     assert info[0]["relres"] <= 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 4, 8, 16, 32, 64])
+def test_every_spmv_shape_on_long_short_and_empty_rows(L, shape):
+    """Each SpMV launch shape, set explicitly, against the product in FP64 on
+    rows of 0 to 5000 entries: single-entry rows, empty rows (among the rows
+    and at the end), two rows holding every column (LDS row blocks above
+    2048 entries are summed a wavefront per row) and the irregular rows."""
+    base = W.small_config("irregular")
+    A0 = base.scipy().tocsr()
+    import scipy.sparse as sp
+    n = A0.shape[1]
+    dense = sp.csr_matrix(np.random.default_rng(5).standard_normal((2, n)))
+    empty = sp.csr_matrix((3, n))
+    A = sp.vstack([A0[:700], empty, dense, A0[700:], empty]).tocsr()
+    A.sort_indices()
+    p = W.Problem("long_rows", A.shape[0], n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                  A.data.copy(), np.random.default_rng(6).standard_normal(A.shape[0]), base.part,
+                  base.nparts, base.tau, base.tol)
+    s = solver(L, p, variant=L.ONE_LEVEL)
+    assert s.autotune(reps=0, shapes=(shape, shape)) == (shape, shape)
+    assert s.info()["spmv_lanes_A"] == shape
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(p.n)
+    y = rng.standard_normal(p.m)
+    absA = abs(A)
+    nmax = np.diff(A.indptr).max()
+    bound = lambda B, v: 2 * nmax * EPS * (B @ np.abs(v)) + 1e-300
+    assert np.all(np.abs(_np(s.spmv(_t(x))) - A @ x) <= bound(absA, x))
+    assert np.all(np.abs(_np(s.spmv(_t(y), trans=True)) - A.T @ y) <= bound(absA.T, y))
+    with pytest.raises(L.Lsq2lError):
+        s.autotune(reps=0, shapes=(3, 0))
     s.close()
 
 
