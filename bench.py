@@ -43,7 +43,9 @@ CALIB_BYTES = 1 << 30          # plain device copy used to calibrate HBM counter
 # counter's reading for the calibration copy (profiles/local_solve_banded_batch_64.md).
 # It describes the kernel source whose SHA-256 is given; for any other source
 # the figure is reported as null.
-TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip", "sha256": None, "bytes": None}
+TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip",
+           "sha256": "da04858b38577bc7de35eff16cadc58e82464cb70e3e265cd2ab3a192317270f",
+           "bytes": 2869024.35 * 1024 * 2.0 + 25203.25 * 1024 * 1.0}
 
 
 def log(*a):
