@@ -307,7 +307,12 @@ def main():
         "setup_ms": round(fp64["setup_ms"], 2),
         "solve_ms": round(fp64["solve_ms"], 2),
         "setup_phases_ms": {k: round(fp64["setup"][k], 2) for k in
-                            ["t_plan_ms", "t_assemble_ms", "t_factor_ms", "t_eigen_ms", "t_coarse_ms"]},
+                            ["t_prepare_ms", "t_plan_ms", "t_assemble_ms", "t_factor_ms", "t_eigen_ms",
+                             "t_coarse_ms"]},
+        "solve_factor": {"tiles": fp64["setup"]["factor_tiles"],
+                         "split_order_tiles": fp64["setup"]["split_tiles"],
+                         "subdomains_in_global_order": fp64["setup"]["solve_permuted"],
+                         "mixed_fp32_factor_fallback": mixed["setup"]["mixed_fallback"]},
         "n0": fp64["setup"]["n0"],
         "mixed_ms_per_step": round(mixed["ms_per_step"], 2),
         "mixed_iterations_max": mixed["iterations_max"],

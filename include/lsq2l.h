@@ -92,11 +92,15 @@ enum { LSQ2L_PCG = 0, LSQ2L_LSQR = 1, LSQ2L_GMRES = 2 };
 typedef struct {
   double  tol;        /* stopping tolerance of the Krylov method (default 1e-8)                  */
   int32_t max_it;     /* iteration limit (default 10000)                                          */
-  int32_t precision;  /* LSQ2L_FP64: everything in double.  LSQ2L_MIXED: the local triangular
-                         solves read a float copy of the (double) local factors, and the coarse
-                         restriction and prolongation a float copy of the (double) coarse basis
-                         (E is built from the double basis); all accumulation, recurrences, dot
-                         products, residuals and the coarse solve stay double                   */
+  int32_t precision;  /* LSQ2L_FP64: everything in double.  LSQ2L_MIXED: the local factors the
+                         triangular solves use are computed in float (FP32 MFMA Cholesky of a
+                         float copy of the equilibrated C_ii, FP32 accumulation) and the solves
+                         run in float; the coarse restriction and prolongation read a float
+                         copy of the (double) coarse basis (E is built from the double basis).
+                         The coarse selection (eq. gevp), E, the coarse solve, recurrences, dot
+                         products and residuals stay double.  If a float factorization meets a
+                         non-positive pivot, every solve factor is computed in double and
+                         rounded to float instead (lsq2l_setup_info.mixed_fallback = 1)        */
   int32_t flexible;   /* PCG: 1 = flexible beta = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k)        */
   int32_t variant;    /* LSQ2L_ADDITIVE, ONE_LEVEL, BALANCED, RAS or DEFLATED (above); a
                          nonsymmetric variant with PCG or LSQR returns LSQ2L_EINVAL              */
@@ -115,8 +119,16 @@ typedef struct {
   int32_t autotune;   /* 1: time the candidate launch shapes of the SpMV on this matrix at setup
                          and keep the fastest (see lsq2l_autotune); 0 (default): the built-in
                          choice                                                                  */
-  int32_t reserved;
+  int32_t solve_order;/* order of Omega_i in the factors the local solves of M use (C_ii^{-1} r
+                         does not depend on it): LSQ2L_ORDER_AUTO (default) takes, per
+                         subdomain, the global-column order when its tile envelope is at most
+                         0.85 of that of [Omega_Ii, Omega_Gamma_i] (the order the coarse
+                         selection factors C_ii in); LSQ2L_ORDER_SPLIT keeps [Omega_Ii,
+                         Omega_Gamma_i] everywhere, LSQ2L_ORDER_GLOBAL takes the global-column
+                         order everywhere                                                      */
 } lsq2l_options;
+
+enum { LSQ2L_ORDER_AUTO = 0, LSQ2L_ORDER_SPLIT = 1, LSQ2L_ORDER_GLOBAL = 2 };
 
 typedef struct {
   int32_t iterations;     /* Krylov iterations performed (per instance for batched handles)  */
@@ -138,13 +150,16 @@ typedef struct {
   int64_t n0;             /* coarse dimension sum_i p_i                                  */
   int32_t max_ni;         /* largest overlapping subdomain |Omega_i|                     */
   int32_t max_p;          /* largest p_i                                                 */
-  int64_t factor_bytes;   /* device bytes of the local factors (stored tiles)            */
+  int64_t factor_bytes;   /* device bytes of the factors the local solves read (stored
+                             tiles, float in LSQ2L_MIXED)                                */
   int64_t factor_dense_bytes; /* what dense lower-triangular local factors would take   */
-  int64_t factor_tiles;   /* number of stored 32 x 32 factor tiles                       */
+  int64_t factor_tiles;   /* stored 32 x 32 tiles of the factors the local solves read   */
   int64_t factor_nnz_min; /* sum_i nnz(L_i): entries of the local Cholesky factors under
-                             a fill-reducing order of each Omega_i that keeps Omega_Gamma_i
-                             last (symbolic factorization; the algorithmic minimum the local
-                             solves must read)                                             */
+                             a fill-reducing order of each Omega_i, the fewest of a
+                             nested-dissection order, the global column order and
+                             [Omega_Ii, Omega_Gamma_i] (symbolic factorization; the
+                             algorithmic minimum the local solves must read); -1 until
+                             lsq2l_time_kernel computed it                               */
   double  shift;          /* s = diag_shift_rel ||C||_F actually applied (0 if none)     */
   double  t_plan_ms;      /* index sets, envelopes, transposition (host + device)        */
   double  t_assemble_ms;  /* local matrices C_ii, Ct_GG, equilibration                  */
@@ -156,6 +171,11 @@ typedef struct {
   int32_t spmv_lanes_AT;  /* the same for A^T                                              */
   double  t_prepare_ms;   /* reading, concatenating and validating the input (before
                              t_total_ms starts)                                         */
+  int64_t split_tiles;    /* stored tiles of the factors in [Omega_Ii, Omega_Gamma_i] order
+                             (the coarse selection's)                                   */
+  int32_t solve_permuted; /* subdomains whose solve factor is in global-column order     */
+  int32_t mixed_fallback; /* LSQ2L_MIXED: 1 if the solve factors were computed in double
+                             after a float factorization broke down                     */
 } lsq2l_setup_info;
 
 /* One least-squares instance for lsq2l_setup_batched. */

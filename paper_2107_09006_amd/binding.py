@@ -20,6 +20,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN = 0, 1, -
 FP64, MIXED = 0, 1
 ADDITIVE, ONE_LEVEL, BALANCED, RAS, DEFLATED = 0, 1, 2, 3, 4
 PCG, LSQR, GMRES = 0, 1, 2
+ORDER_AUTO, ORDER_SPLIT, ORDER_GLOBAL = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
                 -4: "CHOL_BREAKDOWN", -5: "PCG_BREAKDOWN"}
@@ -38,7 +39,7 @@ class Options(C.Structure):
                 ("flexible", C.c_int32), ("variant", C.c_int32), ("nev_max", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("krylov", C.c_int32),
                 ("restart", C.c_int32), ("diag_shift_rel", C.c_double),
-                ("adjoint_tol", C.c_double), ("autotune", C.c_int32), ("reserved", C.c_int32)]
+                ("adjoint_tol", C.c_double), ("autotune", C.c_int32), ("solve_order", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -60,7 +61,8 @@ class SetupInfo(C.Structure):
                 ("t_factor_ms", C.c_double), ("t_eigen_ms", C.c_double),
                 ("t_coarse_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("spmv_lanes_A", C.c_int32), ("spmv_lanes_AT", C.c_int32),
-                ("t_prepare_ms", C.c_double)]
+                ("t_prepare_ms", C.c_double), ("split_tiles", C.c_int64),
+                ("solve_permuted", C.c_int32), ("mixed_fallback", C.c_int32)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

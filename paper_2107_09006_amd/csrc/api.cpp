@@ -195,7 +195,11 @@ lsq2l_ctx::~lsq2l_ctx() {
   if (st) (void)hipStreamSynchronize(st);
   else (void)hipDeviceSynchronize();
   release_staged();
+  if (st2) (void)hipStreamSynchronize(st2);
   if (gst) (void)hipStreamDestroy(gst);
+  if (st2) (void)hipStreamDestroy(st2);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
   for (const DevBlock& b : dev_allocs) cache_give(b.p, b.bytes, b.dev);
   for (void* v : host_allocs) (void)hipHostFree(v);
 }
@@ -231,7 +235,9 @@ void apply_C(lsq2l_ctx* c, const double* x, double* y, double* tmp) {
 
 void local_solves(lsq2l_ctx* c) {
   if (c->opt.precision == LSQ2L_MIXED)
-    launch_local_solve_f32(c->st, c->nsub, c->P, c->fac32, c->dinv32, c->loc);
+    launch_local_solve_f32(c->st, c->nsub, c->Ps, c->fac32, c->dinv32, c->loc);
+  else if (c->solve_plan)
+    launch_local_solve(c->st, c->nsub, c->Ps, c->sfac, c->sdinv, c->loc);
   else
     launch_local_solve(c->st, c->nsub, c->P, c->fac, c->dinv, c->loc);
 }
@@ -601,6 +607,111 @@ struct JoiningThread {
 
 lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps);
 
+// Layout of the factors the local solves read.  C_ii^{-1} r does not depend
+// on the order of Omega_i; the order [Omega_Ii, Omega_Gamma_i] that the
+// coarse selection needs makes the interface rows of L_i dense across the
+// interior.  Per subdomain, the global-column order of Omega_i is taken
+// when its tile envelope (found from the assembled C_ii by k_solve_env) has
+// at most 0.85 of the tiles of the [I, Gamma] one (opt.solve_order may force
+// either).  The mixed path always gets a solve layout (its float factors are
+// computed on their own); the FP64 path only when some subdomain is
+// permuted, else it solves with the selection's factors.  On return the
+// layout Ps is on the device, the gather of its matrix into *s64 (double)
+// is enqueued, and c->solve_plan tells whether it is used.  Called with the
+// assembled, equilibrated C_ii in c->fac.
+lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
+  const hipStream_t st = c->st;
+  const HostPlan& H = c->H;
+  const int nsub = c->nsub;
+  const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  *s64 = nullptr;
+  c->solve_plan = false;
+  c->info.split_tiles = H.total_fac / TT;
+  c->info.solve_permuted = 0;
+  if (!mixed && c->opt.solve_order == LSQ2L_ORDER_SPLIT) return LSQ2L_OK;
+  // global-order layouts: np = roundup(n_i), local-vector slices of
+  // max(np, [I, Gamma] np) entries
+  std::vector<SubDesc> g(H.subs.begin(), H.subs.end());
+  int64_t tb = 0, lo = 0;
+  for (SubDesc& d : g) {
+    const int32_t np_main = d.np;
+    d.np = (d.nI + d.nG + TS - 1) / TS * TS;
+    d.ntiles = d.np / TS;
+    d.tile_base = tb; tb += d.ntiles;
+    d.loc_off = lo; lo += std::max(np_main, d.np);
+  }
+  SubDesc* d_g = nullptr;
+  int32_t *inv = nullptr, *Fg = nullptr;
+  TRY(c->upload(&d_g, g));
+  TRY(c->dalloc(&inv, H.total_loc));
+  TRY(c->dalloc(&Fg, std::max<int64_t>(tb, 1)));
+  launch_solve_inv(st, nsub, c->P, inv);
+  launch_solve_env(st, nsub, c->P, d_g, c->fac, inv, Fg);
+  std::vector<int32_t> hF((size_t)tb);
+  if (tb) LSQ2L_HIP_TRY(hipMemcpyAsync(hF.data(), Fg, sizeof(int32_t) * tb, hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+  // choose per subdomain, then the layout's offsets
+  std::vector<SubDesc> s(g);
+  std::vector<int32_t> sF;
+  std::vector<int64_t> sOff, tiles(nsub);
+  int64_t ftiles = 0, dtiles = 0, stb = 0, split_tiles = 0;
+  int permuted = 0;
+  for (int i = 0; i < nsub; ++i) {
+    const SubDesc& m = H.subs[i];
+    int64_t tm = 0, tg = 0;
+    for (int32_t t = 0; t < m.ntiles; ++t) tm += t - H.tileF[m.tile_base + t] + 1;
+    for (int32_t t = 0; t < g[i].ntiles; ++t) tg += t - hF[g[i].tile_base + t] + 1;
+    split_tiles += tm;
+    const int order = c->opt.solve_order;
+    const bool use_g = order == LSQ2L_ORDER_GLOBAL || (order == LSQ2L_ORDER_AUTO && tg * 100 <= tm * 85);
+    SubDesc& d = s[i];
+    d.np = use_g ? g[i].np : m.np;
+    d.ntiles = use_g ? g[i].ntiles : m.ntiles;
+    d.spare = use_g ? 1 : 0;
+    d.tile_base = stb; stb += d.ntiles;
+    d.fac_off = ftiles * TT;
+    d.dinv_off = dtiles * TT; dtiles += d.ntiles;
+    int64_t run = 0;
+    for (int32_t t = 0; t < d.ntiles; ++t) {
+      const int32_t f = use_g ? hF[g[i].tile_base + t] : H.tileF[m.tile_base + t];
+      sF.push_back(f);
+      sOff.push_back(run);
+      run += t - f + 1;
+    }
+    ftiles += run;
+    tiles[i] = run;
+    permuted += use_g;
+  }
+  c->info.split_tiles = split_tiles;
+  c->info.solve_permuted = permuted;
+  if (!mixed && permuted == 0) return LSQ2L_OK;
+  c->solve_plan = true;
+  c->s_total_fac = ftiles * TT;
+  c->s_total_dinv = dtiles * TT;
+  c->s_total_tiles = stb;
+  c->s_total_np = 0;
+  DevPlan& Ps = c->Ps;
+  Ps.max_np = 0;
+  for (const SubDesc& d : s) { c->s_total_np += d.np; Ps.max_np = std::max(Ps.max_np, (int)d.np); }
+  std::vector<int32_t> order(nsub);
+  for (int i = 0; i < nsub; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x] > tiles[y]; });
+  std::vector<SubDesc> so(nsub);
+  for (int i = 0; i < nsub; ++i) so[i] = s[order[i]];
+  TRY(c->upload(&Ps.subs, s));
+  TRY(c->upload(&Ps.subs_ord, so));
+  TRY(c->upload(&Ps.solve_order, order));
+  TRY(c->upload(&Ps.tileF, sF));
+  TRY(c->upload(&Ps.tileOff, sOff));
+  TRY(c->dalloc(&Ps.sperm, std::max<int64_t>(lo, 1)));
+  launch_fill_i32(st, lo, -1, Ps.sperm);
+  launch_solve_perm(st, nsub, c->P, Ps.subs, inv, Ps.sperm);
+  if (Ps.max_np > 12544) TRY(c->dalloc(&Ps.yscratch, std::max<int64_t>(lo, 1)));
+  TRY(c->dalloc(s64, std::max<int64_t>(c->s_total_fac, 1)));
+  launch_gather_solve(st, nsub, c->P, Ps, c->fac, *s64);
+  return LSQ2L_OK;
+}
+
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const HostVec<int32_t>& part, int32_t nparts,
@@ -621,8 +732,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->dalloc(&temp, (int64_t)std::max<size_t>(tb, 1)));
   LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, c->M.rowptr, c->M.colind, c->M.vals, c->M.trowptr,
                                  c->M.trow, c->M.tvals, c->M.tperm, temp, tb));
-  TRY(c->dalloc(&c->M.blk, spmv_blocks(nnz) + 1));
-  TRY(c->dalloc(&c->M.tblk, spmv_blocks(nnz) + 1));
+  TRY(c->dalloc(&c->M.blk, spmv_table_len(nnz)));
+  TRY(c->dalloc(&c->M.tblk, spmv_table_len(nnz)));
   launch_row_blocks(st, m, c->M.rowptr, nnz, c->M.blk);
   launch_row_blocks(st, n, c->M.trowptr, nnz, c->M.tblk);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
@@ -710,19 +821,78 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     if (c->shift > 0.0) launch_add_diag(st, nparts, c->P, c->shift, c->fac);
   }
   launch_equilibrate(st, nparts, c->P, c->fac, c->ctg, c->scale);
+  // the layout of the solve factors and the gather of its matrix (before
+  // c->fac is factored in place)
+  double* s64 = nullptr;
+  TRY(solve_layout(c, &s64));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_assemble_ms = ms_since(t0);
-  // --- batched local Cholesky
+  // --- batched local Cholesky: the selection's factors (FP64, [I, Gamma])
+  // on st; the solve factors (FP64, or FP32 on MFMA in the mixed path) on
+  // st2, where they overlap the selection and the coarse operator (joined
+  // at the end of the setup, finish_solve_factors)
   t0 = clk::now();
+  const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  if (c->solve_plan) {
+    if (mixed) {
+      TRY(c->dalloc(&c->fac32, c->s_total_fac));
+      TRY(c->dalloc(&c->dinv32, c->s_total_dinv));
+    } else {
+      c->sfac = s64;
+      TRY(c->dalloc(&c->sdinv, c->s_total_dinv));
+    }
+    if (!c->st2) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
+    if (!c->ev_fork) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (!c->ev_join) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));           // after the gather
+    LSQ2L_HIP_TRY(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
+    if (mixed) {
+      launch_to_float(c->st2, c->s_total_fac, s64, c->fac32);
+      launch_chol_local_f32(c->st2, nparts, c->Ps, c->fac32, c->dinv32, c->status + 2);
+    } else {
+      launch_chol_local(c->st2, nparts, c->Ps, c->sfac, c->sdinv, c->status + 2);
+    }
+    LSQ2L_HIP_TRY(hipEventRecord(c->ev_join, c->st2));
+  }
   launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status);
   int32_t hstat[8];
-  LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
-  c->info.t_factor_ms = ms_since(t0);
   if (hstat[0] != 0) {
     set_error("local Cholesky breakdown in subdomain " + std::to_string(hstat[0] - 1));
+    if (c->st2) (void)hipStreamSynchronize(c->st2);
     return LSQ2L_CHOL_BREAKDOWN;
   }
+  c->info.t_factor_ms = ms_since(t0);
+  // joins st2 and checks the solve factors; a broken float factorization
+  // is replaced by the double one, rounded
+  auto finish_solve_factors = [&]() -> lsq2l_status {
+    c->info.mixed_fallback = 0;
+    if (!c->solve_plan) return LSQ2L_OK;
+    LSQ2L_HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0));
+    int32_t hs = 0;
+    LSQ2L_HIP_TRY(hipMemcpyAsync(&hs, c->status + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    if (hs != 0 && mixed) {
+      c->info.mixed_fallback = 1;
+      double* d64 = nullptr;
+      TRY(c->dalloc(&d64, c->s_total_dinv));
+      launch_chol_local(st, nparts, c->Ps, s64, d64, c->status + 3);
+      launch_to_float(st, c->s_total_fac, s64, c->fac32);
+      launch_to_float(st, c->s_total_dinv, d64, c->dinv32);
+      LSQ2L_HIP_TRY(hipMemcpyAsync(&hs, c->status + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+      if (hs != 0) {
+        set_error("local Cholesky breakdown in subdomain " + std::to_string(hs - 1));
+        return LSQ2L_CHOL_BREAKDOWN;
+      }
+    } else if (hs != 0) {
+      set_error("local Cholesky breakdown in subdomain " + std::to_string(hs - 1) +
+                " (global-column order)");
+      return LSQ2L_CHOL_BREAKDOWN;
+    }
+    return LSQ2L_OK;
+  };
   // --- coarse space
   c->p_h.assign(nparts, 0);
   c->coarse = false;
@@ -914,13 +1084,6 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   if (!maps.join()) { set_error(maps.err); return LSQ2L_EINVAL; }
   TRY(c->upload(&c->P.own_ptr, H.own_ptr));
   TRY(c->upload(&c->P.own_pos, H.own_pos));
-  // --- mixed precision copy of the local factors
-  if (c->opt.precision == LSQ2L_MIXED) {
-    TRY(c->dalloc(&c->fac32, H.total_fac));
-    TRY(c->dalloc(&c->dinv32, H.total_dinv));
-    launch_to_float(st, H.total_fac, c->fac, c->fac32);
-    launch_to_float(st, H.total_dinv, c->dinv, c->dinv32);
-  }
   // --- row-permuted iteration copy of A
   ro_thread.t.join();
   c->row_perm = ro.use;
@@ -943,8 +1106,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     launch_permute_rows(st, m, dperm, c->M.rowptr, c->M.colind, c->M.vals, Mi.rowptr, Mi.colind, Mi.vals);
     LSQ2L_HIP_TRY(launch_transpose(st, m, n, nnz, Mi.rowptr, Mi.colind, Mi.vals, Mi.trowptr, Mi.trow,
                                    Mi.tvals, Mi.tperm, temp, tb));
-    TRY(c->dalloc(&Mi.blk, spmv_blocks(nnz) + 1));
-    TRY(c->dalloc(&Mi.tblk, spmv_blocks(nnz) + 1));
+    TRY(c->dalloc(&Mi.blk, spmv_table_len(nnz)));
+    TRY(c->dalloc(&Mi.tblk, spmv_table_len(nnz)));
     launch_row_blocks(st, m, Mi.rowptr, nnz, Mi.blk);
     launch_row_blocks(st, n, Mi.trowptr, nnz, Mi.tblk);
   }
@@ -982,6 +1145,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->upload(&c->d_seg_col, c->seg_col_h));
   TRY(c->upload(&c->d_seg_row, c->seg_row_h));
   TRY(krylov_alloc(c));
+  TRY(finish_solve_factors());
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->release_staged();
   if (c->opt.autotune) TRY(autotune_spmv(c, 10));
@@ -996,8 +1160,9 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     inf.max_p = std::max(inf.max_p, d.p);
     dense += (int64_t)(d.nI + d.nG) * (d.nI + d.nG + 1) / 2 * (int64_t)sizeof(double);
   }
-  inf.factor_tiles = H.total_fac / TT;
-  inf.factor_bytes = H.total_fac * (c->opt.precision == LSQ2L_MIXED ? sizeof(float) : sizeof(double));
+  const int64_t solve_fac = c->solve_plan ? c->s_total_fac : H.total_fac;
+  inf.factor_tiles = solve_fac / TT;
+  inf.factor_bytes = solve_fac * (c->opt.precision == LSQ2L_MIXED ? sizeof(float) : sizeof(double));
   inf.factor_dense_bytes = dense;
   inf.factor_nnz_min = -1;
   inf.shift = c->shift;
@@ -1024,6 +1189,10 @@ lsq2l_status check_common(double tau, const lsq2l_options* opt) {
       return LSQ2L_EINVAL;
     }
     if (opt->nev_max < 0) { set_error("nev_max must be >= 0"); return LSQ2L_EINVAL; }
+    if (opt->solve_order < LSQ2L_ORDER_AUTO || opt->solve_order > LSQ2L_ORDER_GLOBAL) {
+      set_error("bad solve_order");
+      return LSQ2L_EINVAL;
+    }
     if (!(opt->diag_shift_rel >= 0.0) || !(opt->adjoint_tol >= 0.0)) {
       set_error("diag_shift_rel and adjoint_tol must be >= 0");
       return LSQ2L_EINVAL;
@@ -1308,6 +1477,7 @@ void lsq2l_default_options(lsq2l_options* opt) {
   opt->diag_shift_rel = 0.0;
   opt->adjoint_tol = 0.0;
   opt->autotune = 0;
+  opt->solve_order = LSQ2L_ORDER_AUTO;
 }
 
 const char* lsq2l_last_error(void) { return g_err.c_str(); }
@@ -1463,7 +1633,11 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle c, int32_t kernel, int32_t reps, dou
     case 1: *bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * m + 8.0 * n; break;
     // each sweep reads every stored off-diagonal tile and every diagonal
     // inverse once (as many elements as the stored factor), plus y in and out
-    case 2: *bytes = 2.0 * eb * (double)c->H.total_fac + 16.0 * (double)c->H.total_loc; break;
+    case 2:
+      *bytes = c->solve_plan
+                   ? 2.0 * eb * (double)c->s_total_fac + (16.0 + 8.0) * (double)c->s_total_np
+                   : 2.0 * eb * (double)c->H.total_fac + 16.0 * (double)c->H.total_loc;
+      break;
     // the algorithmic minimum: each sweep reads the nnz(L_i) entries of the
     // factors under a fill-reducing order, y in and out per local unknown
     case 4: {

@@ -80,6 +80,10 @@ struct GmresWork {
 struct lsq2l_ctx {
   hipStream_t st = nullptr;
   hipStream_t gst = nullptr;   // stream the PCG iteration graph is captured on
+  // second stream of the setup: the solve factors are computed on it while
+  // the selection and the coarse operator run on st (joined by ev_join)
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   lsq2l_options opt{};
   double tau = 0.0;
   int S = 1;
@@ -101,6 +105,13 @@ struct lsq2l_ctx {
   int64_t etiles = 0;
   double shift = 0.0;       // diagonal shift of C used by the preconditioner
   double *fac = nullptr, *dinv = nullptr, *scale = nullptr, *ctg = nullptr;
+  // Factors of the local solves (see solve_layout in api.cpp).  With
+  // solve_plan unset they are fac / dinv in the layout P; otherwise they are
+  // in the layout Ps: sfac / sdinv (FP64 path), fac32 / dinv32 (mixed path).
+  bool solve_plan = false;
+  lsq2l::DevPlan Ps;
+  int64_t s_total_fac = 0, s_total_dinv = 0, s_total_np = 0, s_total_tiles = 0;
+  double *sfac = nullptr, *sdinv = nullptr;
   float *fac32 = nullptr, *dinv32 = nullptr;
   float* X32 = nullptr;      // MIXED: FP32 copy of X for the restriction and prolongation
   double *X = nullptr, *W = nullptr, *efac = nullptr, *edinv = nullptr, *einv = nullptr;

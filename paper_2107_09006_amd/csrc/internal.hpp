@@ -232,6 +232,24 @@ __device__ inline double lane_bcast(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+__device__ inline float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// 1 / sqrt(d) from the hardware estimate, refined by Newton-Raphson steps
+// r <- r + r (1 - d r^2) / 2 (the error roughly squares each step): two in
+// double, one in float
+__device__ inline double rsqrt_refined(double d) {
+  double rs = __builtin_amdgcn_rsq(d);
+  rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+  return fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+}
+
+__device__ inline float rsqrt_refined(float d) {
+  const float rs = __builtin_amdgcn_rsqf(d);
+  return fmaf(0.5f * rs, fmaf(-d * rs, rs, 1.0f), rs);
+}
+
 // L L^T = W and Inv = L^{-1} for one SPD tile W (column-major in LDS, leading
 // dimension LDT, lower part read), by the 64 lanes of one wave with the tile in
 // registers: lane j < 32 holds column j of the symmetric tile, lane 32 + j
@@ -241,33 +259,31 @@ __device__ inline double lane_bcast(double v, int l) {
 // 1 / sqrt(d_k)).  Column k is broadcast by lane reads, so the 32 steps need no
 // LDS traffic and no barrier.  L and Inv are written to LDS (L may be null).
 // Returns false if a pivot is not positive and finite (it is then replaced by
-// 1, so the caller can continue and report).
-__device__ inline bool tile_potrf_inv_reg(const double* W, double* L, double* Inv, int lane) {
+// 1, so the caller can continue and report).  T is double or float (the
+// arithmetic of the whole tile).
+template <typename T>
+__device__ inline bool tile_potrf_inv_reg(const T* W, T* L, T* Inv, int lane) {
   const int j = lane % TS;
   const bool fac = lane < TS;
-  double v[TS];
+  T v[TS];
 #pragma unroll
   for (int i = 0; i < TS; ++i)
-    v[i] = fac ? ((i >= j) ? W[j * LDT + i] : W[i * LDT + j]) : ((i == j) ? 1.0 : 0.0);
+    v[i] = fac ? ((i >= j) ? W[j * LDT + i] : W[i * LDT + j]) : ((i == j) ? T(1) : T(0));
   bool ok = true;
-  double colscale = 1.0;
+  T colscale = T(1);
   // Every lane runs the same instructions: the lane reads happen in uniform
   // control flow and the per-lane roles are selects, never branches (a lane
   // read inside a divergent branch may see another version of the value).
 #pragma unroll
   for (int k = 0; k < TS; ++k) {
-    double d = lane_bcast(v[k], k);
-    if (!(d > 0.0) || !(d < INFINITY)) { ok = false; d = 1.0; }
-    // 1 / sqrt(d): hardware estimate refined by two Newton-Raphson steps
-    // r <- r + r (1 - d r^2) / 2 (the error roughly squares each step)
-    double rs = __builtin_amdgcn_rsq(d);
-    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-    const double invd = rs * rs, inv_sd = rs;
+    T d = lane_bcast(v[k], k);
+    if (!(d > T(0)) || !(d < T(INFINITY))) { ok = false; d = T(1); }
+    const T rs = rsqrt_refined(d);
+    const T invd = rs * rs, inv_sd = rs;
     // factor lanes j > k: W(i, j) -= W(i, k) W(k, j) / d; inverse lanes j <= k:
     // Z(i, j) -= W(i, k) Z(k, j) / d; other lanes unchanged
     const bool upd = fac ? (j > k) : (j <= k);
-    const double coef = upd ? v[k] * invd : 0.0;
+    const T coef = upd ? v[k] * invd : T(0);
 #pragma unroll
     for (int i = k + 1; i < TS; ++i) v[i] -= lane_bcast(v[i], k) * coef;
     if (!fac && j <= k) v[k] *= inv_sd;
@@ -275,7 +291,7 @@ __device__ inline bool tile_potrf_inv_reg(const double* W, double* L, double* In
   }
 #pragma unroll
   for (int i = 0; i < TS; ++i) {
-    if (fac) { if (L) L[j * LDT + i] = (i >= j) ? v[i] * colscale : 0.0; }
+    if (fac) { if (L) L[j * LDT + i] = (i >= j) ? v[i] * colscale : T(0); }
     else Inv[j * LDT + i] = v[i];
   }
   return ok;

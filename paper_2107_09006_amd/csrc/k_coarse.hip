@@ -526,7 +526,7 @@ k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, i
       tile_acc_store<double>(acc, sW, LDT, lane);
       wave_sync();
     }
-    const bool ok = tile_potrf_inv_reg(sW, nullptr, sInv, lane);
+    const bool ok = tile_potrf_inv_reg<double>(sW, nullptr, sInv, lane);
     if (!ok && lane == 0 && blockIdx.x == 0) atomicCAS(status, 0, J + 1);
   } else if (mine) {
     tile_acc_load<double>(acc, efac + tile_pos(eF, eOff, I, J) * TT, TS, lane);

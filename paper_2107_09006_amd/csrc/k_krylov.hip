@@ -31,69 +31,85 @@ k_spmv(int32_t nrows, const int32_t* __restrict__ rowptr, const int32_t* __restr
 
 // y = A x for short, uneven rows, staged through LDS.  Workgroup b owns the
 // rows whose first entry lies in [b SPMV_NB, (b + 1) SPMV_NB): rows
-// blk[b] .. blk[b + 1] - 1 (a table made once per matrix, k_row_blocks).
-// Its entries are read once, coalesced, as vals[e] x[colind[e]] into LDS;
-// then every thread sums its rows from LDS in entry order and writes y
-// coalesced.  A block whose rows hold more than SPMV_CAP entries (a long
-// last row) sums each row with a wavefront instead.  Every row is summed in
-// one fixed order, so runs are bitwise reproducible.
-constexpr int SPMV_NB = 1024, SPMV_CAP = 2048, SPMV_THREADS = 256;
+// tab[2b] .. tab[2b + 2] - 1, whose entries start at tab[2b + 1] (a table
+// made once per matrix, k_row_blocks), so that one 8-byte load gives the
+// block's extent.  The row starts of the block are staged in LDS while its
+// entries are read once, coalesced, eight per thread in flight, as
+// vals[e] x[colind[e]] into LDS; then every thread sums its rows from LDS in
+// entry order and writes y coalesced.  A block whose rows hold more than
+// SPMV_CAP entries (a long last row) sums each row with a wavefront instead.
+// Every row is summed in one fixed order, so runs are bitwise reproducible.
+constexpr int SPMV_NB = 2048, SPMV_CAP = SPMV_NB + 256, SPMV_RCAP = SPMV_NB, SPMV_THREADS = 256;
+constexpr int SPMV_U = 8;   // entries per thread and pass
 
 int64_t spmv_blocks(int64_t nnz) { return std::max<int64_t>(1, (nnz + SPMV_NB - 1) / SPMV_NB); }
+int64_t spmv_table_len(int64_t nnz) { return 2 * (spmv_blocks(nnz) + 1); }
 
-// blk[b] = first row whose start is >= b SPMV_NB (b < nblk), blk[nblk] = nrows
+// tab[2b] = first row whose start is >= b SPMV_NB (b < nblk), tab[2b + 1] =
+// its start; tab[2 nblk] = nrows, tab[2 nblk + 1] = nnz
 __global__ void k_row_blocks(int32_t nrows, const int32_t* __restrict__ rowptr, int64_t nblk,
-                             int32_t* __restrict__ blk) {
+                             int32_t* __restrict__ tab) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nblk) return;
-  if (b == nblk) { blk[b] = nrows; return; }
-  const int64_t v = b * SPMV_NB;
-  int32_t lo = 0, hi = nrows;
-  while (lo < hi) {
-    const int32_t mid = (int32_t)(((int64_t)lo + hi) >> 1);
-    if (rowptr[mid] < v) lo = mid + 1;
-    else hi = mid;
+  int32_t lo = nrows;
+  if (b < nblk) {
+    const int64_t v = b * SPMV_NB;
+    lo = 0;
+    int32_t hi = nrows;
+    while (lo < hi) {
+      const int32_t mid = (int32_t)(((int64_t)lo + hi) >> 1);
+      if (rowptr[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
   }
-  blk[b] = lo;
+  tab[2 * b] = lo;
+  tab[2 * b + 1] = rowptr[lo];
 }
 
-void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int64_t nnz, int32_t* blk) {
+void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int64_t nnz, int32_t* tab) {
   const int64_t nblk = spmv_blocks(nnz);
-  k_row_blocks<<<(unsigned)((nblk + 1 + 255) / 256), 256, 0, st>>>(nrows, rowptr, nblk, blk);
+  k_row_blocks<<<(unsigned)((nblk + 1 + 255) / 256), 256, 0, st>>>(nrows, rowptr, nblk, tab);
 }
 
 __global__ void __launch_bounds__(SPMV_THREADS)
-k_spmv_stream(const int32_t* __restrict__ blk, const int32_t* __restrict__ rowptr,
+k_spmv_stream(const int32_t* __restrict__ tab, const int32_t* __restrict__ rowptr,
               const int32_t* __restrict__ colind, const double* __restrict__ vals,
               const double* __restrict__ x, double* __restrict__ y) {
   __shared__ double prod[SPMV_CAP];
+  __shared__ int32_t rps[SPMV_RCAP + 1];
   const int tid = threadIdx.x;
-  const int32_t r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+  typedef int32_t i2 __attribute__((ext_vector_type(2)));
+  const i2 lo = reinterpret_cast<const i2*>(tab)[blockIdx.x];
+  const i2 hi = reinterpret_cast<const i2*>(tab)[blockIdx.x + 1];
+  const int32_t r0 = lo.x, e0 = lo.y, r1 = hi.x, e1 = hi.y;
   if (r0 >= r1) return;
-  const int32_t e0 = rowptr[r0], e1 = rowptr[r1];
+  const int32_t nr = r1 - r0;
   if (e1 - e0 <= SPMV_CAP) {
-    // four entries per thread in flight: columns and values first, then x
-    for (int32_t e = e0 + tid; e < e1; e += 4 * SPMV_THREADS) {
-      int32_t c[4];
-      double v[4];
+    const bool staged = nr <= SPMV_RCAP;
+    if (staged)
+      for (int32_t k = tid; k <= nr; k += SPMV_THREADS) rps[k] = rowptr[r0 + k] - e0;
+    for (int32_t e = e0 + tid; e < e1; e += SPMV_U * SPMV_THREADS) {
+      int32_t c[SPMV_U];
+      double v[SPMV_U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < SPMV_U; ++u) {
         const int32_t q = e + u * SPMV_THREADS;
-        c[u] = q < e1 ? colind[q] : 0;
-        v[u] = q < e1 ? vals[q] : 0.0;
+        c[u] = q < e1 ? __builtin_nontemporal_load(colind + q) : 0;
+        v[u] = q < e1 ? __builtin_nontemporal_load(vals + q) : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < SPMV_U; ++u) {
         const int32_t q = e + u * SPMV_THREADS;
         if (q < e1) prod[q - e0] = v[u] * x[c[u]];
       }
     }
     __syncthreads();
-    for (int32_t r = r0 + tid; r < r1; r += SPMV_THREADS) {
-      const int32_t a = rowptr[r] - e0, b = rowptr[r + 1] - e0;
+    for (int32_t r = tid; r < nr; r += SPMV_THREADS) {
+      const int32_t a = staged ? rps[r] : rowptr[r0 + r] - e0;
+      const int32_t b = staged ? rps[r + 1] : rowptr[r0 + r + 1] - e0;
       double s = 0.0;
       for (int32_t k = a; k < b; ++k) s += prod[k];
-      y[r] = s;
+      y[r0 + r] = s;
     }
     return;
   }

@@ -9,6 +9,8 @@
 //   z_i   = C_ii^{-1} r_i                          (eq. one_level_schwarz)
 //
 // One workgroup owns one subdomain; subdomains of uneven size share a launch.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace lsq2l {
@@ -36,7 +38,9 @@ __device__ inline int local_pos(int i, int c, const int32_t* __restrict__ part,
 
 // Lower triangle of C_ii (tile-envelope layout) and of Ct_GG (dense, ld nGp).
 // Thread per local column: every write of a thread lands in its own column,
-// so the accumulation order is fixed and no atomics are needed.
+// so the accumulation order is fixed and no atomics are needed.  Workgroup
+// (i, y) takes the columns y * 256 + t, (y + gridDim.y) * 256 + t, ... of
+// subdomain i, so that a large subdomain spreads over several compute units.
 __global__ void __launch_bounds__(256)
 k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
@@ -53,7 +57,7 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
   const int64_t* off = tileOff + d.tile_base;
   double* A = fac + d.fac_off;
   double* Ct = ctg + d.g_off;
-  for (int a = threadIdx.x; a < d.nI + d.nG; a += blockDim.x) {
+  for (int a = blockIdx.y * blockDim.x + threadIdx.x; a < d.nI + d.nG; a += gridDim.y * blockDim.x) {
     const int j = om[a];
     const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
     const int ta = posa / TS, ra = posa % TS;
@@ -164,7 +168,6 @@ __global__ void __launch_bounds__(256)
 k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
              const int64_t* __restrict__ tileOff, T* __restrict__ fac, T* __restrict__ dinv,
              int32_t* __restrict__ status) {
-  static_assert(sizeof(T) == sizeof(double), "the local factors are computed in double");
   __shared__ T sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
   __shared__ int32_t rows[ROWCAP];
   __shared__ int s_count, s_ok;
@@ -251,11 +254,145 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
     }
     __syncthreads();
   }
-  if (failed && tid == 0) atomicCAS(status, 0, blockIdx.x + 1);
+  if (failed && tid == 0) atomicCAS(status, 0, d.id + 1);
 }
 
 template __global__ void k_chol_local<double>(const SubDesc*, const int32_t*, const int64_t*,
                                               double*, double*, int32_t*);
+template __global__ void k_chol_local<float>(const SubDesc*, const int32_t*, const int64_t*,
+                                             float*, float*, int32_t*);
+
+// ---------------------------------------------------------------------------
+// The factor used by the per-iteration local solves.  C_ii^{-1} r does not
+// depend on the order of Omega_i, and the order [Omega_Ii, Omega_Gamma_i]
+// that the coarse selection needs (T = L_GI L_GI^T) makes the interface rows
+// of L dense across the interior.  The solve factor therefore orders
+// Omega_i by global column (the order of the columns of A) where that stores
+// fewer tiles: position q of that order is the q-th smallest column of
+// Omega_i.  Its envelope comes from the assembled C_ii itself (the first
+// nonzero of each row after the permutation), which the factorization
+// cannot leave; its values are gathered from the assembled, equilibrated
+// C_ii before that is factored in place.
+// ---------------------------------------------------------------------------
+
+// inv[loc_off + pos] = position of the column at [I, Gamma] position pos in
+// the global-column order of Omega_i (-1 on padding): the column's rank
+// among the interior columns plus its rank among the interface columns
+__global__ void __launch_bounds__(256)
+k_solve_inv(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
+            int32_t* __restrict__ inv) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* om = omega + d.omega_off;
+  const int32_t* G = om + d.nI;
+  auto rank = [](const int32_t* v, int n, int32_t c) {   // entries of v below c
+    int lo = 0, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (v[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    int q = -1;
+    if (pos < d.nI) q = pos + rank(G, d.nG, om[pos]);
+    else if (pos >= d.nIp && pos < d.nIp + d.nG) q = (pos - d.nIp) + rank(om, d.nI, G[pos - d.nIp]);
+    inv[d.loc_off + pos] = q;
+  }
+}
+
+// Fg[tile_base + t] = t for every tile row t of the global-order layout
+__global__ void __launch_bounds__(256)
+k_solve_env_init(const SubDesc* __restrict__ gsub, int32_t* __restrict__ Fg) {
+  const SubDesc g = gsub[blockIdx.x];
+  for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) Fg[g.tile_base + t] = t;
+}
+
+// Tile envelope of the global-order layout: for every nonzero C_ii(r, c),
+// r >= c, of the assembled matrix, tile row max(q_r, q_c) / 32 reaches tile
+// column min(q_r, q_c) / 32.  Workgroup (i, y) reads the tile rows
+// y, y + gridDim.y, ... of subdomain i's [I, Gamma] envelope.
+__global__ void __launch_bounds__(256)
+k_solve_env(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ gsub,
+            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
+            const double* __restrict__ fac, const int32_t* __restrict__ inv,
+            int32_t* __restrict__ Fg) {
+  const SubDesc d = subs[blockIdx.x];
+  const SubDesc g = gsub[d.id];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  const int32_t* iv = inv + d.loc_off;
+  int32_t* Fo = Fg + g.tile_base;
+  for (int I = blockIdx.y; I < d.ntiles; I += gridDim.y) {
+    const int nk = I - F[I] + 1;
+    const double* row = A + off[I] * TT;
+    for (int e = threadIdx.x; e < nk * TT; e += blockDim.x) {
+      const int J = F[I] + e / TT, rc = e % TT;
+      const int r = I * TS + rc % TS, c = J * TS + rc / TS;
+      if (r < c || row[e] == 0.0) continue;
+      const int qr = iv[r], qc = iv[c];
+      if (qr < 0 || qc < 0) continue;
+      atomicMin(&Fo[max(qr, qc) / TS], min(qr, qc) / TS);
+    }
+  }
+}
+
+// sperm[loc_off + q] = loc index of the entry the solve layout holds at
+// position q (-1: padding): the global-column order where ssub.spare is set,
+// the [I, Gamma] layout itself otherwise.  sperm is -1 on entry.
+__global__ void __launch_bounds__(256)
+k_solve_perm(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssub,
+             const int32_t* __restrict__ inv, int32_t* __restrict__ sperm) {
+  const SubDesc d = subs[blockIdx.x];
+  const SubDesc s = ssub[d.id];
+  for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+    if (s.spare) {
+      const int q = inv[d.loc_off + pos];
+      if (q >= 0) sperm[s.loc_off + q] = (int32_t)(d.loc_off + pos);
+    } else {
+      sperm[s.loc_off + pos] = (int32_t)(d.loc_off + pos);
+    }
+  }
+}
+
+// The solve layout's matrix (tile envelope, double) from the assembled and
+// equilibrated [I, Gamma] C_ii: entry (q_r, q_c) is C_ii(p_r, p_c) with
+// p = sperm - loc_off, zero outside the [I, Gamma] envelope, and the
+// identity on padding.  Workgroup (i, y) writes tile rows y, y + gridDim.y, ...
+__global__ void __launch_bounds__(256)
+k_gather_solve(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssub,
+               const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
+               const double* __restrict__ fac, const int32_t* __restrict__ stileF,
+               const int64_t* __restrict__ stileOff, const int32_t* __restrict__ sperm,
+               double* __restrict__ out) {
+  const SubDesc d = subs[blockIdx.x];
+  const SubDesc s = ssub[d.id];
+  const int32_t* F = tileF + d.tile_base;
+  const int64_t* off = tileOff + d.tile_base;
+  const double* A = fac + d.fac_off;
+  const int32_t* Fs = stileF + s.tile_base;
+  const int64_t* offs = stileOff + s.tile_base;
+  const int32_t* sp = sperm + s.loc_off;
+  double* O = out + s.fac_off;
+  for (int I = blockIdx.y; I < s.ntiles; I += gridDim.y) {
+    const int nk = I - Fs[I] + 1;
+    double* row = O + offs[I] * TT;
+    for (int e = threadIdx.x; e < nk * TT; e += blockDim.x) {
+      const int J = Fs[I] + e / TT, rc = e % TT;
+      const int qr = I * TS + rc % TS, qc = J * TS + rc / TS;
+      const int pr = sp[qr], pc = sp[qc];
+      double v;
+      if (pr < 0 || pc < 0) {
+        v = (qr == qc) ? 1.0 : 0.0;
+      } else {
+        const int hi = (int)(max(pr, pc) - d.loc_off), lo = (int)(min(pr, pc) - d.loc_off);
+        const int th = hi / TS, tl = lo / TS;
+        v = tl >= F[th] ? A[tile_pos(F, off, th, tl) * TT + (lo % TS) * TS + hi % TS] : 0.0;
+      }
+      row[e] = v;
+    }
+  }
+}
 
 __global__ void k_to_float(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,8 +469,12 @@ void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, cons
 
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
                      double* ctg) {
-  k_assemble<<<nsub, 256, 0, st>>>(P.heavy(), P.omega, P.part, P.locown, M.rowptr, M.colind, M.vals,
-                                   M.trowptr, M.trow, M.tvals, P.tileF, P.tileOff, fac, ctg);
+  // workgroups per subdomain: enough for the largest one to take 2 columns
+  // per thread (at most 64)
+  const int ny = std::max(1, std::min(64, (P.max_np + 511) / 512));
+  k_assemble<<<dim3(nsub, ny), 256, 0, st>>>(P.heavy(), P.omega, P.part, P.locown, M.rowptr,
+                                             M.colind, M.vals, M.trowptr, M.trow, M.tvals, P.tileF,
+                                             P.tileOff, fac, ctg);
 }
 
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
@@ -345,6 +486,32 @@ void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac,
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
                        int32_t* status) {
   k_chol_local<double><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status);
+}
+
+void launch_solve_inv(hipStream_t st, int nsub, const DevPlan& P, int32_t* inv) {
+  k_solve_inv<<<nsub, 256, 0, st>>>(P.heavy(), P.omega, inv);
+}
+
+void launch_solve_env(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* gsub,
+                      const double* fac, const int32_t* inv, int32_t* Fg) {
+  k_solve_env_init<<<nsub, 256, 0, st>>>(gsub, Fg);
+  k_solve_env<<<dim3(nsub, 16), 256, 0, st>>>(P.heavy(), gsub, P.tileF, P.tileOff, fac, inv, Fg);
+}
+
+void launch_solve_perm(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* ssub,
+                       const int32_t* inv, int32_t* sperm) {
+  k_solve_perm<<<nsub, 256, 0, st>>>(P.heavy(), ssub, inv, sperm);
+}
+
+void launch_gather_solve(hipStream_t st, int nsub, const DevPlan& P, const DevPlan& Ps,
+                         const double* fac, double* out) {
+  k_gather_solve<<<dim3(nsub, 16), 256, 0, st>>>(P.heavy(), Ps.subs, P.tileF, P.tileOff, fac,
+                                                  Ps.tileF, Ps.tileOff, Ps.sperm, out);
+}
+
+void launch_chol_local_f32(hipStream_t st, int nsub, const DevPlan& P, float* fac, float* dinv,
+                           int32_t* status) {
+  k_chol_local<float><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status);
 }
 
 void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst) {

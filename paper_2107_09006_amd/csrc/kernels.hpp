@@ -35,6 +35,11 @@ struct DevPlan {              // subdomain layout (device copies of HostPlan)
   SubDesc* subs_ord = nullptr;     // subs in that order: the one-workgroup-per-subdomain
                                    // setup kernels start the largest subdomains first
   int max_np = 0;             // largest padded local size
+  // layout of the solve factor only: where each position lives in the local
+  // vectors (loc index, -1 on padding; null: loc_off + position), and
+  // scratch local vectors for the subdomains solved in global memory
+  int32_t* sperm = nullptr;
+  double* yscratch = nullptr;
   const SubDesc* heavy() const { return subs_ord ? subs_ord : subs; }
 };
 
@@ -84,8 +89,10 @@ void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
                  const double* vals, const double* x, double* y, int group, int64_t nnz,
                  const int32_t* blk);
-// rows of the LDS row blocks of a CSR matrix: spmv_blocks(nnz) + 1 entries
+// the LDS row blocks of a CSR matrix: spmv_blocks(nnz) blocks, described by
+// a table of spmv_table_len(nnz) int32 (first row and its start, per block)
 int64_t spmv_blocks(int64_t nnz);
+int64_t spmv_table_len(int64_t nnz);
 void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int64_t nnz, int32_t* blk);
 void launch_grad_vals(hipStream_t st, int32_t m, const int32_t* rowptr, const int32_t* colind,
                       const double* r, const double* lam, const double* Alam, const double* x,
@@ -168,6 +175,23 @@ void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac,
                         double* scale);
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
                        int32_t* status);
+// the same in FP32 (FP32 MFMA, FP32 accumulation)
+void launch_chol_local_f32(hipStream_t st, int nsub, const DevPlan& P, float* fac, float* dinv,
+                           int32_t* status);
+// solve factor in the global-column order of each subdomain: inv (indexed
+// like loc) maps an [I, Gamma] position to its global-order position;
+// gsub describes the global-order layout (np, ntiles, tile_base); Fg gets
+// its tile envelope from the assembled C_ii
+void launch_solve_inv(hipStream_t st, int nsub, const DevPlan& P, int32_t* inv);
+void launch_solve_env(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* gsub,
+                      const double* fac, const int32_t* inv, int32_t* Fg);
+// Ps.sperm (filled with -1 first) from the chosen layouts (ssub.spare set:
+// global order)
+void launch_solve_perm(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* ssub,
+                       const int32_t* inv, int32_t* sperm);
+// the solve layout's matrix (double) from the assembled, equilibrated C_ii
+void launch_gather_solve(hipStream_t st, int nsub, const DevPlan& P, const DevPlan& Ps,
+                         const double* fac, double* out);
 void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst);
 void launch_gather_local(hipStream_t st, int nsub, const DevPlan& P, const double* scale,
                          const double* r, double* loc);

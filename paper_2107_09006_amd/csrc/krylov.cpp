@@ -293,7 +293,8 @@ lsq2l_status gmres(lsq2l_ctx* c, double* x, bool adjoint, double tol, KrylovResu
 }
 
 // ---------------------------------------------------------------------------
-// sum_i nnz(L_i) under a fill-reducing order that keeps Omega_Gamma_i last
+// sum_i nnz(L_i) under a fill-reducing order of Omega_i (the best of
+// nested dissection, the global column order and [Omega_Ii, Omega_Gamma_i])
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -442,15 +443,20 @@ lsq2l_status factor_nnz_min(lsq2l_ctx* c) {
           }
         }
         for (int32_t a = 0; a < ni; ++a) lpos[om[a]] = -1;
-        // interior by nested dissection, then Omega_Gamma_i in its order
-        std::vector<int32_t> interior(d.nI), ord;
-        for (int32_t a = 0; a < d.nI; ++a) interior[a] = a;
+        // the local solves may use any order of Omega_i: the fewest entries
+        // among a nested-dissection order of all of Omega_i, the global
+        // column order and [Omega_Ii, Omega_Gamma_i]
+        std::vector<int32_t> all(ni), ord;
+        for (int32_t a = 0; a < ni; ++a) all[a] = a;
         std::vector<char> inset(ni, 0);
         std::vector<int32_t> level(ni, -1);
         ord.reserve(ni);
-        nested_dissection(adj, interior, inset, level, ord);
-        for (int32_t a = d.nI; a < ni; ++a) ord.push_back(a);
-        per[i] = symbolic_nnz(adj, ord);
+        nested_dissection(adj, all, inset, level, ord);
+        int64_t best = symbolic_nnz(adj, ord);
+        best = std::min(best, symbolic_nnz(adj, all));
+        std::vector<int32_t> byc(all);
+        std::sort(byc.begin(), byc.end(), [&](int32_t x, int32_t y) { return om[x] < om[y]; });
+        per[i] = std::min(best, symbolic_nnz(adj, byc));
       }
     });
   for (auto& th : pool) th.join();

@@ -39,7 +39,8 @@ lsq2l_status lsqr(lsq2l_ctx* c, const double* b, double* x, double tol, KrylovRe
 lsq2l_status gmres(lsq2l_ctx* c, double* x, bool adjoint, double tol, KrylovResult& res);
 // work vectors of the method chosen in c->opt (krylov.cpp)
 lsq2l_status krylov_alloc(lsq2l_ctx* c);
-// sum_i nnz(L_i) under a fill-reducing order with Omega_Gamma_i last
+// sum_i nnz(L_i) under a fill-reducing order of Omega_i (the best of nested
+// dissection, the global column order and [Omega_Ii, Omega_Gamma_i])
 // (symbolic factorization on the host, krylov.cpp); cached in c->fac_nnz_min
 lsq2l_status factor_nnz_min(lsq2l_ctx* c);
 

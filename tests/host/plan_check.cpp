@@ -5,6 +5,7 @@
 // buffer or outside a tile envelope.  No GPU is used.
 // Input file: int32 header {m, n, nnz, nparts, ninstances}, then rowptr,
 // colind, part (concatenated instances) and the instance of every part.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -209,6 +210,165 @@ int main(int argc, char** argv) {
     CHECK(d.g_off + (int64_t)d.nGp * d.nGp <= H.total_g, "g");
     CHECK(d.dinv_off + (int64_t)d.ntiles * TT <= H.total_dinv, "dinv");
     CHECK(d.nG <= 1024, "eig limit");
+  }
+  // ---- layout of the solve factors (solve_layout in api.cpp; kernels
+  // k_solve_inv, k_solve_env, k_solve_perm, k_gather_solve and the local
+  // solves with a permutation).  The envelope comes from the structural
+  // pattern of C_ii here, a superset of the numerical nonzeros the device
+  // reads.  Both forced choices: global order everywhere, split everywhere.
+  for (int mode = 0; mode < 2; ++mode) {
+    std::vector<SubDesc> g(H.subs.begin(), H.subs.end());
+    int64_t tb = 0, lo = 0;
+    for (SubDesc& d : g) {
+      const int32_t np_main = d.np;
+      d.np = (d.nI + d.nG + TS - 1) / TS * TS;
+      d.ntiles = d.np / TS;
+      d.tile_base = tb; tb += d.ntiles;
+      d.loc_off = lo; lo += std::max(np_main, d.np);
+    }
+    std::vector<int32_t> inv(H.total_loc, -2), Fg(tb, -1);
+    std::vector<std::vector<std::pair<int, int>>> pairs(nparts);   // (posc >= posa) of C_ii
+    for (int i = 0; i < nparts; ++i) {
+      const SubDesc& d = H.subs[i];
+      const int32_t* om = &H.omega[d.omega_off];
+      const int32_t* G = om + d.nI;
+      auto rank = [](const int32_t* v, int cnt, int32_t c) {
+        int a = 0, b = cnt;
+        while (a < b) { int mid = (a + b) / 2; if (v[mid] < c) a = mid + 1; else b = mid; }
+        return a;
+      };
+      std::vector<char> hit(d.nI + d.nG, 0);
+      for (int pos = 0; pos < d.np; ++pos) {
+        int q = -1;
+        if (pos < d.nI) q = pos + rank(G, d.nG, om[pos]);
+        else if (pos >= d.nIp && pos < d.nIp + d.nG) q = (pos - d.nIp) + rank(om, d.nI, G[pos - d.nIp]);
+        CHECK(d.loc_off + pos < H.total_loc, "inv index");
+        inv[d.loc_off + pos] = q;
+        if (q >= 0) { CHECK(q < d.nI + d.nG && !hit[q], "inv not a bijection in sub %d", i); hit[q] = 1; }
+      }
+      for (int t = 0; t < g[i].ntiles; ++t) { CHECK(g[i].tile_base + t < tb, "Fg index"); Fg[g[i].tile_base + t] = t; }
+      auto local_pos = [&](int c) -> int {
+        if (part[c] == i) return H.locown[c];
+        const int k = rank(G, d.nG, c);
+        return (k < d.nG && G[k] == c) ? d.nIp + k : -1;
+      };
+      for (int a = 0; a < d.nI + d.nG; ++a) {
+        const int j = om[a];
+        const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
+        for (int k = trp[j]; k < trp[j + 1]; ++k) {
+          const int r = tcol[k];
+          for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            const int posc = local_pos(ci[e]);
+            if (posc < posa) continue;
+            pairs[i].push_back({posc, posa});
+            const int qr = inv[d.loc_off + posc], qc = inv[d.loc_off + posa];
+            CHECK(qr >= 0 && qc >= 0, "pattern entry on padding");
+            int32_t& f = Fg[g[i].tile_base + std::max(qr, qc) / TS];
+            f = std::min(f, std::min(qr, qc) / TS);
+          }
+        }
+      }
+    }
+    // choice and offsets, as in solve_layout
+    std::vector<SubDesc> sd(g);
+    std::vector<int32_t> sF;
+    std::vector<int64_t> sOff;
+    int64_t ftiles = 0, dtiles = 0, stb = 0;
+    for (int i = 0; i < nparts; ++i) {
+      const SubDesc& mn = H.subs[i];
+      const bool use_g = mode == 0;
+      SubDesc& d = sd[i];
+      d.np = use_g ? g[i].np : mn.np;
+      d.ntiles = use_g ? g[i].ntiles : mn.ntiles;
+      d.spare = use_g;
+      d.tile_base = stb; stb += d.ntiles;
+      d.fac_off = ftiles * TT;
+      d.dinv_off = dtiles * TT; dtiles += d.ntiles;
+      int64_t run = 0;
+      for (int t = 0; t < d.ntiles; ++t) {
+        const int32_t f = use_g ? Fg[g[i].tile_base + t] : H.tileF[mn.tile_base + t];
+        CHECK(f >= 0 && f <= t, "solve envelope start");
+        sF.push_back(f);
+        sOff.push_back(run);
+        run += t - f + 1;
+      }
+      ftiles += run;
+    }
+    const int64_t s_total_fac = ftiles * TT, s_total_dinv = dtiles * TT;
+    // k_solve_perm: every slot written at most once, inside the layout
+    std::vector<int32_t> sperm(lo, -1);
+    for (int i = 0; i < nparts; ++i) {
+      const SubDesc& d = H.subs[i];
+      const SubDesc& sv = sd[i];
+      CHECK(sv.loc_off + sv.np <= lo, "solve layout slice");
+      for (int pos = 0; pos < d.np; ++pos) {
+        int64_t at;
+        if (sv.spare) {
+          const int q = inv[d.loc_off + pos];
+          if (q < 0) continue;
+          at = sv.loc_off + q;
+        } else {
+          at = sv.loc_off + pos;
+        }
+        CHECK(at >= 0 && at < lo && sperm[at] == -1, "sperm write in sub %d", i);
+        sperm[at] = (int32_t)(d.loc_off + pos);
+      }
+    }
+    for (int i = 0; i < nparts; ++i) {
+      const SubDesc& d = H.subs[i];
+      const SubDesc& sv = sd[i];
+      const int32_t* F = &H.tileF[d.tile_base];
+      const int64_t* off = &H.tileOff[d.tile_base];
+      const int32_t* Fs = &sF[sv.tile_base];
+      const int64_t* offs = &sOff[sv.tile_base];
+      const int64_t fac_end = (i + 1 < nparts) ? sd[i + 1].fac_off : s_total_fac;
+      const int64_t stored = (fac_end - sv.fac_off) / TT;
+      const int64_t mstored = ((i + 1 < nparts ? H.subs[i + 1].fac_off : H.total_fac) - d.fac_off) / TT;
+      auto stp = [&](int I, int J) -> int64_t {
+        CHECK(I >= 0 && I < sv.ntiles && J <= I && J >= Fs[I], "solve tile (%d,%d) outside envelope of sub %d", I, J, i);
+        const int64_t t = offs[I] + (J - Fs[I]);
+        CHECK(t >= 0 && t < stored, "solve tile index");
+        return t;
+      };
+      // every entry of C_ii lies inside the solve envelope
+      for (const auto& pr : pairs[i]) {
+        const int qr = sv.spare ? inv[d.loc_off + pr.first] : pr.first;
+        const int qc = sv.spare ? inv[d.loc_off + pr.second] : pr.second;
+        stp(std::max(qr, qc) / TS, std::min(qr, qc) / TS);
+      }
+      // k_gather_solve
+      for (int I = 0; I < sv.ntiles; ++I)
+        for (int J = Fs[I]; J <= I; ++J) {
+          stp(I, J);
+          for (int rc = 0; rc < TT; ++rc) {
+            const int qr = I * TS + rc % TS, qc = J * TS + rc / TS;
+            CHECK(qr < sv.np && qc < sv.np, "gather position");
+            const int32_t pr = sperm[sv.loc_off + qr], pc = sperm[sv.loc_off + qc];
+            if (pr < 0 || pc < 0) continue;
+            const int64_t hi = std::max(pr, pc) - d.loc_off, lw = std::min(pr, pc) - d.loc_off;
+            CHECK(hi >= 0 && hi < d.np && lw >= 0, "gather source");
+            const int th = (int)(hi / TS), tl = (int)(lw / TS);
+            if (tl >= F[th]) {
+              const int64_t t = off[th] + (tl - F[th]);
+              CHECK(t >= 0 && t < mstored, "gather main tile");
+            }
+          }
+        }
+      // the local solves: y in and out through sperm, scratch slice
+      for (int q = 0; q < sv.np; ++q) {
+        const int32_t ix = sperm[sv.loc_off + q];
+        CHECK(ix == -1 || (ix >= d.loc_off && ix < d.loc_off + d.np), "solve position %d of sub %d", q, i);
+      }
+      // k_chol_local on the solve envelope
+      for (int J = 0; J < sv.ntiles; ++J) {
+        int rows = 0;
+        for (int I = J + 1; I < sv.ntiles; ++I) if (Fs[I] <= J) { ++rows; stp(I, J); }
+        CHECK(rows <= 2048, "ROWCAP (solve layout)");
+      }
+      CHECK(sv.dinv_off + (int64_t)sv.ntiles * TT <= s_total_dinv, "solve dinv");
+    }
+    printf("solve layout (%s): %lld tiles against %lld\n", mode == 0 ? "global" : "split",
+           (long long)ftiles, (long long)(H.total_fac / TT));
   }
   for (size_t q = 0; q < H.own_pos.size(); ++q) CHECK(H.own_pos[q] >= 0 && H.own_pos[q] < H.total_loc, "own_pos");
   CHECK(H.own_ptr[n] == (int32_t)H.own_pos.size(), "own_ptr");

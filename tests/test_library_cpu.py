@@ -78,5 +78,6 @@ def test_host_plan_accesses_in_bounds(plan_check, name):
     r = subprocess.run([exe, path], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr + r.stdout
     assert r.stdout.splitlines()[-1].startswith("OK")
+    assert "solve layout (global)" in r.stdout and "solve layout (split)" in r.stdout
     if name == "irregular_16k":
         assert "row order: permuted" in r.stdout
