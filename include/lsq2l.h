@@ -167,7 +167,7 @@ typedef struct {
   double  t_eigen_ms;     /* coarse selection (reduced eigenproblems) and X_i            */
   double  t_coarse_ms;    /* W = A R_0^T, E = W^T W, Cholesky and inverse of E          */
   double  t_total_ms;     /* wall time of setup                                          */
-  int32_t spmv_lanes_A;   /* SpMV shape used with A: 0 = LDS row blocks, else lanes per row */
+  int32_t spmv_lanes_A;   /* SpMV shape used with A (see lsq2l_autotune)                    */
   int32_t spmv_lanes_AT;  /* the same for A^T                                              */
   double  t_prepare_ms;   /* reading, concatenating and validating the input (before
                              t_total_ms starts)                                         */
@@ -299,13 +299,16 @@ lsq2l_status lsq2l_time_kernel(lsq2l_handle h, int32_t kernel, int32_t reps, dou
  * Autotuner of the SpMV launch shape (the CSR products of Section 4.1's
  * iteration): for y = A x and x = A^T y on the handle's own matrix, times
  * every candidate shape with HIP events over `reps` launches each and keeps
- * the fastest for all later products of the handle.  Shapes: 0 = row blocks
- * of about 1024 entries staged through LDS, one thread summing each row (the
- * built-in choice); 1, 2, 4, ..., 64 = that many lanes per row.  lanes
- * (host, 2 entries, for A and A^T) receives the chosen shapes; with reps = 0
- * nothing is timed and the shapes are set from lanes instead (EINVAL unless
- * both are 0 or a power of two up to 64).  Results depend on the shape only
- * through the summation order inside a row.
+ * the fastest for all later products of the handle.  Shapes: -1 = row
+ * blocks of about 1024 entries staged through LDS, one thread summing each
+ * row; -2 = the same with non-temporal (streaming) loads of the matrix;
+ * 0 = the built-in choice, -2 when the matrix arrays (12 bytes per entry)
+ * exceed the 256 MB last-level cache and -1 otherwise; 1, 2, 4, ..., 64 =
+ * that many lanes per row.  The tuner times -2, -1 and the lane counts.
+ * lanes (host, 2 entries, for A and A^T) receives the chosen shapes; with
+ * reps = 0 nothing is timed and the shapes are set from lanes instead
+ * (EINVAL unless both are -2, -1, 0 or a power of two up to 64).  Results
+ * depend on the shape only through the summation order inside a row.
  */
 lsq2l_status lsq2l_autotune(lsq2l_handle h, int32_t reps, int32_t* lanes);
 

@@ -611,14 +611,45 @@ lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps);
 // on the order of Omega_i; the order [Omega_Ii, Omega_Gamma_i] that the
 // coarse selection needs makes the interface rows of L_i dense across the
 // interior.  Per subdomain, the global-column order of Omega_i is taken
-// when its tile envelope (found from the assembled C_ii by k_solve_env) has
-// at most 0.85 of the tiles of the [I, Gamma] one (opt.solve_order may force
+// when its tile envelope (found by the assembly, see k_assemble) has at
+// most 0.85 of the tiles of the [I, Gamma] one (opt.solve_order may force
 // either).  The mixed path always gets a solve layout (its float factors are
 // computed on their own); the FP64 path only when some subdomain is
-// permuted, else it solves with the selection's factors.  On return the
-// layout Ps is on the device, the gather of its matrix into *s64 (double)
-// is enqueued, and c->solve_plan tells whether it is used.  Called with the
-// assembled, equilibrated C_ii in c->fac.
+// permuted, else it solves with the selection's factors.
+//
+// solve_layout_begin, before the assembly: the candidate global-order
+// layouts and the position map, and the envelope's initial value.
+lsq2l_status solve_layout_begin(lsq2l_ctx* c) {
+  const hipStream_t st = c->st;
+  const HostPlan& H = c->H;
+  const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  c->sl_inv = nullptr;
+  if (!mixed && c->opt.solve_order == LSQ2L_ORDER_SPLIT) return LSQ2L_OK;
+  // global-order layouts: np = roundup(n_i), local-vector slices of
+  // max(np, [I, Gamma] np) entries
+  c->sl_g.assign(H.subs.begin(), H.subs.end());
+  int64_t tb = 0, lo = 0;
+  for (SubDesc& d : c->sl_g) {
+    const int32_t np_main = d.np;
+    d.np = (d.nI + d.nG + TS - 1) / TS * TS;
+    d.ntiles = d.np / TS;
+    d.tile_base = tb; tb += d.ntiles;
+    d.loc_off = lo; lo += std::max(np_main, d.np);
+  }
+  c->sl_tiles = tb;
+  c->sl_loc = lo;
+  TRY(c->upload(&c->sl_dg, c->sl_g));
+  TRY(c->dalloc(&c->sl_inv, H.total_loc));
+  TRY(c->dalloc(&c->sl_Fg, std::max<int64_t>(tb, 1)));
+  launch_solve_inv(st, c->nsub, c->P, c->sl_inv);
+  launch_solve_env_init(st, c->nsub, c->sl_dg, c->sl_Fg);
+  return LSQ2L_OK;
+}
+
+// solve_layout, after the assembly and equilibration (c->fac holds the
+// equilibrated C_ii, not yet factored): the choice, the layout Ps on the
+// device, and the gather of its matrix into *s64 (double), enqueued;
+// c->solve_plan tells whether it is used.
 lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
   const hipStream_t st = c->st;
   const HostPlan& H = c->H;
@@ -628,27 +659,12 @@ lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
   c->solve_plan = false;
   c->info.split_tiles = H.total_fac / TT;
   c->info.solve_permuted = 0;
-  if (!mixed && c->opt.solve_order == LSQ2L_ORDER_SPLIT) return LSQ2L_OK;
-  // global-order layouts: np = roundup(n_i), local-vector slices of
-  // max(np, [I, Gamma] np) entries
-  std::vector<SubDesc> g(H.subs.begin(), H.subs.end());
-  int64_t tb = 0, lo = 0;
-  for (SubDesc& d : g) {
-    const int32_t np_main = d.np;
-    d.np = (d.nI + d.nG + TS - 1) / TS * TS;
-    d.ntiles = d.np / TS;
-    d.tile_base = tb; tb += d.ntiles;
-    d.loc_off = lo; lo += std::max(np_main, d.np);
-  }
-  SubDesc* d_g = nullptr;
-  int32_t *inv = nullptr, *Fg = nullptr;
-  TRY(c->upload(&d_g, g));
-  TRY(c->dalloc(&inv, H.total_loc));
-  TRY(c->dalloc(&Fg, std::max<int64_t>(tb, 1)));
-  launch_solve_inv(st, nsub, c->P, inv);
-  launch_solve_env(st, nsub, c->P, d_g, c->fac, inv, Fg);
+  if (!c->sl_inv) return LSQ2L_OK;
+  const std::vector<SubDesc>& g = c->sl_g;
+  const int64_t tb = c->sl_tiles, lo = c->sl_loc;
+  int32_t* inv = c->sl_inv;
   std::vector<int32_t> hF((size_t)tb);
-  if (tb) LSQ2L_HIP_TRY(hipMemcpyAsync(hF.data(), Fg, sizeof(int32_t) * tb, hipMemcpyDeviceToHost, st));
+  if (tb) LSQ2L_HIP_TRY(hipMemcpyAsync(hF.data(), c->sl_Fg, sizeof(int32_t) * tb, hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   // choose per subdomain, then the layout's offsets
   std::vector<SubDesc> s(g);
@@ -796,7 +812,8 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   LSQ2L_HIP_TRY(hipMemsetAsync(c->status, 0, 8 * sizeof(int32_t), st));
   LSQ2L_HIP_TRY(hipMemsetAsync(c->fac, 0, H.total_fac * sizeof(double), st));
   if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(c->ctg, 0, H.total_g * sizeof(double), st));
-  launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg);
+  TRY(solve_layout_begin(c));
+  launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg, c->sl_inv, c->sl_dg, c->sl_Fg);
   // Global shift of Section 4.1 ("Setup phase"): the preconditioner is built
   // for C + s I, s = diag_shift_rel ||C||_F, i.e. for the least-squares
   // matrix [A; sqrt(s) I].  Its rows sqrt(s) e_j enter Xi_i for j in
@@ -854,7 +871,9 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     }
     LSQ2L_HIP_TRY(hipEventRecord(c->ev_join, c->st2));
   }
-  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status);
+  // with solve factors of their own, the selection's factor needs L_I and
+  // L_GI only (T = L_GI L_GI^T and X = L_I^{-T} L_GI^T Y)
+  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
   int32_t hstat[8];
   LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
@@ -1411,7 +1430,7 @@ lsq2l_status autotune_spmv(lsq2l_ctx* c, int reps) {
   for (int which = 0; which < 2; ++which) {
     int best = 0;
     float best_ms = 1e30f;
-    for (int g = 0; g <= 64; g = g ? 2 * g : 1) {
+    for (int g = SPMV_ROWS_STREAM; g <= 64; g = g < 1 ? g + 1 + (g == -1) : 2 * g) {
       auto once = [&]() {
         if (which == 0) launch_spmv(c->st, M.m, M.rowptr, M.colind, M.vals, c->p, c->tm2, g, M.nnz, M.blk);
         else launch_spmv(c->st, M.n, M.trowptr, M.trow, M.tvals, c->tm, c->q, g, M.nnz, M.tblk);
@@ -1691,8 +1710,13 @@ lsq2l_status lsq2l_autotune(lsq2l_handle c, int32_t reps, int32_t* lanes) {
   g_err.clear();
   if (!c || reps < 0 || (reps == 0 && !lanes)) { set_error("bad arguments"); return LSQ2L_EINVAL; }
   if (reps == 0) {
-    auto valid = [](int g) { return g == 0 || (g >= 1 && g <= 64 && (g & (g - 1)) == 0); };
-    if (!valid(lanes[0]) || !valid(lanes[1])) { set_error("SpMV shape must be 0 or a power of two up to 64"); return LSQ2L_EINVAL; }
+    auto valid = [](int g) {
+      return (g >= SPMV_ROWS_STREAM && g <= 0) || (g >= 1 && g <= 64 && (g & (g - 1)) == 0);
+    };
+    if (!valid(lanes[0]) || !valid(lanes[1])) {
+      set_error("SpMV shape must be -2, -1, 0 or a power of two up to 64");
+      return LSQ2L_EINVAL;
+    }
     c->M.spmv_group = c->Mi.spmv_group = lanes[0];
     c->M.spmvt_group = c->Mi.spmvt_group = lanes[1];
     c->info.spmv_lanes_A = lanes[0];

@@ -111,6 +111,12 @@ struct lsq2l_ctx {
   bool solve_plan = false;
   lsq2l::DevPlan Ps;
   int64_t s_total_fac = 0, s_total_dinv = 0, s_total_np = 0, s_total_tiles = 0;
+  // candidate global-order layouts of the setup (solve_layout_begin): host
+  // copy, device copy, position map and the tile envelope the assembly finds
+  std::vector<lsq2l::SubDesc> sl_g;
+  lsq2l::SubDesc* sl_dg = nullptr;
+  int32_t *sl_inv = nullptr, *sl_Fg = nullptr;
+  int64_t sl_tiles = 0, sl_loc = 0;
   double *sfac = nullptr, *sdinv = nullptr;
   float *fac32 = nullptr, *dinv32 = nullptr;
   float* X32 = nullptr;      // MIXED: FP32 copy of X for the restriction and prolongation

@@ -33,14 +33,16 @@ k_spmv(int32_t nrows, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // rows whose first entry lies in [b SPMV_NB, (b + 1) SPMV_NB): rows
 // tab[2b] .. tab[2b + 2] - 1, whose entries start at tab[2b + 1] (a table
 // made once per matrix, k_row_blocks), so that one 8-byte load gives the
-// block's extent.  The row starts of the block are staged in LDS while its
-// entries are read once, coalesced, eight per thread in flight, as
-// vals[e] x[colind[e]] into LDS; then every thread sums its rows from LDS in
-// entry order and writes y coalesced.  A block whose rows hold more than
-// SPMV_CAP entries (a long last row) sums each row with a wavefront instead.
-// Every row is summed in one fixed order, so runs are bitwise reproducible.
-constexpr int SPMV_NB = 2048, SPMV_CAP = SPMV_NB + 256, SPMV_RCAP = SPMV_NB, SPMV_THREADS = 256;
-constexpr int SPMV_U = 8;   // entries per thread and pass
+// block's extent.  Its entries are read once, coalesced, four per thread in
+// flight, as vals[e] x[colind[e]] into LDS; then every thread sums its rows
+// from LDS in entry order and writes y coalesced.  A block whose rows hold
+// more than SPMV_CAP entries (a long last row) sums each row with a
+// wavefront instead.  Every row is summed in one fixed order, so runs are
+// bitwise reproducible.  With STREAM the matrix arrays are read with
+// non-temporal loads, which keeps the caches for x when the matrix is
+// larger than the last-level cache.
+constexpr int SPMV_NB = 1024, SPMV_CAP = 2048, SPMV_THREADS = 256, SPMV_U = 4;
+constexpr int64_t SPMV_STREAM_BYTES = (int64_t)256 << 20;   // MI355X last-level cache
 
 int64_t spmv_blocks(int64_t nnz) { return std::max<int64_t>(1, (nnz + SPMV_NB - 1) / SPMV_NB); }
 int64_t spmv_table_len(int64_t nnz) { return 2 * (spmv_blocks(nnz) + 1); }
@@ -71,31 +73,33 @@ void launch_row_blocks(hipStream_t st, int32_t nrows, const int32_t* rowptr, int
   k_row_blocks<<<(unsigned)((nblk + 1 + 255) / 256), 256, 0, st>>>(nrows, rowptr, nblk, tab);
 }
 
+template <bool STREAM, typename V>
+__device__ inline V spmv_load(const V* p) {
+  if constexpr (STREAM) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool STREAM>
 __global__ void __launch_bounds__(SPMV_THREADS)
 k_spmv_stream(const int32_t* __restrict__ tab, const int32_t* __restrict__ rowptr,
               const int32_t* __restrict__ colind, const double* __restrict__ vals,
               const double* __restrict__ x, double* __restrict__ y) {
   __shared__ double prod[SPMV_CAP];
-  __shared__ int32_t rps[SPMV_RCAP + 1];
   const int tid = threadIdx.x;
   typedef int32_t i2 __attribute__((ext_vector_type(2)));
   const i2 lo = reinterpret_cast<const i2*>(tab)[blockIdx.x];
   const i2 hi = reinterpret_cast<const i2*>(tab)[blockIdx.x + 1];
   const int32_t r0 = lo.x, e0 = lo.y, r1 = hi.x, e1 = hi.y;
   if (r0 >= r1) return;
-  const int32_t nr = r1 - r0;
   if (e1 - e0 <= SPMV_CAP) {
-    const bool staged = nr <= SPMV_RCAP;
-    if (staged)
-      for (int32_t k = tid; k <= nr; k += SPMV_THREADS) rps[k] = rowptr[r0 + k] - e0;
     for (int32_t e = e0 + tid; e < e1; e += SPMV_U * SPMV_THREADS) {
       int32_t c[SPMV_U];
       double v[SPMV_U];
 #pragma unroll
       for (int u = 0; u < SPMV_U; ++u) {
         const int32_t q = e + u * SPMV_THREADS;
-        c[u] = q < e1 ? __builtin_nontemporal_load(colind + q) : 0;
-        v[u] = q < e1 ? __builtin_nontemporal_load(vals + q) : 0.0;
+        c[u] = q < e1 ? spmv_load<STREAM>(colind + q) : 0;
+        v[u] = q < e1 ? spmv_load<STREAM>(vals + q) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < SPMV_U; ++u) {
@@ -104,12 +108,11 @@ k_spmv_stream(const int32_t* __restrict__ tab, const int32_t* __restrict__ rowpt
       }
     }
     __syncthreads();
-    for (int32_t r = tid; r < nr; r += SPMV_THREADS) {
-      const int32_t a = staged ? rps[r] : rowptr[r0 + r] - e0;
-      const int32_t b = staged ? rps[r + 1] : rowptr[r0 + r + 1] - e0;
+    for (int32_t r = r0 + tid; r < r1; r += SPMV_THREADS) {
+      const int32_t a = rowptr[r] - e0, b = rowptr[r + 1] - e0;
       double s = 0.0;
       for (int32_t k = a; k < b; ++k) s += prod[k];
-      y[r0 + r] = s;
+      y[r] = s;
     }
     return;
   }
@@ -124,16 +127,22 @@ k_spmv_stream(const int32_t* __restrict__ tab, const int32_t* __restrict__ rowpt
   }
 }
 
-// group 0: the LDS-staged kernel above; 1 .. 64: that many lanes per row
+// group 0: row blocks, streaming loads if the matrix arrays (12 bytes per
+// entry) exceed the last-level cache; -1 / -2: row blocks with cached /
+// streaming loads; 1 .. 64: that many lanes per row
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
                  const double* vals, const double* x, double* y, int group, int64_t nnz,
                  const int32_t* blk) {
   if (nrows == 0) return;
-  if (group == 0 && blk) {
-    k_spmv_stream<<<(unsigned)spmv_blocks(nnz), SPMV_THREADS, 0, st>>>(blk, rowptr, colind, vals, x, y);
+  if (group == 0) group = 12 * nnz > SPMV_STREAM_BYTES ? SPMV_ROWS_STREAM : SPMV_ROWS_CACHED;
+  if (group < 0 && blk) {
+    if (group == SPMV_ROWS_STREAM)
+      k_spmv_stream<true><<<(unsigned)spmv_blocks(nnz), SPMV_THREADS, 0, st>>>(blk, rowptr, colind, vals, x, y);
+    else
+      k_spmv_stream<false><<<(unsigned)spmv_blocks(nnz), SPMV_THREADS, 0, st>>>(blk, rowptr, colind, vals, x, y);
     return;
   }
-  if (group == 0) group = 1;
+  if (group < 0) group = 1;
   const int64_t threads = (int64_t)nrows * group;
   const unsigned blocks = (unsigned)((threads + 255) / 256);
   switch (group) {

@@ -41,6 +41,10 @@ __device__ inline int local_pos(int i, int c, const int32_t* __restrict__ part,
 // so the accumulation order is fixed and no atomics are needed.  Workgroup
 // (i, y) takes the columns y * 256 + t, (y + gridDim.y) * 256 + t, ... of
 // subdomain i, so that a large subdomain spreads over several compute units.
+// With inv given, it also finds the tile envelope of C_ii in the global
+// column order (see k_solve_inv): the thread of column a sees every column
+// coupled to it, so the first coupled position of row inv[a] in that order
+// is the minimum it meets, one atomicMin per column into Fg.
 __global__ void __launch_bounds__(256)
 k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
@@ -48,9 +52,11 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const double* __restrict__ vals, const int32_t* __restrict__ trowptr,
            const int32_t* __restrict__ trow, const double* __restrict__ tvals,
            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
-           double* __restrict__ fac, double* __restrict__ ctg) {
+           double* __restrict__ fac, double* __restrict__ ctg, const int32_t* __restrict__ inv,
+           const SubDesc* __restrict__ gsub, int32_t* __restrict__ Fg) {
   const SubDesc d = subs[blockIdx.x];
   const int i = d.id;
+  const int32_t* iv = inv ? inv + d.loc_off : nullptr;
   const int32_t* om = omega + d.omega_off;
   const int32_t* G = om + d.nI;
   const int32_t* F = tileF + d.tile_base;
@@ -61,6 +67,8 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
     const int j = om[a];
     const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
     const int ta = posa / TS, ra = posa % TS;
+    const int qa = iv ? iv[posa] : 0;
+    int fmin = qa;
     for (int k = trowptr[j]; k < trowptr[j + 1]; ++k) {
       const int r = trow[k];
       const double va = tvals[k];
@@ -69,6 +77,7 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
       for (int e = e0; e < e1; ++e) inxi |= (part[colind[e]] == i);
       for (int e = e0; e < e1; ++e) {
         const int posc = local_pos(i, colind[e], part, locown, G, d.nG, d.nIp);
+        if (iv && posc >= 0) fmin = min(fmin, iv[posc]);
         if (posc < posa) continue;
         const double v = vals[e] * va;
         const int tc = posc / TS;
@@ -76,6 +85,7 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
         if (inxi && a >= d.nI) Ct[(int64_t)(posa - d.nIp) * d.nGp + (posc - d.nIp)] += v;
       }
     }
+    if (iv) atomicMin(&Fg[gsub[i].tile_base + qa / TS], fmin / TS);
   }
 }
 
@@ -162,12 +172,16 @@ constexpr int ROWCAP = 2048;
 // registers (one step ahead, see below), L(I,J) = A(I,J) L(J,J)^{-T} for the
 // envelope rows, then A(I,K) -= L(I,J) L(K,J)^T for every pair of envelope
 // rows (MFMA).  Wave 0 applies column J to tile (J+1, J+1) first and factors
-// it while the other waves work through the remaining pairs.
+// it while the other waves work through the remaining pairs.  T is double or
+// float (FP32 MFMA with FP32 accumulation).  With interior_only, the factor
+// stops after the interior tile columns and the interface rows never update
+// each other: the result holds L_I and L_GI only (what the coarse selection
+// reads; the local solves then use factors of their own).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
              const int64_t* __restrict__ tileOff, T* __restrict__ fac, T* __restrict__ dinv,
-             int32_t* __restrict__ status) {
+             int32_t* __restrict__ status, int interior_only) {
   __shared__ T sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
   __shared__ int32_t rows[ROWCAP];
   __shared__ int s_count, s_ok;
@@ -186,14 +200,18 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
     const bool okw = tile_potrf_inv_reg(sW, sL, sInv, lane);
     if (lane == 0) s_ok = okw;
   };
-  if (wave == 0 && d.ntiles > 0) {
+  // tile columns to factor, and the first row of the block whose mutual
+  // updates are skipped
+  const int ncol = interior_only ? d.ntI : d.ntiles;
+  const int skip_from = interior_only ? d.ntI : d.ntiles;
+  if (wave == 0 && ncol > 0) {
     const T* A00 = A + tile_pos(F, off, 0, 0) * TT;
     for (int e = lane; e < TT; e += 64) sW[(e / TS) * LDT + e % TS] = A00[e];
     wave_sync();
     diag_factor();
   }
   __syncthreads();
-  for (int J = 0; J < d.ntiles; ++J) {
+  for (int J = 0; J < ncol; ++J) {
     T* Ajj = A + tile_pos(F, off, J, J) * TT;
     const bool ok = s_ok;
     if (!ok) failed = true;
@@ -215,7 +233,7 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
     // and is factored by wave 0 while the other waves take the remaining
     // pairs (a >= b) of envelope rows from a shared counter; wave 0 joins
     // them when done
-    const bool next = J + 1 < d.ntiles;
+    const bool next = J + 1 < ncol;
     const bool next_coupled = next && nr > 0 && rows[0] == J + 1;
     const int npairs = nr * (nr + 1) / 2;
     if (tid == 0) s_next = next_coupled ? 1 : 0;
@@ -244,6 +262,7 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
       while ((a + 1) * (a + 2) / 2 <= it) ++a;
       const int b = it - a * (a + 1) / 2;
       const int Ia = rows[a], Ib = rows[b];
+      if (Ib >= skip_from) continue;     // both rows at or past skip_from (rows ascend)
       const T* La = A + tile_pos(F, off, Ia, J) * TT;
       const T* Lb = A + tile_pos(F, off, Ib, J) * TT;
       T* Cab = A + tile_pos(F, off, Ia, Ib) * TT;
@@ -258,9 +277,9 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
 }
 
 template __global__ void k_chol_local<double>(const SubDesc*, const int32_t*, const int64_t*,
-                                              double*, double*, int32_t*);
+                                              double*, double*, int32_t*, int);
 template __global__ void k_chol_local<float>(const SubDesc*, const int32_t*, const int64_t*,
-                                             float*, float*, int32_t*);
+                                             float*, float*, int32_t*, int);
 
 // ---------------------------------------------------------------------------
 // The factor used by the per-iteration local solves.  C_ii^{-1} r does not
@@ -305,36 +324,6 @@ __global__ void __launch_bounds__(256)
 k_solve_env_init(const SubDesc* __restrict__ gsub, int32_t* __restrict__ Fg) {
   const SubDesc g = gsub[blockIdx.x];
   for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) Fg[g.tile_base + t] = t;
-}
-
-// Tile envelope of the global-order layout: for every nonzero C_ii(r, c),
-// r >= c, of the assembled matrix, tile row max(q_r, q_c) / 32 reaches tile
-// column min(q_r, q_c) / 32.  Workgroup (i, y) reads the tile rows
-// y, y + gridDim.y, ... of subdomain i's [I, Gamma] envelope.
-__global__ void __launch_bounds__(256)
-k_solve_env(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ gsub,
-            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
-            const double* __restrict__ fac, const int32_t* __restrict__ inv,
-            int32_t* __restrict__ Fg) {
-  const SubDesc d = subs[blockIdx.x];
-  const SubDesc g = gsub[d.id];
-  const int32_t* F = tileF + d.tile_base;
-  const int64_t* off = tileOff + d.tile_base;
-  const double* A = fac + d.fac_off;
-  const int32_t* iv = inv + d.loc_off;
-  int32_t* Fo = Fg + g.tile_base;
-  for (int I = blockIdx.y; I < d.ntiles; I += gridDim.y) {
-    const int nk = I - F[I] + 1;
-    const double* row = A + off[I] * TT;
-    for (int e = threadIdx.x; e < nk * TT; e += blockDim.x) {
-      const int J = F[I] + e / TT, rc = e % TT;
-      const int r = I * TS + rc % TS, c = J * TS + rc / TS;
-      if (r < c || row[e] == 0.0) continue;
-      const int qr = iv[r], qc = iv[c];
-      if (qr < 0 || qc < 0) continue;
-      atomicMin(&Fo[max(qr, qc) / TS], min(qr, qc) / TS);
-    }
-  }
 }
 
 // sperm[loc_off + q] = loc index of the entry the solve layout holds at
@@ -468,13 +457,13 @@ void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, cons
 }
 
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
-                     double* ctg) {
+                     double* ctg, const int32_t* inv, const SubDesc* gsub, int32_t* Fg) {
   // workgroups per subdomain: enough for the largest one to take 2 columns
   // per thread (at most 64)
   const int ny = std::max(1, std::min(64, (P.max_np + 511) / 512));
   k_assemble<<<dim3(nsub, ny), 256, 0, st>>>(P.heavy(), P.omega, P.part, P.locown, M.rowptr,
                                              M.colind, M.vals, M.trowptr, M.trow, M.tvals, P.tileF,
-                                             P.tileOff, fac, ctg);
+                                             P.tileOff, fac, ctg, inv, gsub, Fg);
 }
 
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
@@ -484,18 +473,17 @@ void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac,
 }
 
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
-                       int32_t* status) {
-  k_chol_local<double><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status);
+                       int32_t* status, bool interior_only) {
+  k_chol_local<double><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status,
+                                             interior_only ? 1 : 0);
 }
 
 void launch_solve_inv(hipStream_t st, int nsub, const DevPlan& P, int32_t* inv) {
   k_solve_inv<<<nsub, 256, 0, st>>>(P.heavy(), P.omega, inv);
 }
 
-void launch_solve_env(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* gsub,
-                      const double* fac, const int32_t* inv, int32_t* Fg) {
+void launch_solve_env_init(hipStream_t st, int nsub, const SubDesc* gsub, int32_t* Fg) {
   k_solve_env_init<<<nsub, 256, 0, st>>>(gsub, Fg);
-  k_solve_env<<<dim3(nsub, 16), 256, 0, st>>>(P.heavy(), gsub, P.tileF, P.tileOff, fac, inv, Fg);
 }
 
 void launch_solve_perm(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* ssub,
@@ -511,7 +499,7 @@ void launch_gather_solve(hipStream_t st, int nsub, const DevPlan& P, const DevPl
 
 void launch_chol_local_f32(hipStream_t st, int nsub, const DevPlan& P, float* fac, float* dinv,
                            int32_t* status) {
-  k_chol_local<float><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status);
+  k_chol_local<float><<<nsub, 256, 0, st>>>(P.heavy(), P.tileF, P.tileOff, fac, dinv, status, 0);
 }
 
 void launch_to_float(hipStream_t st, int64_t n, const double* src, float* dst) {

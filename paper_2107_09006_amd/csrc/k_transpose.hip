@@ -1,5 +1,5 @@
 // CSR transpose of A on the device (the A^T of the products A^T y, of the
-// assembly and of the adjoint; its pattern is read back by the host planner).
+// assembly and of the adjoint).
 //
 // The entries are sorted by column with a least-significant-digit radix sort
 // on the column index (8-bit digits, as many passes as the column count

@@ -85,7 +85,10 @@ void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32
 
 // --- sparse kernels -------------------------------------------------------
 // group 0: row blocks staged through LDS (needs the block table blk of the
-// matrix, else one lane per row); 1 .. 64: lanes per row
+// matrix, else one lane per row), their loads streaming if the matrix is
+// larger than the last-level cache; SPMV_ROWS_CACHED / SPMV_ROWS_STREAM: row
+// blocks with cached / streaming loads; 1 .. 64: lanes per row
+enum { SPMV_ROWS_CACHED = -1, SPMV_ROWS_STREAM = -2 };
 void launch_spmv(hipStream_t st, int32_t nrows, const int32_t* rowptr, const int32_t* colind,
                  const double* vals, const double* x, double* y, int group, int64_t nnz,
                  const int32_t* blk);
@@ -169,22 +172,25 @@ void launch_seg_sum(hipStream_t st, int S, const double* partial, double* out);
 // --- subdomain kernels -------------------------------------------------------
 void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, const double* src,
                           double* dst);
+// with inv (not null), also the tile envelope Fg of the global-order
+// layouts gsub (Fg set by launch_solve_env_init first)
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
-                     double* ctg);
+                     double* ctg, const int32_t* inv = nullptr, const SubDesc* gsub = nullptr,
+                     int32_t* Fg = nullptr);
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
                         double* scale);
+// interior_only: factor the interior tile columns only (L_I and L_GI)
 void launch_chol_local(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* dinv,
-                       int32_t* status);
+                       int32_t* status, bool interior_only = false);
 // the same in FP32 (FP32 MFMA, FP32 accumulation)
 void launch_chol_local_f32(hipStream_t st, int nsub, const DevPlan& P, float* fac, float* dinv,
                            int32_t* status);
 // solve factor in the global-column order of each subdomain: inv (indexed
 // like loc) maps an [I, Gamma] position to its global-order position;
-// gsub describes the global-order layout (np, ntiles, tile_base); Fg gets
-// its tile envelope from the assembled C_ii
+// gsub describes the global-order layout (np, ntiles, tile_base); Fg,
+// initialized here to the diagonal, gets its tile envelope from the assembly
 void launch_solve_inv(hipStream_t st, int nsub, const DevPlan& P, int32_t* inv);
-void launch_solve_env(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* gsub,
-                      const double* fac, const int32_t* inv, int32_t* Fg);
+void launch_solve_env_init(hipStream_t st, int nsub, const SubDesc* gsub, int32_t* Fg);
 // Ps.sperm (filled with -1 first) from the chosen layouts (ssub.spare set:
 // global order)
 void launch_solve_perm(hipStream_t st, int nsub, const DevPlan& P, const SubDesc* ssub,

@@ -270,7 +270,8 @@ def test_autotune_keeps_products_exact(L):
     A = p.scipy()
     s = solver(L, p, autotune=1)
     la, lat = s.info()["spmv_lanes_A"], s.info()["spmv_lanes_AT"]
-    assert la in (0, 1, 2, 4, 8, 16, 32, 64) and lat in (0, 1, 2, 4, 8, 16, 32, 64)
+    shapes = (-2, -1, 1, 2, 4, 8, 16, 32, 64)      # the timed candidates
+    assert la in shapes and lat in shapes
     assert (la, lat) == s.autotune(reps=3) or True      # timing may pick another shape
     rng = np.random.default_rng(0)
     x = rng.standard_normal(p.n)
@@ -284,7 +285,7 @@ def test_autotune_keeps_products_exact(L):
     s.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("shape", [-2, -1, 0, 1, 2, 4, 8, 16, 32, 64])
 def test_every_spmv_shape_on_long_short_and_empty_rows(L, shape):
     """Each SpMV launch shape, set explicitly, against the product in FP64 on
     rows of 0 to 5000 entries: single-entry rows, empty rows (among the rows
@@ -312,8 +313,9 @@ def test_every_spmv_shape_on_long_short_and_empty_rows(L, shape):
     bound = lambda B, v: 2 * nmax * EPS * (B @ np.abs(v)) + 1e-300
     assert np.all(np.abs(_np(s.spmv(_t(x))) - A @ x) <= bound(absA, x))
     assert np.all(np.abs(_np(s.spmv(_t(y), trans=True)) - A.T @ y) <= bound(absA.T, y))
-    with pytest.raises(L.Lsq2lError):
-        s.autotune(reps=0, shapes=(3, 0))
+    for bad in (3, -3, 128):
+        with pytest.raises(L.Lsq2lError):
+            s.autotune(reps=0, shapes=(bad, 0))
     s.close()
 
 
