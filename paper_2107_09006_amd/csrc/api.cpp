@@ -1232,88 +1232,9 @@ bool is_device_ptr(const void* p) {
   return at.type == hipMemoryTypeDevice;
 }
 
-// Validation of all instances at once, on host threads over ranges of the
-// concatenated rows: row extents (int64 row pointers rp64 of instance k at
-// rp64 + r0_k + k, m_k + 1 each) first, so that the column pass reads inside
-// ci, then the columns (already shifted by the instance's first column, so
-// valid in [col0_k, col0_k + n_k)) in strictly increasing order per row.
-// The int32 row pointers of the concatenation are written on the way.  The
-// first failing row of the first failing pass is reported.
-lsq2l_status validate_all(int count, const lsq2l_problem* probs, const std::vector<int64_t>& r0,
-                          const std::vector<int64_t>& c0, const std::vector<int64_t>& e0,
-                          const int64_t* rp64, const int32_t* ci, int32_t* rp32) {
-  const int64_t M = r0[count];
-  for (int k = 0; k < count; ++k) {
-    const int64_t* lrp = rp64 + r0[k] + k;
-    const std::string who = count > 1 ? "problem " + std::to_string(k) + ": " : std::string();
-    if (lrp[0] != 0) { set_error(who + "rowptr[0] must be 0"); return LSQ2L_EINVAL; }
-    if (lrp[probs[k].m] != probs[k].nnz) { set_error(who + "rowptr[m] != nnz"); return LSQ2L_EINVAL; }
-  }
-  const unsigned nth = M < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<int64_t> bad_row(nth, INT64_MAX);
-  std::vector<int> bad_kind(nth, 0), bad_inst(nth, 0);
-  auto run = [&](auto&& fn) {
-    if (nth == 1) {
-      fn(0u);
-    } else {
-      std::vector<std::thread> pool;
-      for (unsigned t = 0; t < nth; ++t) pool.emplace_back(fn, t);
-      for (auto& th : pool) th.join();
-    }
-  };
-  // visit(t, fn): rows [M t / nth, M (t + 1) / nth) as (instance, local row)
-  auto visit = [&](unsigned t, auto&& fn) {
-    const int64_t g0 = M * t / nth, g1 = M * (t + 1) / nth;
-    int k = (int)(std::upper_bound(r0.begin(), r0.end(), g0) - r0.begin()) - 1;
-    for (int64_t g = g0; g < g1; ++g) {
-      while (g >= r0[k + 1]) ++k;
-      if (!fn(k, g - r0[k], g)) return;
-    }
-  };
-  run([&](unsigned t) {
-    visit(t, [&](int k, int64_t r, int64_t g) {
-      const int64_t* lrp = rp64 + r0[k] + k;
-      if (lrp[r + 1] < lrp[r] || lrp[r + 1] > probs[k].nnz) {
-        bad_row[t] = r; bad_kind[t] = 1; bad_inst[t] = k;
-        return false;
-      }
-      rp32[g + 1] = (int32_t)(e0[k] + lrp[r + 1]);
-      return true;
-    });
-  });
-  bool extents_ok = true;
-  for (unsigned t = 0; t < nth; ++t) extents_ok = extents_ok && !bad_kind[t];
-  if (extents_ok)
-    run([&](unsigned t) {
-      visit(t, [&](int k, int64_t r, int64_t) {
-        const int64_t* lrp = rp64 + r0[k] + k;
-        const int32_t* lci = ci + e0[k];
-        const int64_t lo = c0[k], hi = c0[k] + probs[k].n;
-        for (int64_t e = lrp[r]; e < lrp[r + 1]; ++e) {
-          int kind = 0;
-          if (lci[e] < lo || lci[e] >= hi) kind = 2;
-          else if (e > lrp[r] && lci[e] <= lci[e - 1]) kind = 3;
-          if (kind) { bad_row[t] = r; bad_kind[t] = kind; bad_inst[t] = k; return false; }
-        }
-        return true;
-      });
-    });
-  rp32[0] = 0;
-  for (unsigned t = 0; t < nth; ++t) {
-    if (!bad_kind[t]) continue;
-    const std::string who = count > 1 ? "problem " + std::to_string(bad_inst[t]) + ": " : std::string();
-    const std::string r = std::to_string(bad_row[t]);
-    if (bad_kind[t] == 1) set_error(who + "rowptr is not monotone (or exceeds nnz) at row " + r);
-    else if (bad_kind[t] == 2) set_error(who + "column index out of range in row " + r);
-    else set_error(who + "columns not strictly increasing in row " + r);
-    return LSQ2L_EINVAL;
-  }
-  return LSQ2L_OK;
-}
-
-// Setup of one or several instances: their CSR arrays are concatenated on
-// the device (row pointers narrowed to int32 and shifted, columns shifted),
-// the patterns read back once into pinned memory and validated on the host.
+// Setup of one or several instances: their CSR arrays are concatenated and
+// checked on the device in three launches (launch_concat), and the
+// concatenated pattern is read back once into pinned memory for the planner.
 lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs) {
   auto t_prep = clk::now();
   const hipStream_t st = c->st;
@@ -1339,33 +1260,36 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   TRY(c->dalloc(&c->M.rowptr, M + 1));
   TRY(c->dalloc(&c->M.colind, NNZ));
   TRY(c->dalloc(&c->M.vals, NNZ));
-  PinnedArray<int64_t> rp64;
-  PinnedArray<int32_t> ci;
-  TRY(rp64.alloc(M + count));
-  TRY(ci.alloc(NNZ));
   std::vector<int64_t> r0(count + 1, 0), c0(count + 1, 0), e0(count + 1, 0), p0(count + 1, 0);
+  std::vector<InstDesc> desc(count);
   for (int k = 0; k < count; ++k) {
     r0[k + 1] = r0[k] + probs[k].m;
     c0[k + 1] = c0[k] + probs[k].n;
     e0[k + 1] = e0[k] + probs[k].nnz;
     p0[k + 1] = p0[k] + probs[k].nparts;
-  }
-  for (int k = 0; k < count; ++k) {
-    const lsq2l_problem& pr = probs[k];
-    launch_narrow_i64(st, pr.m + 1, pr.rowptr, 0, (int32_t)e0[k], c->M.rowptr + r0[k]);
-    launch_offset_i32(st, pr.nnz, pr.colind, (int32_t)c0[k], c->M.colind + e0[k]);
-    if (pr.nnz) LSQ2L_HIP_TRY(hipMemcpyAsync(c->M.vals + e0[k], pr.vals, pr.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-    LSQ2L_HIP_TRY(hipMemcpyAsync(rp64.p + r0[k] + k, pr.rowptr, (pr.m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    desc[k] = InstDesc{probs[k].rowptr, probs[k].colind, probs[k].vals, probs[k].m, probs[k].n,
+                       probs[k].nnz, r0[k], c0[k], e0[k]};
   }
   for (int k = 0; k <= count; ++k) {
     c->seg_row_h[k] = r0[k];
     c->seg_col_h[k] = c0[k];
   }
+  InstDesc* d_desc = nullptr;
+  unsigned long long* d_bad = nullptr;
+  TRY(c->upload(&d_desc, desc));
+  TRY(c->dalloc(&d_bad, CSR_KINDS));
+  launch_concat(st, count, d_desc, M, NNZ, c->M.rowptr, c->M.colind, c->M.vals, d_bad);
+  PinnedArray<int32_t> rp, ci;
+  TRY(rp.alloc(M + 1));
+  TRY(ci.alloc(NNZ));
+  unsigned long long hbad[CSR_KINDS];
+  LSQ2L_HIP_TRY(hipMemcpyAsync(hbad, d_bad, sizeof(hbad), hipMemcpyDeviceToHost, st));
+  LSQ2L_HIP_TRY(hipMemcpyAsync(rp.p, c->M.rowptr, (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   if (NNZ) LSQ2L_HIP_TRY(hipMemcpyAsync(ci.p, c->M.colind, NNZ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   // partitions: host arrays are read in place, device arrays copied back
-  HostVec<int32_t> pt, rp;
+  HostVec<int32_t> pt;
   std::vector<int32_t> seg_of_part(NP);
-  if (!pt.resize(N) || !rp.resize(M + 1)) { set_error("host allocation failed"); return LSQ2L_ENOMEM; }
+  if (!pt.resize(N)) { set_error("host allocation failed"); return LSQ2L_ENOMEM; }
   std::vector<PinnedArray<int32_t>> pdev(count);
   for (int k = 0; k < count; ++k)
     if (is_device_ptr(probs[k].part)) {
@@ -1374,7 +1298,21 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
     }
   const hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return LSQ2L_EHIP; }
-  TRY(validate_all(count, probs, r0, c0, e0, rp64.p, ci.p, rp.data()));
+  // the first failure in the order of the checks: row extents, then columns
+  // (reported only when the extents hold)
+  for (int kind : {CSR_FIRST, CSR_LAST, CSR_MONO, CSR_RANGE, CSR_ORDER}) {
+    if (hbad[kind] == ~0ull) continue;
+    const int64_t g = (int64_t)hbad[kind];
+    const int k = (int)(std::upper_bound(r0.begin(), r0.end(), g) - r0.begin()) - 1;
+    const std::string who = count > 1 ? "problem " + std::to_string(k) + ": " : std::string();
+    const std::string row = std::to_string(g - r0[k]);
+    static const char* what[CSR_KINDS] = {"rowptr[0] must be 0", "rowptr[m] != nnz",
+                                          "rowptr is not monotone (or exceeds nnz) at row ",
+                                          "column index out of range in row ",
+                                          "columns not strictly increasing in row "};
+    set_error(who + what[kind] + (kind >= CSR_MONO ? row : std::string()));
+    return LSQ2L_EINVAL;
+  }
   // global part numbers, checked, in parallel over column ranges
   {
     const unsigned nth = N < (1 << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -1407,7 +1345,7 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   for (int k = 0; k < count; ++k)
     for (int32_t q = 0; q < probs[k].nparts; ++q) seg_of_part[p0[k] + q] = k;
   c->info.t_prepare_ms = ms_since(t_prep);
-  return setup_core(c, rp.data(), ci.p, pt, (int32_t)NP, seg_of_part);
+  return setup_core(c, rp.p, ci.p, pt, (int32_t)NP, seg_of_part);
 }
 
 lsq2l_ctx* new_handle(double tau, const lsq2l_options* opt, void* hip_stream) {

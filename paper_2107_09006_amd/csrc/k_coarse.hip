@@ -168,6 +168,9 @@ __device__ inline void tile_io_cols(double4_t acc[4], double* C, int ldc, int nb
 }
 
 constexpr int XS_MAXROWS = 8192, XS_MAXP = 1024;   // LDS copies of S_I and sigma (p <= 1024 always)
+// the backward substitution keeps F, the tile offsets and the last envelope
+// row of every interior tile column in LDS (aliasing the copies of S_I)
+constexpr int XS_TMAX = XS_MAXROWS * 2 / 3;
 // X_i = S_I L_I^{-T} (L_GI^T Y) diag(1/sigma), written as nIp x p (column-major).
 // H = L_GI^T Y by 32 x 32 output blocks (one per wave task), then the
 // backward substitution with L_I^T by tile rows (left-looking, a wave per
@@ -240,6 +243,24 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
     }
   }
   __syncthreads();
+  // envelope of the interior in LDS: F, the tile offsets and, per tile
+  // column I, the last interior tile row K with F(K) <= I (the backward
+  // substitution then visits only the rows that can hold a tile of column I)
+  int32_t* sF = reinterpret_cast<int32_t*>(sXs);
+  int32_t* sOff = sF + XS_TMAX;
+  int32_t* sLast = sOff + XS_TMAX;
+  const bool staged = d.ntI <= XS_TMAX;
+  if (staged) {
+    for (int K = tid; K < d.ntI; K += nthr) {
+      sF[K] = F[K];
+      sOff[K] = (int32_t)off[K];
+      sLast[K] = K;
+    }
+    __syncthreads();
+    for (int K = tid; K < d.ntI; K += nthr)
+      for (int I = sF[K]; I < K; ++I) atomicMax(&sLast[I], K);
+    __syncthreads();
+  }
   // backward substitution with L_I^T, left-looking, one wave per block of 32
   // columns with no block barriers: for I from the last tile row down,
   // X_I = Dinv_I^T (H_I - sum over K > I with F(K) <= I of L(K,I)^T X_K)
@@ -249,9 +270,14 @@ k_coarse_X(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF,
     for (int I = d.ntI - 1; I >= 0; --I) {
       double4_t acc[4];
       tile_io_cols(acc, Hp + I * TS, ldh, nb, lane, false);
-      for (int K = I + 1; K < d.ntI; ++K)
-        if (F[K] <= I)
-          tile_mma_cols<true>(acc, A + tile_pos(F, off, K, I) * TT, TS, Hp + K * TS, ldh, nb, lane, true);
+      const int kend = staged ? sLast[I] : d.ntI - 1;
+      for (int K = I + 1; K <= kend; ++K) {
+        const int fk = staged ? sF[K] : F[K];
+        if (fk <= I) {
+          const int64_t t = staged ? (int64_t)sOff[K] + (I - fk) : tile_pos(F, off, K, I);
+          tile_mma_cols<true>(acc, A + t * TT, TS, Hp + K * TS, ldh, nb, lane, true);
+        }
+      }
       tile_io_cols(acc, Hp + I * TS, ldh, nb, lane, true);
       wg_fence();
       tile_acc_zero<double>(acc);

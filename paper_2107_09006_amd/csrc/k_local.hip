@@ -166,6 +166,7 @@ __device__ inline int envelope_rows(const int32_t* F, int J, int ntiles, int32_t
 }
 
 constexpr int ROWCAP = 2048;
+constexpr int CHOL_TMAX = 2048;   // tile rows whose envelope the factorization keeps in LDS
 
 // Right-looking tile Cholesky of one envelope matrix per workgroup:
 // for each tile column J: the diagonal tile factored and inverted in
@@ -184,10 +185,24 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
              int32_t* __restrict__ status, int interior_only) {
   __shared__ T sW[TS * LDT], sL[TS * LDT], sInv[TS * LDT];
   __shared__ int32_t rows[ROWCAP];
+  __shared__ int32_t sF[CHOL_TMAX], sO[CHOL_TMAX];
   __shared__ int s_count, s_ok;
   const SubDesc d = subs[blockIdx.x];
   const int32_t* F = tileF + d.tile_base;
   const int64_t* off = tileOff + d.tile_base;
+  // the envelope (first tile column and offset of each tile row) in LDS, so
+  // that finding a tile costs no global round trip
+  const bool staged = d.ntiles <= CHOL_TMAX;
+  if (staged)
+    for (int I = threadIdx.x; I < d.ntiles; I += blockDim.x) {
+      sF[I] = F[I];
+      sO[I] = (int32_t)off[I];
+    }
+  __syncthreads();
+  const int32_t* Fp = staged ? sF : F;
+  auto tpos = [&](int I, int J) -> int64_t {
+    return staged ? (int64_t)sO[I] + (J - sF[I]) : tile_pos(F, off, I, J);
+  };
   T* A = fac + d.fac_off;
   T* Di = dinv + d.dinv_off;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -205,25 +220,25 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
   const int ncol = interior_only ? d.ntI : d.ntiles;
   const int skip_from = interior_only ? d.ntI : d.ntiles;
   if (wave == 0 && ncol > 0) {
-    const T* A00 = A + tile_pos(F, off, 0, 0) * TT;
+    const T* A00 = A + tpos(0, 0) * TT;
     for (int e = lane; e < TT; e += 64) sW[(e / TS) * LDT + e % TS] = A00[e];
     wave_sync();
     diag_factor();
   }
   __syncthreads();
   for (int J = 0; J < ncol; ++J) {
-    T* Ajj = A + tile_pos(F, off, J, J) * TT;
+    T* Ajj = A + tpos(J, J) * TT;
     const bool ok = s_ok;
     if (!ok) failed = true;
     for (int e = tid; e < TT; e += nthr) {
       Ajj[e] = sL[(e / TS) * LDT + e % TS];
       Di[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
     }
-    const int nr = envelope_rows(F, J, d.ntiles, rows, ROWCAP, &s_count);
+    const int nr = envelope_rows(Fp, J, d.ntiles, rows, ROWCAP, &s_count);
     if (nr > ROWCAP) { failed = true; break; }
     // panel
     for (int a = wave; a < nr; a += nwaves) {
-      T* Aij = A + tile_pos(F, off, rows[a], J) * TT;
+      T* Aij = A + tpos(rows[a], J) * TT;
       typename Mfma<T>::acc_t acc[4];
       tile_acc_zero<T>(acc);
       tile_mma_nt<T, false>(acc, Aij, TS, sInv, LDT, lane);
@@ -239,9 +254,9 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
     if (tid == 0) s_next = next_coupled ? 1 : 0;
     __syncthreads();
     if (wave == 0 && next) {
-      const T* Ann = A + tile_pos(F, off, J + 1, J + 1) * TT;
+      const T* Ann = A + tpos(J + 1, J + 1) * TT;
       if (next_coupled) {
-        const T* Ln = A + tile_pos(F, off, J + 1, J) * TT;
+        const T* Ln = A + tpos(J + 1, J) * TT;
         typename Mfma<T>::acc_t acc[4];
         tile_acc_load<T>(acc, Ann, TS, lane);
         tile_mma_nt<T, true>(acc, Ln, TS, Ln, TS, lane);
@@ -263,9 +278,9 @@ k_chol_local(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tileF
       const int b = it - a * (a + 1) / 2;
       const int Ia = rows[a], Ib = rows[b];
       if (Ib >= skip_from) continue;     // both rows at or past skip_from (rows ascend)
-      const T* La = A + tile_pos(F, off, Ia, J) * TT;
-      const T* Lb = A + tile_pos(F, off, Ib, J) * TT;
-      T* Cab = A + tile_pos(F, off, Ia, Ib) * TT;
+      const T* La = A + tpos(Ia, J) * TT;
+      const T* Lb = A + tpos(Ib, J) * TT;
+      T* Cab = A + tpos(Ia, Ib) * TT;
       typename Mfma<T>::acc_t acc[4];
       tile_acc_load<T>(acc, Cab, TS, lane);
       tile_mma_nt<T, true>(acc, La, TS, Lb, TS, lane);

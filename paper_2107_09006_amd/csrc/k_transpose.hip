@@ -308,29 +308,84 @@ void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32
   k_check_cols<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, colind, n, flag);
 }
 
-// int64 row pointer -> int32 (values checked below 2^31 on the host)
-__global__ void k_narrow_i64(int64_t n, const int64_t* __restrict__ in, int64_t sub,
-                             int32_t add, int32_t* __restrict__ out) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = (int32_t)(in[k] - sub) + add;
+// ---------------------------------------------------------------------------
+// Input of the setup: the CSR arrays of all instances concatenated into the
+// handle's copy of A (row pointers narrowed to int32 and shifted by the
+// instance's first entry, columns shifted by its first column), checked on
+// the way.  A failed check records the smallest failing (global) row of its
+// kind in bad[kind] (atomicMin; INT64_MAX when none): CSR_FIRST rowptr[0] !=
+// 0, CSR_LAST rowptr[m] != nnz, CSR_MONO a row start below the previous one
+// or above nnz, CSR_RANGE a column outside [0, n), CSR_ORDER columns not
+// strictly increasing.  Reads never leave an instance's arrays, whatever
+// they hold.
+// ---------------------------------------------------------------------------
+// the instance holding global index g of the table field (r0 or e0)
+__device__ inline int instance_of(const InstDesc* __restrict__ d, int S, int64_t g, bool by_rows) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((by_rows ? d[mid].r0 : d[mid].e0) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
-void launch_narrow_i64(hipStream_t st, int64_t n, const int64_t* in, int64_t sub, int32_t add,
-                       int32_t* out) {
-  if (n == 0) return;
-  k_narrow_i64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, in, sub, add, out);
+__global__ void k_concat_rows(int S, const InstDesc* __restrict__ d, int64_t M,
+                              int32_t* __restrict__ rp, unsigned long long* __restrict__ bad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M) return;
+  const int k = instance_of(d, S, g, true);
+  const InstDesc D = d[k];
+  const int64_t r = g - D.r0;
+  const int64_t lo = D.rowptr[r], hi = D.rowptr[r + 1];
+  if (r == 0 && lo != 0) atomicMin(&bad[CSR_FIRST], (unsigned long long)g);
+  if (r == D.m - 1 && hi != D.nnz) atomicMin(&bad[CSR_LAST], (unsigned long long)g);
+  if (hi < lo || hi > D.nnz) atomicMin(&bad[CSR_MONO], (unsigned long long)g);
+  rp[g + 1] = (int32_t)(D.e0 + min(max(hi, (int64_t)0), D.nnz));
+  if (g == 0) rp[0] = 0;
 }
 
-// colind of one instance shifted by its first column (batched setup)
-__global__ void k_offset_i32(int64_t n, const int32_t* __restrict__ in, int32_t add,
-                             int32_t* __restrict__ out) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = in[k] + add;
+__global__ void k_concat_entries(int S, const InstDesc* __restrict__ d, int64_t NNZ,
+                                 int32_t* __restrict__ ci, double* __restrict__ vals) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NNZ) return;
+  const int k = instance_of(d, S, e, false);
+  const InstDesc D = d[k];
+  const int64_t q = e - D.e0;
+  ci[e] = D.colind[q] + (int32_t)D.c0;
+  vals[e] = D.vals[q];
 }
 
-void launch_offset_i32(hipStream_t st, int64_t n, const int32_t* in, int32_t add, int32_t* out) {
-  if (n == 0) return;
-  k_offset_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, in, add, out);
+// columns of every row (rp as written by k_concat_rows: inside each
+// instance's entries even for a corrupt rowptr)
+__global__ void k_check_rows(int S, const InstDesc* __restrict__ d, int64_t M,
+                             const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             unsigned long long* __restrict__ bad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M) return;
+  const int k = instance_of(d, S, g, true);
+  const InstDesc D = d[k];
+  const int32_t a = rp[g], b = rp[g + 1];
+  const int64_t c0 = D.c0, c1 = D.c0 + D.n;
+  for (int32_t e = a; e < b; ++e) {
+    const int32_t c = ci[e];
+    if (c < c0 || c >= c1) { atomicMin(&bad[CSR_RANGE], (unsigned long long)g); return; }
+    if (e > a && c <= ci[e - 1]) { atomicMin(&bad[CSR_ORDER], (unsigned long long)g); return; }
+  }
+}
+
+__global__ void k_fill_u64(int n, unsigned long long v, unsigned long long* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = v;
+}
+
+void launch_concat(hipStream_t st, int S, const InstDesc* d, int64_t M, int64_t NNZ, int32_t* rp,
+                   int32_t* ci, double* vals, unsigned long long* bad) {
+  k_fill_u64<<<1, 64, 0, st>>>(CSR_KINDS, ~0ull, bad);
+  k_concat_rows<<<(unsigned)((M + 255) / 256), 256, 0, st>>>(S, d, M, rp, bad);
+  if (NNZ > 0)
+    k_concat_entries<<<(unsigned)((NNZ + 255) / 256), 256, 0, st>>>(S, d, NNZ, ci, vals);
+  k_check_rows<<<(unsigned)((M + 255) / 256), 256, 0, st>>>(S, d, M, rp, ci, bad);
 }
 
 // ---------------------------------------------------------------------------

@@ -77,9 +77,19 @@ hipError_t launch_transpose(hipStream_t st, int32_t m, int32_t n, int64_t nnz, c
                             const int32_t* colind, const double* vals, int32_t* trowptr,
                             int32_t* trow, double* tvals, int32_t* tperm, void* temp,
                             size_t temp_bytes);
-void launch_narrow_i64(hipStream_t st, int64_t n, const int64_t* in, int64_t sub, int32_t add,
-                       int32_t* out);
-void launch_offset_i32(hipStream_t st, int64_t n, const int32_t* in, int32_t add, int32_t* out);
+// one instance of the input of a (batched) setup, with its first row,
+// column and entry in the concatenation
+struct InstDesc {
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* vals;
+  int64_t m, n, nnz, r0, c0, e0;
+};
+enum { CSR_FIRST = 0, CSR_LAST, CSR_MONO, CSR_RANGE, CSR_ORDER, CSR_KINDS };
+// the concatenated, checked CSR of all S instances (see k_concat_rows):
+// rp (M + 1), ci and vals (NNZ), bad (CSR_KINDS smallest failing rows)
+void launch_concat(hipStream_t st, int S, const InstDesc* d, int64_t M, int64_t NNZ, int32_t* rp,
+                   int32_t* ci, double* vals, unsigned long long* bad);
 // flag (one int32, device) = 1 if a column index lies outside [0, n)
 void launch_check_cols(hipStream_t st, int64_t nnz, const int32_t* colind, int32_t n, int32_t* flag);
 
