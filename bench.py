@@ -44,8 +44,8 @@ CALIB_BYTES = 1 << 30          # plain device copy used to calibrate HBM counter
 # It describes the kernel source whose SHA-256 is given; for any other source
 # the figure is reported as null.
 TRAFFIC = {"source": "paper_2107_09006_amd/csrc/k_solve.hip",
-           "sha256": "da04858b38577bc7de35eff16cadc58e82464cb70e3e265cd2ab3a192317270f",
-           "bytes": 2869024.35 * 1024 * 2.0 + 25203.25 * 1024 * 1.0}
+           "sha256": "3730a371a904e7e39a98b740966380b5f5a7f7a6c63f2243ecf41d40cc648404",
+           "bytes": 2107597.3 * 1024 * 2.0 + 24834.91 * 1024 * 1.0}
 
 
 def log(*a):

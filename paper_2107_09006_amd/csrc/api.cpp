@@ -845,11 +845,17 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   c->info.t_assemble_ms = ms_since(t0);
   // --- batched local Cholesky: the selection's factors (FP64, [I, Gamma])
-  // on st; the solve factors (FP64, or FP32 on MFMA in the mixed path) on
-  // st2, where they overlap the selection and the coarse operator (joined
-  // at the end of the setup, finish_solve_factors)
+  // on st; then the solve factors (FP64, or FP32 on MFMA in the mixed path)
+  // on st2, where they overlap the selection and the coarse operator (joined
+  // at the end of the setup, finish_solve_factors).  Both factorizations
+  // are bound by the tile-column chains of the largest subdomains and slow
+  // each other down when they run together; the selection's kernels leave
+  // room beside them.
   t0 = clk::now();
   const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  // with solve factors of their own, the selection's factor needs L_I and
+  // L_GI only (T = L_GI L_GI^T and X = L_I^{-T} L_GI^T Y)
+  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
   if (c->solve_plan) {
     if (mixed) {
       TRY(c->dalloc(&c->fac32, c->s_total_fac));
@@ -861,7 +867,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     if (!c->st2) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     if (!c->ev_fork) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     if (!c->ev_join) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));           // after the gather
+    LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));           // after the gather and the first factor
     LSQ2L_HIP_TRY(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
     if (mixed) {
       launch_to_float(c->st2, c->s_total_fac, s64, c->fac32);
@@ -871,9 +877,6 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     }
     LSQ2L_HIP_TRY(hipEventRecord(c->ev_join, c->st2));
   }
-  // with solve factors of their own, the selection's factor needs L_I and
-  // L_GI only (T = L_GI L_GI^T and X = L_I^{-T} L_GI^T Y)
-  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
   int32_t hstat[8];
   LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));

@@ -359,6 +359,8 @@ k_solve_perm(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssub,
   }
 }
 
+constexpr int GATHER_TMAX = 2048;
+
 // The solve layout's matrix (tile envelope, double) from the assembled and
 // equilibrated [I, Gamma] C_ii: entry (q_r, q_c) is C_ii(p_r, p_c) with
 // p = sperm - loc_off, zero outside the [I, Gamma] envelope, and the
@@ -369,6 +371,7 @@ k_gather_solve(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssu
                const double* __restrict__ fac, const int32_t* __restrict__ stileF,
                const int64_t* __restrict__ stileOff, const int32_t* __restrict__ sperm,
                double* __restrict__ out) {
+  __shared__ int32_t lF[GATHER_TMAX], lO[GATHER_TMAX];
   const SubDesc d = subs[blockIdx.x];
   const SubDesc s = ssub[d.id];
   const int32_t* F = tileF + d.tile_base;
@@ -378,6 +381,14 @@ k_gather_solve(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssu
   const int64_t* offs = stileOff + s.tile_base;
   const int32_t* sp = sperm + s.loc_off;
   double* O = out + s.fac_off;
+  // the [I, Gamma] envelope table in LDS (looked up for every entry)
+  const bool staged = d.ntiles <= GATHER_TMAX;
+  if (staged)
+    for (int I = threadIdx.x; I < d.ntiles; I += blockDim.x) {
+      lF[I] = F[I];
+      lO[I] = (int32_t)off[I];
+    }
+  __syncthreads();
   for (int I = blockIdx.y; I < s.ntiles; I += gridDim.y) {
     const int nk = I - Fs[I] + 1;
     double* row = O + offs[I] * TT;
@@ -391,7 +402,9 @@ k_gather_solve(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ ssu
       } else {
         const int hi = (int)(max(pr, pc) - d.loc_off), lo = (int)(min(pr, pc) - d.loc_off);
         const int th = hi / TS, tl = lo / TS;
-        v = tl >= F[th] ? A[tile_pos(F, off, th, tl) * TT + (lo % TS) * TS + hi % TS] : 0.0;
+        const int fh = staged ? lF[th] : F[th];
+        const int64_t t = staged ? (int64_t)lO[th] + (tl - fh) : tile_pos(F, off, th, tl);
+        v = tl >= fh ? A[t * TT + (lo % TS) * TS + hi % TS] : 0.0;
       }
       row[e] = v;
     }

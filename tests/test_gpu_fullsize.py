@@ -177,3 +177,59 @@ def test_irregular_1m_at_size(L):
             ang = sla.subspace_angles(s.coarse_basis(i), res["X"])
             assert ang.max() <= span_tolerance(Cii, Ctii, st.nI, p.tau)
     s.close()
+
+
+def test_banded_batch_64_at_size(L):
+    """The 64-instance batch at its real size (2,994 subdomains of 40 to
+    12,400 local unknowns, both streaming bins): every instance's true
+    residual on the host in FP64 and mixed precision with per-instance
+    iteration counts; x of the three smallest instances against the
+    oracle's solution at tol 1e-10; index sets of the largest subdomain and
+    index sets and selection counts of two mid-size ones."""
+    probs = W.banded_batch_64()
+    args = [(p.indptr, p.indices, p.data, p.part, p.nparts, p.m, p.n) for p in probs]
+    b = np.concatenate([p.b for p in probs])
+    n0 = np.cumsum([0] + [p.n for p in probs])
+    for prec in (L.FP64, L.MIXED):
+        s = L.Solver.batched(args, 0.1, precision=prec, tol=1e-8)
+        x, info, _ = s.solve(_t(b))
+        xn = _np(x)
+        assert len(info) == len(probs)
+        for k, p in enumerate(probs):
+            A = p.scipy()
+            rhs = A.T @ p.b
+            xk = xn[n0[k]:n0[k + 1]]
+            assert info[k]["relres"] <= 1e-8
+            assert np.linalg.norm(rhs - A.T @ (A @ xk)) <= 1.5e-8 * np.linalg.norm(rhs), k
+        its = [i["iterations"] for i in info]
+        assert min(its) < max(its)            # per-instance counts, not the batch's
+        s.close()
+    # parity of x on the three smallest instances (tol 1e-10)
+    s = L.Solver.batched(args, 0.1, tol=1e-10)
+    x, info, _ = s.solve(_t(b))
+    xn = _np(x)
+    for k in sorted(range(len(probs)), key=lambda k: probs[k].n)[:3]:
+        p = probs[k]
+        ref = O.Oracle(p.scipy(), p.part, p.nparts, p.tau).setup().solve(p.b, tol=1e-10)
+        assert info[k]["relres"] <= 1e-10
+        assert_close(xn[n0[k]:n0[k + 1]], ref["x"], 1e-8)
+    # index sets of the largest subdomain, selection of two mid-size ones
+    p0 = np.cumsum([0] + [p.nparts for p in probs])
+    subs = [s.subdomain(i) for i in range(p0[-1])]
+    sizes = np.array([d["I"].size + d["G"].size for d in subs])
+    big = int(np.argmax(sizes))
+    mid = [int(i) for i in np.argsort(np.abs(sizes - 1500))[:2]]
+    for g in [big] + mid:
+        k = int(np.searchsorted(p0, g, side="right") - 1)
+        p, i = probs[k], g - p0[k]
+        A = p.scipy()
+        st = O.index_sets(A, p.part, p.nparts, subdomains=[i])[0]
+        d = subs[g]
+        np.testing.assert_array_equal(d["I"] - n0[k], st.I)
+        np.testing.assert_array_equal(d["G"] - n0[k], st.G)
+        if g == big:
+            continue
+        Cii, Ctii = O.local_matrices(A, st)
+        res = O.coarse_vectors(Cii, Ctii, st.nI, p.tau)
+        assert d["p"] == res["p"], (g, d["p"], res["p"])
+    s.close()
