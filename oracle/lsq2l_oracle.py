@@ -22,6 +22,12 @@ decomposition preconditioner for sparse normal equations"):
 * ``Oracle.setup``      -- Algorithm 1 steps in order: index sets, D_i, R_i,
                            Cholesky of C_ii, Z_i, R_0^T = [R_1^T D_1 Z_1, ...],
                            Cholesky of C_00 = (A R_0^T)^T (A R_0^T);
+* ``local_factor_qr``, ``coarse_vectors_angles`` -- Remarks 3.1 and 3.2
+                           (``Oracle(local_factor="qr")``): L_i from a thin QR
+                           of A(:,Omega_i), and the selection from the
+                           principal angles between range(A(Xi_i,Omega_Ii))
+                           and range(A(Xi_i,Omega_Gamma_i)) (Bjorck-Golub),
+                           sin^2 theta < tau;
 * ``Oracle.apply``      -- M_additive = R_0^T C_00^{-1} R_0 + sum_i R_i^T C_ii^{-1} R_i
                            (eq. two_level_schwarz), the one-level M_ASM
                            (eq. one_level_schwarz), M_RAS (eq. RAS), and the
@@ -84,7 +90,7 @@ __all__ = [
     "selection_count_angles", "selection_count_inertia", "multiplicity",
     "greedy_colouring", "theorem26_bound", "Oracle", "pcg", "lsqr", "gmres", "csr_matrix",
     "dense_preconditioner", "spmv", "spmv_t", "frobenius_normal", "gradients",
-    "normal_solve_direct",
+    "normal_solve_direct", "local_factor_qr", "coarse_vectors_angles",
 ]
 
 
@@ -283,6 +289,74 @@ def selection_count_inertia(Cii, Ctii, nI, tau) -> int:
 
 
 # ---------------------------------------------------------------------------
+# Remarks 3.1 and 3.2: local factors and coarse selection without C_ii
+# ---------------------------------------------------------------------------
+
+def local_factor_qr(A: sp.csr_matrix, s: Subdomain) -> np.ndarray:
+    """Remark 3.1: the Cholesky factor of C_ii from a thin QR factorization
+    of A(:, Omega_i), without forming C_ii.  Rows of A with no stored entry in
+    Omega_i are zero rows of A(:, Omega_i) and are left out.  R is made unique
+    by a positive diagonal; returns L_i = R^T, so that C_ii = L_i L_i^T."""
+    A = sp.csr_matrix(A)
+    Ac = A[:, s.Omega].tocsr()
+    rows = np.flatnonzero(np.diff(Ac.indptr))
+    R = np.linalg.qr(Ac[rows].toarray(), mode="r")
+    sg = np.where(np.diag(R) < 0.0, -1.0, 1.0)
+    return (sg[:, None] * R).T
+
+
+def coarse_vectors_angles(A: sp.csr_matrix, s: Subdomain, tau: float,
+                          nev_max: int = 0) -> dict:
+    """Lemma 2.4's selection read through principal angles (Remark 3.2: no
+    C_ii or Ct_ii is formed).
+
+    With A_I = A(Xi_i, Omega_Ii) and A_G = A(Xi_i, Omega_Gamma_i), eliminating
+    the interface block from eq. (gevp) leaves S x = mu C_I x with
+    S = A_I^T (I - P_G) A_I, P_G the orthogonal projector onto range(A_G), and
+    lambda = 1/mu.  Written with orthonormal bases, the eigenvalues mu are
+    sin^2 theta for the principal angles theta between range(A_I) and
+    range(A_G) (and 1 for the directions of range(A_I) orthogonal to
+    range(A_G)); theta = 0 covers the infinite eigenvalues of L_i^perp.
+    Selected: sin^2 theta < tau, i.e. cos^2 theta > 1 - tau.
+
+    The angles are those of Bjorck and Golub:
+      Q_I R_I = A_I                (thin QR; A_I has full column rank, C_I
+                                    being positive definite);
+      A_G S P = Q R                (QR with column pivoting of A_G with unit
+                                    columns, S = diag of inverse column norms;
+                                    numerical rank r = #{k : |R_kk| > n_G eps},
+                                    Q_G = Q(:, :r) spans range(A_G));
+      U diag(cos theta) V^T = Q_I^T Q_G   (SVD, angles ascending).
+    The interior part of the eigenvector of angle theta_k is proportional to
+    C_I^{-1} C_IG y = R_I^{-1} Q_I^T A_G y with A_G y = Q_G v_k, that is to
+    R_I^{-1} u_k; X_i = R_I^{-1} U(:, selected) is C_I-orthonormal.  With
+    ``nev_max`` the nev_max smallest angles are kept."""
+    A = sp.csr_matrix(A)
+    AXi = A[s.Xi, :]
+    AI = AXi[:, s.I].toarray()
+    AG = AXi[:, s.G].toarray()
+    nI, nG = AI.shape[1], AG.shape[1]
+    QI, RI = np.linalg.qr(AI)
+    if nG == 0:
+        return {"X": np.zeros((nI, 0)), "p": 0, "mu": np.zeros(0), "rank_g": 0}
+    cn = np.sqrt((AG * AG).sum(axis=0))
+    sc = np.zeros(nG)
+    sc[cn > 0] = 1.0 / cn[cn > 0]
+    Q, R, _ = sla.qr(AG * sc[None, :], mode="economic", pivoting=True)
+    r = int((np.abs(np.diag(R)) > nG * EPS).sum())
+    if r == 0:
+        return {"X": np.zeros((nI, 0)), "p": 0, "mu": np.zeros(0), "rank_g": 0}
+    U, cos, _ = np.linalg.svd(QI.T @ Q[:, :r], full_matrices=False)
+    cos = np.minimum(cos, 1.0)
+    mu = 1.0 - cos * cos
+    sel = np.flatnonzero(cos * cos > 1.0 - tau)
+    if nev_max and sel.size > nev_max:
+        sel = sel[:nev_max]
+    X = sla.solve_triangular(RI, U[:, sel], lower=False)
+    return {"X": X, "p": int(sel.size), "mu": mu, "rank_g": r}
+
+
+# ---------------------------------------------------------------------------
 # constants of the condition-number bound
 # ---------------------------------------------------------------------------
 
@@ -336,6 +410,7 @@ class Oracle:
     variant: str = "additive"          # or "one_level", "balanced", "ras", "deflated"
     nev_max: int = 0
     diag_shift_rel: float = 0.0
+    local_factor: str = "cholesky"     # or "qr" (Remarks 3.1 and 3.2)
     shift: float = 0.0
     sets: list = field(default_factory=list)
     chol: list = field(default_factory=list)
@@ -372,11 +447,21 @@ class Oracle:
         self.chol = [None] * self.nparts
         self.X = [np.zeros((s.nI, 0)) for s in self.sets]
         self.info = [None] * self.nparts
+        two_level = self.variant in ("additive", "balanced", "deflated")
         for i in todo:
             s = self.sets[i]
+            if self.local_factor == "qr":
+                # Remark 3.1: L_i from a QR of A(:, Omega_i); Remark 3.2: the
+                # selection by principal angles, no C_ii or Ct_ii formed
+                self.chol[i] = (local_factor_qr(Ab, s), True)
+                if two_level:
+                    res = coarse_vectors_angles(Ab, s, self.tau, self.nev_max)
+                    self.X[i] = res["X"]
+                    self.info[i] = res
+                continue
             Cii, Ctii = local_matrices(Ab, s)
             self.chol[i] = sla.cho_factor(Cii, lower=True)
-            if self.variant in ("additive", "balanced", "deflated"):
+            if two_level:
                 res = coarse_vectors(Cii, Ctii, s.nI, self.tau, self.nev_max)
                 self.X[i] = res["X"]
                 self.info[i] = res

@@ -206,3 +206,56 @@ def test_shift_on_squared_norm_is_caught(monkeypatch):
     plant(monkeypatch, "frobenius_normal", lambda A: float(np.sum((A.T @ A).tocsr().data ** 2)))
     with pytest.raises(AssertionError):
         PK.test_shift_single_subdomain_is_shifted_inverse()
+
+
+# ---------------------------------------------------------------------------
+# Remarks 3.1 and 3.2 (QR factors, principal-angle selection)
+# ---------------------------------------------------------------------------
+
+def test_qr_factor_over_xi_rows_only_is_caught(monkeypatch):
+    """Dropped rows: the QR taken over Xi_i only gives the factor of the
+    splitting matrix Ct_ii, not of C_ii."""
+    def bad(A, s):
+        A = sp.csr_matrix(A)
+        R = np.linalg.qr(A[s.Xi, :][:, s.Omega].toarray(), mode="r")
+        sg = np.where(np.diag(R) < 0.0, -1.0, 1.0)
+        return (sg[:, None] * R).T
+    plant(monkeypatch, "local_factor_qr", bad)
+    with pytest.raises(AssertionError):
+        P.test_qr_factor_is_the_cholesky_factor(W.small_config("grid"))
+
+
+def test_qr_factor_without_sign_fix_is_caught(monkeypatch):
+    def bad(A, s):
+        A = sp.csr_matrix(A)
+        Ac = A[:, s.Omega].tocsr()
+        rows = np.flatnonzero(np.diff(Ac.indptr))
+        return np.linalg.qr(Ac[rows].toarray(), mode="r").T
+    plant(monkeypatch, "local_factor_qr", bad)
+    with pytest.raises(AssertionError):
+        P.test_qr_factor_is_the_cholesky_factor(W.worked_example())
+
+
+def test_angle_threshold_on_cosines_is_caught(monkeypatch):
+    """Threshold read the wrong way: cos^2 theta < tau instead of sin^2."""
+    good = OM.coarse_vectors_angles
+
+    def bad(A, s, tau, nev_max=0):
+        return good(A, s, 1.0 - tau, nev_max)
+    plant(monkeypatch, "coarse_vectors_angles", bad)
+    with pytest.raises(AssertionError):
+        P.test_worked_example_angle_selection_thresholds(0.70, (1, 1))
+
+
+def test_angle_vectors_without_inverse_factor_are_caught(monkeypatch):
+    """Inverted operand: X = R_I U instead of R_I^{-1} U."""
+    good = OM.coarse_vectors_angles
+
+    def bad(A, s, tau, nev_max=0):
+        res = good(A, s, tau, nev_max)
+        _, RI = np.linalg.qr(sp.csr_matrix(A)[s.Xi, :][:, s.I].toarray())
+        res["X"] = RI @ (RI @ res["X"])      # R_I U with U = R_I X
+        return res
+    plant(monkeypatch, "coarse_vectors_angles", bad)
+    with pytest.raises(AssertionError):
+        P.test_angle_selection_matches_library_angles_and_lemma24(W.small_config("grid"), 0.1)

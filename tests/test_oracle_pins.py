@@ -491,3 +491,113 @@ def test_generators_are_deterministic():
     for r in range(a.m):
         cols = a.indices[a.indptr[r]:a.indptr[r + 1]]
         assert np.all(np.diff(cols) > 0)
+
+
+# ---------------------------------------------------------------------------
+# Remarks 3.1 and 3.2: QR local factors and principal-angle selection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prob", _small_problems() + [W.worked_example()], ids=lambda p: p.name)
+def test_qr_factor_is_the_cholesky_factor(prob):
+    """Remark 3.1: R of a thin QR of A(:, Omega_i) with a positive diagonal
+    is the Cholesky factor of C_ii (uniqueness of both); checked against the
+    library Cholesky of the formed C_ii."""
+    A = prob.scipy()
+    for s in O.index_sets(A, prob.part, prob.nparts):
+        Cii, _ = O.local_matrices(A, s)
+        L = O.local_factor_qr(A, s)
+        Lc = np.linalg.cholesky(Cii)
+        assert np.all(np.triu(L, 1) == 0) and np.all(np.diag(L) > 0)
+        kap = np.linalg.cond(Cii)
+        np.testing.assert_allclose(L, Lc, atol=1e2 * kap ** 0.5 * np.finfo(float).eps * np.abs(Lc).max())
+
+
+def test_qr_factor_where_cholesky_breaks_down():
+    """Closed form: A = G [[1, 1], [0, d]] with a plane rotation G has
+    R = [[1, 1], [0, d]].  At d = 1e-10, C = A^T A = [[1, 1], [1, 1 + d^2]]
+    rounds to a singular matrix and its Cholesky factorization fails, while
+    the QR route recovers d to about eps / d."""
+    d, th = 1e-10, 0.7
+    c, sn = np.cos(th), np.sin(th)
+    Ad = np.array([[c, c - sn * d], [sn, sn + c * d]])
+    A = sp.csr_matrix(Ad)
+    s = O.Subdomain(np.array([0, 1]), np.array([0, 1]), np.array([], dtype=np.int64))
+    L = O.local_factor_qr(A, s)
+    assert L[0, 0] == pytest.approx(1.0, rel=1e-15)
+    assert L[1, 0] == pytest.approx(1.0, rel=1e-14)
+    assert L[1, 1] == pytest.approx(d, rel=1e-4)
+    C = Ad.T @ Ad
+    try:
+        Lc = np.linalg.cholesky(C)
+    except np.linalg.LinAlgError:
+        return
+    assert not (abs(Lc[1, 1] - d) <= 1e-4 * d)
+
+
+@pytest.mark.parametrize("prob", [W.banded_1000(), W.small_config("grid"),
+                                  W.small_config("banded"),
+                                  W.random_banded(480, 960, 32, seed=232, name="rb32")],
+                         ids=lambda p: p.name)
+@pytest.mark.parametrize("tau", [0.05, 0.1, 0.3, 0.6])
+def test_angle_selection_matches_library_angles_and_lemma24(prob, tau):
+    """Remark 3.2 / route (iii) as the production route: sin^2 of the
+    Bjorck-Golub angles equal those of the library routine
+    (scipy.linalg.subspace_angles), the count equals the Lemma 2.4 count,
+    and X_i spans the same space as Lemma 2.4's, C_I-orthonormal."""
+    A = prob.scipy()
+    for s in O.index_sets(A, prob.part, prob.nparts):
+        res = O.coarse_vectors_angles(A, s, tau)
+        ca, mua = O.selection_count_angles(A, s, tau)
+        if np.any(np.abs(mua - tau) <= 1e-9 * tau):
+            pytest.skip("near tie at the threshold")
+        k = min(res["mu"].size, mua.size)
+        np.testing.assert_allclose(np.sort(res["mu"])[:k], np.sort(mua)[:k], atol=1e-12)
+        Cii, Ctii = O.local_matrices(A, s)
+        ref = O.coarse_vectors(Cii, Ctii, s.nI, tau)
+        assert res["p"] == ca == ref["p"]
+        X = res["X"]
+        if X.shape[1] == 0:
+            continue
+        CI = Cii[:s.nI, :s.nI]
+        np.testing.assert_allclose(X.T @ CI @ X, np.eye(X.shape[1]), atol=1e-9)
+        # principal angles between the two spans, in the C_I inner product
+        Lc = np.linalg.cholesky(CI)
+        Qa, _ = np.linalg.qr(Lc.T @ X)
+        Qb, _ = np.linalg.qr(Lc.T @ ref["X"])
+        sv = np.linalg.svd(Qa.T @ Qb, compute_uv=False)
+        assert sv.min() >= 1.0 - 1e-10
+
+
+@pytest.mark.parametrize("tau,expect", [(0.6, (0, 1)), (0.70, (1, 1)), (0.69, (0, 1)),
+                                        (0.47, (0, 1)), (0.46, (0, 0))])
+def test_worked_example_angle_selection_thresholds(tau, expect):
+    """The printed example through the QR route: subdomain 1 is selected iff
+    tau > 9/13, subdomain 2 iff tau > 100/213 (sin^2 theta = 9/13 and
+    100/213, the reciprocals of the closed-form eigenvalues), and the coarse
+    vector at tau = 0.6 is (0, 113, 0, -35)."""
+    p = W.worked_example()
+    orc = O.Oracle(p.scipy(), p.part, p.nparts, tau, local_factor="qr").setup()
+    assert tuple(orc.p) == expect
+    sets = O.index_sets(p.scipy(), p.part, p.nparts)
+    mus = [np.sort(O.coarse_vectors_angles(p.scipy(), s, tau)["mu"]) for s in sets]
+    assert mus[0][0] == pytest.approx(9 / 13, rel=1e-13)
+    assert mus[1][0] == pytest.approx(100 / 213, rel=1e-13)
+    if tau == 0.6:
+        v = orc.R0T.toarray()[:, 0]
+        ref = np.array([0.0, 113.0, 0.0, -35.0])
+        assert abs(v @ ref) / (np.linalg.norm(v) * np.linalg.norm(ref)) == pytest.approx(1.0, abs=1e-14)
+
+
+@pytest.mark.parametrize("variant", ["additive", "one_level"])
+def test_qr_route_pcg_matches_dense_least_squares(variant):
+    prob = W.banded_1000()
+    A = prob.scipy()
+    orc = O.Oracle(A, prob.part, prob.nparts, prob.tau, variant=variant, local_factor="qr").setup()
+    ref = O.Oracle(A, prob.part, prob.nparts, prob.tau, variant=variant).setup()
+    assert np.array_equal(orc.p, ref.p)
+    r = np.random.default_rng(3).standard_normal(prob.n)
+    z, zr = orc.apply(r), ref.apply(r)
+    assert np.linalg.norm(z - zr) <= 1e-8 * np.linalg.norm(zr)
+    sol = orc.solve(prob.b, tol=1e-12)
+    xs = np.linalg.lstsq(A.toarray(), prob.b, rcond=None)[0]
+    assert np.linalg.norm(sol["x"] - xs) <= 1e-9 * np.linalg.norm(xs)
