@@ -126,9 +126,22 @@ typedef struct {
                          selection factors C_ii in); LSQ2L_ORDER_SPLIT keeps [Omega_Ii,
                          Omega_Gamma_i] everywhere, LSQ2L_ORDER_GLOBAL takes the global-column
                          order everywhere                                                      */
+  int32_t local_factor;/* LSQ2L_FACTOR_CHOLESKY (default): local factors from the Cholesky
+                         factorization of the assembled, equilibrated C_ii.  LSQ2L_FACTOR_QR:
+                         C_ii is never formed (Remarks 3.1 and 3.2): every local factor is the
+                         R of a thin Householder QR of the equilibrated A(:, Omega_i) (FP64;
+                         rounded to float for the solves of LSQ2L_MIXED), and the coarse
+                         selection takes the principal angles between range(A(Xi_i, Omega_Ii))
+                         and range(A(Xi_i, Omega_Gamma_i)), the numerical range of the latter
+                         from a column-pivoted QR of the R of A(Xi_i, Omega_Gamma_i); the
+                         condition number of the local blocks is not squared on the way.  Not
+                         with diag_shift_rel > 0 (LSQ2L_EINVAL); subdomains of up to 65,536
+                         positions, interfaces of up to 2,047 columns (else
+                         LSQ2L_CHOL_BREAKDOWN with a message)                                  */
 } lsq2l_options;
 
 enum { LSQ2L_ORDER_AUTO = 0, LSQ2L_ORDER_SPLIT = 1, LSQ2L_ORDER_GLOBAL = 2 };
+enum { LSQ2L_FACTOR_CHOLESKY = 0, LSQ2L_FACTOR_QR = 1 };
 
 typedef struct {
   int32_t iterations;     /* Krylov iterations performed (per instance for batched handles)  */

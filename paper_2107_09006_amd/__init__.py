@@ -8,6 +8,6 @@ from .binding import (  # noqa: F401
     Solver, solver_from_problem, load_library, default_options, release_cache, transpose,
     Lsq2lError, OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, CHOL_BREAKDOWN, PCG_BREAKDOWN,
     FP64, MIXED, ADDITIVE, ONE_LEVEL, BALANCED, RAS, DEFLATED, PCG, LSQR, GMRES, EXPORTS,
-    ORDER_AUTO, ORDER_SPLIT, ORDER_GLOBAL,
+    ORDER_AUTO, ORDER_SPLIT, ORDER_GLOBAL, FACTOR_CHOLESKY, FACTOR_QR,
 )
 from .autograd import LeastSquaresSolve, lstsq  # noqa: F401,E402

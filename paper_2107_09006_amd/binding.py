@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 ADDITIVE, ONE_LEVEL, BALANCED, RAS, DEFLATED = 0, 1, 2, 3, 4
 PCG, LSQR, GMRES = 0, 1, 2
 ORDER_AUTO, ORDER_SPLIT, ORDER_GLOBAL = 0, 1, 2
+FACTOR_CHOLESKY, FACTOR_QR = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
                 -4: "CHOL_BREAKDOWN", -5: "PCG_BREAKDOWN"}
@@ -39,7 +40,8 @@ class Options(C.Structure):
                 ("flexible", C.c_int32), ("variant", C.c_int32), ("nev_max", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("krylov", C.c_int32),
                 ("restart", C.c_int32), ("diag_shift_rel", C.c_double),
-                ("adjoint_tol", C.c_double), ("autotune", C.c_int32), ("solve_order", C.c_int32)]
+                ("adjoint_tol", C.c_double), ("autotune", C.c_int32), ("solve_order", C.c_int32),
+                ("local_factor", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

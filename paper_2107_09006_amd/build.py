@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblsq2l.so")
-SOURCES = ["api.cpp", "krylov.cpp", "plan.cpp", "k_local.hip", "k_solve.hip", "k_krylov.hip", "k_coarse.hip", "k_select.hip", "k_transpose.hip"]
+SOURCES = ["api.cpp", "krylov.cpp", "plan.cpp", "k_local.hip", "k_solve.hip", "k_krylov.hip", "k_coarse.hip", "k_select.hip", "k_transpose.hip", "k_qr.hip"]
 ARCH = os.environ.get("LSQ2L_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

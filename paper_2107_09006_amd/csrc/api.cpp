@@ -623,8 +623,9 @@ lsq2l_status solve_layout_begin(lsq2l_ctx* c) {
   const hipStream_t st = c->st;
   const HostPlan& H = c->H;
   const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  const bool qr = c->opt.local_factor == LSQ2L_FACTOR_QR;
   c->sl_inv = nullptr;
-  if (!mixed && c->opt.solve_order == LSQ2L_ORDER_SPLIT) return LSQ2L_OK;
+  if (!mixed && !qr && c->opt.solve_order == LSQ2L_ORDER_SPLIT) return LSQ2L_OK;
   // global-order layouts: np = roundup(n_i), local-vector slices of
   // max(np, [I, Gamma] np) entries
   c->sl_g.assign(H.subs.begin(), H.subs.end());
@@ -649,12 +650,14 @@ lsq2l_status solve_layout_begin(lsq2l_ctx* c) {
 // solve_layout, after the assembly and equilibration (c->fac holds the
 // equilibrated C_ii, not yet factored): the choice, the layout Ps on the
 // device, and the gather of its matrix into *s64 (double), enqueued;
-// c->solve_plan tells whether it is used.
+// c->solve_plan tells whether it is used.  With the QR local factors (no
+// C_ii assembled) the solve layout is always used and *s64 comes zeroed.
 lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
   const hipStream_t st = c->st;
   const HostPlan& H = c->H;
   const int nsub = c->nsub;
   const bool mixed = c->opt.precision == LSQ2L_MIXED;
+  const bool qr = c->opt.local_factor == LSQ2L_FACTOR_QR;
   *s64 = nullptr;
   c->solve_plan = false;
   c->info.split_tiles = H.total_fac / TT;
@@ -700,7 +703,7 @@ lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
   }
   c->info.split_tiles = split_tiles;
   c->info.solve_permuted = permuted;
-  if (!mixed && permuted == 0) return LSQ2L_OK;
+  if (!mixed && !qr && permuted == 0) return LSQ2L_OK;
   c->solve_plan = true;
   c->s_total_fac = ftiles * TT;
   c->s_total_dinv = dtiles * TT;
@@ -724,7 +727,8 @@ lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
   launch_solve_perm(st, nsub, c->P, Ps.subs, inv, Ps.sperm);
   if (Ps.max_np > 12544) TRY(c->dalloc(&Ps.yscratch, std::max<int64_t>(lo, 1)));
   TRY(c->dalloc(s64, std::max<int64_t>(c->s_total_fac, 1)));
-  launch_gather_solve(st, nsub, c->P, Ps, c->fac, *s64);
+  if (qr) LSQ2L_HIP_TRY(hipMemsetAsync(*s64, 0, c->s_total_fac * sizeof(double), st));
+  else launch_gather_solve(st, nsub, c->P, Ps, c->fac, *s64);
   return LSQ2L_OK;
 }
 
@@ -813,6 +817,14 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   LSQ2L_HIP_TRY(hipMemsetAsync(c->fac, 0, H.total_fac * sizeof(double), st));
   if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(c->ctg, 0, H.total_g * sizeof(double), st));
   TRY(solve_layout_begin(c));
+  const bool qr = c->opt.local_factor == LSQ2L_FACTOR_QR;
+  if (qr) {
+    // QR local factors (Remarks 3.1, 3.2): no C_ii is formed.  The pattern
+    // pass of the assembly still gives the envelope of the global-order
+    // layouts; the equilibration's scaling comes from the column norms of A.
+    if (c->sl_inv) launch_assemble(st, nparts, c->P, c->M, nullptr, nullptr, c->sl_inv, c->sl_dg, c->sl_Fg);
+    launch_col_scale(st, nparts, c->P, c->M, c->scale);
+  } else {
   launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg, c->sl_inv, c->sl_dg, c->sl_Fg);
   // Global shift of Section 4.1 ("Setup phase"): the preconditioner is built
   // for C + s I, s = diag_shift_rel ||C||_F, i.e. for the least-squares
@@ -838,6 +850,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     if (c->shift > 0.0) launch_add_diag(st, nparts, c->P, c->shift, c->fac);
   }
   launch_equilibrate(st, nparts, c->P, c->fac, c->ctg, c->scale);
+  }
   // the layout of the solve factors and the gather of its matrix (before
   // c->fac is factored in place)
   double* s64 = nullptr;
@@ -854,22 +867,48 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   t0 = clk::now();
   const bool mixed = c->opt.precision == LSQ2L_MIXED;
   // with solve factors of their own, the selection's factor needs L_I and
-  // L_GI only (T = L_GI L_GI^T and X = L_I^{-T} L_GI^T Y)
-  launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
+  // L_GI only (T = L_GI L_GI^T and X = L_I^{-T} L_GI^T Y).  The QR route
+  // merges the rows of A into R; its row strips (zero between uses) are one
+  // per stream.
+  double* qstrip = nullptr;
+  const int64_t strip_len = (int64_t)QR_STRIP_ROWS * H.total_loc;
+  if (qr) {
+    TRY(c->dalloc(&qstrip, strip_len));
+    LSQ2L_HIP_TRY(hipMemsetAsync(qstrip, 0, strip_len * sizeof(double), st));
+    launch_qr_local(st, QR_SEL, nparts, c->P, c->P, c->M, nullptr, c->scale, c->fac, c->dinv, qstrip,
+                    c->status);
+  } else {
+    launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
+  }
   if (c->solve_plan) {
+    double* qdinv = nullptr;     // FP64 inverse diagonal tiles of the QR solve factors
+    double* qstrip2 = nullptr;
     if (mixed) {
       TRY(c->dalloc(&c->fac32, c->s_total_fac));
       TRY(c->dalloc(&c->dinv32, c->s_total_dinv));
+      if (qr) TRY(c->dalloc(&qdinv, c->s_total_dinv));
     } else {
       c->sfac = s64;
       TRY(c->dalloc(&c->sdinv, c->s_total_dinv));
+      qdinv = c->sdinv;
+    }
+    if (qr) {
+      TRY(c->dalloc(&qstrip2, strip_len));
+      LSQ2L_HIP_TRY(hipMemsetAsync(qstrip2, 0, strip_len * sizeof(double), st));
     }
     if (!c->st2) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     if (!c->ev_fork) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     if (!c->ev_join) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));           // after the gather and the first factor
     LSQ2L_HIP_TRY(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
-    if (mixed) {
+    if (qr) {
+      launch_qr_local(c->st2, QR_SOLVE, nparts, c->P, c->Ps, c->M, c->sl_inv, c->scale, s64, qdinv,
+                      qstrip2, c->status + 2);
+      if (mixed) {
+        launch_to_float(c->st2, c->s_total_fac, s64, c->fac32);
+        launch_to_float(c->st2, c->s_total_dinv, qdinv, c->dinv32);
+      }
+    } else if (mixed) {
       launch_to_float(c->st2, c->s_total_fac, s64, c->fac32);
       launch_chol_local_f32(c->st2, nparts, c->Ps, c->fac32, c->dinv32, c->status + 2);
     } else {
@@ -881,7 +920,11 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   if (hstat[0] != 0) {
-    set_error("local Cholesky breakdown in subdomain " + std::to_string(hstat[0] - 1));
+    if (qr)
+      set_error("QR local factor failed in subdomain " + std::to_string(hstat[0] - 1) +
+                " (A(Xi_i, Omega_Ii) rank deficient, or more than 65,536 positions)");
+    else
+      set_error("local Cholesky breakdown in subdomain " + std::to_string(hstat[0] - 1));
     if (c->st2) (void)hipStreamSynchronize(c->st2);
     return LSQ2L_CHOL_BREAKDOWN;
   }
@@ -895,6 +938,11 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     int32_t hs = 0;
     LSQ2L_HIP_TRY(hipMemcpyAsync(&hs, c->status + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    if (hs != 0 && qr) {
+      set_error("QR solve factor failed in subdomain " + std::to_string(hs - 1) +
+                " (A(:, Omega_i) rank deficient, or a layout beyond the QR kernel's tables)");
+      return LSQ2L_CHOL_BREAKDOWN;
+    }
     if (hs != 0 && mixed) {
       c->info.mixed_fallback = 1;
       double* d64 = nullptr;
@@ -932,10 +980,21 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     if (H.total_g) LSQ2L_HIP_TRY(hipMemsetAsync(work, 0, SEL_WORK_MATS * H.total_g * sizeof(double), st));
     LSQ2L_HIP_TRY(hipMemsetAsync(pc, 0, (nparts + 1) * sizeof(int32_t), st));
     launch_gamma_T(st, nparts, c->P, c->fac, Tg);
-    launch_select(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig);
+    // QR route: the interface factors R_G of A(Xi_i, Omega_Gamma_i) replace Ct_GG
+    if (qr)
+      launch_qr_local(st, QR_GAMMA, nparts, c->P, c->P, c->M, nullptr, c->scale, c->ctg, nullptr,
+                      qstrip, c->status + 4);
+    launch_select(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig, qr ? 1 : 0);
     std::vector<int32_t> ph(nparts + 1);
+    int32_t gstat = 0;
     LSQ2L_HIP_TRY(hipMemcpyAsync(ph.data(), pc, (nparts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (qr) LSQ2L_HIP_TRY(hipMemcpyAsync(&gstat, c->status + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ2L_HIP_TRY(hipStreamSynchronize(st));
+    if (gstat != 0) {
+      set_error("QR interface factor failed in subdomain " + std::to_string(gstat - 1) +
+                " (interface beyond the QR kernel's tables)");
+      return LSQ2L_CHOL_BREAKDOWN;
+    }
     if (ph[nparts] != 0) {
       set_error(ph[nparts] == 2 ? "interface larger than the eigensolver limit (1024)"
                                 : "non-finite entries in a coarse eigenproblem");
@@ -1219,6 +1278,14 @@ lsq2l_status check_common(double tau, const lsq2l_options* opt) {
       set_error("diag_shift_rel and adjoint_tol must be >= 0");
       return LSQ2L_EINVAL;
     }
+    if (opt->local_factor != LSQ2L_FACTOR_CHOLESKY && opt->local_factor != LSQ2L_FACTOR_QR) {
+      set_error("bad local_factor");
+      return LSQ2L_EINVAL;
+    }
+    if (opt->local_factor == LSQ2L_FACTOR_QR && opt->diag_shift_rel > 0.0) {
+      set_error("the QR local factors take no diagonal shift (diag_shift_rel must be 0)");
+      return LSQ2L_EINVAL;
+    }
   }
   return LSQ2L_OK;
 }
@@ -1438,6 +1505,7 @@ void lsq2l_default_options(lsq2l_options* opt) {
   opt->adjoint_tol = 0.0;
   opt->autotune = 0;
   opt->solve_order = LSQ2L_ORDER_AUTO;
+  opt->local_factor = LSQ2L_FACTOR_CHOLESKY;
 }
 
 const char* lsq2l_last_error(void) { return g_err.c_str(); }

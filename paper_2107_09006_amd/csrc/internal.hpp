@@ -298,6 +298,45 @@ __device__ inline bool tile_potrf_inv_reg(const T* W, T* L, T* Inv, int lane) {
 }
 
 // -------------------------------------------------------------------------
+// subdomain addressing shared by the setup kernels
+// -------------------------------------------------------------------------
+// Local position of global column c in subdomain i (or -1): interior columns
+// are found through the owner table, interface columns by binary search in
+// the sorted Omega_Gamma_i.
+__device__ inline int local_pos(int i, int c, const int32_t* __restrict__ part,
+                                const int32_t* __restrict__ locown, const int32_t* __restrict__ G,
+                                int nG, int nIp) {
+  if (part[c] == i) return locown[c];
+  int lo = 0, hi = nG;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (G[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return (lo < nG && G[lo] == c) ? nIp + lo : -1;
+}
+
+// Rows I > J of the tile envelope whose envelope reaches column J, in
+// ascending order (ballot compaction by wave 0).  Returns the count.
+__device__ inline int envelope_rows(const int32_t* F, int J, int ntiles, int32_t* list, int cap,
+                                    int* s_count) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int cnt = 0;
+    for (int base = J + 1; base < ntiles; base += 64) {
+      const int I = base + lane;
+      const bool fl = I < ntiles && F[I] <= J;
+      const unsigned long long mask = __ballot(fl);
+      const int before = __popcll(mask & ((1ull << lane) - 1ull));
+      if (fl && cnt + before < cap) list[cnt + before] = I;
+      cnt += __popcll(mask);
+    }
+    if (lane == 0) *s_count = cnt;
+  }
+  __syncthreads();
+  return *s_count;
+}
+
+// -------------------------------------------------------------------------
 // host-side helpers shared by the translation units
 // -------------------------------------------------------------------------
 void set_error(const std::string& msg);

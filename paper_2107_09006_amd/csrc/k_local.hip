@@ -21,22 +21,8 @@ __global__ void k_gather_values(int64_t nnz, const int32_t* __restrict__ perm,
   if (k < nnz) dst[k] = src[perm[k]];
 }
 
-// Local position of global column c in subdomain i (or -1): interior columns
-// are found through the owner table, interface columns by binary search in
-// the sorted Omega_Gamma_i.
-__device__ inline int local_pos(int i, int c, const int32_t* __restrict__ part,
-                                const int32_t* __restrict__ locown, const int32_t* __restrict__ G,
-                                int nG, int nIp) {
-  if (part[c] == i) return locown[c];
-  int lo = 0, hi = nG;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (G[mid] < c) lo = mid + 1; else hi = mid;
-  }
-  return (lo < nG && G[lo] == c) ? nIp + lo : -1;
-}
-
-// Lower triangle of C_ii (tile-envelope layout) and of Ct_GG (dense, ld nGp).
+// Lower triangle of C_ii (tile-envelope layout) and of Ct_GG (dense, ld nGp);
+// with fac null, only the envelope Fg below.
 // Thread per local column: every write of a thread lands in its own column,
 // so the accumulation order is fixed and no atomics are needed.  Workgroup
 // (i, y) takes the columns y * 256 + t, (y + gridDim.y) * 256 + t, ... of
@@ -61,8 +47,8 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
   const int32_t* G = om + d.nI;
   const int32_t* F = tileF + d.tile_base;
   const int64_t* off = tileOff + d.tile_base;
-  double* A = fac + d.fac_off;
-  double* Ct = ctg + d.g_off;
+  double* A = fac ? fac + d.fac_off : nullptr;    // null: the envelope Fg only
+  double* Ct = ctg ? ctg + d.g_off : nullptr;
   for (int a = blockIdx.y * blockDim.x + threadIdx.x; a < d.nI + d.nG; a += gridDim.y * blockDim.x) {
     const int j = om[a];
     const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
@@ -74,11 +60,11 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
       const double va = tvals[k];
       const int e0 = rowptr[r], e1 = rowptr[r + 1];
       bool inxi = false;
-      for (int e = e0; e < e1; ++e) inxi |= (part[colind[e]] == i);
+      if (A) for (int e = e0; e < e1; ++e) inxi |= (part[colind[e]] == i);
       for (int e = e0; e < e1; ++e) {
         const int posc = local_pos(i, colind[e], part, locown, G, d.nG, d.nIp);
         if (iv && posc >= 0) fmin = min(fmin, iv[posc]);
-        if (posc < posa) continue;
+        if (!A || posc < posa) continue;
         const double v = vals[e] * va;
         const int tc = posc / TS;
         A[tile_pos(F, off, tc, ta) * TT + ra * TS + (posc % TS)] += v;
@@ -142,27 +128,6 @@ k_equil_apply(const SubDesc* __restrict__ subs, const int32_t* __restrict__ tile
     const int r = (int)(e % d.nGp), c = (int)(e / d.nGp);
     Ct[e] *= s[d.nIp + r] * s[d.nIp + c];   // zero on padding
   }
-}
-
-// Rows I > J of the tile envelope whose envelope reaches column J, in
-// ascending order (ballot compaction by wave 0).  Returns the count.
-__device__ inline int envelope_rows(const int32_t* F, int J, int ntiles, int32_t* list, int cap,
-                                    int* s_count) {
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    int cnt = 0;
-    for (int base = J + 1; base < ntiles; base += 64) {
-      const int I = base + lane;
-      const bool fl = I < ntiles && F[I] <= J;
-      const unsigned long long mask = __ballot(fl);
-      const int before = __popcll(mask & ((1ull << lane) - 1ull));
-      if (fl && cnt + before < cap) list[cnt + before] = I;
-      cnt += __popcll(mask);
-    }
-    if (lane == 0) *s_count = cnt;
-  }
-  __syncthreads();
-  return *s_count;
 }
 
 constexpr int ROWCAP = 2048;

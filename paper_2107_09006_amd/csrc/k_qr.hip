@@ -1,0 +1,443 @@
+// Local factors and interface factors from thin QR factorizations, without
+// forming C_ii (Remark 3.1, Section 3.1; Remark 3.2, Section 3.3.2).
+//
+// R of A(rows, Omega_i) S (S the column scaling of the equilibration, so
+// that R^T R is the equilibrated C_ii) is built by merging the rows of A into
+// R, QB rows at a time, tile column by tile column: for the block B of rows
+// and the tile column J of its first nonzero,
+//     [R(J, J) R(J, K...)]          [R'(J, J) R'(J, K...)]
+//     [B(:, J) B(:, K...)]  <-  Q^T [   0     B'(:, K...)]
+// with Q the product of the 32 Householder reflectors that zero B(:, J)
+// against the triangle R(J, J) (the LAPACK reflector convention: beta =
+// -sign(alpha) ||x||, tau = (beta - alpha) / beta).  The tiles K are the
+// tile rows of the envelope that reach column J (F(K) <= J): a row of B that
+// is nonzero in tile K when tile J is eliminated either had an entry there
+// (coupling columns J and K in C_ii) or received it from a row of R, so R
+// stays inside the envelope of C_ii that the Cholesky factor uses, and L =
+// R^T is written over the same layout.  The block is done when no tile of it
+// is nonzero.  At the end the rows of R get a positive diagonal (then L is
+// the Cholesky factor of the equilibrated C_ii) and the diagonal tiles of L
+// are inverted for the triangular solves.
+//
+// Three uses (one workgroup per subdomain):
+//   QR_SEL    rows Xi_i in the [Omega_Ii, Omega_Gamma_i] layout, interior
+//             tile columns only: L_I and L_GI, what the coarse selection and
+//             the coarse basis read (rows outside Xi_i have no interior entry
+//             and do not change them);
+//   QR_SOLVE  every row of A with an entry in Omega_i (Xi_i, then the rows
+//             reached through the columns of Omega_Gamma_i only), in the solve
+//             layout of each subdomain (global column order or [I, Gamma]):
+//             the factor of C_ii the local solves read;
+//   QR_GAMMA  rows Xi_i restricted to Omega_Gamma_i into a dense n_G x n_G
+//             upper triangle R_G (column-major, ld nGp, in the interface
+//             work matrix): R_G^T R_G = Ct_GG, the input of the
+//             principal-angle selection.
+// The rows of a block live in a per-subdomain strip of QB x np doubles in
+// global memory (position-major, QB rows contiguous), which is all zero
+// between blocks: every tile a block touches is zeroed when it is eliminated
+// (or, for QR_SEL, at the end of the block).
+#include <climits>
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace lsq2l {
+
+namespace {
+
+constexpr int QB = QR_STRIP_ROWS;   // rows merged per block: 8 groups of 4 per column
+constexpr int QR_THREADS = 256;   // thread t: column t / 8 of the tile, rows 4 (t % 8) ..
+constexpr int QR_TMAX = 2048;     // tiles per side (and interface prefix entries) held in LDS
+
+// sum over the 8 lanes 8 q .. 8 q + 7; every lane gets the same bits
+__device__ inline double oct_allsum(double x) {
+  x = dpp_pair_sum<0xB1>(x);
+  x = dpp_pair_sum<0x4E>(x);
+  return dpp_pair_sum<0x141>(x);
+}
+
+// max over the same 8 lanes
+__device__ inline double oct_allmax(double x) {
+  auto step = [](double v, auto ctrl) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), decltype(ctrl)::value, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), decltype(ctrl)::value, 0xF, 0xF, false);
+    return fmax(v, __hiloint2double(hi, lo));
+  };
+  x = step(x, std::integral_constant<int, 0xB1>{});
+  x = step(x, std::integral_constant<int, 0x4E>{});
+  return step(x, std::integral_constant<int, 0x141>{});
+}
+
+// exclusive scan of v over the 256 threads, total in *tot
+__device__ inline int block_scan_256(int v, int* sh, int* tot) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += sh[w];
+    all += sh[w];
+  }
+  __syncthreads();
+  *tot = all;
+  return before + x - v;
+}
+
+}  // namespace
+
+template <int MODE>
+__global__ void __launch_bounds__(QR_THREADS)
+k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
+           const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
+           const int32_t* __restrict__ omega, const int32_t* __restrict__ xi,
+           const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
+           const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+           const double* __restrict__ vals, const int32_t* __restrict__ trowptr,
+           const int32_t* __restrict__ trow, const int32_t* __restrict__ inv,
+           const double* __restrict__ scale, double* __restrict__ out,
+           double* __restrict__ dinv, double* __restrict__ strip, int32_t* __restrict__ status) {
+  __shared__ double sV[TS * QB];          // reflector c: sV[c * QB + row]
+  __shared__ double sTau[TS], sSgn[TS];
+  __shared__ double sX[TS * LDT];
+  __shared__ int32_t sF[QR_TMAX], sO[QR_TMAX], sGen[QR_TMAX], sRows[QR_TMAX], sGpre[QR_TMAX];
+  __shared__ int s_jmin, s_jmax, s_count, s_fail, s_tot;
+  __shared__ int s_scan[4];
+  const SubDesc d = subs[blockIdx.x];
+  const SubDesc pd = psubs[d.id];
+  const int i = d.id;
+  const int tid = threadIdx.x, k = tid >> 3, g = tid & 7;
+  const int32_t* om = omega + pd.omega_off;
+  const int32_t* G = om + pd.nI;
+  // layout written: tiles per side, interior tiles, the envelope (dense for QR_GAMMA)
+  const int ntiles = MODE == QR_GAMMA ? pd.nGp / TS : d.ntiles;
+  const int ntI = MODE == QR_GAMMA ? 0 : d.ntI;
+  const int ld = pd.nGp;
+  if (ntiles > QR_TMAX || (MODE == QR_SOLVE && pd.nG + 1 > QR_TMAX)) {
+    if (tid == 0) atomicCAS(status, 0, i + 1);
+    return;
+  }
+  if (MODE != QR_GAMMA)
+    for (int I = tid; I < ntiles; I += QR_THREADS) {
+      sF[I] = tileF[d.tile_base + I];
+      sO[I] = (int32_t)tileOff[d.tile_base + I];
+    }
+  for (int I = tid; I < ntiles; I += QR_THREADS) sGen[I] = -1;
+  if (tid == 0) s_fail = 0;
+  // rows reached through the interface columns only (QR_SOLVE): candidate t
+  // of the stream is entry t - sGpre[g] of column G[g] of A^T
+  int nextra = 0;
+  if (MODE == QR_SOLVE) {
+    int run = 0;
+    for (int b0 = 0; b0 <= pd.nG; b0 += QR_THREADS) {
+      const int gg = b0 + tid;
+      const int len = gg < pd.nG ? trowptr[G[gg] + 1] - trowptr[G[gg]] : 0;
+      int tot;
+      const int ex = block_scan_256(len, s_scan, &tot);
+      if (gg <= pd.nG) sGpre[gg] = run + ex;
+      run += tot;
+    }
+    nextra = run;
+  }
+  __syncthreads();
+  double* Lf = MODE == QR_GAMMA ? out + pd.g_off : out + d.fac_off;
+  double* Di = MODE == QR_GAMMA ? nullptr : dinv + d.dinv_off;
+  double* Bs = strip + (int64_t)QB * pd.loc_off;
+  // element (c, kk) of R(J, K) (row 32 J + c, column 32 K + kk) is base[c * sc + kk * sk]
+  auto rtile = [&](int J, int K) -> double* {
+    if (MODE == QR_GAMMA) return Lf + (int64_t)(K * TS) * ld + J * TS;
+    return Lf + ((int64_t)sO[K] + (J - sF[K])) * TT;
+  };
+  const int sc = MODE == QR_GAMMA ? 1 : TS, sk = MODE == QR_GAMMA ? ld : 1;
+  // position of a global column in the layout written, -1 if not there
+  auto layout_pos = [&](int c, int* posP) -> int {
+    const int p = local_pos(i, c, part, locown, G, pd.nG, pd.nIp);
+    *posP = p;
+    if (p < 0) return -1;
+    if (MODE == QR_GAMMA) return p >= pd.nIp ? p - pd.nIp : -1;
+    if (MODE == QR_SOLVE && d.spare) return inv[pd.loc_off + p];
+    return p;
+  };
+  const int64_t nstream = (int64_t)pd.nXi + nextra;
+  for (int64_t blk = 0; blk * QB < nstream; ++blk) {
+    const int gen = (int)blk;
+    if (tid == 0) { s_jmin = INT_MAX; s_jmax = -1; }
+    __syncthreads();
+    // ---- the rows of the block into the strip (one thread per row)
+    if (tid < QB) {
+      const int64_t s = blk * QB + tid;
+      int r = -1;
+      if (s < pd.nXi) {
+        r = xi[pd.xi_off + s];
+      } else if (MODE == QR_SOLVE && s < nstream) {
+        const int t = (int)(s - pd.nXi);
+        int lo = 0, hi = pd.nG - 1;               // largest gg with sGpre[gg] <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sGpre[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int gg = lo, cg = G[gg];
+        r = trow[trowptr[cg] + (t - sGpre[gg])];
+        // taken once, at its first interface column, and only if no column
+        // of the row is interior (those rows are in Xi_i)
+        for (int e = rowptr[r]; e < rowptr[r + 1] && r >= 0; ++e) {
+          const int c = colind[e];
+          if (part[c] == i) { r = -1; break; }
+          if (c < cg) {
+            int a = 0, b = pd.nG;
+            while (a < b) {
+              const int mid = (a + b) >> 1;
+              if (G[mid] < c) a = mid + 1; else b = mid;
+            }
+            if (a < pd.nG && G[a] == c) r = -1;
+          }
+        }
+      }
+      if (r >= 0) {
+        int jmin = INT_MAX, jmax = -1;
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          int posP;
+          const int pos = layout_pos(colind[e], &posP);
+          if (pos < 0) continue;
+          Bs[(int64_t)pos * QB + tid] = vals[e] * scale[pd.loc_off + posP];
+          const int K = pos / TS;
+          sGen[K] = gen;
+          jmin = min(jmin, K);
+          jmax = max(jmax, K);
+        }
+        if (jmax >= 0) { atomicMin(&s_jmin, jmin); atomicMax(&s_jmax, jmax); }
+      }
+    }
+    __syncthreads();
+    // ---- tile columns of the block, ascending
+    int J = s_jmin;
+    while (true) {
+      while (J <= s_jmax && sGen[J] != gen) ++J;
+      if (J > s_jmax || (MODE == QR_SEL && J >= ntI)) break;
+      int nr;
+      if (MODE == QR_GAMMA) {
+        nr = ntiles - J - 1;
+        for (int a = tid; a < nr; a += QR_THREADS) sRows[a] = J + 1 + a;
+        __syncthreads();
+      } else {
+        nr = envelope_rows(sF, J, ntiles, sRows, QR_TMAX, &s_count);
+      }
+      // panel: the triangle R(J, J) over B(:, J)
+      double* Rjj = rtile(J, J);
+      double* Bj = Bs + (int64_t)(J * TS + k) * QB + 4 * g;
+      double b[4], rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b[q] = Bj[q];
+        rr[q] = Rjj[(4 * g + q) * sc + k * sk];
+      }
+      for (int c = 0; c < TS; ++c) {
+        const int gc = c >> 2, qc = c & 3;
+        const double rc = qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3];
+        // ||(alpha, x)|| with the column scaled by a power of two near its
+        // largest entry first: entries left by rounding in earlier steps can
+        // be so small that their squares underflow (a column whose entries
+        // are all below 1e-290 is not reflected; the block drops them)
+        const double alpha = oct_allsum(g == gc ? rc : 0.0);
+        const double mx = oct_allmax(fmax(fmax(fabs(b[0]), fabs(b[1])), fmax(fabs(b[2]), fabs(b[3]))));
+        const double p2 = mx > 0.0 ? ldexp(1.0, -ilogb(fmax(mx, fabs(alpha)))) : 1.0;
+        const double s2 = oct_allsum((b[0] * p2) * (b[0] * p2) + (b[1] * p2) * (b[1] * p2) +
+                                     (b[2] * p2) * (b[2] * p2) + (b[3] * p2) * (b[3] * p2));
+        if (k == c) {
+          double tau = 0.0, beta = alpha, scl = 0.0;
+          if (mx > 1e-290) {             // below: rounding residue, left to be dropped
+            const double as = alpha * p2;
+            const double nrm = sqrt(as * as + s2) / p2;
+            beta = alpha > 0.0 ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scl = 1.0 / (alpha - beta);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            b[q] *= scl;
+            sV[c * QB + 4 * g + q] = b[q];
+          }
+          if (g == gc) {
+            if (qc == 0) rr[0] = beta; else if (qc == 1) rr[1] = beta;
+            else if (qc == 2) rr[2] = beta; else rr[3] = beta;
+          }
+          if (g == 0) sTau[c] = tau;
+        }
+        __syncthreads();
+        const double tau = sTau[c];
+        if (tau != 0.0) {
+          double v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = sV[c * QB + 4 * g + q];
+          double wp = g == gc ? (qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3]) : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) wp += v[q] * b[q];
+          const double w = oct_allsum(wp) * tau;
+          if (k > c) {
+            if (g == gc) {
+              if (qc == 0) rr[0] -= w; else if (qc == 1) rr[1] -= w;
+              else if (qc == 2) rr[2] -= w; else rr[3] -= w;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] -= v[q] * w;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Rjj[(4 * g + q) * sc + k * sk] = rr[q];
+        Bj[q] = 0.0;
+      }
+      // the reflectors applied to the tiles right of J in the envelope
+      for (int a = 0; a < nr; ++a) {
+        const int K = sRows[a];
+        double* Rjk = rtile(J, K);
+        double* Bk = Bs + (int64_t)(K * TS + k) * QB + 4 * g;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          b[q] = Bk[q];
+          rr[q] = Rjk[(4 * g + q) * sc + k * sk];
+        }
+        for (int c = 0; c < TS; ++c) {
+          const double tau = sTau[c];
+          if (tau == 0.0) continue;
+          const int gc = c >> 2, qc = c & 3;
+          double v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = sV[c * QB + 4 * g + q];
+          double wp = g == gc ? (qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3]) : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) wp += v[q] * b[q];
+          const double w = oct_allsum(wp) * tau;
+          if (g == gc) {
+            if (qc == 0) rr[0] -= w; else if (qc == 1) rr[1] -= w;
+            else if (qc == 2) rr[2] -= w; else rr[3] -= w;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[q] -= v[q] * w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          Rjk[(4 * g + q) * sc + k * sk] = rr[q];
+          Bk[q] = b[q];
+        }
+      }
+      if (tid == 0 && nr > 0) {
+        for (int a = 0; a < nr; ++a) sGen[sRows[a]] = gen;
+        s_jmax = max(s_jmax, sRows[nr - 1]);
+      }
+      __syncthreads();
+      ++J;
+    }
+    if (MODE == QR_SEL) {
+      // interface tiles of the block were not eliminated: clear them
+      for (int K = ntI; K < ntiles; ++K) {
+        if (sGen[K] != gen) continue;
+        double* Bk = Bs + (int64_t)K * TS * QB;
+        for (int e = tid; e < TS * QB; e += QR_THREADS) Bk[e] = 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  if (MODE == QR_GAMMA) return;
+  // ---- positive diagonal, identity on padding, inverse diagonal tiles
+  const int ncol = MODE == QR_SEL ? ntI : ntiles;
+  for (int J = 0; J < ncol; ++J) {
+    const int nr = envelope_rows(sF, J, ntiles, sRows, QR_TMAX, &s_count);
+    double* Ljj = rtile(J, J);
+    if (tid < TS) {
+      const int c = tid, pos = J * TS + c;
+      const bool real = (MODE == QR_SOLVE && d.spare) ? pos < pd.nI + pd.nG
+                                                     : (pos < pd.nI || (pos >= pd.nIp && pos < pd.nIp + pd.nG));
+      const double dg = Ljj[c * TS + c];
+      double sg = dg < 0.0 ? -1.0 : 1.0;
+      if (!real) {
+        Ljj[c * TS + c] = 1.0;
+        sg = 1.0;
+      } else if (!(fabs(dg) > 0.0) || !(fabs(dg) < INFINITY)) {
+        s_fail = 1;
+        Ljj[c * TS + c] = 1.0;
+        sg = 1.0;
+      }
+      sSgn[c] = sg;
+    }
+    __syncthreads();
+    // column c of L in every tile of tile column J times its sign
+    for (int a = -1; a < nr; ++a) {
+      double* T = a < 0 ? Ljj : rtile(J, sRows[a]);
+      for (int e = tid; e < TT; e += QR_THREADS) {
+        const int c = e / TS, rw = e % TS;
+        if (a < 0 && rw < c) continue;
+        T[e] *= sSgn[c];
+      }
+    }
+    __syncthreads();
+    // L(J, J)^{-1}, lane c forming column c by forward substitution
+    for (int e = tid; e < TT; e += QR_THREADS) sX[(e / TS) * LDT + e % TS] = Ljj[e];
+    __syncthreads();
+    if (tid < TS) {
+      const int c = tid;
+      double x[TS];
+#pragma unroll
+      for (int a = 0; a < TS; ++a) {
+        double t = a == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int bq = 0; bq < a; ++bq) t -= sX[bq * LDT + a] * x[bq];
+        x[a] = a < c ? 0.0 : t / sX[a * LDT + a];
+      }
+#pragma unroll
+      for (int a = 0; a < TS; ++a) Di[(int64_t)J * TT + c * TS + a] = x[a];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_fail) atomicCAS(status, 0, i + 1);
+}
+
+void launch_qr_local(hipStream_t st, int mode, int nsub, const DevPlan& P, const DevPlan& Lay,
+                     const DevMatrix& M, const int32_t* inv, const double* scale, double* out,
+                     double* dinv, double* strip, int32_t* status) {
+  if (nsub <= 0) return;
+#define LSQ2L_QR_ARGS                                                                          \
+  Lay.heavy(), P.subs, Lay.tileF, Lay.tileOff, P.omega, P.xi, P.part, P.locown, M.rowptr,     \
+      M.colind, M.vals, M.trowptr, M.trow, inv, scale, out, dinv, strip, status
+  if (mode == QR_SEL) k_qr_local<QR_SEL><<<nsub, QR_THREADS, 0, st>>>(LSQ2L_QR_ARGS);
+  else if (mode == QR_SOLVE) k_qr_local<QR_SOLVE><<<nsub, QR_THREADS, 0, st>>>(LSQ2L_QR_ARGS);
+  else k_qr_local<QR_GAMMA><<<nsub, QR_THREADS, 0, st>>>(LSQ2L_QR_ARGS);
+#undef LSQ2L_QR_ARGS
+}
+
+// scale[pos] = 1 / ||A(:, c)|| for the column c at position pos of Omega_i
+// (0 on padding): the equilibration S C_ii S of the Cholesky route, read off
+// the columns of A instead of the diagonal of the formed C_ii.
+__global__ void __launch_bounds__(256)
+k_col_scale(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
+            const int32_t* __restrict__ trowptr, const double* __restrict__ tvals,
+            double* __restrict__ scale) {
+  const SubDesc d = subs[blockIdx.x];
+  const int32_t* om = omega + d.omega_off;
+  for (int pos = blockIdx.y * blockDim.x + threadIdx.x; pos < d.np; pos += gridDim.y * blockDim.x) {
+    int a = -1;
+    if (pos < d.nI) a = pos;
+    else if (pos >= d.nIp && pos < d.nIp + d.nG) a = d.nI + (pos - d.nIp);
+    double s = 0.0;
+    if (a >= 0) {
+      const int c = om[a];
+      double t = 0.0;
+      for (int e = trowptr[c]; e < trowptr[c + 1]; ++e) t += tvals[e] * tvals[e];
+      s = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+    }
+    scale[d.loc_off + pos] = s;
+  }
+}
+
+void launch_col_scale(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* scale) {
+  if (nsub <= 0) return;
+  const int ny = (int)std::min(64, (P.max_np + 255) / 256);
+  k_col_scale<<<dim3(nsub, std::max(ny, 1)), 256, 0, st>>>(P.subs, P.omega, M.trowptr, M.tvals, scale);
+}
+
+}  // namespace lsq2l

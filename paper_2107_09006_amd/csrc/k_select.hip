@@ -20,6 +20,14 @@
 //      thread per vector), clusters of close eigenvalues re-orthonormalised,
 //      and back-transformation through the Householder reflectors;
 //   6. Y = W U (interface coefficients of the selected vectors), sigma.
+// With qr_range (the QR route of Remarks 3.1 / 3.2), ctg holds instead the
+// upper triangle R_G of a QR of A(Xi_i, Omega_Gamma_i) S (R_G^T R_G = Ct),
+// and step 1 takes W from a QR with column pivoting of R_G with unit
+// columns, stopped when the largest remaining column norm is at most n eps:
+// no Gram matrix of A is formed on the way to W.  With T from the QR factor
+// of A(Xi_i, Omega_i), K = W^T T W is the Gram matrix of Q_I^T Q_G and its
+// eigenvalues are the squared cosines of the principal angles between
+// range(A(Xi_i, Omega_Ii)) and range(A(Xi_i, Omega_Gamma_i)).
 // Work matrices (ld = nGp, five per subdomain at 5 g_off): M0 scaled Ct and
 // the pivoted factor, then K and the Householder vectors, then Y; M1 the
 // permuted T, then U; M2 R11^{-T}; M3 products, then with M4 the scratch of
@@ -263,7 +271,8 @@ template <int THREADS, int MINN, int MAXN>
 __global__ void __launch_bounds__(THREADS)
 k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
          const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
-         int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail) {
+         int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail,
+         int qr_range) {
   constexpr int NG = THREADS / 256;   // thread groups splitting the columns of A22 v
   static_assert(NG >= 1 && THREADS % 256 == 0, "whole groups of 256 threads");
   __shared__ double sd[MAXN], se[MAXN], stau[MAXN], sv[MAXN], sw[MAXN], sD2[MAXN], slam[MAXN];
@@ -297,7 +306,12 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   // a zero diagonal (stored zeros only) leaves its column out of range(Ct)
   int nz = 0;
   for (int a = tid; a < n; a += nthr) {
-    const double c = Ct[(int64_t)a * ld + a];
+    double c = 0.0;
+    if (qr_range) {                       // diagonal of Ct = squared column norm of R_G
+      for (int b = 0; b <= a; ++b) { const double t = Ct[(int64_t)a * ld + b]; c += t * t; }
+    } else {
+      c = Ct[(int64_t)a * ld + a];
+    }
     sD2[a] = c > 0.0 ? 1.0 / sqrt(c) : 0.0;
     nz += !(c > 0.0);
   }
@@ -307,8 +321,13 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     const int r = (int)(q % ld), c = (int)(q / ld);
     double v = 0.0;
     if (r < n && c < n) {
-      v = (r >= c) ? Ct[(int64_t)c * ld + r] : Ct[(int64_t)r * ld + c];
-      v *= sD2[r] * sD2[c];
+      if (qr_range) {
+        // R_G D2, upper triangle; Ct is diagonal iff R_G is
+        v = r <= c ? Ct[(int64_t)c * ld + r] * sD2[c] : 0.0;
+      } else {
+        v = (r >= c) ? Ct[(int64_t)c * ld + r] : Ct[(int64_t)r * ld + c];
+        v *= sD2[r] * sD2[c];
+      }
       if (r != c) off += fabs(v);   // exact zero test: any coupling needs the general route
     }
     M0[q] = v;
@@ -326,6 +345,83 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     }
     __syncthreads();
   } else {
+   if (qr_range) {
+    // QR with column pivoting of M0 = R_G D2 (unit columns): step k takes the
+    // remaining column of largest norm (ties: the first), reflects it onto
+    // row k and applies the reflector to the columns right of it, one thread
+    // per column.  Column norms over rows k.. are downdated and recomputed
+    // when the downdate has cancelled below 1e-4 of the last exact value.  R
+    // ends in the upper triangle, sperm holds the column order.
+    double* snrm = sd;                    // sd / se are free until step 3
+    double* sref = se;
+    for (int a = tid; a < n; a += nthr) {
+      sperm[a] = a;
+      double t = 0.0;
+      for (int b = 0; b < n; ++b) { const double x = M0[(int64_t)a * ld + b]; t += x * x; }
+      snrm[a] = t;
+      sref[a] = t;
+    }
+    __syncthreads();
+    const double tol = (double)n * SEL_EPS;
+    int k = 0;
+    for (; k < n; ++k) {
+      double bv = -1.0;
+      int bi = n;
+      for (int j = k + tid; j < n; j += nthr)
+        if (snrm[j] > bv) { bv = snrm[j]; bi = j; }
+      double mv;
+      int mj;
+      wg_argmax(bv, bi, sred, sredi, &mv, &mj);
+      if (!(mv > tol * tol)) break;
+      if (mj != k) {
+        for (int a = tid; a < n; a += nthr) {
+          const double t = M0[(int64_t)k * ld + a];
+          M0[(int64_t)k * ld + a] = M0[(int64_t)mj * ld + a];
+          M0[(int64_t)mj * ld + a] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int t = sperm[k]; sperm[k] = sperm[mj]; sperm[mj] = t;
+          double u = snrm[k]; snrm[k] = snrm[mj]; snrm[mj] = u;
+          u = sref[k]; sref[k] = sref[mj]; sref[mj] = u;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int a = k + 1 + tid; a < n; a += nthr) { const double t = M0[(int64_t)k * ld + a]; part += t * t; }
+      const double xn2 = wg_sum(part, sred);
+      const double alpha = M0[(int64_t)k * ld + k];
+      double tk = 0.0, beta = alpha, scl = 0.0;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (beta - alpha) / beta;
+        scl = 1.0 / (alpha - beta);
+      }
+      for (int a = k + tid; a < n; a += nthr) {
+        sv[a] = a == k ? 1.0 : M0[(int64_t)k * ld + a] * scl;
+        M0[(int64_t)k * ld + a] = a == k ? beta : 0.0;
+      }
+      __syncthreads();
+      for (int j = k + 1 + tid; j < n; j += nthr) {
+        double* cj = M0 + (int64_t)j * ld;
+        if (tk != 0.0) {
+          double w = 0.0;
+          for (int a = k; a < n; ++a) w += sv[a] * cj[a];
+          w *= tk;
+          for (int a = k; a < n; ++a) cj[a] -= w * sv[a];
+        }
+        double t = snrm[j] - cj[k] * cj[k];
+        if (!(t > 1e-4 * sref[j])) {
+          t = 0.0;
+          for (int a = k + 1; a < n; ++a) t += cj[a] * cj[a];
+          sref[j] = t;
+        }
+        snrm[j] = t;
+      }
+      __syncthreads();
+    }
+    r = k;
+   } else {
     // pivoted Cholesky of M0 with symmetric row/column interchanges; row k of
     // the upper triangle receives row k of R, sperm the pivot order.  Only the
     // upper triangle is kept up to date (the trailing block is symmetric, and
@@ -381,6 +477,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       __syncthreads();
     }
     r = k;
+   }
     if (r == 0) {
       if (tid == 0) p_out[i] = 0;
       return;
@@ -801,14 +898,15 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
 }
 
 void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
-                   double* work, double tau, int nev_max, int32_t* p_out, double* sig_out) {
+                   double* work, double tau, int nev_max, int32_t* p_out, double* sig_out,
+                   int qr_range) {
   // size classes of the interface: up to 128, 512 and SEL_MAXN columns
   k_select<256, 0, 128><<<nsub, 256, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out,
-                                              p_out + nsub);
+                                              p_out + nsub, qr_range);
   k_select<512, 128, 512><<<nsub, 512, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out,
-                                                sig_out, p_out + nsub);
+                                                sig_out, p_out + nsub, qr_range);
   k_select<SEL_THREADS, 512, SEL_MAXN><<<nsub, SEL_THREADS, 0, st>>>(
-      P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out, p_out + nsub);
+      P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out, p_out + nsub, qr_range);
 }
 
 }  // namespace lsq2l

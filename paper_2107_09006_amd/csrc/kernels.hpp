@@ -230,13 +230,33 @@ void launch_frob_interior(hipStream_t st, int nsub, const DevPlan& P, const doub
 // C_ii += s I on the real (non-padding) positions
 void launch_add_diag(hipStream_t st, int nsub, const DevPlan& P, double s, double* fac);
 
+// --- local factors from thin QR factorizations (k_qr.hip) --------------------
+// QR_SEL: L_I and L_GI of the layout P from the rows Xi_i (out = fac, dinv);
+// QR_SOLVE: the whole factor of C_ii in the layout Lay (the solve layout, inv
+// the [I, Gamma] -> global-order position map of its permuted subdomains);
+// QR_GAMMA: R_G of A(Xi_i, Omega_Gamma_i) into the dense interface matrices
+// (out = ctg, zeroed by the caller).  The factor arrays must be zero on
+// entry; strip holds 32 * P.total_loc doubles, zero on entry and on return.
+// status: first failing subdomain + 1 (zero or non-finite diagonal, or a
+// layout beyond the kernel's tables).
+enum { QR_SEL = 0, QR_SOLVE = 1, QR_GAMMA = 2 };
+constexpr int QR_STRIP_ROWS = 32;
+void launch_qr_local(hipStream_t st, int mode, int nsub, const DevPlan& P, const DevPlan& Lay,
+                     const DevMatrix& M, const int32_t* inv, const double* scale, double* out,
+                     double* dinv, double* strip, int32_t* status);
+// scale = 1 / ||A(:, c)|| per position of the layout P (0 on padding)
+void launch_col_scale(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* scale);
+
 // --- coarse space ------------------------------------------------------------
 void launch_gamma_T(hipStream_t st, int nsub, const DevPlan& P, const double* fac, double* Tg);
 // ld x ld work matrices per subdomain of the selection (work holds
 // SEL_WORK_MATS * total_g doubles; Y, the selected vectors, is the first)
 constexpr int SEL_WORK_MATS = 5;
+// qr_range: ctg holds the interface factors R_G of the QR route (k_qr.hip)
+// instead of Ct_GG, and the range basis comes from a pivoted QR of them
 void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
-                   double* work, double tau, int nev_max, int32_t* p_out, double* sig_out);
+                   double* work, double tau, int nev_max, int32_t* p_out, double* sig_out,
+                   int qr_range = 0);
 void launch_coarse_X(hipStream_t st, int nsub, const DevPlan& P, const double* fac,
                      const double* dinv, const double* scale, const double* work,
                      const double* sig, double* X);

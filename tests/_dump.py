@@ -3,7 +3,7 @@ read by tests/host/plan_check.cpp."""
 import numpy as np
 
 
-def dump_problems(problems, path):
+def dump_problems(problems, path, values=False):
     rp = [0]
     ci, part, sop = [], [], []
     M = N = NP = 0
@@ -21,3 +21,5 @@ def dump_problems(problems, path):
         ci.tofile(f)
         part.tofile(f)
         np.array(sop, dtype=np.int32).tofile(f)
+        if values:
+            np.concatenate([np.asarray(p.data, dtype=np.float64) for p in problems]).tofile(f)
