@@ -88,12 +88,12 @@ class Workload:
         return L.Solver.batched(args, p0.tau, device="cuda:0", tol=p0.tol, **opts)
 
 
-def run_step(L, wl, precision, variant):
+def run_step(L, wl, precision, variant, **extra):
     """setup + solve + destroy; returns (ms, per-instance solve infos, setup info)."""
     import torch
     t0 = time.perf_counter()
     s = wl.solver(L, precision=precision, variant=variant,
-                  flexible=int(variant == L.BALANCED and precision == L.MIXED))
+                  flexible=int(variant == L.BALANCED and precision == L.MIXED), **extra)
     _, info, _ = s.solve(wl.b, x=wl.x)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
@@ -102,16 +102,16 @@ def run_step(L, wl, precision, variant):
     return ms, info, sinfo
 
 
-def timed(L, wl, precision, variant, steps, warmup, tag):
+def timed(L, wl, precision, variant, steps, warmup, tag, **extra):
     import torch
     for w in range(warmup):
-        ms, info, _ = run_step(L, wl, precision, variant)
+        ms, info, _ = run_step(L, wl, precision, variant, **extra)
         log(f"[bench] {tag} warmup {w}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = []
     for k in range(steps):
-        out.append(run_step(L, wl, precision, variant))
+        out.append(run_step(L, wl, precision, variant, **extra))
         ms, info, _ = out[-1]
         log(f"[bench] {tag} step {k}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}, "
             f"relres {max(i['relres'] for i in info):.2e}")
@@ -265,6 +265,9 @@ def main():
     mixed = timed(L, wl, L.MIXED, variant, args.steps, args.warmup, "mixed")
     kern64, info64 = kernel_times(L, wl, L.FP64)
     kern32, _ = kernel_times(L, wl, L.MIXED)
+    # the QR route of Remarks 3.1 / 3.2 (local factors from thin QR
+    # factorizations of A(:, Omega_i), principal-angle selection), FP64
+    qr = timed(L, wl, L.FP64, variant, 1, 1, "qr", local_factor=L.FACTOR_QR)
 
     # dominant per-iteration kernel of the FP64 path: the batched local
     # triangular solves; achieved = algorithmic bytes (nnz(L_i) under a
@@ -323,6 +326,13 @@ def main():
                                    "GBs": round(v["GBs"], 1)}
                     for tag, kd in (("fp64", kern64), ("mixed", kern32)) for k, v in kd.items()},
         "roofline": roofline,
+        "qr_route": {"ms_per_step": round(qr["ms_per_step"], 2), "setup_ms": round(qr["setup_ms"], 2),
+                     "solve_ms": round(qr["solve_ms"], 2),
+                     "setup_phases_ms": {k: round(qr["setup"][k], 2) for k in
+                                         ["t_plan_ms", "t_assemble_ms", "t_factor_ms", "t_eigen_ms",
+                                          "t_coarse_ms"]},
+                     "iterations_max": qr["iterations_max"], "relres_max": qr["relres_max"],
+                     "n0": qr["setup"]["n0"]},
     }
     if not args.no_context:
         ctx = {}

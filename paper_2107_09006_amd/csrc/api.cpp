@@ -871,18 +871,22 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   // merges the rows of A into R; its row strips (zero between uses) are one
   // per stream.
   double* qstrip = nullptr;
+  int32_t* qscr = nullptr;
   const int64_t strip_len = (int64_t)QR_STRIP_ROWS * H.total_loc;
+  const int64_t qscr_len = 2 * H.total_loc + nparts;
   if (qr) {
     TRY(c->dalloc(&qstrip, strip_len));
+    TRY(c->dalloc(&qscr, qscr_len));
     LSQ2L_HIP_TRY(hipMemsetAsync(qstrip, 0, strip_len * sizeof(double), st));
     launch_qr_local(st, QR_SEL, nparts, c->P, c->P, c->M, nullptr, c->scale, c->fac, c->dinv, qstrip,
-                    c->status);
+                    qscr, H.total_loc, c->status);
   } else {
     launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
   }
   if (c->solve_plan) {
     double* qdinv = nullptr;     // FP64 inverse diagonal tiles of the QR solve factors
     double* qstrip2 = nullptr;
+    int32_t* qscr2 = nullptr;
     if (mixed) {
       TRY(c->dalloc(&c->fac32, c->s_total_fac));
       TRY(c->dalloc(&c->dinv32, c->s_total_dinv));
@@ -894,6 +898,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     }
     if (qr) {
       TRY(c->dalloc(&qstrip2, strip_len));
+      TRY(c->dalloc(&qscr2, qscr_len));
       LSQ2L_HIP_TRY(hipMemsetAsync(qstrip2, 0, strip_len * sizeof(double), st));
     }
     if (!c->st2) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
@@ -903,7 +908,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     LSQ2L_HIP_TRY(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
     if (qr) {
       launch_qr_local(c->st2, QR_SOLVE, nparts, c->P, c->Ps, c->M, c->sl_inv, c->scale, s64, qdinv,
-                      qstrip2, c->status + 2);
+                      qstrip2, qscr2, H.total_loc, c->status + 2);
       if (mixed) {
         launch_to_float(c->st2, c->s_total_fac, s64, c->fac32);
         launch_to_float(c->st2, c->s_total_dinv, qdinv, c->dinv32);
@@ -983,7 +988,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     // QR route: the interface factors R_G of A(Xi_i, Omega_Gamma_i) replace Ct_GG
     if (qr)
       launch_qr_local(st, QR_GAMMA, nparts, c->P, c->P, c->M, nullptr, c->scale, c->ctg, nullptr,
-                      qstrip, c->status + 4);
+                      qstrip, qscr, H.total_loc, c->status + 4);
     launch_select(st, nparts, c->P, c->ctg, Tg, work, c->tau, c->opt.nev_max, pc, sig, qr ? 1 : 0);
     std::vector<int32_t> ph(nparts + 1);
     int32_t gstat = 0;

@@ -24,14 +24,17 @@
 //             tile columns only: L_I and L_GI, what the coarse selection and
 //             the coarse basis read (rows outside Xi_i have no interior entry
 //             and do not change them);
-//   QR_SOLVE  every row of A with an entry in Omega_i (Xi_i, then the rows
-//             reached through the columns of Omega_Gamma_i only), in the solve
-//             layout of each subdomain (global column order or [I, Gamma]):
-//             the factor of C_ii the local solves read;
+//   QR_SOLVE  every row of A with an entry in Omega_i, in the solve layout
+//             of each subdomain (global column order or [I, Gamma]): the
+//             factor of C_ii the local solves read;
 //   QR_GAMMA  rows Xi_i restricted to Omega_Gamma_i into a dense n_G x n_G
 //             upper triangle R_G (column-major, ld nGp, in the interface
 //             work matrix): R_G^T R_G = Ct_GG, the input of the
 //             principal-angle selection.
+// Rows enter in the order of their first position in the layout (found
+// through the columns of A^T, no sort), as in Givens row merging: R is then
+// still empty past the rows merged so far, and a block stops within a few
+// tiles of where it starts.
 // The rows of a block live in a per-subdomain strip of QB x np doubles in
 // global memory (position-major, QB rows contiguous), which is all zero
 // between blocks: every tile a block touches is zeroed when it is eliminated
@@ -47,7 +50,8 @@ namespace {
 
 constexpr int QB = QR_STRIP_ROWS;   // rows merged per block: 8 groups of 4 per column
 constexpr int QR_THREADS = 256;   // thread t: column t / 8 of the tile, rows 4 (t % 8) ..
-constexpr int QR_TMAX = 2048;     // tiles per side (and interface prefix entries) held in LDS
+constexpr int QR_TMAX = 2048;     // tiles per side held in LDS
+constexpr int QR_CH = 1024;       // rows of the stream buffered in LDS
 
 // sum over the 8 lanes 8 q .. 8 q + 7; every lane gets the same bits
 __device__ inline double oct_allsum(double x) {
@@ -94,7 +98,7 @@ template <int MODE>
 __global__ void __launch_bounds__(QR_THREADS)
 k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
-           const int32_t* __restrict__ omega, const int32_t* __restrict__ xi,
+           const int32_t* __restrict__ omega, int32_t* __restrict__ qscr, int64_t qcol_off,
            const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
            const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
            const double* __restrict__ vals, const int32_t* __restrict__ trowptr,
@@ -104,8 +108,9 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
   __shared__ double sV[TS * QB];          // reflector c: sV[c * QB + row]
   __shared__ double sTau[TS], sSgn[TS];
   __shared__ double sX[TS * LDT];
-  __shared__ int32_t sF[QR_TMAX], sO[QR_TMAX], sGen[QR_TMAX], sRows[QR_TMAX], sGpre[QR_TMAX];
-  __shared__ int s_jmin, s_jmax, s_count, s_fail, s_tot;
+  __shared__ int32_t sF[QR_TMAX], sO[QR_TMAX], sGen[QR_TMAX], sRows[QR_TMAX], sBuf[QR_CH];
+  __shared__ uint8_t sNZ[QR_TMAX];       // tile of the list left nonzero in the block
+  __shared__ int s_jmin, s_jmax, s_count, s_fail, s_q;
   __shared__ int s_scan[4];
   const SubDesc d = subs[blockIdx.x];
   const SubDesc pd = psubs[d.id];
@@ -117,7 +122,7 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
   const int ntiles = MODE == QR_GAMMA ? pd.nGp / TS : d.ntiles;
   const int ntI = MODE == QR_GAMMA ? 0 : d.ntI;
   const int ld = pd.nGp;
-  if (ntiles > QR_TMAX || (MODE == QR_SOLVE && pd.nG + 1 > QR_TMAX)) {
+  if (ntiles > QR_TMAX) {
     if (tid == 0) atomicCAS(status, 0, i + 1);
     return;
   }
@@ -128,22 +133,6 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
     }
   for (int I = tid; I < ntiles; I += QR_THREADS) sGen[I] = -1;
   if (tid == 0) s_fail = 0;
-  // rows reached through the interface columns only (QR_SOLVE): candidate t
-  // of the stream is entry t - sGpre[g] of column G[g] of A^T
-  int nextra = 0;
-  if (MODE == QR_SOLVE) {
-    int run = 0;
-    for (int b0 = 0; b0 <= pd.nG; b0 += QR_THREADS) {
-      const int gg = b0 + tid;
-      const int len = gg < pd.nG ? trowptr[G[gg] + 1] - trowptr[G[gg]] : 0;
-      int tot;
-      const int ex = block_scan_256(len, s_scan, &tot);
-      if (gg <= pd.nG) sGpre[gg] = run + ex;
-      run += tot;
-    }
-    nextra = run;
-  }
-  __syncthreads();
   double* Lf = MODE == QR_GAMMA ? out + pd.g_off : out + d.fac_off;
   double* Di = MODE == QR_GAMMA ? nullptr : dinv + d.dinv_off;
   double* Bs = strip + (int64_t)QB * pd.loc_off;
@@ -162,55 +151,102 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
     if (MODE == QR_SOLVE && d.spare) return inv[pd.loc_off + p];
     return p;
   };
-  const int64_t nstream = (int64_t)pd.nXi + nextra;
-  for (int64_t blk = 0; blk * QB < nstream; ++blk) {
-    const int gen = (int)blk;
+  // ---- the row stream: rows ordered by their first position in the layout
+  // (the order of Givens row merging; a row that arrives after R has filled
+  // behind it would carry its fill down every remaining tile).  Candidate t
+  // is entry t - qpre[q] of column col_at(q) of A^T; a row is taken at the
+  // position q where it starts.  QR_SEL: rows of Xi_i (they start at an
+  // interior position); QR_GAMMA: rows of Xi_i by their first interface
+  // column; QR_SOLVE: every row with an entry in Omega_i.
+  const int npos = MODE == QR_SEL ? pd.nI : MODE == QR_GAMMA ? pd.nG : d.np;
+  int32_t* qpre = qscr + pd.loc_off + d.id;       // npos + 1 entries
+  int32_t* qcol = qscr + qcol_off + pd.loc_off;   // QR_SOLVE, global order: column at each position
+  if (MODE == QR_SOLVE && d.spare) {
+    for (int p = tid; p < pd.np; p += QR_THREADS) {
+      const int q = inv[pd.loc_off + p];
+      if (q >= 0) qcol[q] = p < pd.nI ? om[p] : G[p - pd.nIp];
+    }
+    __syncthreads();
+  }
+  auto col_at = [&](int q) -> int {
+    if (MODE == QR_SEL) return om[q];
+    if (MODE == QR_GAMMA) return G[q];
+    if (d.spare) return q < pd.nI + pd.nG ? qcol[q] : -1;
+    if (q < pd.nI) return om[q];
+    return (q >= pd.nIp && q < pd.nIp + pd.nG) ? G[q - pd.nIp] : -1;
+  };
+  int ncand = 0;
+  for (int b0 = 0; b0 <= npos; b0 += QR_THREADS) {
+    const int q = b0 + tid;
+    int len = 0;
+    if (q < npos) {
+      const int c = col_at(q);
+      if (c >= 0) len = trowptr[c + 1] - trowptr[c];
+    }
+    int tot;
+    const int ex = block_scan_256(len, s_scan, &tot);
+    if (q <= npos) qpre[q] = ncand + ex;
+    ncand += tot;
+  }
+  __syncthreads();
+  int cand = 0, qcur = 0, nbuf = 0;
+  int64_t blk = 0;
+  while (true) {
+    // refill the buffer, QR_THREADS candidates at a time, keeping their order
+    while (nbuf <= QR_CH - QR_THREADS && cand < ncand) {
+      const int t = cand + tid;
+      int take = -1, qt = npos;
+      if (t < ncand) {
+        int lo = qcur, hi = npos - 1;             // largest q with qpre[q] <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (qpre[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        qt = lo;
+        const int r = trow[trowptr[col_at(lo)] + (t - qpre[lo])];
+        int first = INT_MAX;
+        bool interior = false;
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int c = colind[e];
+          interior |= part[c] == i;
+          int posP;
+          const int pos = layout_pos(c, &posP);
+          if (pos >= 0) first = min(first, pos);
+        }
+        if (first == lo && (MODE != QR_GAMMA || interior)) take = r;
+      }
+      int tot;
+      const int ex = block_scan_256(take >= 0 ? 1 : 0, s_scan, &tot);
+      if (take >= 0) sBuf[nbuf + ex] = take;
+      if (tid == QR_THREADS - 1) s_q = qt;
+      __syncthreads();
+      nbuf += tot;
+      cand += QR_THREADS;
+      qcur = min(s_q, max(npos - 1, 0));
+      __syncthreads();
+    }
+    if (nbuf == 0) break;
+    int head = 0;
+    while (nbuf - head >= QB || (cand >= ncand && head < nbuf)) {
+    const int nrow = min(QB, nbuf - head);
+    const int gen = (int)blk++;
     if (tid == 0) { s_jmin = INT_MAX; s_jmax = -1; }
     __syncthreads();
     // ---- the rows of the block into the strip (one thread per row)
-    if (tid < QB) {
-      const int64_t s = blk * QB + tid;
-      int r = -1;
-      if (s < pd.nXi) {
-        r = xi[pd.xi_off + s];
-      } else if (MODE == QR_SOLVE && s < nstream) {
-        const int t = (int)(s - pd.nXi);
-        int lo = 0, hi = pd.nG - 1;               // largest gg with sGpre[gg] <= t
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sGpre[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-        const int gg = lo, cg = G[gg];
-        r = trow[trowptr[cg] + (t - sGpre[gg])];
-        // taken once, at its first interface column, and only if no column
-        // of the row is interior (those rows are in Xi_i)
-        for (int e = rowptr[r]; e < rowptr[r + 1] && r >= 0; ++e) {
-          const int c = colind[e];
-          if (part[c] == i) { r = -1; break; }
-          if (c < cg) {
-            int a = 0, b = pd.nG;
-            while (a < b) {
-              const int mid = (a + b) >> 1;
-              if (G[mid] < c) a = mid + 1; else b = mid;
-            }
-            if (a < pd.nG && G[a] == c) r = -1;
-          }
-        }
+    if (tid < nrow) {
+      const int r = sBuf[head + tid];
+      int jmin = INT_MAX, jmax = -1;
+      for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int posP;
+        const int pos = layout_pos(colind[e], &posP);
+        if (pos < 0) continue;
+        Bs[(int64_t)pos * QB + tid] = vals[e] * scale[pd.loc_off + posP];
+        const int K = pos / TS;
+        sGen[K] = gen;
+        jmin = min(jmin, K);
+        jmax = max(jmax, K);
       }
-      if (r >= 0) {
-        int jmin = INT_MAX, jmax = -1;
-        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-          int posP;
-          const int pos = layout_pos(colind[e], &posP);
-          if (pos < 0) continue;
-          Bs[(int64_t)pos * QB + tid] = vals[e] * scale[pd.loc_off + posP];
-          const int K = pos / TS;
-          sGen[K] = gen;
-          jmin = min(jmin, K);
-          jmax = max(jmax, K);
-        }
-        if (jmax >= 0) { atomicMin(&s_jmin, jmin); atomicMax(&s_jmax, jmax); }
-      }
+      if (jmax >= 0) { atomicMin(&s_jmin, jmin); atomicMax(&s_jmax, jmax); }
     }
     __syncthreads();
     // ---- tile columns of the block, ascending
@@ -226,6 +262,7 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
       } else {
         nr = envelope_rows(sF, J, ntiles, sRows, QR_TMAX, &s_count);
       }
+      for (int a = tid; a < nr; a += QR_THREADS) sNZ[a] = 0;
       // panel: the triangle R(J, J) over B(:, J)
       double* Rjj = rtile(J, J);
       double* Bj = Bs + (int64_t)(J * TS + k) * QB + 4 * g;
@@ -325,11 +362,17 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
           Rjk[(4 * g + q) * sc + k * sk] = rr[q];
           Bk[q] = b[q];
         }
+        if (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0 || b[3] != 0.0) sNZ[a] = 1;
       }
-      if (tid == 0 && nr > 0) {
-        for (int a = 0; a < nr; ++a) sGen[sRows[a]] = gen;
-        s_jmax = max(s_jmax, sRows[nr - 1]);
-      }
+      __syncthreads();
+      // a tile joins the block only if some row of it is nonzero there:
+      // exact zeros stay zeros, and the block ends where its rows do
+      if (tid == 0)
+        for (int a = 0; a < nr; ++a)
+          if (sNZ[a]) {
+            sGen[sRows[a]] = gen;
+            s_jmax = max(s_jmax, sRows[a]);
+          }
       __syncthreads();
       ++J;
     }
@@ -342,6 +385,16 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
       }
       __syncthreads();
     }
+    head += nrow;
+    }
+    // the rows not yet merged (fewer than a block) to the front
+    const int rem = nbuf - head;
+    const int keep = tid < rem ? sBuf[head + tid] : 0;
+    __syncthreads();
+    if (tid < rem) sBuf[tid] = keep;
+    nbuf = rem;
+    __syncthreads();
+    if (cand >= ncand && nbuf == 0) break;
   }
   if (MODE == QR_GAMMA) return;
   // ---- positive diagonal, identity on padding, inverse diagonal tiles
@@ -399,10 +452,11 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
 
 void launch_qr_local(hipStream_t st, int mode, int nsub, const DevPlan& P, const DevPlan& Lay,
                      const DevMatrix& M, const int32_t* inv, const double* scale, double* out,
-                     double* dinv, double* strip, int32_t* status) {
+                     double* dinv, double* strip, int32_t* qscr, int64_t total_loc, int32_t* status) {
   if (nsub <= 0) return;
-#define LSQ2L_QR_ARGS                                                                          \
-  Lay.heavy(), P.subs, Lay.tileF, Lay.tileOff, P.omega, P.xi, P.part, P.locown, M.rowptr,     \
+  const int64_t qcol_off = total_loc + nsub;
+#define LSQ2L_QR_ARGS                                                                              \
+  Lay.heavy(), P.subs, Lay.tileF, Lay.tileOff, P.omega, qscr, qcol_off, P.part, P.locown, M.rowptr, \
       M.colind, M.vals, M.trowptr, M.trow, inv, scale, out, dinv, strip, status
   if (mode == QR_SEL) k_qr_local<QR_SEL><<<nsub, QR_THREADS, 0, st>>>(LSQ2L_QR_ARGS);
   else if (mode == QR_SOLVE) k_qr_local<QR_SOLVE><<<nsub, QR_THREADS, 0, st>>>(LSQ2L_QR_ARGS);

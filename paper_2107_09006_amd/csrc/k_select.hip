@@ -387,10 +387,11 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
         }
         __syncthreads();
       }
+      // alpha is read before the barriers of the sum: (k, k) is overwritten below
+      const double alpha = M0[(int64_t)k * ld + k];
       double part = 0.0;
       for (int a = k + 1 + tid; a < n; a += nthr) { const double t = M0[(int64_t)k * ld + a]; part += t * t; }
       const double xn2 = wg_sum(part, sred);
-      const double alpha = M0[(int64_t)k * ld + k];
       double tk = 0.0, beta = alpha, scl = 0.0;
       if (xn2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -402,21 +403,30 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
         M0[(int64_t)k * ld + a] = a == k ? beta : 0.0;
       }
       __syncthreads();
-      for (int j = k + 1 + tid; j < n; j += nthr) {
-        double* cj = M0 + (int64_t)j * ld;
-        if (tk != 0.0) {
+      // one wave per column, lanes over its rows (each lane rereads only
+      // the entries it wrote)
+      {
+        const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
+        for (int j = k + 1 + wv; j < n; j += nwv) {
+          double* cj = M0 + (int64_t)j * ld;
+          const double ck = cj[k];
           double w = 0.0;
-          for (int a = k; a < n; ++a) w += sv[a] * cj[a];
-          w *= tk;
-          for (int a = k; a < n; ++a) cj[a] -= w * sv[a];
+          if (tk != 0.0) {
+            for (int a = k + ln; a < n; a += 64) w += sv[a] * cj[a];
+            w = wave_allsum(w) * tk;
+            for (int a = k + ln; a < n; a += 64) cj[a] -= w * sv[a];
+          }
+          const double ckn = ck - w;          // the new entry (k, j): sv[k] = 1
+          double t = snrm[j] - ckn * ckn;
+          if (!(t > 1e-4 * sref[j])) {
+            double part = 0.0;
+            for (int a = k + ln; a < n; a += 64)
+              if (a > k) part += cj[a] * cj[a];
+            t = wave_allsum(part);
+            if (ln == 0) sref[j] = t;
+          }
+          if (ln == 0) snrm[j] = t;
         }
-        double t = snrm[j] - cj[k] * cj[k];
-        if (!(t > 1e-4 * sref[j])) {
-          t = 0.0;
-          for (int a = k + 1; a < n; ++a) t += cj[a] * cj[a];
-          sref[j] = t;
-        }
-        snrm[j] = t;
       }
       __syncthreads();
     }

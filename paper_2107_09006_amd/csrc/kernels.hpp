@@ -236,14 +236,15 @@ void launch_add_diag(hipStream_t st, int nsub, const DevPlan& P, double s, doubl
 // the [I, Gamma] -> global-order position map of its permuted subdomains);
 // QR_GAMMA: R_G of A(Xi_i, Omega_Gamma_i) into the dense interface matrices
 // (out = ctg, zeroed by the caller).  The factor arrays must be zero on
-// entry; strip holds 32 * P.total_loc doubles, zero on entry and on return.
+// entry; strip holds 32 * total_loc doubles, zero on entry and on return;
+// qscr holds 2 total_loc + nsub int32 (row-stream tables).
 // status: first failing subdomain + 1 (zero or non-finite diagonal, or a
 // layout beyond the kernel's tables).
 enum { QR_SEL = 0, QR_SOLVE = 1, QR_GAMMA = 2 };
 constexpr int QR_STRIP_ROWS = 32;
 void launch_qr_local(hipStream_t st, int mode, int nsub, const DevPlan& P, const DevPlan& Lay,
                      const DevMatrix& M, const int32_t* inv, const double* scale, double* out,
-                     double* dinv, double* strip, int32_t* status);
+                     double* dinv, double* strip, int32_t* qscr, int64_t total_loc, int32_t* status);
 // scale = 1 / ||A(:, c)|| per position of the layout P (0 on padding)
 void launch_col_scale(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* scale);
 

@@ -1,5 +1,5 @@
 // Host replay of the QR local factors of the library (k_qr.hip): the same
-// row stream, blocks of 32 rows, tile-column order, envelope lists, strip
+// row stream (rows by first layout position), blocks of 32 rows, tile-column order, envelope lists, strip
 // layout and final pass, computed on the CPU with every strip, factor and
 // interface-matrix access checked against its buffer and the tile envelope.
 // It also checks the property the kernel relies on: when tile column J of a
@@ -42,6 +42,7 @@ struct Ctx {
 };
 
 static double maxerr = 0.0;
+static int64_t panels = 0, max_panels = 0, max_blocks = 0;   // tile columns eliminated
 
 // The kernel's arithmetic for subdomain i in one mode; returns the factor
 // (stored tiles, or the dense nGp x nGp R_G) and the inverse diagonal tiles.
@@ -95,40 +96,67 @@ static void replay(const Ctx& X, int i, int mode, const Lay& L, const std::vecto
     CHECK(pos >= 0 && (int64_t)pos * QB + l < (int64_t)B.size() && l >= 0 && l < QB, "strip index");
     return B[(size_t)pos * QB + l];
   };
-  // interface-column prefix of A^T row lengths (QR_SOLVE)
-  std::vector<int> gpre(d.nG + 1, 0);
-  int nextra = 0;
-  if (mode == SOLVE) {
-    for (int g = 0; g < d.nG; ++g) gpre[g + 1] = gpre[g] + ((*X.trp)[G[g] + 1] - (*X.trp)[G[g]]);
-    nextra = gpre[d.nG];
+  // the row stream: rows in the order of their first position in the layout,
+  // found through the columns of A^T (position ascending, A^T order inside)
+  const int npos = mode == SEL ? d.nI : mode == GAMMA ? d.nG : L.np;
+  std::vector<int> qcol(L.np, -1);
+  if (mode == SOLVE && L.global)
+    for (int p = 0; p < d.np; ++p) {
+      const int q = inv[d.loc_off + p];
+      if (q >= 0) qcol[q] = p < d.nI ? om[p] : G[p - d.nIp];
+    }
+  auto col_at = [&](int q) -> int {
+    if (mode == SEL) return om[q];
+    if (mode == GAMMA) return G[q];
+    if (L.global) return q < d.nI + d.nG ? qcol[q] : -1;
+    if (q < d.nI) return om[q];
+    return (q >= d.nIp && q < d.nIp + d.nG) ? G[q - d.nIp] : -1;
+  };
+  std::vector<int> stream;
+  for (int q = 0; q < npos; ++q) {
+    const int c = col_at(q);
+    if (c < 0) continue;
+    for (int k = (*X.trp)[c]; k < (*X.trp)[c + 1]; ++k) {
+      const int r = (*X.tcol)[k];
+      int first = INT32_MAX;
+      bool interior = false;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        interior |= part[ci[e]] == i;
+        int posP;
+        const int pos = layout_pos(ci[e], &posP);
+        if (pos >= 0) first = std::min(first, pos);
+      }
+      if (first == q && (mode != GAMMA || interior)) stream.push_back(r);
+    }
   }
-  const int64_t nstream = (int64_t)d.nXi + nextra;
+  {
+    // every row the mode needs, exactly once
+    std::vector<int> want;
+    for (int r = 0; r < X.m; ++r) {
+      bool in_omega = false, interior = false, gamma = false;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int p = local_pos(ci[e]);
+        in_omega |= p >= 0;
+        interior |= part[ci[e]] == i;
+        gamma |= p >= d.nIp;
+      }
+      if ((mode == SEL && interior) || (mode == SOLVE && in_omega) || (mode == GAMMA && interior && gamma))
+        want.push_back(r);
+    }
+    std::vector<int> got(stream);
+    std::sort(got.begin(), got.end());
+    CHECK(got == want, "row stream of sub %d (mode %d): %zu rows, %zu wanted", i, mode, got.size(), want.size());
+  }
+  const int64_t nstream = (int64_t)stream.size();
+  const int64_t p0 = panels;
+  struct Tally { int64_t p0, nb; ~Tally() { const int64_t n = panels - p0; if (n > max_panels) { max_panels = n; max_blocks = nb; } } } tally{p0, (nstream + QB - 1) / QB};
   for (int64_t blk = 0; blk * QB < nstream; ++blk) {
     const int gn = (int)blk;
     int jmin = INT32_MAX, jmax = -1;
     for (int l = 0; l < QB; ++l) {
       const int64_t s = blk * QB + l;
-      int r = -1;
-      if (s < d.nXi) {
-        r = H.xi[d.xi_off + s];
-      } else if (mode == SOLVE && s < nstream) {
-        const int t = (int)(s - d.nXi);
-        int lo = 0, hi = d.nG - 1;
-        while (lo < hi) { const int mid = (lo + hi + 1) / 2; if (gpre[mid] <= t) lo = mid; else hi = mid - 1; }
-        const int gg = lo, cg = G[gg];
-        CHECK(t - gpre[gg] >= 0 && t - gpre[gg] < (*X.trp)[cg + 1] - (*X.trp)[cg], "extra candidate");
-        r = (*X.tcol)[(*X.trp)[cg] + (t - gpre[gg])];
-        for (int e = rp[r]; e < rp[r + 1] && r >= 0; ++e) {
-          const int c = ci[e];
-          if (part[c] == i) { r = -1; break; }
-          if (c < cg) {
-            int a = 0, b = d.nG;
-            while (a < b) { const int mid = (a + b) / 2; if (G[mid] < c) a = mid + 1; else b = mid; }
-            if (a < d.nG && G[a] == c) r = -1;
-          }
-        }
-      }
-      if (r < 0) continue;
+      if (s >= nstream) break;
+      const int r = stream[s];
       for (int e = rp[r]; e < rp[r + 1]; ++e) {
         int posP;
         const int pos = layout_pos(ci[e], &posP);
@@ -147,6 +175,7 @@ static void replay(const Ctx& X, int i, int mode, const Lay& L, const std::vecto
       if (J > jmax || (mode == SEL && J >= ntI)) break;
       std::vector<int> rows;
       for (int K = J + 1; K < ntiles; ++K) if (dense || L.F[K] <= J) rows.push_back(K);
+      ++panels;
       // panel
       double V[TS][QB], tau[TS];
       for (int c = 0; c < TS; ++c) {
@@ -200,8 +229,9 @@ static void replay(const Ctx& X, int i, int mode, const Lay& L, const std::vecto
             for (int l = 0; l < QB; ++l) Bat(K * TS + kk, l) -= V[c][l] * w;
           }
         }
-        gen[K] = gn;
-        jmax = std::max(jmax, K);
+        bool nz = false;
+        for (int kk = 0; kk < TS; ++kk) for (int l = 0; l < QB; ++l) nz |= Bat(K * TS + kk, l) != 0.0;
+        if (nz) { gen[K] = gn; jmax = std::max(jmax, K); }
       }
       ++J;
     }
@@ -433,6 +463,8 @@ int main(int argc, char** argv) {
       CHECK(e <= 1e-12 * std::max(scl, 1.0), "R_G of sub %d off by %g", i, e);
     }
   }
+  printf("panels: %lld in all, at most %lld in one factor (%lld blocks)\n", (long long)panels,
+         (long long)max_panels, (long long)max_blocks);
   printf("OK %d subdomains replayed, %d checked against the definitions, max rel error %.3g\n", nparts,
          checked, maxerr);
   return 0;
