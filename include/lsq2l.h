@@ -135,9 +135,8 @@ typedef struct {
                          and range(A(Xi_i, Omega_Gamma_i)), the numerical range of the latter
                          from a column-pivoted QR of the R of A(Xi_i, Omega_Gamma_i); the
                          condition number of the local blocks is not squared on the way.  Not
-                         with diag_shift_rel > 0 (LSQ2L_EINVAL); subdomains of up to 65,536
-                         positions, interfaces of up to 2,047 columns (else
-                         LSQ2L_CHOL_BREAKDOWN with a message)                                  */
+                         with diag_shift_rel > 0 (LSQ2L_EINVAL); subdomains of up to 32,768
+                         padded positions (else LSQ2L_CHOL_BREAKDOWN with a message)           */
 } lsq2l_options;
 
 enum { LSQ2L_ORDER_AUTO = 0, LSQ2L_ORDER_SPLIT = 1, LSQ2L_ORDER_GLOBAL = 2 };

@@ -875,11 +875,12 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   const int64_t strip_len = (int64_t)QR_STRIP_ROWS * H.total_loc;
   const int64_t qscr_len = 2 * H.total_loc + nparts;
   if (qr) {
+    // the two QR factorizations are bound by the row-block chains of the
+    // largest subdomains and leave room beside each other: the solve
+    // factors start first on st2 (below), the selection's on st after them
     TRY(c->dalloc(&qstrip, strip_len));
     TRY(c->dalloc(&qscr, qscr_len));
     LSQ2L_HIP_TRY(hipMemsetAsync(qstrip, 0, strip_len * sizeof(double), st));
-    launch_qr_local(st, QR_SEL, nparts, c->P, c->P, c->M, nullptr, c->scale, c->fac, c->dinv, qstrip,
-                    qscr, H.total_loc, c->status);
   } else {
     launch_chol_local(st, nparts, c->P, c->fac, c->dinv, c->status, c->solve_plan);
   }
@@ -904,7 +905,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     if (!c->st2) LSQ2L_HIP_TRY(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     if (!c->ev_fork) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     if (!c->ev_join) LSQ2L_HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));           // after the gather and the first factor
+    LSQ2L_HIP_TRY(hipEventRecord(c->ev_fork, st));   // after the gather (Cholesky: and the first factor)
     LSQ2L_HIP_TRY(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
     if (qr) {
       launch_qr_local(c->st2, QR_SOLVE, nparts, c->P, c->Ps, c->M, c->sl_inv, c->scale, s64, qdinv,
@@ -921,13 +922,16 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     }
     LSQ2L_HIP_TRY(hipEventRecord(c->ev_join, c->st2));
   }
+  if (qr)
+    launch_qr_local(st, QR_SEL, nparts, c->P, c->P, c->M, nullptr, c->scale, c->fac, c->dinv, qstrip,
+                    qscr, H.total_loc, c->status);
   int32_t hstat[8];
   LSQ2L_HIP_TRY(hipMemcpyAsync(hstat, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipStreamSynchronize(st));
   if (hstat[0] != 0) {
     if (qr)
       set_error("QR local factor failed in subdomain " + std::to_string(hstat[0] - 1) +
-                " (A(Xi_i, Omega_Ii) rank deficient, or more than 65,536 positions)");
+                " (A(Xi_i, Omega_Ii) rank deficient, or more than 32,768 positions)");
     else
       set_error("local Cholesky breakdown in subdomain " + std::to_string(hstat[0] - 1));
     if (c->st2) (void)hipStreamSynchronize(c->st2);
@@ -945,7 +949,7 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     LSQ2L_HIP_TRY(hipStreamSynchronize(st));
     if (hs != 0 && qr) {
       set_error("QR solve factor failed in subdomain " + std::to_string(hs - 1) +
-                " (A(:, Omega_i) rank deficient, or a layout beyond the QR kernel's tables)");
+                " (A(:, Omega_i) rank deficient, or more than 32,768 positions)");
       return LSQ2L_CHOL_BREAKDOWN;
     }
     if (hs != 0 && mixed) {

@@ -40,7 +40,6 @@
 // between blocks: every tile a block touches is zeroed when it is eliminated
 // (or, for QR_SEL, at the end of the block).
 #include <climits>
-#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -48,28 +47,30 @@ namespace lsq2l {
 
 namespace {
 
-constexpr int QB = QR_STRIP_ROWS;   // rows merged per block: 8 groups of 4 per column
-constexpr int QR_THREADS = 256;   // thread t: column t / 8 of the tile, rows 4 (t % 8) ..
-constexpr int QR_TMAX = 2048;     // tiles per side held in LDS
-constexpr int QR_CH = 1024;       // rows of the stream buffered in LDS
+constexpr int QB = QR_STRIP_ROWS;   // rows merged per block
+constexpr int QR_THREADS = 256;   // four waves; lane (kc, h): column kc, rows 16 h .. 16 h + 15
+constexpr int QR_TMAX = 1024;     // tiles per side held in LDS (32,768 positions)
+constexpr int QR_CH = 512;        // rows of the stream buffered in LDS
 
-// sum over the 8 lanes 8 q .. 8 q + 7; every lane gets the same bits
-__device__ inline double oct_allsum(double x) {
-  x = dpp_pair_sum<0xB1>(x);
-  x = dpp_pair_sum<0x4E>(x);
-  return dpp_pair_sum<0x141>(x);
+// 1 / x from the hardware estimate and two Newton steps (a few units in the
+// last place, in a fraction of a division's latency)
+__device__ inline double rcp2(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-// max over the same 8 lanes
-__device__ inline double oct_allmax(double x) {
-  auto step = [](double v, auto ctrl) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), decltype(ctrl)::value, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), decltype(ctrl)::value, 0xF, 0xF, false);
-    return fmax(v, __hiloint2double(hi, lo));
-  };
-  x = step(x, std::integral_constant<int, 0xB1>{});
-  x = step(x, std::integral_constant<int, 0x4E>{});
-  return step(x, std::integral_constant<int, 0x141>{});
+// sum of a[q] b[q] over 16 entries in four independent chains
+__device__ inline double dot16(const double* a, const double* b, double init) {
+  double p0 = init, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; q += 4) {
+    p0 = fma(a[q], b[q], p0);
+    p1 = fma(a[q + 1], b[q + 1], p1);
+    p2 = fma(a[q + 2], b[q + 2], p2);
+    p3 = fma(a[q + 3], b[q + 3], p3);
+  }
+  return (p0 + p1) + (p2 + p3);
 }
 
 // exclusive scan of v over the 256 threads, total in *tot
@@ -105,9 +106,10 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
            const int32_t* __restrict__ trow, const int32_t* __restrict__ inv,
            const double* __restrict__ scale, double* __restrict__ out,
            double* __restrict__ dinv, double* __restrict__ strip, int32_t* __restrict__ status) {
-  __shared__ double sV[TS * QB];          // reflector c: sV[c * QB + row]
+  __shared__ double sV[TS * LDT];         // reflector c: sV[c * QB + row]; the inverse tile at the end
   __shared__ double sTau[TS], sSgn[TS];
   __shared__ double sX[TS * LDT];
+  double* const sInv = sV;
   __shared__ int32_t sF[QR_TMAX], sO[QR_TMAX], sGen[QR_TMAX], sRows[QR_TMAX], sBuf[QR_CH];
   __shared__ uint8_t sNZ[QR_TMAX];       // tile of the list left nonzero in the block
   __shared__ int s_jmin, s_jmax, s_count, s_fail, s_q;
@@ -115,7 +117,8 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
   const SubDesc d = subs[blockIdx.x];
   const SubDesc pd = psubs[d.id];
   const int i = d.id;
-  const int tid = threadIdx.x, k = tid >> 3, g = tid & 7;
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64, kc = lane & 31, h = lane >> 5;
   const int32_t* om = omega + pd.omega_off;
   const int32_t* G = om + pd.nI;
   // layout written: tiles per side, interior tiles, the envelope (dense for QR_GAMMA)
@@ -263,106 +266,117 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
         nr = envelope_rows(sF, J, ntiles, sRows, QR_TMAX, &s_count);
       }
       for (int a = tid; a < nr; a += QR_THREADS) sNZ[a] = 0;
-      // panel: the triangle R(J, J) over B(:, J)
+      // panel: the triangle R(J, J) over B(:, J), on wave 0.  Lane (kc, h)
+      // holds column kc of the tile, B rows 16 h .. 16 h + 15 and R rows
+      // 16 h .. 16 h + 15; a column's two lanes are 32 apart, so its sums
+      // take one lane swap and no workgroup barrier is needed.  Reflector c
+      // goes to LDS (sV, sTau) for the other columns and the trailing tiles.
       double* Rjj = rtile(J, J);
-      double* Bj = Bs + (int64_t)(J * TS + k) * QB + 4 * g;
-      double b[4], rr[4];
+      if (wave == 0) {
+        double* Bj = Bs + (int64_t)(J * TS + kc) * QB + 16 * h;
+        double b[16], rr[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        b[q] = Bj[q];
-        rr[q] = Rjj[(4 * g + q) * sc + k * sk];
-      }
-      for (int c = 0; c < TS; ++c) {
-        const int gc = c >> 2, qc = c & 3;
-        const double rc = qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3];
-        // ||(alpha, x)|| with the column scaled by a power of two near its
-        // largest entry first: entries left by rounding in earlier steps can
-        // be so small that their squares underflow (a column whose entries
-        // are all below 1e-290 is not reflected; the block drops them)
-        const double alpha = oct_allsum(g == gc ? rc : 0.0);
-        const double mx = oct_allmax(fmax(fmax(fabs(b[0]), fabs(b[1])), fmax(fabs(b[2]), fabs(b[3]))));
-        const double p2 = mx > 0.0 ? ldexp(1.0, -ilogb(fmax(mx, fabs(alpha)))) : 1.0;
-        const double s2 = oct_allsum((b[0] * p2) * (b[0] * p2) + (b[1] * p2) * (b[1] * p2) +
-                                     (b[2] * p2) * (b[2] * p2) + (b[3] * p2) * (b[3] * p2));
-        if (k == c) {
+        for (int q = 0; q < 16; ++q) {
+          b[q] = Bj[q];
+          rr[q] = Rjj[(16 * h + q) * sc + kc * sk];
+        }
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+          const int hc = c >> 4, ic = c & 15;
+          const double s2 = half_pair_sum(dot16(b, b, 0.0));
+          const double al = half_pair_sum(h == hc ? rr[ic] : 0.0);
+          const double s2c = lane_bcast(s2, c), alpha = lane_bcast(al, c);
           double tau = 0.0, beta = alpha, scl = 0.0;
-          if (mx > 1e-290) {             // below: rounding residue, left to be dropped
-            const double as = alpha * p2;
-            const double nrm = sqrt(as * as + s2) / p2;
-            beta = alpha > 0.0 ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scl = 1.0 / (alpha - beta);
-          }
+          if (s2c > 0.0) {
+            double nrm;
+            bool keep = true;
+            if (s2c >= 1e-280) {
+              const double t = fma(alpha, alpha, s2c);
+              nrm = t * rsqrt_refined(t);
+            } else {
+              // entries left by rounding can be so small that their squares
+              // underflow: the column scaled by a power of two near its largest
+              // entry first (all below 1e-290: not reflected, dropped)
+              double mx = 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            b[q] *= scl;
-            sV[c * QB + 4 * g + q] = b[q];
-          }
-          if (g == gc) {
-            if (qc == 0) rr[0] = beta; else if (qc == 1) rr[1] = beta;
-            else if (qc == 2) rr[2] = beta; else rr[3] = beta;
-          }
-          if (g == 0) sTau[c] = tau;
-        }
-        __syncthreads();
-        const double tau = sTau[c];
-        if (tau != 0.0) {
-          double v[4];
+              for (int q = 0; q < 16; ++q) mx = fmax(mx, fabs(b[q]));
+              mx = lane_bcast(fmax(mx, __shfl_xor(mx, 32, 64)), c);
+              const double p2 = ldexp(1.0, -ilogb(fmax(mx, fabs(alpha))));
+              double t2 = 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = sV[c * QB + 4 * g + q];
-          double wp = g == gc ? (qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3]) : 0.0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) wp += v[q] * b[q];
-          const double w = oct_allsum(wp) * tau;
-          if (k > c) {
-            if (g == gc) {
-              if (qc == 0) rr[0] -= w; else if (qc == 1) rr[1] -= w;
-              else if (qc == 2) rr[2] -= w; else rr[3] -= w;
+              for (int q = 0; q < 16; ++q) t2 += (b[q] * p2) * (b[q] * p2);
+              t2 = lane_bcast(half_pair_sum(t2), c);
+              nrm = sqrt((alpha * p2) * (alpha * p2) + t2) / p2;
+              keep = mx > 1e-290;
             }
+            if (keep) {
+              beta = alpha > 0.0 ? -nrm : nrm;
+              tau = (beta - alpha) * rcp2(beta);
+              scl = rcp2(alpha - beta);
+            }
+          }
+          if (kc == c) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[q] -= v[q] * w;
+            for (int q = 0; q < 16; ++q) {
+              b[q] *= scl;
+              sV[c * QB + 16 * h + q] = b[q];
+            }
+            if (h == hc) rr[ic] = beta;
+            if (h == 0) sTau[c] = tau;
+          }
+          wave_sync();
+          if (tau != 0.0) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = sV[c * QB + 16 * h + q];
+            const double w = half_pair_sum(dot16(v, b, h == hc ? rr[ic] : 0.0)) * tau;
+            if (kc > c) {
+              if (h == hc) rr[ic] -= w;
+#pragma unroll
+              for (int q = 0; q < 16; ++q) b[q] = fma(-v[q], w, b[q]);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Rjj[(4 * g + q) * sc + k * sk] = rr[q];
-        Bj[q] = 0.0;
+        for (int q = 0; q < 16; ++q) {
+          Rjj[(16 * h + q) * sc + kc * sk] = rr[q];
+          Bj[q] = 0.0;
+        }
       }
-      // the reflectors applied to the tiles right of J in the envelope
-      for (int a = 0; a < nr; ++a) {
+      __syncthreads();
+      // the reflectors applied to the tiles right of J in the envelope, one
+      // wave per tile with the same lane map
+      for (int a = wave; a < nr; a += QR_THREADS / 64) {
         const int K = sRows[a];
         double* Rjk = rtile(J, K);
-        double* Bk = Bs + (int64_t)(K * TS + k) * QB + 4 * g;
+        double* Bk = Bs + (int64_t)(K * TS + kc) * QB + 16 * h;
+        double b[16], rr[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 16; ++q) {
           b[q] = Bk[q];
-          rr[q] = Rjk[(4 * g + q) * sc + k * sk];
+          rr[q] = Rjk[(16 * h + q) * sc + kc * sk];
         }
+#pragma unroll
         for (int c = 0; c < TS; ++c) {
           const double tau = sTau[c];
           if (tau == 0.0) continue;
-          const int gc = c >> 2, qc = c & 3;
-          double v[4];
+          const int hc = c >> 4, ic = c & 15;
+          double v[16];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = sV[c * QB + 4 * g + q];
-          double wp = g == gc ? (qc == 0 ? rr[0] : qc == 1 ? rr[1] : qc == 2 ? rr[2] : rr[3]) : 0.0;
+          for (int q = 0; q < 16; ++q) v[q] = sV[c * QB + 16 * h + q];
+          const double w = half_pair_sum(dot16(v, b, h == hc ? rr[ic] : 0.0)) * tau;
+          if (h == hc) rr[ic] -= w;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) wp += v[q] * b[q];
-          const double w = oct_allsum(wp) * tau;
-          if (g == gc) {
-            if (qc == 0) rr[0] -= w; else if (qc == 1) rr[1] -= w;
-            else if (qc == 2) rr[2] -= w; else rr[3] -= w;
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) b[q] -= v[q] * w;
+          for (int q = 0; q < 16; ++q) b[q] = fma(-v[q], w, b[q]);
         }
+        bool nz = false;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          Rjk[(4 * g + q) * sc + k * sk] = rr[q];
+        for (int q = 0; q < 16; ++q) {
+          Rjk[(16 * h + q) * sc + kc * sk] = rr[q];
           Bk[q] = b[q];
+          nz |= b[q] != 0.0;
         }
-        if (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0 || b[3] != 0.0) sNZ[a] = 1;
+        if (nz) sNZ[a] = 1;
       }
       __syncthreads();
       // a tile joins the block only if some row of it is nonzero there:
@@ -433,18 +447,21 @@ k_qr_local(const SubDesc* __restrict__ subs, const SubDesc* __restrict__ psubs,
     for (int e = tid; e < TT; e += QR_THREADS) sX[(e / TS) * LDT + e % TS] = Ljj[e];
     __syncthreads();
     if (tid < TS) {
+      // column c of the inverse, lane c, by forward substitution
       const int c = tid;
       double x[TS];
 #pragma unroll
       for (int a = 0; a < TS; ++a) {
         double t = a == c ? 1.0 : 0.0;
 #pragma unroll
-        for (int bq = 0; bq < a; ++bq) t -= sX[bq * LDT + a] * x[bq];
+        for (int bq = 0; bq < a; ++bq) t = fma(-sX[bq * LDT + a], x[bq], t);
         x[a] = a < c ? 0.0 : t / sX[a * LDT + a];
       }
 #pragma unroll
-      for (int a = 0; a < TS; ++a) Di[(int64_t)J * TT + c * TS + a] = x[a];
+      for (int a = 0; a < TS; ++a) sInv[c * LDT + a] = x[a];
     }
+    __syncthreads();
+    for (int e = tid; e < TT; e += QR_THREADS) Di[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
     __syncthreads();
   }
   if (tid == 0 && s_fail) atomicCAS(status, 0, i + 1);
