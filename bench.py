@@ -75,10 +75,12 @@ class Workload:
         self.nnz = sum(p.nnz for p in probs)
         self.nparts = sum(p.nparts for p in probs)
         self.x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self.opts = {}                     # options every setup of this workload takes
         torch.cuda.synchronize()
 
     def solver(self, L, **opts):
         p0 = self.probs[0]
+        opts = {**self.opts, **opts}
         if len(self.probs) == 1:
             d = self.dev[0]
             return L.Solver(d["rowptr"], d["colind"], d["vals"], p0.part, p0.nparts, p0.m, p0.n,
@@ -249,6 +251,9 @@ def main():
     ap.add_argument("--no-context", action="store_true",
                     help="skip the other workloads reported as context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--local-factor", choices=["cholesky", "qr"], default="cholesky",
+                    help="local factors of the whole line: Cholesky of C_ii (default) or thin QR "
+                         "of A(:, Omega_i) with the principal-angle selection (Remarks 3.1, 3.2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -260,6 +265,8 @@ def main():
     variant = L.BALANCED if args.variant == "balanced" else L.ADDITIVE
     log(f"[bench] generating {args.workload}")
     wl = make_workload(args.workload)
+    if args.local_factor == "qr":
+        wl.opts["local_factor"] = L.FACTOR_QR
     calibration_copy()
     fp64 = timed(L, wl, L.FP64, variant, args.steps, args.warmup, "fp64")
     mixed = timed(L, wl, L.MIXED, variant, args.steps, args.warmup, "mixed")
@@ -267,7 +274,8 @@ def main():
     kern32, _ = kernel_times(L, wl, L.MIXED)
     # the QR route of Remarks 3.1 / 3.2 (local factors from thin QR
     # factorizations of A(:, Omega_i), principal-angle selection), FP64
-    qr = timed(L, wl, L.FP64, variant, 1, 1, "qr", local_factor=L.FACTOR_QR)
+    qr = fp64 if args.local_factor == "qr" else timed(L, wl, L.FP64, variant, 1, 1, "qr",
+                                                     local_factor=L.FACTOR_QR)
 
     # dominant per-iteration kernel of the FP64 path: the batched local
     # triangular solves; achieved = algorithmic bytes (nnz(L_i) under a
@@ -303,7 +311,7 @@ def main():
         "config": {"workload": wl.describe, "instances": len(wl.probs), "m": wl.m, "n": wl.n,
                    "nnz": wl.nnz, "nparts": wl.nparts, "tau": wl.probs[0].tau,
                    "tol": wl.probs[0].tol, "overlap": 1, "variant": args.variant,
-                   "krylov": "pcg"},
+                   "krylov": "pcg", "local_factor": args.local_factor},
         "iterations_max": fp64["iterations_max"],
         "iterations_mean": round(fp64["iterations_mean"], 2),
         "relres_max": fp64["relres_max"],
