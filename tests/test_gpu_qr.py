@@ -9,6 +9,8 @@ route (``Oracle(local_factor="qr")``):
   * the PCG solve;
   * a subdomain above the streaming local solve's 12,544 unknowns (checked
     against the Cholesky oracle: both factor the same C_ii);
+  * the balanced, RAS and deflated forms, LSQR and GMRES, and a batch of
+    instances in one handle;
   * the option's restrictions.
 """
 import numpy as np
@@ -190,3 +192,70 @@ def test_qr_deterministic(L):
         out.append(_np(x))
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("name", ["banded_1000", "grid", "wide"])
+@pytest.mark.parametrize("variant", ["balanced", "ras", "deflated"])
+def test_qr_other_forms(L, name, variant):
+    """The balanced, RAS and deflated forms on the QR factors and the
+    principal-angle coarse space: z = M r against the oracle's QR route
+    (tolerances as for the Cholesky route; C amplifies the coarse error once
+    more in the deflated form)."""
+    p = problem(name)
+    orc = qr_oracle(name, variant=variant)
+    var = {"balanced": L.BALANCED, "ras": L.RAS, "deflated": L.DEFLATED}[variant]
+    kry = L.GMRES if variant in ("ras", "deflated") else L.PCG
+    s = solver(L, p, variant=var, krylov=kry, local_factor=L.FACTOR_QR)
+    r = np.random.default_rng(7).standard_normal(p.n)
+    z = _np(s.apply_preconditioner(_t(r)))
+    tol = 10 * EPS * max_local_condition(name)
+    if variant != "ras" and orc.E is not None:
+        tol = max(tol, _qr_tol(name, orc))
+        if variant == "deflated":
+            tol *= 10
+    assert_close(z, orc.apply(r), tol)
+    s.close()
+
+
+@pytest.mark.parametrize("method", ["lsqr", "gmres"])
+def test_qr_krylov_methods(L, method):
+    """LSQR (additive) and GMRES(100) (deflated) on the QR route against the
+    oracle's QR route with the same method."""
+    p = problem("banded_1000")
+    variant = "additive" if method == "lsqr" else "deflated"
+    ref = qr_oracle("banded_1000", variant=variant).solve(p.b, tol=1e-10, method=method)
+    s = solver(L, p, tol=1e-10, local_factor=L.FACTOR_QR,
+               variant=L.ADDITIVE if method == "lsqr" else L.DEFLATED,
+               krylov=L.LSQR if method == "lsqr" else L.GMRES)
+    x, info, st = s.solve(_t(p.b))
+    assert st == L.OK
+    if method == "lsqr":
+        assert info[0]["relres_rec"] <= 1e-10
+        assert_close(_np(x), ref["x"], 1e-7)
+    else:
+        assert info[0]["relres"] <= 1e-10
+        assert_close(_np(x), ref["x"], 1e-8)
+    s.close()
+
+
+def test_qr_batched(L):
+    """Five instances in one handle on the QR route: per-instance solutions
+    and selection counts against the oracle's QR route."""
+    from workloads import generators as W
+    probs = [W.random_banded(300 + 70 * k, 600 + 140 * k, 3 + k, seed=40 + k, name=f"qb{k}")
+             for k in range(5)]
+    s = L.Solver.batched([(q.indptr, q.indices, q.data, q.part, q.nparts, q.m, q.n) for q in probs],
+                         0.1, tol=1e-10, local_factor=L.FACTOR_QR)
+    x, infos, _ = s.solve(_t(np.concatenate([q.b for q in probs])))
+    x = _np(x)
+    off = sub = 0
+    for k, q in enumerate(probs):
+        orc = O.Oracle(q.scipy(), q.part, q.nparts, 0.1, local_factor="qr").setup()
+        ref = orc.solve(q.b, tol=1e-10)
+        assert infos[k]["relres"] <= 1e-10
+        assert_close(x[off:off + q.n], ref["x"], 1e-8)
+        for i in range(q.nparts):
+            assert s.subdomain(sub + i)["p"] == orc.p[i]
+        off += q.n
+        sub += q.nparts
+    s.close()
