@@ -264,11 +264,129 @@ __device__ inline void tri_inv_upper_tile(const double* R, int ld, double* X, in
   wg_fence();
 }
 
+// acc += sign * A * B^T (32 x 32 tiles, column-major), operands loaded one
+// contraction step of four at a time (fewer registers than tile_mma_nt)
+template <bool NEG>
+__device__ inline void tile_mma_nt_lean(double4_t acc[4], const double* A, int lda, const double* B,
+                                        int ldb, int lane) {
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll 2
+  for (int kk = 0; kk < TS; kk += 4) {
+    double a0 = A[(int64_t)(kk + lk) * lda + li];
+    double a1 = A[(int64_t)(kk + lk) * lda + 16 + li];
+    const double b0 = B[(int64_t)(kk + lk) * ldb + li];
+    const double b1 = B[(int64_t)(kk + lk) * ldb + 16 + li];
+    if (NEG) { a0 = -a0; a1 = -a1; }
+    acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
+    acc[1] = Mfma<double>::mma(a0, b1, acc[1]);
+    acc[2] = Mfma<double>::mma(a1, b0, acc[2]);
+    acc[3] = Mfma<double>::mma(a1, b1, acc[3]);
+  }
+}
+
+// Cholesky factor L (lower triangle, in place) and Inv = L^{-1} of a 32 x 32
+// tile W in LDS (leading dimension LDT, lower part read) by one wave.  Step k
+// scales column k and updates the trailing lower triangle, lanes over rows
+// and two interleaved column sets; then lane c < 32 forms column c of the
+// inverse by forward substitution.  Returns false if a pivot is not positive
+// and finite (it is then taken as 1).
+__device__ inline bool tile_chol_inv_lds(double* W, double* Inv, int lane) {
+  bool ok = true;
+  const int i = lane % TS, h = lane / TS;
+  for (int k = 0; k < TS; ++k) {
+    double d = W[k * LDT + k];
+    if (!(d > 0.0) || !(d < INFINITY)) { ok = false; d = 1.0; }
+    const double sd = sqrt(d), rs = 1.0 / sd;
+    wave_sync();
+    if (h == 0 && i > k) W[k * LDT + i] *= rs;
+    if (lane == k) W[k * LDT + k] = sd;
+    wave_sync();
+    if (i > k) {
+      const double lik = W[k * LDT + i];
+      for (int j = k + 1 + h; j <= i; j += 2) W[j * LDT + i] -= lik * W[k * LDT + j];
+    }
+    wave_sync();
+  }
+  if (h == 0) {
+    double* xc = Inv + i * LDT;
+    for (int a = 0; a < i; ++a) xc[a] = 0.0;
+    xc[i] = 1.0 / W[i * LDT + i];
+    for (int a = i + 1; a < TS; ++a) {
+      double t = 0.0;
+      for (int b = i; b < a; ++b) t += W[b * LDT + a] * xc[b];
+      xc[a] = -t / W[a * LDT + a];
+    }
+  }
+  wave_sync();
+  return ok;
+}
+
+// True if S = sh I - K is positive definite for the symmetric K (r x r,
+// column-major, leading dimension ld): a right-looking Cholesky of S by
+// 32 x 32 tiles in M (its lower triangle, identity on the padding to whole
+// tiles; ld >= the padded size), the diagonal tile by one wave in LDS, the
+// tiles below it and the trailing tiles on MFMA; a pivot that is not
+// positive ends it.  Called by the whole workgroup; sW, sI are LDS tiles.
+__device__ __forceinline__ bool below_shift(const double* K, double* M, int r, int ld, double sh,
+                                         double* sW, double* sI, int* s_ok) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nb = (r + TS - 1) / TS, np = nb * TS;
+  const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
+  for (int64_t q = tid; q < (int64_t)np * np; q += nthr) {
+    const int a = (int)(q % np), c = (int)(q / np);
+    if (a < c) continue;
+    double v = a == c ? 1.0 : 0.0;
+    if (a < r) v = (a == c ? sh : 0.0) - K[(int64_t)c * ld + a];
+    M[(int64_t)c * ld + a] = v;
+  }
+  __syncthreads();
+  for (int J = 0; J < nb; ++J) {
+    if (wv == 0) {
+      const double* Sjj = M + (int64_t)(J * TS) * ld + J * TS;
+      for (int e = ln; e < TT; e += 64) {
+        const int a = e % TS, c = e / TS;
+        sW[c * LDT + a] = a >= c ? Sjj[(int64_t)c * ld + a] : 0.0;
+      }
+      wave_sync();
+      const bool ok = tile_chol_inv_lds(sW, sI, ln);
+      if (ln == 0) *s_ok = ok;
+    }
+    __syncthreads();
+    if (!*s_ok) return false;
+    // S_IJ <- S_IJ L_JJ^{-T} below the diagonal tile
+    for (int I = J + 1 + wv; I < nb; I += nwv) {
+      double* Sij = M + (int64_t)(J * TS) * ld + I * TS;
+      double4_t acc[4];
+      tile_acc_zero<double>(acc);
+      tile_mma_nt_lean<false>(acc, Sij, ld, sI, LDT, ln);
+      tile_acc_store<double>(acc, Sij, ld, ln);
+    }
+    __syncthreads();
+    // S_ab -= S_aJ S_bJ^T for J < b <= a
+    const int m = nb - J - 1;
+    for (int it = wv; it < m * (m + 1) / 2; it += nwv) {
+      int a = (int)((sqrt(8.0 * it + 1.0) - 1.0) / 2.0);
+      while (a * (a + 1) / 2 > it) --a;
+      while ((a + 1) * (a + 2) / 2 <= it) ++a;
+      const int b = it - a * (a + 1) / 2;
+      const int ta = J + 1 + a, tb = J + 1 + b;
+      double* Sab = M + (int64_t)(tb * TS) * ld + ta * TS;
+      double4_t acc[4];
+      tile_acc_load<double>(acc, Sab, ld, ln);
+      tile_mma_nt_lean<true>(acc, M + (int64_t)(J * TS) * ld + ta * TS, ld,
+                             M + (int64_t)(J * TS) * ld + tb * TS, ld, ln);
+      tile_acc_store<double>(acc, Sab, ld, ln);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 // Interfaces of up to MAXN columns (and more than MINN) with THREADS threads:
 // the LDS arrays scale with MAXN, so small interfaces run many workgroups
 // per CU.  Workgroups of other sizes return at once.
 template <int THREADS, int MINN, int MAXN>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
          const double* __restrict__ Tg, double* __restrict__ work, double tau, int nev_max,
          int32_t* __restrict__ p_out, double* __restrict__ sig_out, int32_t* __restrict__ fail,
@@ -281,7 +399,8 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __shared__ double svp[MAXN], swp[MAXN];   // the previous reflector's v and w
   __shared__ double sred[16];
   __shared__ int sredi[16];
-  __shared__ int s_r, s_p, s_nclus, s_diag;
+  __shared__ double sPW[TS * LDT], sPI[TS * LDT];   // diagonal tile of the test of step 2b
+  __shared__ int s_r, s_p, s_nclus, s_diag, s_pd;
   __shared__ double s_anorm;
   const SubDesc dsc = subs[blockIdx.x];
   const int i = dsc.id;
@@ -559,6 +678,14 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       }
     }
     __syncthreads();
+  }
+
+  // ---- 2b. nothing to select: if S = (1 - tau) I - K is positive definite,
+  // every eigenvalue of K lies below 1 - tau, the least value the threshold
+  // of step 4 takes, and p = 0 without the eigen-decomposition.
+  if (1.0 - tau > 0.0 && below_shift(M0, M1, r, ld, 1.0 - tau, sPW, sPI, &s_pd)) {
+    if (tid == 0) p_out[i] = 0;
+    return;
   }
 
   // ---- 3. tridiagonalization of K (r x r) in M0.  Step k reflects column k
