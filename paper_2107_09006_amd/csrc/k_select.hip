@@ -38,6 +38,7 @@ namespace lsq2l {
 
 constexpr int SEL_THREADS = 1024;
 constexpr int SEL_MAXN = 1024;
+constexpr int SEL_NBP = 16;        // rows of the pivoted Cholesky per panel
 constexpr double SEL_EPS = 2.220446049250313e-16;
 
 // ----------------------------------------------------------------------------
@@ -551,60 +552,105 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     }
     r = k;
    } else {
-    // pivoted Cholesky of M0 with symmetric row/column interchanges; row k of
-    // the upper triangle receives row k of R, sperm the pivot order.  Only the
-    // upper triangle is kept up to date (the trailing block is symmetric, and
-    // R and every later read lie in the upper triangle)
-    for (int a = tid; a < n; a += nthr) sperm[a] = a;
-    __syncthreads();
+    // pivoted Cholesky of M0 (both triangles) without moving entries: thread
+    // c owns column c and its updated diagonal d_c.  Step k takes the
+    // unpivoted column c* of largest d (ties: the smallest index); row k of R
+    // in the original column order is
+    //   R(k, c) = (M0(c*, c) - sum_{s in panel, s < k} R(s, c*) R(s, c)) / sqrt(d_c*)
+    // (zero on columns pivoted earlier), and d_c -= R(k, c)^2.  Rows are
+    // formed SEL_NBP at a time in registers; M0 (its upper triangle, the only
+    // part read) takes the panel's update R_P^T R_P once per panel, on MFMA.
+    // R's rows go to M2 (entry (k, c) at c ld + k), R11 in pivot order back
+    // to the upper triangle of M0 at the end; sperm holds the pivot order,
+    // then the unpivoted columns in ascending order.
     const double tol = n * SEL_EPS;     // the scaled matrix has unit diagonal
+    const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
+    double dc = tid < n ? M0[(int64_t)tid * ld + tid] : 0.0;
+    bool piv = tid >= n;                  // pivoted (or not a column)
     int k = 0;
-    for (; k < n; ++k) {
-      double bv = -1.0;
-      int bi = n;
-      for (int j = k + tid; j < n; j += nthr) {
-        const double v = M0[(int64_t)j * ld + j];
-        if (v > bv) { bv = v; bi = j; }
-      }
-      double mv;
-      int mj;
-      wg_argmax(bv, bi, sred, sredi, &mv, &mj);
-      if (!(mv > tol)) break;
-      if (mj != k) {
-        // interchange k and mj (k < mj) in the upper triangle: columns k and
-        // mj of the rows of R above k; in the trailing block the diagonal
-        // entries, (k, q) with (q, mj) for k < q < mj, and (k, q) with
-        // (mj, q) for q > mj ((k, mj) stays).  The pairs are disjoint.
-        for (int q = tid; q < n; q += nthr) {
-          int64_t x = -1, y = -1;
-          if (q < k) { x = (int64_t)k * ld + q; y = (int64_t)mj * ld + q; }
-          else if (q == k) { x = (int64_t)k * ld + k; y = (int64_t)mj * ld + mj; }
-          else if (q < mj) { x = (int64_t)q * ld + k; y = (int64_t)mj * ld + q; }
-          else if (q > mj) { x = (int64_t)q * ld + k; y = (int64_t)q * ld + mj; }
-          if (x >= 0) {
-            const double t = M0[x];
-            M0[x] = M0[y];
-            M0[y] = t;
+    bool stop = n == 0;
+    while (!stop) {
+      const int k0 = k;
+      double P[SEL_NBP];
+#pragma unroll
+      for (int jj = 0; jj < SEL_NBP; ++jj) {
+        P[jj] = 0.0;
+        if (stop) continue;               // uniform
+        double mv;
+        int mj;
+        wg_argmax(piv ? -1.0 : dc, piv ? n : tid, sred, sredi, &mv, &mj);
+        if (!(mv > tol)) { stop = true; continue; }
+        if (tid == mj) {
+#pragma unroll
+          for (int q = 0; q < jj; ++q) sv[q] = P[q];
+          sperm[k] = mj;
+        }
+        __syncthreads();
+        if (tid < n) {
+          // M0(c*, c) from the upper triangle
+          double u = tid <= mj ? M0[(int64_t)mj * ld + tid] : M0[(int64_t)tid * ld + mj];
+#pragma unroll
+          for (int q = 0; q < jj; ++q) u -= sv[q] * P[q];
+          const double sk = sqrt(mv);
+          if (tid == mj) {
+            P[jj] = sk;
+            piv = true;
+          } else if (!piv) {
+            P[jj] = u / sk;
+            dc -= P[jj] * P[jj];
           }
         }
-        if (tid == 0) { const int t = sperm[k]; sperm[k] = sperm[mj]; sperm[mj] = t; }
-        __syncthreads();
+        ++k;
+        if (k == n) stop = true;
       }
-      const double sk = sqrt(M0[(int64_t)k * ld + k]);
-      for (int b = k + 1 + tid; b < n; b += nthr) {
-        const double v = M0[(int64_t)b * ld + k] / sk;
-        sv[b] = v;
-        M0[(int64_t)b * ld + k] = v;
-      }
+      const int nr = k - k0;
+      if (tid < n)
+#pragma unroll
+        for (int q = 0; q < SEL_NBP; ++q)
+          if (q < nr) M2[(int64_t)tid * ld + k0 + q] = P[q];
       __syncthreads();
-      if (tid == 0) M0[(int64_t)k * ld + k] = sk;
-      const int rem = n - k - 1;
-      for (int64_t q = tid; q < (int64_t)rem * rem; q += nthr) {
-        const int a = k + 1 + (int)(q % rem), b = k + 1 + (int)(q / rem);
-        if (a <= b) M0[(int64_t)b * ld + a] -= sv[a] * sv[b];
+      if (stop) break;
+      // M0 -= R_P^T R_P on the 16 x 16 quadrants of the upper triangle
+      const int nq = (n + 15) / 16;
+      const int li = ln % 16, lk = ln / 16;
+      for (int t = wv; t < nq * (nq + 1) / 2; t += nwv) {
+        int qj = (int)((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
+        while (qj * (qj + 1) / 2 > t) --qj;
+        while ((qj + 1) * (qj + 2) / 2 <= t) ++qj;
+        const int qi = t - qj * (qj + 1) / 2;      // qi <= qj
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s0 = 0; s0 < SEL_NBP; s0 += 4) {
+          const double a = M2[(int64_t)(16 * qi + li) * ld + k0 + s0 + lk];
+          const double bb = M2[(int64_t)(16 * qj + li) * ld + k0 + s0 + lk];
+          acc = Mfma<double>::mma(a, bb, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * qi + Mfma<double>::acc_row(ln, v);
+          const int col = 16 * qj + Mfma<double>::acc_col(ln, v);
+          M0[(int64_t)col * ld + row] -= acc[v];
+        }
       }
       __syncthreads();
     }
+    // the unpivoted columns after the r pivots, ascending
+    {
+      const bool up = tid < n && !piv;
+      const unsigned long long bal = __ballot(up);
+      if (ln == 0) sredi[wv] = __popcll(bal);
+      __syncthreads();
+      int base = k;
+      for (int w = 0; w < wv; ++w) base += sredi[w];
+      if (up) sperm[base + __popcll(bal & ((1ull << ln) - 1ull))] = tid;
+      __syncthreads();
+    }
+    // R11 (r x r, pivot order) into the upper triangle of M0, zero elsewhere
+    for (int64_t q = tid; q < mm; q += nthr) {
+      const int a = (int)(q % ld), c = (int)(q / ld);
+      M0[q] = (a <= c && c < k) ? M2[(int64_t)sperm[c] * ld + a] : 0.0;
+    }
+    __syncthreads();
     r = k;
    }
     if (r == 0) {
