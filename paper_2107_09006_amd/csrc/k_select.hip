@@ -74,33 +74,6 @@ __device__ inline void wg_argmax(double v, int idx, double* redv, int* redi, dou
   *outi = bi;
 }
 
-// C (M x N) = op(A) op(B) with M, N, Kd multiples of 16 (zero padded operands),
-// all column-major with leading dimension ld; one 16 x 16 quadrant of the
-// output per wave at a time.
-// Only the first Kv entries of the contraction are read (the rest count as 0).
-template <bool TA, bool TB>
-__device__ void wg_gemm(double* C, const double* A, const double* B, int M, int N, int Kd, int Kv,
-                        int ld) {
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
-  const int li = lane % 16, lk = lane / 16;
-  const int mq = M / 16, nq = N / 16;
-  for (int q = wave; q < mq * nq; q += nw) {
-    const int qi = q % mq, qj = q / mq;
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < Kd; k0 += 4) {
-      const int k = k0 + lk;
-      double a = 0.0, b = 0.0;
-      if (k < Kv) {
-        a = TA ? A[(int64_t)(16 * qi + li) * ld + k] : A[(int64_t)k * ld + 16 * qi + li];
-        b = TB ? B[(int64_t)k * ld + 16 * qj + li] : B[(int64_t)(16 * qj + li) * ld + k];
-      }
-      acc = Mfma<double>::mma(a, b, acc);
-    }
-    for (int v = 0; v < 4; ++v)
-      C[(int64_t)(16 * qj + Mfma<double>::acc_col(lane, v)) * ld + 16 * qi + Mfma<double>::acc_row(lane, v)] = acc[v];
-  }
-}
-
 // ----------------------------------------------------------------------------
 // tridiagonal helpers (single thread)
 // ----------------------------------------------------------------------------
@@ -657,7 +630,6 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       if (tid == 0) p_out[i] = 0;
       return;
     }
-    const int rp = (r + 15) / 16 * 16;
     // M2 = Q = R11^{-T} from X = R11^{-1}, formed in M3 by 32 x 32 tiles.
     // The factor is padded to nb tiles with an identity block, so X is too.
     // Phase 1: each diagonal tile's inverse D_I (one wave per tile); phase
@@ -710,20 +682,42 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       M1[q] = v;
     }
     __syncthreads();
-    // K = Q T11 Q^T: M3 = Q T11, M0 = M3 Q^T
-    wg_gemm<false, false>(M3, M2, M1, rp, rp, rp, r, ld);
-    __syncthreads();
-    wg_gemm<false, true>(M0, M3, M2, rp, rp, rp, r, ld);
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {     // symmetrise
-      const int a = (int)(q % r), c = (int)(q / r);
-      if (a > c) {
-        const double v = 0.5 * (M0[(int64_t)c * ld + a] + M0[(int64_t)a * ld + c]);
-        M0[(int64_t)c * ld + a] = v;
-        M0[(int64_t)a * ld + c] = v;
+    // K = Q T11 Q^T by 32 x 32 tiles, one wave per output tile, with Q lower
+    // triangular: M3 = Q T11 (tile (I, J) sums K <= I), then the lower tiles
+    // of M0 = M3 Q^T (tile (I, J), I >= J, sums K <= J), mirrored to the
+    // upper triangle
+    {
+      const int nb = (r + TS - 1) / TS;
+      const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
+      for (int t = wv; t < nb * nb; t += nwv) {
+        const int I = t % nb, J = t / nb;
+        double4_t acc[4];
+        tile_acc_zero<double>(acc);
+        for (int K = 0; K <= I; ++K)
+          tile_mma_nn<false>(acc, M2 + (int64_t)(K * TS) * ld + I * TS, ld,
+                             M1 + (int64_t)(J * TS) * ld + K * TS, ld, ln);
+        tile_acc_store<double>(acc, M3 + (int64_t)(J * TS) * ld + I * TS, ld, ln);
       }
+      __syncthreads();
+      for (int t = wv; t < nb * (nb + 1) / 2; t += nwv) {
+        int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
+        while (I * (I + 1) / 2 > t) --I;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;        // J <= I
+        double4_t acc[4];
+        tile_acc_zero<double>(acc);
+        for (int K = 0; K <= J; ++K)
+          tile_mma_nt_lean<false>(acc, M3 + (int64_t)(K * TS) * ld + I * TS, ld,
+                                  M2 + (int64_t)(K * TS) * ld + J * TS, ld, ln);
+        tile_acc_store<double>(acc, M0 + (int64_t)(J * TS) * ld + I * TS, ld, ln);
+      }
+      __syncthreads();
+      for (int64_t q = tid; q < (int64_t)r * r; q += nthr) {
+        const int a = (int)(q % r), c = (int)(q / r);
+        if (a < c) M0[(int64_t)c * ld + a] = M0[(int64_t)a * ld + c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // ---- 2b. nothing to select: if S = (1 - tau) I - K is positive definite,
