@@ -38,7 +38,8 @@ namespace lsq2l {
 
 constexpr int SEL_THREADS = 1024;
 constexpr int SEL_MAXN = 1024;
-constexpr int SEL_NBP = 16;        // rows of the pivoted Cholesky per panel
+constexpr int SEL_NBP = 24;        // rows of the pivoted Cholesky per panel (interfaces above 128)
+constexpr int TRD_U = 8;           // loads in flight per thread in the tridiagonalization
 constexpr double SEL_EPS = 2.220446049250313e-16;
 
 // ----------------------------------------------------------------------------
@@ -531,11 +532,13 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     // in the original column order is
     //   R(k, c) = (M0(c*, c) - sum_{s in panel, s < k} R(s, c*) R(s, c)) / sqrt(d_c*)
     // (zero on columns pivoted earlier), and d_c -= R(k, c)^2.  Rows are
-    // formed SEL_NBP at a time in registers; M0 (its upper triangle, the only
+    // formed NBP at a time in registers; M0 (its upper triangle, the only
     // part read) takes the panel's update R_P^T R_P once per panel, on MFMA.
-    // R's rows go to M2 (entry (k, c) at c ld + k), R11 in pivot order back
-    // to the upper triangle of M0 at the end; sperm holds the pivot order,
-    // then the unpivoted columns in ascending order.
+    // R goes to M3 (entry (k, c) at c ld + k) and, for the panel update, to
+    // M2 (at k ld + c); R11 in pivot order goes back to the upper triangle of
+    // M0 at the end.  sperm holds the pivot order, then the unpivoted columns
+    // in ascending order.
+    constexpr int NBP = MAXN <= 128 ? 16 : SEL_NBP;
     const double tol = n * SEL_EPS;     // the scaled matrix has unit diagonal
     const int wv = tid / 64, ln = tid % 64, nwv = nthr / 64;
     double dc = tid < n ? M0[(int64_t)tid * ld + tid] : 0.0;
@@ -544,9 +547,9 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     bool stop = n == 0;
     while (!stop) {
       const int k0 = k;
-      double P[SEL_NBP];
+      double P[NBP];
 #pragma unroll
-      for (int jj = 0; jj < SEL_NBP; ++jj) {
+      for (int jj = 0; jj < NBP; ++jj) {
         P[jj] = 0.0;
         if (stop) continue;               // uniform
         double mv;
@@ -579,31 +582,39 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       const int nr = k - k0;
       if (tid < n)
 #pragma unroll
-        for (int q = 0; q < SEL_NBP; ++q)
-          if (q < nr) M2[(int64_t)tid * ld + k0 + q] = P[q];
+        for (int q = 0; q < NBP; ++q)
+          if (q < nr) {
+            M3[(int64_t)tid * ld + k0 + q] = P[q];     // column c of R, for R11 below
+            M2[(int64_t)(k0 + q) * ld + tid] = P[q];   // row k of R, for the panel update
+          }
       __syncthreads();
       if (stop) break;
-      // M0 -= R_P^T R_P on the 16 x 16 quadrants of the upper triangle
-      const int nq = (n + 15) / 16;
+      // M0 -= R_P^T R_P on the 32 x 32 tiles (I, J), I <= J, of the upper
+      // triangle, one wave per tile
+      const int nbt = (n + TS - 1) / TS;
       const int li = ln % 16, lk = ln / 16;
-      for (int t = wv; t < nq * (nq + 1) / 2; t += nwv) {
-        int qj = (int)((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
-        while (qj * (qj + 1) / 2 > t) --qj;
-        while ((qj + 1) * (qj + 2) / 2 <= t) ++qj;
-        const int qi = t - qj * (qj + 1) / 2;      // qi <= qj
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int t = wv; t < nbt * (nbt + 1) / 2; t += nwv) {
+        int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
+        while (J * (J + 1) / 2 > t) --J;
+        while ((J + 1) * (J + 2) / 2 <= t) ++J;
+        const int I = t - J * (J + 1) / 2;
+        double* Cij = M0 + (int64_t)(J * TS) * ld + I * TS;
+        double4_t acc[4];
+        tile_acc_load<double>(acc, Cij, ld, ln);
+        const double* RI = M2 + (int64_t)k0 * ld + I * TS;
+        const double* RJ = M2 + (int64_t)k0 * ld + J * TS;
 #pragma unroll
-        for (int s0 = 0; s0 < SEL_NBP; s0 += 4) {
-          const double a = M2[(int64_t)(16 * qi + li) * ld + k0 + s0 + lk];
-          const double bb = M2[(int64_t)(16 * qj + li) * ld + k0 + s0 + lk];
-          acc = Mfma<double>::mma(a, bb, acc);
+        for (int s0 = 0; s0 < NBP; s0 += 4) {
+          const double a0 = -RI[(int64_t)(s0 + lk) * ld + li];
+          const double a1 = -RI[(int64_t)(s0 + lk) * ld + 16 + li];
+          const double b0 = RJ[(int64_t)(s0 + lk) * ld + li];
+          const double b1 = RJ[(int64_t)(s0 + lk) * ld + 16 + li];
+          acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
+          acc[1] = Mfma<double>::mma(a0, b1, acc[1]);
+          acc[2] = Mfma<double>::mma(a1, b0, acc[2]);
+          acc[3] = Mfma<double>::mma(a1, b1, acc[3]);
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * qi + Mfma<double>::acc_row(ln, v);
-          const int col = 16 * qj + Mfma<double>::acc_col(ln, v);
-          M0[(int64_t)col * ld + row] -= acc[v];
-        }
+        tile_acc_store<double>(acc, Cij, ld, ln);
       }
       __syncthreads();
     }
@@ -621,7 +632,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     // R11 (r x r, pivot order) into the upper triangle of M0, zero elsewhere
     for (int64_t q = tid; q < mm; q += nthr) {
       const int a = (int)(q % ld), c = (int)(q / ld);
-      M0[q] = (a <= c && c < k) ? M2[(int64_t)sperm[c] * ld + a] : 0.0;
+      M0[q] = (a <= c && c < k) ? M3[(int64_t)sperm[c] * ld + a] : 0.0;
     }
     __syncthreads();
     r = k;
@@ -771,17 +782,36 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       for (int a0 = 0; a0 < m; a0 += 256) {
         const int a = a0 + t256;
         double acc = 0.0;
-        if (a < m)
-          for (int b = g; b < m; b += NG) {
-            double* e = M0 + (int64_t)(k + 1 + b) * ld + k + 1 + a;
-            double x = *e;
+        if (a < m) {
+          // row a of the block, columns b = g, g + NG, ...: TRD_U loads in
+          // flight before their updates are stored
+          double* rowa = M0 + (int64_t)(k + 1) * ld + k + 1 + a;
+          const double va = svp[a + 1], wa = swp[a + 1];
+          int b = g;
+          for (; b + (TRD_U - 1) * NG < m; b += TRD_U * NG) {
+            double x[TRD_U];
+#pragma unroll
+            for (int u = 0; u < TRD_U; ++u) x[u] = rowa[(int64_t)(b + u * NG) * ld];
+#pragma unroll
+            for (int u = 0; u < TRD_U; ++u) {
+              const int bu = b + u * NG;
+              if (pend) {
+                x[u] -= va * swp[bu + 1] + wa * svp[bu + 1];
+                rowa[(int64_t)bu * ld] = x[u];
+              }
+              acc += x[u] * sv[bu];
+            }
+          }
+          for (; b < m; b += NG) {
+            double x = rowa[(int64_t)b * ld];
             if (pend) {
-              x -= svp[a + 1] * swp[b + 1] + swp[a + 1] * svp[b + 1];
-              *e = x;
+              x -= va * swp[b + 1] + wa * svp[b + 1];
+              rowa[(int64_t)b * ld] = x;
             }
             acc += x * sv[b];
           }
-        if (a < m) spart[g][a] = acc;
+          spart[g][a] = acc;
+        }
       }
     }
     __syncthreads();

@@ -143,7 +143,7 @@ struct LocalOut {
 void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* part,
               const int32_t* locown, const uint8_t* bnd, int32_t nI, const int32_t* xi,
               int32_t nXi, BitSet& colset, std::vector<int32_t>& f, std::vector<int32_t>& rpos,
-              LocalOut& out) {
+              std::vector<int32_t>& gpos, LocalOut& out) {
   // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii, ascending; only
   // rows with columns in several parts hold such columns
   out.gamma.clear();
@@ -155,6 +155,10 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
   }
   colset.drain(out.gamma);
   const int32_t nG = (int32_t)out.gamma.size();
+  // position of each interface column in Omega_Gamma_i (entries of other
+  // columns are stale and never read: every column of a row of Xi_i outside
+  // Omega_Ii is in Omega_Gamma_i)
+  for (int32_t k = 0; k < nG; ++k) gpos[out.gamma[k]] = k;
   const int32_t nIp = roundup32(nI), np = nIp + roundup32(nG);
   // Row envelope of C_ii: f(a) = smallest local position coupled to a, the
   // minimum over the rows holding column a of the row's smallest local
@@ -178,8 +182,7 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
         if (part[c] == i) {
           q = locown[c];
         } else {
-          // every column of a row of Xi_i lies in Omega_i
-          q = nIp + (int32_t)(std::lower_bound(out.gamma.begin(), out.gamma.end(), c) - out.gamma.begin());
+          q = nIp + gpos[c];
         }
         rpos.push_back(q);
         best = std::min(best, q);
@@ -315,12 +318,12 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     std::atomic<int32_t> next{0};
     run_threads(nth, [&](unsigned) {
       BitSet colset(n);
-      std::vector<int32_t> f, rpos;
+      std::vector<int32_t> f, rpos, gpos((size_t)n);
       for (int32_t w = next++; w < nparts; w = next++) {
         const int32_t i = order[w];
         plan_one(i, rowptr, colind, part, P.locown.data(), bnd.data(),
                  (int32_t)(pptr[i + 1] - pptr[i]), P.xi.data() + xoff[i],
-                 (int32_t)(xoff[i + 1] - xoff[i]), colset, f, rpos, outs[i]);
+                 (int32_t)(xoff[i + 1] - xoff[i]), colset, f, rpos, gpos, outs[i]);
       }
     });
   }
