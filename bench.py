@@ -274,7 +274,7 @@ def main():
     kern32, _ = kernel_times(L, wl, L.MIXED)
     # the QR route of Remarks 3.1 / 3.2 (local factors from thin QR
     # factorizations of A(:, Omega_i), principal-angle selection), FP64
-    qr = fp64 if args.local_factor == "qr" else timed(L, wl, L.FP64, variant, 1, 1, "qr",
+    qr = fp64 if args.local_factor == "qr" else timed(L, wl, L.FP64, variant, 2, 1, "qr",
                                                      local_factor=L.FACTOR_QR)
 
     # dominant per-iteration kernel of the FP64 path: the batched local

@@ -15,7 +15,7 @@
 //   2. K = W^T T W with MFMA tile products;
 //   3. Householder tridiagonalization of K;
 //   4. p = number of eigenvalues above 1 - tau (one Sturm count), then the
-//      p largest eigenvalues by bisection (one thread each);
+//      p largest eigenvalues by multisection (one wave each);
 //   5. eigenvectors of the tridiagonal matrix by inverse iteration (one
 //      thread per vector), clusters of close eigenvalues re-orthonormalised,
 //      and back-transformation through the Householder reflectors;
@@ -857,7 +857,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   }
   const double pivmin = fmax(SEL_EPS * anorm * 1e-2, 1e-300);
 
-  // ---- 4. count above 1 - tau, bisection for the p largest eigenvalues.  A
+  // ---- 4. count above 1 - tau, multisection for the p largest eigenvalues.  A
   // selected sigma^2 must also be numerically positive (it divides X).
   const double thr = fmax(1.0 - tau, r * SEL_EPS * anorm);
   if (tid == 0) {
@@ -871,16 +871,29 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     if (tid == 0) p_out[i] = 0;
     return;
   }
-  // the j-th largest is the (r-1-j)-th smallest; all p lie above thr
-  for (int j = tid; j < p; j += nthr) {
-    const int kidx = r - 1 - j;
-    double lo = thr, hi = anorm * (1.0 + 4.0 * SEL_EPS) + pivmin;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * SEL_EPS * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-      if (sturm_below_fast(sd, se, r, mid, pivmin) > kidx) hi = mid; else lo = mid;
+  // the j-th largest is the (r-1-j)-th smallest; all p lie above thr.  One
+  // wave per eigenvalue, multisection: each round the 64 lanes count at 64
+  // points splitting [lo, hi] into 65 equal parts, and the first point with
+  // more than r-1-j eigenvalues below it bounds the interval (the invariant
+  // count(lo) <= r-1-j < count(hi) of bisection, shrinking 65-fold a round)
+  {
+    const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
+    for (int j = wave; j < p; j += nw) {
+      const int kidx = r - 1 - j;
+      double lo = thr, hi = anorm * (1.0 + 4.0 * SEL_EPS) + pivmin;
+      for (int it = 0; it < 64; ++it) {
+        if (hi - lo <= 2.0 * SEL_EPS * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        const double h = (hi - lo) / 65.0;
+        const bool above = sturm_below_fast(sd, se, r, lo + (lane + 1) * h, pivmin) > kidx;
+        const unsigned long long bal = __ballot(above);
+        const int first = bal ? __ffsll((long long)bal) - 1 : 64;
+        const double nlo = first == 0 ? lo : lo + first * h;
+        const double nhi = first == 64 ? hi : lo + (first + 1) * h;
+        lo = nlo;
+        hi = nhi;
+      }
+      if (lane == 0) slam[j] = 0.5 * (lo + hi);
     }
-    slam[j] = 0.5 * (lo + hi);
   }
   __syncthreads();
   // clusters of close eigenvalues (descending order); separate equal ones.

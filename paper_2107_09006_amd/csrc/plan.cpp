@@ -141,7 +141,8 @@ struct LocalOut {
 // the rows that hold columns of several parts (bnd).  Work is proportional
 // to the entries of A in the rows of Xi_i.
 void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int32_t* part,
-              const int32_t* locown, const uint8_t* bnd, int32_t nI, const int32_t* xi,
+              const int32_t* locown, const uint8_t* bnd, const int32_t* own_cols,
+              const int32_t* fown, int32_t nI, const int32_t* xi,
               int32_t nXi, BitSet& colset, std::vector<int32_t>& f, std::vector<int32_t>& rpos,
               std::vector<int32_t>& gpos, LocalOut& out) {
   // Omega_Gamma_i: columns of A(Xi_i, :) outside Omega_Ii, ascending; only
@@ -168,8 +169,12 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
   // column, whose position (< nIp) already bounds f there.  Such rows thus
   // never lower a tile's first column, and their entries of C_ii lie inside
   // the envelope.
+  // The rows with all their columns in part i were taken into fown while
+  // Xi was built (fown[c]: least position coupled to c by such rows); the
+  // rows with columns in several parts are visited here.
   f.resize((size_t)np);
-  for (int32_t a = 0; a < np; ++a) f[a] = a;
+  for (int32_t a = 0; a < nI; ++a) f[a] = std::min(a, fown[own_cols[a]]);
+  for (int32_t a = nI; a < np; ++a) f[a] = a;
   for (int32_t a = 0; a < nXi; ++a) {
     const int32_t r = xi[a];
     const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
@@ -188,13 +193,6 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
         best = std::min(best, q);
       }
       for (int32_t q : rpos) f[q] = std::min(f[q], best);
-      continue;
-    }
-    // all columns in part i, ascending, and locown is increasing inside a part
-    const int32_t best = locown[colind[e0]];
-    for (int32_t e = e0; e < e1; ++e) {
-      int32_t& fq = f[locown[colind[e]]];
-      fq = std::min(fq, best);
     }
   }
   const int32_t nt = np / TS;
@@ -261,22 +259,50 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
   rb[rt] = m;
   // the counting pass keeps every row's list (length, then the parts) for
   // the placing pass
+  // The same pass folds every row with all its columns in one part into
+  // fown: for each column c, the least local position of the first column
+  // of such a row through c (columns ascend in a row and locown increases
+  // inside a part, so that is the row's least position).
   std::vector<std::vector<int64_t>> xcnt(rt, std::vector<int64_t>((size_t)nparts, 0));
   std::vector<HostVec<int32_t>> lists(rt);
   std::vector<uint8_t> ok(rt, 1);
+  // Each thread folds its rows into a table of its own; the tables are
+  // merged by column ranges afterwards.
+  std::vector<HostVec<int32_t>> fpriv(rt);
+  HostVec<int32_t> fown;
+  if (!fown.resize((size_t)n)) { err = "host allocation failed"; return false; }
   run_threads(rt, [&](unsigned t) {
     const int32_t a = rb[t], b = std::max(rb[t], rb[t + 1]);
-    if (!lists[t].resize((size_t)(b - a) + (size_t)(rowptr[b] - rowptr[a]))) { ok[t] = 0; return; }
+    if (!lists[t].resize((size_t)(b - a) + (size_t)(rowptr[b] - rowptr[a])) ||
+        !fpriv[t].resize((size_t)n)) {
+      ok[t] = 0;
+      return;
+    }
     int32_t* out = lists[t].data();
+    const int32_t* lo = P.locown.data();
+    int32_t* fo = fpriv[t].data();
+    std::fill(fo, fo + n, INT32_MAX);
     for (int32_t r = a; r < b; ++r) {
       const int k = row_parts(rowptr, colind, part, r, out + 1);
       *out = k;
       for (int q = 0; q < k; ++q) xcnt[t][out[1 + q]]++;
       out += 1 + k;
+      if (k != 1) continue;
+      const int32_t best = lo[colind[rowptr[r]]];
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) fo[colind[e]] = std::min(fo[colind[e]], best);
     }
   });
   for (unsigned t = 0; t < rt; ++t)
     if (!ok[t]) { err = "host allocation failed"; return false; }
+  run_threads(rt, [&](unsigned t) {
+    const int32_t a = (int32_t)((int64_t)n * t / rt), b = (int32_t)((int64_t)n * (t + 1) / rt);
+    for (int32_t c = a; c < b; ++c) {
+      int32_t v = fpriv[0][c];
+      for (unsigned u = 1; u < rt; ++u) v = std::min(v, fpriv[u][c]);
+      fown[c] = v;
+    }
+  });
+  fpriv.clear();
   std::vector<int64_t> xoff((size_t)nparts + 1, 0);
   for (int32_t i = 0; i < nparts; ++i) {
     int64_t run = 0;
@@ -321,8 +347,8 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       std::vector<int32_t> f, rpos, gpos((size_t)n);
       for (int32_t w = next++; w < nparts; w = next++) {
         const int32_t i = order[w];
-        plan_one(i, rowptr, colind, part, P.locown.data(), bnd.data(),
-                 (int32_t)(pptr[i + 1] - pptr[i]), P.xi.data() + xoff[i],
+        plan_one(i, rowptr, colind, part, P.locown.data(), bnd.data(), pcols.data() + pptr[i],
+                 fown.data(), (int32_t)(pptr[i + 1] - pptr[i]), P.xi.data() + xoff[i],
                  (int32_t)(xoff[i + 1] - xoff[i]), colset, f, rpos, gpos, outs[i]);
       }
     });
