@@ -266,22 +266,31 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
   std::vector<std::vector<int64_t>> xcnt(rt, std::vector<int64_t>((size_t)nparts, 0));
   std::vector<HostVec<int32_t>> lists(rt);
   std::vector<uint8_t> ok(rt, 1);
-  // Each thread folds its rows into a table of its own; the tables are
-  // merged by column ranges afterwards.
+  // Each thread folds its rows into a table of its own over the column
+  // range its rows touch; the tables are merged by column ranges afterwards.
   std::vector<HostVec<int32_t>> fpriv(rt);
+  std::vector<int32_t> flo(rt, 0), fhi(rt, -1);
   HostVec<int32_t> fown;
   if (!fown.resize((size_t)n)) { err = "host allocation failed"; return false; }
   run_threads(rt, [&](unsigned t) {
     const int32_t a = rb[t], b = std::max(rb[t], rb[t + 1]);
+    int32_t cmin = INT32_MAX, cmax = -1;
+    for (int32_t e = rowptr[a]; e < rowptr[b]; ++e) {
+      cmin = std::min(cmin, colind[e]);
+      cmax = std::max(cmax, colind[e]);
+    }
+    if (cmax < cmin) cmin = 0;
+    flo[t] = cmin;
+    fhi[t] = cmax;
     if (!lists[t].resize((size_t)(b - a) + (size_t)(rowptr[b] - rowptr[a])) ||
-        !fpriv[t].resize((size_t)n)) {
+        !fpriv[t].resize((size_t)std::max(cmax - cmin + 1, 1))) {
       ok[t] = 0;
       return;
     }
     int32_t* out = lists[t].data();
     const int32_t* lo = P.locown.data();
-    int32_t* fo = fpriv[t].data();
-    std::fill(fo, fo + n, INT32_MAX);
+    int32_t* fo = fpriv[t].data() - cmin;     // indexed by column
+    std::fill(fpriv[t].data(), fpriv[t].data() + std::max(cmax - cmin + 1, 1), INT32_MAX);
     for (int32_t r = a; r < b; ++r) {
       const int k = row_parts(rowptr, colind, part, r, out + 1);
       *out = k;
@@ -296,10 +305,11 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     if (!ok[t]) { err = "host allocation failed"; return false; }
   run_threads(rt, [&](unsigned t) {
     const int32_t a = (int32_t)((int64_t)n * t / rt), b = (int32_t)((int64_t)n * (t + 1) / rt);
-    for (int32_t c = a; c < b; ++c) {
-      int32_t v = fpriv[0][c];
-      for (unsigned u = 1; u < rt; ++u) v = std::min(v, fpriv[u][c]);
-      fown[c] = v;
+    std::fill(fown.data() + a, fown.data() + b, INT32_MAX);
+    for (unsigned u = 0; u < rt; ++u) {
+      const int32_t c0 = std::max(a, flo[u]), c1 = std::min(b - 1, fhi[u]);
+      const int32_t* fu = fpriv[u].data() - flo[u];
+      for (int32_t c = c0; c <= c1; ++c) fown[c] = std::min(fown[c], fu[c]);
     }
   });
   fpriv.clear();
