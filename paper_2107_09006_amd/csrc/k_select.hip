@@ -239,6 +239,35 @@ __device__ inline void tri_inv_upper_tile(const double* R, int ld, double* X, in
   wg_fence();
 }
 
+// The same by one wave with the tile staged in LDS (sR, sX: TS x LDT), X
+// formed there and copied out: the dependent reads of the back substitution
+// then go to LDS instead of global memory.
+__device__ inline void tri_inv_upper_tile_lds(const double* R, int ld, double* X, double* sR,
+                                              double* sX, int lane) {
+  for (int e = lane; e < TT; e += 64) {
+    const int a = e % TS, c = e / TS;
+    sR[c * LDT + a] = R[(int64_t)c * ld + a];
+  }
+  wave_sync();
+  if (lane < TS) {
+    const int c = lane;
+    double* xc = sX + c * LDT;
+    for (int a = c + 1; a < TS; ++a) xc[a] = 0.0;
+    xc[c] = 1.0 / sR[c * LDT + c];
+    for (int a = c - 1; a >= 0; --a) {
+      double t = 0.0;
+      for (int b = a + 1; b <= c; ++b) t += sR[b * LDT + a] * xc[b];
+      xc[a] = -t / sR[a * LDT + a];
+    }
+  }
+  wave_sync();
+  for (int e = lane; e < TT; e += 64) {
+    const int a = e % TS, c = e / TS;
+    X[(int64_t)c * ld + a] = sX[c * LDT + a];
+  }
+  wg_fence();
+}
+
 // acc += sign * A * B^T (32 x 32 tiles, column-major), operands loaded one
 // contraction step of four at a time (fewer registers than tile_mma_nt)
 template <bool NEG>
@@ -263,9 +292,9 @@ __device__ inline void tile_mma_nt_lean(double4_t acc[4], const double* A, int l
 // tile W in LDS (leading dimension LDT, lower part read) by one wave.  Step k
 // scales column k and updates the trailing lower triangle, lanes over rows
 // and two interleaved column sets; then lane c < 32 forms column c of the
-// inverse by forward substitution.  Returns false if a pivot is not positive
-// and finite (it is then taken as 1).
-__device__ inline bool tile_chol_inv_lds(double* W, double* Inv, int lane) {
+// inverse by forward substitution (only if want_inv).  Returns false if a
+// pivot is not positive and finite (it is then taken as 1).
+__device__ inline bool tile_chol_inv_lds(double* W, double* Inv, int lane, bool want_inv) {
   bool ok = true;
   const int i = lane % TS, h = lane / TS;
   for (int k = 0; k < TS; ++k) {
@@ -282,7 +311,7 @@ __device__ inline bool tile_chol_inv_lds(double* W, double* Inv, int lane) {
     }
     wave_sync();
   }
-  if (h == 0) {
+  if (want_inv && h == 0) {
     double* xc = Inv + i * LDT;
     for (int a = 0; a < i; ++a) xc[a] = 0.0;
     xc[i] = 1.0 / W[i * LDT + i];
@@ -323,7 +352,7 @@ __device__ __forceinline__ bool below_shift(const double* K, double* M, int r, i
         sW[c * LDT + a] = a >= c ? Sjj[(int64_t)c * ld + a] : 0.0;
       }
       wave_sync();
-      const bool ok = tile_chol_inv_lds(sW, sI, ln);
+      const bool ok = tile_chol_inv_lds(sW, sI, ln, J + 1 < nb);
       if (ln == 0) *s_ok = ok;
     }
     __syncthreads();
@@ -655,9 +684,18 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
         if (a <= c && c >= r) M0[(int64_t)c * ld + a] = (a == c) ? 1.0 : 0.0;
       }
       __syncthreads();
-      for (int I = wv; I < nb; I += nwv)
-        tri_inv_upper_tile(M0 + (int64_t)(I * TS) * ld + I * TS, ld,
-                           M3 + (int64_t)(I * TS) * ld + I * TS, ln);
+      // (up to four tiles one after another by wave 0 through LDS, more in
+      // parallel, one wave each, in global memory)
+      if (nb <= 4) {
+        if (wv == 0)
+          for (int I = 0; I < nb; ++I)
+            tri_inv_upper_tile_lds(M0 + (int64_t)(I * TS) * ld + I * TS, ld,
+                                   M3 + (int64_t)(I * TS) * ld + I * TS, sPW, sPI, ln);
+      } else {
+        for (int I = wv; I < nb; I += nwv)
+          tri_inv_upper_tile(M0 + (int64_t)(I * TS) * ld + I * TS, ld,
+                             M3 + (int64_t)(I * TS) * ld + I * TS, ln);
+      }
       __syncthreads();
       for (int J = wv; J < nb; J += nwv)
         for (int I = J - 1; I >= 0; --I) {
@@ -914,13 +952,16 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __syncthreads();
 
   // ---- 5. inverse iteration, one thread per vector (scratch of 3 r doubles
-  // in M3, free now).  Shifts are accurate to rounding, so after a few sweeps
+  // per vector, in LDS or in M3 / M4).  Shifts are accurate to rounding, so after a few sweeps
   // every vector lies in the invariant subspace of its cluster; only clusters
   // of (numerically) multiple eigenvalues need orthonormalising, which is done
   // after the independent sweeps and again after one cleaning sweep.
   // Vectors in M1 (r x p).
   const double tiny = SEL_EPS * anorm;
-  const int slots = (int)min<int64_t>(2 * mm / (3 * r), nthr);
+  // The scratch sits in LDS (svp, swp, spart[0], free now: MAXN doubles each)
+  // when every vector fits in one round there, else in M3 / M4.
+  const bool lds_scr = p <= MAXN / r;
+  const int slots = lds_scr ? p : (int)min<int64_t>(2 * mm / (3 * r), nthr);
   const int wave = tid / 64, lane = tid % 64, nw = nthr / 64;
   for (int64_t q = tid; q < (int64_t)ld * p; q += nthr) {
     const int row = (int)(q % ld), j = (int)(q / ld);
@@ -933,6 +974,9 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       if (tid >= slots || j >= p) continue;
       double* x = M1 + (int64_t)j * ld;
       double* scr = M3 + tid;                // row q of array k at (k r + q) slots
+      double* s0 = lds_scr ? svp + tid : scr;
+      double* s1 = lds_scr ? swp + tid : scr + (int64_t)r * slots;
+      double* s2 = lds_scr ? spart[0] + tid : scr + (int64_t)2 * r * slots;
       double nr = 0.0;
       for (int q0 = 0; q0 < r; q0 += TRI_CH) {
         double xq[TRI_CH];
@@ -944,8 +988,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       }
       nr = 1.0 / sqrt(nr);
       // the solve scales its right-hand side by nr as it reads it
-      tri_solve(sd, se, r, slam[j], tiny, nr, x, scr, scr + (int64_t)r * slots,
-                scr + (int64_t)2 * r * slots, slots);
+      tri_solve(sd, se, r, slam[j], tiny, nr, x, s0, s1, s2, slots);
     }
     __syncthreads();
     if (sweep < 2) continue;
