@@ -778,7 +778,12 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   TRY(c->upload(&c->P.locown, H.locown));
   TRY(c->upload(&c->P.tileF, H.tileF));
   TRY(c->upload(&c->P.tileOff, H.tileOff));
-  for (const SubDesc& d : H.subs) c->P.max_np = std::max(c->P.max_np, (int)d.np);
+  c->P.min_nG = INT32_MAX;
+  for (const SubDesc& d : H.subs) {
+    c->P.max_np = std::max(c->P.max_np, (int)d.np);
+    c->P.min_nG = std::min(c->P.min_nG, (int)d.nG);
+    c->P.max_nG = std::max(c->P.max_nG, (int)d.nG);
+  }
   // the local solves and the one-workgroup-per-subdomain setup kernels start
   // the subdomains with the most stored tiles first: one launch holds all of
   // them, and the largest set its length

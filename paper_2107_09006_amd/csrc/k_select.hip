@@ -1163,13 +1163,19 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
 void launch_select(hipStream_t st, int nsub, const DevPlan& P, const double* ctg, const double* Tg,
                    double* work, double tau, int nev_max, int32_t* p_out, double* sig_out,
                    int qr_range) {
-  // size classes of the interface: up to 128, 512 and SEL_MAXN columns
-  k_select<256, 0, 128><<<nsub, 256, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out,
-                                              p_out + nsub, qr_range);
-  k_select<512, 128, 512><<<nsub, 512, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out,
+  // size classes of the interface: up to 128, 512 and SEL_MAXN columns (the
+  // last also reports larger ones); a class is launched only when some
+  // interface size may fall in it, so that idle workgroups of the larger
+  // classes do not wait for CUs held by kernels on the other stream
+  if (P.min_nG <= 128)
+    k_select<256, 0, 128><<<nsub, 256, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out,
                                                 sig_out, p_out + nsub, qr_range);
-  k_select<SEL_THREADS, 512, SEL_MAXN><<<nsub, SEL_THREADS, 0, st>>>(
-      P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out, p_out + nsub, qr_range);
+  if (P.max_nG > 128 && P.min_nG <= 512)
+    k_select<512, 128, 512><<<nsub, 512, 0, st>>>(P.heavy(), ctg, Tg, work, tau, nev_max, p_out,
+                                                  sig_out, p_out + nsub, qr_range);
+  if (P.max_nG > 512)
+    k_select<SEL_THREADS, 512, SEL_MAXN><<<nsub, SEL_THREADS, 0, st>>>(
+        P.heavy(), ctg, Tg, work, tau, nev_max, p_out, sig_out, p_out + nsub, qr_range);
 }
 
 }  // namespace lsq2l

@@ -35,6 +35,7 @@ struct DevPlan {              // subdomain layout (device copies of HostPlan)
   SubDesc* subs_ord = nullptr;     // subs in that order: the one-workgroup-per-subdomain
                                    // setup kernels start the largest subdomains first
   int max_np = 0;             // largest padded local size
+  int min_nG = 0, max_nG = 0;  // least and largest interface size
   // layout of the solve factor only: where each position lives in the local
   // vectors (loc index, -1 on padding; null: loc_off + position), and
   // scratch local vectors for the subdomains solved in global memory
