@@ -1067,20 +1067,42 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
         launch_coarse_E_shift(st, (int)(CP.items.size() / 4), c->P, c->Cc, c->X, c->shift, c->efac);
       // right-looking Cholesky of E, one tile column per launch, each launch
       // also applying the previous column to the tiles right of the current
-      // one (rows of column J - 1 below J: its list without row J)
+      // one (rows of column J - 1 below J: its list without row J).  E is
+      // block diagonal over the instances of a batch, so launch s takes
+      // tile column s of every instance that has one.
       TRY(c->upload(&c->Cc.erows, CP.erows));
       TRY(c->upload(&c->Cc.eptr, CP.eptr));
-      int32_t* d_erows = c->Cc.erows;
-      for (int64_t J = 0; J < c->etiles; ++J) {
-        const int nr = (int)(CP.eptr[J + 1] - CP.eptr[J]);
-        int64_t p0 = 0, p1 = 0;
-        if (J > 0) {
-          p0 = CP.eptr[J - 1];
-          p1 = CP.eptr[J];
-          if (p0 < p1 && CP.erows[p0] == J) ++p0;
+      {
+        int64_t steps = 0;
+        for (const SegDesc& sg : CP.segs) steps = std::max(steps, sg.etiles);
+        std::vector<int32_t> jobs;
+        std::vector<int64_t> first(1, 0);       // first job of every step
+        std::vector<int32_t> nblk;              // workgroups of every step
+        for (int64_t sidx = 0; sidx < steps; ++sidx) {
+          int32_t blocks = 0;
+          for (const SegDesc& sg : CP.segs) {
+            if (sg.etiles <= sidx) continue;
+            const int64_t J = sg.etile0 + sidx;
+            const int nr = (int)(CP.eptr[J + 1] - CP.eptr[J]);
+            int64_t p0 = CP.eptr[J], p1 = CP.eptr[J];
+            if (sidx > 0) {
+              p0 = CP.eptr[J - 1];
+              p1 = CP.eptr[J];
+              if (p0 < p1 && CP.erows[p0] == J) ++p0;
+            }
+            jobs.insert(jobs.end(), {(int32_t)J, (int32_t)CP.eptr[J], nr, (int32_t)p0,
+                                     (int32_t)(p1 - p0), blocks});
+            blocks += echol_job_blocks(nr, (int)(p1 - p0));
+          }
+          first.push_back((int64_t)(jobs.size() / EJOB_INTS));
+          nblk.push_back(blocks);
         }
-        launch_echol_step(st, c->Cc, (int)J, d_erows + CP.eptr[J], nr, d_erows + p0, (int)(p1 - p0),
-                          c->efac, c->edinv, c->status + 1);
+        int32_t* d_jobs = nullptr;
+        TRY(c->upload(&d_jobs, jobs));
+        for (int64_t sidx = 0; sidx < steps; ++sidx)
+          launch_echol_step(st, c->Cc, d_jobs + EJOB_INTS * first[sidx],
+                            (int)(first[sidx + 1] - first[sidx]), nblk[sidx], c->efac, c->edinv,
+                            c->status + 1);
       }
       TRY(c->dalloc(&c->einv, CP.einv_tot));
       TRY(c->dalloc(&c->Cc.e_part, CP.einv_tot / TS));

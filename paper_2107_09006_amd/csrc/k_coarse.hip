@@ -491,7 +491,12 @@ k_coarse_E_shift(const SubDesc* __restrict__ subs, const PairDesc* __restrict__ 
 }
 
 // One step J of the right-looking tile Cholesky of E, fused with the
-// trailing update of the previous column, in one launch.
+// trailing update of the previous column.  One launch holds that step for
+// several independent diagonal blocks of E (the instances of a batch: step s
+// of every instance with more than s tile columns), one job each; a job
+// (EJOB_INTS ints: J, first of its rows in erows, their number nr, first of
+// the rows of column J - 1 below J, their number npr, first workgroup)
+// takes the workgroups from its first up to the next job's.
 // - Workgroups below ndiag (panel role) apply column J - 1 to the tiles of
 //   column J themselves: A(J, J) -= L(J, J-1) L(J, J-1)^T, and for their
 //   panel rows A(I, J) -= L(I, J-1) L(J, J-1)^T.  In every such workgroup
@@ -508,17 +513,28 @@ constexpr int ESTEP_WAVES = 8;
 constexpr int EPANEL = ESTEP_WAVES - 1;    // panel tiles per workgroup (waves 1..)
 
 __global__ void __launch_bounds__(ESTEP_WAVES * 64)
-k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, int J,
-             const int32_t* __restrict__ rows, int nr, const int32_t* __restrict__ prows, int npr,
-             int ndiag, double* __restrict__ efac, double* __restrict__ edinv,
-             int32_t* __restrict__ status) {
+k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff,
+             const int32_t* __restrict__ erows, const int32_t* __restrict__ jobs, int njobs,
+             double* __restrict__ efac, double* __restrict__ edinv, int32_t* __restrict__ status) {
   __shared__ double sW[TS * LDT], sInv[TS * LDT];
   __shared__ double sS[ESTEP_WAVES][TS * LDT];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid / 64, lane = tid % 64;
+  // this workgroup's job: the last one whose first workgroup is at most ours
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[EJOB_INTS * mid + 5] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const int32_t* jb = jobs + EJOB_INTS * lo;
+  const int J = jb[0], nr = jb[2], npr = jb[4];
+  const int32_t* rows = erows + jb[1];
+  const int32_t* prows = erows + jb[3];
+  const int bx = (int)blockIdx.x - jb[5];
+  const int ndiag = max(1, (nr + EPANEL - 1) / EPANEL);
   double4_t acc[4];
-  if ((int)blockIdx.x >= ndiag) {
-    const int64_t gw = (int64_t)(blockIdx.x - ndiag) * ESTEP_WAVES + wave;
+  if (bx >= ndiag) {
+    const int64_t gw = (int64_t)(bx - ndiag) * ESTEP_WAVES + wave;
     const int64_t npairs = (int64_t)npr * (npr + 1) / 2;
     if (gw >= npairs) return;
     // pair index -> (a, b), a >= b
@@ -538,7 +554,7 @@ k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, i
   const double* Ljp = prevJ ? efac + tile_pos(eF, eOff, J, J - 1) * TT : nullptr;
   // wave 0 factors and inverts the diagonal tile; meanwhile waves 1.. hold
   // their panel tiles' A(I, J) - L(I, J-1) L(J, J-1)^T in registers
-  const int a = blockIdx.x * EPANEL + wave - 1;
+  const int a = bx * EPANEL + wave - 1;
   const bool mine = wave > 0 && a < nr;
   const int I = mine ? rows[a] : 0;
   if (wave == 0) {
@@ -553,14 +569,14 @@ k_echol_step(const int32_t* __restrict__ eF, const int64_t* __restrict__ eOff, i
       wave_sync();
     }
     const bool ok = tile_potrf_inv_reg<double>(sW, nullptr, sInv, lane);
-    if (!ok && lane == 0 && blockIdx.x == 0) atomicCAS(status, 0, J + 1);
+    if (!ok && lane == 0 && bx == 0) atomicCAS(status, 0, J + 1);
   } else if (mine) {
     tile_acc_load<double>(acc, efac + tile_pos(eF, eOff, I, J) * TT, TS, lane);
     if (prevJ && eF[I] <= J - 1)
       tile_mma_nt<double, true>(acc, efac + tile_pos(eF, eOff, I, J - 1) * TT, TS, Ljp, TS, lane);
   }
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (bx == 0)
     for (int e = tid; e < TT; e += nthr) edinv[(int64_t)J * TT + e] = sInv[(e / TS) * LDT + e % TS];
   if (mine) {
     double* S = sS[wave];
@@ -1096,14 +1112,17 @@ void launch_coarse_E_shift(hipStream_t st, int nitems, const DevPlan& P, const D
   k_coarse_E_shift<<<nitems, 256, 0, st>>>(P.subs, Cc.pairs, Cc.e_items, Cc.eF, Cc.eOff, X, s, efac);
 }
 
-void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                       const int32_t* prows, int npr, double* efac, double* edinv,
-                       int32_t* status) {
-  const int ndiag = max(1, (nr + EPANEL - 1) / EPANEL);
+int echol_job_blocks(int nr, int npr) {
+  const int ndiag = std::max(1, (nr + EPANEL - 1) / EPANEL);
   const int64_t npairs = (int64_t)npr * (npr + 1) / 2;
-  const int nupd = (int)((npairs + ESTEP_WAVES - 1) / ESTEP_WAVES);
-  k_echol_step<<<ndiag + nupd, ESTEP_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, J, rows, nr, prows, npr,
-                                                         ndiag, efac, edinv, status);
+  return ndiag + (int)((npairs + ESTEP_WAVES - 1) / ESTEP_WAVES);
+}
+
+void launch_echol_step(hipStream_t st, const DevCoarse& Cc, const int32_t* jobs, int njobs,
+                       int nblocks, double* efac, double* edinv, int32_t* status) {
+  if (njobs == 0) return;
+  k_echol_step<<<nblocks, ESTEP_WAVES * 64, 0, st>>>(Cc.eF, Cc.eOff, Cc.erows, jobs, njobs, efac,
+                                                    edinv, status);
 }
 
 void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out) {

@@ -269,8 +269,13 @@ void launch_coarse_E(hipStream_t st, int nitems, const DevPlan& P, const DevCoar
 // diagonal blocks of E += s X_i^T X_i (the rows sqrt(s) e_j of a shifted C)
 void launch_coarse_E_shift(hipStream_t st, int nitems, const DevPlan& P, const DevCoarse& Cc,
                            const double* X, double s, double* efac);
-void launch_echol_step(hipStream_t st, const DevCoarse& Cc, int J, const int32_t* rows, int nr,
-                       const int32_t* prows, int npr, double* efac, double* edinv, int32_t* status);
+// one step of the tile Cholesky of E for a list of independent diagonal
+// blocks (jobs of EJOB_INTS ints, see k_echol_step); echol_job_blocks gives
+// the workgroups one job takes
+constexpr int EJOB_INTS = 6;
+int echol_job_blocks(int nr, int npr);
+void launch_echol_step(hipStream_t st, const DevCoarse& Cc, const int32_t* jobs, int njobs,
+                       int nblocks, double* efac, double* edinv, int32_t* status);
 void launch_tile_transpose(hipStream_t st, int64_t ntiles, const double* in, double* out);
 void launch_einv(hipStream_t st, int nbins, const DevCoarse& Cc, const double* efac,
                  const double* edinv, const double* efacT, const double* edinvT, double* einv);
