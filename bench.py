@@ -23,6 +23,7 @@ bounded sample, extrapolated) as the reported CPU baseline.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -109,16 +110,25 @@ def timed(L, wl, precision, variant, steps, warmup, tag, **extra):
     for w in range(warmup):
         ms, info, _ = run_step(L, wl, precision, variant, **extra)
         log(f"[bench] {tag} warmup {w}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}")
+    # Python's collector stays off while the steps are timed (it is run
+    # before and after), so that a collection pause of the interpreter does
+    # not land inside a step
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = []
     for k in range(steps):
         out.append(run_step(L, wl, precision, variant, **extra))
         ms, info, _ = out[-1]
+        ph = out[-1][2]
         log(f"[bench] {tag} step {k}: {ms:.1f} ms, its {max(i['iterations'] for i in info)}, "
-            f"relres {max(i['relres'] for i in info):.2e}")
+            f"relres {max(i['relres'] for i in info):.2e}, setup " +
+            " ".join(f"{q[2:-3]} {ph[q]:.1f}" for q in ["t_prepare_ms", "t_plan_ms", "t_assemble_ms",
+                                                          "t_factor_ms", "t_eigen_ms", "t_coarse_ms"]))
     torch.cuda.synchronize()
     total = (time.perf_counter() - t0) * 1e3
+    gc.enable()
     ms, info, sinfo = out[-1]
     return {"ms_per_step": total / steps,
             "iterations_max": max(i["iterations"] for i in info),
