@@ -829,6 +829,13 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
     // layouts; the equilibration's scaling comes from the column norms of A.
     if (c->sl_inv) launch_assemble(st, nparts, c->P, c->M, nullptr, nullptr, c->sl_inv, c->sl_dg, c->sl_Fg);
     launch_col_scale(st, nparts, c->P, c->M, c->scale);
+  } else if (c->opt.diag_shift_rel <= 0.0) {
+    // S = diag(C_ii)^{-1/2} = 1 / ||A(:, c)|| first, then S C_ii S and
+    // S Ct_GG S assembled in one pass
+    c->shift = 0.0;
+    launch_col_scale(st, nparts, c->P, c->M, c->scale);
+    launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg, c->sl_inv, c->sl_dg, c->sl_Fg,
+                    c->scale);
   } else {
   launch_assemble(st, nparts, c->P, c->M, c->fac, c->ctg, c->sl_inv, c->sl_dg, c->sl_Fg);
   // Global shift of Section 4.1 ("Setup phase"): the preconditioner is built

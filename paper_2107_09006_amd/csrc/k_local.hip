@@ -31,6 +31,10 @@ __global__ void k_gather_values(int64_t nnz, const int32_t* __restrict__ perm,
 // column order (see k_solve_inv): the thread of column a sees every column
 // coupled to it, so the first coupled position of row inv[a] in that order
 // is the minimum it meets, one atomicMin per column into Fg.
+// With scl given (S = diag(C_ii)^{-1/2} per local position, which is
+// 1 / ||A(:, c)||: C_ii holds whole columns of A), every product is scaled as
+// it is added, so the result is S C_ii S and S Ct_GG S directly, with unit
+// diagonal entries on the padding positions (the equilibration in one pass).
 __global__ void __launch_bounds__(256)
 k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const int32_t* __restrict__ part, const int32_t* __restrict__ locown,
@@ -39,9 +43,11 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
            const int32_t* __restrict__ trow, const double* __restrict__ tvals,
            const int32_t* __restrict__ tileF, const int64_t* __restrict__ tileOff,
            double* __restrict__ fac, double* __restrict__ ctg, const int32_t* __restrict__ inv,
-           const SubDesc* __restrict__ gsub, int32_t* __restrict__ Fg) {
+           const SubDesc* __restrict__ gsub, int32_t* __restrict__ Fg,
+           const double* __restrict__ scl) {
   const SubDesc d = subs[blockIdx.x];
   const int i = d.id;
+  const double* sl = scl ? scl + d.loc_off : nullptr;
   const int32_t* iv = inv ? inv + d.loc_off : nullptr;
   const int32_t* om = omega + d.omega_off;
   const int32_t* G = om + d.nI;
@@ -54,6 +60,7 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
     const int posa = a < d.nI ? a : d.nIp + (a - d.nI);
     const int ta = posa / TS, ra = posa % TS;
     const int qa = iv ? iv[posa] : 0;
+    const double sa = sl ? sl[posa] : 1.0;
     int fmin = qa;
     for (int k = trowptr[j]; k < trowptr[j + 1]; ++k) {
       const int r = trow[k];
@@ -65,7 +72,7 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
         const int posc = local_pos(i, colind[e], part, locown, G, d.nG, d.nIp);
         if (iv && posc >= 0) fmin = min(fmin, iv[posc]);
         if (!A || posc < posa) continue;
-        const double v = vals[e] * va;
+        const double v = sl ? vals[e] * va * (sa * sl[posc]) : vals[e] * va;
         const int tc = posc / TS;
         A[tile_pos(F, off, tc, ta) * TT + ra * TS + (posc % TS)] += v;
         if (inxi && a >= d.nI) Ct[(int64_t)(posa - d.nIp) * d.nGp + (posc - d.nIp)] += v;
@@ -73,6 +80,11 @@ k_assemble(const SubDesc* __restrict__ subs, const int32_t* __restrict__ omega,
     }
     if (iv) atomicMin(&Fg[gsub[i].tile_base + qa / TS], fmin / TS);
   }
+  if (A && sl && blockIdx.y == 0)
+    for (int pos = threadIdx.x; pos < d.np; pos += blockDim.x) {
+      const bool real = pos < d.nI || (pos >= d.nIp && pos < d.nIp + d.nG);
+      if (!real) A[tile_pos(F, off, pos / TS, pos / TS) * TT + (pos % TS) * TS + pos % TS] = 1.0;
+    }
 }
 
 // Symmetric diagonal equilibration S C S, S = diag(C)^{-1/2} (an exact
@@ -450,13 +462,14 @@ void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, cons
 }
 
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
-                     double* ctg, const int32_t* inv, const SubDesc* gsub, int32_t* Fg) {
+                     double* ctg, const int32_t* inv, const SubDesc* gsub, int32_t* Fg,
+                     const double* scale) {
   // workgroups per subdomain: enough for the largest one to take 2 columns
   // per thread (at most 64)
   const int ny = std::max(1, std::min(64, (P.max_np + 511) / 512));
   k_assemble<<<dim3(nsub, ny), 256, 0, st>>>(P.heavy(), P.omega, P.part, P.locown, M.rowptr,
                                              M.colind, M.vals, M.trowptr, M.trow, M.tvals, P.tileF,
-                                             P.tileOff, fac, ctg, inv, gsub, Fg);
+                                             P.tileOff, fac, ctg, inv, gsub, Fg, scale);
 }
 
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,

@@ -185,9 +185,11 @@ void launch_gather_values(hipStream_t st, int64_t nnz, const int32_t* perm, cons
                           double* dst);
 // with inv (not null), also the tile envelope Fg of the global-order
 // layouts gsub (Fg set by launch_solve_env_init first)
+// scale non-null: assemble S C_ii S and S Ct_GG S directly (S = scale, from
+// launch_col_scale), identity on the padding diagonal
 void launch_assemble(hipStream_t st, int nsub, const DevPlan& P, const DevMatrix& M, double* fac,
                      double* ctg, const int32_t* inv = nullptr, const SubDesc* gsub = nullptr,
-                     int32_t* Fg = nullptr);
+                     int32_t* Fg = nullptr, const double* scale = nullptr);
 void launch_equilibrate(hipStream_t st, int nsub, const DevPlan& P, double* fac, double* ctg,
                         double* scale);
 // interior_only: factor the interior tile columns only (L_I and L_GI)
