@@ -289,8 +289,8 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     }
     int32_t* out = lists[t].data();
     const int32_t* lo = P.locown.data();
-    int32_t* fo = fpriv[t].data() - cmin;     // indexed by column
-    std::fill(fpriv[t].data(), fpriv[t].data() + std::max(cmax - cmin + 1, 1), INT32_MAX);
+    int32_t* fo = fpriv[t].data();            // column c at c - cmin
+    std::fill(fo, fo + std::max(cmax - cmin + 1, 1), INT32_MAX);
     for (int32_t r = a; r < b; ++r) {
       const int k = row_parts(rowptr, colind, part, r, out + 1);
       *out = k;
@@ -298,7 +298,10 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
       out += 1 + k;
       if (k != 1) continue;
       const int32_t best = lo[colind[rowptr[r]]];
-      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) fo[colind[e]] = std::min(fo[colind[e]], best);
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t& slot = fo[colind[e] - cmin];
+        slot = std::min(slot, best);
+      }
     }
   });
   for (unsigned t = 0; t < rt; ++t)
@@ -308,8 +311,8 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
     std::fill(fown.data() + a, fown.data() + b, INT32_MAX);
     for (unsigned u = 0; u < rt; ++u) {
       const int32_t c0 = std::max(a, flo[u]), c1 = std::min(b - 1, fhi[u]);
-      const int32_t* fu = fpriv[u].data() - flo[u];
-      for (int32_t c = c0; c <= c1; ++c) fown[c] = std::min(fown[c], fu[c]);
+      const int32_t* fu = fpriv[u].data();
+      for (int32_t c = c0; c <= c1; ++c) fown[c] = std::min(fown[c], fu[c - flo[u]]);
     }
   });
   fpriv.clear();
