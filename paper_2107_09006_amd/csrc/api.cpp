@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -735,7 +736,8 @@ lsq2l_status solve_layout(lsq2l_ctx* c, double** s64) {
 // Everything after the matrix is resident in the handle (c->M rowptr/colind/vals).
 lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
                         const HostVec<int32_t>& part, int32_t nparts,
-                        const std::vector<int32_t>& seg_of_part) {
+                        const std::vector<int32_t>& seg_of_part,
+                        const std::function<void(int64_t)>& wait_nnz) {
   const hipStream_t st = c->st;
   const int32_t m = c->M.m, n = c->M.n;
   const int64_t nnz = c->M.nnz;
@@ -761,9 +763,12 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   // Row order of the copy used for C p = A^T (A p), found on a host thread
   // while the device assembles, factors and selects (see row_order).
   RowOrder ro;
-  JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci]() { row_order(m, n, rp, ci, ro); })};
+  JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci, nnz, &wait_nnz]() {
+    if (wait_nnz) wait_nnz(nnz);
+    row_order(m, n, rp, ci, ro);
+  })};
   std::string err;
-  if (!plan_build(m, n, rp, ci, part.data(), nparts, seg_of_part, c->H, err)) {
+  if (!plan_build(m, n, rp, ci, part.data(), nparts, seg_of_part, c->H, err, wait_nnz)) {
     set_error(err);
     return LSQ2L_EINVAL;
   }
@@ -1345,6 +1350,47 @@ bool is_device_ptr(const void* p) {
   return at.type == hipMemoryTypeDevice;
 }
 
+// Device-to-host copy of the concatenated column indices in chunks, each
+// closed by an event.  head closes everything queued before the chunks.  The
+// destructor waits for the last chunk, so the pinned buffer is never handed
+// back while a copy into it is in flight (also on early error returns).
+struct PatternChunks {
+  static constexpr int NCH = 8;
+  hipEvent_t head = nullptr;
+  hipEvent_t ev[NCH] = {};
+  int64_t bound[NCH + 1] = {};
+  int nch = 0;
+  lsq2l_status start(hipStream_t st, int32_t* host, const int32_t* dev, int64_t nnz) {
+    LSQ2L_HIP_TRY(hipEventCreateWithFlags(&head, hipEventDisableTiming));
+    LSQ2L_HIP_TRY(hipEventRecord(head, st));
+    const int want = nnz >= ((int64_t)1 << 20) ? NCH : (nnz > 0 ? 1 : 0);
+    for (int q = 0; q < want; ++q) {
+      const int64_t a = nnz * q / want, b = nnz * (q + 1) / want;
+      LSQ2L_HIP_TRY(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+      nch = q + 1;
+      bound[q] = a;
+      bound[q + 1] = b;
+      if (b > a)
+        LSQ2L_HIP_TRY(hipMemcpyAsync(host + a, dev + a, (b - a) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      LSQ2L_HIP_TRY(hipEventRecord(ev[q], st));
+    }
+    return LSQ2L_OK;
+  }
+  // returns once entries [0, upto) are in place
+  void wait(int64_t upto) const {
+    for (int q = nch - 1; q >= 0; --q)
+      if (bound[q] < upto) {              // chunks complete in order: the last one needed suffices
+        (void)hipEventSynchronize(ev[q]);
+        return;
+      }
+  }
+  ~PatternChunks() {
+    if (nch > 0) (void)hipEventSynchronize(ev[nch - 1]);
+    for (int q = 0; q < nch; ++q) (void)hipEventDestroy(ev[q]);
+    if (head) (void)hipEventDestroy(head);
+  }
+};
+
 // Setup of one or several instances: their CSR arrays are concatenated and
 // checked on the device in three launches (launch_concat), and the
 // concatenated pattern is read back once into pinned memory for the planner.
@@ -1398,7 +1444,6 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   unsigned long long hbad[CSR_KINDS];
   LSQ2L_HIP_TRY(hipMemcpyAsync(hbad, d_bad, sizeof(hbad), hipMemcpyDeviceToHost, st));
   LSQ2L_HIP_TRY(hipMemcpyAsync(rp.p, c->M.rowptr, (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  if (NNZ) LSQ2L_HIP_TRY(hipMemcpyAsync(ci.p, c->M.colind, NNZ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   // partitions: host arrays are read in place, device arrays copied back
   HostVec<int32_t> pt;
   std::vector<int32_t> seg_of_part(NP);
@@ -1409,7 +1454,12 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
       TRY(pdev[k].alloc(probs[k].n));
       LSQ2L_HIP_TRY(hipMemcpyAsync(pdev[k].p, probs[k].part, probs[k].n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
-  const hipError_t e = hipStreamSynchronize(st);
+  // the column indices come back in chunks, each closed by an event, so that
+  // the planner starts on the rows that have arrived while the rest is in
+  // flight (the checks, row pointers and parts are waited for here)
+  PatternChunks chunks;
+  TRY(chunks.start(st, ci.p, c->M.colind, NNZ));
+  const hipError_t e = hipEventSynchronize(chunks.head);
   if (e != hipSuccess) { set_error(std::string("reading A: ") + hipGetErrorString(e)); return LSQ2L_EHIP; }
   // the first failure in the order of the checks: row extents, then columns
   // (reported only when the extents hold)
@@ -1458,7 +1508,8 @@ lsq2l_status setup_instances(lsq2l_ctx* c, int count, const lsq2l_problem* probs
   for (int k = 0; k < count; ++k)
     for (int32_t q = 0; q < probs[k].nparts; ++q) seg_of_part[p0[k] + q] = k;
   c->info.t_prepare_ms = ms_since(t_prep);
-  return setup_core(c, rp.p, ci.p, pt, (int32_t)NP, seg_of_part);
+  return setup_core(c, rp.p, ci.p, pt, (int32_t)NP, seg_of_part,
+                    [&chunks](int64_t e) { chunks.wait(e); });
 }
 
 lsq2l_ctx* new_handle(double tau, const lsq2l_options* opt, void* hip_stream) {

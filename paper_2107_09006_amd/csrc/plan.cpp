@@ -208,7 +208,7 @@ void plan_one(int32_t i, const int32_t* rowptr, const int32_t* colind, const int
 
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
-                HostPlan& P, std::string& err) {
+                HostPlan& P, std::string& err, const std::function<void(int64_t)>& wait_nnz) {
   P.nparts = nparts;
   const unsigned nth = std::min<unsigned>(planner_threads(), (unsigned)std::max(nparts, 1));
   // columns of each part, ascending, and each column's position in its part:
@@ -274,6 +274,7 @@ bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* coli
   if (!fown.resize((size_t)n)) { err = "host allocation failed"; return false; }
   run_threads(rt, [&](unsigned t) {
     const int32_t a = rb[t], b = std::max(rb[t], rb[t + 1]);
+    if (wait_nnz) wait_nnz(rowptr[b]);       // this range's column indices are in place
     int32_t cmin = INT32_MAX, cmax = -1;
     for (int32_t e = rowptr[a]; e < rowptr[b]; ++e) {
       cmin = std::min(cmin, colind[e]);

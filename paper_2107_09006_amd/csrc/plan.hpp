@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "internal.hpp"
@@ -105,10 +106,13 @@ bool plan_transpose(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* 
                     std::vector<int32_t>& trowptr, std::vector<int32_t>& tcol,
                     std::vector<int32_t>& tperm);
 
-// Index sets, local layouts and envelopes of every subdomain.
+// Index sets, local layouts and envelopes of every subdomain.  colind may
+// still be arriving: wait_nnz(e), if given, returns once colind[0 .. e) is
+// in place, and every read of colind comes after such a call.
 bool plan_build(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* colind,
                 const int32_t* part, int32_t nparts, const std::vector<int32_t>& seg_of_part,
-                HostPlan& P, std::string& err);
+                HostPlan& P, std::string& err,
+                const std::function<void(int64_t)>& wait_nnz = std::function<void(int64_t)>());
 
 // Overlap maps of a built plan: for every column the local positions holding
 // it (own_ptr / own_pos), and the pairs of subdomains sharing rows (cpair_*,
