@@ -12,7 +12,9 @@
 //      range(Ct) by null(Ct) only, which T annihilates (T <= Ct_GG because the
 //      splitting matrix Ct_ii is positive semidefinite with C_I as its
 //      interior block), so K is the same as on range(Ct);
-//   2. K = W^T T W with MFMA tile products;
+//   2. K = W^T T W with MFMA tile products; if (1 - tau) I - K has a
+//      Cholesky factor (tiled, on MFMA), no eigenvalue reaches the threshold
+//      and the subdomain selects nothing (steps 3-6 are skipped);
 //   3. Householder tridiagonalization of K;
 //   4. p = number of eigenvalues above 1 - tau (one Sturm count), then the
 //      p largest eigenvalues by multisection (one wave each);
@@ -952,11 +954,11 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __syncthreads();
 
   // ---- 5. inverse iteration, one thread per vector (scratch of 3 r doubles
-  // per vector, in LDS or in M3 / M4).  Shifts are accurate to rounding, so after a few sweeps
-  // every vector lies in the invariant subspace of its cluster; only clusters
-  // of (numerically) multiple eigenvalues need orthonormalising, which is done
-  // after the independent sweeps and again after one cleaning sweep.
-  // Vectors in M1 (r x p).
+  // per vector, in LDS or in M3 / M4).  Shifts are accurate to rounding, so
+  // after a few sweeps every vector lies in the invariant subspace of its
+  // cluster; only clusters of (numerically) multiple eigenvalues need
+  // orthonormalising, which is done after the independent sweeps and again
+  // after one cleaning sweep.  Vectors in M1 (r x p).
   const double tiny = SEL_EPS * anorm;
   // The scratch sits in LDS (svp, swp, spart[0], free now: MAXN doubles each)
   // when every vector fits in one round there, else in M3 / M4.
