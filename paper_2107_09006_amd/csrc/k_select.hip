@@ -42,6 +42,7 @@ constexpr int SEL_THREADS = 1024;
 constexpr int SEL_MAXN = 1024;
 constexpr int SEL_NBP = 24;        // rows of the pivoted Cholesky per panel (interfaces above 128)
 constexpr int TRD_U = 8;           // loads in flight per thread in the tridiagonalization
+constexpr int TRD_NB = 16;         // reflectors per panel of the tridiagonalization
 constexpr double SEL_EPS = 2.220446049250313e-16;
 
 // ----------------------------------------------------------------------------
@@ -406,6 +407,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
   __shared__ double sred[16];
   __shared__ int sredi[16];
   __shared__ double sPW[TS * LDT], sPI[TS * LDT];   // diagonal tile of the test of step 2b
+  __shared__ double sc1[TRD_NB], sc2[TRD_NB];   // dot products of the tridiagonalization's panel
   __shared__ int s_r, s_p, s_nclus, s_diag, s_pd;
   __shared__ double s_anorm;
   const SubDesc dsc = subs[blockIdx.x];
@@ -779,105 +781,147 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     return;
   }
 
-  // ---- 3. tridiagonalization of K (r x r) in M0.  Step k reflects column k
-  // (v, tk) and updates the trailing block, A22 -= v w^T + w v^T with
-  // w = tk A22 v - (tk^2 / 2) (v^T A22 v) v.  The update of step k is applied
-  // during the pass of step k + 1 that forms A22 v there, so each step reads
-  // and writes the trailing block once; column k + 1, which the next reflector
-  // needs first, takes the pending update on its own.  Every entry receives
-  // the same operations in the same order as with the update as a pass of its
-  // own.
-  bool pend = false;                      // svp, swp hold an update not yet applied
-  for (int k = 0; k + 2 < r; ++k) {
-    const int m = r - k - 1;
-    // column k (rows k .. r-1) with the pending update of step k - 1, whose
-    // block starts at row k (local index i - k), into sw
-    for (int a = tid; a <= m; a += nthr) {
-      double x = M0[(int64_t)k * ld + k + a];
-      if (pend) x -= svp[a] * swp[0] + swp[a] * svp[0];
-      sw[a] = x;
-    }
-    __syncthreads();
-    double part = 0.0;
-    for (int a = 1 + tid; a < m; a += nthr) { const double t = sw[1 + a]; part += t * t; }
-    const double xn2 = wg_sum(part, sred);
-    const double alpha = sw[1];
-    double tk = 0.0, beta = alpha;
-    if (xn2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tk = (beta - alpha) / beta;
-      const double sc = 1.0 / (alpha - beta);
-      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : sw[1 + a] * sc;
-    } else {
-      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) { se[k] = beta; sd[k] = sw[0]; stau[k] = tk; }
-    for (int a = 1 + tid; a < m; a += nthr) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
-    if (tk != 0.0 || pend) {
-      // one pass over A22 (rows and columns k + 1 ..): the pending update,
-      // then w = tk A22 v from NG thread groups splitting the columns,
-      // their partial sums added in a fixed order
-      const int g = tid / 256, t256 = tid % 256;
-      for (int a0 = 0; a0 < m; a0 += 256) {
-        const int a = a0 + t256;
-        double acc = 0.0;
-        if (a < m) {
-          // row a of the block, columns b = g, g + NG, ...: TRD_U loads in
-          // flight before their updates are stored
-          double* rowa = M0 + (int64_t)(k + 1) * ld + k + 1 + a;
-          const double va = svp[a + 1], wa = swp[a + 1];
-          int b = g;
-          for (; b + (TRD_U - 1) * NG < m; b += TRD_U * NG) {
-            double x[TRD_U];
-#pragma unroll
-            for (int u = 0; u < TRD_U; ++u) x[u] = rowa[(int64_t)(b + u * NG) * ld];
-#pragma unroll
-            for (int u = 0; u < TRD_U; ++u) {
-              const int bu = b + u * NG;
-              if (pend) {
-                x[u] -= va * swp[bu + 1] + wa * svp[bu + 1];
-                rowa[(int64_t)bu * ld] = x[u];
-              }
-              acc += x[u] * sv[bu];
-            }
-          }
-          for (; b < m; b += NG) {
-            double x = rowa[(int64_t)b * ld];
-            if (pend) {
-              x -= va * swp[b + 1] + wa * svp[b + 1];
-              rowa[(int64_t)b * ld] = x;
-            }
-            acc += x * sv[b];
-          }
-          spart[g][a] = acc;
+  // ---- 3. tridiagonalization of K (r x r) in M0, TRD_NB reflectors per
+  // panel.  Step k reflects column k (v, tk); the trailing block's update
+  // A22 -= v w^T + w v^T, w = tk A22 v - (tk^2 / 2) (v^T A22 v) v, is held
+  // back as the panel's columns of V and Wm (in M3) and applied once per
+  // panel on MFMA tiles, so the steps only read the block: inside a panel,
+  // column k and A22 v are formed from the matrix at the panel's start
+  // minus V Wm^T + Wm V^T of the earlier steps.
+  {
+    double* VV = M3;                      // panel reflectors, column q at q ld (rows k + 1 ..)
+    double* WW = M3 + (int64_t)TRD_NB * ld;
+    const int wave = tid / 64, lane = tid % 64, nwv = nthr / 64;
+    int k = 0;
+    while (k + 2 < r) {
+      const int k0 = k;
+      int jj = 0;
+      for (; jj < TRD_NB && k + 2 < r; ++jj, ++k) {
+        const int m = r - k - 1;
+        // row k of the panel's V and Wm
+        if (tid < jj) { svp[tid] = VV[(int64_t)tid * ld + k]; swp[tid] = WW[(int64_t)tid * ld + k]; }
+        __syncthreads();
+        // column k (rows k .. r-1) of the current matrix into sw
+        for (int a = tid; a <= m; a += nthr) {
+          double x = M0[(int64_t)k * ld + k + a];
+          for (int q = 0; q < jj; ++q)
+            x -= VV[(int64_t)q * ld + k + a] * swp[q] + WW[(int64_t)q * ld + k + a] * svp[q];
+          sw[a] = x;
         }
-      }
-    }
-    __syncthreads();
-    if (tk != 0.0) {
-      double pp = 0.0;
-      for (int a = tid; a < m; a += nthr) {
-        double sp = spart[0][a];
+        __syncthreads();
+        double part = 0.0;
+        for (int a = 1 + tid; a < m; a += nthr) { const double t = sw[1 + a]; part += t * t; }
+        const double xn2 = wg_sum(part, sred);
+        const double alpha = sw[1];
+        double tk = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+          beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+          tk = (beta - alpha) / beta;
+          const double sc = 1.0 / (alpha - beta);
+          for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : sw[1 + a] * sc;
+        } else {
+          for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) { se[k] = beta; sd[k] = sw[0]; stau[k] = tk; }
+        for (int a = tid; a < m; a += nthr) {
+          if (a >= 1) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
+          VV[(int64_t)jj * ld + k + 1 + a] = sv[a];
+        }
+        if (tk == 0.0) {
+          for (int a = tid; a < m; a += nthr) WW[(int64_t)jj * ld + k + 1 + a] = 0.0;
+          __syncthreads();
+          continue;
+        }
+        // Wm^T v and V^T v over the earlier steps of the panel, one wave each
+        for (int t = wave; t < 2 * jj; t += nwv) {
+          const double* col = (t < jj ? WW + (int64_t)t * ld : VV + (int64_t)(t - jj) * ld) + k + 1;
+          double d = 0.0;
+          for (int a = lane; a < m; a += 64) d += col[a] * sv[a];
+          d = wave_allsum(d);
+          if (lane == 0) { if (t < jj) sc1[t] = d; else sc2[t - jj] = d; }
+        }
+        // A22 v from the matrix at the panel's start, NG thread groups
+        // splitting the columns, TRD_U loads in flight
+        {
+          const int g = tid / 256, t256 = tid % 256;
+          for (int a0 = 0; a0 < m; a0 += 256) {
+            const int a = a0 + t256;
+            if (a >= m) continue;
+            const double* rowa = M0 + (int64_t)(k + 1) * ld + k + 1 + a;
+            double acc = 0.0;
+            int b = g;
+            for (; b + (TRD_U - 1) * NG < m; b += TRD_U * NG) {
+              double x[TRD_U];
 #pragma unroll
-        for (int q = 1; q < NG; ++q) sp += spart[q][a];
-        sw[a] = tk * sp;
-        pp += sw[a] * sv[a];
+              for (int u = 0; u < TRD_U; ++u) x[u] = rowa[(int64_t)(b + u * NG) * ld];
+#pragma unroll
+              for (int u = 0; u < TRD_U; ++u) acc += x[u] * sv[b + u * NG];
+            }
+            for (; b < m; b += NG) acc += rowa[(int64_t)b * ld] * sv[b];
+            spart[g][a] = acc;
+          }
+        }
+        __syncthreads();
+        // y = A22 v - V (Wm^T v) - Wm (V^T v), w = tk y - (tk / 2)(tk y^T v) v
+        double pp = 0.0;
+        for (int a = tid; a < m; a += nthr) {
+          double y = spart[0][a];
+#pragma unroll
+          for (int q = 1; q < NG; ++q) y += spart[q][a];
+          for (int q = 0; q < jj; ++q)
+            y -= VV[(int64_t)q * ld + k + 1 + a] * sc1[q] + WW[(int64_t)q * ld + k + 1 + a] * sc2[q];
+          sw[a] = tk * y;
+          pp += sw[a] * sv[a];
+        }
+        const double wv = wg_sum(pp, sred);
+        const double a2 = -0.5 * tk * wv;
+        for (int a = tid; a < m; a += nthr) WW[(int64_t)jj * ld + k + 1 + a] = sw[a] + a2 * sv[a];
+        __syncthreads();
       }
-      const double wv = wg_sum(pp, sred);
-      const double a2 = -0.5 * tk * wv;
-      for (int a = tid; a < m; a += nthr) {
-        swp[a] = sw[a] + a2 * sv[a];
-        svp[a] = sv[a];
+      // the panel's update of rows and columns from k on (the next panel's
+      // first column and everything after it): A -= V Wm^T + Wm V^T on
+      // 32 x 32 tiles, entries before k left as they are
+      const int nq = jj, kn = k;
+      const int tlo = kn / TS, nbt = (r + TS - 1) / TS, nt = nbt - tlo;
+      for (int t = wave; t < nt * nt; t += nwv) {
+        const int I = tlo + t % nt, J = tlo + t / nt;
+        double4_t acc[4];
+        double* C = M0 + (int64_t)(J * TS) * ld + I * TS;
+        tile_acc_load<double>(acc, C, ld, lane);
+        const int li = lane % 16, lk = lane / 16;
+        for (int q0 = 0; q0 < nq; q0 += 4) {
+          const int q = q0 + lk;
+          const bool in = q < nq;
+          const double* vq = VV + (int64_t)q * ld;
+          const double* wq = WW + (int64_t)q * ld;
+          const double av0 = in ? -vq[I * TS + li] : 0.0, av1 = in ? -vq[I * TS + 16 + li] : 0.0;
+          const double aw0 = in ? -wq[I * TS + li] : 0.0, aw1 = in ? -wq[I * TS + 16 + li] : 0.0;
+          const double bw0 = in ? wq[J * TS + li] : 0.0, bw1 = in ? wq[J * TS + 16 + li] : 0.0;
+          const double bv0 = in ? vq[J * TS + li] : 0.0, bv1 = in ? vq[J * TS + 16 + li] : 0.0;
+          acc[0] = Mfma<double>::mma(av0, bw0, acc[0]);
+          acc[1] = Mfma<double>::mma(av0, bw1, acc[1]);
+          acc[2] = Mfma<double>::mma(av1, bw0, acc[2]);
+          acc[3] = Mfma<double>::mma(av1, bw1, acc[3]);
+          acc[0] = Mfma<double>::mma(aw0, bv0, acc[0]);
+          acc[1] = Mfma<double>::mma(aw0, bv1, acc[1]);
+          acc[2] = Mfma<double>::mma(aw1, bv0, acc[2]);
+          acc[3] = Mfma<double>::mma(aw1, bv1, acc[3]);
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = I * TS + 16 * bi + Mfma<double>::acc_row(lane, v);
+              const int col = J * TS + 16 * bj + Mfma<double>::acc_col(lane, v);
+              if (row >= kn && col >= kn && row < r && col < r) C[(int64_t)(16 * bj + Mfma<double>::acc_col(lane, v)) * ld + 16 * bi + Mfma<double>::acc_row(lane, v)] = acc[bi * 2 + bj][v];
+            }
       }
+      __syncthreads();
+      (void)k0;
     }
-    pend = tk != 0.0;
-    __syncthreads();
-  }
-  if (pend && tid == 0) {                 // the last update reaches rows r-2, r-1
-    for (int b = 0; b < 2; ++b)
-      for (int a = b; a < 2; ++a)
-        M0[(int64_t)(r - 2 + b) * ld + r - 2 + a] -= svp[a] * swp[b] + swp[a] * svp[b];
   }
   __syncthreads();
   if (tid == 0) {
