@@ -781,8 +781,111 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
     return;
   }
 
-  // ---- 3. tridiagonalization of K (r x r) in M0, TRD_NB reflectors per
-  // panel.  Step k reflects column k (v, tk); the trailing block's update
+  // ---- 3. tridiagonalization of K (r x r) in M0: for interfaces up to 128
+  // columns step by step (below), larger ones by panels (further below).
+  if constexpr (MAXN <= 128) {
+  // Step k reflects column k
+  // (v, tk) and updates the trailing block, A22 -= v w^T + w v^T with
+  // w = tk A22 v - (tk^2 / 2) (v^T A22 v) v.  The update of step k is applied
+  // during the pass of step k + 1 that forms A22 v there, so each step reads
+  // and writes the trailing block once; column k + 1, which the next reflector
+  // needs first, takes the pending update on its own.  Every entry receives
+  // the same operations in the same order as with the update as a pass of its
+  // own.
+  bool pend = false;                      // svp, swp hold an update not yet applied
+  for (int k = 0; k + 2 < r; ++k) {
+    const int m = r - k - 1;
+    // column k (rows k .. r-1) with the pending update of step k - 1, whose
+    // block starts at row k (local index i - k), into sw
+    for (int a = tid; a <= m; a += nthr) {
+      double x = M0[(int64_t)k * ld + k + a];
+      if (pend) x -= svp[a] * swp[0] + swp[a] * svp[0];
+      sw[a] = x;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int a = 1 + tid; a < m; a += nthr) { const double t = sw[1 + a]; part += t * t; }
+    const double xn2 = wg_sum(part, sred);
+    const double alpha = sw[1];
+    double tk = 0.0, beta = alpha;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tk = (beta - alpha) / beta;
+      const double sc = 1.0 / (alpha - beta);
+      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : sw[1 + a] * sc;
+    } else {
+      for (int a = tid; a < m; a += nthr) sv[a] = (a == 0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) { se[k] = beta; sd[k] = sw[0]; stau[k] = tk; }
+    for (int a = 1 + tid; a < m; a += nthr) M0[(int64_t)k * ld + k + 1 + a] = sv[a];
+    if (tk != 0.0 || pend) {
+      // one pass over A22 (rows and columns k + 1 ..): the pending update,
+      // then w = tk A22 v from NG thread groups splitting the columns,
+      // their partial sums added in a fixed order
+      const int g = tid / 256, t256 = tid % 256;
+      for (int a0 = 0; a0 < m; a0 += 256) {
+        const int a = a0 + t256;
+        double acc = 0.0;
+        if (a < m) {
+          // row a of the block, columns b = g, g + NG, ...: TRD_U loads in
+          // flight before their updates are stored
+          double* rowa = M0 + (int64_t)(k + 1) * ld + k + 1 + a;
+          const double va = svp[a + 1], wa = swp[a + 1];
+          int b = g;
+          for (; b + (TRD_U - 1) * NG < m; b += TRD_U * NG) {
+            double x[TRD_U];
+#pragma unroll
+            for (int u = 0; u < TRD_U; ++u) x[u] = rowa[(int64_t)(b + u * NG) * ld];
+#pragma unroll
+            for (int u = 0; u < TRD_U; ++u) {
+              const int bu = b + u * NG;
+              if (pend) {
+                x[u] -= va * swp[bu + 1] + wa * svp[bu + 1];
+                rowa[(int64_t)bu * ld] = x[u];
+              }
+              acc += x[u] * sv[bu];
+            }
+          }
+          for (; b < m; b += NG) {
+            double x = rowa[(int64_t)b * ld];
+            if (pend) {
+              x -= va * swp[b + 1] + wa * svp[b + 1];
+              rowa[(int64_t)b * ld] = x;
+            }
+            acc += x * sv[b];
+          }
+          spart[g][a] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (tk != 0.0) {
+      double pp = 0.0;
+      for (int a = tid; a < m; a += nthr) {
+        double sp = spart[0][a];
+#pragma unroll
+        for (int q = 1; q < NG; ++q) sp += spart[q][a];
+        sw[a] = tk * sp;
+        pp += sw[a] * sv[a];
+      }
+      const double wv = wg_sum(pp, sred);
+      const double a2 = -0.5 * tk * wv;
+      for (int a = tid; a < m; a += nthr) {
+        swp[a] = sw[a] + a2 * sv[a];
+        svp[a] = sv[a];
+      }
+    }
+    pend = tk != 0.0;
+    __syncthreads();
+  }
+  if (pend && tid == 0) {                 // the last update reaches rows r-2, r-1
+    for (int b = 0; b < 2; ++b)
+      for (int a = b; a < 2; ++a)
+        M0[(int64_t)(r - 2 + b) * ld + r - 2 + a] -= svp[a] * swp[b] + swp[a] * svp[b];
+  }
+  } else {
+  // TRD_NB reflectors per panel.  Step k reflects column k (v, tk); the trailing block's update
   // A22 -= v w^T + w v^T, w = tk A22 v - (tk^2 / 2) (v^T A22 v) v, is held
   // back as the panel's columns of V and Wm (in M3) and applied once per
   // panel on MFMA tiles, so the steps only read the block: inside a panel,
@@ -922,6 +1025,7 @@ k_select(const SubDesc* __restrict__ subs, const double* __restrict__ ctg,
       __syncthreads();
       (void)k0;
     }
+  }
   }
   __syncthreads();
   if (tid == 0) {
