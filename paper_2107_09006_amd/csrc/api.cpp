@@ -760,18 +760,19 @@ lsq2l_status setup_core(lsq2l_ctx* c, const int32_t* rp, const int32_t* ci,
   launch_row_blocks(st, n, c->M.trowptr, nnz, c->M.tblk);
   c->M.spmv_group = pick_group(m ? (double)nnz / m : 1.0);
   c->M.spmvt_group = pick_group(n ? (double)nnz / n : 1.0);
-  // Row order of the copy used for C p = A^T (A p), found on a host thread
-  // while the device assembles, factors and selects (see row_order).
-  RowOrder ro;
-  JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci, nnz, &wait_nnz]() {
-    if (wait_nnz) wait_nnz(nnz);
-    row_order(m, n, rp, ci, ro);
-  })};
   std::string err;
   if (!plan_build(m, n, rp, ci, part.data(), nparts, seg_of_part, c->H, err, wait_nnz)) {
     set_error(err);
     return LSQ2L_EINVAL;
   }
+  // Row order of the copy used for C p = A^T (A p), found on a host thread
+  // while the device assembles, factors and selects (see row_order); started
+  // once the planner's threads are done, so that it takes none of their cores.
+  RowOrder ro;
+  JoiningThread ro_thread{std::thread([&ro, m, n, rp, ci, nnz, &wait_nnz]() {
+    if (wait_nnz) wait_nnz(nnz);
+    row_order(m, n, rp, ci, ro);
+  })};
   HostPlan& H = c->H;
   c->nsub = nparts;
   MapsJob maps;
